@@ -1,0 +1,582 @@
+"""CPU FP64 oracle of the SLR preconditioner hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code
+with the device library (``paper_1505_04340_amd``) and never imports it.
+
+Reference: R. Li, Y. Xi, Y. Saad, "Schur complement based domain
+decomposition preconditioners with low-rank corrections" (2015).
+Every function cites the passage it follows.  Readings where the paper is
+silent are marked READING.
+
+Plain, slow and step-by-step: scipy/numpy are used only for library
+primitives (sparse permutation/slicing and mat-vec, banded Cholesky and
+banded triangular solves for the exact factors, a symmetric tridiagonal
+eigensolver, dot products); the incomplete factorisations and sparse
+triangular sweeps are the plain C loops in ``sparse_loops.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def build_c(force: bool = False) -> str:
+    """Compile the oracle's C loops with gcc (plain -O2, no vector tricks)."""
+    import subprocess
+    src = os.path.join(_HERE, "sparse_loops.c")
+    out = os.path.join(_HERE, "_sparse_loops.so")
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", out + ".tmp", src, "-lm"])
+        os.replace(out + ".tmp", out)
+    return out
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        lib = ctypes.CDLL(build_c())
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.orc_ic0.argtypes = [I64, P, P, P]
+        lib.orc_ic0.restype = ctypes.c_int
+        lib.orc_ildlt0.argtypes = [I64, P, P, P, P]
+        lib.orc_ildlt0.restype = ctypes.c_int
+        lib.orc_lower_solve.argtypes = [I64, P, P, P, P, ctypes.c_int]
+        lib.orc_upper_solve.argtypes = [I64, P, P, P, P, ctypes.c_int]
+        lib.orc_diag_solve.argtypes = [I64, P, P, P]
+        _LIB = lib
+    return _LIB
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: str, msg: str):
+        super().__init__(f"{code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# C1 / C2: classification and domain-decomposition ordering (Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+def classify(A: sp.csr_matrix, part: np.ndarray, nparts: int):
+    """Interior / interface labels (Sec. 2.1, local view of a subdomain).
+
+    Vertex-based partitioning: a node is a local interface node when it is
+    coupled to a node of another subdomain; otherwise it is interior.
+    Edge-based partitioning: nodes labelled -1 form the vertex separator
+    (shared interface); coupling to a separator node does not make a node
+    an interface node.  Returns (is_interface bool[n], owner int[n]) with
+    owner = -1 for separator nodes."""
+    part = np.asarray(part)
+    if part.shape != (A.shape[0],) or part.min() < -1 or part.max() >= nparts:
+        raise OracleError("PARTITION", "labels out of range")
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    cols = A.indices
+    pr, pc = part[rows], part[cols]
+    cross = (pr >= 0) & (pc >= 0) & (pr != pc)
+    iface = np.zeros(A.shape[0], dtype=bool)
+    iface[rows[cross]] = True
+    iface |= part < 0
+    return iface, part.copy()
+
+
+def greedy_colors(C: sp.csr_matrix) -> np.ndarray:
+    """READING for the multicolour ordering of C: greedy colouring in the
+    current row order, each node taking the smallest colour unused by its
+    already-coloured neighbours."""
+    n = C.shape[0]
+    col = -np.ones(n, dtype=np.int64)
+    for i in range(n):
+        used = set(col[C.indices[C.indptr[i]:C.indptr[i + 1]]].tolist())
+        c = 0
+        while c in used:
+            c += 1
+        col[i] = c
+    return col
+
+
+def dd_ordering(A: sp.csr_matrix, part: np.ndarray, nparts: int, c_order: str = "subdomain"):
+    """Global DD ordering of eq. (Global): interiors u_1..u_p by subdomain,
+    then the interface y.  READING: ascending original index inside each
+    group; interface grouped by owner subdomain 0..p-1 with separator nodes
+    last (eq. Global2 with y = [y_1; ...; y_p]).  With c_order='multicolor'
+    the interface is additionally stably sorted by greedy colour.
+    Returns (perm new->old, interior offsets [p+1], interface offsets
+    [p+2] (last group = separator), colours or None)."""
+    iface, owner = classify(A, part, nparts)
+    idx = np.arange(A.shape[0])
+    inter = [idx[(~iface) & (owner == q)] for q in range(nparts)]
+    ifc = [idx[iface & (owner == q)] for q in range(nparts)] + [idx[iface & (owner < 0)]]
+    off_b = np.concatenate([[0], np.cumsum([len(a) for a in inter])])
+    off_y = np.concatenate([[0], np.cumsum([len(a) for a in ifc])])
+    perm = np.concatenate(inter + ifc).astype(np.int64)
+    colors = None
+    if c_order == "multicolor":
+        m = off_b[-1]
+        y = perm[m:]
+        C = A[y][:, y].tocsr()
+        colors = greedy_colors(C)
+        order = np.argsort(colors, kind="stable")
+        perm = np.concatenate([perm[:m], y[order]])
+        colors = colors[order]
+    elif c_order != "subdomain":
+        raise OracleError("ARG", c_order)
+    return perm, off_b, off_y, colors
+
+
+# ---------------------------------------------------------------------------
+# C3: local factorisations (Sec. 5.2)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Factor:
+    """L L^T (kind 'ic0' / 'chol') or L D L^T (kind 'ildlt0') of a block
+    diagonal matrix.  For 'chol' each block is kept in LAPACK lower-band
+    storage (band[i - j, j] = L[i, j])."""
+    kind: str
+    n: int
+    rp: np.ndarray = None
+    ci: np.ndarray = None
+    v: np.ndarray = None
+    blocks: list = field(default_factory=list)   # (start, lower band of L) for chol
+
+    def round_to(self, prec: str):
+        """READING (reduced precision): factors are computed in FP64 and the
+        stored values rounded to nearest-even FP32."""
+        if prec == "fp64":
+            return
+        if self.v is not None:
+            self.v = self.v.astype(np.float32).astype(np.float64)
+        self.blocks = [(s, L.astype(np.float32).astype(np.float64)) for s, L in self.blocks]
+
+    def _band_solve(self, x: np.ndarray, trans: str) -> np.ndarray:
+        for s, cb in self.blocks:
+            nb = cb.shape[1]
+            y, info = sla.lapack.dtbtrs(cb, x[s:s + nb].reshape(nb, 1), uplo="L", trans=trans)
+            if info != 0:
+                raise OracleError("BREAKDOWN", f"dtbtrs info {info}")
+            x[s:s + nb] = y.ravel()
+        return x
+
+    def lower(self, x: np.ndarray) -> np.ndarray:
+        """x <- L^{-1} x (unit L for LDL^T)."""
+        x = np.array(x, dtype=np.float64, copy=True)
+        if self.kind == "chol":
+            return self._band_solve(x, "N")
+        _lib().orc_lower_solve(self.n, _p(self.rp), _p(self.ci), _p(self.v), _p(x),
+                               1 if self.kind == "ildlt0" else 0)
+        return x
+
+    def upper(self, x: np.ndarray) -> np.ndarray:
+        """x <- L^{-T} x."""
+        x = np.array(x, dtype=np.float64, copy=True)
+        if self.kind == "chol":
+            return self._band_solve(x, "T")
+        _lib().orc_upper_solve(self.n, _p(self.rp), _p(self.ci), _p(self.v), _p(x),
+                               1 if self.kind == "ildlt0" else 0)
+        return x
+
+    def dense_lower(self, a: int, b: int) -> np.ndarray:
+        """Dense copy of the diagonal block [a, b) of L (tests only)."""
+        if self.kind == "chol":
+            for s, cb in self.blocks:
+                if s == a and s + cb.shape[1] == b:
+                    nb = cb.shape[1]
+                    L = np.zeros((nb, nb))
+                    for d in range(cb.shape[0]):
+                        L[np.arange(d, nb), np.arange(0, nb - d)] = cb[d, :nb - d]
+                    return L
+            raise KeyError((a, b))
+        M = sp.csr_matrix((self.v, self.ci, self.rp), shape=(self.n, self.n))
+        return M[a:b][:, a:b].toarray()
+
+    def solve(self, x: np.ndarray) -> np.ndarray:
+        """x <- (L L^T)^{-1} x, or (L D L^T)^{-1} x."""
+        y = self.lower(x)
+        if self.kind == "ildlt0":
+            _lib().orc_diag_solve(self.n, _p(self.rp), _p(self.v), _p(y))
+        return self.upper(y)
+
+
+def _tril_csr(M: sp.csr_matrix):
+    T = sp.tril(M, format="csr")
+    T.sort_indices()
+    rp = T.indptr.astype(np.int64)
+    ci = T.indices.astype(np.int32)
+    v = T.data.astype(np.float64).copy()
+    # the diagonal must be the last entry of each row
+    for i in range(T.shape[0]):
+        if rp[i + 1] == rp[i] or ci[rp[i + 1] - 1] != i:
+            raise OracleError("BREAKDOWN", f"missing diagonal in row {i}")
+    return rp, ci, v
+
+
+def factorize(M: sp.csr_matrix, kind: str, block_offsets=None, what: str = "B") -> Factor:
+    """Factor a (block diagonal) symmetric matrix.
+
+    'ic0'    incomplete Cholesky with zero fill: the unique lower L on the
+             pattern of tril(M) with (L L^T)_ij = m_ij on that pattern.
+    'ildlt0' incomplete L D L^T with zero fill, unit L.
+    'chol'   exact Cholesky of every diagonal block (banded LAPACK)."""
+    n = M.shape[0]
+    if kind == "chol":
+        # exact Cholesky of every diagonal block, in LAPACK lower-band form
+        offs = block_offsets if block_offsets is not None else [0, n]
+        blocks = []
+        Md = M.tocsr()
+        for a, b in zip(offs[:-1], offs[1:]):
+            if b > a:
+                Bk = Md[a:b][:, a:b].tocoo()
+                bw = int(max(0, (Bk.row - Bk.col).max()))
+                ab = np.zeros((bw + 1, b - a))
+                lo = Bk.row >= Bk.col
+                ab[(Bk.row - Bk.col)[lo], Bk.col[lo]] = Bk.data[lo]
+                try:
+                    blocks.append((a, sla.cholesky_banded(ab, lower=True)))
+                except np.linalg.LinAlgError:
+                    raise OracleError("C_NOT_SPD" if what == "C" else "BREAKDOWN",
+                                      "Cholesky failed")
+        return Factor("chol", n, blocks=blocks)
+    rp, ci, v = _tril_csr(M.tocsr())
+    if kind == "ic0":
+        rc = _lib().orc_ic0(n, _p(rp), _p(ci), _p(v))
+    elif kind == "ildlt0":
+        d = np.zeros(n)
+        rc = _lib().orc_ildlt0(n, _p(rp), _p(ci), _p(v), _p(d))
+    else:
+        raise OracleError("ARG", kind)
+    if rc != 0:
+        raise OracleError("C_NOT_SPD" if what == "C" else "BREAKDOWN",
+                          f"{kind} pivot failure in row {-rc - 1}")
+    return Factor(kind, n, rp, ci, v)
+
+
+# ---------------------------------------------------------------------------
+# Reduced-precision emulation helpers (stored-data rounding only)
+# ---------------------------------------------------------------------------
+
+def round_fp32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_bf16(x):
+    """READING: BF16 storage = round-to-nearest-even of the FP32-rounded value."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(f.shape)
+
+
+# ---------------------------------------------------------------------------
+# The preconditioner
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SLR:
+    A: sp.csr_matrix            # original matrix
+    perm: np.ndarray            # new -> old
+    off_b: np.ndarray
+    off_y: np.ndarray
+    m: int
+    s: int
+    Ap: sp.csr_matrix           # A in DD order
+    E: sp.csr_matrix            # m x s
+    C: sp.csr_matrix            # s x s
+    FB: Factor
+    FC: Factor
+    k: int = 0
+    U: np.ndarray = None        # s x k (C-factor order)
+    lam: np.ndarray = None      # k Ritz values, descending
+    theta: float = 0.0
+    ritz: np.ndarray = None     # all Ritz values of T_m, descending
+    steps: int = 0
+    alpha: np.ndarray = None
+    beta: np.ndarray = None
+    colors: np.ndarray = None
+
+    # -- products with the blocks -------------------------------------------------
+    def G(self, v: np.ndarray) -> np.ndarray:
+        """H v = L^{-1} E^T B^{-1} E L^{-T} v (eq. H), the operator Lanczos
+        runs on (Sec. 5.1)."""
+        t = self.FC.upper(v)
+        e = self.E @ t
+        z = self.FB.solve(e)
+        g = self.E.T @ z
+        return self.FC.lower(g)
+
+    def apply_dd(self, r: np.ndarray) -> np.ndarray:
+        """M^{-1} r in DD order, M of eq. (M) with S~^{-1} of eq. (skt).
+
+        The inverse of the block factorisation needs two solves with B and
+        one with S~ (Sec. 2.2):
+          z  = B^{-1} f
+          g' = g - E^T z
+          S~^{-1} g' = L^{-T}[(1-theta)^{-1} w + U_k D U_k^T w], w = L^{-1} g',
+                       D = diag((1-lambda_i)^{-1} - (1-theta)^{-1})   (eq. skt,
+                       in the L-form used in its proof, Z_k = L^{-T} U_k)
+          u  = B^{-1}(f - E y)."""
+        r = np.asarray(r, dtype=np.float64)
+        f, g = r[:self.m], r[self.m:]
+        z = self.FB.solve(f)
+        gp = g - self.E.T @ z
+        w = self.FC.lower(gp)
+        rho = 1.0 / (1.0 - self.theta)
+        wp = rho * w
+        if self.k:
+            c = self.U.T @ w
+            c = c * (1.0 / (1.0 - self.lam) - rho)
+            wp = wp + self.U @ c
+        y = self.FC.upper(wp)
+        u = self.FB.solve(f - self.E @ y)
+        return np.concatenate([u, y])
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        """M^{-1} r in original order (column-major block of vectors ok)."""
+        r = np.asarray(r, dtype=np.float64)
+        if r.ndim == 2:
+            return np.column_stack([self.apply(r[:, j]) for j in range(r.shape[1])])
+        out = np.empty_like(r)
+        out[self.perm] = self.apply_dd(r[self.perm])
+        return out
+
+
+def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "ic0",
+          c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
+          fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
+          lowrank=None) -> SLR:
+    """Build the SLR preconditioner (Sec. 4 and Sec. 5).
+
+    A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
+    (-1 = separator).  lanczos_steps 0 means 5k (Sec. 6).  v0: Lanczos start
+    vector in original node order (its interface entries are used).
+    lowrank: optional (U, lam, theta) to use instead of running Lanczos."""
+    if isinstance(A, tuple):
+        indptr, indices, data, n = A
+        A = sp.csr_matrix((data, indices, indptr), shape=(n, n))
+    A = sp.csr_matrix(A)
+    if abs(A - A.T).max() > 0:
+        raise OracleError("NOT_SYMMETRIC", "A must be symmetric")
+    perm, off_b, off_y, colors = dd_ordering(A, part, nparts, c_order)
+    m = int(off_b[-1])
+    s = A.shape[0] - m
+    Ap = A[perm][:, perm].tocsr()
+    B = Ap[:m, :m].tocsr()
+    E = Ap[:m, m:].tocsr()
+    C = Ap[m:, m:].tocsr()
+    FB = factorize(B, b_fact, off_b, "B")
+    # exact C solve: one dense block; otherwise IC(0)
+    FC = factorize(C, c_fact, [0, s], "C")
+    FB.round_to(fact_prec)
+    FC.round_to(fact_prec)
+    P = SLR(A, perm, off_b, off_y, m, s, Ap, E, C, FB, FC, colors=colors)
+    if lowrank is not None:
+        U, lam, theta = lowrank
+        P.U = np.array(U, dtype=np.float64).reshape(s, -1)
+        P.lam = np.array(lam, dtype=np.float64)
+        P.k = P.U.shape[1]
+        P.theta = float(theta)
+    elif k > 0:
+        steps = lanczos_steps or 5 * k
+        if v0 is None:
+            v0 = np.random.Generator(np.random.PCG64(7)).uniform(-1, 1, A.shape[0])
+        lanczos_lowrank(P, k, steps, np.asarray(v0)[perm[m:]], theta_mode)
+    else:
+        P.theta = 0.0
+    if uk_prec == "fp32":
+        P.U = round_fp32(P.U)
+    elif uk_prec == "bf16":
+        P.U = round_bf16(P.U)
+    return P
+
+
+def lanczos(G, v0: np.ndarray, steps: int):
+    """Lanczos with full reorthogonalisation (Sec. 5.1).
+
+    READING: full classical Gram-Schmidt applied twice (CGS2) replaces the
+    paper's partial reorthogonalisation; stop after ``steps`` steps or when
+    beta_j <= 1e-14 ||T_j||_inf.  Returns (V, alpha, beta) with V the
+    orthonormal basis actually built (s x m) and beta of length m (its last
+    entry is the residual norm beta_m of the final step)."""
+    s = v0.shape[0]
+    V = np.zeros((s, steps))
+    alpha, beta = [], []
+    V[:, 0] = v0 / np.linalg.norm(v0)
+    tnorm = 0.0
+    for j in range(steps):
+        v = V[:, j]
+        w = G(v)
+        a = float(v @ w)
+        w = w - a * v
+        if j > 0:
+            w = w - beta[j - 1] * V[:, j - 1]
+        for _ in range(2):
+            h = V[:, :j + 1].T @ w
+            w = w - V[:, :j + 1] @ h
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        row = abs(a) + b + (beta[j - 1] if j > 0 else 0.0)
+        tnorm = max(tnorm, row)
+        if j + 1 == steps or b <= 1e-14 * tnorm:
+            return V[:, :j + 1], np.array(alpha), np.array(beta + [b])
+        beta.append(b)
+        V[:, j + 1] = w / b
+
+
+def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode: str):
+    """(U_k, Lambda_k, theta) from Lanczos on H (Sec. 5.1, eq. skt).
+
+    The Ritz pairs of the tridiagonal T_m are sorted by decreasing value;
+    the k largest give Lambda_k and U_k = V_m Y_k; theta = lambda_{k+1}
+    (Sec. 4, the paper's choice) or 0 (eq. Lambda-1, truncation)."""
+    V, alpha, beta = lanczos(P.G, v0_iface, steps)
+    mm = V.shape[1]
+    T = np.diag(alpha) + np.diag(beta[:mm - 1], 1) + np.diag(beta[:mm - 1], -1)
+    ev, Y = np.linalg.eigh(T)
+    ev, Y = ev[::-1], Y[:, ::-1]
+    need = k + 1 if theta_mode == "lambda_k1" else k
+    if mm < need:
+        raise OracleError("LANCZOS_SHORT", f"{mm} Ritz pairs < {need}")
+    P.k = k
+    P.lam = ev[:k].copy()
+    P.U = V @ Y[:, :k]
+    P.theta = float(ev[k]) if theta_mode == "lambda_k1" else 0.0
+    P.ritz = ev
+    P.steps = mm
+    P.alpha, P.beta = alpha, beta
+    if np.any(np.abs(1.0 - P.lam) < 1e-12) or abs(1.0 - P.theta) < 1e-12:
+        raise OracleError("RITZ_SINGULAR", "Ritz value too close to 1")
+    return P
+
+
+# ---------------------------------------------------------------------------
+# C6: Krylov accelerators (Sec. 6: CG for SPD, GMRES(40) for indefinite;
+#     stop when the residual norm is reduced by 1e-8, at most 300 its)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    true_relres: float
+    history: list
+
+
+def _true_relres(A, x, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(b - A @ x) / nb) if nb > 0 else 0.0
+
+
+def pcg(A, M, b, rtol=1e-8, maxit=300, flexible=False) -> SolveResult:
+    """Preconditioned CG, x0 = 0.  READING: stop on the recurrence residual
+    ||r_j|| <= rtol ||b||; the iteration count is the number of products
+    with A.  flexible=True uses the Polak-Ribiere beta (flexible CG)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.linalg.norm(b)
+    hist = [1.0]
+    if nb == 0:
+        return SolveResult(x, 0, True, 0.0, hist)
+    z = M(r)
+    p = z.copy()
+    rz = float(r @ z)
+    for it in range(1, maxit + 1):
+        q = A @ p
+        alpha = rz / float(p @ q)
+        x += alpha * p
+        r_old = r
+        r = r - alpha * q
+        rn = np.linalg.norm(r)
+        hist.append(rn / nb)
+        if rn <= rtol * nb:
+            return SolveResult(x, it, True, _true_relres(A, x, b), hist)
+        z = M(r)
+        rz_new = float(r @ z)
+        beta = (float(z @ (r - r_old)) if flexible else rz_new) / rz
+        rz = rz_new
+        p = z + beta * p
+    return SolveResult(x, maxit, False, _true_relres(A, x, b), hist)
+
+
+def fgmres(A, M, b, rtol=1e-8, maxit=300, restart=40) -> SolveResult:
+    """Right-preconditioned flexible GMRES(restart) (Saad 1993), x0 = 0,
+    modified Gram-Schmidt Arnoldi, Givens rotations.  READING: stop when the
+    least-squares residual estimate falls to rtol ||b||; the iteration count
+    is the number of products with A."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0]
+    x = np.zeros(n)
+    nb = np.linalg.norm(b)
+    hist = [1.0]
+    if nb == 0:
+        return SolveResult(x, 0, True, 0.0, hist)
+    it = 0
+    while True:
+        r = b - A @ x
+        beta = np.linalg.norm(r)
+        V = np.zeros((n, restart + 1))
+        Z = np.zeros((n, restart))
+        H = np.zeros((restart + 1, restart))
+        cs, sn = np.zeros(restart), np.zeros(restart)
+        gvec = np.zeros(restart + 1)
+        gvec[0] = beta
+        V[:, 0] = r / beta
+        j_done = 0
+        done = False
+        for j in range(restart):
+            Z[:, j] = M(V[:, j])
+            w = A @ Z[:, j]
+            it += 1
+            for i in range(j + 1):
+                H[i, j] = float(w @ V[:, i])
+                w = w - H[i, j] * V[:, i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0:
+                V[:, j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            gvec[j + 1] = -sn[j] * gvec[j]
+            gvec[j] = cs[j] * gvec[j]
+            hist.append(abs(gvec[j + 1]) / nb)
+            j_done = j + 1
+            if abs(gvec[j + 1]) <= rtol * nb or it >= maxit:
+                done = True
+                break
+        y = sla.solve_triangular(H[:j_done, :j_done], gvec[:j_done])
+        x = x + Z[:, :j_done] @ y
+        if done:
+            conv = hist[-1] <= rtol
+            return SolveResult(x, it, conv, _true_relres(A, x, b), hist)
+
+
+def solve(P: SLR, b: np.ndarray, method: str = "pcg", rtol=1e-8, maxit=300, restart=40):
+    """Solve A x = b with the SLR preconditioner, in the original ordering."""
+    A = P.A
+    M = P.apply
+    if method == "pcg":
+        return pcg(A, M, b, rtol, maxit)
+    if method == "fcg":
+        return pcg(A, M, b, rtol, maxit, flexible=True)
+    if method == "fgmres":
+        return fgmres(A, M, b, rtol, maxit, restart)
+    raise OracleError("ARG", method)

@@ -1,0 +1,452 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-type the oracle's formulas: each compares the oracle with
+an independent dense computation, a closed form, a value the paper prints,
+or an identity the method must satisfy (Li, Xi & Saad 2015).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle as O
+import slr_inputs as si
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dense_blocks(P):
+    Ad = P.Ap.toarray()
+    m = P.m
+    return Ad, Ad[:m, :m], Ad[:m, m:], Ad[m:, m:]
+
+
+def _dense_H(P):
+    """H = L^{-1} E^T B^{-1} E L^{-T} with L = chol(C), by dense algebra
+    (eq. S, eq. H) -- independent of the oracle's sparse code."""
+    _, B, E, C = _dense_blocks(P)
+    L = np.linalg.cholesky(C)
+    X = np.linalg.solve(B, E)
+    H = sla.solve_triangular(L, E.T @ X, lower=True)
+    H = sla.solve_triangular(L, H.T, lower=True).T
+    return 0.5 * (H + H.T), L
+
+
+def _tiny(N=12, boxes=2, **kw):
+    csr = si.laplacian_2d(N)
+    part = si.box_partition_2d(N, boxes, boxes)
+    return csr, part, boxes * boxes
+
+
+# ---------------------------------------------------------------- generators
+
+def test_generator_closed_form_spectrum_2d_3d():
+    """5/7-point Dirichlet eigenvalues 4 sum sin^2(j pi / (2(N+1))) (the
+    unscaled stencil of Sec. 3.2)."""
+    for N, d in ((9, 2), (5, 3)):
+        csr = si.laplacian_2d(N) if d == 2 else si.laplacian_3d(N)
+        A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(csr[3],) * 2).toarray()
+        l1 = 4 * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
+        grid = np.add.outer(l1, l1) if d == 2 else np.add.outer(np.add.outer(l1, l1), l1)
+        assert np.allclose(np.sort(np.linalg.eigvalsh(A)), np.sort(grid.ravel()), atol=1e-12)
+
+
+def test_shift_gives_requested_negative_count():
+    N = 8
+    s = si.shift_for_negative_count_3d(N, 4)
+    csr = si.laplacian_3d(N, s)
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(csr[3],) * 2).toarray()
+    assert int((np.linalg.eigvalsh(A) < 0).sum()) == 4
+
+
+# ------------------------------------------------------ classification, order
+
+def test_classification_hand_drawn_6x6():
+    """6x6 grid, 2x2 boxes of 3x3: a node is a local interface node iff it
+    has a neighbour in another box (Sec. 2.1) -- lines x in {2,3} or
+    y in {2,3}, drawn by hand."""
+    csr = si.laplacian_2d(6)
+    part = si.box_partition_2d(6, 2, 2)
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(36, 36))
+    iface, _ = O.classify(A, part, 4)
+    expect = np.array([[x in (2, 3) or y in (2, 3) for x in range(6)] for y in range(6)]).ravel()
+    assert (iface == expect).all()
+    perm, off_b, off_y, _ = O.dd_ordering(A, part, 4)
+    # box 0 interior: (0,0),(1,0),(0,1),(1,1)
+    assert perm[:4].tolist() == [0, 1, 6, 7]
+    assert off_b.tolist() == [0, 4, 8, 12, 16]
+    assert off_y.tolist() == [0, 5, 10, 15, 20, 20]
+    # interface of box 0 in ascending index: (2,0),(2,1),(0,2),(1,2),(2,2)
+    assert perm[16:21].tolist() == [2, 8, 12, 13, 14]
+
+
+def test_separator_labels_are_interface_and_neighbours_interior():
+    A, part = si.separator_model(5, 3)
+    M = sp.csr_matrix((A[2], A[1], A[0]), shape=(A[3],) * 2)
+    iface, _ = O.classify(M, part, 2)
+    assert iface.sum() == 5 and (iface == (part < 0)).all()
+
+
+def test_multicolor_is_a_proper_colouring():
+    pr = si.make_config("lap3d_64", N=16, boxes=2)
+    A = pr.scipy()
+    perm, off_b, off_y, colors = O.dd_ordering(A, pr.part, pr.nparts, "multicolor")
+    m = off_b[-1]
+    C = A[perm[m:]][:, perm[m:]].tocoo()
+    assert (colors[C.row[C.row != C.col]] != colors[C.col[C.row != C.col]]).all()
+    assert (np.diff(colors) >= 0).all()
+
+
+# --------------------------------------------------------------- factorisations
+
+def test_ic0_defining_property_and_tridiagonal_exactness():
+    pr = si.make_config("lap3d_64", N=8, boxes=2)
+    A = pr.scipy()
+    F = O.factorize(sp.tril(A).tocsr() + sp.triu(A, 1).tocsr(), "ic0")
+    L = sp.csr_matrix((F.v, F.ci, F.rp), shape=A.shape).toarray()
+    LLt = L @ L.T
+    Ad = A.toarray()
+    mask = np.tril(Ad != 0)
+    assert np.abs((LLt - Ad)[mask]).max() < 1e-13
+    # IC(0) of a tridiagonal matrix has no dropped fill: it is the Cholesky factor
+    T = sp.csr_matrix(sp.diags([-np.ones(29), 2.5 * np.ones(30), -np.ones(29)], [-1, 0, 1]))
+    F1 = O.factorize(T, "ic0")
+    L1 = sp.csr_matrix((F1.v, F1.ci, F1.rp), shape=T.shape).toarray()
+    assert np.allclose(L1, np.linalg.cholesky(T.toarray()), atol=1e-14)
+
+
+def test_ildlt0_defining_property_on_indefinite_pattern():
+    csr = si.laplacian_3d(6, shift=5.5)
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(csr[3],) * 2)
+    F = O.factorize(A, "ildlt0")
+    M = sp.csr_matrix((F.v, F.ci, F.rp), shape=A.shape).toarray()
+    D = np.diag(M).copy()
+    L = np.tril(M, -1) + np.eye(A.shape[0])
+    Ad = A.toarray()
+    mask = np.tril(Ad != 0)
+    assert np.abs((L @ np.diag(D) @ L.T - Ad)[mask]).max() < 1e-12
+    assert (D < 0).any()
+
+
+def test_triangular_sweeps_match_dense_solves():
+    pr = si.make_config("lap3d_64", N=8, boxes=2)
+    A = pr.scipy()
+    rng = np.random.default_rng(3)
+    for kind in ("ic0", "ildlt0", "chol"):
+        F = O.factorize(A, kind)
+        L = F.dense_lower(0, A.shape[0])
+        if kind == "ildlt0":
+            D = np.diag(L).copy()
+            L = np.tril(L, -1) + np.eye(A.shape[0])
+        b = rng.standard_normal(A.shape[0])
+        assert np.allclose(F.lower(b), sla.solve_triangular(L, b, lower=True), atol=1e-12)
+        assert np.allclose(F.upper(b), sla.solve_triangular(L, b, lower=True, trans="T"), atol=1e-12)
+        if kind == "chol":
+            assert np.allclose(L @ L.T, A.toarray(), atol=1e-12)
+            assert np.allclose(F.solve(b), np.linalg.solve(A.toarray(), b), atol=1e-10)
+
+
+def test_exact_B_blocks_are_31x31_dirichlet_laplacians():
+    """In the 64x64 / 2x2 configuration each interior block B_i is the
+    5-point Laplacian of a 31x31 Dirichlet grid (closed-form spectrum)."""
+    pr = si.make_config("lap2d_64")
+    P = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact="chol", c_fact="chol")
+    assert P.m == 4 * 961 and P.s == 252
+    B0 = P.Ap[:961][:, :961].toarray()
+    l1 = 4 * np.sin(np.arange(1, 32) * np.pi / 64) ** 2
+    assert np.allclose(np.sort(np.linalg.eigvalsh(B0)), np.sort(np.add.outer(l1, l1).ravel()), atol=1e-11)
+
+
+# -------------------------------------------------- operator H and spectrum
+
+def test_G_matches_dense_H_and_lemma_bounds():
+    """eq. H by dense algebra; Lemma (A SPD => 0 <= lambda(H) < 1)."""
+    csr, part, p = _tiny(14)
+    P = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol")
+    H, _ = _dense_H(P)
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(P.s)
+    assert np.allclose(P.G(v), H @ v, atol=1e-12)
+    ev = np.linalg.eigvalsh(H)
+    assert ev.min() > -1e-12 and ev.max() < 1.0
+
+
+def test_lanczos_ritz_values_match_dense_spectrum_and_residual_bound():
+    """Lanczos on H (Sec. 5.1): converged top Ritz values equal dense
+    eigenvalues; Ritz residual ||H u - lambda u|| = beta_m |e_m^T y|."""
+    pr = si.make_config("lap2d_64")
+    P = O.setup(pr.csr, pr.part, pr.nparts, pr.k, pr.lanczos_steps, "chol", "chol", v0=pr.v0())
+    H, _ = _dense_H(P)
+    ev = np.sort(np.linalg.eigvalsh(H))[::-1]
+    assert np.all(P.ritz < 1.0) and P.ritz.min() > -1e-12
+    mm = P.steps
+    T = np.diag(P.alpha) + np.diag(P.beta[:mm - 1], 1) + np.diag(P.beta[:mm - 1], -1)
+    tev, Y = np.linalg.eigh(T)
+    tev, Y = tev[::-1], Y[:, ::-1]
+    near = np.abs(P.ritz[:, None] - ev[None, :]).min(axis=1)
+    for i in range(pr.k + 1):
+        bound = P.beta[-1] * abs(Y[-1, i])        # ||H u_i - lambda_i u_i||
+        if i < pr.k:
+            res = np.linalg.norm(H @ P.U[:, i] - P.lam[i] * P.U[:, i])
+            assert abs(res - bound) < 1e-10
+        # for symmetric H an eigenvalue lies within the residual of a Ritz value
+        assert near[i] <= bound + 1e-12
+    assert abs(P.ritz[0] - ev[0]) < 1e-12
+
+
+def test_full_lanczos_equals_dense_spectrum_with_breakdown():
+    """With steps >= s and distinct eigenvalues, Lanczos spans the space and
+    every eigenvalue of H is recovered; it stops on beta ~ 0."""
+    A, part = si.separator_model(24, 10)
+    P = O.setup(A, part, 2, 8, 60, "chol", "chol")
+    H, _ = _dense_H(P)
+    assert P.steps == P.s == 24
+    assert np.allclose(np.sort(P.ritz), np.sort(np.linalg.eigvalsh(H)), atol=1e-12)
+
+
+# ------------------------------------------------------ the preconditioner
+
+def _dense_lowrank(P, k, theta_mode="lambda_k1"):
+    H, L = _dense_H(P)
+    lam, U = np.linalg.eigh(H)
+    lam, U = lam[::-1], U[:, ::-1]
+    theta = lam[k] if (theta_mode == "lambda_k1" and k < len(lam)) else 0.0
+    return H, L, lam, U, theta
+
+
+def test_P1_full_rank_exact_solves_make_M_equal_A():
+    """k = s with exact B and C: S~ = S, so M = A (eq. M with eq. Sinv) and
+    M^{-1} A x = x; PCG converges in one iteration."""
+    csr, part, p = _tiny(12)
+    P0 = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol")
+    H, L, lam, U, _ = _dense_lowrank(P0, P0.s)
+    P = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol", lowrank=(U, lam, 0.0))
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, P.A.shape[0])
+    assert np.abs(P.apply(P.A @ x) - x).max() < 1e-11
+    res = O.solve(P, P.A @ x, "pcg")
+    assert res.iters == 1 and res.true_relres < 1e-12
+    res = O.solve(P, P.A @ x, "fgmres")
+    assert res.iters == 1 and res.true_relres < 1e-12
+
+
+def test_P6_skt_form_equals_tildeSinv_and_schur_bruteforce():
+    """Interface part of M^{-1}(0; g) equals S~^{-1} g with S~^{-1} built
+    from ALL eigenvectors by eq. tildeSinv (Lambda~ = Lambda_k, theta on the
+    tail, eq. main); the oracle uses only k of them (Prop. skt).  With
+    k = s it equals S^{-1} g, S = C - E^T B^{-1} E formed densely (eq. Schur)."""
+    csr, part, p = _tiny(14)
+    P0 = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol")
+    _, B, E, C = _dense_blocks(P0)
+    S = C - E.T @ np.linalg.solve(B, E)
+    for k in (3, 9):
+        H, L, lam, U, theta = _dense_lowrank(P0, k)
+        P = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol",
+                    lowrank=(U[:, :k], lam[:k], theta))
+        lt = np.concatenate([lam[:k], np.full(P.s - k, theta)])
+        Linv = np.linalg.inv(L)
+        St_inv = Linv.T @ U @ np.diag(1.0 / (1.0 - lt)) @ U.T @ Linv
+        g = np.random.default_rng(k).standard_normal(P.s)
+        r = np.concatenate([np.zeros(P.m), g])
+        out = P.apply_dd(r)
+        assert np.allclose(out[P.m:], St_inv @ g, atol=1e-11)
+        assert np.allclose(out[:P.m], -np.linalg.solve(B, E @ out[P.m:]), atol=1e-11)
+    H, L, lam, U, _ = _dense_lowrank(P0, P0.s)
+    P = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol", lowrank=(U, lam, 0.0))
+    g = np.random.default_rng(5).standard_normal(P.s)
+    out = P.apply_dd(np.concatenate([np.zeros(P.m), g]))
+    assert np.allclose(out[P.m:], np.linalg.solve(S, g), atol=1e-10)
+
+
+def _spectrum_MinvA(P):
+    n = P.A.shape[0]
+    Ad = P.A.toarray()
+    MA = np.column_stack([P.apply(Ad[:, j]) for j in range(n)])
+    return np.sort(np.linalg.eigvals(MA).real)
+
+
+@pytest.mark.parametrize("theta_mode", ["lambda_k1", "zero"])
+def test_P2_P7_spectrum_of_preconditioned_matrix(theta_mode):
+    """eig(M^{-1}A) = {1}^(m+k) U {(1 - lambda_i)/(1 - theta)}_{i>k}
+    (Prop. eigSS with eq. main; theta = 0 is eq. Lambda-1), and
+    kappa(S S~^{-1}) = (1-lambda_s)/(1-lambda_{k+1}) for theta = lambda_{k+1}
+    (Prop. kappa)."""
+    csr, part, p = _tiny(10)
+    P0 = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol")
+    k = 5
+    H, L, lam, U, theta = _dense_lowrank(P0, k, theta_mode)
+    P = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol", lowrank=(U[:, :k], lam[:k], theta))
+    got = _spectrum_MinvA(P)
+    expect = np.sort(np.concatenate([np.ones(P.m + k), (1 - lam[k:]) / (1 - theta)]))
+    assert np.allclose(got, expect, atol=1e-9)
+    if theta_mode == "lambda_k1":
+        sig = (1 - lam[k:]) / (1 - theta)
+        kappa = max(sig.max(), 1.0) / min(sig.min(), 1.0)
+        assert math.isclose(kappa, (1 - lam[-1]) / (1 - lam[k]), rel_tol=1e-12)
+
+
+def test_P3prime_inertia_counts_negative_eigenvalues():
+    """Indefinite A with SPD B (exact solves): by Sylvester's law on
+    eq. Schur, #{lambda(H) > 1} = #negative eigenvalues of A."""
+    N = 10
+    s = si.shift_for_negative_count_3d(N, 4)
+    csr = si.laplacian_3d(N, s)
+    part = si.box_partition_3d(N, 2)
+    P = O.setup(csr, part, 8, 0, b_fact="chol", c_fact="chol")
+    H, _ = _dense_H(P)
+    A = P.A.toarray()
+    nneg = int((np.linalg.eigvalsh(A) < 0).sum())
+    assert nneg == 4
+    assert int((np.linalg.eigvalsh(H) > 1).sum()) == nneg
+    # the oracle's Lanczos sees them among its largest Ritz values
+    Pl = O.setup(csr, part, 8, 8, 40, "chol", "chol", v0=si.lanczos_start(csr[3], 3))
+    assert int((Pl.ritz > 1).sum()) >= 1
+    assert np.all(np.abs(Pl.ritz[:3] - np.sort(np.linalg.eigvalsh(H))[::-1][:3]) < 1e-8)
+
+
+def test_P4_two_domain_closed_form_matches_bruteforce():
+    """eq. gammak0: eigenvalues of S^{-1} - C^{-1} in the separator model
+    (Prop. of Sec. 3.2, eq. etak0) against dense brute force."""
+    nx, ny = 20, 10
+    A, part = si.separator_model(nx, ny)
+    P = O.setup(A, part, 2, 0, b_fact="chol", c_fact="chol")
+    _, B, E, C = _dense_blocks(P)
+    S = C - E.T @ np.linalg.solve(B, E)
+    got = np.sort(np.linalg.eigvalsh(np.linalg.inv(S) - np.linalg.inv(C)))
+    kk = np.arange(1, nx + 1)
+    eta = 1 + 2 * np.sin(kk * np.pi / (2 * (nx + 1))) ** 2
+    th = np.arccosh(eta)
+    gamma = np.sinh(ny * th) / (eta * (np.sinh((ny + 2) * th) - np.sinh(ny * th)))
+    assert np.allclose(got, np.sort(gamma), rtol=1e-12, atol=1e-14)
+
+
+def _separator_lambda(nx, ny):
+    kk = np.arange(1, nx + 1)
+    eta = 1 + 2 * np.sin(kk * np.pi / (2 * (nx + 1))) ** 2
+    th = np.arccosh(eta)
+    gamma = np.sinh(ny * th) / (eta * (np.sinh((ny + 2) * th) - np.sinh(ny * th)))
+    zeta = 2 * eta * gamma
+    return np.sort(zeta / (1 + zeta))[::-1]
+
+
+def test_P4_fig_kappa_printed_values_from_closed_form():
+    """The values printed with the kappa(theta) figure (Sec. 4) follow from
+    the two-domain closed form: lambda(H) = zeta/(1+zeta), zeta = 2 eta gamma."""
+    g = json.load(open(os.path.join(GOLDEN, "fig_kappa.json")))
+    lam = _separator_lambda(g["nx"], g["ny"])
+    k = g["k"]
+    assert round(lam[-1], 5) == g["lambda_s"]
+    assert round(lam[k], 5) == g["lambda_k1"]
+    assert round((1 - lam[-1]) / (1 - lam[k]), 4) == g["kappa"]
+
+
+@pytest.mark.slow
+def test_P4_fig_kappa_through_oracle_lanczos():
+    """The oracle's own Lanczos on the 256 x 513 separator grid, exact
+    solves, k = 64, 5k = 320 >= s steps, reproduces the printed values."""
+    g = json.load(open(os.path.join(GOLDEN, "fig_kappa.json")))
+    A, part = si.separator_model(g["nx"], g["ny"])
+    P = O.setup(A, part, 2, g["k"], 0, "chol", "chol", v0=si.lanczos_start(A[3], 7))
+    assert P.steps == P.s == g["nx"]
+    lam_s = P.ritz[-1]
+    kappa = (1 - lam_s) / (1 - P.theta)
+    assert round(lam_s, 5) == g["lambda_s"]
+    assert round(P.theta, 5) == g["lambda_k1"]
+    assert round(kappa, 4) == g["kappa"]
+    assert np.allclose(P.ritz, _separator_lambda(g["nx"], g["ny"]), atol=1e-11)
+
+
+# --------------------------------------------------------------- Krylov
+
+def test_krylov_iteration_counts_on_known_spectra():
+    """CG / flexible CG / FGMRES take exactly d iterations on a matrix with
+    d distinct eigenvalues (identity preconditioner), and with the exact
+    inverse as preconditioner one iteration."""
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    d = np.repeat([1.0, 3.0, 7.0], [10, 15, 15])
+    A = sp.csr_matrix(Q @ np.diag(d) @ Q.T)
+    b = rng.standard_normal(40)
+    for fl in (False, True):
+        r = O.pcg(A, lambda v: v, b, rtol=1e-10, flexible=fl)
+        assert r.iters == 3 and r.true_relres < 1e-9
+    r = O.fgmres(A, lambda v: v, b, rtol=1e-10)
+    assert r.iters == 3 and r.true_relres < 1e-9
+    Ainv = np.linalg.inv(A.toarray())
+    assert O.pcg(A, lambda v: Ainv @ v, b).iters == 1
+    # restart: GMRES(2) on 3 distinct eigenvalues needs more than 3 products
+    r = O.fgmres(A, lambda v: v, b, rtol=1e-10, restart=2, maxit=200)
+    assert r.converged and r.iters > 3
+
+
+def test_pcg_solves_the_small_configuration():
+    pr = si.make_config("lap2d_64")
+    P = O.setup(pr.csr, pr.part, pr.nparts, pr.k, pr.lanczos_steps, "chol", "chol", v0=pr.v0())
+    x, b = pr.rhs()
+    r = O.solve(P, b[:, 0])
+    assert r.converged and r.true_relres <= 1e-8
+    assert np.abs(r.x - x[:, 0]).max() < 1e-6
+
+
+# ------------------------------------------------------- precision emulation
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    import torch
+    rng = np.random.default_rng(9)
+    x = np.concatenate([rng.standard_normal(2000), [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -0.0, 1e-30]])
+    ref = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert (O.round_bf16(x) == ref).all()
+    assert O.round_bf16(np.array([1.0 + 2 ** -8]))[0] == 1.0
+
+
+# ------------------------------------------- planted mistakes must be caught
+
+def test_planted_mistakes_fail_the_pins(monkeypatch):
+    """A sign error, a transposed factor, or a dropped scalar in the apply
+    breaks the M = A identity (P1); a wrong factor in G breaks eq. H."""
+    csr, part, p = _tiny(10)
+    P0 = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol")
+    H, L, lam, U, _ = _dense_lowrank(P0, P0.s)
+    x = np.random.default_rng(2).uniform(-1, 1, P0.A.shape[0])
+
+    def p1_error(P):
+        return np.abs(P.apply(P.A @ x) - x).max()
+
+    good = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol", lowrank=(U, lam, 0.0))
+    assert p1_error(good) < 1e-11
+    orig = O.SLR.apply_dd
+
+    def sign_flip(self, r):
+        r2 = np.array(r, copy=True)
+        E = self.E
+        self.E = -E
+        try:
+            return orig(self, r2)
+        finally:
+            self.E = E
+    monkeypatch.setattr(O.SLR, "apply_dd", sign_flip)
+    assert p1_error(good) > 1e-3
+    monkeypatch.setattr(O.SLR, "apply_dd", orig)
+
+    # lower/upper swapped in the interface solve
+    F = good.FC
+    lo, up = F.lower, F.upper
+    monkeypatch.setattr(F, "lower", up)
+    monkeypatch.setattr(F, "upper", lo)
+    assert p1_error(good) > 1e-3 or np.abs(good.G(np.ones(good.s)) - H @ np.ones(good.s)).max() > 1e-6
+    monkeypatch.setattr(F, "lower", lo)
+    monkeypatch.setattr(F, "upper", up)
+
+    # dropped (1 - theta)^{-1} scaling with theta != 0
+    k = 4
+    H, L, lam, U, theta = _dense_lowrank(P0, k)
+    Pk = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol", lowrank=(U[:, :k], lam[:k], theta))
+    spec = _spectrum_MinvA(Pk)
+    expect = np.sort(np.concatenate([np.ones(Pk.m + k), (1 - lam[k:]) / (1 - theta)]))
+    assert np.allclose(spec, expect, atol=1e-9)
+    Pk.theta = 0.0   # keeps the same U, lam: drops the theta scaling
+    assert not np.allclose(_spectrum_MinvA(Pk), expect, atol=1e-6)
