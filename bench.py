@@ -1,0 +1,190 @@
+"""Benchmark of the SLR hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp64|mixed]
+
+Workload: 3-D 7-point Laplacian on a 64^3 grid (n = 262,144), 4x4x4 box
+decomposition (64 subdomains), IC(0) factors of the B_i and of C, rank
+k = 32 from 160 Lanczos steps, PCG to rtol 1e-8, one right-hand side
+b = A x*, x* ~ U[-1, 1] (seeded).
+
+One step = one pass of the whole hot path on the device: the Lanczos build
+of (U_k, Lambda_k, theta) on H with the resident factors, then the
+preconditioned Krylov solve (every iteration: SpMV, BLAS-1, the SLR apply
+with its two batched B solves, interface sweeps and rank-k block).  Host
+factorisation is setup and is not timed.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "PCG solves/s at rtol 1e-8, SLR-apply HBM GB/s; p50/p99 latency mixed vs FP64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+FORMS = {
+    # FP64 factors and U_k, plain PCG
+    "fp64": dict(fact_prec="fp64", uk_prec="fp64", method="pcg", c_order="multicolor", dtype="f64"),
+    # FP32 factors / U_k inside the apply, flexible CG with FP64 recurrences
+    "mixed": dict(fact_prec="fp32", uk_prec="fp32", method="fcg", c_order="multicolor", dtype="f32-apply/f64-krylov"),
+}
+
+
+def bsolve_bytes(info, nrhs, bf):
+    """Algorithmic bytes of one batched B-solve launch (apply, first half):
+    every stored factor entry of the forward and backward sweeps read once
+    (value + 4-byte index; a diagonal counts as one entry), E^T entries read
+    once, f read once, g read once and g' written once per column."""
+    return ((2 * info["nnz_LB"] + info["nnz_E"]) * (bf + 4)
+            + nrhs * (info["m"] * 8 + 2 * info["s"] * 8))
+
+
+def apply_bytes(info, nrhs, bf, bu, k):
+    """Algorithmic bytes of one whole apply: four B sweeps, two interface
+    sweeps, E and E^T once each, U_k read twice, vectors once each."""
+    return ((4 * info["nnz_LB"] + 2 * info["nnz_LC"] + 2 * info["nnz_E"]) * (bf + 4)
+            + 2 * info["s"] * k * bu
+            + nrhs * (2 * info["n"] * 8 + 2 * info["m"] * 8 + 8 * info["s"] * 8))
+
+
+def cpu_baseline(pr, form, budget_s=30.0):
+    """The oracle, single-threaded, on a bounded sample of the same workload:
+    one full step (Lanczos build + PCG solve of the one right-hand side)."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    with threadpool_limits(1):
+        P = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=pr.b_fact, c_fact=pr.c_fact,
+                    c_order=form["c_order"], fact_prec=form["fact_prec"])
+        v0 = pr.v0()[P.perm[P.m:]]
+        xs, b = pr.rhs()
+        t0 = time.perf_counter()
+        O.lanczos_lowrank(P, pr.k, pr.lanczos_steps, v0, "lambda_k1")
+        if form["uk_prec"] == "fp32":
+            P.U = O.round_fp32(P.U)
+        t1 = time.perf_counter()
+        res = O.solve(P, b[:, 0], "fcg" if form["method"] == "fcg" else "pcg")
+        t2 = time.perf_counter()
+    return {"value": 1.0 / (t2 - t0), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one full step on the same workload (oracle Lanczos {pr.lanczos_steps} steps "
+                       f"{t1 - t0:.2f} s + PCG {res.iters} its {t2 - t1:.2f} s), 1 thread"),
+            "oracle_iters": res.iters, "oracle_relres": res.true_relres}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--form", choices=sorted(FORMS), default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", default="lap3d_64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is a design note, not a built path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1505_04340_amd as P
+    import slr_inputs as si
+
+    form = FORMS[args.form]
+    pr = si.make_config(args.config)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    log(f"[bench] setup {pr.name} n={pr.n} p={pr.nparts} k={pr.k} form={args.form}")
+    t0 = time.perf_counter()
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order=form["c_order"], fact_prec=form["fact_prec"],
+              uk_prec=form["uk_prec"], v0=pr.v0())
+    torch.cuda.synchronize()
+    info = G.query()
+    log(f"[bench] setup done in {time.perf_counter() - t0:.2f} s (host {info['setup_host_s']:.2f} s, "
+        f"Lanczos {info['setup_lanczos_s']:.3f} s); s={info['s']} m={info['m']}")
+    xs, b = pr.rhs()
+    bd = torch.tensor(b[:, 0], dtype=torch.float64, device="cuda")
+    v0 = pr.v0()
+
+    def step():
+        G.update_lowrank(pr.k, pr.lanczos_steps, v0)
+        return G.solve(bd, form["method"], rtol=1e-8, maxit=300)
+
+    for i in range(args.warmup):
+        x, inf = step()
+        log(f"[bench] warmup {i}: iters {inf[0]['iters']} relres {inf[0]['relres']:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for i in range(args.steps):
+        x, inf = step()
+        iters.append(inf[0]["iters"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log(f"[bench] {args.steps} steps in {el:.3f} s; iters {iters}; relres {inf[0]['relres']:.2e}")
+    relres = inf[0]["relres"]
+    err = float(np.abs(x.cpu().numpy() - xs[:, 0]).max())
+
+    # solve-only rate (preconditioner resident) and stage timings
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ns = max(3, args.steps)
+    for i in range(ns):
+        G.solve(bd, form["method"], rtol=1e-8, maxit=300)
+    torch.cuda.synchronize()
+    solve_only = ns / (time.perf_counter() - t1)
+    t2 = time.perf_counter()
+    nl = max(2, args.steps // 2)
+    for i in range(nl):
+        G.update_lowrank(pr.k, pr.lanczos_steps, v0)
+    torch.cuda.synchronize()
+    lanczos_ms = 1e3 * (time.perf_counter() - t2) / nl
+    stages = {st: G.time_kernel(st, 1, 50) for st in ("bsolve1", "cfwd", "lowrank", "cbwd", "bsolve2",
+                                                      "apply", "spmv")}
+    log("[bench] stage ms: " + ", ".join(f"{k} {v:.4f}" for k, v in stages.items()))
+    bf = 8 if form["fact_prec"] == "fp64" else 4
+    bu = {"fp64": 8, "fp32": 4, "bf16": 2}[form["uk_prec"]]
+    ab = apply_bytes(info, 1, bf, bu, info["k"])
+    bb = bsolve_bytes(info, 1, bf)
+    dom = "bsolve1"
+    achieved = bb / (stages[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "k_bsolve (batched B_i solves + E^T epilogue)",
+            "algorithmic_bytes_per_launch": int(bb), "avg_launch_ms": round(stages[dom], 5)}
+    out = {
+        "metric": METRIC, "value": round(args.steps / el, 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": form["dtype"],
+        "data": "synthetic",
+        "config": {"workload": "3-D 7-point Laplacian 64^3 (n=262144), 4x4x4 boxes (64 subdomains), "
+                               "IC(0) B_i and C (multicolour C ordering), k=32 from 160 Lanczos steps, "
+                               "PCG rtol 1e-8, 1 RHS; step = device Lanczos build + solve",
+                   "form": args.form, "nrhs": 1},
+        "roofline": roof,
+        "iters": iters[-1], "final_relres_fp64": relres, "max_abs_err_vs_xstar": err,
+        "solve_only_solves_per_s": round(solve_only, 3), "lanczos_build_ms": round(lanczos_ms, 3),
+        "apply_ms": round(stages["apply"], 5),
+        "apply_algorithmic_GBs": round(ab / (stages["apply"] * 1e-3) / 1e9, 2),
+        "stage_ms": {k: round(v, 5) for k, v in stages.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle, 1 thread) ...")
+        out["cpu_baseline"] = cpu_baseline(pr, form)
+        log(f"[bench] CPU baseline {out['cpu_baseline']['value']:.4f} solves/s")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

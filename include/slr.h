@@ -1,0 +1,241 @@
+/*
+ * slr.h -- C ABI of the MI355X (gfx950) Schur-complement low-rank (SLR)
+ * preconditioner library.
+ *
+ * Method: R. Li, Y. Xi, Y. Saad, "Schur complement based domain
+ * decomposition preconditioners with low-rank corrections" (2015).
+ *
+ * Problem: A x = b with A sparse symmetric (eq. linsys), split by a p-way
+ * vertex-based partition into interiors and an interface (Sec. 2.1,
+ * eq. Global / Global2):
+ *
+ *        [ B   E ] [u]   [f]        S = C - E^T B^{-1} E      (eq. Schur)
+ *        [ E^T C ] [y] = [g],       C = L L^T,  H = L^{-1} E^T B^{-1} E L^{-T}
+ *
+ * The preconditioner is M = [I; E^T B^{-1} I] [B E; 0 S~] (eq. M) with
+ *   S~^{-1} = (1-theta)^{-1} C^{-1} + L^{-T} U_k [(I-Lambda_k)^{-1} - (1-theta)^{-1} I] U_k^T L^{-1}
+ * (eq. skt written with Z_k = L^{-T} U_k), where (U_k, Lambda_k) are the k
+ * largest Ritz pairs of H from Lanczos (Sec. 5.1) and theta = lambda_{k+1}
+ * (Sec. 4) or 0 (eq. Lambda-1).
+ *
+ * Conventions shared by every entry point:
+ *  - All integers are 0-based.  Vectors are FP64.  Blocks of nrhs vectors
+ *    are column-major with leading dimension n (original node order).
+ *  - Pointers named *_dev are device pointers (hipMalloc'd, or
+ *    torch.Tensor.data_ptr()); all other pointers are host pointers.
+ *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the default
+ *    stream).  Calls that return host results synchronise that stream.
+ *  - Every call returns SLR_OK (0) or a negative SLR_ERR_* code and never
+ *    throws; slr_last_error() gives a message for the calling thread.
+ *  - A context is not thread-safe.  Several contexts may share a device.
+ *  - The library copies what it needs from caller buffers during a call
+ *    and never retains caller pointers past the call.
+ */
+#ifndef SLR_H
+#define SLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+  SLR_OK = 0,
+  SLR_ERR_ARG = -1,            /* invalid argument / unsupported option      */
+  SLR_ERR_NOT_SYMMETRIC = -2,  /* A's pattern or values are not symmetric    */
+  SLR_ERR_PARTITION = -3,      /* labels out of range / unsupported layout   */
+  SLR_ERR_BREAKDOWN = -4,      /* factorisation pivot of a B_i failed        */
+  SLR_ERR_C_NOT_SPD = -5,      /* factorisation of C failed (C must be SPD)  */
+  SLR_ERR_RITZ_SINGULAR = -6,  /* |1 - lambda_i| < 1e-12 or |1 - theta| < 1e-12 */
+  SLR_ERR_LANCZOS_SHORT = -7,  /* Lanczos produced fewer than the needed Ritz pairs */
+  SLR_ERR_NOCONV = -8,         /* a right-hand side did not converge (x written) */
+  SLR_ERR_OOM = -9,            /* device allocation failed                   */
+  SLR_ERR_HIP = -10,           /* a HIP runtime call failed                  */
+  SLR_ERR_ADMIT = -11          /* batch admission refused (no slot / memory) */
+};
+
+/* ---- options -------------------------------------------------------------- */
+enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1 };
+enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2 };
+enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1 };
+enum { SLR_FP64 = 0, SLR_FP32 = 1, SLR_BF16 = 2 };
+enum { SLR_PCG = 0, SLR_FCG = 1, SLR_FGMRES = 2 };
+
+typedef struct {
+  int64_t n;              /* order of A                                      */
+  int64_t nnz;            /* stored entries (full symmetric pattern)         */
+  const int64_t *rowptr;  /* host, n+1                                       */
+  const int32_t *col;     /* host, nnz, sorted ascending within each row     */
+  const double *val;      /* host, nnz                                       */
+} slr_csr;
+
+typedef struct {
+  int32_t k;              /* rank of the correction (Sec. 4); 0 = none        */
+  int32_t lanczos_steps;  /* 0 => 5k (Sec. 6)                                 */
+  int32_t theta_mode;     /* SLR_THETA_LAMBDA_K1 (Sec. 4) | SLR_THETA_ZERO    */
+  int32_t b_fact;         /* local solver of the B_i (Sec. 5.2): CHOL|IC0|ILDLT0 */
+  int32_t c_fact;         /* factor of C = L L^T: CHOL | IC0                  */
+  int32_t c_order;        /* ordering of the interface for C's factor         */
+  int32_t fact_prec;      /* SLR_FP64 | SLR_FP32: storage and arithmetic of the
+                             B_i / C solves inside the apply                   */
+  int32_t uk_prec;        /* SLR_FP64 | SLR_FP32 | SLR_BF16: storage of U_k  */
+  uint64_t seed;          /* Lanczos start vector when lanczos_v0 == NULL     */
+  const double *lanczos_v0; /* host, n (original order); its interface
+                               entries start Lanczos.  May be NULL.           */
+  /* Optional low-rank part supplied by the caller instead of Lanczos
+     (Sec. 5.3: an SLR preconditioner can be updated without rebuilding).
+     U_in: host, s x k_in column-major, rows in the library's interface
+     order (see slr_export perm); lambda_in: host, k_in.                      */
+  int32_t k_in;
+  const double *U_in;
+  const double *lambda_in;
+  double theta_in;
+} slr_opts;
+
+typedef struct {
+  int32_t method;         /* SLR_PCG | SLR_FCG (flexible CG) | SLR_FGMRES   */
+  int32_t restart;        /* FGMRES restart length (default 40, Sec. 6)      */
+  int32_t maxit;          /* default 300 (Sec. 6)                            */
+  int32_t check_every;    /* host convergence poll period in iterations      */
+  double rtol;            /* ||r_j|| <= rtol ||b|| (default 1e-8, Sec. 6)     */
+} slr_solve_opts;
+
+typedef struct {
+  int32_t iters;          /* products with A                                 */
+  int32_t status;         /* SLR_OK or SLR_ERR_NOCONV                        */
+  double relres;          /* final true ||b - A x|| / ||b||, FP64            */
+} slr_solve_info;
+
+typedef struct {
+  int64_t n, m, s;        /* unknowns, interior, interface                   */
+  int32_t p;              /* subdomains                                      */
+  int32_t k;              /* rank in use                                     */
+  int32_t lanczos_steps;  /* steps actually taken                            */
+  int32_t b_levels_max;   /* deepest level schedule of a B_i sweep           */
+  int32_t c_levels;       /* level count of C's forward sweep                */
+  int32_t c_colors;       /* colours (multicolour ordering) or 0             */
+  int64_t nnz_LB, nnz_LC, nnz_E, nnz_A; /* incl. diagonals for L_B, L_C      */
+  int64_t m_min, m_max;   /* smallest / largest subdomain interior           */
+  double theta;
+  double setup_host_s;    /* host factorisation + analysis time              */
+  double setup_lanczos_s; /* device Lanczos + eigensolve time                */
+  int64_t device_bytes;   /* persistent device memory held by the context    */
+} slr_info;
+
+typedef struct slr_ctx slr_ctx;
+typedef struct slr_batch slr_batch;
+
+/* slr_default_opts / slr_default_solve_opts: fill with the paper's defaults
+ * (theta = lambda_{k+1}, IC(0) factors, 5k Lanczos steps, rtol 1e-8,
+ * maxit 300, GMRES restart 40; Sec. 4 and Sec. 6). */
+void slr_default_opts(slr_opts *o);
+void slr_default_solve_opts(slr_solve_opts *o);
+
+/* slr_setup: build the preconditioner for A and partition `part`
+ * (host, n labels in 0..p-1; vertex-based partitioning of Sec. 2.1).
+ * Classification, DD ordering (eq. Global), the B_i and C factorisations
+ * and level schedules run on the host; the factors are uploaded and the
+ * Lanczos build of (U_k, Lambda_k, theta) on H (eq. H, Sec. 5.1) runs on
+ * the device.  Errors: ARG, NOT_SYMMETRIC, PARTITION (labels out of range
+ * or separator labels -1, which the device path does not take),
+ * BREAKDOWN, C_NOT_SPD, RITZ_SINGULAR, LANCZOS_SHORT, OOM, HIP. */
+int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *o,
+              void *hip_stream, slr_ctx **out);
+
+/* slr_analyze: the host part of slr_setup only (classification, DD
+ * ordering, factorisations, level schedules) -- no device memory is
+ * touched.  Fills `info` (sizes, nnz, level depths; k, theta and the
+ * Lanczos fields are 0; device_bytes is the estimated persistent device
+ * footprint of slr_setup) and, if perm != NULL, the internal -> original
+ * permutation (n int64).  Same errors as slr_setup's host part. */
+int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *o, slr_info *info,
+                int64_t *perm);
+
+/* slr_update_lowrank: rebuild (U_k, Lambda_k, theta) on the device by a
+ * fresh Lanczos run on H with the resident factors (Sec. 5.1); k <= 64,
+ * lanczos_steps 0 => 5k, lanczos_v0 as in slr_opts (NULL => seed).  An
+ * SLR preconditioner can be improved this way without refactoring
+ * (Sec. 5.3).  Synchronises hip_stream.  Errors as slr_setup's Lanczos. */
+int slr_update_lowrank(slr_ctx *c, int32_t k, int32_t lanczos_steps, const double *lanczos_v0,
+                       void *hip_stream);
+
+/* slr_time_kernel: average device time (ms, via HIP events on hip_stream)
+ * of `reps` back-to-back launches of one hot-path stage on nrhs internal
+ * scratch columns, in the launch configuration slr_apply_dd uses:
+ * 0 = first batched B solve (B^{-1} f with the E^T epilogue),
+ * 1 = interface forward sweep, 2 = rank-k block, 3 = interface backward
+ * sweep, 4 = second batched B solve (E y prologue), 5 = whole apply,
+ * 6 = SpMV with A.  Inputs are deterministic filler values. */
+int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void *hip_stream, double *ms);
+
+/* slr_apply: z = M^{-1} r for nrhs vectors (eq. M with eq. skt).  r_dev,
+ * z_dev: device, n x nrhs column-major, original order; may not alias.
+ * Two B solves, one S~ solve (Sec. 2.2).  Asynchronous on hip_stream. */
+int slr_apply(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream);
+
+/* slr_apply_dd: as slr_apply but vectors are in the library's internal DD
+ * order (interiors by subdomain, then interface; slr_export perm). */
+int slr_apply_dd(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream);
+
+/* slr_solve: preconditioned Krylov solve A x = b (Sec. 6: CG for SPD,
+ * GMRES(40) for indefinite; flexible CG for reduced-precision factors).
+ * b_dev, x_dev: device n x nrhs (original order); x0 = 0.  Stops when
+ * ||r_j|| <= rtol ||b|| per column, or at maxit.  info: host array of
+ * nrhs entries.  Returns SLR_ERR_NOCONV if any column failed (x is still
+ * written).  FGMRES takes nrhs = 1.  Synchronises hip_stream. */
+int slr_solve(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs,
+              const slr_solve_opts *so, slr_solve_info *info, void *hip_stream);
+
+/* slr_solve_workspace_bytes: device bytes slr_solve needs for nrhs. */
+size_t slr_solve_workspace_bytes(const slr_ctx *c, int32_t nrhs, int32_t method);
+
+/* slr_query: sizes, level depths, theta, timings, memory. */
+int slr_query(const slr_ctx *c, slr_info *info);
+
+/* slr_export: copy setup results to host buffers (any may be NULL):
+ * perm (n int64, internal -> original index), ritz (lanczos_steps values,
+ * descending), lambda (k), U (s x k column-major FP64, interface order),
+ * alpha/beta (Lanczos tridiagonal, lanczos_steps each; beta's last entry is
+ * the final residual norm). */
+int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda,
+               double *U, double *alpha, double *beta);
+
+/* slr_spmv: y = A x in the original order (device n x nrhs), FP64. */
+int slr_spmv(slr_ctx *c, const double *x_dev, double *y_dev, int32_t nrhs, void *hip_stream);
+
+/* ---- continuous batching (serving) -----------------------------------
+ * A batch owns `max_cols` right-hand-side slots of one context, each with
+ * its own Krylov state kept on the device.  Requests are admitted while
+ * slots are free; slr_batch_step advances every active slot by `iters`
+ * iterations; finished requests are returned by slr_batch_poll and their
+ * slots are reused.  A column's arithmetic does not depend on the other
+ * columns, so a result is the same alone and in a mix.  PCG / FCG only. */
+int slr_batch_create(slr_ctx *c, int32_t max_cols, int32_t method, double rtol,
+                     int32_t maxit, slr_batch **out);
+/* Admit one request of nrhs columns: b_dev / x_dev device n x nrhs
+ * (original order); x_dev is written when the request completes.  Returns
+ * SLR_ERR_ADMIT when fewer than nrhs slots are free. */
+int slr_batch_admit(slr_batch *b, const double *b_dev, double *x_dev, int32_t nrhs,
+                    int64_t tag, void *hip_stream);
+int slr_batch_step(slr_batch *b, int32_t iters, void *hip_stream);
+/* Retire finished requests: writes up to max_done tags (and per-request
+ * worst iteration count / relres / status) and returns how many. */
+int slr_batch_poll(slr_batch *b, int64_t *tags, slr_solve_info *info, int32_t max_done,
+                   void *hip_stream);
+int slr_batch_active(const slr_batch *b);       /* columns in flight */
+size_t slr_batch_bytes(const slr_batch *b);     /* device bytes held */
+void slr_batch_destroy(slr_batch *b);
+
+/* ---- misc ------------------------------------------------------------- */
+void slr_destroy(slr_ctx *c);
+const char *slr_strerror(int code);
+const char *slr_last_error(void);
+int slr_device_lds_bytes(void);   /* LDS per workgroup the library plans for */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLR_H */

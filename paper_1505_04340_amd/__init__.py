@@ -1,0 +1,371 @@
+"""MI355X (gfx950) Schur-complement low-rank (SLR) preconditioner.
+
+Thin ctypes binding over the C ABI in include/slr.h (libslr.so, built
+in-tree by ``paper_1505_04340_amd.build``).  Only argument marshalling
+happens here: every step of setup's Lanczos build, the preconditioner
+apply and the Krylov solves runs in the library's HIP kernels.  Device
+memory and streams come from PyTorch-ROCm.
+
+Method: Li, Xi & Saad, "Schur complement based domain decomposition
+preconditioners with low-rank corrections" (2015).
+
+The module-level functions carry the C names (slr_setup, slr_apply, ...);
+``SLR`` and ``Batch`` wrap them for torch tensors.  Vectors are FP64 torch
+tensors on the GPU of shape (n,) or (n, nrhs); they are passed to the
+library column-major.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libslr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1505_04340_amd/build.py` "
+                      "(there is no CPU fallback)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- constants (include/slr.h) -------------------------------------------------
+SLR_OK, SLR_ERR_ARG, SLR_ERR_NOT_SYMMETRIC, SLR_ERR_PARTITION = 0, -1, -2, -3
+SLR_ERR_BREAKDOWN, SLR_ERR_C_NOT_SPD, SLR_ERR_RITZ_SINGULAR, SLR_ERR_LANCZOS_SHORT = -4, -5, -6, -7
+SLR_ERR_NOCONV, SLR_ERR_OOM, SLR_ERR_HIP, SLR_ERR_ADMIT = -8, -9, -10, -11
+SLR_THETA_LAMBDA_K1, SLR_THETA_ZERO = 0, 1
+SLR_FACT_CHOL, SLR_FACT_IC0, SLR_FACT_ILDLT0 = 0, 1, 2
+SLR_CORDER_SUBDOMAIN, SLR_CORDER_MULTICOLOR = 0, 1
+SLR_FP64, SLR_FP32, SLR_BF16 = 0, 1, 2
+SLR_PCG, SLR_FCG, SLR_FGMRES = 0, 1, 2
+
+_FACT = {"chol": SLR_FACT_CHOL, "ic0": SLR_FACT_IC0, "ildlt0": SLR_FACT_ILDLT0}
+_PREC = {"fp64": SLR_FP64, "fp32": SLR_FP32, "bf16": SLR_BF16}
+_CORD = {"subdomain": SLR_CORDER_SUBDOMAIN, "multicolor": SLR_CORDER_MULTICOLOR}
+_THETA = {"lambda_k1": SLR_THETA_LAMBDA_K1, "zero": SLR_THETA_ZERO}
+_METHOD = {"pcg": SLR_PCG, "fcg": SLR_FCG, "fgmres": SLR_FGMRES}
+
+_P = ctypes.c_void_p
+_I32, _I64, _D, _U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+
+
+class slr_csr(ctypes.Structure):
+    _fields_ = [("n", _I64), ("nnz", _I64), ("rowptr", _P), ("col", _P), ("val", _P)]
+
+
+class slr_opts(ctypes.Structure):
+    _fields_ = [("k", _I32), ("lanczos_steps", _I32), ("theta_mode", _I32), ("b_fact", _I32),
+                ("c_fact", _I32), ("c_order", _I32), ("fact_prec", _I32), ("uk_prec", _I32),
+                ("seed", _U64), ("lanczos_v0", _P), ("k_in", _I32), ("U_in", _P),
+                ("lambda_in", _P), ("theta_in", _D)]
+
+
+class slr_solve_opts(ctypes.Structure):
+    _fields_ = [("method", _I32), ("restart", _I32), ("maxit", _I32), ("check_every", _I32),
+                ("rtol", _D)]
+
+
+class slr_solve_info(ctypes.Structure):
+    _fields_ = [("iters", _I32), ("status", _I32), ("relres", _D)]
+
+
+class slr_info(ctypes.Structure):
+    _fields_ = [("n", _I64), ("m", _I64), ("s", _I64), ("p", _I32), ("k", _I32),
+                ("lanczos_steps", _I32), ("b_levels_max", _I32), ("c_levels", _I32),
+                ("c_colors", _I32), ("nnz_LB", _I64), ("nnz_LC", _I64), ("nnz_E", _I64),
+                ("nnz_A", _I64), ("m_min", _I64), ("m_max", _I64), ("theta", _D),
+                ("setup_host_s", _D), ("setup_lanczos_s", _D), ("device_bytes", _I64)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+slr_default_opts = _sig("slr_default_opts", None, [ctypes.POINTER(slr_opts)])
+slr_default_solve_opts = _sig("slr_default_solve_opts", None, [ctypes.POINTER(slr_solve_opts)])
+slr_setup = _sig("slr_setup", ctypes.c_int, [ctypes.POINTER(slr_csr), _P, _I32, ctypes.POINTER(slr_opts), _P,
+                                             ctypes.POINTER(_P)])
+slr_analyze = _sig("slr_analyze", ctypes.c_int, [ctypes.POINTER(slr_csr), _P, _I32, ctypes.POINTER(slr_opts),
+                                                 ctypes.POINTER(slr_info), _P])
+slr_update_lowrank = _sig("slr_update_lowrank", ctypes.c_int, [_P, _I32, _I32, _P, _P])
+slr_time_kernel = _sig("slr_time_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P, ctypes.POINTER(_D)])
+slr_apply = _sig("slr_apply", ctypes.c_int, [_P, _P, _P, _I32, _P])
+slr_apply_dd = _sig("slr_apply_dd", ctypes.c_int, [_P, _P, _P, _I32, _P])
+slr_solve = _sig("slr_solve", ctypes.c_int, [_P, _P, _P, _I32, ctypes.POINTER(slr_solve_opts),
+                                             ctypes.POINTER(slr_solve_info), _P])
+slr_solve_workspace_bytes = _sig("slr_solve_workspace_bytes", ctypes.c_size_t, [_P, _I32, _I32])
+slr_query = _sig("slr_query", ctypes.c_int, [_P, ctypes.POINTER(slr_info)])
+slr_export = _sig("slr_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P])
+slr_spmv = _sig("slr_spmv", ctypes.c_int, [_P, _P, _P, _I32, _P])
+slr_batch_create = _sig("slr_batch_create", ctypes.c_int, [_P, _I32, _I32, _D, _I32, ctypes.POINTER(_P)])
+slr_batch_admit = _sig("slr_batch_admit", ctypes.c_int, [_P, _P, _P, _I32, _I64, _P])
+slr_batch_step = _sig("slr_batch_step", ctypes.c_int, [_P, _I32, _P])
+slr_batch_poll = _sig("slr_batch_poll", ctypes.c_int, [_P, _P, ctypes.POINTER(slr_solve_info), _I32, _P])
+slr_batch_active = _sig("slr_batch_active", ctypes.c_int, [_P])
+slr_batch_bytes = _sig("slr_batch_bytes", ctypes.c_size_t, [_P])
+slr_batch_destroy = _sig("slr_batch_destroy", None, [_P])
+slr_destroy = _sig("slr_destroy", None, [_P])
+slr_strerror = _sig("slr_strerror", ctypes.c_char_p, [ctypes.c_int])
+slr_last_error = _sig("slr_last_error", ctypes.c_char_p, [])
+slr_device_lds_bytes = _sig("slr_device_lds_bytes", ctypes.c_int, [])
+
+EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_analyze", "slr_update_lowrank",
+            "slr_time_kernel", "slr_apply", "slr_apply_dd",
+            "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_spmv",
+            "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
+            "slr_batch_active", "slr_batch_bytes", "slr_batch_destroy", "slr_destroy",
+            "slr_strerror", "slr_last_error", "slr_device_lds_bytes")
+
+
+class SLRError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = slr_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {slr_strerror(code).decode()} ({code}): {msg}")
+
+
+def _check(rc: int, where: str):
+    if rc != SLR_OK:
+        raise SLRError(rc, where)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _colmajor(t):
+    """(n,) or (n, r) FP64 CUDA tensor -> contiguous (r, n) storage."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError("expected a float64 CUDA tensor")
+    if t.dim() == 1:
+        return t.contiguous().view(1, -1), True
+    return t.t().contiguous(), False
+
+
+def _csr_arrays(A):
+    if isinstance(A, tuple):
+        indptr, indices, data, n = A
+    else:
+        A = A.tocsr()
+        indptr, indices, data, n = A.indptr, A.indices, A.data, A.shape[0]
+    return (np.ascontiguousarray(indptr, dtype=np.int64), np.ascontiguousarray(indices, dtype=np.int32),
+            np.ascontiguousarray(data, dtype=np.float64), int(n))
+
+
+def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fact="ic0",
+               c_order="subdomain", fact_prec="fp64", uk_prec="fp64", seed=7):
+    o = slr_opts()
+    slr_default_opts(ctypes.byref(o))
+    o.k = k
+    o.lanczos_steps = lanczos_steps
+    o.theta_mode = _THETA[theta_mode]
+    o.b_fact, o.c_fact = _FACT[b_fact], _FACT[c_fact]
+    o.c_order = _CORD[c_order]
+    o.fact_prec, o.uk_prec = _PREC[fact_prec], _PREC[uk_prec]
+    o.seed = seed
+    return o
+
+
+def analyze(A, part, nparts: int, **opts):
+    """Host-only analysis (slr_analyze): (info dict, perm internal->original)."""
+    indptr, indices, data, n = _csr_arrays(A)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    o = _make_opts(**opts)
+    csr = slr_csr(n, int(indptr[-1]), indptr.ctypes.data, indices.ctypes.data, data.ctypes.data)
+    info = slr_info()
+    perm = np.empty(n, dtype=np.int64)
+    _check(slr_analyze(ctypes.byref(csr), part.ctypes.data, nparts, ctypes.byref(o), ctypes.byref(info),
+                       perm.ctypes.data), "slr_analyze")
+    return {f: getattr(info, f) for f, _ in slr_info._fields_}, perm
+
+
+class SLR:
+    """An SLR preconditioner resident on the current GPU (slr_setup)."""
+
+    def __init__(self, A, part, nparts: int, k: int = 16, lanczos_steps: int = 0,
+                 theta_mode: str = "lambda_k1", b_fact: str = "ic0", c_fact: str = "ic0",
+                 c_order: str = "subdomain", fact_prec: str = "fp64", uk_prec: str = "fp64",
+                 v0=None, seed: int = 7, lowrank=None, stream=None):
+        indptr, indices, data, n = _csr_arrays(A)
+        self.n = n
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        o = _make_opts(k, lanczos_steps, theta_mode, b_fact, c_fact, c_order, fact_prec, uk_prec, seed)
+        keep = []
+        if v0 is not None:
+            v0 = np.ascontiguousarray(v0, dtype=np.float64)
+            keep.append(v0)
+            o.lanczos_v0 = v0.ctypes.data
+        if lowrank is not None:
+            U, lam, theta = lowrank
+            U = np.asfortranarray(U, dtype=np.float64)
+            lam = np.ascontiguousarray(lam, dtype=np.float64)
+            keep += [U, lam]
+            o.k_in = U.shape[1]
+            o.U_in = U.ctypes.data
+            o.lambda_in = lam.ctypes.data
+            o.theta_in = float(theta)
+        csr = slr_csr(n, int(indptr[-1]), indptr.ctypes.data, indices.ctypes.data, data.ctypes.data)
+        h = _P()
+        _check(slr_setup(ctypes.byref(csr), part.ctypes.data, nparts, ctypes.byref(o), _stream(stream),
+                         ctypes.byref(h)), "slr_setup")
+        self._h = h
+        self.info = self.query()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            slr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def update_lowrank(self, k: int, lanczos_steps: int = 0, v0=None, stream=None):
+        """Rebuild (U_k, Lambda_k, theta) on the device (slr_update_lowrank)."""
+        p = None
+        if v0 is not None:
+            v0 = np.ascontiguousarray(v0, dtype=np.float64)
+            p = v0.ctypes.data
+        _check(slr_update_lowrank(self._h, k, lanczos_steps, p, _stream(stream)), "slr_update_lowrank")
+        self.info = self.query()
+
+    STAGES = {"bsolve1": 0, "cfwd": 1, "lowrank": 2, "cbwd": 3, "bsolve2": 4, "apply": 5, "spmv": 6}
+
+    def time_kernel(self, stage: str, nrhs: int = 1, reps: int = 20, stream=None) -> float:
+        """Average ms per launch of one hot-path stage (slr_time_kernel)."""
+        ms = _D()
+        _check(slr_time_kernel(self._h, self.STAGES[stage], nrhs, reps, _stream(stream), ctypes.byref(ms)),
+               "slr_time_kernel")
+        return ms.value
+
+    def query(self) -> dict:
+        i = slr_info()
+        _check(slr_query(self._h, ctypes.byref(i)), "slr_query")
+        return {f: getattr(i, f) for f, _ in slr_info._fields_}
+
+    def export(self) -> dict:
+        inf = self.query()
+        n, s, k, st = inf["n"], inf["s"], inf["k"], inf["lanczos_steps"]
+        perm = np.empty(n, dtype=np.int64)
+        ritz = np.empty(max(st, k), dtype=np.float64)
+        lam = np.empty(k, dtype=np.float64)
+        U = np.empty((s, k), dtype=np.float64, order="F")
+        al = np.empty(st, dtype=np.float64)
+        be = np.empty(st, dtype=np.float64)
+        _check(slr_export(self._h, perm.ctypes.data, ritz.ctypes.data, lam.ctypes.data,
+                          U.ctypes.data if k else None, al.ctypes.data, be.ctypes.data), "slr_export")
+        return {"perm": perm, "ritz": ritz[:st] if st else ritz[:k], "lambda": lam, "U": U,
+                "alpha": al, "beta": be, "theta": inf["theta"], "m": inf["m"], "s": s}
+
+    def _call(self, fn, r, name, stream=None):
+        import torch
+        rc_, vec = _colmajor(r)
+        out = torch.empty_like(rc_)
+        _check(fn(self._h, ctypes.c_void_p(rc_.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                  rc_.shape[0], _stream(stream)), name)
+        return out.view(-1) if vec else out.t()
+
+    def apply(self, r, stream=None):
+        """z = M^{-1} r (original order)."""
+        return self._call(slr_apply, r, "slr_apply", stream)
+
+    def apply_dd(self, r, stream=None):
+        """z = M^{-1} r in the internal DD order."""
+        return self._call(slr_apply_dd, r, "slr_apply_dd", stream)
+
+    def spmv(self, x, stream=None):
+        return self._call(slr_spmv, x, "slr_spmv", stream)
+
+    def solve(self, b, method: str = "pcg", rtol: float = 1e-8, maxit: int = 300, restart: int = 40,
+              check_every: int = 8, stream=None, raise_noconv: bool = False):
+        """x with A x = b; returns (x, [{'iters', 'status', 'relres'}, ...])."""
+        import torch
+        bc, vec = _colmajor(b)
+        x = torch.empty_like(bc)
+        so = slr_solve_opts()
+        slr_default_solve_opts(ctypes.byref(so))
+        so.method = _METHOD[method]
+        so.rtol, so.maxit, so.restart, so.check_every = rtol, maxit, restart, check_every
+        nr = bc.shape[0]
+        infos = (slr_solve_info * nr)()
+        rc = slr_solve(self._h, ctypes.c_void_p(bc.data_ptr()), ctypes.c_void_p(x.data_ptr()), nr,
+                       ctypes.byref(so), infos, _stream(stream))
+        if rc != SLR_OK and (rc != SLR_ERR_NOCONV or raise_noconv):
+            raise SLRError(rc, "slr_solve")
+        out = [{"iters": i.iters, "status": i.status, "relres": i.relres} for i in infos]
+        return (x.view(-1) if vec else x.t()), out
+
+    def workspace_bytes(self, nrhs: int, method: str = "pcg") -> int:
+        return int(slr_solve_workspace_bytes(self._h, nrhs, _METHOD[method]))
+
+
+class Batch:
+    """Continuous-batching solver state of one SLR context (slr_batch_*)."""
+
+    def __init__(self, slr: SLR, max_cols: int, method: str = "pcg", rtol: float = 1e-8, maxit: int = 300):
+        self.slr = slr
+        h = _P()
+        _check(slr_batch_create(slr.handle, max_cols, _METHOD[method], rtol, maxit, ctypes.byref(h)),
+               "slr_batch_create")
+        self._h = h
+        self._keep = {}
+
+    def admit(self, b, tag: int, stream=None):
+        """Admit b (n,) or (n, r); returns the output tensor x or None when
+        no slots are free (SLR_ERR_ADMIT)."""
+        import torch
+        bc, vec = _colmajor(b)
+        x = torch.empty_like(bc)
+        rc = slr_batch_admit(self._h, ctypes.c_void_p(bc.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                             bc.shape[0], tag, _stream(stream))
+        if rc == SLR_ERR_ADMIT:
+            return None
+        _check(rc, "slr_batch_admit")
+        self._keep[tag] = (bc, x, vec)
+        return x
+
+    def step(self, iters: int = 1, stream=None):
+        _check(slr_batch_step(self._h, iters, _stream(stream)), "slr_batch_step")
+
+    def poll(self, max_done: int = 64, stream=None):
+        """[(tag, x, info)] of finished requests."""
+        tags = (ctypes.c_int64 * max_done)()
+        infos = (slr_solve_info * max_done)()
+        nd = slr_batch_poll(self._h, tags, infos, max_done, _stream(stream))
+        if nd < 0:
+            raise SLRError(nd, "slr_batch_poll")
+        out = []
+        for t in range(nd):
+            bc, x, vec = self._keep.pop(tags[t])
+            out.append((tags[t], x.view(-1) if vec else x.t(),
+                        {"iters": infos[t].iters, "status": infos[t].status, "relres": infos[t].relres}))
+        return out
+
+    def active(self) -> int:
+        return int(slr_batch_active(self._h))
+
+    def bytes(self) -> int:
+        return int(slr_batch_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            slr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1241 @@
+// C ABI of the SLR preconditioner library (declared in include/slr.h).
+//
+// Paper: Li, Xi & Saad, "Schur complement based domain decomposition
+// preconditioners with low-rank corrections" (2015).
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "slr.h"
+#include "slr_dev.h"
+#include "slr_host.h"
+#include "slr_kern.h"
+
+using namespace slr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(SLR_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocations owned by one object, freed together.
+struct DevPool {
+  std::vector<void *> ptrs;
+  int64_t bytes = 0;
+  template <typename T>
+  T *alloc(size_t n) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    bytes += (int64_t)(n * sizeof(T));
+    return (T *)p;
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v) {
+    T *p = alloc<T>(v.size());
+    if (p && !v.empty()) {
+      if (hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    }
+    return p;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+template <typename TS>
+std::vector<TS> conv(const std::vector<double> &v) {
+  std::vector<TS> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (TS)v[i];
+  return o;
+}
+
+// Scratch of one apply pipeline (one per context, one per batch).
+struct ApplyWS {
+  int32_t cap = 0;
+  double *W = nullptr;        // s x cap interface temporary
+  double *lr_part = nullptr;  // lr_nblk x cap x k
+  double *cbuf = nullptr;     // k x cap
+  unsigned int *counter = nullptr;
+  DevPool pool;
+};
+
+}  // namespace
+
+struct slr_ctx {
+  int device = 0;
+  int64_t n = 0, m = 0, s = 0;
+  int32_t p = 0;
+  slr_opts opts{};
+  int fact_prec = SLR_FP64, uk_prec = SLR_FP64;
+  DevPool pool;
+  // internal order
+  std::vector<int64_t> perm_h;
+  int64_t *perm = nullptr;
+  int64_t *a_rp = nullptr;
+  int32_t *a_ci = nullptr;
+  double *a_v = nullptr;
+  int64_t nnz_a = 0;
+  // B blocks and interface sweeps (one of the two precisions is used)
+  BlockArrays<double> Bd;
+  BlockArrays<float> Bf;
+  SweepArrays<double> Cfd, Cbd;
+  SweepArrays<float> Cff, Cbf;
+  std::vector<int32_t> cf_lev_h, cb_lev_h;
+  int32_t cf_nlev = 0, cb_nlev = 0;
+  bool c_one_wg = true;
+  int32_t b_threads = 256;
+  int32_t b_max_m = 0, b_max_lev = 0;
+  size_t lds_limit = 65536;
+  // low-rank part
+  int32_t k = 0;
+  double theta = 0.0, rho = 1.0;
+  void *U = nullptr;            // s x k row-major, storage precision
+  double *U64 = nullptr;        // s x k row-major, FP64 (export)
+  double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
+  std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
+  int32_t lr_nblk = 256;
+  DevPool lrpool;               // U, U64, dsc
+  // stats
+  slr_info info{};
+  ApplyWS ws;
+  // original <-> internal order scratch of slr_apply / slr_spmv
+  DevPool ppool;
+  int32_t pcap = 0;
+  double *pr = nullptr, *pz = nullptr;
+  // solve workspace
+  DevPool spool;
+  int32_t scap = 0;
+  double *sX = nullptr, *sR = nullptr, *sZ = nullptr, *sP = nullptr, *sQ = nullptr, *sB = nullptr;
+  KState *sst = nullptr;
+  double *spart = nullptr;
+  unsigned int *scnt = nullptr;
+};
+
+struct slr_batch {
+  slr_ctx *c = nullptr;
+  int32_t cap = 0, method = SLR_PCG, maxit = 300;
+  double rtol = 1e-8;
+  DevPool pool;
+  ApplyWS ws;
+  double *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr, *B = nullptr;
+  KState *st = nullptr;
+  double *part = nullptr;
+  unsigned int *counter = nullptr;
+  std::vector<int64_t> owner;   // request index per column, -1 free
+  struct Req {
+    int64_t tag;
+    int32_t c0, nrhs;
+    double *x_dev;
+    bool live;
+  };
+  std::vector<Req> reqs;
+  int32_t hi = 0;               // columns [0, hi) may be active
+  std::vector<KState> st_h;
+};
+
+namespace {
+
+constexpr int RED_NBLK = 512;
+
+int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
+  if (w.cap >= nrhs && w.W) return SLR_OK;
+  w.pool.release();
+  int32_t cap = std::max<int32_t>(nrhs, 1);
+  w.W = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
+  w.lr_part = w.pool.alloc<double>((size_t)c->lr_nblk * cap * std::max(c->k, 1));
+  w.cbuf = w.pool.alloc<double>((size_t)cap * std::max(c->k, 1));
+  w.counter = w.pool.alloc<unsigned int>(16);
+  if (!w.W || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
+  HIPCHK(hipMemset(w.counter, 0, 16 * sizeof(unsigned int)));
+  w.cap = cap;
+  return SLR_OK;
+}
+
+// largest number of right-hand sides per B workgroup that fits the LDS
+int32_t b_rhs_per_wg(const slr_ctx *c, int32_t nrhs, size_t tc_bytes) {
+  size_t lev = sizeof(int32_t) * 2 * (size_t)(c->b_max_lev + 1);
+  size_t per = tc_bytes * (size_t)std::max(c->b_max_m, 1);
+  if (per + lev > c->lds_limit) return 0;
+  int32_t R = (int32_t)std::min<size_t>((c->lds_limit - lev) / per, 16);
+  return std::max(1, std::min(R, nrhs));
+}
+
+template <typename TS, typename TC>
+int run_bsolve(slr_ctx *c, const BlockArrays<TS> &B, const BArgs &a0, hipStream_t st) {
+  BArgs a = a0;
+  int32_t R = b_rhs_per_wg(c, a.nrhs, sizeof(TC));
+  if (R == 0) return fail(SLR_ERR_ARG, "a subdomain does not fit the LDS of one workgroup");
+  a.R = R;
+  size_t lds = sizeof(TC) * (size_t)c->b_max_m * R + sizeof(int32_t) * 2 * (size_t)(c->b_max_lev + 1);
+  launch_bsolve<TS, TC>(B, c->p, a, c->b_threads, lds, st);
+  return SLR_OK;
+}
+
+// B kernel dispatch by (storage, compute) precision
+int bsolve(slr_ctx *c, const BArgs &a, bool compute64, hipStream_t st) {
+  if (c->fact_prec == SLR_FP64) return run_bsolve<double, double>(c, c->Bd, a, st);
+  if (compute64) return run_bsolve<float, double>(c, c->Bf, a, st);
+  return run_bsolve<float, float>(c, c->Bf, a, st);
+}
+
+void csweep(slr_ctx *c, bool fwd, double *x, int64_t ldx, int32_t nrhs, bool compute64, hipStream_t st) {
+  const int32_t nlev = fwd ? c->cf_nlev : c->cb_nlev;
+  const int32_t *lev = fwd ? c->cf_lev_h.data() : c->cb_lev_h.data();
+  if (c->fact_prec == SLR_FP64) {
+    launch_sweep<double, double>(fwd ? c->Cfd : c->Cbd, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st);
+  } else if (compute64) {
+    launch_sweep<float, double>(fwd ? c->Cff : c->Cbf, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st);
+  } else {
+    launch_sweep<float, float>(fwd ? c->Cff : c->Cbf, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st);
+  }
+}
+
+void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs,
+             hipStream_t st) {
+  const int k = c->k;
+  switch (c->uk_prec) {
+    case SLR_FP64:
+      launch_lowrank<double>((const double *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo, nrhs, w.lr_part,
+                             c->lr_nblk, w.cbuf, w.counter, st);
+      break;
+    case SLR_FP32:
+      launch_lowrank<float>((const float *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo, nrhs, w.lr_part,
+                            c->lr_nblk, w.cbuf, w.counter, st);
+      break;
+    default:
+      launch_lowrank<__hip_bfloat16>((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo,
+                                     nrhs, w.lr_part, c->lr_nblk, w.cbuf, w.counter, st);
+  }
+}
+
+// z = M^{-1} r in the internal order, eq. M with S~^{-1} of eq. skt:
+//   (1) z_B = B^{-1} f ; W = g - E^T z_B          (B kernel, epilogue)
+//   (2) W <- L^{-1} W                              (interface forward sweep)
+//   (3) y' = rho W + U_k D U_k^T W                 (rank-k block)
+//   (4) y = L^{-T} y'                              (interface backward sweep)
+//   (5) u = B^{-1}(f - E y)                        (B kernel, prologue)
+int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, int64_t ldz, int32_t nrhs,
+             hipStream_t st) {
+  if (nrhs <= 0) return SLR_OK;
+  int rc = ws_ensure(c, w, nrhs);
+  if (rc) return rc;
+  const int64_t m = c->m, s = c->s;
+  if (s > 0) {
+    BArgs a;
+    a.f = r; a.ldf = ldr; a.a_f = 1.0;
+    a.g = r + m; a.ldg = ldr; a.c_g = 1.0;
+    a.gout = w.W; a.ldgo = s; a.d_t = -1.0;
+    a.nrhs = nrhs;
+    if ((rc = bsolve(c, a, false, st))) return rc;
+    csweep(c, true, w.W, s, nrhs, false, st);
+    lowrank(c, w, w.W, s, z + m, ldz, nrhs, st);
+    csweep(c, false, z + m, ldz, nrhs, false, st);
+  }
+  if (m > 0) {
+    BArgs a;
+    a.f = r; a.ldf = ldr; a.a_f = 1.0;
+    a.y = z + m; a.ldy = ldz; a.b_y = (s > 0) ? -1.0 : 0.0;
+    a.u = z; a.ldu = ldz;
+    a.nrhs = nrhs;
+    if ((rc = bsolve(c, a, false, st))) return rc;
+  }
+  return SLR_OK;
+}
+
+// w = H v = L^{-1} E^T B^{-1} E L^{-T} v (eq. H), FP64 arithmetic on the
+// stored factors; t: s-vector scratch.
+int apply_H(slr_ctx *c, const double *v, double *w, double *t, hipStream_t st) {
+  const int64_t s = c->s;
+  launch_axpby(s, 1, 1.0, v, s, 0.0, t, s, st);
+  csweep(c, false, t, s, 1, true, st);
+  BArgs a;
+  a.y = t; a.ldy = s; a.b_y = 1.0;
+  a.gout = w; a.ldgo = s; a.d_t = 1.0;
+  a.nrhs = 1;
+  int rc = bsolve(c, a, true, st);
+  if (rc) return rc;
+  csweep(c, true, w, s, 1, true, st);
+  return SLR_OK;
+}
+
+template <typename TU>
+int upload_lowrank_T(slr_ctx *c, hipStream_t st) {
+  TU *U = c->lrpool.alloc<TU>((size_t)c->s * c->k);
+  if (!U) return fail(SLR_ERR_OOM, "U storage");
+  launch_round_copy<TU>((int64_t)c->s * c->k, c->U64, U, st);
+  c->U = U;
+  return SLR_OK;
+}
+
+int finish_lowrank(slr_ctx *c, hipStream_t st) {
+  // scales of eq. skt: (1 - lambda_i)^{-1} - (1 - theta)^{-1}
+  if (std::fabs(1.0 - c->theta) < 1e-12) return fail(SLR_ERR_RITZ_SINGULAR, "|1 - theta| < 1e-12");
+  c->rho = 1.0 / (1.0 - c->theta);
+  std::vector<double> d(std::max(c->k, 1), 0.0);
+  for (int i = 0; i < c->k; ++i) {
+    if (std::fabs(1.0 - c->lam_h[i]) < 1e-12) return fail(SLR_ERR_RITZ_SINGULAR, "|1 - lambda_i| < 1e-12");
+    d[i] = 1.0 / (1.0 - c->lam_h[i]) - c->rho;
+  }
+  c->dsc = c->lrpool.upload(d);
+  if (!c->dsc) return fail(SLR_ERR_OOM, "dsc");
+  if (c->k == 0) return SLR_OK;
+  if (c->uk_prec == SLR_FP64) {
+    c->U = c->U64;
+    return SLR_OK;
+  }
+  if (c->uk_prec == SLR_FP32) return upload_lowrank_T<float>(c, st);
+  return upload_lowrank_T<__hip_bfloat16>(c, st);
+}
+
+// Lanczos on H with CGS2 full reorthogonalisation (Sec. 5.1), then the
+// tridiagonal eigensolve and the Ritz vectors U_k = V_m Y_k.
+int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
+  const int64_t s = c->s;
+  const int32_t k = c->k;
+  int32_t steps = c->opts.lanczos_steps > 0 ? c->opts.lanczos_steps : 5 * k;
+  steps = (int32_t)std::min<int64_t>(steps, std::max<int64_t>(s, 1));
+  if (steps > 1024) return fail(SLR_ERR_ARG, "at most 1024 Lanczos steps");
+  const bool need_k1 = c->opts.theta_mode == SLR_THETA_LAMBDA_K1;
+  DevPool tmp;
+  double *V = tmp.alloc<double>((size_t)s * steps);
+  double *Wl = tmp.alloc<double>(s);
+  double *T = tmp.alloc<double>(s);
+  double *h = tmp.alloc<double>(steps + 1);
+  double *sc = tmp.alloc<double>(4);
+  double *al = tmp.alloc<double>(steps);
+  double *be = tmp.alloc<double>(steps);
+  double *part = tmp.alloc<double>((size_t)RED_NBLK * (steps + 1));
+  unsigned int *cnt = tmp.alloc<unsigned int>(4);
+  if (!V || !Wl || !T || !h || !sc || !al || !be || !part || !cnt) {
+    tmp.release();
+    return fail(SLR_ERR_OOM, "Lanczos basis");
+  }
+  int rc = SLR_OK;
+  auto bail = [&](int code) {
+    tmp.release();
+    return code;
+  };
+  HIPCHK(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned int), st));
+  HIPCHK(hipMemsetAsync(sc, 0, 4 * sizeof(double), st));
+  // start vector: interface entries of v0 (original order), normalised
+  std::vector<double> v0(s);
+  for (int64_t q = 0; q < s; ++q) v0[q] = v0_host[c->perm_h[c->m + q]];
+  double nv = 0.0;
+  for (double x : v0) nv += x * x;
+  nv = std::sqrt(nv);
+  if (!(nv > 0.0)) return bail(fail(SLR_ERR_ARG, "Lanczos start vector is zero on the interface"));
+  for (double &x : v0) x /= nv;
+  HIPCHK(hipMemcpyAsync(V, v0.data(), sizeof(double) * s, hipMemcpyHostToDevice, st));
+  c->alpha_h.clear();
+  c->beta_h.clear();
+  double tnorm = 0.0, bprev = 0.0;
+  int32_t mm = 0;
+  for (int32_t j = 0; j < steps; ++j) {
+    double *vj = V + (int64_t)j * s;
+    if ((rc = apply_H(c, vj, Wl, T, st))) return bail(rc);
+    launch_multidot(s, 1, vj, s, Wl, part, RED_NBLK, sc, cnt, st);             // alpha_j
+    launch_lanczos_axpy(s, Wl, vj, j > 0 ? vj - s : nullptr, sc, st);          // three-term
+    for (int pass = 0; pass < 2; ++pass) {                                      // CGS2
+      launch_multidot(s, j + 1, V, s, Wl, part, RED_NBLK, h, cnt, st);
+      launch_gemv_sub(s, j + 1, V, s, h, Wl, st);
+    }
+    launch_multidot(s, 1, Wl, s, Wl, part, RED_NBLK, sc + 2, cnt, st);          // ||w||^2
+    launch_lanczos_record(j, sc, al, be, st);
+    double ab[2];
+    HIPCHK(hipMemcpyAsync(ab, al + j, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ab + 1, be + j, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->alpha_h.push_back(ab[0]);
+    c->beta_h.push_back(ab[1]);
+    mm = j + 1;
+    tnorm = std::max(tnorm, std::fabs(ab[0]) + ab[1] + bprev);
+    bprev = ab[1];
+    if (!std::isfinite(ab[0]) || !std::isfinite(ab[1]))
+      return bail(fail(SLR_ERR_BREAKDOWN, "non-finite Lanczos coefficients"));
+    if (j + 1 == steps || ab[1] <= 1e-14 * tnorm) break;
+    launch_scale_inv_sqrt(s, Wl, V + (int64_t)(j + 1) * s, sc + 2, st);
+  }
+  const int32_t need = need_k1 ? k + 1 : k;
+  if (mm < need) return bail(fail(SLR_ERR_LANCZOS_SHORT, "Lanczos produced fewer Ritz pairs than needed"));
+  double *Z = tmp.alloc<double>((size_t)mm * mm);
+  double *ev = tmp.alloc<double>(mm);
+  double *Y = tmp.alloc<double>((size_t)mm * std::max(k, 1));
+  int *info = tmp.alloc<int>(1);
+  if (!Z || !ev || !Y || !info) return bail(fail(SLR_ERR_OOM, "eigensolve"));
+  launch_tridiag_eig(mm, al, be, Z, ev, Y, k, info, st);
+  c->U64 = c->lrpool.alloc<double>((size_t)s * std::max(k, 1));
+  if (!c->U64) return bail(fail(SLR_ERR_OOM, "U"));
+  launch_ritz<double>(s, mm, k, V, s, Y, c->U64, c->U64, st);
+  int info_h = 0;
+  c->ritz_h.assign(mm, 0.0);
+  HIPCHK(hipMemcpyAsync(&info_h, info, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(c->ritz_h.data(), ev, sizeof(double) * mm, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  tmp.release();
+  if (info_h) return fail(SLR_ERR_BREAKDOWN, "tridiagonal eigensolve did not converge");
+  c->lam_h.assign(c->ritz_h.begin(), c->ritz_h.begin() + k);
+  c->theta = need_k1 ? c->ritz_h[k] : 0.0;
+  c->info.lanczos_steps = mm;
+  return finish_lowrank(c, st);
+}
+
+template <typename TS>
+void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArrays<TS> &Cf, SweepArrays<TS> &Cb,
+                   bool &ok) {
+  std::vector<BlockDesc> desc(H.p);
+  std::vector<int32_t> f_lev, f_rows, f_rp, f_ci, b_lev, b_rows, b_rp, b_ci;
+  std::vector<double> f_w, f_sc, b_w, b_sc;
+  std::vector<int32_t> e_row, e_ptr, e_q, t_q, t_ptr, t_j;
+  std::vector<double> e_val, t_val;
+  int32_t max_m = 0, max_lev = 0;
+  for (int32_t q = 0; q < H.p; ++q) {
+    const Block &b = H.blocks[q];
+    BlockDesc &d = desc[q];
+    d.m0 = b.m0;
+    d.m = b.m;
+    max_m = std::max(max_m, b.m);
+    max_lev = std::max({max_lev, b.fwd.nlev, b.bwd.nlev});
+    auto put = [](const Sweep &sw, std::vector<int32_t> &lev, std::vector<int32_t> &rows,
+                  std::vector<int32_t> &rp, std::vector<int32_t> &ci, std::vector<double> &w,
+                  std::vector<double> &sc, int32_t &o_lev, int32_t &o_nlev, int32_t &o_row, int32_t &o_rp,
+                  int32_t &o_ent) {
+      o_lev = (int32_t)lev.size();
+      o_nlev = sw.nlev;
+      o_row = (int32_t)rows.size();
+      o_rp = (int32_t)rp.size();
+      o_ent = (int32_t)ci.size();
+      lev.insert(lev.end(), sw.levptr.begin(), sw.levptr.end());
+      if (sw.levptr.empty()) lev.push_back(0);
+      rows.insert(rows.end(), sw.rows.begin(), sw.rows.end());
+      sc.insert(sc.end(), sw.sc.begin(), sw.sc.end());
+      for (int32_t x : sw.rp) rp.push_back(o_ent + x);
+      if (sw.rp.empty()) rp.push_back(o_ent);
+      ci.insert(ci.end(), sw.ci.begin(), sw.ci.end());
+      w.insert(w.end(), sw.w.begin(), sw.w.end());
+    };
+    put(b.fwd, f_lev, f_rows, f_rp, f_ci, f_w, f_sc, d.f_lev, d.f_nlev, d.f_row, d.f_rp, d.f_ent);
+    put(b.bwd, b_lev, b_rows, b_rp, b_ci, b_w, b_sc, d.b_lev, d.b_nlev, d.b_row, d.b_rp, d.b_ent);
+    d.e_row = (int32_t)e_row.size();
+    d.e_n = (int32_t)b.e_row.size();
+    d.e_ptr = (int32_t)e_ptr.size();
+    const int32_t eb = (int32_t)e_q.size();
+    e_row.insert(e_row.end(), b.e_row.begin(), b.e_row.end());
+    for (int32_t x : b.e_ptr) e_ptr.push_back(eb + x);
+    e_q.insert(e_q.end(), b.e_q.begin(), b.e_q.end());
+    e_val.insert(e_val.end(), b.e_val.begin(), b.e_val.end());
+    d.t_row = (int32_t)t_q.size();
+    d.t_n = (int32_t)b.t_q.size();
+    d.t_ptr = (int32_t)t_ptr.size();
+    const int32_t tb = (int32_t)t_j.size();
+    t_q.insert(t_q.end(), b.t_q.begin(), b.t_q.end());
+    for (int32_t x : b.t_ptr) t_ptr.push_back(tb + x);
+    t_j.insert(t_j.end(), b.t_j.begin(), b.t_j.end());
+    t_val.insert(t_val.end(), b.t_val.begin(), b.t_val.end());
+  }
+  auto &P = c->pool;
+  B.desc = P.upload(desc);
+  B.fwd.lev = P.upload(f_lev); B.fwd.rows = P.upload(f_rows); B.fwd.rp = P.upload(f_rp);
+  B.fwd.ci = P.upload(f_ci); B.fwd.w = P.upload(conv<TS>(f_w)); B.fwd.sc = P.upload(conv<TS>(f_sc));
+  B.bwd.lev = P.upload(b_lev); B.bwd.rows = P.upload(b_rows); B.bwd.rp = P.upload(b_rp);
+  B.bwd.ci = P.upload(b_ci); B.bwd.w = P.upload(conv<TS>(b_w)); B.bwd.sc = P.upload(conv<TS>(b_sc));
+  B.e_row = P.upload(e_row); B.e_ptr = P.upload(e_ptr); B.e_q = P.upload(e_q);
+  B.e_val = P.upload(conv<TS>(e_val));
+  B.t_q = P.upload(t_q); B.t_ptr = P.upload(t_ptr); B.t_j = P.upload(t_j);
+  B.t_val = P.upload(conv<TS>(t_val));
+  B.max_m = max_m;
+  B.max_lev = max_lev;
+  c->b_max_m = max_m;
+  c->b_max_lev = max_lev;
+  auto upc = [&](const Sweep &sw, SweepArrays<TS> &S) {
+    std::vector<int32_t> lev = sw.levptr;
+    if (lev.empty()) lev.push_back(0);
+    S.lev = P.upload(lev);
+    S.rows = P.upload(sw.rows);
+    S.rp = P.upload(sw.rp.empty() ? std::vector<int32_t>{0} : sw.rp);
+    S.ci = P.upload(sw.ci);
+    S.w = P.upload(conv<TS>(sw.w));
+    S.sc = P.upload(conv<TS>(sw.sc));
+    return S.lev && S.rows && S.rp && S.ci && S.w && S.sc;
+  };
+  ok = B.desc && B.fwd.lev && B.fwd.rows && B.fwd.rp && B.fwd.ci && B.fwd.w && B.fwd.sc && B.bwd.lev &&
+       B.bwd.rows && B.bwd.rp && B.bwd.ci && B.bwd.w && B.bwd.sc && B.e_row && B.e_ptr && B.e_q && B.e_val &&
+       B.t_q && B.t_ptr && B.t_j && B.t_val;
+  ok = ok && upc(H.cfwd, Cf) && upc(H.cbwd, Cb);
+}
+
+int perm_ws(slr_ctx *c, int32_t nrhs) {
+  if (c->pcap >= nrhs && c->pr) return SLR_OK;
+  c->ppool.release();
+  c->pr = c->ppool.alloc<double>((size_t)c->n * nrhs);
+  c->pz = c->ppool.alloc<double>((size_t)c->n * nrhs);
+  if (!c->pr || !c->pz) return fail(SLR_ERR_OOM, "permutation scratch");
+  c->pcap = nrhs;
+  return SLR_OK;
+}
+
+hipStream_t S(void *p) { return (hipStream_t)p; }
+
+// Default Lanczos start vector: U[-1, 1) from SplitMix64 (Steele, Lea &
+// Flood 2014) keyed by the original node index.
+const double *seeded_v0(int64_t n, uint64_t seed, std::vector<double> &v0) {
+  v0.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v0[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+  return v0.data();
+}
+
+}  // namespace
+
+extern "C" {
+
+void slr_default_opts(slr_opts *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->k = 16;
+  o->lanczos_steps = 0;
+  o->theta_mode = SLR_THETA_LAMBDA_K1;
+  o->b_fact = SLR_FACT_IC0;
+  o->c_fact = SLR_FACT_IC0;
+  o->c_order = SLR_CORDER_SUBDOMAIN;
+  o->fact_prec = SLR_FP64;
+  o->uk_prec = SLR_FP64;
+  o->seed = 7;
+}
+
+void slr_default_solve_opts(slr_solve_opts *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->method = SLR_PCG;
+  o->restart = 40;
+  o->maxit = 300;
+  o->check_every = 8;
+  o->rtol = 1e-8;
+}
+
+const char *slr_strerror(int code) {
+  switch (code) {
+    case SLR_OK: return "ok";
+    case SLR_ERR_ARG: return "invalid argument";
+    case SLR_ERR_NOT_SYMMETRIC: return "matrix is not symmetric";
+    case SLR_ERR_PARTITION: return "invalid or unsupported partition";
+    case SLR_ERR_BREAKDOWN: return "factorisation or iteration breakdown";
+    case SLR_ERR_C_NOT_SPD: return "interface matrix C is not SPD";
+    case SLR_ERR_RITZ_SINGULAR: return "Ritz value too close to 1";
+    case SLR_ERR_LANCZOS_SHORT: return "too few Lanczos Ritz pairs";
+    case SLR_ERR_NOCONV: return "did not converge";
+    case SLR_ERR_OOM: return "out of device memory";
+    case SLR_ERR_HIP: return "HIP runtime error";
+    case SLR_ERR_ADMIT: return "admission refused";
+    default: return "unknown error";
+  }
+}
+
+const char *slr_last_error(void) { return g_err.c_str(); }
+
+int slr_device_lds_bytes(void) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 65536;
+  return (int)prop.sharedMemPerBlock;
+}
+
+int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *o, void *hip_stream,
+              slr_ctx **out) {
+  if (!A || !part || !o || !out || !A->rowptr || !A->col || !A->val) return fail(SLR_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (o->k < 0 || o->k > 64) return fail(SLR_ERR_ARG, "k must be in [0, 64]");
+  if (o->fact_prec != SLR_FP64 && o->fact_prec != SLR_FP32) return fail(SLR_ERR_ARG, "fact_prec");
+  if (o->uk_prec < SLR_FP64 || o->uk_prec > SLR_BF16) return fail(SLR_ERR_ARG, "uk_prec");
+  if (o->b_fact < SLR_FACT_CHOL || o->b_fact > SLR_FACT_ILDLT0) return fail(SLR_ERR_ARG, "b_fact");
+  if (o->c_fact != SLR_FACT_CHOL && o->c_fact != SLR_FACT_IC0) return fail(SLR_ERR_ARG, "c_fact");
+  if (A->rowptr[A->n] != A->nnz) return fail(SLR_ERR_ARG, "rowptr[n] != nnz");
+  hipStream_t st = S(hip_stream);
+  const double t0 = now_s();
+  HostSetup H;
+  SetupParams prm;
+  prm.b_fact = o->b_fact;
+  prm.c_fact = o->c_fact;
+  prm.c_order = o->c_order;
+  prm.fact_prec = o->fact_prec;
+  std::string err;
+  int rc = host_setup(A->n, A->rowptr, A->col, A->val, part, p, prm, H, err);
+  if (rc) return fail(rc, err);
+  slr_ctx *c = new slr_ctx();
+  (void)hipGetDevice(&c->device);
+  c->opts = *o;
+  c->n = H.n;
+  c->m = H.m;
+  c->s = H.s;
+  c->p = H.p;
+  c->fact_prec = o->fact_prec;
+  c->uk_prec = o->uk_prec;
+  c->lds_limit = (size_t)slr_device_lds_bytes();
+  c->perm_h = H.perm;
+  auto destroy_fail = [&](int code) {
+    slr_destroy(c);
+    return code;
+  };
+  c->perm = c->pool.upload(H.perm);
+  c->a_rp = c->pool.upload(H.a_rp);
+  c->a_ci = c->pool.upload(H.a_ci);
+  c->a_v = c->pool.upload(H.a_v);
+  c->nnz_a = (int64_t)H.a_ci.size();
+  bool ok = c->perm && c->a_rp && c->a_ci && c->a_v;
+  if (c->fact_prec == SLR_FP64)
+    upload_blocks<double>(c, H, c->Bd, c->Cfd, c->Cbd, ok);
+  else {
+    bool ok2 = true;
+    upload_blocks<float>(c, H, c->Bf, c->Cff, c->Cbf, ok2);
+    ok = ok && ok2;
+  }
+  if (!ok) return destroy_fail(fail(SLR_ERR_OOM, "factor upload"));
+  c->cf_lev_h = H.cfwd.levptr;
+  c->cb_lev_h = H.cbwd.levptr;
+  c->cf_nlev = H.cfwd.nlev;
+  c->cb_nlev = H.cbwd.nlev;
+  // shallow interface schedules (multicolour) run one launch per level
+  c->c_one_wg = std::max(c->cf_nlev, c->cb_nlev) > 8;
+  if (c->c_one_wg && sizeof(int32_t) * (size_t)(std::max(c->cf_nlev, c->cb_nlev) + 1) > c->lds_limit)
+    return destroy_fail(fail(SLR_ERR_ARG, "interface level schedule too deep for one workgroup"));
+  if (b_rhs_per_wg(c, 1, 8) == 0 && b_rhs_per_wg(c, 1, 4) == 0)
+    return destroy_fail(fail(SLR_ERR_ARG, "largest subdomain does not fit one workgroup's LDS"));
+  // stats
+  slr_info &I = c->info;
+  I.n = c->n; I.m = c->m; I.s = c->s; I.p = c->p;
+  I.b_levels_max = c->b_max_lev;
+  I.c_levels = H.cfwd.nlev;
+  I.c_colors = H.c_colors;
+  I.nnz_LB = 0;
+  I.m_min = INT64_MAX; I.m_max = 0;
+  for (const auto &b : H.blocks) {
+    I.nnz_LB += b.nnz_L;
+    I.m_min = std::min<int64_t>(I.m_min, b.m);
+    I.m_max = std::max<int64_t>(I.m_max, b.m);
+  }
+  I.nnz_LC = H.nnz_LC;
+  I.nnz_E = H.nnz_E;
+  I.nnz_A = c->nnz_a;
+  I.setup_host_s = now_s() - t0;
+  // low-rank part
+  const double t1 = now_s();
+  if (o->U_in && o->k_in > 0) {
+    if (o->k_in > 64 || !o->lambda_in) return destroy_fail(fail(SLR_ERR_ARG, "imported low-rank part"));
+    c->k = o->k_in;
+    std::vector<double> Urm((size_t)c->s * c->k);
+    for (int64_t i = 0; i < c->s; ++i)
+      for (int q = 0; q < c->k; ++q) Urm[i * c->k + q] = o->U_in[i + (int64_t)q * c->s];
+    c->U64 = c->lrpool.upload(Urm);
+    if (!c->U64) return destroy_fail(fail(SLR_ERR_OOM, "U"));
+    c->lam_h.assign(o->lambda_in, o->lambda_in + c->k);
+    c->ritz_h = c->lam_h;
+    c->theta = o->theta_in;
+    if ((rc = finish_lowrank(c, st))) return destroy_fail(rc);
+  } else if (o->k > 0 && c->s > 0) {
+    c->k = o->k;
+    std::vector<double> v0;
+    const double *v0p = o->lanczos_v0 ? o->lanczos_v0 : seeded_v0(c->n, o->seed, v0);
+    if ((rc = lanczos_build(c, v0p, st))) return destroy_fail(rc);
+  } else {
+    c->k = 0;
+    c->theta = 0.0;
+    if ((rc = finish_lowrank(c, st))) return destroy_fail(rc);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  I.k = c->k;
+  I.theta = c->theta;
+  I.setup_lanczos_s = now_s() - t1;
+  if ((rc = ws_ensure(c, c->ws, 1))) return destroy_fail(rc);
+  I.device_bytes = c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes;
+  *out = c;
+  return SLR_OK;
+}
+
+int slr_update_lowrank(slr_ctx *c, int32_t k, int32_t lanczos_steps, const double *lanczos_v0,
+                       void *hip_stream) {
+  if (!c || k < 0 || k > 64 || lanczos_steps < 0) return fail(SLR_ERR_ARG, "bad update arguments");
+  hipStream_t st = S(hip_stream);
+  HIPCHK(hipStreamSynchronize(st));
+  c->lrpool.release();
+  c->U = nullptr;
+  c->U64 = nullptr;
+  c->dsc = nullptr;
+  c->ws.pool.release();
+  c->ws.cap = 0;
+  c->ws.W = nullptr;
+  c->k = k;
+  c->opts.k = k;
+  c->opts.lanczos_steps = lanczos_steps;
+  const double t1 = now_s();
+  int rc;
+  if (k > 0 && c->s > 0) {
+    std::vector<double> v0;
+    const double *v0p = lanczos_v0 ? lanczos_v0 : seeded_v0(c->n, c->opts.seed, v0);
+    rc = lanczos_build(c, v0p, st);
+  } else {
+    c->k = 0;
+    c->theta = 0.0;
+    c->lam_h.clear();
+    c->ritz_h.clear();
+    rc = finish_lowrank(c, st);
+  }
+  if (rc) return rc;
+  if ((rc = ws_ensure(c, c->ws, 1))) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  c->info.k = c->k;
+  c->info.theta = c->theta;
+  c->info.setup_lanczos_s = now_s() - t1;
+  return SLR_OK;
+}
+
+int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void *hip_stream, double *ms) {
+  if (!c || !ms || nrhs <= 0 || reps <= 0 || which < 0 || which > 6) return fail(SLR_ERR_ARG, "bad timing args");
+  hipStream_t st = S(hip_stream);
+  int rc = perm_ws(c, nrhs);
+  if (rc) return rc;
+  if ((rc = ws_ensure(c, c->ws, nrhs))) return rc;
+  const int64_t n = c->n, m = c->m, s = c->s;
+  // deterministic filler: r = 1 everywhere, then one apply to get realistic z
+  std::vector<double> ones((size_t)n * nrhs, 1.0);
+  HIPCHK(hipMemcpyAsync(c->pr, ones.data(), sizeof(double) * ones.size(), hipMemcpyHostToDevice, st));
+  if ((rc = apply_dd(c, c->ws, c->pr, n, c->pz, n, nrhs, st))) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto one = [&]() -> int {
+    switch (which) {
+      case 0: {
+        BArgs a;
+        a.f = c->pr; a.ldf = n; a.a_f = 1.0;
+        a.g = c->pr + m; a.ldg = n; a.c_g = 1.0;
+        a.gout = c->ws.W; a.ldgo = s; a.d_t = -1.0;
+        a.nrhs = nrhs;
+        return bsolve(c, a, false, st);
+      }
+      case 1: csweep(c, true, c->ws.W, s, nrhs, false, st); return SLR_OK;
+      case 2: lowrank(c, c->ws, c->ws.W, s, c->pz + m, n, nrhs, st); return SLR_OK;
+      case 3: csweep(c, false, c->pz + m, n, nrhs, false, st); return SLR_OK;
+      case 4: {
+        BArgs a;
+        a.f = c->pr; a.ldf = n; a.a_f = 1.0;
+        a.y = c->pz + m; a.ldy = n; a.b_y = -1.0;
+        a.u = c->pz; a.ldu = n;
+        a.nrhs = nrhs;
+        return bsolve(c, a, false, st);
+      }
+      case 5: return apply_dd(c, c->ws, c->pr, n, c->pz, n, nrhs, st);
+      default: launch_spmv(n, c->a_rp, c->a_ci, c->a_v, c->pr, n, c->pz, n, nrhs, st); return SLR_OK;
+    }
+  };
+  if ((rc = one())) return rc;
+  HIPCHK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i)
+    if ((rc = one())) return rc;
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0.0f;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  return SLR_OK;
+}
+
+int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *o, slr_info *info,
+                int64_t *perm) {
+  if (!A || !part || !o || !info || !A->rowptr || !A->col || !A->val) return fail(SLR_ERR_ARG, "null argument");
+  if (A->rowptr[A->n] != A->nnz) return fail(SLR_ERR_ARG, "rowptr[n] != nnz");
+  const double t0 = now_s();
+  HostSetup H;
+  SetupParams prm;
+  prm.b_fact = o->b_fact;
+  prm.c_fact = o->c_fact;
+  prm.c_order = o->c_order;
+  prm.fact_prec = o->fact_prec;
+  std::string err;
+  int rc = host_setup(A->n, A->rowptr, A->col, A->val, part, p, prm, H, err);
+  if (rc) return fail(rc, err);
+  std::memset(info, 0, sizeof(*info));
+  info->n = H.n; info->m = H.m; info->s = H.s; info->p = H.p;
+  info->c_levels = H.cfwd.nlev;
+  info->c_colors = H.c_colors;
+  info->nnz_LC = H.nnz_LC;
+  info->nnz_E = H.nnz_E;
+  info->nnz_A = (int64_t)H.a_ci.size();
+  info->m_min = INT64_MAX;
+  const int64_t fb = o->fact_prec == SLR_FP32 ? 4 : 8;
+  int64_t bytes = (int64_t)H.a_ci.size() * 12 + (H.n + 1) * 8 + H.n * 8;
+  for (const auto &b : H.blocks) {
+    info->nnz_LB += b.nnz_L;
+    info->b_levels_max = std::max({info->b_levels_max, b.fwd.nlev, b.bwd.nlev});
+    info->m_min = std::min<int64_t>(info->m_min, b.m);
+    info->m_max = std::max<int64_t>(info->m_max, b.m);
+    bytes += (int64_t)(b.fwd.ci.size() + b.bwd.ci.size()) * (4 + fb) + (int64_t)b.m * (2 * (8 + fb) + 8) +
+             (int64_t)(b.e_q.size() + b.t_j.size()) * (4 + fb);
+  }
+  bytes += (int64_t)(H.cfwd.ci.size() + H.cbwd.ci.size()) * (4 + fb) + H.s * 2 * (8 + fb);
+  const int64_t ub = o->uk_prec == SLR_FP64 ? 8 : (o->uk_prec == SLR_FP32 ? 4 : 2);
+  bytes += H.s * (int64_t)o->k * (8 + (o->uk_prec == SLR_FP64 ? 0 : ub));
+  info->device_bytes = bytes;
+  info->setup_host_s = now_s() - t0;
+  if (perm) std::copy(H.perm.begin(), H.perm.end(), perm);
+  return SLR_OK;
+}
+
+void slr_destroy(slr_ctx *c) {
+  if (!c) return;
+  c->pool.release();
+  c->ws.pool.release();
+  c->lrpool.release();
+  c->ppool.release();
+  c->spool.release();
+  delete c;
+}
+
+int slr_query(const slr_ctx *c, slr_info *info) {
+  if (!c || !info) return fail(SLR_ERR_ARG, "null");
+  *info = c->info;
+  info->device_bytes = c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes;
+  return SLR_OK;
+}
+
+int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda, double *U, double *alpha,
+               double *beta) {
+  if (!c) return fail(SLR_ERR_ARG, "null");
+  if (perm) std::copy(c->perm_h.begin(), c->perm_h.end(), perm);
+  if (ritz) std::copy(c->ritz_h.begin(), c->ritz_h.end(), ritz);
+  if (lambda) std::copy(c->lam_h.begin(), c->lam_h.end(), lambda);
+  if (alpha) std::copy(c->alpha_h.begin(), c->alpha_h.end(), alpha);
+  if (beta) std::copy(c->beta_h.begin(), c->beta_h.end(), beta);
+  if (U && c->k > 0) {
+    std::vector<double> Urm((size_t)c->s * c->k);
+    HIPCHK(hipMemcpy(Urm.data(), c->U64, sizeof(double) * Urm.size(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < c->s; ++i)
+      for (int q = 0; q < c->k; ++q) U[i + (int64_t)q * c->s] = Urm[i * c->k + q];
+  }
+  return SLR_OK;
+}
+
+int slr_apply_dd(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream) {
+  if (!c || !r_dev || !z_dev || nrhs < 0) return fail(SLR_ERR_ARG, "bad apply arguments");
+  return apply_dd(c, c->ws, r_dev, c->n, z_dev, c->n, nrhs, S(hip_stream));
+}
+
+int slr_apply(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream) {
+  if (!c || !r_dev || !z_dev || nrhs < 0) return fail(SLR_ERR_ARG, "bad apply arguments");
+  if (nrhs == 0) return SLR_OK;
+  hipStream_t st = S(hip_stream);
+  int rc = perm_ws(c, nrhs);
+  if (rc) return rc;
+  launch_permute(c->n, c->perm, r_dev, c->n, c->pr, c->n, nrhs, false, st);
+  rc = apply_dd(c, c->ws, c->pr, c->n, c->pz, c->n, nrhs, st);
+  if (rc == SLR_OK) launch_permute(c->n, c->perm, c->pz, c->n, z_dev, c->n, nrhs, true, st);
+  return rc;
+}
+
+int slr_spmv(slr_ctx *c, const double *x_dev, double *y_dev, int32_t nrhs, void *hip_stream) {
+  if (!c || !x_dev || !y_dev || nrhs < 0) return fail(SLR_ERR_ARG, "bad spmv arguments");
+  if (nrhs == 0) return SLR_OK;
+  hipStream_t st = S(hip_stream);
+  int rc = perm_ws(c, nrhs);
+  if (rc) return rc;
+  launch_permute(c->n, c->perm, x_dev, c->n, c->pr, c->n, nrhs, false, st);
+  launch_spmv(c->n, c->a_rp, c->a_ci, c->a_v, c->pr, c->n, c->pz, c->n, nrhs, st);
+  launch_permute(c->n, c->perm, c->pz, c->n, y_dev, c->n, nrhs, true, st);
+  return SLR_OK;
+}
+
+size_t slr_solve_workspace_bytes(const slr_ctx *c, int32_t nrhs, int32_t method) {
+  if (!c) return 0;
+  size_t n = (size_t)c->n;
+  if (method == SLR_FGMRES) return sizeof(double) * n * (2 * 41 + 4) + sizeof(double) * RED_NBLK * 48;
+  return sizeof(double) * n * nrhs * 6 + sizeof(KState) * nrhs + sizeof(double) * RED_NBLK * nrhs * 2 +
+         sizeof(double) * (size_t)c->s * nrhs;
+}
+
+}  // extern "C"
+
+namespace {
+
+int solve_ws(slr_ctx *c, int32_t nrhs) {
+  if (c->scap >= nrhs && c->sX) return SLR_OK;
+  c->spool.release();
+  const size_t n = (size_t)c->n;
+  c->sX = c->spool.alloc<double>(n * nrhs);
+  c->sR = c->spool.alloc<double>(n * nrhs);
+  c->sZ = c->spool.alloc<double>(n * nrhs);
+  c->sP = c->spool.alloc<double>(n * nrhs);
+  c->sQ = c->spool.alloc<double>(n * nrhs);
+  c->sB = c->spool.alloc<double>(n * nrhs);
+  c->sst = c->spool.alloc<KState>(nrhs);
+  c->spart = c->spool.alloc<double>((size_t)RED_NBLK * nrhs * 2);
+  c->scnt = c->spool.alloc<unsigned int>(4);
+  if (!c->sX || !c->sR || !c->sZ || !c->sP || !c->sQ || !c->sB || !c->sst || !c->spart || !c->scnt)
+    return fail(SLR_ERR_OOM, "solve workspace");
+  HIPCHK(hipMemset(c->scnt, 0, 4 * sizeof(unsigned int)));
+  c->scap = nrhs;
+  return SLR_OK;
+}
+
+KArgs kargs(slr_ctx *c, double *X, double *R, double *Z, double *P, double *Q, int64_t ld, KState *st,
+            double *part, unsigned int *cnt, int maxit, double rtol) {
+  KArgs K;
+  K.X = X; K.R = R; K.Z = Z; K.P = P; K.Q = Q;
+  K.ld = ld;
+  K.st = st;
+  K.part = part;
+  K.counter = cnt;
+  K.nblk = RED_NBLK;
+  K.maxit = maxit;
+  K.rtol2 = rtol * rtol;
+  (void)c;
+  return K;
+}
+
+// CG / flexible CG on columns [c0, c0+nc) whose R holds b (internal order).
+int cg_start(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, hipStream_t st) {
+  launch_cg(CG_INIT, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+  int rc = apply_dd(c, w, K.R + (int64_t)c0 * K.ld, K.ld, K.Z + (int64_t)c0 * K.ld, K.ld, nc, st);
+  if (rc) return rc;
+  launch_cg(CG_BETA_INIT, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+  launch_axpby(c->n, nc, 1.0, K.Z + (int64_t)c0 * K.ld, K.ld, 0.0, K.P + (int64_t)c0 * K.ld, K.ld, st);
+  return SLR_OK;
+}
+
+int cg_iter(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, hipStream_t st) {
+  launch_cg(CG_SPMV, c->n, c->a_rp, c->a_ci, c->a_v, K, c0, nc, flexible, st);
+  launch_cg(CG_UPDATE, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+  int rc = apply_dd(c, w, K.R + (int64_t)c0 * K.ld, K.ld, K.Z + (int64_t)c0 * K.ld, K.ld, nc, st);
+  if (rc) return rc;
+  launch_cg(CG_BETA, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+  launch_cg(CG_P, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+  return SLR_OK;
+}
+
+int solve_cg(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const slr_solve_opts &so,
+             slr_solve_info *info, hipStream_t st) {
+  int rc = solve_ws(c, nrhs);
+  if (rc) return rc;
+  const int64_t n = c->n;
+  const int flexible = so.method == SLR_FCG;
+  KArgs K = kargs(c, c->sX, c->sR, c->sZ, c->sP, c->sQ, n, c->sst, c->spart, c->scnt, so.maxit, so.rtol);
+  launch_permute(n, c->perm, b_dev, n, c->sB, n, nrhs, false, st);
+  launch_axpby(n, nrhs, 1.0, c->sB, n, 0.0, c->sR, n, st);
+  if ((rc = cg_start(c, c->ws, K, 0, nrhs, flexible, st))) return rc;
+  std::vector<KState> h(nrhs);
+  const int every = std::max(1, so.check_every);
+  for (int it = 0; it < so.maxit; it += every) {
+    for (int j = 0; j < every && it + j < so.maxit; ++j)
+      if ((rc = cg_iter(c, c->ws, K, 0, nrhs, flexible, st))) return rc;
+    HIPCHK(hipMemcpyAsync(h.data(), c->sst, sizeof(KState) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool any = false;
+    for (auto &x : h) any |= x.active != 0;
+    if (!any) break;
+  }
+  // true residual ||b - A x|| / ||b|| in FP64
+  launch_spmv(n, c->a_rp, c->a_ci, c->a_v, c->sX, n, c->sQ, n, nrhs, st);
+  launch_relres(n, c->sB, n, c->sQ, n, K, 0, nrhs, st);
+  launch_permute(n, c->perm, c->sX, n, x_dev, n, nrhs, true, st);
+  HIPCHK(hipMemcpyAsync(h.data(), c->sst, sizeof(KState) * nrhs, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int worst = SLR_OK;
+  for (int j = 0; j < nrhs; ++j) {
+    info[j].iters = h[j].iters;
+    info[j].relres = h[j].relres;
+    info[j].status = (h[j].active == 0 && h[j].status == 0) ? SLR_OK : SLR_ERR_NOCONV;
+    if (info[j].status) worst = SLR_ERR_NOCONV;
+  }
+  if (worst) g_err = "a right-hand side did not converge";
+  return worst;
+}
+
+// Right-preconditioned flexible GMRES(restart) (Sec. 6 uses GMRES(40)),
+// CGS2 Arnoldi, Givens rotations, x0 = 0, one right-hand side.
+int solve_fgmres(slr_ctx *c, const double *b_dev, double *x_dev, const slr_solve_opts &so, slr_solve_info *info,
+                 hipStream_t st) {
+  const int64_t n = c->n;
+  const int32_t mr = std::max(1, std::min(so.restart, 200));
+  DevPool tmp;
+  double *V = tmp.alloc<double>((size_t)n * (mr + 1));
+  double *Zb = tmp.alloc<double>((size_t)n * mr);
+  double *Bd = tmp.alloc<double>(n);
+  double *X = tmp.alloc<double>(n);
+  double *T = tmp.alloc<double>(n);
+  double *Hm = tmp.alloc<double>((size_t)(mr + 1) * mr);
+  double *h1 = tmp.alloc<double>(mr + 1);
+  double *h2 = tmp.alloc<double>(mr + 1);
+  double *cs = tmp.alloc<double>(mr);
+  double *sn = tmp.alloc<double>(mr);
+  double *g = tmp.alloc<double>(mr + 1);
+  double *y = tmp.alloc<double>(mr);
+  double *sc = tmp.alloc<double>(4);
+  double *part = tmp.alloc<double>((size_t)RED_NBLK * (mr + 1));
+  unsigned int *cnt = tmp.alloc<unsigned int>(4);
+  int *flags = tmp.alloc<int>(2);
+  if (!V || !Zb || !Bd || !X || !T || !Hm || !h1 || !h2 || !cs || !sn || !g || !y || !sc || !part || !cnt ||
+      !flags) {
+    tmp.release();
+    return fail(SLR_ERR_OOM, "FGMRES workspace");
+  }
+  int rc = SLR_OK;
+  auto bail = [&](int code) {
+    tmp.release();
+    return code;
+  };
+  HIPCHK(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned int), st));
+  HIPCHK(hipMemsetAsync(X, 0, sizeof(double) * n, st));
+  launch_permute(n, c->perm, b_dev, n, Bd, n, 1, false, st);
+  launch_multidot(n, 1, Bd, n, Bd, part, RED_NBLK, sc + 3, cnt, st);
+  double bb = 0.0;
+  HIPCHK(hipMemcpyAsync(&bb, sc + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double bn = std::sqrt(bb);
+  const double tol = so.rtol * bn;
+  int its = 0;
+  bool conv = bn == 0.0;
+  while (!conv && its < so.maxit) {
+    // r = b - A x ; v_0 = r / ||r|| ; g = ||r|| e_1
+    launch_spmv(n, c->a_rp, c->a_ci, c->a_v, X, n, T, n, 1, st);
+    launch_axpby(n, 1, 1.0, Bd, n, -1.0, T, n, st);
+    launch_multidot(n, 1, T, n, T, part, RED_NBLK, sc, cnt, st);
+    launch_scale_inv_sqrt(n, T, V, sc, st);
+    launch_gmres_g0(mr + 1, sc, g, st);
+    int jj = 0;
+    for (int j = 0; j < mr; ++j) {
+      double *vj = V + (int64_t)j * n, *zj = Zb + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
+      if ((rc = apply_dd(c, c->ws, vj, n, zj, n, 1, st))) return bail(rc);
+      launch_spmv(n, c->a_rp, c->a_ci, c->a_v, zj, n, w, n, 1, st);
+      launch_multidot(n, j + 1, V, n, w, part, RED_NBLK, h1, cnt, st);
+      launch_gemv_sub(n, j + 1, V, n, h1, w, st);
+      launch_multidot(n, j + 1, V, n, w, part, RED_NBLK, h2, cnt, st);
+      launch_gemv_sub(n, j + 1, V, n, h2, w, st);
+      launch_multidot(n, 1, w, n, w, part, RED_NBLK, sc + 1, cnt, st);
+      launch_gmres_givens(j, mr + 1, Hm, h1, h2, sc + 1, cs, sn, g, tol, flags, sc + 2, st);
+      launch_div_scalar(n, w, w, sc + 2, st);
+      ++its;
+      jj = j + 1;
+      int fl[2];
+      HIPCHK(hipMemcpyAsync(fl, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (fl[0]) conv = true;
+      if (fl[0] || fl[1] || its >= so.maxit) break;
+    }
+    launch_gmres_solve(jj, mr + 1, Hm, g, y, st);
+    launch_gemv_add(n, jj, Zb, n, y, X, st);
+  }
+  // true residual
+  launch_spmv(n, c->a_rp, c->a_ci, c->a_v, X, n, T, n, 1, st);
+  launch_axpby(n, 1, 1.0, Bd, n, -1.0, T, n, st);
+  launch_multidot(n, 1, T, n, T, part, RED_NBLK, sc, cnt, st);
+  launch_permute(n, c->perm, X, n, x_dev, n, 1, true, st);
+  double rr = 0.0;
+  HIPCHK(hipMemcpyAsync(&rr, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  tmp.release();
+  info[0].iters = its;
+  info[0].relres = bn > 0.0 ? std::sqrt(rr) / bn : 0.0;
+  info[0].status = conv ? SLR_OK : SLR_ERR_NOCONV;
+  if (!conv) g_err = "FGMRES did not converge";
+  return conv ? SLR_OK : SLR_ERR_NOCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slr_solve(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const slr_solve_opts *so_in,
+              slr_solve_info *info, void *hip_stream) {
+  if (!c || !b_dev || !x_dev || !info || nrhs <= 0) return fail(SLR_ERR_ARG, "bad solve arguments");
+  slr_solve_opts so;
+  if (so_in)
+    so = *so_in;
+  else
+    slr_default_solve_opts(&so);
+  if (so.maxit <= 0 || !(so.rtol > 0.0)) return fail(SLR_ERR_ARG, "maxit / rtol");
+  hipStream_t st = S(hip_stream);
+  if (so.method == SLR_FGMRES) {
+    if (nrhs != 1) return fail(SLR_ERR_ARG, "FGMRES takes one right-hand side");
+    return solve_fgmres(c, b_dev, x_dev, so, info, st);
+  }
+  if (so.method != SLR_PCG && so.method != SLR_FCG) return fail(SLR_ERR_ARG, "method");
+  return solve_cg(c, b_dev, x_dev, nrhs, so, info, st);
+}
+
+// ---------------------------------------------------------------------------
+// continuous batching
+// ---------------------------------------------------------------------------
+int slr_batch_create(slr_ctx *c, int32_t max_cols, int32_t method, double rtol, int32_t maxit, slr_batch **out) {
+  if (!c || !out || max_cols <= 0 || (method != SLR_PCG && method != SLR_FCG) || !(rtol > 0) || maxit <= 0)
+    return fail(SLR_ERR_ARG, "bad batch arguments");
+  slr_batch *b = new slr_batch();
+  b->c = c;
+  b->cap = max_cols;
+  b->method = method;
+  b->rtol = rtol;
+  b->maxit = maxit;
+  const size_t n = (size_t)c->n;
+  b->X = b->pool.alloc<double>(n * max_cols);
+  b->R = b->pool.alloc<double>(n * max_cols);
+  b->Z = b->pool.alloc<double>(n * max_cols);
+  b->P = b->pool.alloc<double>(n * max_cols);
+  b->Q = b->pool.alloc<double>(n * max_cols);
+  b->B = b->pool.alloc<double>(n * max_cols);
+  b->st = b->pool.alloc<KState>(max_cols);
+  b->part = b->pool.alloc<double>((size_t)RED_NBLK * max_cols * 2);
+  b->counter = b->pool.alloc<unsigned int>(4);
+  if (!b->X || !b->R || !b->Z || !b->P || !b->Q || !b->B || !b->st || !b->part || !b->counter) {
+    slr_batch_destroy(b);
+    return fail(SLR_ERR_OOM, "batch state");
+  }
+  if (hipMemset(b->counter, 0, 4 * sizeof(unsigned int)) != hipSuccess ||
+      hipMemset(b->st, 0, sizeof(KState) * max_cols) != hipSuccess) {
+    slr_batch_destroy(b);
+    return fail(SLR_ERR_HIP, "batch init");
+  }
+  int rc = ws_ensure(c, b->ws, max_cols);
+  if (rc) {
+    slr_batch_destroy(b);
+    return rc;
+  }
+  b->owner.assign(max_cols, -1);
+  b->st_h.resize(max_cols);
+  *out = b;
+  return SLR_OK;
+}
+
+void slr_batch_destroy(slr_batch *b) {
+  if (!b) return;
+  b->pool.release();
+  b->ws.pool.release();
+  delete b;
+}
+
+int slr_batch_active(const slr_batch *b) {
+  if (!b) return 0;
+  int a = 0;
+  for (int64_t o : b->owner) a += o >= 0;
+  return a;
+}
+
+size_t slr_batch_bytes(const slr_batch *b) { return b ? (size_t)(b->pool.bytes + b->ws.pool.bytes) : 0; }
+
+int slr_batch_admit(slr_batch *b, const double *b_dev, double *x_dev, int32_t nrhs, int64_t tag, void *hip_stream) {
+  if (!b || !b_dev || !x_dev || nrhs <= 0) return fail(SLR_ERR_ARG, "bad admit arguments");
+  // first fit of nrhs contiguous free columns
+  int32_t c0 = -1;
+  for (int32_t i = 0; i + nrhs <= b->cap; ++i) {
+    bool ok = true;
+    for (int32_t j = 0; j < nrhs && ok; ++j) ok = b->owner[i + j] < 0;
+    if (ok) {
+      c0 = i;
+      break;
+    }
+  }
+  if (c0 < 0) return fail(SLR_ERR_ADMIT, "no free slots");
+  slr_ctx *c = b->c;
+  hipStream_t st = S(hip_stream);
+  const int64_t n = c->n;
+  KArgs K = kargs(c, b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->counter, b->maxit, b->rtol);
+  launch_permute(n, c->perm, b_dev, n, b->B + (int64_t)c0 * n, n, nrhs, false, st);
+  launch_axpby(n, nrhs, 1.0, b->B + (int64_t)c0 * n, n, 0.0, b->R + (int64_t)c0 * n, n, st);
+  int rc = cg_start(c, b->ws, K, c0, nrhs, b->method == SLR_FCG, st);
+  if (rc) return rc;
+  const int64_t rid = (int64_t)b->reqs.size();
+  b->reqs.push_back({tag, c0, nrhs, x_dev, true});
+  for (int32_t j = 0; j < nrhs; ++j) b->owner[c0 + j] = rid;
+  b->hi = std::max(b->hi, c0 + nrhs);
+  return SLR_OK;
+}
+
+int slr_batch_step(slr_batch *b, int32_t iters, void *hip_stream) {
+  if (!b || iters < 0) return fail(SLR_ERR_ARG, "bad step arguments");
+  if (b->hi == 0) return SLR_OK;
+  slr_ctx *c = b->c;
+  hipStream_t st = S(hip_stream);
+  KArgs K = kargs(c, b->X, b->R, b->Z, b->P, b->Q, c->n, b->st, b->part, b->counter, b->maxit, b->rtol);
+  for (int32_t i = 0; i < iters; ++i) {
+    int rc = cg_iter(c, b->ws, K, 0, b->hi, b->method == SLR_FCG, st);
+    if (rc) return rc;
+  }
+  return SLR_OK;
+}
+
+int slr_batch_poll(slr_batch *b, int64_t *tags, slr_solve_info *info, int32_t max_done, void *hip_stream) {
+  if (!b || (max_done > 0 && (!tags || !info))) return fail(SLR_ERR_ARG, "bad poll arguments");
+  if (b->hi == 0) return 0;
+  slr_ctx *c = b->c;
+  hipStream_t st = S(hip_stream);
+  const int64_t n = c->n;
+  if (hipMemcpyAsync(b->st_h.data(), b->st, sizeof(KState) * b->hi, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(SLR_ERR_HIP, "poll copy");
+  KArgs K = kargs(c, b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->counter, b->maxit, b->rtol);
+  int32_t done = 0;
+  std::vector<int64_t> fin;
+  for (int64_t rid = 0; rid < (int64_t)b->reqs.size() && done < max_done; ++rid) {
+    auto &rq = b->reqs[rid];
+    if (!rq.live) continue;
+    bool all = true;
+    for (int32_t j = 0; j < rq.nrhs && all; ++j) all = b->st_h[rq.c0 + j].active == 0;
+    if (!all) continue;
+    // true residual of the request's columns, then x to the caller
+    launch_spmv(n, c->a_rp, c->a_ci, c->a_v, b->X + (int64_t)rq.c0 * n, n, b->Q + (int64_t)rq.c0 * n, n, rq.nrhs,
+                st);
+    launch_relres(n, b->B + (int64_t)rq.c0 * n, n, b->Q + (int64_t)rq.c0 * n, n, K, rq.c0, rq.nrhs, st);
+    launch_permute(n, c->perm, b->X + (int64_t)rq.c0 * n, n, rq.x_dev, n, rq.nrhs, true, st);
+    fin.push_back(rid);
+    ++done;
+  }
+  if (fin.empty()) return 0;
+  if (hipMemcpyAsync(b->st_h.data(), b->st, sizeof(KState) * b->hi, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(SLR_ERR_HIP, "poll copy");
+  for (size_t t = 0; t < fin.size(); ++t) {
+    auto &rq = b->reqs[fin[t]];
+    slr_solve_info w{0, SLR_OK, 0.0};
+    for (int32_t j = 0; j < rq.nrhs; ++j) {
+      const KState &k = b->st_h[rq.c0 + j];
+      w.iters = std::max(w.iters, k.iters);
+      w.relres = std::max(w.relres, k.relres);
+      if (k.status != 0) w.status = SLR_ERR_NOCONV;
+      b->owner[rq.c0 + j] = -1;
+    }
+    rq.live = false;
+    tags[t] = rq.tag;
+    info[t] = w;
+  }
+  int32_t hi = 0;
+  for (int32_t i = 0; i < b->cap; ++i)
+    if (b->owner[i] >= 0) hi = i + 1;
+  b->hi = hi;
+  return (int)fin.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,427 @@
+// Host-side analysis for slr_setup (see slr_host.h).
+//
+// Paper: Li, Xi & Saad, "Schur complement based domain decomposition
+// preconditioners with low-rank corrections" (2015).
+//   Sec. 2.1  vertex-based partitioning: interior vs. local interface nodes
+//   eq. Global / Global2  DD ordering [u_1..u_p ; y]
+//   Sec. 5.2  local solves with B_i and with C
+#include "slr_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "slr.h"
+
+namespace slr {
+namespace {
+
+// A symmetric in pattern and value: every (i, j) has a matching (j, i).
+bool is_symmetric(int64_t n, const int64_t *rp, const int32_t *ci, const double *v) {
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      int64_t j = ci[e];
+      if (j < 0 || j >= n) return false;
+      const int32_t *b = ci + rp[j], *en = ci + rp[j + 1];
+      const int32_t *f = std::lower_bound(b, en, (int32_t)i);
+      if (f == en || *f != i) return false;
+      if (v[rp[j] + (f - b)] != v[e]) return false;
+    }
+  }
+  return true;
+}
+
+// Build a level-scheduled sweep from per-row dependency lists.
+// deps(i) lists the rows whose solved values row i needs; `order` is the
+// elimination order (row indices in the order a sequential solve visits).
+template <class Deps, class Emit>
+void schedule(int32_t nrows, const std::vector<int32_t> &order, Deps deps, Emit emit, Sweep &sw) {
+  std::vector<int32_t> lev(nrows, 0);
+  int32_t nlev = 0;
+  for (int32_t i : order) {
+    int32_t l = 0;
+    deps(i, [&](int32_t j) { l = std::max(l, lev[j] + 1); });
+    lev[i] = l;
+    nlev = std::max(nlev, l + 1);
+  }
+  if (nrows == 0) nlev = 0;
+  sw.nrows = nrows;
+  sw.nlev = nlev;
+  sw.levptr.assign(nlev + 1, 0);
+  for (int32_t i = 0; i < nrows; ++i) sw.levptr[lev[i] + 1]++;
+  for (int32_t l = 0; l < nlev; ++l) sw.levptr[l + 1] += sw.levptr[l];
+  // stable within a level: ascending elimination position
+  std::vector<int32_t> pos(sw.levptr.begin(), sw.levptr.end() - (nlev ? 1 : 0));
+  sw.rows.assign(nrows, 0);
+  for (int32_t i : order) sw.rows[pos[lev[i]]++] = i;
+  sw.rp.assign(nrows + 1, 0);
+  sw.ci.clear();
+  sw.w.clear();
+  sw.sc.assign(nrows, 0.0);
+  for (int32_t t = 0; t < nrows; ++t) {
+    int32_t i = sw.rows[t];
+    emit(i, sw.sc[t], [&](int32_t j, double w) {
+      sw.ci.push_back(j);
+      sw.w.push_back(w);
+    });
+    sw.rp[t + 1] = (int32_t)sw.ci.size();
+  }
+}
+
+inline double r32(double x) { return (double)(float)x; }
+
+// Forward and backward sweeps of a lower factor.
+//   L L^T :  fwd  x_i = b_i / l_ii - sum_j (l_ij / l_ii) x_j
+//            bwd  x_i = b_i / l_ii - sum_t (l_ti / l_ii) x_t
+//   L D L^T (unit L): fwd  x_i = b_i - sum_j l_ij x_j
+//                     bwd  x_i = b_i / d_i - sum_t l_ti x_t
+// With fp32 storage the factor values are rounded to FP32 first and the
+// stored coefficients are rounded again after the division.
+void build_sweeps(const LowerFactor &F, bool fp32, Sweep &fwd, Sweep &bwd) {
+  const int32_t n = F.n;
+  std::vector<double> v = F.v;
+  if (fp32)
+    for (double &x : v) x = r32(x);
+  auto rd = [&](double x) { return fp32 ? r32(x) : x; };
+  const bool ldl = F.kind == 2;
+  auto diag = [&](int32_t i) { return v[F.rp[i + 1] - 1]; };
+  // transpose (strictly lower part) for the backward sweep
+  std::vector<int32_t> tp(n + 1, 0), tj;
+  std::vector<double> tv;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e) tp[F.ci[e] + 1]++;
+  for (int32_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+  tj.resize(tp[n]);
+  tv.resize(tp[n]);
+  {
+    std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e) {
+        int32_t c = F.ci[e];
+        tj[fill[c]] = i;
+        tv[fill[c]++] = v[e];
+      }
+  }
+  std::vector<int32_t> up(n), down(n);
+  std::iota(up.begin(), up.end(), 0);
+  for (int32_t i = 0; i < n; ++i) down[i] = n - 1 - i;
+  schedule(
+      n, up,
+      [&](int32_t i, auto f) {
+        for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e) f(F.ci[e]);
+      },
+      [&](int32_t i, double &sc, auto put) {
+        double d = diag(i);
+        sc = ldl ? 1.0 : rd(1.0 / d);
+        for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e)
+          put(F.ci[e], ldl ? v[e] : rd(v[e] / d));
+      },
+      fwd);
+  schedule(
+      n, down,
+      [&](int32_t i, auto f) {
+        for (int32_t e = tp[i]; e < tp[i + 1]; ++e) f(tj[e]);
+      },
+      [&](int32_t i, double &sc, auto put) {
+        double d = diag(i);
+        sc = rd(1.0 / d);
+        for (int32_t e = tp[i]; e < tp[i + 1]; ++e) put(tj[e], ldl ? tv[e] : rd(tv[e] / d));
+      },
+      bwd);
+}
+
+// Zero-fill incomplete factorisation on the pattern of tril(M) (Sec. 5.2 /
+// Sec. 6 local solvers restricted to no fill).  The row being built is
+// scattered into a dense work array; row j's entries are walked against it.
+//   IC(0):    l_ij = (m_ij - sum_{k<j} l_ik l_jk) / l_jj,  l_ii = sqrt(m_ii - sum l_ik^2)
+//   ILDL(0):  l_ij = (m_ij - sum_{k<j} l_ik d_k l_jk) / d_j, d_i = m_ii - sum l_ik^2 d_k
+// Returns -1 - i on a failed pivot of row i, else 0.
+int incomplete_factor(LowerFactor &F) {
+  const int32_t n = F.n;
+  const bool ldl = F.kind == 2;
+  std::vector<double> dense(n, 0.0), d(n, 0.0);
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t a = F.rp[i], b = F.rp[i + 1] - 1;
+    if (b < a || F.ci[b] != i) return -1 - i;
+    double acc_d = 0.0;
+    for (int32_t e = a; e < b; ++e) {
+      int32_t j = F.ci[e];
+      double s = 0.0;
+      for (int32_t t = F.rp[j]; t < F.rp[j + 1] - 1; ++t) {
+        int32_t k = F.ci[t];
+        s += ldl ? dense[k] * F.v[t] * d[k] : dense[k] * F.v[t];
+      }
+      double pj = ldl ? d[j] : F.v[F.rp[j + 1] - 1];
+      double l = (F.v[e] - s) / pj;
+      F.v[e] = l;
+      dense[j] = l;
+      acc_d += ldl ? l * l * d[j] : l * l;
+    }
+    double piv = F.v[b] - acc_d;
+    for (int32_t e = a; e < b; ++e) dense[F.ci[e]] = 0.0;
+    if (ldl) {
+      if (!(std::fabs(piv) >= 1e-300)) return -1 - i;
+      d[i] = piv;
+      F.v[b] = piv;
+    } else {
+      if (!(piv > 0.0)) return -1 - i;
+      F.v[b] = std::sqrt(piv);
+    }
+  }
+  return 0;
+}
+
+// Exact Cholesky in envelope (profile) storage: row i of L spans columns
+// [first_i, i]; fill stays inside the envelope.
+int envelope_cholesky(int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                      const std::vector<double> &v, LowerFactor &F) {
+  std::vector<int32_t> first(n);
+  std::vector<int64_t> start(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    first[i] = (rp[i + 1] > rp[i]) ? std::min(ci[rp[i]], i) : i;
+    start[i + 1] = start[i] + (i - first[i] + 1);
+  }
+  std::vector<double> L(start[n], 0.0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) L[start[i] + ci[e] - first[i]] = v[e];
+  for (int32_t i = 0; i < n; ++i) {
+    double *Li = &L[start[i]];
+    for (int32_t j = first[i]; j <= i; ++j) {
+      const double *Lj = &L[start[j]];
+      int32_t k0 = std::max(first[i], first[j]);
+      double s = Li[j - first[i]];
+      for (int32_t k = k0; k < j; ++k) s -= Li[k - first[i]] * Lj[k - first[j]];
+      if (j < i) {
+        Li[j - first[i]] = s / Lj[j - first[j]];
+      } else {
+        if (!(s > 0.0)) return -1 - i;
+        Li[i - first[i]] = std::sqrt(s);
+      }
+    }
+  }
+  F.n = n;
+  F.kind = 0;
+  F.rp.assign(n + 1, 0);
+  F.ci.clear();
+  F.v.clear();
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t j = first[i]; j <= i; ++j) {
+      F.ci.push_back(j);
+      F.v.push_back(L[start[i] + j - first[i]]);
+    }
+    F.rp[i + 1] = (int32_t)F.ci.size();
+  }
+  return 0;
+}
+
+// factor a block given as the lower triangle (diag last) in local indices
+int factor_block(int kind, int32_t n, std::vector<int32_t> &rp, std::vector<int32_t> &ci,
+                 std::vector<double> &v, LowerFactor &F) {
+  if (kind == SLR_FACT_CHOL) return envelope_cholesky(n, rp, ci, v, F);
+  F.n = n;
+  F.kind = kind == SLR_FACT_ILDLT0 ? 2 : 0;
+  F.rp = rp;
+  F.ci = ci;
+  F.v = v;
+  return incomplete_factor(F);
+}
+
+}  // namespace
+
+int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+               const int32_t *part, int32_t p, const SetupParams &prm, HostSetup &H,
+               std::string &err) {
+  if (n <= 0 || p <= 0 || n > INT32_MAX) {
+    err = "bad sizes";
+    return SLR_ERR_ARG;
+  }
+  if (!is_symmetric(n, rowptr, col, val)) {
+    err = "A is not symmetric (pattern and values must match)";
+    return SLR_ERR_NOT_SYMMETRIC;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (part[i] == -1) {
+      err = "separator labels (-1, edge-based partitioning) are not taken by the device path";
+      return SLR_ERR_PARTITION;
+    }
+    if (part[i] < 0 || part[i] >= p) {
+      err = "partition label out of range";
+      return SLR_ERR_PARTITION;
+    }
+  }
+  H.n = n;
+  H.p = p;
+  // Sec. 2.1: local interface = coupled to a node of another subdomain
+  std::vector<char> iface(n, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+      if (part[col[e]] != part[i]) {
+        iface[i] = 1;
+        break;
+      }
+  // eq. Global: interiors by subdomain, then interface by owner;
+  // ascending original index inside each group
+  std::vector<std::vector<int64_t>> inner(p), ifc(p);
+  for (int64_t i = 0; i < n; ++i) (iface[i] ? ifc : inner)[part[i]].push_back(i);
+  H.perm.clear();
+  H.blocks.assign(p, Block());
+  for (int32_t q = 0; q < p; ++q) {
+    H.blocks[q].m0 = (int32_t)H.perm.size();
+    H.blocks[q].m = (int32_t)inner[q].size();
+    H.perm.insert(H.perm.end(), inner[q].begin(), inner[q].end());
+  }
+  H.m = (int64_t)H.perm.size();
+  std::vector<int64_t> y;
+  for (int32_t q = 0; q < p; ++q) y.insert(y.end(), ifc[q].begin(), ifc[q].end());
+  H.s = (int64_t)y.size();
+  const int64_t s = H.s, m = H.m;
+  // interface positions before any colouring
+  std::vector<int64_t> ypos(n, -1);
+  for (int64_t t = 0; t < s; ++t) ypos[y[t]] = t;
+  H.c_colors = 0;
+  if (prm.c_order == SLR_CORDER_MULTICOLOR && s > 0) {
+    // greedy colouring in interface order, then a stable sort by colour
+    std::vector<int32_t> color(s, -1);
+    std::vector<int32_t> mark;
+    int32_t ncol = 0;
+    for (int64_t t = 0; t < s; ++t) {
+      int64_t i = y[t];
+      mark.assign(ncol + 1, 0);
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        int64_t u = ypos[col[e]];
+        if (u >= 0 && color[u] >= 0) mark[color[u]] = 1;
+      }
+      int32_t c = 0;
+      while (mark[c]) ++c;
+      color[t] = c;
+      ncol = std::max(ncol, c + 1);
+    }
+    std::vector<int64_t> idx(s);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return color[a] < color[b]; });
+    std::vector<int64_t> y2(s);
+    for (int64_t t = 0; t < s; ++t) y2[t] = y[idx[t]];
+    y.swap(y2);
+    H.c_colors = ncol;
+  } else if (prm.c_order != SLR_CORDER_SUBDOMAIN) {
+    err = "unknown c_order";
+    return SLR_ERR_ARG;
+  }
+  H.perm.insert(H.perm.end(), y.begin(), y.end());
+  H.iperm.assign(n, -1);
+  for (int64_t t = 0; t < n; ++t) H.iperm[H.perm[t]] = t;
+
+  // A in the internal order
+  H.a_rp.assign(n + 1, 0);
+  H.a_ci.clear();
+  H.a_v.clear();
+  H.a_ci.reserve(rowptr[n]);
+  H.a_v.reserve(rowptr[n]);
+  {
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t t = 0; t < n; ++t) {
+      int64_t i = H.perm[t];
+      row.clear();
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+        row.emplace_back((int32_t)H.iperm[col[e]], val[e]);
+      std::sort(row.begin(), row.end());
+      for (auto &pr : row) {
+        H.a_ci.push_back(pr.first);
+        H.a_v.push_back(pr.second);
+      }
+      H.a_rp[t + 1] = (int64_t)H.a_ci.size();
+    }
+  }
+  const bool fp32 = prm.fact_prec == SLR_FP32;
+  // Blocks: B_i factor, E rows and E^T rows (vertex-based partitioning:
+  // interior nodes of subdomain i couple only to the interface of i).
+  H.nnz_E = 0;
+  for (int32_t q = 0; q < p; ++q) {
+    Block &b = H.blocks[q];
+    std::vector<int32_t> rp(b.m + 1, 0), ci;
+    std::vector<double> v;
+    for (int32_t r = 0; r < b.m; ++r) {
+      int64_t t = b.m0 + r;
+      bool has_e = false;
+      for (int64_t e = H.a_rp[t]; e < H.a_rp[t + 1]; ++e) {
+        int64_t c = H.a_ci[e];
+        if (c < m) {
+          if (c < b.m0 || c >= b.m0 + b.m) {
+            err = "interior nodes of two subdomains are coupled";
+            return SLR_ERR_PARTITION;
+          }
+          if (c <= t) {
+            ci.push_back((int32_t)(c - b.m0));
+            v.push_back(H.a_v[e]);
+          }
+        } else {
+          if (!has_e) {
+            b.e_row.push_back(r);
+            b.e_ptr.push_back((int32_t)b.e_q.size());
+            has_e = true;
+          }
+          b.e_q.push_back((int32_t)(c - m));
+          b.e_val.push_back(H.a_v[e]);
+        }
+      }
+      rp[r + 1] = (int32_t)ci.size();
+    }
+    b.e_ptr.push_back((int32_t)b.e_q.size());
+    H.nnz_E += (int64_t)b.e_q.size();
+    LowerFactor F;
+    int rc = factor_block(prm.b_fact, b.m, rp, ci, v, F);
+    if (rc != 0) {
+      err = "factorisation of B_" + std::to_string(q) + " failed at local row " +
+            std::to_string(-1 - rc);
+      return SLR_ERR_BREAKDOWN;
+    }
+    b.nnz_L = (int64_t)F.v.size();
+    build_sweeps(F, fp32, b.fwd, b.bwd);
+  }
+  // E^T rows grouped by owner subdomain
+  for (int64_t t = 0; t < s; ++t) {
+    int64_t i = H.perm[m + t];
+    Block &b = H.blocks[part[i]];
+    b.t_q.push_back((int32_t)t);
+    b.t_ptr.push_back((int32_t)b.t_j.size());
+    for (int64_t e = H.a_rp[m + t]; e < H.a_rp[m + t + 1]; ++e) {
+      int64_t c = H.a_ci[e];
+      if (c < m) {
+        if (c < b.m0 || c >= b.m0 + b.m) {
+          err = "interface node coupled to the interior of another subdomain";
+          return SLR_ERR_PARTITION;
+        }
+        b.t_j.push_back((int32_t)(c - b.m0));
+        b.t_val.push_back(H.a_v[e]);
+      }
+    }
+  }
+  for (auto &b : H.blocks) b.t_ptr.push_back((int32_t)b.t_j.size());
+  // C and its factor (Sec. 3.1: C = L L^T), in the interface order
+  {
+    std::vector<int32_t> rp(s + 1, 0), ci;
+    std::vector<double> v;
+    for (int64_t t = 0; t < s; ++t) {
+      for (int64_t e = H.a_rp[m + t]; e < H.a_rp[m + t + 1]; ++e) {
+        int64_t c = H.a_ci[e];
+        if (c >= m && c <= m + t) {
+          ci.push_back((int32_t)(c - m));
+          v.push_back(H.a_v[e]);
+        }
+      }
+      rp[t + 1] = (int32_t)ci.size();
+    }
+    LowerFactor F;
+    int kind = prm.c_fact == SLR_FACT_CHOL ? SLR_FACT_CHOL : SLR_FACT_IC0;
+    int rc = factor_block(kind, (int32_t)s, rp, ci, v, F);
+    if (rc != 0) {
+      err = "factorisation of C failed at interface row " + std::to_string(-1 - rc);
+      return SLR_ERR_C_NOT_SPD;
+    }
+    H.nnz_LC = (int64_t)F.v.size();
+    build_sweeps(F, fp32, H.cfwd, H.cbwd);
+  }
+  return SLR_OK;
+}
+
+}  // namespace slr

@@ -1,0 +1,71 @@
+// Host-side analysis of the SLR preconditioner: classification, DD
+// ordering, block extraction, local factorisations and level schedules.
+// Everything here runs once per slr_setup; the results are uploaded.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace slr {
+
+// One triangular sweep of one diagonal block, level scheduled.
+// Row t of the level-sorted list computes
+//     x[rows[t]] = sc[t] * x[rows[t]] - sum_e w[e] * x[ci[e]],  e in [rp[t], rp[t+1])
+// in place: x holds the right-hand side on entry.  All indices are local
+// to the block.  The off-diagonal weights are pre-divided by the pivot.
+struct Sweep {
+  int32_t nrows = 0, nlev = 0;
+  std::vector<int32_t> levptr;  // nlev + 1, into the level-sorted rows
+  std::vector<int32_t> rows;    // nrows
+  std::vector<int32_t> rp;      // nrows + 1
+  std::vector<int32_t> ci;
+  std::vector<double> w;
+  std::vector<double> sc;
+};
+
+// Lower factor in CSR (sorted columns, diagonal last in each row).
+// kind 0: L L^T (Cholesky / IC(0));  kind 2: unit L with D in the diagonal slots.
+struct LowerFactor {
+  int32_t n = 0;
+  int kind = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+};
+
+struct Block {            // one subdomain
+  int32_t m0 = 0, m = 0;  // interior range in the internal order
+  Sweep fwd, bwd;
+  // E rows: interior rows (local) coupled to the interface
+  std::vector<int32_t> e_row, e_ptr, e_q;   // e_q: interface index (0..s)
+  std::vector<double> e_val;
+  // E^T rows: interface rows owned by this subdomain
+  std::vector<int32_t> t_q, t_ptr, t_j;     // t_j: local interior index
+  std::vector<double> t_val;
+  int64_t nnz_L = 0;
+};
+
+struct HostSetup {
+  int64_t n = 0, m = 0, s = 0;
+  int32_t p = 0;
+  std::vector<int64_t> perm;    // internal -> original
+  std::vector<int64_t> iperm;   // original -> internal
+  std::vector<Block> blocks;
+  Sweep cfwd, cbwd;             // interface factor sweeps (indices 0..s)
+  int64_t nnz_LC = 0, nnz_E = 0;
+  int32_t c_colors = 0;
+  // A in the internal order (for the Krylov SpMV)
+  std::vector<int64_t> a_rp;
+  std::vector<int32_t> a_ci;
+  std::vector<double> a_v;
+};
+
+struct SetupParams {
+  int b_fact = 1, c_fact = 1, c_order = 0, fact_prec = 0;
+};
+
+// Returns 0 or an SLR_ERR_* code; `err` receives a message.
+int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+               const int32_t *part, int32_t p, const SetupParams &prm, HostSetup &out,
+               std::string &err);
+
+}  // namespace slr

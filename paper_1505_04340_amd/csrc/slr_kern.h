@@ -1,0 +1,96 @@
+// Launchers of the Krylov / Lanczos / utility kernels (slr_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+
+namespace slr {
+
+// Per-column Krylov state kept on the device (CG / flexible CG).
+struct KState {
+  double rz;      // r . z of the current iterate
+  double alpha, beta;
+  double rr;      // ||r||^2 of the recurrence residual
+  double bb;      // ||b||^2
+  double relres;  // final true relative residual
+  int32_t active; // 1 while iterating
+  int32_t status; // 0 converged, -8 not converged / broken down
+  int32_t iters;  // products with A
+  int32_t pad;
+};
+
+struct KArgs {
+  double *X, *R, *Z, *P, *Q;  // n x ncols, leading dimension ld (internal order)
+  int64_t ld;
+  KState *st;
+  double *part;               // nblk x ncols x 2 partials
+  unsigned int *counter;      // last-block ticket (zero between launches)
+  int32_t nblk;
+  int32_t maxit;
+  double rtol2;
+};
+
+enum { CG_INIT = 0, CG_SPMV, CG_UPDATE, CG_BETA, CG_BETA_INIT, CG_P };
+
+// Round an FP64 value for storage: FP32 is round-to-nearest-even; BF16 is
+// round-to-nearest-even of the FP32-rounded value.
+template <typename TU>
+__device__ __forceinline__ TU round_store(double x);
+template <>
+__device__ __forceinline__ double round_store<double>(double x) {
+  return x;
+}
+template <>
+__device__ __forceinline__ float round_store<float>(double x) {
+  return (float)x;
+}
+template <>
+__device__ __forceinline__ __hip_bfloat16 round_store<__hip_bfloat16>(double x) {
+  const float f = (float)x;
+  uint32_t u = __float_as_uint(f);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  __hip_bfloat16 r;
+  unsigned short h = (unsigned short)u;
+  __builtin_memcpy(&r, &h, sizeof(h));
+  return r;
+}
+
+void launch_axpby(int64_t n, int32_t nrhs, double a, const double *x, int64_t ldx, double b, double *y,
+                  int64_t ldy, hipStream_t st);
+void launch_permute(int64_t n, const int64_t *idx, const double *src, int64_t lds, double *dst, int64_t ldd,
+                    int32_t nrhs, bool scatter, hipStream_t st);
+void launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+                 int64_t ldx, double *y, int64_t ldy, int32_t nrhs, hipStream_t st);
+void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const KArgs &K,
+               int32_t c0, int32_t nc, int32_t flexible, hipStream_t st);
+void launch_relres(int64_t n, const double *B, int64_t ldb, const double *AX, int64_t ldax, const KArgs &K,
+                   int32_t c0, int32_t nc, hipStream_t st);
+void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
+                     int32_t nblk, double *out, unsigned int *counter, hipStream_t st);
+void launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const double *h, double *w,
+                     hipStream_t st);
+void launch_gemv_add(int64_t n, int32_t J, const double *V, int64_t ldv, const double *y, double *x,
+                     hipStream_t st);
+void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, const double *sc,
+                         hipStream_t st);
+void launch_scale_inv_sqrt(int64_t s, const double *w, double *out, const double *nrm2, hipStream_t st);
+void launch_div_scalar(int64_t n, const double *w, double *v, const double *scale, hipStream_t st);
+void launch_gmres_givens(int32_t j, int32_t ldh, double *Hm, const double *h1, const double *h2,
+                         const double *hn2, double *cs, double *sn, double *g, double tol, int *flags,
+                         double *vscale, hipStream_t st);
+void launch_gmres_solve(int32_t jj, int32_t ldh, const double *Hm, const double *g, double *y, hipStream_t st);
+void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, double *Z, double *eval, double *Y,
+                        int32_t K, int *info, hipStream_t st);
+template <typename TU>
+void launch_ritz(int64_t s, int32_t m, int32_t k, const double *V, int64_t ldv, const double *Y, double *U64,
+                 TU *U, hipStream_t st);
+template <typename TU>
+void launch_round_copy(int64_t n, const double *src, TU *dst, hipStream_t st);
+
+}  // namespace slr
+
+namespace slr {
+void launch_lanczos_record(int32_t j, double *sc, double *alpha, double *beta, hipStream_t st);
+void launch_gmres_g0(int32_t len, const double *nrm2, double *g, hipStream_t st);
+}  // namespace slr

@@ -1,0 +1,72 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol
+that include/slr.h declares, and the Python structs match the C layout.
+No device compute is called."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slr.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(slr_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1505_04340_amd as P
+    lib = ctypes.CDLL(P.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert sorted(P.EXPORTED) == names
+
+
+def test_binding_struct_layout_matches_header(tmp_path):
+    import paper_1505_04340_amd as P
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "slr.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "sizeof(slr_csr), sizeof(slr_opts), sizeof(slr_solve_opts), sizeof(slr_solve_info),"
+        "sizeof(slr_info), offsetof(slr_opts, lanczos_v0), offsetof(slr_opts, theta_in),"
+        "offsetof(slr_info, theta));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(P.slr_csr), ctypes.sizeof(P.slr_opts), ctypes.sizeof(P.slr_solve_opts),
+            ctypes.sizeof(P.slr_solve_info), ctypes.sizeof(P.slr_info), P.slr_opts.lanczos_v0.offset,
+            P.slr_opts.theta_in.offset, P.slr_info.theta.offset]
+    assert got == want
+
+
+def test_host_only_entry_points():
+    import paper_1505_04340_amd as P
+    o = P.slr_opts()
+    P.slr_default_opts(ctypes.byref(o))
+    assert (o.theta_mode, o.b_fact, o.c_fact, o.fact_prec) == (P.SLR_THETA_LAMBDA_K1, P.SLR_FACT_IC0,
+                                                               P.SLR_FACT_IC0, P.SLR_FP64)
+    so = P.slr_solve_opts()
+    P.slr_default_solve_opts(ctypes.byref(so))
+    assert (so.restart, so.maxit, so.rtol) == (40, 300, 1e-8)
+    assert P.slr_strerror(P.SLR_ERR_NOCONV) == b"did not converge"
+    # null arguments are rejected on the host without touching the device
+    h = ctypes.c_void_p()
+    assert P.slr_setup(None, None, 1, None, None, ctypes.byref(h)) == P.SLR_ERR_ARG
+    assert b"null" in P.slr_last_error()
+    assert P.slr_apply(None, None, None, 1, None) == P.SLR_ERR_ARG
+    assert P.slr_batch_active(None) == 0
+
+
+def test_build_sources_are_gfx950_hip():
+    from paper_1505_04340_amd import build
+    assert build.ARCH == "gfx950" or os.environ.get("SLR_OFFLOAD_ARCH")
+    srcs = build.sources()
+    assert any(s.endswith(".hip") for s in srcs)
+    assert "-packed-fp32-ops" in build.HIP_FLAGS

@@ -1,0 +1,253 @@
+"""Device parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (from the method's problem statement): FP64 apply <= 1e-12 relative
+per column, FP32/BF16-stored apply <= 1e-5 against the oracle run on the
+same rounded stored data; top Ritz values <= 1e-10 relative; solves reach
+true relative residual <= 1e-8 with FP64 iteration counts within +-1 of
+the oracle.  Integer outputs (orderings) must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import slr_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+
+
+def _relerr(a, b):
+    a = np.atleast_2d(np.asarray(a).T).T if np.asarray(a).ndim == 1 else np.asarray(a)
+    b = np.atleast_2d(np.asarray(b).T).T if np.asarray(b).ndim == 1 else np.asarray(b)
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+def _oracle(pr, **kw):
+    args = dict(k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact, c_fact=pr.c_fact, v0=pr.v0())
+    args.update(kw)
+    k = args.pop("k")
+    steps = args.pop("lanczos_steps")
+    return O.setup(pr.csr, pr.part, pr.nparts, k, steps, **args)
+
+
+def _slr(pr, **kw):
+    import paper_1505_04340_amd as P
+    args = dict(k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact, c_fact=pr.c_fact, v0=pr.v0())
+    args.update(kw)
+    return P.SLR(pr.csr, pr.part, pr.nparts, **args)
+
+
+def _rand(n, r, seed):
+    return np.random.default_rng(seed).uniform(-1, 1, (n, r))
+
+
+# ----------------------------------------------------------------- fixtures
+@pytest.fixture(scope="module")
+def lap2d():
+    pr = si.make_config("lap2d_64")
+    return pr, _oracle(pr)
+
+
+@pytest.fixture(scope="module")
+def lap3d():
+    pr = si.make_config("lap3d_64")
+    return pr, _oracle(pr)
+
+
+@pytest.fixture(scope="module")
+def lap3d_mc():
+    pr = si.make_config("lap3d_64")
+    return pr, _oracle(pr, c_order="multicolor")
+
+
+# ------------------------------------------------------- 64x64, exact solves
+def test_lap2d_ordering_and_lanczos(lap2d):
+    pr, Po = lap2d
+    G = _slr(pr)
+    ex = G.export()
+    assert (ex["perm"] == Po.perm).all()
+    assert ex["ritz"].shape[0] == Po.steps
+    rel = np.abs(ex["ritz"][:pr.k + 1] - Po.ritz[:pr.k + 1]) / np.abs(Po.ritz[:pr.k + 1])
+    assert rel.max() <= 1e-10, rel.max()
+    assert abs(ex["theta"] - Po.theta) <= 1e-10 * abs(Po.theta)
+    # the device Ritz vectors span the same converged directions
+    ov = np.abs(np.sum(ex["U"] * Po.U, axis=0))
+    assert ov[:8].min() > 1 - 1e-8
+
+
+def test_lap2d_apply_fp64(lap2d):
+    pr, Po = lap2d
+    G = _slr(pr, lowrank=(Po.U, Po.lam, Po.theta))
+    r = _rand(pr.n, 3, 11)
+    z = G.apply(_dev(r)).cpu().numpy()
+    zo = Po.apply(r)
+    assert _relerr(z, zo).max() <= 1e-12
+
+
+def test_lap2d_pcg(lap2d):
+    pr, Po = lap2d
+    G = _slr(pr)
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "pcg")
+    x, info = G.solve(_dev(b[:, 0]), "pcg")
+    assert info[0]["status"] == 0
+    assert abs(info[0]["iters"] - ro.iters) <= 1
+    assert info[0]["relres"] <= 1e-8
+    rr = np.linalg.norm(b[:, 0] - Po.A @ x.cpu().numpy()) / np.linalg.norm(b[:, 0])
+    assert rr <= 1e-8
+
+
+# ------------------------------------------------------- 64^3, IC(0) / IC(0)
+@pytest.mark.parametrize("which", ["subdomain", "multicolor"])
+def test_lap3d_lanczos_apply_pcg(which, lap3d, lap3d_mc):
+    pr, Po = lap3d if which == "subdomain" else lap3d_mc
+    G = _slr(pr, c_order=which)
+    ex = G.export()
+    assert (ex["perm"] == Po.perm).all()
+    rel = np.abs(ex["ritz"][:pr.k + 1] - Po.ritz[:pr.k + 1]) / np.abs(Po.ritz[:pr.k + 1])
+    assert rel.max() <= 1e-10, rel.max()
+    # apply parity on the oracle's low-rank part
+    Gi = _slr(pr, c_order=which, lowrank=(Po.U, Po.lam, Po.theta))
+    r = _rand(pr.n, 2, 5)
+    assert _relerr(Gi.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max() <= 1e-12
+    # solve parity
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "pcg")
+    x, info = G.solve(_dev(b[:, 0]), "pcg")
+    assert info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    assert abs(info[0]["iters"] - ro.iters) <= 1
+
+
+# --------------------------------------------------- reduced precision forms
+@pytest.mark.parametrize("fact_prec,uk_prec", [("fp32", "fp32"), ("fp32", "bf16"), ("fp64", "bf16")])
+def test_reduced_precision_apply(fact_prec, uk_prec):
+    pr = si.make_config("lap3d_64", N=32, boxes=4)
+    Po = _oracle(pr, fact_prec=fact_prec, uk_prec=uk_prec, c_order="multicolor")
+    G = _slr(pr, fact_prec=fact_prec, uk_prec=uk_prec, c_order="multicolor",
+             lowrank=(O.round_fp32(Po.U) if uk_prec == "fp32" else Po.U, Po.lam, Po.theta))
+    r = _rand(pr.n, 3, 21)
+    err = _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max()
+    tol = 1e-12 if fact_prec == "fp64" and uk_prec == "fp64" else 1e-5
+    if fact_prec == "fp64":
+        tol = 1e-12
+    assert err <= tol, err
+
+
+def test_mixed_form_fcg_reaches_fp64_accuracy():
+    pr = si.make_config("lap3d_64", N=32, boxes=4)
+    G = _slr(pr, fact_prec="fp32", uk_prec="fp32", c_order="multicolor")
+    xs, b = pr.rhs()
+    x, info = G.solve(_dev(b[:, 0]), "fcg")
+    assert info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    Gd = _slr(pr, c_order="multicolor")
+    x2, info2 = Gd.solve(_dev(b[:, 0]), "pcg")
+    assert abs(info[0]["iters"] - info2[0]["iters"]) <= 3
+
+
+# ------------------------------------------- multi-RHS, invariance, edges
+def test_multi_rhs_columns_equal_single_columns():
+    pr = si.make_config("lap3d_64", N=24, boxes=3)
+    G = _slr(pr, fact_prec="fp32", uk_prec="bf16", c_order="multicolor")
+    r = _rand(pr.n, 7, 3)
+    Z = G.apply(_dev(r)).cpu().numpy()
+    for j in (0, 3, 6):
+        zj = G.apply(_dev(r[:, j])).cpu().numpy()
+        assert np.array_equal(zj, Z[:, j])
+
+
+@pytest.mark.parametrize("case", ["ragged", "k0", "theta0", "ildlt"])
+def test_edge_cases_apply(case):
+    if case == "ragged":
+        pr = si.make_config("lap3d_64", N=18, boxes=4)     # boxes of 4 and 5 nodes
+        kw = {}
+    elif case == "k0":
+        pr = si.make_config("lap3d_64", N=16, boxes=2)
+        kw = {"k": 0}
+    elif case == "theta0":
+        pr = si.make_config("lap2d_64", N=40)
+        kw = {"theta_mode": "zero"}
+    else:
+        pr = si.make_config("shifted3d_128", N=16, boxes=2, neg=3)
+        kw = {"k": 8, "lanczos_steps": 40}
+    Po = _oracle(pr, **kw)
+    kk = dict(kw)
+    kk.pop("k", None)
+    kk.pop("lanczos_steps", None)
+    if Po.k:
+        G = _slr(pr, lowrank=(Po.U, Po.lam, Po.theta), **kk)
+    else:
+        G = _slr(pr, k=0, **kk)
+    r = _rand(pr.n, 2, 8)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max() <= 1e-12
+    z0 = G.apply(_dev(np.zeros((pr.n, 1)))).cpu().numpy()
+    assert np.all(z0 == 0)
+
+
+def test_fgmres_indefinite():
+    pr = si.make_config("shifted3d_128", N=24, boxes=4, neg=4)
+    Po = _oracle(pr, k=16, lanczos_steps=80)
+    G = _slr(pr, k=16, lanczos_steps=80)
+    ex = G.export()
+    assert (ex["ritz"][:3] > 1).sum() >= 1          # negative directions of S captured
+    rel = np.abs(ex["ritz"][:17] - Po.ritz[:17]) / np.abs(Po.ritz[:17])
+    assert rel.max() <= 1e-10
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "fgmres")
+    x, info = G.solve(_dev(b[:, 0]), "fgmres")
+    assert info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    assert abs(info[0]["iters"] - ro.iters) <= 1
+
+
+def test_spmv_matches_scipy():
+    pr = si.make_config("diffusion2d_1024", N=64, boxes=4)
+    G = _slr(pr, k=4, lanczos_steps=20)
+    x = _rand(pr.n, 2, 4)
+    y = G.spmv(_dev(x)).cpu().numpy()
+    assert np.abs(y - pr.scipy() @ x).max() <= 1e-13 * np.abs(pr.scipy() @ x).max() * 10
+
+
+# ------------------------------------------------------ continuous batching
+def test_batch_results_equal_alone_and_in_mix():
+    import paper_1505_04340_amd as P
+    pr = si.make_config("lap3d_64", N=24, boxes=3)
+    G = _slr(pr, k=8, lanczos_steps=40, fact_prec="fp32", uk_prec="bf16", c_order="multicolor")
+    rng = np.random.default_rng(0)
+    reqs = [rng.uniform(-1, 1, (pr.n, r)) for r in (1, 3, 2, 1)]
+    # alone: each request in its own batch
+    alone = []
+    for q, b in enumerate(reqs):
+        bt = P.Batch(G, 4, "fcg")
+        x = bt.admit(_dev(b), q)
+        out = []
+        while not out:
+            bt.step(4)
+            out = bt.poll()
+        alone.append((out[0][1].cpu().numpy(), out[0][2]))
+        bt.close()
+    # mix: requests arrive while others are in flight
+    bt = P.Batch(G, 5, "fcg")
+    got = {}
+    pending = list(enumerate(reqs))
+    steps = 0
+    while len(got) < len(reqs):
+        while pending and bt.admit(_dev(pending[0][1]), pending[0][0]) is not None:
+            pending.pop(0)
+        bt.step(3)
+        steps += 1
+        for tag, x, info in bt.poll():
+            got[tag] = (x.cpu().numpy(), info)
+        assert steps < 1000
+    for q in range(len(reqs)):
+        xa, ia = alone[q]
+        xm, im = got[q]
+        assert ia["status"] == 0 and im["status"] == 0
+        assert ia["iters"] == im["iters"]
+        assert np.array_equal(xa.reshape(pr.n, -1), xm.reshape(pr.n, -1))
+        assert im["relres"] <= 1e-8

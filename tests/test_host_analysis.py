@@ -1,0 +1,65 @@
+"""Host analysis of the library (slr_analyze: classification, DD ordering,
+factorisation sizes, level schedules) against the oracle -- CPU only.
+Integer results must match exactly."""
+import numpy as np
+import pytest
+
+import oracle as O
+import slr_inputs as si
+
+CASES = [
+    ("lap2d_64", {}, "chol", "chol", "subdomain"),
+    ("lap3d_64", {"N": 16, "boxes": 2}, "ic0", "ic0", "subdomain"),
+    ("lap3d_64", {"N": 16, "boxes": 2}, "ic0", "ic0", "multicolor"),
+    ("lap3d_64", {"N": 18, "boxes": 4}, "ic0", "ic0", "multicolor"),   # ragged boxes 4/5 wide
+    ("shifted3d_128", {"N": 16, "boxes": 2, "neg": 3}, "ildlt0", "ic0", "subdomain"),
+    ("diffusion2d_1024", {"N": 96, "boxes": 4}, "ic0", "ic0", "multicolor"),
+]
+
+
+@pytest.mark.parametrize("name,over,bf,cf,co", CASES)
+def test_analysis_matches_oracle(name, over, bf, cf, co):
+    import paper_1505_04340_amd as P
+    pr = si.make_config(name, **over)
+    info, perm = P.analyze(pr.csr, pr.part, pr.nparts, k=4, b_fact=bf, c_fact=cf, c_order=co)
+    Ps = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=bf, c_fact=cf, c_order=co)
+    assert (perm == Ps.perm).all()
+    assert info["m"] == Ps.m and info["s"] == Ps.s and info["p"] == pr.nparts
+    if bf != "chol":
+        assert info["nnz_LB"] == Ps.FB.v.size
+    if cf != "chol":
+        assert info["nnz_LC"] == Ps.FC.v.size
+    assert info["nnz_E"] == Ps.E.nnz
+    if co == "multicolor":
+        assert info["c_colors"] == int(Ps.colors.max()) + 1
+        assert info["c_levels"] <= info["c_colors"]
+    assert info["device_bytes"] > 0
+
+
+def test_analysis_errors_are_reported():
+    import paper_1505_04340_amd as P
+    pr = si.make_config("lap2d_64", N=12)
+    bad = pr.part.copy()
+    bad[3] = 7
+    with pytest.raises(P.SLRError) as e:
+        P.analyze(pr.csr, bad, 4)
+    assert e.value.code == P.SLR_ERR_PARTITION
+    A, part = si.separator_model(6, 3)
+    with pytest.raises(P.SLRError) as e:
+        P.analyze(A, part, 2)
+    assert e.value.code == P.SLR_ERR_PARTITION
+    indptr, indices, data, n = pr.csr
+    d2 = data.copy()
+    d2[1] += 1e-3                       # breaks symmetry of one pair
+    with pytest.raises(P.SLRError) as e:
+        P.analyze((indptr, indices, d2, n), pr.part, 4)
+    assert e.value.code == P.SLR_ERR_NOT_SYMMETRIC
+    # a strongly shifted matrix: IC(0) of a B_i breaks down
+    csr = si.laplacian_2d(12, shift=7.0)
+    with pytest.raises(P.SLRError) as e:
+        P.analyze(csr, pr.part, 4, b_fact="ic0")
+    assert e.value.code == P.SLR_ERR_BREAKDOWN
+    # ILDL^T(0) takes it, but C = IC(0) of the shifted interface does not
+    with pytest.raises(P.SLRError) as e:
+        P.analyze(csr, pr.part, 4, b_fact="ildlt0")
+    assert e.value.code == P.SLR_ERR_C_NOT_SPD
