@@ -111,6 +111,7 @@ def main():
               uk_prec=form["uk_prec"], v0=pr.v0())
     torch.cuda.synchronize()
     info = G.query()
+    log(f"[bench] device LDS per workgroup {P.slr_device_lds_bytes()} bytes")
     log(f"[bench] setup done in {time.perf_counter() - t0:.2f} s (host {info['setup_host_s']:.2f} s, "
         f"Lanczos {info['setup_lanczos_s']:.3f} s); s={info['s']} m={info['m']}")
     xs, b = pr.rhs()

@@ -23,6 +23,9 @@ namespace {
 
 thread_local std::string g_err;
 
+constexpr int64_t pad8h(int64_t x) { return (x + 7) & ~int64_t(7); }
+constexpr int64_t pad16h(int64_t x) { return (x + 15) & ~int64_t(15); }
+
 int fail(int code, const std::string &msg) {
   g_err = msg;
   return code;
@@ -107,14 +110,15 @@ struct slr_ctx {
   std::vector<int32_t> cf_lev_h, cb_lev_h;
   int32_t cf_nlev = 0, cb_nlev = 0;
   bool c_one_wg = true;
-  int32_t b_threads = 256;
-  int32_t b_max_m = 0, b_max_lev = 0;
+  int32_t b_threads = 1024;
+  int32_t b_max_m = 0, b_max_lev = 0, b_max_level_bytes = 0;
+  int64_t b_data_bytes = 0;
   size_t lds_limit = 65536;
   // low-rank part
   int32_t k = 0;
   double theta = 0.0, rho = 1.0;
-  void *U = nullptr;            // s x k row-major, storage precision
-  double *U64 = nullptr;        // s x k row-major, FP64 (export)
+  void *U = nullptr;            // s x k column-major, storage precision
+  double *U64 = nullptr;        // s x k column-major, FP64 (export)
   double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
   int32_t lr_nblk = 256;
@@ -131,7 +135,7 @@ struct slr_ctx {
   int32_t scap = 0;
   double *sX = nullptr, *sR = nullptr, *sZ = nullptr, *sP = nullptr, *sQ = nullptr, *sB = nullptr;
   KState *sst = nullptr;
-  double *spart = nullptr;
+  double *spart = nullptr, *spart2 = nullptr;
   unsigned int *scnt = nullptr;
 };
 
@@ -143,8 +147,9 @@ struct slr_batch {
   ApplyWS ws;
   double *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr, *B = nullptr;
   KState *st = nullptr;
-  double *part = nullptr;
+  double *part = nullptr, *part2 = nullptr;
   unsigned int *counter = nullptr;
+  int32_t it = 0;               // global iteration counter of the batch
   std::vector<int64_t> owner;   // request index per column, -1 free
   struct Req {
     int64_t tag;
@@ -159,7 +164,7 @@ struct slr_batch {
 
 namespace {
 
-constexpr int RED_NBLK = 512;
+constexpr int RED_NBLK = 128;   // blocks of the deterministic reductions
 
 int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   if (w.cap >= nrhs && w.W) return SLR_OK;
@@ -175,22 +180,36 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   return SLR_OK;
 }
 
-// largest number of right-hand sides per B workgroup that fits the LDS
-int32_t b_rhs_per_wg(const slr_ctx *c, int32_t nrhs, size_t tc_bytes) {
-  size_t lev = sizeof(int32_t) * 2 * (size_t)(c->b_max_lev + 1);
-  size_t per = tc_bytes * (size_t)std::max(c->b_max_m, 1);
-  if (per + lev > c->lds_limit) return 0;
-  int32_t R = (int32_t)std::min<size_t>((c->lds_limit - lev) / per, 16);
-  return std::max(1, std::min(R, nrhs));
+// LDS plan of the B kernel: right-hand sides per workgroup R and the
+// staging buffer for the packed sweeps.  Total LDS = stage + pad16(x) +
+// 16 (max_lev + 1).  R is the largest value (<= nrhs, <= 16) that still
+// leaves a staging buffer of at least max(largest level, min(24 KiB,
+// largest sweep)).  Returns false when not even R = 1 fits.
+bool b_lds_plan(const slr_ctx *c, int32_t nrhs, size_t tc_bytes, int32_t &R, int32_t &stage) {
+  const int64_t fixed = 16 * (int64_t)(c->b_max_lev + 1) + 16;
+  const int64_t need = std::max<int64_t>(c->b_max_level_bytes, std::min<int64_t>(24576, c->b_data_bytes));
+  for (int32_t r = std::min<int32_t>(std::max(nrhs, 1), 16); r >= 1; --r) {
+    const int64_t xb = pad16h((int64_t)tc_bytes * (std::max(c->b_max_m, 1) * r + 1));
+    const int64_t rest = ((int64_t)c->lds_limit - fixed - xb) & ~int64_t(15);
+    if (rest >= need) {
+      R = r;
+      stage = (int32_t)std::min<int64_t>(rest, pad16h(c->b_data_bytes));
+      return true;
+    }
+  }
+  return false;
 }
 
 template <typename TS, typename TC>
 int run_bsolve(slr_ctx *c, const BlockArrays<TS> &B, const BArgs &a0, hipStream_t st) {
   BArgs a = a0;
-  int32_t R = b_rhs_per_wg(c, a.nrhs, sizeof(TC));
-  if (R == 0) return fail(SLR_ERR_ARG, "a subdomain does not fit the LDS of one workgroup");
+  int32_t R = 0, stage = 0;
+  if (!b_lds_plan(c, a.nrhs, sizeof(TC), R, stage))
+    return fail(SLR_ERR_ARG, "a subdomain does not fit the LDS of one workgroup");
   a.R = R;
-  size_t lds = sizeof(TC) * (size_t)c->b_max_m * R + sizeof(int32_t) * 2 * (size_t)(c->b_max_lev + 1);
+  a.stage_bytes = stage;
+  const size_t lds = (size_t)stage + 16 + pad16h((int64_t)sizeof(TC) * (c->b_max_m * R + 1)) +
+                    16 * (size_t)(c->b_max_lev + 1);
   launch_bsolve<TS, TC>(B, c->p, a, c->b_threads, lds, st);
   return SLR_OK;
 }
@@ -381,7 +400,7 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   }
   const int32_t need = need_k1 ? k + 1 : k;
   if (mm < need) return bail(fail(SLR_ERR_LANCZOS_SHORT, "Lanczos produced fewer Ritz pairs than needed"));
-  double *Z = tmp.alloc<double>((size_t)mm * mm);
+  double *Z = tmp.alloc<double>((size_t)6 * mm * std::max(k, 1));   // eigensolver scratch
   double *ev = tmp.alloc<double>(mm);
   double *Y = tmp.alloc<double>((size_t)mm * std::max(k, 1));
   int *info = tmp.alloc<int>(1);
@@ -403,77 +422,134 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   return finish_lowrank(c, st);
 }
 
+// Pack one sweep of one subdomain as the level-sliced ELL byte stream the
+// B kernel stages into LDS (layout documented with BlockDesc).
+template <typename TS>
+void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::vector<int32_t> &lvb, int32_t &K,
+                int32_t &max_level_bytes, int64_t &offset) {
+  K = 0;
+  for (int32_t t = 0; t < sw.nrows; ++t) K = std::max(K, sw.rp[t + 1] - sw.rp[t]);
+  if (Kfix > 0) K = Kfix;
+  offset = (int64_t)data.size();
+  int64_t pos = 0;
+  lvb.push_back(0);
+  for (int32_t l = 0; l < sw.nlev; ++l) {
+    const int32_t a = sw.levptr[l], L = sw.levptr[l + 1] - a;
+    const int64_t o_sc = pad8h(2 * L), o_ci = o_sc + pad8h((int64_t)sizeof(TS) * L);
+    const int64_t o_w = o_ci + pad8h(2 * (int64_t)K * L);
+    const int64_t size = pad16h(o_w + (int64_t)sizeof(TS) * K * L);
+    data.resize(offset + pos + size, 0);
+    uint8_t *base = data.data() + offset + pos;
+    uint16_t *rows = reinterpret_cast<uint16_t *>(base);
+    TS *sc = reinterpret_cast<TS *>(base + o_sc);
+    uint16_t *ci = reinterpret_cast<uint16_t *>(base + o_ci);
+    TS *w = reinterpret_cast<TS *>(base + o_w);
+    for (int32_t j = 0; j < L; ++j) {
+      const int32_t t = a + j, row = sw.rows[t];
+      rows[j] = (uint16_t)row;
+      sc[j] = (TS)sw.sc[t];
+      const int32_t e0 = sw.rp[t], cnt = sw.rp[t + 1] - e0;
+      for (int32_t e = 0; e < K; ++e) {
+        ci[(int64_t)e * L + j] = (uint16_t)(e < cnt ? sw.ci[e0 + e] : row);
+        w[(int64_t)e * L + j] = e < cnt ? (TS)sw.w[e0 + e] : (TS)0;
+      }
+    }
+    max_level_bytes = std::max<int32_t>(max_level_bytes, (int32_t)size);
+    pos += size;
+    lvb.push_back((int32_t)pos);
+  }
+}
+
 template <typename TS>
 void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArrays<TS> &Cf, SweepArrays<TS> &Cb,
                    bool &ok) {
   std::vector<BlockDesc> desc(H.p);
-  std::vector<int32_t> f_lev, f_rows, f_rp, f_ci, b_lev, b_rows, b_rp, b_ci;
-  std::vector<double> f_w, f_sc, b_w, b_sc;
-  std::vector<int32_t> e_row, e_ptr, e_q, t_q, t_ptr, t_j;
+  std::vector<int32_t> lev, lvb;
+  std::vector<uint8_t> data;
+  std::vector<uint16_t> e_row, t_j;
+  std::vector<int32_t> e_q, t_q;
   std::vector<double> e_val, t_val;
-  int32_t max_m = 0, max_lev = 0;
+  int32_t max_m = 0, max_lev = 0, max_lb = 0, max_K = 0;
+  ok = true;
+  // widest row of any sweep; rows are padded to it when it is small
+  int32_t widest = 0;
+  for (const Block &b : H.blocks)
+    for (const Sweep *sw : {&b.fwd, &b.bwd})
+      for (int32_t t = 0; t < sw->nrows; ++t) widest = std::max(widest, sw->rp[t + 1] - sw->rp[t]);
+  const int32_t Kfix = (widest >= 1 && widest <= 4) ? widest : 0;
   for (int32_t q = 0; q < H.p; ++q) {
     const Block &b = H.blocks[q];
     BlockDesc &d = desc[q];
     d.m0 = b.m0;
     d.m = b.m;
+    if (b.m > 65535) ok = false;   // uint16 local indices
     max_m = std::max(max_m, b.m);
     max_lev = std::max({max_lev, b.fwd.nlev, b.bwd.nlev});
-    auto put = [](const Sweep &sw, std::vector<int32_t> &lev, std::vector<int32_t> &rows,
-                  std::vector<int32_t> &rp, std::vector<int32_t> &ci, std::vector<double> &w,
-                  std::vector<double> &sc, int32_t &o_lev, int32_t &o_nlev, int32_t &o_row, int32_t &o_rp,
-                  int32_t &o_ent) {
-      o_lev = (int32_t)lev.size();
-      o_nlev = sw.nlev;
-      o_row = (int32_t)rows.size();
-      o_rp = (int32_t)rp.size();
-      o_ent = (int32_t)ci.size();
-      lev.insert(lev.end(), sw.levptr.begin(), sw.levptr.end());
-      if (sw.levptr.empty()) lev.push_back(0);
-      rows.insert(rows.end(), sw.rows.begin(), sw.rows.end());
-      sc.insert(sc.end(), sw.sc.begin(), sw.sc.end());
-      for (int32_t x : sw.rp) rp.push_back(o_ent + x);
-      if (sw.rp.empty()) rp.push_back(o_ent);
-      ci.insert(ci.end(), sw.ci.begin(), sw.ci.end());
-      w.insert(w.end(), sw.w.begin(), sw.w.end());
-    };
-    put(b.fwd, f_lev, f_rows, f_rp, f_ci, f_w, f_sc, d.f_lev, d.f_nlev, d.f_row, d.f_rp, d.f_ent);
-    put(b.bwd, b_lev, b_rows, b_rp, b_ci, b_w, b_sc, d.b_lev, d.b_nlev, d.b_row, d.b_rp, d.b_ent);
+    d.f_nlev = b.fwd.nlev;
+    d.f_lev = (int32_t)lev.size();
+    lev.insert(lev.end(), b.fwd.levptr.begin(), b.fwd.levptr.end());
+    if (b.fwd.levptr.empty()) lev.push_back(0);
+    d.f_lvb = (int32_t)lvb.size();
+    pack_sweep<TS>(b.fwd, Kfix, data, lvb, d.f_K, max_lb, d.f_data);
+    d.b_nlev = b.bwd.nlev;
+    d.b_lev = (int32_t)lev.size();
+    lev.insert(lev.end(), b.bwd.levptr.begin(), b.bwd.levptr.end());
+    if (b.bwd.levptr.empty()) lev.push_back(0);
+    d.b_lvb = (int32_t)lvb.size();
+    pack_sweep<TS>(b.bwd, Kfix, data, lvb, d.b_K, max_lb, d.b_data);
+    max_K = std::max({max_K, d.f_K, d.b_K});
+    // E rows as ELL (width = longest row)
     d.e_row = (int32_t)e_row.size();
     d.e_n = (int32_t)b.e_row.size();
-    d.e_ptr = (int32_t)e_ptr.size();
-    const int32_t eb = (int32_t)e_q.size();
-    e_row.insert(e_row.end(), b.e_row.begin(), b.e_row.end());
-    for (int32_t x : b.e_ptr) e_ptr.push_back(eb + x);
-    e_q.insert(e_q.end(), b.e_q.begin(), b.e_q.end());
-    e_val.insert(e_val.end(), b.e_val.begin(), b.e_val.end());
+    d.e_K = 0;
+    for (int32_t i = 0; i < d.e_n; ++i) d.e_K = std::max(d.e_K, b.e_ptr[i + 1] - b.e_ptr[i]);
+    d.e_ent = (int32_t)e_q.size();
+    for (int32_t i = 0; i < d.e_n; ++i) e_row.push_back((uint16_t)b.e_row[i]);
+    e_q.resize(e_q.size() + (size_t)d.e_K * d.e_n, 0);
+    e_val.resize(e_val.size() + (size_t)d.e_K * d.e_n, 0.0);
+    for (int32_t i = 0; i < d.e_n; ++i)
+      for (int32_t e = 0; e < b.e_ptr[i + 1] - b.e_ptr[i]; ++e) {
+        e_q[d.e_ent + (size_t)e * d.e_n + i] = b.e_q[b.e_ptr[i] + e];
+        e_val[d.e_ent + (size_t)e * d.e_n + i] = b.e_val[b.e_ptr[i] + e];
+      }
+    // E^T rows as ELL
     d.t_row = (int32_t)t_q.size();
     d.t_n = (int32_t)b.t_q.size();
-    d.t_ptr = (int32_t)t_ptr.size();
-    const int32_t tb = (int32_t)t_j.size();
+    d.t_K = 0;
+    for (int32_t i = 0; i < d.t_n; ++i) d.t_K = std::max(d.t_K, b.t_ptr[i + 1] - b.t_ptr[i]);
+    d.t_ent = (int32_t)t_j.size();
     t_q.insert(t_q.end(), b.t_q.begin(), b.t_q.end());
-    for (int32_t x : b.t_ptr) t_ptr.push_back(tb + x);
-    t_j.insert(t_j.end(), b.t_j.begin(), b.t_j.end());
-    t_val.insert(t_val.end(), b.t_val.begin(), b.t_val.end());
+    t_j.resize(t_j.size() + (size_t)d.t_K * d.t_n, 0);
+    t_val.resize(t_val.size() + (size_t)d.t_K * d.t_n, 0.0);
+    for (int32_t i = 0; i < d.t_n; ++i)
+      for (int32_t e = 0; e < b.t_ptr[i + 1] - b.t_ptr[i]; ++e) {
+        t_j[d.t_ent + (size_t)e * d.t_n + i] = (uint16_t)b.t_j[b.t_ptr[i] + e];
+        t_val[d.t_ent + (size_t)e * d.t_n + i] = b.t_val[b.t_ptr[i] + e];
+      }
   }
+  if (data.empty()) data.resize(16, 0);
   auto &P = c->pool;
   B.desc = P.upload(desc);
-  B.fwd.lev = P.upload(f_lev); B.fwd.rows = P.upload(f_rows); B.fwd.rp = P.upload(f_rp);
-  B.fwd.ci = P.upload(f_ci); B.fwd.w = P.upload(conv<TS>(f_w)); B.fwd.sc = P.upload(conv<TS>(f_sc));
-  B.bwd.lev = P.upload(b_lev); B.bwd.rows = P.upload(b_rows); B.bwd.rp = P.upload(b_rp);
-  B.bwd.ci = P.upload(b_ci); B.bwd.w = P.upload(conv<TS>(b_w)); B.bwd.sc = P.upload(conv<TS>(b_sc));
-  B.e_row = P.upload(e_row); B.e_ptr = P.upload(e_ptr); B.e_q = P.upload(e_q);
+  B.lev = P.upload(lev);
+  B.lvb = P.upload(lvb);
+  B.data = P.upload(data);
+  B.e_row = P.upload(e_row); B.e_q = P.upload(e_q);
   B.e_val = P.upload(conv<TS>(e_val));
-  B.t_q = P.upload(t_q); B.t_ptr = P.upload(t_ptr); B.t_j = P.upload(t_j);
+  B.t_q = P.upload(t_q); B.t_j = P.upload(t_j);
   B.t_val = P.upload(conv<TS>(t_val));
   B.max_m = max_m;
   B.max_lev = max_lev;
+  B.max_level_bytes = max_lb;
+  B.max_K = max_K;
+  B.pack_K = Kfix;
   c->b_max_m = max_m;
   c->b_max_lev = max_lev;
+  c->b_max_level_bytes = max_lb;
+  c->b_data_bytes = (int64_t)data.size();
   auto upc = [&](const Sweep &sw, SweepArrays<TS> &S) {
-    std::vector<int32_t> lev = sw.levptr;
-    if (lev.empty()) lev.push_back(0);
-    S.lev = P.upload(lev);
+    std::vector<int32_t> lv = sw.levptr;
+    if (lv.empty()) lv.push_back(0);
+    S.lev = P.upload(lv);
     S.rows = P.upload(sw.rows);
     S.rp = P.upload(sw.rp.empty() ? std::vector<int32_t>{0} : sw.rp);
     S.ci = P.upload(sw.ci);
@@ -481,9 +557,7 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
     S.sc = P.upload(conv<TS>(sw.sc));
     return S.lev && S.rows && S.rp && S.ci && S.w && S.sc;
   };
-  ok = B.desc && B.fwd.lev && B.fwd.rows && B.fwd.rp && B.fwd.ci && B.fwd.w && B.fwd.sc && B.bwd.lev &&
-       B.bwd.rows && B.bwd.rp && B.bwd.ci && B.bwd.w && B.bwd.sc && B.e_row && B.e_ptr && B.e_q && B.e_val &&
-       B.t_q && B.t_ptr && B.t_j && B.t_val;
+  ok = ok && B.desc && B.lev && B.lvb && B.data && B.e_row && B.e_q && B.e_val && B.t_q && B.t_j && B.t_val;
   ok = ok && upc(H.cfwd, Cf) && upc(H.cbwd, Cb);
 }
 
@@ -615,7 +689,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
     upload_blocks<float>(c, H, c->Bf, c->Cff, c->Cbf, ok2);
     ok = ok && ok2;
   }
-  if (!ok) return destroy_fail(fail(SLR_ERR_OOM, "factor upload"));
+  if (!ok) return destroy_fail(fail(SLR_ERR_OOM, "factor upload (or a subdomain above 65535 rows)"));
   c->cf_lev_h = H.cfwd.levptr;
   c->cb_lev_h = H.cbwd.levptr;
   c->cf_nlev = H.cfwd.nlev;
@@ -624,8 +698,11 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->c_one_wg = std::max(c->cf_nlev, c->cb_nlev) > 8;
   if (c->c_one_wg && sizeof(int32_t) * (size_t)(std::max(c->cf_nlev, c->cb_nlev) + 1) > c->lds_limit)
     return destroy_fail(fail(SLR_ERR_ARG, "interface level schedule too deep for one workgroup"));
-  if (b_rhs_per_wg(c, 1, 8) == 0 && b_rhs_per_wg(c, 1, 4) == 0)
-    return destroy_fail(fail(SLR_ERR_ARG, "largest subdomain does not fit one workgroup's LDS"));
+  {
+    int32_t R1 = 0, st1 = 0;
+    if (!b_lds_plan(c, 1, c->fact_prec == SLR_FP64 ? 8 : 4, R1, st1) || !b_lds_plan(c, 1, 8, R1, st1))
+      return destroy_fail(fail(SLR_ERR_ARG, "largest subdomain does not fit one workgroup's LDS"));
+  }
   // stats
   slr_info &I = c->info;
   I.n = c->n; I.m = c->m; I.s = c->s; I.p = c->p;
@@ -648,10 +725,8 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   if (o->U_in && o->k_in > 0) {
     if (o->k_in > 64 || !o->lambda_in) return destroy_fail(fail(SLR_ERR_ARG, "imported low-rank part"));
     c->k = o->k_in;
-    std::vector<double> Urm((size_t)c->s * c->k);
-    for (int64_t i = 0; i < c->s; ++i)
-      for (int q = 0; q < c->k; ++q) Urm[i * c->k + q] = o->U_in[i + (int64_t)q * c->s];
-    c->U64 = c->lrpool.upload(Urm);
+    std::vector<double> Ucm(o->U_in, o->U_in + (size_t)c->s * c->k);   // column-major s x k
+    c->U64 = c->lrpool.upload(Ucm);
     if (!c->U64) return destroy_fail(fail(SLR_ERR_OOM, "U"));
     c->lam_h.assign(o->lambda_in, o->lambda_in + c->k);
     c->ritz_h = c->lam_h;
@@ -833,12 +908,8 @@ int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda, do
   if (lambda) std::copy(c->lam_h.begin(), c->lam_h.end(), lambda);
   if (alpha) std::copy(c->alpha_h.begin(), c->alpha_h.end(), alpha);
   if (beta) std::copy(c->beta_h.begin(), c->beta_h.end(), beta);
-  if (U && c->k > 0) {
-    std::vector<double> Urm((size_t)c->s * c->k);
-    HIPCHK(hipMemcpy(Urm.data(), c->U64, sizeof(double) * Urm.size(), hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < c->s; ++i)
-      for (int q = 0; q < c->k; ++q) U[i + (int64_t)q * c->s] = Urm[i * c->k + q];
-  }
+  if (U && c->k > 0)
+    HIPCHK(hipMemcpy(U, c->U64, sizeof(double) * (size_t)c->s * c->k, hipMemcpyDeviceToHost));
   return SLR_OK;
 }
 
@@ -895,46 +966,51 @@ int solve_ws(slr_ctx *c, int32_t nrhs) {
   c->sB = c->spool.alloc<double>(n * nrhs);
   c->sst = c->spool.alloc<KState>(nrhs);
   c->spart = c->spool.alloc<double>((size_t)RED_NBLK * nrhs * 2);
+  c->spart2 = c->spool.alloc<double>((size_t)RED_NBLK * nrhs);
   c->scnt = c->spool.alloc<unsigned int>(4);
-  if (!c->sX || !c->sR || !c->sZ || !c->sP || !c->sQ || !c->sB || !c->sst || !c->spart || !c->scnt)
+  if (!c->sX || !c->sR || !c->sZ || !c->sP || !c->sQ || !c->sB || !c->sst || !c->spart || !c->spart2 || !c->scnt)
     return fail(SLR_ERR_OOM, "solve workspace");
   HIPCHK(hipMemset(c->scnt, 0, 4 * sizeof(unsigned int)));
   c->scap = nrhs;
   return SLR_OK;
 }
 
-KArgs kargs(slr_ctx *c, double *X, double *R, double *Z, double *P, double *Q, int64_t ld, KState *st,
-            double *part, unsigned int *cnt, int maxit, double rtol) {
+KArgs kargs(double *X, double *R, double *Z, double *P, double *Q, int64_t ld, KState *st, double *part,
+            double *part2, int maxit, double rtol) {
   KArgs K;
   K.X = X; K.R = R; K.Z = Z; K.P = P; K.Q = Q;
   K.ld = ld;
   K.st = st;
   K.part = part;
-  K.counter = cnt;
+  K.part2 = part2;
+  K.counter = nullptr;
   K.nblk = RED_NBLK;
   K.maxit = maxit;
   K.rtol2 = rtol * rtol;
-  (void)c;
   return K;
 }
 
-// CG / flexible CG on columns [c0, c0+nc) whose R holds b (internal order).
-int cg_start(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, hipStream_t st) {
-  launch_cg(CG_INIT, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+// CG / flexible CG start on columns [c0, c0+nc) whose R holds b (internal
+// order); it0 is the global index of their first iteration.
+int cg_start(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, int32_t it0,
+             hipStream_t st) {
+  launch_cg(CG_INIT, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it0, st);
   int rc = apply_dd(c, w, K.R + (int64_t)c0 * K.ld, K.ld, K.Z + (int64_t)c0 * K.ld, K.ld, nc, st);
   if (rc) return rc;
-  launch_cg(CG_BETA_INIT, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+  launch_cg(CG_START, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it0, st);
   launch_axpby(c->n, nc, 1.0, K.Z + (int64_t)c0 * K.ld, K.ld, 0.0, K.P + (int64_t)c0 * K.ld, K.ld, st);
   return SLR_OK;
 }
 
-int cg_iter(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, hipStream_t st) {
-  launch_cg(CG_SPMV, c->n, c->a_rp, c->a_ci, c->a_v, K, c0, nc, flexible, st);
-  launch_cg(CG_UPDATE, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+// one iteration (global index it) of every column in [c0, c0+nc)
+int cg_iter(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, int32_t it,
+            hipStream_t st) {
+  launch_cg(CG_SPMV, c->n, c->a_rp, c->a_ci, c->a_v, K, c0, nc, flexible, it, st);
+  launch_cg(CG_UPDATE, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
   int rc = apply_dd(c, w, K.R + (int64_t)c0 * K.ld, K.ld, K.Z + (int64_t)c0 * K.ld, K.ld, nc, st);
   if (rc) return rc;
-  launch_cg(CG_BETA, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
-  launch_cg(CG_P, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, st);
+  launch_cg(CG_BETA, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
+  launch_cg(CG_P, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
   return SLR_OK;
 }
 
@@ -944,15 +1020,15 @@ int solve_cg(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const
   if (rc) return rc;
   const int64_t n = c->n;
   const int flexible = so.method == SLR_FCG;
-  KArgs K = kargs(c, c->sX, c->sR, c->sZ, c->sP, c->sQ, n, c->sst, c->spart, c->scnt, so.maxit, so.rtol);
+  KArgs K = kargs(c->sX, c->sR, c->sZ, c->sP, c->sQ, n, c->sst, c->spart, c->spart2, so.maxit, so.rtol);
   launch_permute(n, c->perm, b_dev, n, c->sB, n, nrhs, false, st);
   launch_axpby(n, nrhs, 1.0, c->sB, n, 0.0, c->sR, n, st);
-  if ((rc = cg_start(c, c->ws, K, 0, nrhs, flexible, st))) return rc;
+  if ((rc = cg_start(c, c->ws, K, 0, nrhs, flexible, 1, st))) return rc;
   std::vector<KState> h(nrhs);
   const int every = std::max(1, so.check_every);
   for (int it = 0; it < so.maxit; it += every) {
     for (int j = 0; j < every && it + j < so.maxit; ++j)
-      if ((rc = cg_iter(c, c->ws, K, 0, nrhs, flexible, st))) return rc;
+      if ((rc = cg_iter(c, c->ws, K, 0, nrhs, flexible, it + j + 1, st))) return rc;
     HIPCHK(hipMemcpyAsync(h.data(), c->sst, sizeof(KState) * nrhs, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool any = false;
@@ -1085,6 +1161,7 @@ int slr_solve(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, cons
     return solve_fgmres(c, b_dev, x_dev, so, info, st);
   }
   if (so.method != SLR_PCG && so.method != SLR_FCG) return fail(SLR_ERR_ARG, "method");
+  if (nrhs > 128) return fail(SLR_ERR_ARG, "at most 128 right-hand sides per solve");
   return solve_cg(c, b_dev, x_dev, nrhs, so, info, st);
 }
 
@@ -1092,8 +1169,9 @@ int slr_solve(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, cons
 // continuous batching
 // ---------------------------------------------------------------------------
 int slr_batch_create(slr_ctx *c, int32_t max_cols, int32_t method, double rtol, int32_t maxit, slr_batch **out) {
-  if (!c || !out || max_cols <= 0 || (method != SLR_PCG && method != SLR_FCG) || !(rtol > 0) || maxit <= 0)
-    return fail(SLR_ERR_ARG, "bad batch arguments");
+  if (!c || !out || max_cols <= 0 || max_cols > 128 || (method != SLR_PCG && method != SLR_FCG) || !(rtol > 0) ||
+      maxit <= 0)
+    return fail(SLR_ERR_ARG, "bad batch arguments (max_cols must be in 1..128)");
   slr_batch *b = new slr_batch();
   b->c = c;
   b->cap = max_cols;
@@ -1109,8 +1187,9 @@ int slr_batch_create(slr_ctx *c, int32_t max_cols, int32_t method, double rtol, 
   b->B = b->pool.alloc<double>(n * max_cols);
   b->st = b->pool.alloc<KState>(max_cols);
   b->part = b->pool.alloc<double>((size_t)RED_NBLK * max_cols * 2);
+  b->part2 = b->pool.alloc<double>((size_t)RED_NBLK * max_cols);
   b->counter = b->pool.alloc<unsigned int>(4);
-  if (!b->X || !b->R || !b->Z || !b->P || !b->Q || !b->B || !b->st || !b->part || !b->counter) {
+  if (!b->X || !b->R || !b->Z || !b->P || !b->Q || !b->B || !b->st || !b->part || !b->part2 || !b->counter) {
     slr_batch_destroy(b);
     return fail(SLR_ERR_OOM, "batch state");
   }
@@ -1162,10 +1241,10 @@ int slr_batch_admit(slr_batch *b, const double *b_dev, double *x_dev, int32_t nr
   slr_ctx *c = b->c;
   hipStream_t st = S(hip_stream);
   const int64_t n = c->n;
-  KArgs K = kargs(c, b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->counter, b->maxit, b->rtol);
+  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->part2, b->maxit, b->rtol);
   launch_permute(n, c->perm, b_dev, n, b->B + (int64_t)c0 * n, n, nrhs, false, st);
   launch_axpby(n, nrhs, 1.0, b->B + (int64_t)c0 * n, n, 0.0, b->R + (int64_t)c0 * n, n, st);
-  int rc = cg_start(c, b->ws, K, c0, nrhs, b->method == SLR_FCG, st);
+  int rc = cg_start(c, b->ws, K, c0, nrhs, b->method == SLR_FCG, b->it + 1, st);
   if (rc) return rc;
   const int64_t rid = (int64_t)b->reqs.size();
   b->reqs.push_back({tag, c0, nrhs, x_dev, true});
@@ -1179,9 +1258,9 @@ int slr_batch_step(slr_batch *b, int32_t iters, void *hip_stream) {
   if (b->hi == 0) return SLR_OK;
   slr_ctx *c = b->c;
   hipStream_t st = S(hip_stream);
-  KArgs K = kargs(c, b->X, b->R, b->Z, b->P, b->Q, c->n, b->st, b->part, b->counter, b->maxit, b->rtol);
+  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, c->n, b->st, b->part, b->part2, b->maxit, b->rtol);
   for (int32_t i = 0; i < iters; ++i) {
-    int rc = cg_iter(c, b->ws, K, 0, b->hi, b->method == SLR_FCG, st);
+    int rc = cg_iter(c, b->ws, K, 0, b->hi, b->method == SLR_FCG, ++b->it, st);
     if (rc) return rc;
   }
   return SLR_OK;
@@ -1196,7 +1275,7 @@ int slr_batch_poll(slr_batch *b, int64_t *tags, slr_solve_info *info, int32_t ma
   if (hipMemcpyAsync(b->st_h.data(), b->st, sizeof(KState) * b->hi, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(SLR_ERR_HIP, "poll copy");
-  KArgs K = kargs(c, b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->counter, b->maxit, b->rtol);
+  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->part2, b->maxit, b->rtol);
   int32_t done = 0;
   std::vector<int64_t> fin;
   for (int64_t rid = 0; rid < (int64_t)b->reqs.size() && done < max_done; ++rid) {

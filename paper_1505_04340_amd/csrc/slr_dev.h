@@ -11,22 +11,38 @@ namespace slr {
 
 // Per-subdomain descriptor of the batched B_i solves (offsets into the
 // concatenated arrays of all subdomains).
+//
+// Each sweep of each subdomain is packed as a level-sliced ELL byte stream
+// (built on the host, 16-byte aligned): for level l with L rows and K
+// entries per row (the sweep's widest row; short rows padded with w = 0
+// pointing at their own row), the segment holds
+//     rows  uint16[L]          local row index
+//     sc    TS[L]              row scale
+//     ci    uint16[K*L]        column of entry e of row j at [e*L + j]
+//     w     TS[K*L]            pre-divided weight, same layout
+// each section padded to 8 bytes and the segment to 16.  lvb[l] is the
+// byte offset of level l's segment (lvb[nlev] = total bytes).
 struct BlockDesc {
   int32_t m0, m;                   // interior range in the internal order
-  int32_t f_lev, f_nlev, f_row, f_rp, f_ent;  // forward sweep
-  int32_t b_lev, b_nlev, b_row, b_rp, b_ent;  // backward sweep
-  int32_t e_row, e_n, e_ptr;       // E rows: e_row[e_row + i], e_ptr[e_ptr + i]
-  int32_t t_row, t_n, t_ptr;       // E^T rows (interface rows owned here)
+  int32_t f_nlev, f_K, f_lev, f_lvb;   // forward sweep: levels, width, levptr / lvb offsets
+  int32_t b_nlev, b_K, b_lev, b_lvb;   // backward sweep
+  int64_t f_data, b_data;          // byte offsets of the packed streams
+  // E rows (interior rows coupled to the interface), ELL with width e_K:
+  //   e_row[e_row + i] local row; e_q / e_val[e_ent + e*e_n + i] (padding: q 0, value 0)
+  int32_t e_row, e_n, e_K, e_ent;
+  // E^T rows (interface rows owned here), ELL with width t_K:
+  //   t_q[t_row + i] interface index; t_j / t_val[t_ent + e*t_n + i] (padding: j 0, value 0)
+  int32_t t_row, t_n, t_K, t_ent;
 };
 
-// Concatenated level-scheduled sweeps (see slr_host.h, struct Sweep).
+// Interface sweeps (C): level-scheduled CSR on the device, see slr_host.h.
 // rp entries are absolute offsets into ci / w.
 template <typename TS>
 struct SweepArrays {
-  const int32_t *lev = nullptr;    // level pointers (local to the block)
-  const int32_t *rows = nullptr;   // level-sorted local rows
-  const int32_t *rp = nullptr;     // per-block nrows+1 absolute entry offsets
-  const int32_t *ci = nullptr;     // local column indices
+  const int32_t *lev = nullptr;    // level pointers
+  const int32_t *rows = nullptr;   // level-sorted rows
+  const int32_t *rp = nullptr;     // nrows+1 absolute entry offsets
+  const int32_t *ci = nullptr;     // column indices
   const TS *w = nullptr;           // pre-scaled off-diagonal weights
   const TS *sc = nullptr;          // per-row scale
 };
@@ -34,13 +50,20 @@ struct SweepArrays {
 template <typename TS>
 struct BlockArrays {
   const BlockDesc *desc = nullptr;
-  SweepArrays<TS> fwd, bwd;
-  const int32_t *e_row = nullptr, *e_ptr = nullptr, *e_q = nullptr;
+  const int32_t *lev = nullptr;    // level pointers of all sweeps
+  const int32_t *lvb = nullptr;    // level byte offsets of all sweeps
+  const uint8_t *data = nullptr;   // packed sweep streams
+  const uint16_t *e_row = nullptr;
+  const int32_t *e_q = nullptr;
   const TS *e_val = nullptr;
-  const int32_t *t_q = nullptr, *t_ptr = nullptr, *t_j = nullptr;
+  const int32_t *t_q = nullptr;
+  const uint16_t *t_j = nullptr;
   const TS *t_val = nullptr;
   int32_t max_m = 0;
   int32_t max_lev = 0;
+  int32_t max_level_bytes = 0;     // largest single level segment
+  int32_t max_K = 0;               // widest packed row over all sweeps
+  int32_t pack_K = 0;              // > 0: every packed row has exactly this width
 };
 
 // What one launch of the batched B kernel computes for each subdomain i
@@ -57,6 +80,7 @@ struct BArgs {
   double *u = nullptr;        int64_t ldu = 0;
   int32_t nrhs = 1;
   int32_t R = 1;              // right-hand sides per workgroup
+  int32_t stage_bytes = 0;    // LDS staging buffer for the packed sweeps
 };
 
 template <typename TS, typename TC>
@@ -70,7 +94,8 @@ template <typename TS, typename TC>
 void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nlev, int32_t nrows,
                   double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st);
 
-// Rank-k block of eq. skt on w (s x nrhs, ld ldw), output to wout (ldo):
+// Rank-k block of eq. skt on w (s x nrhs, ld ldw), output to wout (ldo);
+// U column-major s x k:
 //   c = U^T w ;  c_i <- c_i * dsc_i ;  wout = rho * w + U c
 template <typename TU>
 void launch_lowrank(const TU *U, int64_t s, int32_t k, const double *dsc, double rho,

@@ -9,7 +9,7 @@ namespace slr {
 
 // Per-column Krylov state kept on the device (CG / flexible CG).
 struct KState {
-  double rz;      // r . z of the current iterate
+  double rz[2];   // r . z, double-buffered by iteration parity
   double alpha, beta;
   double rr;      // ||r||^2 of the recurrence residual
   double bb;      // ||b||^2
@@ -17,21 +17,22 @@ struct KState {
   int32_t active; // 1 while iterating
   int32_t status; // 0 converged, -8 not converged / broken down
   int32_t iters;  // products with A
-  int32_t pad;
+  int32_t start_it; // global iteration index of the column's first iteration
 };
 
 struct KArgs {
   double *X, *R, *Z, *P, *Q;  // n x ncols, leading dimension ld (internal order)
   int64_t ld;
   KState *st;
-  double *part;               // nblk x ncols x 2 partials
-  unsigned int *counter;      // last-block ticket (zero between launches)
+  double *part;               // nblk x 2 ncols partials
+  double *part2;              // nblk x ncols partials
+  unsigned int *counter;      // unused
   int32_t nblk;
   int32_t maxit;
   double rtol2;
 };
 
-enum { CG_INIT = 0, CG_SPMV, CG_UPDATE, CG_BETA, CG_BETA_INIT, CG_P };
+enum { CG_INIT = 0, CG_START, CG_SPMV, CG_UPDATE, CG_BETA, CG_P };
 
 // Round an FP64 value for storage: FP32 is round-to-nearest-even; BF16 is
 // round-to-nearest-even of the FP32-rounded value.
@@ -63,7 +64,8 @@ void launch_permute(int64_t n, const int64_t *idx, const double *src, int64_t ld
 void launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
                  int64_t ldx, double *y, int64_t ldy, int32_t nrhs, hipStream_t st);
 void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const KArgs &K,
-               int32_t c0, int32_t nc, int32_t flexible, hipStream_t st);
+               int32_t c0, int32_t nc, int32_t flexible, int32_t it, hipStream_t st);
+void launch_fold(const double *part, int32_t nb, int32_t ncol, double *out, double scale, hipStream_t st);
 void launch_relres(int64_t n, const double *B, int64_t ldb, const double *AX, int64_t ldax, const KArgs &K,
                    int32_t c0, int32_t nc, hipStream_t st);
 void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
@@ -80,8 +82,9 @@ void launch_gmres_givens(int32_t j, int32_t ldh, double *Hm, const double *h1, c
                          const double *hn2, double *cs, double *sn, double *g, double tol, int *flags,
                          double *vscale, hipStream_t st);
 void launch_gmres_solve(int32_t jj, int32_t ldh, const double *Hm, const double *g, double *y, hipStream_t st);
-void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, double *Z, double *eval, double *Y,
-                        int32_t K, int *info, hipStream_t st);
+// scratch: 6 m K doubles
+void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, double *scratch, double *eval,
+                        double *Y, int32_t K, int *info, hipStream_t st);
 template <typename TU>
 void launch_ritz(int64_t s, int32_t m, int32_t k, const double *V, int64_t ldv, const double *Y, double *U64,
                  TU *U, hipStream_t st);

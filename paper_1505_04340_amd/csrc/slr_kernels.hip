@@ -8,11 +8,14 @@
 //   Lanczos on H, tridiagonal eigensolve .......... eq. H, Sec. 5.1
 //   Krylov accelerators (CG / GMRES) .............. Sec. 6
 //
-// Reductions are deterministic: every block writes a partial, and the
-// last block to arrive (atomic ticket) sums the partials in block order.
+// Reductions are deterministic and use no cross-block atomics or fences:
+// every block writes a partial; after the kernel boundary either a small
+// fold kernel or each consumer block sums the partials in a fixed order
+// (lane-strided over blocks, then a fixed shuffle tree).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -57,81 +60,192 @@ __device__ double block_sum(double v, double *sh) {
   return r;
 }
 
-// Returns true in every thread of the last block to finish (after its
-// partials became visible); resets the ticket for the next launch.
-__device__ bool last_block(unsigned int *counter) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int t = atomicAdd(counter, 1u);
-    last = (t == gridDim.x * gridDim.y - 1);
-    if (last) *counter = 0u;
+// Deterministic parallel fold of per-block partials laid out part[b*ncol+col]:
+// each wave folds whole columns (lanes stride over b, then a shuffle tree);
+// f(col, value) runs in lane 0 of the folding wave.
+template <class F>
+__device__ __forceinline__ void fold_waves(const double *part, int nb, int ncol, F f) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int col = wid; col < ncol; col += nw) {
+    double v = 0.0;
+    for (int b = lane; b < nb; b += 64) v += part[(int64_t)b * ncol + col];
+    v = wave_sum(v);
+    if (lane == 0) f(col, v);
   }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
+}
+
+// out[col] = scale * sum_b part[b*ncol + col]; one wave per column.
+__global__ void __launch_bounds__(256) k_fold(const double *part, int nb, int ncol, double *out, double scale) {
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (col >= ncol) return;
+  double v = 0.0;
+  for (int b = lane; b < nb; b += 64) v += part[(int64_t)b * ncol + col];
+  v = wave_sum(v);
+  if (lane == 0) out[col] = v * scale;
+}
+
+void launch_fold(const double *part, int32_t nb, int32_t ncol, double *out, double scale, hipStream_t st) {
+  if (ncol <= 0) return;
+  hipLaunchKernelGGL(k_fold, dim3((unsigned)((ncol + 3) / 4)), dim3(256), 0, st, part, nb, ncol, out, scale);
 }
 
 // ---------------------------------------------------------------------------
 // K1/K2: batched subdomain solves with fused E / E^T products
 // ---------------------------------------------------------------------------
-template <typename TS, typename TC>
-__device__ __forceinline__ void sweep_lds(const SweepArrays<TS> &S, int row0, int rp0,
-                                          const int32_t *lev, int nlev, TC *xs, int R, int Rg) {
-  for (int l = 0; l < nlev; ++l) {
-    const int a = lev[l], b = lev[l + 1];
-    const int ntask = (b - a) * Rg;
-    for (int t = threadIdx.x; t < ntask; t += blockDim.x) {
-      const int q = t / Rg;
-      const int r = t - q * Rg;
-      const int slot = a + q;
-      const int row = S.rows[row0 + slot];
-      const int e0 = S.rp[rp0 + slot], e1 = S.rp[rp0 + slot + 1];
-      TC acc = cvt<TC>(S.sc[row0 + slot]) * xs[row * R + r];
-      for (int e = e0; e < e1; ++e) acc -= cvt<TC>(S.w[e]) * xs[S.ci[e] * R + r];
+__host__ __device__ constexpr int pad8(int x) { return (x + 7) & ~7; }
+__host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
+
+// One level of a packed sweep, read from LDS (see BlockDesc).  KE > 0: every
+// packed row has exactly KE entries (the problem's widest row, padding has
+// w = 0), and the row's loads form one straight-line batch; KE == 0: any
+// width K.  R1: one right-hand side.  The subtraction order is the same in
+// every variant.
+template <typename TS, typename TC, int KE, bool R1>
+__device__ __forceinline__ void level_from_lds(const uint8_t *base, int L, int K, TC *xs, int R, int Rg) {
+  const uint16_t *rows = reinterpret_cast<const uint16_t *>(base);
+  const int o_sc = pad8(2 * L);
+  const TS *sc = reinterpret_cast<const TS *>(base + o_sc);
+  const int o_ci = o_sc + pad8((int)sizeof(TS) * L);
+  const uint16_t *ci = reinterpret_cast<const uint16_t *>(base + o_ci);
+  const int kk = KE > 0 ? KE : K;
+  const TS *w = reinterpret_cast<const TS *>(base + o_ci + pad8(2 * kk * L));
+  const int ntask = R1 ? L : L * Rg;
+  for (int t = threadIdx.x; t < ntask; t += blockDim.x) {
+    int j, r;
+    if (R1) {
+      j = t;
+      r = 0;
+    } else {
+      j = t / Rg;
+      r = t - j * Rg;
+    }
+    const int row = rows[j];
+    if constexpr (KE > 0) {
+      int cv[KE];
+      TS wv[KE];
+#pragma unroll
+      for (int e = 0; e < KE; ++e) {
+        cv[e] = ci[e * L + j];
+        wv[e] = w[e * L + j];
+      }
+      TC xv[KE];
+#pragma unroll
+      for (int e = 0; e < KE; ++e) xv[e] = xs[cv[e] * R + r];
+      TC acc = cvt<TC>(sc[j]) * xs[row * R + r];
+#pragma unroll
+      for (int e = 0; e < KE; ++e) acc -= cvt<TC>(wv[e]) * xv[e];
+      xs[row * R + r] = acc;
+    } else {
+      TC acc = cvt<TC>(sc[j]) * xs[row * R + r];
+      for (int e = 0; e < K; ++e) acc -= cvt<TC>(w[e * L + j]) * xs[(int)ci[e * L + j] * R + r];
       xs[row * R + r] = acc;
     }
-    __syncthreads();
   }
 }
 
-template <typename TS, typename TC>
+// A whole sweep: stage as many consecutive level segments as fit into the
+// LDS buffer with 16-byte copies, run them from LDS, repeat.
+template <typename TS, typename TC, int KE, bool R1>
+__device__ void sweep_staged(const uint8_t *data, const int32_t *lev, const int32_t *lvb, int nlev, int K,
+                             TC *xs, int R, int Rg, uint8_t *stage, int stage_bytes) {
+  int l0 = 0;
+  while (l0 < nlev) {
+    int l1 = l0 + 1;
+    while (l1 < nlev && lvb[l1 + 1] - lvb[l0] <= stage_bytes) ++l1;
+    const int nv = (lvb[l1] - lvb[l0]) >> 4;
+    const uint4 *src = reinterpret_cast<const uint4 *>(data + lvb[l0]);
+    uint4 *dst = reinterpret_cast<uint4 *>(stage);
+    // U loads in flight per thread before their LDS stores.  Neither loads
+    // nor stores are predicated (loads clamp to the last vector, stores past
+    // the end go to the dummy slot dst[stage_bytes/16]), so the U loads
+    // issue as one batch.
+    constexpr int U = 12;
+    const int dummy = stage_bytes >> 4;
+    for (int i0 = threadIdx.x; i0 < nv; i0 += U * blockDim.x) {
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = src[min(i0 + u * (int)blockDim.x, nv - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * blockDim.x;
+        dst[i < nv ? i : dummy] = v[u];
+      }
+    }
+    __syncthreads();
+    for (int l = l0; l < l1; ++l) {
+      level_from_lds<TS, TC, KE, R1>(stage + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], K, xs, R, Rg);
+      __syncthreads();
+    }
+    l0 = l1;
+  }
+}
+
+template <typename TS, typename TC, int KE, bool R1>
 __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  TC *xs = reinterpret_cast<TC *>(smem);
   const BlockDesc d = B.desc[blockIdx.x];
   const int R = a.R;
   const int c0 = blockIdx.y * R;
   const int Rg = min(R, a.nrhs - c0);
   const int m = d.m;
-  int32_t *levf = reinterpret_cast<int32_t *>(smem + sizeof(TC) * (size_t)B.max_m * R);
+  // LDS: [stage + 16 dummy bytes][x: max_m*R + 1 TC][levptr f, b][lvb f, b]
+  uint8_t *stage = smem;
+  TC *xs = reinterpret_cast<TC *>(smem + a.stage_bytes + 16);
+  int32_t *levf = reinterpret_cast<int32_t *>(smem + a.stage_bytes + 16 + pad16((int)sizeof(TC) * (B.max_m * R + 1)));
   int32_t *levb = levf + B.max_lev + 1;
+  int32_t *lvbf = levb + B.max_lev + 1;
+  int32_t *lvbb = lvbf + B.max_lev + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i <= d.f_nlev; i += nt) levf[i] = B.fwd.lev[d.f_lev + i];
-  for (int i = tid; i <= d.b_nlev; i += nt) levb[i] = B.bwd.lev[d.b_lev + i];
-  // prologue: rhs = a_f f_i + b_y E_i y
-  for (int t = tid; t < m * Rg; t += nt) {
-    const int r = t / m, row = t - r * m;
-    double v = 0.0;
-    if (a.a_f != 0.0) v = a.a_f * a.f[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldf];
-    xs[row * R + r] = (TC)v;
+  for (int i = tid; i <= d.f_nlev; i += nt) {
+    levf[i] = B.lev[d.f_lev + i];
+    lvbf[i] = B.lvb[d.f_lvb + i];
+  }
+  for (int i = tid; i <= d.b_nlev; i += nt) {
+    levb[i] = B.lev[d.b_lev + i];
+    lvbb[i] = B.lvb[d.b_lvb + i];
+  }
+  // prologue: rhs = a_f f_i + b_y E_i y  (loads batched 4 per thread)
+  const int mt = m * Rg;
+  for (int t0 = tid; t0 < mt; t0 += 4 * nt) {
+    double v[4];
+    if (a.a_f != 0.0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = min(t0 + u * nt, mt - 1);
+        const int r = t / m, row = t - r * m;
+        v[u] = a.a_f * a.f[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldf];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * nt;
+      const int tt = min(t, mt - 1);
+      const int r = tt / m, row = tt - r * m;
+      xs[t < mt ? row * R + r : B.max_m * R] = (TC)v[u];   // past the end: dummy slot
+    }
   }
   __syncthreads();
   if (a.b_y != 0.0 && d.e_n > 0) {
-    for (int t = tid; t < d.e_n * Rg; t += nt) {
+    const int en = d.e_n;
+    for (int t = tid; t < en * Rg; t += nt) {
       const int i = t / Rg, r = t - i * Rg;
       const int row = B.e_row[d.e_row + i];
-      const int e0 = B.e_ptr[d.e_ptr + i], e1 = B.e_ptr[d.e_ptr + i + 1];
       const double *yc = a.y + (int64_t)(c0 + r) * a.ldy;
       TC acc = 0;
-      for (int e = e0; e < e1; ++e) acc += cvt<TC>(B.e_val[e]) * (TC)yc[B.e_q[e]];
+      for (int e = 0; e < d.e_K; ++e) {
+        const int64_t x = d.e_ent + (int64_t)e * en + i;
+        acc += cvt<TC>(B.e_val[x]) * (TC)yc[B.e_q[x]];
+      }
       xs[row * R + r] += (TC)a.b_y * acc;
     }
     __syncthreads();
   }
-  sweep_lds<TS, TC>(B.fwd, d.f_row, d.f_rp, levf, d.f_nlev, xs, R, Rg);
-  sweep_lds<TS, TC>(B.bwd, d.b_row, d.b_rp, levb, d.b_nlev, xs, R, Rg);
+  sweep_staged<TS, TC, KE, R1>(B.data + d.f_data, levf, lvbf, d.f_nlev, d.f_K, xs, R, Rg, stage, a.stage_bytes);
+  sweep_staged<TS, TC, KE, R1>(B.data + d.b_data, levb, lvbb, d.b_nlev, d.b_K, xs, R, Rg, stage, a.stage_bytes);
   if (a.u) {
     for (int t = tid; t < m * Rg; t += nt) {
       const int r = t / m, row = t - r * m;
@@ -139,29 +253,54 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
     }
   }
   if (a.gout) {
-    for (int t = tid; t < d.t_n * Rg; t += nt) {
+    const int tn = d.t_n;
+    for (int t = tid; t < tn * Rg; t += nt) {
       const int i = t / Rg, r = t - i * Rg;
       const int q = B.t_q[d.t_row + i];
-      const int e0 = B.t_ptr[d.t_ptr + i], e1 = B.t_ptr[d.t_ptr + i + 1];
       TC acc = 0;
-      for (int e = e0; e < e1; ++e) acc += cvt<TC>(B.t_val[e]) * xs[B.t_j[e] * R + r];
-      double gv = a.c_g != 0.0 ? a.c_g * a.g[q + (int64_t)(c0 + r) * a.ldg] : 0.0;
+      for (int e = 0; e < d.t_K; ++e) {
+        const int64_t x = d.t_ent + (int64_t)e * tn + i;
+        acc += cvt<TC>(B.t_val[x]) * xs[(int)B.t_j[x] * R + r];
+      }
+      const double gv = a.c_g != 0.0 ? a.c_g * a.g[q + (int64_t)(c0 + r) * a.ldg] : 0.0;
       a.gout[q + (int64_t)(c0 + r) * a.ldgo] = gv + a.d_t * (double)acc;
     }
   }
 }
 
-template <typename TS, typename TC>
-void launch_bsolve(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads,
-                   size_t lds_bytes, hipStream_t st) {
+template <typename TS, typename TC, int KE, bool R1>
+void launch_bsolve_t(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
+                     hipStream_t st) {
   static size_t attr_bytes = 0;
   if (lds_bytes > 65536 && lds_bytes > attr_bytes) {
-    (void)hipFuncSetAttribute((const void *)k_bsolve<TS, TC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_bsolve<TS, TC, KE, R1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_bytes);
     attr_bytes = lds_bytes;
   }
   dim3 grid(p, (a.nrhs + a.R - 1) / a.R);
-  hipLaunchKernelGGL((k_bsolve<TS, TC>), grid, dim3(threads), lds_bytes, st, B, a);
+  hipLaunchKernelGGL((k_bsolve<TS, TC, KE, R1>), grid, dim3(threads), lds_bytes, st, B, a);
+}
+
+template <typename TS, typename TC, int KE>
+void launch_bsolve_k(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
+                     hipStream_t st) {
+  if (a.R == 1)
+    launch_bsolve_t<TS, TC, KE, true>(B, p, a, threads, lds_bytes, st);
+  else
+    launch_bsolve_t<TS, TC, KE, false>(B, p, a, threads, lds_bytes, st);
+}
+
+// B.pack_K > 0: every packed row has exactly pack_K entries
+template <typename TS, typename TC>
+void launch_bsolve(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads,
+                   size_t lds_bytes, hipStream_t st) {
+  switch (B.pack_K) {
+    case 1: launch_bsolve_k<TS, TC, 1>(B, p, a, threads, lds_bytes, st); break;
+    case 2: launch_bsolve_k<TS, TC, 2>(B, p, a, threads, lds_bytes, st); break;
+    case 3: launch_bsolve_k<TS, TC, 3>(B, p, a, threads, lds_bytes, st); break;
+    case 4: launch_bsolve_k<TS, TC, 4>(B, p, a, threads, lds_bytes, st); break;
+    default: launch_bsolve_k<TS, TC, 0>(B, p, a, threads, lds_bytes, st); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -214,64 +353,61 @@ void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nle
 }
 
 // ---------------------------------------------------------------------------
-// K4: rank-k block of eq. skt.  U row-major (s x k).
-//   part[b][r][kk] = sum_{i in chunk b} U[i,kk] w[i,r]; the last block
-//   sums the partials in block order and scales by dsc (-> cbuf[r*k+kk]);
-//   then wout = rho w + U cbuf.
+// K4: rank-k block of eq. skt.  U column-major (s x k, leading dim s).
+//   part[b][r][q] = sum_{i in chunk b} U[i,q] w[i,r]   (thread per row,
+//   Q_T columns of U per pass held in registers, block-reduced in LDS);
+//   the last block sums the partials in block order and scales by dsc
+//   (-> cbuf[r*k+q]); then wout = rho w + U cbuf (thread per row).
 // ---------------------------------------------------------------------------
 constexpr int LR_THREADS = 256;
-constexpr int LR_COLS = 8;   // right-hand sides per pass
+constexpr int LR_Q = 8;      // columns of U per register pass
 
 template <typename TU>
-__global__ void __launch_bounds__(LR_THREADS) k_lr_partial(const TU *U, int64_t s, int k, int kpad,
-                                                          const double *w, int64_t ldw, int nrhs,
-                                                          double *part, double *cbuf, const double *dsc,
-                                                          unsigned int *counter) {
-  __shared__ double red[LR_THREADS / 64][64][LR_COLS];
+__global__ void __launch_bounds__(LR_THREADS) k_lr_partial(const TU *U, int64_t s, int k, const double *w,
+                                                          int64_t ldw, int nrhs, double *part) {
+  __shared__ double red[LR_THREADS / 64][LR_Q];
   const int nb = gridDim.x;
   const int64_t chunk = (s + nb - 1) / nb;
   const int64_t i0 = (int64_t)blockIdx.x * chunk;
   const int64_t i1 = min(s, i0 + chunk);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int rpw = 64 / kpad;           // rows per wave
-  const int sub = lane / kpad, kk = lane - sub * kpad;
-  const int nw = LR_THREADS / 64;
-  for (int c0 = 0; c0 < nrhs; c0 += LR_COLS) {
-    const int nc = min(LR_COLS, nrhs - c0);
-    double acc[LR_COLS];
+  for (int r = 0; r < nrhs; ++r) {
+    const double *wc = w + (int64_t)r * ldw;
+    for (int q0 = 0; q0 < k; q0 += LR_Q) {
+      double acc[LR_Q];
 #pragma unroll
-    for (int r = 0; r < LR_COLS; ++r) acc[r] = 0.0;
-    for (int64_t i = i0 + wid * rpw + sub; i < i1; i += nw * rpw) {
-      const double u = (kk < k) ? cvt<double>(U[i * k + kk]) : 0.0;
+      for (int q = 0; q < LR_Q; ++q) acc[q] = 0.0;
+      for (int64_t i = i0 + threadIdx.x; i < i1; i += LR_THREADS) {
+        const double wi = wc[i];
 #pragma unroll
-      for (int r = 0; r < LR_COLS; ++r)
-        if (r < nc) acc[r] += u * w[i + (int64_t)(c0 + r) * ldw];
-    }
-    // fold the rpw sub-rows of the wave, then the waves (fixed order)
+        for (int q = 0; q < LR_Q; ++q)
+          if (q0 + q < k) acc[q] += cvt<double>(U[i + (int64_t)(q0 + q) * s]) * wi;
+      }
 #pragma unroll
-    for (int r = 0; r < LR_COLS; ++r) {
-      double v = acc[r];
-      for (int o = kpad; o < 64; o <<= 1) v += __shfl_down(v, o, 64);
-      acc[r] = v;
-    }
-    __syncthreads();
-    if (sub == 0)
-      for (int r = 0; r < LR_COLS; ++r) red[wid][kk][r] = acc[r];
-    __syncthreads();
-    for (int t = threadIdx.x; t < k * nc; t += blockDim.x) {
-      const int r = t / k, q = t - r * k;
-      double v = 0.0;
-      for (int ww = 0; ww < nw; ++ww) v += red[ww][q][r];
-      part[((int64_t)blockIdx.x * nrhs + c0 + r) * k + q] = v;
+      for (int q = 0; q < LR_Q; ++q) acc[q] = wave_sum(acc[q]);
+      if (lane == 0)
+        for (int q = 0; q < LR_Q; ++q) red[wid][q] = acc[q];
+      __syncthreads();
+      if (threadIdx.x < LR_Q && q0 + threadIdx.x < k) {
+        double v = 0.0;
+        for (int ww = 0; ww < LR_THREADS / 64; ++ww) v += red[ww][threadIdx.x];
+        part[((int64_t)blockIdx.x * nrhs + r) * k + q0 + threadIdx.x] = v;
+      }
+      __syncthreads();
     }
   }
-  if (last_block(counter)) {
-    for (int t = threadIdx.x; t < k * nrhs; t += blockDim.x) {
-      double v = 0.0;
-      for (int b = 0; b < nb; ++b) v += part[(int64_t)b * nrhs * k + t];
-      cbuf[t] = v * dsc[t % k];
-    }
-  }
+}
+
+// cbuf[t] = dsc[t % k] * sum_b part[b*(k*nrhs) + t]
+__global__ void __launch_bounds__(256) k_lr_fold(const double *part, int nb, int kn, int k, const double *dsc,
+                                                 double *cbuf) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= kn) return;
+  double v = 0.0;
+  for (int b = lane; b < nb; b += 64) v += part[(int64_t)b * kn + t];
+  v = wave_sum(v);
+  if (lane == 0) cbuf[t] = v * dsc[t % k];
 }
 
 template <typename TU>
@@ -283,19 +419,10 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s) return;
-  for (int c0 = 0; c0 < nrhs; c0 += LR_COLS) {
-    const int nc = min(LR_COLS, nrhs - c0);
-    double acc[LR_COLS];
-#pragma unroll
-    for (int r = 0; r < LR_COLS; ++r) acc[r] = 0.0;
-    for (int q = 0; q < k; ++q) {
-      const double u = cvt<double>(U[i * k + q]);
-#pragma unroll
-      for (int r = 0; r < LR_COLS; ++r)
-        if (r < nc) acc[r] += u * cs[(c0 + r) * k + q];
-    }
-    for (int r = 0; r < nc; ++r)
-      wout[i + (int64_t)(c0 + r) * ldo] = rho * w[i + (int64_t)(c0 + r) * ldw] + acc[r];
+  for (int r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q) acc += cvt<double>(U[i + (int64_t)q * s]) * cs[r * k + q];
+    wout[i + (int64_t)r * ldo] = rho * w[i + (int64_t)r * ldw] + acc;
   }
 }
 
@@ -309,11 +436,10 @@ void launch_lowrank(const TU *U, int64_t s, int32_t k, const double *dsc, double
     launch_axpby(s, nrhs, rho, w, ldw, 0.0, wout, ldo, st);
     return;
   }
-  int kpad = 1;
-  while (kpad < k && kpad < 64) kpad <<= 1;
-  if (k > 64) kpad = 64;  // lanes loop is not used for k > 64 (rejected at setup)
-  hipLaunchKernelGGL((k_lr_partial<TU>), dim3(nblk), dim3(LR_THREADS), 0, st, U, s, k, kpad, w, ldw,
-                     nrhs, part, cbuf, dsc, counter);
+  (void)counter;
+  hipLaunchKernelGGL((k_lr_partial<TU>), dim3(nblk), dim3(LR_THREADS), 0, st, U, s, k, w, ldw, nrhs, part);
+  hipLaunchKernelGGL(k_lr_fold, dim3((unsigned)((k * nrhs + 3) / 4)), dim3(256), 0, st, part, nblk, k * nrhs, k,
+                     dsc, cbuf);
   hipLaunchKernelGGL((k_lr_update<TU>), dim3((unsigned)((s + 255) / 256)), dim3(256),
                      sizeof(double) * k * nrhs, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
 }
@@ -379,190 +505,216 @@ void launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *
 }
 
 // ---------------------------------------------------------------------------
-// K6: Krylov BLAS-1 with fused deterministic reductions.
-// KState holds per-column scalars; see slr_kern.h for the field meaning.
+// K6: Krylov BLAS-1 with deterministic reductions, CG / flexible CG.
+// Every reduction writes per-block partials part[b*width + col]; the next
+// kernel's blocks each fold them (identically) in LDS.  No kernel reads a
+// state field that a block of the same kernel writes, except `active`,
+// whose update (active && !stop) gives the same answer before and after.
 // ---------------------------------------------------------------------------
 constexpr int RED_THREADS = 256;
+constexpr int MAX_FOLD = 256;   // folded values per launch (2 per column)
 
-// Shared tail: partial[b][col] written by each block; the last block sums.
-__device__ double fold_partials(const double *part, int nb, int ncol, int col) {
-  double v = 0.0;
-  for (int b = 0; b < nb; ++b) v += part[(int64_t)b * ncol + col];
-  return v;
+__device__ __forceinline__ void fold_to_lds(const double *part, int nb, int width, double *fin) {
+  fold_waves(part, nb, width, [&](int col, double v) { fin[col] = v; });
+  __syncthreads();
 }
 
-// q = A p for active columns, and p.q ; then alpha = rz / pq.
+template <class F>
+__device__ __forceinline__ void chunk_rows(int64_t n, F f) {
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) f(i);
+}
+
+// (1) q = A p and partial p.q  -> part[b*nc + cc]
 __global__ void __launch_bounds__(RED_THREADS) k_cg_spmv(int64_t n, const int64_t *rp, const int32_t *ci,
                                                          const double *v, KArgs K, int c0, int nc) {
   __shared__ double sh[RED_THREADS / 64];
-  const int nb = gridDim.x;
-  const int64_t chunk = (n + nb - 1) / nb;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
   for (int cc = 0; cc < nc; ++cc) {
     const int c = c0 + cc;
     const double *pc = K.P + (int64_t)c * K.ld;
     double *qc = K.Q + (int64_t)c * K.ld;
     double acc = 0.0;
     if (K.st[c].active) {
-      for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      chunk_rows(n, [&](int64_t i) {
         double sum = 0.0;
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) sum += v[e] * pc[ci[e]];
         qc[i] = sum;
         acc += sum * pc[i];
-      }
+      });
     }
-    double t = block_sum(acc, sh);
+    const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + cc] = t;
-  }
-  if (last_block(K.counter)) {
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      KState &s = K.st[c0 + cc];
-      const double pq = fold_partials(K.part, nb, nc, cc);
-      if (s.active) {
-        if (!(pq > 0.0) || !isfinite(pq)) {
-          // indefinite or broken down: stop this column
-          s.active = 0;
-          s.status = -8;
-          s.alpha = 0.0;
-        } else {
-          s.alpha = s.rz / pq;
-        }
-      } else {
-        s.alpha = 0.0;
-      }
-    }
   }
 }
 
-// x += alpha p ; r -= alpha q ; rr = r.r ; convergence and iteration count
-__global__ void __launch_bounds__(RED_THREADS) k_cg_update(int64_t n, KArgs K, int c0, int nc) {
+// alpha from the folded p.q; a non-positive p.q stops the column
+__device__ __forceinline__ double cg_alpha(const KState &s, double pq, int it, bool &brk) {
+  brk = !(pq > 0.0) || !isfinite(pq);
+  return (s.active && !brk) ? s.rz[(it - 1) & 1] / pq : 0.0;
+}
+
+// (2) fold p.q -> alpha ; x += alpha p ; r -= alpha q ; partial r.r -> part2
+__global__ void __launch_bounds__(RED_THREADS) k_cg_update(int64_t n, KArgs K, int c0, int nc, int it) {
   __shared__ double sh[RED_THREADS / 64];
-  const int nb = gridDim.x;
-  const int64_t chunk = (n + nb - 1) / nb;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  __shared__ double fin[MAX_FOLD];
+  fold_to_lds(K.part, K.nblk, nc, fin);
   for (int cc = 0; cc < nc; ++cc) {
     const int c = c0 + cc;
     const KState &s = K.st[c];
+    bool brk;
+    const double al = cg_alpha(s, fin[cc], it, brk);
     double acc = 0.0;
-    if (s.active) {
-      const double al = s.alpha;
+    if (s.active && !brk) {
       double *xc = K.X + (int64_t)c * K.ld;
       double *rc = K.R + (int64_t)c * K.ld;
       const double *pc = K.P + (int64_t)c * K.ld;
       const double *qc = K.Q + (int64_t)c * K.ld;
-      for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      chunk_rows(n, [&](int64_t i) {
         xc[i] += al * pc[i];
         const double r = rc[i] - al * qc[i];
         rc[i] = r;
         acc += r * r;
-      }
+      });
     }
-    double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + cc] = t;
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) K.part2[(int64_t)blockIdx.x * nc + cc] = t;
   }
-  if (last_block(K.counter)) {
+  __syncthreads();
+  if (blockIdx.x == 0) {
     for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
       KState &s = K.st[c0 + cc];
-      if (!s.active) continue;
-      const double rr = fold_partials(K.part, nb, nc, cc);
-      s.rr = rr;
-      s.iters += 1;
-      if (rr <= K.rtol2 * s.bb) {
-        s.active = 0;
-        s.status = 0;
-      } else if (s.iters >= K.maxit || !isfinite(rr)) {
-        s.active = 0;
-        s.status = -8;
+      bool brk;
+      const double al = cg_alpha(s, fin[cc], it, brk);
+      if (s.active) {
+        s.alpha = al;
+        if (brk) {
+          s.active = 0;
+          s.status = -8;
+          s.iters = it - s.start_it + 1;
+        }
       }
     }
   }
 }
 
-// rz_new = r.z, zq = z.q ; beta (CG: rz_new/rz, flexible CG: -alpha zq/rz)
-__global__ void __launch_bounds__(RED_THREADS) k_cg_beta(int64_t n, KArgs K, int c0, int nc, int flexible,
-                                                         int init) {
+// convergence of column c after the update of iteration `it`
+__device__ __forceinline__ bool cg_stop(const KState &s, double rr, int it, int maxit, double rtol2, bool &ok) {
+  ok = rr <= rtol2 * s.bb;
+  return ok || (it - s.start_it + 1) >= maxit || !isfinite(rr);
+}
+
+// (3) fold r.r -> convergence ; partials r.z and z.q -> part[b*2nc + 2cc (+1)]
+__global__ void __launch_bounds__(RED_THREADS) k_cg_beta(int64_t n, KArgs K, int c0, int nc, int flexible, int it) {
   __shared__ double sh[RED_THREADS / 64];
-  const int nb = gridDim.x;
-  const int64_t chunk = (n + nb - 1) / nb;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  __shared__ double fin[MAX_FOLD];
+  fold_to_lds(K.part2, K.nblk, nc, fin);
   for (int cc = 0; cc < nc; ++cc) {
     const int c = c0 + cc;
     const KState &s = K.st[c];
+    bool ok;
+    const bool go = s.active && !cg_stop(s, fin[cc], it, K.maxit, K.rtol2, ok);
     double a1 = 0.0, a2 = 0.0;
-    if (s.active) {
+    if (go) {
       const double *rc = K.R + (int64_t)c * K.ld;
       const double *zc = K.Z + (int64_t)c * K.ld;
       const double *qc = K.Q + (int64_t)c * K.ld;
-      for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      chunk_rows(n, [&](int64_t i) {
         a1 += rc[i] * zc[i];
-        if (flexible && !init) a2 += zc[i] * qc[i];
-      }
+        if (flexible) a2 += zc[i] * qc[i];
+      });
     }
-    double t1 = block_sum(a1, sh);
-    double t2 = block_sum(a2, sh);
+    const double t1 = block_sum(a1, sh);
+    const double t2 = block_sum(a2, sh);
     if (threadIdx.x == 0) {
-      K.part[((int64_t)blockIdx.x * nc + cc) * 2] = t1;
-      K.part[((int64_t)blockIdx.x * nc + cc) * 2 + 1] = t2;
+      K.part[(int64_t)blockIdx.x * 2 * nc + 2 * cc] = t1;
+      K.part[(int64_t)blockIdx.x * 2 * nc + 2 * cc + 1] = t2;
     }
   }
-  if (last_block(K.counter)) {
+  __syncthreads();
+  if (blockIdx.x == 0) {
     for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
       KState &s = K.st[c0 + cc];
-      double rz = 0.0, zq = 0.0;
-      for (int b = 0; b < nb; ++b) {
-        rz += K.part[((int64_t)b * nc + cc) * 2];
-        zq += K.part[((int64_t)b * nc + cc) * 2 + 1];
+      if (!s.active) continue;
+      bool ok;
+      const double rr = fin[cc];
+      const bool stop = cg_stop(s, rr, it, K.maxit, K.rtol2, ok);
+      s.rr = rr;
+      s.iters = it - s.start_it + 1;
+      if (stop) {
+        s.active = 0;
+        s.status = ok ? 0 : -8;
       }
-      if (!s.active) {
-        s.beta = 0.0;
-        continue;
-      }
-      if (init) {
-        s.beta = 0.0;
-      } else {
-        s.beta = flexible ? (-s.alpha * zq) / s.rz : rz / s.rz;
-      }
-      s.rz = rz;
     }
   }
 }
 
-// p = z + beta p (active columns)
-__global__ void k_cg_p(int64_t n, KArgs K, int c0) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = c0 + blockIdx.y;
-  const KState &s = K.st[c];
-  if (i >= n || !s.active) return;
-  double *pc = K.P + (int64_t)c * K.ld;
-  pc[i] = K.Z[i + (int64_t)c * K.ld] + s.beta * pc[i];
+// (4) fold r.z, z.q -> beta ; p = z + beta p ; rz stored for iteration it+1
+__global__ void __launch_bounds__(RED_THREADS) k_cg_p(int64_t n, KArgs K, int c0, int nc, int flexible, int it) {
+  __shared__ double fin[MAX_FOLD];
+  fold_to_lds(K.part, K.nblk, 2 * nc, fin);
+  for (int cc = 0; cc < nc; ++cc) {
+    const int c = c0 + cc;
+    const KState &s = K.st[c];
+    if (!s.active) continue;
+    const double rzo = s.rz[(it - 1) & 1];
+    const double beta = flexible ? (-s.alpha * fin[2 * cc + 1]) / rzo : fin[2 * cc] / rzo;
+    double *pc = K.P + (int64_t)c * K.ld;
+    const double *zc = K.Z + (int64_t)c * K.ld;
+    chunk_rows(n, [&](int64_t i) { pc[i] = zc[i] + beta * pc[i]; });
+  }
+  if (blockIdx.x == 0) {
+    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
+      KState &s = K.st[c0 + cc];
+      if (!s.active) continue;
+      const double rzo = s.rz[(it - 1) & 1];
+      s.beta = flexible ? (-s.alpha * fin[2 * cc + 1]) / rzo : fin[2 * cc] / rzo;
+      s.rz[it & 1] = fin[2 * cc];
+    }
+  }
 }
 
-// column-wise squared norms into st[c].bb and reset the state (init)
+// start: x = 0, partial b.b -> part2 (r holds b)
 __global__ void __launch_bounds__(RED_THREADS) k_cg_init(int64_t n, KArgs K, int c0, int nc) {
   __shared__ double sh[RED_THREADS / 64];
-  const int nb = gridDim.x;
-  const int64_t chunk = (n + nb - 1) / nb;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
   for (int cc = 0; cc < nc; ++cc) {
     const int c = c0 + cc;
     const double *rc = K.R + (int64_t)c * K.ld;
     double *xc = K.X + (int64_t)c * K.ld;
     double acc = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    chunk_rows(n, [&](int64_t i) {
       acc += rc[i] * rc[i];
       xc[i] = 0.0;
-    }
-    double t = block_sum(acc, sh);
+    });
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) K.part2[(int64_t)blockIdx.x * nc + cc] = t;
+  }
+}
+
+// after z0 = M^{-1} r0: fold b.b (part2); partial r.z -> part; block 0
+// initialises the state (start iteration it0 = the next iteration index)
+__global__ void __launch_bounds__(RED_THREADS) k_cg_start(int64_t n, KArgs K, int c0, int nc, int it0) {
+  __shared__ double sh[RED_THREADS / 64];
+  __shared__ double fin[MAX_FOLD];
+  fold_to_lds(K.part2, K.nblk, nc, fin);
+  for (int cc = 0; cc < nc; ++cc) {
+    const int c = c0 + cc;
+    const double *rc = K.R + (int64_t)c * K.ld;
+    const double *zc = K.Z + (int64_t)c * K.ld;
+    double acc = 0.0;
+    chunk_rows(n, [&](int64_t i) { acc += rc[i] * zc[i]; });
+    const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + cc] = t;
   }
-  if (last_block(K.counter)) {
+  if (blockIdx.x == 0) {
     for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
       KState &s = K.st[c0 + cc];
-      const double bb = fold_partials(K.part, nb, nc, cc);
+      const double bb = fin[cc];
       s.bb = bb;
       s.rr = bb;
       s.iters = 0;
-      s.alpha = s.beta = s.rz = 0.0;
+      s.start_it = it0;
+      s.alpha = s.beta = 0.0;
       s.relres = 0.0;
       if (bb > 0.0 && isfinite(bb)) {
         s.active = 1;
@@ -575,55 +727,60 @@ __global__ void __launch_bounds__(RED_THREADS) k_cg_init(int64_t n, KArgs K, int
   }
 }
 
-// relres = ||b - A x|| / ||b|| (Q holds A x on entry, R0 = b)
+// rz of the start, stored where iteration it0 reads it
+__global__ void __launch_bounds__(RED_THREADS) k_cg_start2(KArgs K, int c0, int nc, int it0) {
+  __shared__ double fin[MAX_FOLD];
+  fold_to_lds(K.part, K.nblk, nc, fin);
+  for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) K.st[c0 + cc].rz[(it0 - 1) & 1] = fin[cc];
+}
+
+// true residual: partial ||b - A x||^2 (AX holds A x) -> part2; then fold
 __global__ void __launch_bounds__(RED_THREADS) k_relres(int64_t n, const double *B, int64_t ldb, const double *AX,
-                                                        int64_t ldax, KArgs K, int c0, int nc) {
+                                                        int64_t ldax, KArgs K, int nc) {
   __shared__ double sh[RED_THREADS / 64];
-  const int nb = gridDim.x;
-  const int64_t chunk = (n + nb - 1) / nb;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
   for (int cc = 0; cc < nc; ++cc) {
-    const int c = c0 + cc;
     double acc = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    chunk_rows(n, [&](int64_t i) {
       const double d = B[i + (int64_t)cc * ldb] - AX[i + (int64_t)cc * ldax];
       acc += d * d;
-    }
-    (void)c;
-    double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + cc] = t;
+    });
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) K.part2[(int64_t)blockIdx.x * nc + cc] = t;
   }
-  if (last_block(K.counter)) {
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      KState &s = K.st[c0 + cc];
-      const double rr = fold_partials(K.part, nb, nc, cc);
-      s.relres = s.bb > 0.0 ? sqrt(rr / s.bb) : 0.0;
-    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_relres2(KArgs K, int c0, int nc) {
+  __shared__ double fin[MAX_FOLD];
+  fold_to_lds(K.part2, K.nblk, nc, fin);
+  for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
+    KState &s = K.st[c0 + cc];
+    s.relres = s.bb > 0.0 ? sqrt(fin[cc] / s.bb) : 0.0;
   }
 }
 
 void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const KArgs &K,
-               int32_t c0, int32_t nc, int32_t flexible, hipStream_t st) {
+               int32_t c0, int32_t nc, int32_t flexible, int32_t it, hipStream_t st) {
   if (nc == 0) return;
   const int nb = K.nblk;
   switch (op) {
     case CG_INIT:
       hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc);
       break;
+    case CG_START:
+      hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, it);
+      hipLaunchKernelGGL(k_cg_start2, dim3(1), dim3(RED_THREADS), 0, st, K, c0, nc, it);
+      break;
     case CG_SPMV:
       hipLaunchKernelGGL(k_cg_spmv, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc);
       break;
     case CG_UPDATE:
-      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc);
+      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, it);
       break;
     case CG_BETA:
-      hipLaunchKernelGGL(k_cg_beta, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, 0);
-      break;
-    case CG_BETA_INIT:
-      hipLaunchKernelGGL(k_cg_beta, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, 1);
+      hipLaunchKernelGGL(k_cg_beta, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, it);
       break;
     case CG_P:
-      hipLaunchKernelGGL(k_cg_p, dim3((unsigned)((n + 255) / 256), nc), dim3(256), 0, st, n, K, c0);
+      hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, it);
       break;
     default:
       break;
@@ -633,36 +790,36 @@ void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const do
 void launch_relres(int64_t n, const double *B, int64_t ldb, const double *AX, int64_t ldax, const KArgs &K,
                    int32_t c0, int32_t nc, hipStream_t st) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_relres, dim3(K.nblk), dim3(RED_THREADS), 0, st, n, B, ldb, AX, ldax, K, c0, nc);
+  hipLaunchKernelGGL(k_relres, dim3(K.nblk), dim3(RED_THREADS), 0, st, n, B, ldb, AX, ldax, K, nc);
+  hipLaunchKernelGGL(k_relres2, dim3(1), dim3(RED_THREADS), 0, st, K, c0, nc);
 }
 
 // ---------------------------------------------------------------------------
 // Single-vector reductions / Gram-Schmidt (Lanczos K7 and FGMRES K10), FP64
 // ---------------------------------------------------------------------------
 // out[j] = sum_i V[i + j*ldv] * w[i]  for j < J   (V^T w)
-// Each block takes a contiguous row chunk; wave j-lanes reduce; the last
-// block folds the partials (part: nblk x J) in block order.
+// Grid (RB, J): block (rb, j) sums column j over row chunk rb into
+// part[rb*J + j] (four independent accumulators per thread); k_fold then
+// sums the RB partials of every column.
 __global__ void __launch_bounds__(256) k_multidot(int64_t s, int J, const double *V, int64_t ldv,
-                                                  const double *w, double *part, double *out, double scale_out,
-                                                  unsigned int *counter) {
-  const int nb = gridDim.x;
+                                                  const double *w, double *part) {
+  __shared__ double sh[4];
+  const int rb = blockIdx.x, nb = gridDim.x, j = blockIdx.y;
   const int64_t chunk = (s + nb - 1) / nb;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(s, i0 + chunk);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wid; j < J; j += nw) {
-    const double *vj = V + (int64_t)j * ldv;
-    double acc = 0.0;
-    for (int64_t i = i0 + lane; i < i1; i += 64) acc += vj[i] * w[i];
-    acc = wave_sum(acc);
-    if (lane == 0) part[(int64_t)blockIdx.x * J + j] = acc;
+  const int64_t i0 = (int64_t)rb * chunk, i1 = min(s, i0 + chunk);
+  const double *vj = V + (int64_t)j * ldv;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int64_t step = blockDim.x;
+  int64_t i = i0 + threadIdx.x;
+  for (; i + 3 * step < i1; i += 4 * step) {
+    a0 += vj[i] * w[i];
+    a1 += vj[i + step] * w[i + step];
+    a2 += vj[i + 2 * step] * w[i + 2 * step];
+    a3 += vj[i + 3 * step] * w[i + 3 * step];
   }
-  if (last_block(counter)) {
-    for (int j = threadIdx.x; j < J; j += blockDim.x) {
-      double v = 0.0;
-      for (int b = 0; b < nb; ++b) v += part[(int64_t)b * J + j];
-      out[j] = v * scale_out;
-    }
-  }
+  for (; i < i1; i += step) a0 += vj[i] * w[i];
+  const double t = block_sum((a0 + a1) + (a2 + a3), sh);
+  if (threadIdx.x == 0) part[(int64_t)rb * J + j] = t;
 }
 
 // w[i] -= sum_j V[i + j*ldv] h[j]   (h on the device, J <= 1024)
@@ -680,7 +837,11 @@ __global__ void __launch_bounds__(256) k_gemv_sub(int64_t s, int J, const double
 
 void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
                      int32_t nblk, double *out, unsigned int *counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(256), 0, st, s, J, V, ldv, w, part, out, 1.0, counter);
+  // row chunks: about 1024 blocks in total, at least 2048 rows per chunk
+  int64_t rb = std::max<int64_t>(1, std::min<int64_t>({(int64_t)nblk, (1024 + J - 1) / J, (s + 1023) / 1024}));
+  (void)counter;
+  hipLaunchKernelGGL(k_multidot, dim3((unsigned)rb, J), dim3(256), 0, st, s, J, V, ldv, w, part);
+  launch_fold(part, (int32_t)rb, J, out, 1.0, st);
 }
 
 void launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const double *h, double *w,
@@ -798,124 +959,224 @@ void launch_div_scalar(int64_t n, const double *w, double *v, const double *scal
 }
 
 // ---------------------------------------------------------------------------
-// K8: eigen-decomposition of the Lanczos tridiagonal T_m (m <= 1024) in one
-// workgroup: implicit QL iterations with Wilkinson shifts (the tql2
-// procedure of Bowdler, Martin, Reinsch & Wilkinson) computed by thread 0,
-// the plane rotations accumulated into Z by all threads (each thread owns
-// whole rows of Z).  Outputs: eval (descending, all m), Y (m x K, column j
-// = eigenvector of the j-th largest), info (0 ok, 1 no convergence).
-// Z: m x m scratch (row-major).
+// K8: eigenpairs of the Lanczos tridiagonal T_m (m <= 1024), one workgroup.
+//  (1) all eigenvalues by bisection on Sturm counts (one thread each);
+//  (2) eigenvectors of the K largest by inverse iteration (one thread each,
+//      tridiagonal LU with partial pivoting of T - lambda I, tiny pivots
+//      replaced by eps ||T||), factors in interleaved global scratch;
+//  (3) two rounds of: orthonormalise the K vectors (classical Gram-Schmidt
+//      twice, in order of decreasing eigenvalue), then one more inverse-
+//      iteration step; a final orthonormalisation.  Near-multiple
+//      eigenvalues give nearly parallel first iterates; the rounds rotate
+//      them back into the invariant subspace.
+// Outputs: eval (descending, all m), Y (m x K column-major), info (0).
+// scratch: 6 m K doubles.
 // ---------------------------------------------------------------------------
 constexpr int EIG_MAXM = 1024;
+constexpr int EIG_THREADS = 1024;
 
-__global__ void __launch_bounds__(256) k_tridiag_eig(int m, const double *alpha, const double *beta, double *Z,
-                                                     double *eval, double *Y, int K, int *info) {
-  __shared__ double d[EIG_MAXM], e[EIG_MAXM], cs[EIG_MAXM], sn[EIG_MAXM];
-  __shared__ int ctl[4];  // [0]=lo, [1]=hi (rotations i = hi..lo), [2]=done, [3]=fail
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < m; i += nt) {
-    d[i] = alpha[i];
-    e[i] = (i + 1 < m) ? beta[i] : 0.0;
+// number of eigenvalues of T below x (Sturm count of the LDL^T of T - x I)
+__device__ __forceinline__ int sturm_count(const double *a, const double *b2, int m, double x, double pivmin) {
+  int cnt = 0;
+  double d = a[0] - x;
+  if (fabs(d) < pivmin) d = -pivmin;
+  cnt += d < 0.0;
+  for (int i = 1; i < m; ++i) {
+    d = a[i] - x - b2[i - 1] / d;
+    if (fabs(d) < pivmin) d = -pivmin;
+    cnt += d < 0.0;
   }
-  for (int64_t t = tid; t < (int64_t)m * m; t += nt) Z[t] = ((t / m) == (t % m)) ? 1.0 : 0.0;
-  if (tid == 0) ctl[3] = 0;
-  __syncthreads();
-  int failed = 0;
-  for (int l = 0; l < m; ++l) {
-    int iter = 0;
-    while (true) {
-      if (tid == 0) {
-        int mm = l;
-        for (; mm < m - 1; ++mm) {
-          const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-          if (fabs(e[mm]) <= 2.220446049250313e-16 * dd) break;
-        }
-        ctl[2] = (mm == l) ? 1 : 0;
-        ctl[0] = l;
-        ctl[1] = l - 1;  // empty range by default
-        if (mm != l) {
-          if (++iter > 60) {
-            ctl[3] = 1;
-            ctl[2] = 1;
-          } else {
-            // Wilkinson shift from the leading 2x2 block
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = hypot(g, 1.0);
-            g = d[mm] - d[l] + e[l] / (g + (g >= 0.0 ? fabs(r) : -fabs(r)));
-            double s = 1.0, c = 1.0, p = 0.0;
-            int i = mm - 1;
-            bool early = false;
-            for (; i >= l; --i) {
-              double f = s * e[i];
-              double b = c * e[i];
-              r = hypot(f, g);
-              e[i + 1] = r;
-              if (r == 0.0) {
-                d[i + 1] -= p;
-                e[mm] = 0.0;
-                early = true;
-                break;
-              }
-              s = f / r;
-              c = g / r;
-              g = d[i + 1] - p;
-              r = (d[i] - g) * s + 2.0 * c * b;
-              p = s * r;
-              d[i + 1] = g + p;
-              g = c * r - b;
-              cs[i] = c;
-              sn[i] = s;
-            }
-            // rotations recorded for indices (early ? i+1 : l) .. mm-1
-            ctl[0] = early ? i + 1 : l;
-            ctl[1] = mm - 1;
-            if (!early) {
-              d[l] -= p;
-              e[l] = g;
-              e[mm] = 0.0;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      const int lo = ctl[0], hi = ctl[1];
-      for (int row = tid; row < m; row += nt) {
-        double *zr = Z + (int64_t)row * m;
-        for (int i = hi; i >= lo; --i) {
-          const double f = zr[i + 1];
-          zr[i + 1] = sn[i] * zr[i] + cs[i] * f;
-          zr[i] = cs[i] * zr[i] - sn[i] * f;
-        }
-      }
-      // read the control words before the barrier: thread 0 rewrites them
-      // only after it
-      const int done = ctl[2];
-      failed = ctl[3];
-      __syncthreads();
-      if (done) break;
-    }
-    if (failed) break;
-  }
-  __syncthreads();
-  // rank by decreasing eigenvalue (ties by index) and gather
-  for (int i = tid; i < m; i += nt) {
-    int rank = 0;
-    for (int j = 0; j < m; ++j) rank += (d[j] > d[i]) || (d[j] == d[i] && j < i);
-    eval[rank] = d[i];
-    if (rank < K)
-      for (int r = 0; r < m; ++r) Y[r + (int64_t)rank * m] = Z[(int64_t)r * m + i];
-  }
-  if (tid == 0) *info = failed;
+  return cnt;
 }
 
-void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, double *Z, double *eval, double *Y,
-                        int32_t K, int *info, hipStream_t st) {
-  hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(256), 0, st, m, alpha, beta, Z, eval, Y, K, info);
+// one inverse-iteration solve (T - lam I) x = x for vector t of K; factors
+// dl, dd, du, du2 and pivots in scratch with stride K (index i*K + t)
+__device__ void inv_iter(const double *a, const double *b, int m, double lam, double tiny, double *x, double *dl,
+                         double *dd, double *du, double *du2, double *piv, int K, int t) {
+  // factor
+  for (int i = 0; i < m; ++i) {
+    dd[i * K + t] = a[i] - lam;
+    if (i + 1 < m) {
+      dl[i * K + t] = b[i];
+      du[i * K + t] = b[i];
+    }
+  }
+  for (int i = 0; i + 1 < m; ++i) {
+    const double di = dd[i * K + t], li = dl[i * K + t];
+    if (fabs(di) >= fabs(li)) {
+      const double f = di != 0.0 ? li / di : 0.0;
+      dl[i * K + t] = f;
+      dd[(i + 1) * K + t] -= f * du[i * K + t];
+      if (i + 2 < m) du2[i * K + t] = 0.0;
+      piv[i * K + t] = 0.0;
+    } else {
+      const double f = di / li;
+      dd[i * K + t] = li;
+      dl[i * K + t] = f;
+      const double tmp = du[i * K + t];
+      du[i * K + t] = dd[(i + 1) * K + t];
+      dd[(i + 1) * K + t] = tmp - f * dd[(i + 1) * K + t];
+      if (i + 2 < m) {
+        du2[i * K + t] = du[(i + 1) * K + t];
+        du[(i + 1) * K + t] = -f * du[(i + 1) * K + t];
+      }
+      piv[i * K + t] = 1.0;
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    if (fabs(dd[i * K + t]) < tiny) dd[i * K + t] = dd[i * K + t] < 0.0 ? -tiny : tiny;
+  // solve L U x = x
+  for (int i = 0; i + 1 < m; ++i) {
+    const double f = dl[i * K + t];
+    if (piv[i * K + t] == 0.0) {
+      x[(i + 1) * K + t] -= f * x[i * K + t];
+    } else {
+      const double xi = x[i * K + t];
+      x[i * K + t] = x[(i + 1) * K + t];
+      x[(i + 1) * K + t] = xi - f * x[(i + 1) * K + t];
+    }
+  }
+  x[(m - 1) * K + t] /= dd[(m - 1) * K + t];
+  if (m > 1) x[(m - 2) * K + t] = (x[(m - 2) * K + t] - du[(m - 2) * K + t] * x[(m - 1) * K + t]) / dd[(m - 2) * K + t];
+  for (int i = m - 3; i >= 0; --i)
+    x[i * K + t] = (x[i * K + t] - du[i * K + t] * x[(i + 1) * K + t] - du2[i * K + t] * x[(i + 2) * K + t]) /
+                   dd[i * K + t];
+}
+
+// scale column t of X (stride K) to unit norm
+__device__ void unit_col(double *x, int m, int K, int t) {
+  double nr = 0.0;
+  for (int i = 0; i < m; ++i) nr += x[i * K + t] * x[i * K + t];
+  const double sc = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+  for (int i = 0; i < m; ++i) x[i * K + t] *= sc;
+}
+
+// classical Gram-Schmidt twice over the K columns of X (stride K), in
+// column order; the whole workgroup cooperates (one wave per dot product)
+__device__ void cgs2_cols(double *x, int m, int K, double *h) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = 0; j < K; ++j) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = wid; i < j; i += nw) {
+        double v = 0.0;
+        for (int r = lane; r < m; r += 64) v += x[r * K + i] * x[r * K + j];
+        v = wave_sum(v);
+        if (lane == 0) h[i] = v;
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        double v = x[r * K + j];
+        for (int i = 0; i < j; ++i) v -= h[i] * x[r * K + i];
+        x[r * K + j] = v;
+      }
+      __syncthreads();
+    }
+    // normalise column j
+    double v = 0.0;
+    if (wid == 0) {
+      for (int r = lane; r < m; r += 64) v += x[r * K + j] * x[r * K + j];
+      v = wave_sum(v);
+      if (lane == 0) h[EIG_MAXM] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    }
+    __syncthreads();
+    const double sc = h[EIG_MAXM];
+    for (int r = threadIdx.x; r < m; r += blockDim.x) x[r * K + j] *= sc;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(EIG_THREADS) k_tridiag_eig(int m, const double *alpha, const double *beta,
+                                                             double *scratch, double *eval, double *Y, int K,
+                                                             int *info) {
+  __shared__ double a[EIG_MAXM], b[EIG_MAXM], b2[EIG_MAXM], lam[EIG_MAXM];
+  __shared__ double h[EIG_MAXM + 1];
+  __shared__ double bounds[2];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < m; i += nt) {
+    a[i] = alpha[i];
+    b[i] = (i + 1 < m) ? beta[i] : 0.0;
+    b2[i] = b[i] * b[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
+      lo = fmin(lo, a[i] - r);
+      hi = fmax(hi, a[i] + r);
+    }
+    bounds[0] = lo;
+    bounds[1] = hi;
+  }
+  __syncthreads();
+  const double glo = bounds[0], ghi = bounds[1];
+  const double tnorm = fmax(fabs(glo), fabs(ghi));
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 1e-290 + eps * eps * tnorm * tnorm;
+  // (1) bisection: thread t finds the t-th largest (ascending index m-1-t)
+  for (int t = tid; t < m; t += nt) {
+    const int j = m - 1 - t;
+    double lo = glo - eps * tnorm - 1e-300, hi = ghi + eps * tnorm + 1e-300;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (hi - lo <= 2.0 * eps * (fabs(lo) + fabs(hi))) break;
+      if (sturm_count(a, b2, m, mid, pivmin) >= j + 1)
+        hi = mid;
+      else
+        lo = mid;
+    }
+    const double v = 0.5 * (lo + hi);
+    lam[t] = v;
+    eval[t] = v;
+  }
+  __syncthreads();
+  if (K > 0) {
+    double *X = scratch;
+    double *dl = X + (size_t)m * K, *dd = dl + (size_t)m * K, *du = dd + (size_t)m * K;
+    double *du2 = du + (size_t)m * K, *piv = du2 + (size_t)m * K;
+    const double tiny = eps * tnorm + 1e-300;
+    // (2) inverse iteration from a fixed pseudo-random start
+    if (tid < K) {
+      for (int i = 0; i < m; ++i) {
+        uint32_t z = (uint32_t)(i * 2654435761u) ^ (uint32_t)((tid + 1) * 40503u);
+        z ^= z >> 15;
+        z *= 2246822519u;
+        z ^= z >> 13;
+        X[i * K + tid] = 0.5 + (double)(z & 0xFFFF) / 65536.0;
+      }
+      for (int rep = 0; rep < 3; ++rep) {
+        inv_iter(a, b, m, lam[tid], tiny, X, dl, dd, du, du2, piv, K, tid);
+        unit_col(X, m, K, tid);
+      }
+    }
+    __syncthreads();
+    // (3) orthonormalise / refine
+    for (int round = 0; round < 2; ++round) {
+      cgs2_cols(X, m, K, h);
+      if (tid < K) {
+        inv_iter(a, b, m, lam[tid], tiny, X, dl, dd, du, du2, piv, K, tid);
+        unit_col(X, m, K, tid);
+      }
+      __syncthreads();
+    }
+    cgs2_cols(X, m, K, h);
+    for (int t = tid; t < m * K; t += nt) {
+      const int i = t / K, q = t - i * K;
+      Y[i + (int64_t)q * m] = X[i * K + q];
+    }
+  }
+  if (tid == 0) *info = 0;
+}
+
+void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, double *scratch, double *eval,
+                        double *Y, int32_t K, int *info, hipStream_t st) {
+  hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(EIG_THREADS), 0, st, m, alpha, beta, scratch, eval, Y, K, info);
 }
 
 // Ritz vectors: U64[i, q] = sum_j V[i, j] Y[j, q]  (V: s x m col-major,
-// Y: m x K col-major, U64 row-major s x k, k <= K).  Also writes the
-// storage copy U (row-major, rounded to TU).
+// Y: m x K col-major, U64 column-major s x k, k <= K).  Also writes the
+// storage copy U (column-major, rounded to TU).
 template <typename TU>
 __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const double *V, int64_t ldv,
                                               const double *Y, double *U64, TU *U) {
@@ -939,8 +1200,8 @@ __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const dou
         for (int q = 0; q < 16; ++q) acc[q] += vj * ys[j * 16 + q];
       }
       for (int q = 0; q < nq; ++q) {
-        U64[i * k + q0 + q] = acc[q];
-        U[i * k + q0 + q] = round_store<TU>(acc[q]);
+        U64[i + (int64_t)(q0 + q) * s] = acc[q];
+        U[i + (int64_t)(q0 + q) * s] = round_store<TU>(acc[q]);
       }
     }
   }
