@@ -80,6 +80,7 @@ std::vector<TS> conv(const std::vector<double> &v) {
 struct ApplyWS {
   int32_t cap = 0;
   double *W = nullptr;        // s x cap interface temporary
+  double *W2 = nullptr;       // second s x cap interface temporary
   double *lr_part = nullptr;  // lr_nblk x cap x k
   double *cbuf = nullptr;     // k x cap
   unsigned int *counter = nullptr;
@@ -110,6 +111,7 @@ struct slr_ctx {
   std::vector<int32_t> cf_lev_h, cb_lev_h;
   int32_t cf_nlev = 0, cb_nlev = 0;
   bool c_one_wg = true;
+  bool c_two_level = false;     // interface schedules of <= 2 levels: one launch per sweep
   int32_t b_threads = 1024;
   int32_t b_max_m = 0, b_max_lev = 0, b_max_level_bytes = 0;
   int64_t b_data_bytes = 0;
@@ -121,7 +123,7 @@ struct slr_ctx {
   double *U64 = nullptr;        // s x k column-major, FP64 (export)
   double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
-  int32_t lr_nblk = 256;
+  int32_t lr_nblk = 128;
   DevPool lrpool;               // U, U64, dsc
   // stats
   slr_info info{};
@@ -164,17 +166,18 @@ struct slr_batch {
 
 namespace {
 
-constexpr int RED_NBLK = 128;   // blocks of the deterministic reductions
+constexpr int RED_NBLK = 512;   // blocks of the deterministic reductions
 
 int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   if (w.cap >= nrhs && w.W) return SLR_OK;
   w.pool.release();
   int32_t cap = std::max<int32_t>(nrhs, 1);
   w.W = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
+  w.W2 = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
   w.lr_part = w.pool.alloc<double>((size_t)c->lr_nblk * cap * std::max(c->k, 1));
   w.cbuf = w.pool.alloc<double>((size_t)cap * std::max(c->k, 1));
   w.counter = w.pool.alloc<unsigned int>(16);
-  if (!w.W || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
+  if (!w.W || !w.W2 || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
   HIPCHK(hipMemset(w.counter, 0, 16 * sizeof(unsigned int)));
   w.cap = cap;
   return SLR_OK;
@@ -233,6 +236,18 @@ void csweep(slr_ctx *c, bool fwd, double *x, int64_t ldx, int32_t nrhs, bool com
   }
 }
 
+// out-of-place two-level interface sweep (multicolour schedules)
+void csweep2(slr_ctx *c, bool fwd, const double *x, int64_t ldx, double *y, int64_t ldy, int32_t nrhs,
+             bool compute64, hipStream_t st) {
+  const int32_t s = (int32_t)c->s;
+  if (c->fact_prec == SLR_FP64)
+    launch_sweep2<double, double>(fwd ? c->Cfd : c->Cbd, s, x, ldx, y, ldy, nrhs, st);
+  else if (compute64)
+    launch_sweep2<float, double>(fwd ? c->Cff : c->Cbf, s, x, ldx, y, ldy, nrhs, st);
+  else
+    launch_sweep2<float, float>(fwd ? c->Cff : c->Cbf, s, x, ldx, y, ldy, nrhs, st);
+}
+
 void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs,
              hipStream_t st) {
   const int k = c->k;
@@ -270,9 +285,15 @@ int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, in
     a.gout = w.W; a.ldgo = s; a.d_t = -1.0;
     a.nrhs = nrhs;
     if ((rc = bsolve(c, a, false, st))) return rc;
-    csweep(c, true, w.W, s, nrhs, false, st);
-    lowrank(c, w, w.W, s, z + m, ldz, nrhs, st);
-    csweep(c, false, z + m, ldz, nrhs, false, st);
+    if (c->c_two_level) {
+      csweep2(c, true, w.W, s, w.W2, s, nrhs, false, st);
+      lowrank(c, w, w.W2, s, w.W, s, nrhs, st);
+      csweep2(c, false, w.W, s, z + m, ldz, nrhs, false, st);
+    } else {
+      csweep(c, true, w.W, s, nrhs, false, st);
+      lowrank(c, w, w.W, s, z + m, ldz, nrhs, st);
+      csweep(c, false, z + m, ldz, nrhs, false, st);
+    }
   }
   if (m > 0) {
     BArgs a;
@@ -287,17 +308,24 @@ int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, in
 
 // w = H v = L^{-1} E^T B^{-1} E L^{-T} v (eq. H), FP64 arithmetic on the
 // stored factors; t: s-vector scratch.
-int apply_H(slr_ctx *c, const double *v, double *w, double *t, hipStream_t st) {
+int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipStream_t st) {
   const int64_t s = c->s;
-  launch_axpby(s, 1, 1.0, v, s, 0.0, t, s, st);
-  csweep(c, false, t, s, 1, true, st);
+  if (c->c_two_level) {
+    csweep2(c, false, v, s, t, s, 1, true, st);
+  } else {
+    launch_axpby(s, 1, 1.0, v, s, 0.0, t, s, st);
+    csweep(c, false, t, s, 1, true, st);
+  }
   BArgs a;
   a.y = t; a.ldy = s; a.b_y = 1.0;
-  a.gout = w; a.ldgo = s; a.d_t = 1.0;
+  a.gout = c->c_two_level ? t2 : w; a.ldgo = s; a.d_t = 1.0;
   a.nrhs = 1;
   int rc = bsolve(c, a, true, st);
   if (rc) return rc;
-  csweep(c, true, w, s, 1, true, st);
+  if (c->c_two_level)
+    csweep2(c, true, t2, s, w, s, 1, true, st);
+  else
+    csweep(c, true, w, s, 1, true, st);
   return SLR_OK;
 }
 
@@ -343,13 +371,14 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   double *V = tmp.alloc<double>((size_t)s * steps);
   double *Wl = tmp.alloc<double>(s);
   double *T = tmp.alloc<double>(s);
-  double *h = tmp.alloc<double>(steps + 1);
+  double *T2 = tmp.alloc<double>(s);
+  double *h = tmp.alloc<double>(2048);
   double *sc = tmp.alloc<double>(4);
   double *al = tmp.alloc<double>(steps);
   double *be = tmp.alloc<double>(steps);
   double *part = tmp.alloc<double>((size_t)RED_NBLK * (steps + 1));
   unsigned int *cnt = tmp.alloc<unsigned int>(4);
-  if (!V || !Wl || !T || !h || !sc || !al || !be || !part || !cnt) {
+  if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !cnt) {
     tmp.release();
     return fail(SLR_ERR_OOM, "Lanczos basis");
   }
@@ -369,34 +398,42 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   if (!(nv > 0.0)) return bail(fail(SLR_ERR_ARG, "Lanczos start vector is zero on the interface"));
   for (double &x : v0) x /= nv;
   HIPCHK(hipMemcpyAsync(V, v0.data(), sizeof(double) * s, hipMemcpyHostToDevice, st));
+  // All steps are queued without host round-trips.  The stopping test
+  // (beta_j <= 1e-14 ||T_j||_inf) is applied afterwards to the recorded
+  // coefficients: steps after a breakdown only produce basis columns that
+  // are never used.
+  // Step j: w = H v_j; two classical Gram-Schmidt passes against
+  // [v_0 .. v_j].  The first pass's coefficient on v_j is v_j . H v_j =
+  // alpha_j (it also removes the beta_{j-1} v_{j-1} term), so the
+  // three-term recurrence is subsumed by the full reorthogonalisation.
+  for (int32_t j = 0; j < steps; ++j) {
+    double *vj = V + (int64_t)j * s;
+    if ((rc = apply_H(c, vj, Wl, T, T2, st))) return bail(rc);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_multidot(s, j + 1, V, s, Wl, part, RED_NBLK, pass == 0 ? h : h + 1024, cnt, st);
+      launch_gemv_sub(s, j + 1, V, s, pass == 0 ? h : h + 1024, Wl, st);
+    }
+    int32_t rb = launch_multidot_partial(s, 1, Wl, s, Wl, part, RED_NBLK, st);           // ||w||^2
+    launch_lanczos_next(s, j, Wl, j + 1 < steps ? V + (int64_t)(j + 1) * s : nullptr, sc, al, be, part, rb, h + j,
+                        st);
+  }
+  std::vector<double> ah(steps), bh(steps);
+  HIPCHK(hipMemcpyAsync(ah.data(), al, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(bh.data(), be, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   c->alpha_h.clear();
   c->beta_h.clear();
   double tnorm = 0.0, bprev = 0.0;
   int32_t mm = 0;
   for (int32_t j = 0; j < steps; ++j) {
-    double *vj = V + (int64_t)j * s;
-    if ((rc = apply_H(c, vj, Wl, T, st))) return bail(rc);
-    launch_multidot(s, 1, vj, s, Wl, part, RED_NBLK, sc, cnt, st);             // alpha_j
-    launch_lanczos_axpy(s, Wl, vj, j > 0 ? vj - s : nullptr, sc, st);          // three-term
-    for (int pass = 0; pass < 2; ++pass) {                                      // CGS2
-      launch_multidot(s, j + 1, V, s, Wl, part, RED_NBLK, h, cnt, st);
-      launch_gemv_sub(s, j + 1, V, s, h, Wl, st);
-    }
-    launch_multidot(s, 1, Wl, s, Wl, part, RED_NBLK, sc + 2, cnt, st);          // ||w||^2
-    launch_lanczos_record(j, sc, al, be, st);
-    double ab[2];
-    HIPCHK(hipMemcpyAsync(ab, al + j, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ab + 1, be + j, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    c->alpha_h.push_back(ab[0]);
-    c->beta_h.push_back(ab[1]);
-    mm = j + 1;
-    tnorm = std::max(tnorm, std::fabs(ab[0]) + ab[1] + bprev);
-    bprev = ab[1];
-    if (!std::isfinite(ab[0]) || !std::isfinite(ab[1]))
+    if (!std::isfinite(ah[j]) || !std::isfinite(bh[j]))
       return bail(fail(SLR_ERR_BREAKDOWN, "non-finite Lanczos coefficients"));
-    if (j + 1 == steps || ab[1] <= 1e-14 * tnorm) break;
-    launch_scale_inv_sqrt(s, Wl, V + (int64_t)(j + 1) * s, sc + 2, st);
+    c->alpha_h.push_back(ah[j]);
+    c->beta_h.push_back(bh[j]);
+    mm = j + 1;
+    tnorm = std::max(tnorm, std::fabs(ah[j]) + bh[j] + bprev);
+    bprev = bh[j];
+    if (bh[j] <= 1e-14 * tnorm) break;
   }
   const int32_t need = need_k1 ? k + 1 : k;
   if (mm < need) return bail(fail(SLR_ERR_LANCZOS_SHORT, "Lanczos produced fewer Ritz pairs than needed"));
@@ -555,7 +592,17 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
     S.ci = P.upload(sw.ci);
     S.w = P.upload(conv<TS>(sw.w));
     S.sc = P.upload(conv<TS>(sw.sc));
-    return S.lev && S.rows && S.rp && S.ci && S.w && S.sc;
+    bool okw2 = true;
+    if (sw.nlev <= 2) {
+      // weights times the (stored) scale of the dependency row, rounded to TS
+      std::vector<double> scr(sw.nrows, 0.0);
+      for (int32_t t = 0; t < sw.nrows; ++t) scr[sw.rows[t]] = (double)(TS)sw.sc[t];
+      std::vector<double> w2(sw.w.size());
+      for (size_t e = 0; e < sw.w.size(); ++e) w2[e] = (double)(TS)sw.w[e] * scr[sw.ci[e]];
+      S.w2 = P.upload(conv<TS>(w2));
+      okw2 = S.w2 != nullptr;
+    }
+    return S.lev && S.rows && S.rp && S.ci && S.w && S.sc && okw2;
   };
   ok = ok && B.desc && B.lev && B.lvb && B.data && B.e_row && B.e_q && B.e_val && B.t_q && B.t_j && B.t_val;
   ok = ok && upc(H.cfwd, Cf) && upc(H.cbwd, Cb);
@@ -696,6 +743,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->cb_nlev = H.cbwd.nlev;
   // shallow interface schedules (multicolour) run one launch per level
   c->c_one_wg = std::max(c->cf_nlev, c->cb_nlev) > 8;
+  c->c_two_level = std::max(c->cf_nlev, c->cb_nlev) <= 2;
   if (c->c_one_wg && sizeof(int32_t) * (size_t)(std::max(c->cf_nlev, c->cb_nlev) + 1) > c->lds_limit)
     return destroy_fail(fail(SLR_ERR_ARG, "interface level schedule too deep for one workgroup"));
   {
@@ -813,9 +861,19 @@ int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void 
         a.nrhs = nrhs;
         return bsolve(c, a, false, st);
       }
-      case 1: csweep(c, true, c->ws.W, s, nrhs, false, st); return SLR_OK;
-      case 2: lowrank(c, c->ws, c->ws.W, s, c->pz + m, n, nrhs, st); return SLR_OK;
-      case 3: csweep(c, false, c->pz + m, n, nrhs, false, st); return SLR_OK;
+      case 1:
+        if (c->c_two_level)
+          csweep2(c, true, c->ws.W, s, c->ws.W2, s, nrhs, false, st);
+        else
+          csweep(c, true, c->ws.W, s, nrhs, false, st);
+        return SLR_OK;
+      case 2: lowrank(c, c->ws, c->ws.W2, s, c->ws.W, s, nrhs, st); return SLR_OK;
+      case 3:
+        if (c->c_two_level)
+          csweep2(c, false, c->ws.W, s, c->pz + m, n, nrhs, false, st);
+        else
+          csweep(c, false, c->pz + m, n, nrhs, false, st);
+        return SLR_OK;
       case 4: {
         BArgs a;
         a.f = c->pr; a.ldf = n; a.a_f = 1.0;

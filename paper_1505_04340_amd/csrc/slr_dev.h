@@ -45,6 +45,7 @@ struct SweepArrays {
   const int32_t *ci = nullptr;     // column indices
   const TS *w = nullptr;           // pre-scaled off-diagonal weights
   const TS *sc = nullptr;          // per-row scale
+  const TS *w2 = nullptr;          // two-level schedules: w * sc of the dependency row
 };
 
 template <typename TS>
@@ -93,6 +94,11 @@ void launch_bsolve(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t 
 template <typename TS, typename TC>
 void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nlev, int32_t nrows,
                   double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st);
+
+// Out-of-place sweep of a schedule with at most two levels, one launch.
+template <typename TS, typename TC>
+void launch_sweep2(const SweepArrays<TS> &S, int32_t nrows, const double *x, int64_t ldx, double *y, int64_t ldy,
+                   int32_t nrhs, hipStream_t st);
 
 // Rank-k block of eq. skt on w (s x nrhs, ld ldw), output to wout (ldo);
 // U column-major s x k:

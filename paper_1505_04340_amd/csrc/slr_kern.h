@@ -74,8 +74,15 @@ void launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const d
                      hipStream_t st);
 void launch_gemv_add(int64_t n, int32_t J, const double *V, int64_t ldv, const double *y, double *x,
                      hipStream_t st);
-void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, const double *sc,
-                         hipStream_t st);
+void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
+                         const double *apart, int32_t rb, hipStream_t st);
+// aval: device pointer to alpha_j (or nullptr: alpha_j is sc[0])
+void launch_lanczos_next(int64_t s, int32_t j, const double *w, double *vnext, double *sc, double *alpha,
+                         double *beta, const double *bpart, int32_t rb, const double *aval, hipStream_t st);
+int32_t launch_multidot_partial(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
+                                int32_t nblk, hipStream_t st);
+void launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
+                          double *w, hipStream_t st);
 void launch_scale_inv_sqrt(int64_t s, const double *w, double *out, const double *nrm2, hipStream_t st);
 void launch_div_scalar(int64_t n, const double *w, double *v, const double *scale, hipStream_t st);
 void launch_gmres_givens(int32_t j, int32_t ldh, double *Hm, const double *h1, const double *h2,
@@ -95,5 +102,6 @@ void launch_round_copy(int64_t n, const double *src, TU *dst, hipStream_t st);
 
 namespace slr {
 void launch_lanczos_record(int32_t j, double *sc, double *alpha, double *beta, hipStream_t st);
+void launch_lanczos_alpha(int32_t j, const double *h, double *sc, hipStream_t st);
 void launch_gmres_g0(int32_t len, const double *nrm2, double *g, hipStream_t st);
 }  // namespace slr

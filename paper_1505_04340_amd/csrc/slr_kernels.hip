@@ -335,6 +335,32 @@ __global__ void __launch_bounds__(256) k_sweep_lvl(SweepArrays<TS> S, int a, int
   sweep_row<TS, TC>(S, t, x + (int64_t)blockIdx.y * ldx);
 }
 
+// Whole sweep of a schedule with at most two levels, out of place
+// (y = T^{-1} x): level-0 rows have no entries (y = sc x); level-1 rows
+// depend on level-0 rows only, whose values sc_j x_j are folded into the
+// stored weights w2 = w * sc_j, so every row reads x alone.
+template <typename TS, typename TC>
+__global__ void __launch_bounds__(256) k_sweep2(SweepArrays<TS> S, int nrows, const double *x, int64_t ldx, double *y,
+                                                int64_t ldy) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const double *xc = x + (int64_t)blockIdx.y * ldx;
+  double *yc = y + (int64_t)blockIdx.y * ldy;
+  const int row = S.rows[t];
+  const int e0 = S.rp[t], e1 = S.rp[t + 1];
+  TC acc = cvt<TC>(S.sc[t]) * (TC)xc[row];
+  for (int e = e0; e < e1; ++e) acc -= cvt<TC>(S.w2[e]) * (TC)xc[S.ci[e]];
+  yc[row] = (double)acc;
+}
+
+template <typename TS, typename TC>
+void launch_sweep2(const SweepArrays<TS> &S, int32_t nrows, const double *x, int64_t ldx, double *y, int64_t ldy,
+                   int32_t nrhs, hipStream_t st) {
+  if (nrows == 0 || nrhs == 0) return;
+  hipLaunchKernelGGL((k_sweep2<TS, TC>), dim3((nrows + 255) / 256, nrhs), dim3(256), 0, st, S, nrows, x, ldx, y,
+                     ldy);
+}
+
 template <typename TS, typename TC>
 void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nlev, int32_t nrows,
                   double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st) {
@@ -360,7 +386,7 @@ void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nle
 //   (-> cbuf[r*k+q]); then wout = rho w + U cbuf (thread per row).
 // ---------------------------------------------------------------------------
 constexpr int LR_THREADS = 256;
-constexpr int LR_Q = 8;      // columns of U per register pass
+constexpr int LR_Q = 32;     // columns of U per register pass
 
 template <typename TU>
 __global__ void __launch_bounds__(LR_THREADS) k_lr_partial(const TU *U, int64_t s, int k, const double *w,
@@ -379,13 +405,15 @@ __global__ void __launch_bounds__(LR_THREADS) k_lr_partial(const TU *U, int64_t 
       for (int q = 0; q < LR_Q; ++q) acc[q] = 0.0;
       for (int64_t i = i0 + threadIdx.x; i < i1; i += LR_THREADS) {
         const double wi = wc[i];
+        // columns past k are clamped to column k-1 (valid loads, unpredicated
+        // so they issue as one batch); their sums are never stored
 #pragma unroll
-        for (int q = 0; q < LR_Q; ++q)
-          if (q0 + q < k) acc[q] += cvt<double>(U[i + (int64_t)(q0 + q) * s]) * wi;
+        for (int q = 0; q < LR_Q; ++q) acc[q] += cvt<double>(U[i + (int64_t)min(q0 + q, k - 1) * s]) * wi;
       }
 #pragma unroll
       for (int q = 0; q < LR_Q; ++q) acc[q] = wave_sum(acc[q]);
       if (lane == 0)
+#pragma unroll
         for (int q = 0; q < LR_Q; ++q) red[wid][q] = acc[q];
       __syncthreads();
       if (threadIdx.x < LR_Q && q0 + threadIdx.x < k) {
@@ -421,7 +449,15 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
   if (i >= s) return;
   for (int r = 0; r < nrhs; ++r) {
     double acc = 0.0;
-    for (int q = 0; q < k; ++q) acc += cvt<double>(U[i + (int64_t)q * s]) * cs[r * k + q];
+    int q = 0;
+    for (; q + 8 <= k; q += 8) {
+      double u[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) u[e] = cvt<double>(U[i + (int64_t)(q + e) * s]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc += u[e] * cs[r * k + q + e];
+    }
+    for (; q < k; ++q) acc += cvt<double>(U[i + (int64_t)q * s]) * cs[r * k + q];
     wout[i + (int64_t)r * ldo] = rho * w[i + (int64_t)r * ldw] + acc;
   }
 }
@@ -822,17 +858,43 @@ __global__ void __launch_bounds__(256) k_multidot(int64_t s, int J, const double
   if (threadIdx.x == 0) part[(int64_t)rb * J + j] = t;
 }
 
-// w[i] -= sum_j V[i + j*ldv] h[j]   (h on the device, J <= 1024)
+// sum_j V[i + j*ldv] c[j] in column order, 16 loads in flight (the last
+// group clamps its column index and multiplies padding by zero)
+__device__ __forceinline__ double dot_rows16(const double *V, int64_t ldv, int64_t i, const double *c, int J) {
+  double acc = 0.0;
+  for (int j0 = 0; j0 < J; j0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = V[i + (int64_t)min(j0 + e, J - 1) * ldv];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      if (j0 + e < J) acc += v[e] * c[j0 + e];
+  }
+  return acc;
+}
+
+// w[i] -= sum_j V[i + j*ldv] h[j]   (J <= 1024).  h is either on the
+// device (hpart == nullptr) or folded here from the rb multidot partials.
 __global__ void __launch_bounds__(256) k_gemv_sub(int64_t s, int J, const double *V, int64_t ldv,
-                                                  const double *h, double *w) {
+                                                  const double *h, double *w, const double *hpart, int rb) {
   __shared__ double hs[1024];
-  for (int j = threadIdx.x; j < J; j += blockDim.x) hs[j] = h[j];
+  if (hpart) {
+    fold_waves(hpart, rb, J, [&](int j, double v) { hs[j] = v; });
+  } else {
+    for (int j = threadIdx.x; j < J; j += blockDim.x) hs[j] = h[j];
+  }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s) return;
-  double acc = 0.0;
-  for (int j = 0; j < J; ++j) acc += V[i + (int64_t)j * ldv] * hs[j];
-  w[i] -= acc;
+  w[i] -= dot_rows16(V, ldv, i, hs, J);
+}
+
+int32_t launch_multidot_partial(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
+                                int32_t nblk, hipStream_t st) {
+  const int64_t rb =
+      std::max<int64_t>(1, std::min<int64_t>({(int64_t)nblk, (1024 + J - 1) / J, (s + 1023) / 1024}));
+  hipLaunchKernelGGL(k_multidot, dim3((unsigned)rb, J), dim3(256), 0, st, s, J, V, ldv, w, part);
+  return (int32_t)rb;
 }
 
 void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
@@ -846,22 +908,64 @@ void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const d
 
 void launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const double *h, double *w,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_gemv_sub, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, J, V, ldv, h, w);
+  hipLaunchKernelGGL(k_gemv_sub, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, J, V, ldv, h, w,
+                     (const double *)nullptr, 0);
 }
 
-// Lanczos three-term step: a = v.w computed by multidot into sc[0];
-//   w -= a v + b_prev v_prev   (b_prev = sc[1])
-__global__ void k_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, const double *sc) {
+void launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
+                          double *w, hipStream_t st) {
+  hipLaunchKernelGGL(k_gemv_sub, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, J, V, ldv,
+                     (const double *)nullptr, w, hpart, rb);
+}
+
+// Lanczos three-term step: alpha = v.w folded from the rb multidot
+// partials (block 0 stores it in sc[0]);  w -= alpha v + b_prev v_prev
+// with b_prev = sc[1].
+__global__ void __launch_bounds__(256) k_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev,
+                                                      double *sc, const double *apart, int rb) {
+  __shared__ double al;
+  fold_waves(apart, rb, 1, [&](int, double x) { al = x; });
+  __syncthreads();
+  const double a = al;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[0] = a;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s) return;
-  double t = w[i] - sc[0] * v[i];
+  double t = w[i] - a * v[i];
   if (vprev) t -= sc[1] * vprev[i];
   w[i] = t;
 }
 
-void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, const double *sc,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_lanczos_axpy, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, w, v, vprev, sc);
+void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
+                         const double *apart, int32_t rb, hipStream_t st) {
+  hipLaunchKernelGGL(k_lanczos_axpy, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, w, v, vprev, sc,
+                     apart, rb);
+}
+
+// End of Lanczos step j: beta_j = ||w|| folded from the rb multidot
+// partials; v_{j+1} = w / beta_j (if vnext); block 0 records alpha_j
+// (sc[0]) and beta_j and leaves beta_j in sc[1] for the next step.  sc[1]
+// is read by the previous kernel only, so the write cannot race.
+__global__ void __launch_bounds__(256) k_lanczos_next(int64_t s, int j, const double *w, double *vnext, double *sc,
+                                                      double *alpha, double *beta, const double *bpart, int rb,
+                                                      const double *aval) {
+  __shared__ double bt;
+  fold_waves(bpart, rb, 1, [&](int, double x) { bt = sqrt(x); });
+  __syncthreads();
+  const double b = bt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    alpha[j] = aval ? *aval : sc[0];
+    beta[j] = b;
+    sc[1] = b;
+  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s || !vnext) return;
+  vnext[i] = b > 0.0 ? w[i] / b : 0.0;
+}
+
+void launch_lanczos_next(int64_t s, int32_t j, const double *w, double *vnext, double *sc, double *alpha,
+                         double *beta, const double *bpart, int32_t rb, const double *aval, hipStream_t st) {
+  hipLaunchKernelGGL(k_lanczos_next, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, j, w, vnext, sc, alpha,
+                     beta, bpart, rb, aval);
 }
 
 // v_next = w / beta, beta = sqrt(sc[2]) (sc[2] holds w.w)
@@ -884,9 +988,7 @@ __global__ void __launch_bounds__(256) k_gemv_add(int64_t n, int J, const double
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double acc = 0.0;
-  for (int j = 0; j < J; ++j) acc += V[i + (int64_t)j * ldv] * ys[j];
-  x[i] += acc;
+  x[i] += dot_rows16(V, ldv, i, ys, J);
 }
 
 void launch_gemv_add(int64_t n, int32_t J, const double *V, int64_t ldv, const double *y, double *x,
@@ -1240,6 +1342,12 @@ template void launch_bsolve<float, float>(const BlockArrays<float> &, int32_t, c
                                           hipStream_t);
 template void launch_bsolve<float, double>(const BlockArrays<float> &, int32_t, const BArgs &, int32_t, size_t,
                                            hipStream_t);
+template void launch_sweep2<double, double>(const SweepArrays<double> &, int32_t, const double *, int64_t, double *,
+                                            int64_t, int32_t, hipStream_t);
+template void launch_sweep2<float, float>(const SweepArrays<float> &, int32_t, const double *, int64_t, double *,
+                                          int64_t, int32_t, hipStream_t);
+template void launch_sweep2<float, double>(const SweepArrays<float> &, int32_t, const double *, int64_t, double *,
+                                           int64_t, int32_t, hipStream_t);
 template void launch_sweep<double, double>(const SweepArrays<double> &, const int32_t *, int32_t, int32_t, double *,
                                            int64_t, int32_t, bool, hipStream_t);
 template void launch_sweep<float, float>(const SweepArrays<float> &, const int32_t *, int32_t, int32_t, double *,
@@ -1278,6 +1386,15 @@ __global__ void k_lanczos_record(int j, double *sc, double *alpha, double *beta)
     beta[j] = b;
     sc[1] = b;
   }
+}
+
+// alpha_j = the first Gram-Schmidt pass's coefficient on v_j
+__global__ void k_lanczos_alpha(int j, const double *h, double *sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = h[j];
+}
+
+void launch_lanczos_alpha(int32_t j, const double *h, double *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_lanczos_alpha, dim3(1), dim3(64), 0, st, j, h, sc);
 }
 
 void launch_lanczos_record(int32_t j, double *sc, double *alpha, double *beta, hipStream_t st) {
