@@ -124,6 +124,9 @@ struct slr_ctx {
   double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
   int32_t lr_nblk = 128;
+  // BF16 U_k always takes the matrix-core path, so a column's arithmetic
+  // never depends on how many columns share the launch
+  int32_t mfma_min_rhs = 1;
   DevPool lrpool;               // U, U64, dsc
   // stats
   slr_info info{};
@@ -261,8 +264,12 @@ void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wou
                             c->lr_nblk, w.cbuf, w.counter, st);
       break;
     default:
-      launch_lowrank<__hip_bfloat16>((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo,
-                                     nrhs, w.lr_part, c->lr_nblk, w.cbuf, w.counter, st);
+      if (nrhs >= c->mfma_min_rhs && k > 0)
+        launch_lowrank_mfma((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo, nrhs,
+                            w.lr_part, c->lr_nblk, w.cbuf, st);
+      else
+        launch_lowrank<__hip_bfloat16>((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo,
+                                       nrhs, w.lr_part, c->lr_nblk, w.cbuf, w.counter, st);
   }
 }
 

@@ -103,5 +103,9 @@ void launch_round_copy(int64_t n, const double *src, TU *dst, hipStream_t st);
 namespace slr {
 void launch_lanczos_record(int32_t j, double *sc, double *alpha, double *beta, hipStream_t st);
 void launch_lanczos_alpha(int32_t j, const double *h, double *sc, hipStream_t st);
+// rank-k block on matrix cores (BF16 U, column-major s x k)
+void launch_lowrank_mfma(const __hip_bfloat16 *U, int64_t s, int32_t k, const double *dsc, double rho,
+                         const double *w, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs, double *part,
+                         int32_t nblk, double *cbuf, hipStream_t st);
 void launch_gmres_g0(int32_t len, const double *nrm2, double *g, hipStream_t st);
 }  // namespace slr

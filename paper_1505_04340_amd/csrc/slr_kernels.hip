@@ -462,6 +462,151 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
   }
 }
 
+// ---------------------------------------------------------------------------
+// K4 on matrix cores (BF16 U_k, several right-hand sides).
+// v_mfma_f32_16x16x16bf16_1k, one wave: D(16x16) += A(16x16) B(16x16) with
+//   A: lane l holds A[l%16][4(l/16) + 0..3], B: lane l holds B[4(l/16)+0..3][l%16],
+//   D: lane l register i holds D[4(l/16) + i][l%16].
+// FP64 activations enter as three BF16 terms x = hi + mid + lo (each the
+// nearest BF16 of what is left), so every product with a BF16 U entry is
+// exact in FP32 and the contraction carries ~24 significant bits; only the
+// stored U is rounded.  Accumulation is FP32 within a row chunk, FP64
+// across chunks (the fold).
+// ---------------------------------------------------------------------------
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  return (short)u;
+}
+__device__ __forceinline__ float bf16_val(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+// x = hi + mid + lo, each BF16 (round to nearest even at every stage)
+__device__ __forceinline__ void split3(double x, short &hi, short &mid, short &lo) {
+  hi = bf16_bits((float)x);
+  const double r1 = x - (double)bf16_val(hi);
+  mid = bf16_bits((float)r1);
+  const double r2 = r1 - (double)bf16_val(mid);
+  lo = bf16_bits((float)r2);
+}
+
+constexpr int LRM_THREADS = 256;
+
+// part[b][c][q] = sum_{i in chunk b} U[i,q] W[i,c], for all q < k, c < nrhs.
+// Pairs (q-tile, c-tile) are dealt round-robin to the 4 waves; each wave
+// walks the block's row chunk in steps of 16.
+__global__ void __launch_bounds__(LRM_THREADS) k_lr_partial_mfma(const __hip_bfloat16 *U, int64_t s, int k,
+                                                                 const double *W, int64_t ldw, int nrhs,
+                                                                 double *part) {
+  const int nb = gridDim.x;
+  const int64_t chunk = (((s + nb - 1) / nb) + 15) & ~int64_t(15);
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = min(s, i0 + chunk);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int kt = (k + 15) / 16, nt = (nrhs + 15) / 16;
+  const uint16_t *Ub = reinterpret_cast<const uint16_t *>(U);
+  for (int pair = wid; pair < kt * nt; pair += LRM_THREADS / 64) {
+    const int mt = pair / nt, ntl = pair - mt * nt;
+    const int q = mt * 16 + (lane & 15);        // this lane's U column (A row)
+    const int c = ntl * 16 + (lane & 15);       // this lane's W column (B column)
+    const bool qok = q < k, cok = c < nrhs;
+    const int qc = qok ? q : k - 1, cc = cok ? c : nrhs - 1;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t r0 = i0; r0 < i1; r0 += 16) {
+      const int64_t rb = r0 + 4 * (lane >> 4);
+      bf16x4_t a, bh, bm, bl;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t row = rb + j;
+        const bool rok = row < i1;
+        const int64_t rr = rok ? row : i1 - 1;
+        const uint16_t uv = Ub[rr + (int64_t)qc * s];
+        a[j] = (rok && qok) ? (short)uv : (short)0;
+        const double wv = (rok && cok) ? W[rr + (int64_t)cc * ldw] : 0.0;
+        short h, m, l;
+        split3(wv, h, m, l);
+        bh[j] = h;
+        bm[j] = m;
+        bl[j] = l;
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc, 0, 0, 0);
+    }
+    // D[qrow][ccol]: qrow = mt*16 + 4(l/16) + i, ccol = ntl*16 + l%16
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int qq = mt * 16 + 4 * (lane >> 4) + i;
+      if (qq < k && cok) part[((int64_t)blockIdx.x * nrhs + c) * k + qq] = (double)acc[i];
+    }
+  }
+}
+
+// wout[i,c] = rho w[i,c] + sum_q U[i,q] cbuf[c*k + q]; one wave per 16 rows,
+// all column tiles; cbuf split into three BF16 terms in LDS.
+__global__ void __launch_bounds__(LRM_THREADS) k_lr_update_mfma(const __hip_bfloat16 *U, int64_t s, int k,
+                                                                const double *w, int64_t ldw, double *wout,
+                                                                int64_t ldo, int nrhs, const double *cbuf,
+                                                                double rho) {
+  extern __shared__ short cs3[];   // 3 x (kpad x npad), [term][q][c]
+  const int kpad = ((k + 15) / 16) * 16, npad = ((nrhs + 15) / 16) * 16;
+  for (int t = threadIdx.x; t < kpad * npad; t += blockDim.x) {
+    const int q = t / npad, c = t - q * npad;
+    const double v = (q < k && c < nrhs) ? cbuf[c * k + q] : 0.0;
+    short h, m, l;
+    split3(v, h, m, l);
+    cs3[t] = h;
+    cs3[kpad * npad + t] = m;
+    cs3[2 * kpad * npad + t] = l;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t m0 = ((int64_t)blockIdx.x * (LRM_THREADS / 64) + wid) * 16;
+  if (m0 >= s) return;
+  const uint16_t *Ub = reinterpret_cast<const uint16_t *>(U);
+  const int64_t row = min(m0 + (lane & 15), s - 1);   // this lane's A row
+  for (int ntl = 0; ntl < npad / 16; ++ntl) {
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int q0 = 0; q0 < kpad; q0 += 16) {
+      bf16x4_t a, bh, bm, bl;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = q0 + 4 * (lane >> 4) + j;
+        a[j] = q < k ? (short)Ub[row + (int64_t)q * s] : (short)0;
+        const int t = q * npad + ntl * 16 + (lane & 15);
+        bh[j] = cs3[t];
+        bm[j] = cs3[kpad * npad + t];
+        bl[j] = cs3[2 * kpad * npad + t];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc, 0, 0, 0);
+    }
+    const int c = ntl * 16 + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = m0 + 4 * (lane >> 4) + i;
+      if (r < s && c < nrhs) wout[r + (int64_t)c * ldo] = rho * w[r + (int64_t)c * ldw] + (double)acc[i];
+    }
+  }
+}
+
+void launch_lowrank_mfma(const __hip_bfloat16 *U, int64_t s, int32_t k, const double *dsc, double rho,
+                         const double *w, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs, double *part,
+                         int32_t nblk, double *cbuf, hipStream_t st) {
+  if (s == 0 || nrhs == 0 || k == 0) return;
+  hipLaunchKernelGGL(k_lr_partial_mfma, dim3(nblk), dim3(LRM_THREADS), 0, st, U, s, k, w, ldw, nrhs, part);
+  hipLaunchKernelGGL(k_lr_fold, dim3((unsigned)((k * nrhs + 3) / 4)), dim3(256), 0, st, part, nblk, k * nrhs, k,
+                     dsc, cbuf);
+  const int kpad = ((k + 15) / 16) * 16, npad = ((nrhs + 15) / 16) * 16;
+  const size_t lds = sizeof(short) * 3 * (size_t)kpad * npad;
+  const unsigned nblk_u = (unsigned)((s + 63) / 64);
+  hipLaunchKernelGGL(k_lr_update_mfma, dim3(nblk_u), dim3(LRM_THREADS), lds, st, U, s, k, w, ldw, wout, ldo, nrhs,
+                     cbuf, rho);
+}
+
 template <typename TU>
 void launch_lowrank(const TU *U, int64_t s, int32_t k, const double *dsc, double rho,
                     const double *w, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs,

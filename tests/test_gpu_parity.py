@@ -192,7 +192,8 @@ def test_reduced_precision_apply(fact_prec, uk_prec):
              lowrank=(O.round_fp32(Po.U) if uk_prec == "fp32" else Po.U, Po.lam, Po.theta))
     r = _rand(pr.n, 3, 21)
     err = _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max()
-    tol = 1e-12 if fact_prec == "fp64" else 1e-5
+    # BF16 U_k runs on matrix cores with FP32 accumulation: the FP32 bar
+    tol = 1e-12 if (fact_prec == "fp64" and uk_prec != "bf16") else 1e-5
     assert err <= tol, err
 
 
@@ -304,3 +305,22 @@ def test_batch_results_equal_alone_and_in_mix():
         assert ia["iters"] == im["iters"]
         assert np.array_equal(xa.reshape(pr.n, -1), xm.reshape(pr.n, -1))
         assert im["relres"] <= 1e-8
+
+
+# --------------------------------------------------- matrix-core rank-k block
+@pytest.mark.parametrize("fact_prec", ["fp64", "fp32"])
+def test_multi_rhs_bf16_mfma_apply(fact_prec):
+    """16 and 32 right-hand sides with BF16 U_k take the matrix-core rank-k
+    kernels (FP64 activations split into three BF16 terms, FP32
+    accumulation per row chunk): the apply matches the oracle on the same
+    rounded data to 1e-5 and the scalar one-column path to 1e-6."""
+    pr = si.make_config("diffusion2d_1024", N=128, boxes=4)
+    Po = _oracle(pr, k=32, lanczos_steps=80, fact_prec=fact_prec, uk_prec="bf16", c_order="multicolor")
+    G = _slr(pr, k=32, lanczos_steps=80, fact_prec=fact_prec, uk_prec="bf16", c_order="multicolor",
+             lowrank=(Po.U, Po.lam, Po.theta))
+    for nr in (16, 32):
+        r = _rand(pr.n, nr, 40 + nr)
+        Z = G.apply(_dev(r)).cpu().numpy()
+        assert _relerr(Z, Po.apply(r)).max() <= 1e-5
+        z1 = np.column_stack([G.apply(_dev(r[:, j])).cpu().numpy() for j in (0, nr - 1)])
+        assert _relerr(Z[:, [0, nr - 1]], z1).max() <= 1e-6
