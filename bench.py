@@ -37,8 +37,10 @@ def log(*a):
 FORMS = {
     # FP64 factors and U_k, plain PCG
     "fp64": dict(fact_prec="fp64", uk_prec="fp64", method="pcg", c_order="multicolor", dtype="f64"),
-    # FP32 factors / U_k inside the apply, flexible CG with FP64 recurrences
-    "mixed": dict(fact_prec="fp32", uk_prec="fp32", method="fcg", c_order="multicolor", dtype="f32-apply/f64-krylov"),
+    # FP32 factors, BF16 U_k on matrix cores (FP32 accumulation); flexible CG
+    # with FP64 recurrences, dot products and residuals
+    "mixed": dict(fact_prec="fp32", uk_prec="bf16", method="fcg", c_order="multicolor",
+                  dtype="f32/bf16-apply, f64-krylov"),
 }
 
 
@@ -73,6 +75,8 @@ def cpu_baseline(pr, form, budget_s=30.0):
         O.lanczos_lowrank(P, pr.k, pr.lanczos_steps, v0, "lambda_k1")
         if form["uk_prec"] == "fp32":
             P.U = O.round_fp32(P.U)
+        elif form["uk_prec"] == "bf16":
+            P.U = O.round_bf16(P.U)
         t1 = time.perf_counter()
         res = O.solve(P, b[:, 0], "fcg" if form["method"] == "fcg" else "pcg")
         t2 = time.perf_counter()
@@ -82,13 +86,115 @@ def cpu_baseline(pr, form, budget_s=30.0):
             "oracle_iters": res.iters, "oracle_relres": res.true_relres}
 
 
+def measure_form(P, pr, form, steps, warmup, v0, bd, xs, log_prefix):
+    import torch
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order=form["c_order"], fact_prec=form["fact_prec"],
+              uk_prec=form["uk_prec"], v0=v0)
+    torch.cuda.synchronize()
+    info = G.query()
+    log(f"{log_prefix} setup: host {info['setup_host_s']:.2f} s, Lanczos {info['setup_lanczos_s']:.3f} s; "
+        f"s={info['s']} m={info['m']} theta={info['theta']:.5f}")
+
+    def step():
+        G.update_lowrank(pr.k, pr.lanczos_steps, v0)
+        return G.solve(bd, form["method"], rtol=1e-8, maxit=300)
+
+    for i in range(warmup):
+        x, inf = step()
+        log(f"{log_prefix} warmup {i}: iters {inf[0]['iters']} relres {inf[0]['relres']:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for i in range(steps):
+        x, inf = step()
+        iters.append(inf[0]["iters"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log(f"{log_prefix} {steps} steps in {el:.3f} s; iters {iters}; relres {inf[0]['relres']:.2e}")
+    relres = inf[0]["relres"]
+    err = float(np.abs(x.cpu().numpy() - xs[:, 0]).max())
+    t1 = time.perf_counter()
+    ns = max(3, steps)
+    for i in range(ns):
+        G.solve(bd, form["method"], rtol=1e-8, maxit=300)
+    torch.cuda.synchronize()
+    solve_only = ns / (time.perf_counter() - t1)
+    t2 = time.perf_counter()
+    nl = max(2, steps // 2)
+    for i in range(nl):
+        G.update_lowrank(pr.k, pr.lanczos_steps, v0)
+    torch.cuda.synchronize()
+    lanczos_ms = 1e3 * (time.perf_counter() - t2) / nl
+    stages = {st: G.time_kernel(st, 1, 50) for st in ("bsolve1", "cfwd", "lowrank", "cbwd", "bsolve2",
+                                                      "apply", "spmv")}
+    log(f"{log_prefix} stage ms: " + ", ".join(f"{k} {v:.4f}" for k, v in stages.items()))
+    bf = 8 if form["fact_prec"] == "fp64" else 4
+    bu = {"fp64": 8, "fp32": 4, "bf16": 2}[form["uk_prec"]]
+    res = {"steps_per_s": round(steps / el, 4), "ms_per_step": round(1e3 * el / steps, 3), "iters": iters[-1],
+           "final_relres_fp64": relres, "max_abs_err_vs_xstar": err,
+           "solve_only_solves_per_s": round(solve_only, 3), "lanczos_build_ms": round(lanczos_ms, 3),
+           "apply_ms": round(stages["apply"], 5),
+           "apply_algorithmic_GBs": round(apply_bytes(info, 1, bf, bu, info["k"]) / (stages["apply"] * 1e-3) / 1e9, 2),
+           "stage_ms": {k: round(v, 5) for k, v in stages.items()}}
+    return G, info, res, stages, bf
+
+
+SERVE_MAXIT = 1000
+
+
+def serving(P, torch, n_req, seed=13):
+    """Continuous batching (mixed form, flexible CG) vs one-request-at-a-time
+    plain FP64 PCG over four resident preconditioners."""
+    import slr_inputs as si
+    from paper_1505_04340_amd import serve
+    names = ["serve_lap2d_256", "serve_lap2d_512", "serve_lap3d_64", "serve_lap3d_96"]
+    prs = [si.make_config(nm) for nm in names]
+    mixed, plain = [], []
+    for pr in prs:
+        kw = dict(k=pr.k, lanczos_steps=pr.lanczos_steps, c_order="multicolor", v0=pr.v0())
+        mixed.append(P.SLR(pr.csr, pr.part, pr.nparts, fact_prec="fp32", uk_prec="bf16", **kw))
+        plain.append(P.SLR(pr.csr, pr.part, pr.nparts, **kw))
+    ns = [pr.n for pr in prs]
+    out = {"matrices": [f"{nm} (n={pr.n}, p={pr.nparts}, k={pr.k})" for nm, pr in zip(names, prs)]}
+
+    def run(kind, rate):
+        reqs = serve.make_requests(ns, n_req, rate, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "mixed_batched":
+            svc = serve.Service(mixed, "fcg", maxit=SERVE_MAXIT)
+            svc.run(reqs)
+            dev = svc.device_bytes()
+            svc.close()
+        else:
+            serve.serve_plain(plain, reqs, "pcg", maxit=SERVE_MAXIT)
+            dev = 0
+        wall = time.perf_counter() - t0
+        sm = serve.summarize(reqs, wall)
+        if dev:
+            sm["batch_device_bytes"] = dev
+        log(f"[serve] {kind} rate {rate:.1f}/s: {sm}")
+        return sm
+
+    sat_p = run("plain_fp64", 0.0)
+    sat_m = run("mixed_batched", 0.0)
+    rate = 0.8 * sat_p["requests_per_s"]
+    out["saturation"] = {"plain_fp64": sat_p, "mixed_batched": sat_m}
+    out["poisson_rate_per_s"] = round(rate, 3)
+    out["poisson"] = {"plain_fp64": run("plain_fp64", rate), "mixed_batched": run("mixed_batched", rate)}
+    out["speedup_solves_per_s"] = round(sat_m["solves_per_s"] / sat_p["solves_per_s"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", choices=sorted(FORMS), default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--config", default="lap3d_64")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -100,89 +206,52 @@ def main():
     import paper_1505_04340_amd as P
     import slr_inputs as si
 
-    form = FORMS[args.form]
     pr = si.make_config(args.config)
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    log(f"[bench] setup {pr.name} n={pr.n} p={pr.nparts} k={pr.k} form={args.form}")
-    t0 = time.perf_counter()
-    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
-              c_fact=pr.c_fact, c_order=form["c_order"], fact_prec=form["fact_prec"],
-              uk_prec=form["uk_prec"], v0=pr.v0())
-    torch.cuda.synchronize()
-    info = G.query()
-    log(f"[bench] device LDS per workgroup {P.slr_device_lds_bytes()} bytes")
-    log(f"[bench] setup done in {time.perf_counter() - t0:.2f} s (host {info['setup_host_s']:.2f} s, "
-        f"Lanczos {info['setup_lanczos_s']:.3f} s); s={info['s']} m={info['m']}")
+    log(f"[bench] {pr.name} n={pr.n} p={pr.nparts} k={pr.k}; device LDS per workgroup "
+        f"{P.slr_device_lds_bytes()} bytes")
     xs, b = pr.rhs()
     bd = torch.tensor(b[:, 0], dtype=torch.float64, device="cuda")
     v0 = pr.v0()
-
-    def step():
-        G.update_lowrank(pr.k, pr.lanczos_steps, v0)
-        return G.solve(bd, form["method"], rtol=1e-8, maxit=300)
-
-    for i in range(args.warmup):
-        x, inf = step()
-        log(f"[bench] warmup {i}: iters {inf[0]['iters']} relres {inf[0]['relres']:.2e}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = []
-    for i in range(args.steps):
-        x, inf = step()
-        iters.append(inf[0]["iters"])
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    log(f"[bench] {args.steps} steps in {el:.3f} s; iters {iters}; relres {inf[0]['relres']:.2e}")
-    relres = inf[0]["relres"]
-    err = float(np.abs(x.cpu().numpy() - xs[:, 0]).max())
-
-    # solve-only rate (preconditioner resident) and stage timings
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ns = max(3, args.steps)
-    for i in range(ns):
-        G.solve(bd, form["method"], rtol=1e-8, maxit=300)
-    torch.cuda.synchronize()
-    solve_only = ns / (time.perf_counter() - t1)
-    t2 = time.perf_counter()
-    nl = max(2, args.steps // 2)
-    for i in range(nl):
-        G.update_lowrank(pr.k, pr.lanczos_steps, v0)
-    torch.cuda.synchronize()
-    lanczos_ms = 1e3 * (time.perf_counter() - t2) / nl
-    stages = {st: G.time_kernel(st, 1, 50) for st in ("bsolve1", "cfwd", "lowrank", "cbwd", "bsolve2",
-                                                      "apply", "spmv")}
-    log("[bench] stage ms: " + ", ".join(f"{k} {v:.4f}" for k, v in stages.items()))
-    bf = 8 if form["fact_prec"] == "fp64" else 4
-    bu = {"fp64": 8, "fp32": 4, "bf16": 2}[form["uk_prec"]]
-    ab = apply_bytes(info, 1, bf, bu, info["k"])
-    bb = bsolve_bytes(info, 1, bf)
-    dom = "bsolve1"
-    achieved = bb / (stages[dom] * 1e-3) / 1e9
+    forms = {}
+    G = None
+    for name in ("fp64", "mixed"):
+        Gf, info, res, stages, bf = measure_form(P, pr, FORMS[name], args.steps, args.warmup, v0, bd, xs,
+                                                 f"[bench:{name}]")
+        forms[name] = res
+        if name == "fp64":
+            G, info64, stages64, bf64 = Gf, info, stages, bf
+        else:
+            del Gf
+    res = forms["fp64"]
+    bb = bsolve_bytes(info64, 1, bf64)
+    achieved = bb / (stages64["bsolve1"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
             "kernel": "k_bsolve (batched B_i solves + E^T epilogue)",
-            "algorithmic_bytes_per_launch": int(bb), "avg_launch_ms": round(stages[dom], 5)}
+            "algorithmic_bytes_per_launch": int(bb), "avg_launch_ms": round(stages64["bsolve1"], 5)}
     out = {
-        "metric": METRIC, "value": round(args.steps / el, 4), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": form["dtype"],
+        "metric": METRIC, "value": res["steps_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": FORMS["fp64"]["dtype"],
         "data": "synthetic",
         "config": {"workload": "3-D 7-point Laplacian 64^3 (n=262144), 4x4x4 boxes (64 subdomains), "
                                "IC(0) B_i and C (multicolour C ordering), k=32 from 160 Lanczos steps, "
                                "PCG rtol 1e-8, 1 RHS; step = device Lanczos build + solve",
-                   "form": args.form, "nrhs": 1},
+                   "form": "fp64", "nrhs": 1},
         "roofline": roof,
-        "iters": iters[-1], "final_relres_fp64": relres, "max_abs_err_vs_xstar": err,
-        "solve_only_solves_per_s": round(solve_only, 3), "lanczos_build_ms": round(lanczos_ms, 3),
-        "apply_ms": round(stages["apply"], 5),
-        "apply_algorithmic_GBs": round(ab / (stages["apply"] * 1e-3) / 1e9, 2),
-        "stage_ms": {k: round(v, 5) for k, v in stages.items()},
+        "iters": res["iters"], "final_relres_fp64": res["final_relres_fp64"],
+        "solve_only_solves_per_s": res["solve_only_solves_per_s"], "lanczos_build_ms": res["lanczos_build_ms"],
+        "apply_ms": res["apply_ms"], "apply_algorithmic_GBs": res["apply_algorithmic_GBs"],
+        "forms": forms,
     }
+    if not args.no_serve:
+        del G
+        torch.cuda.empty_cache()
+        out["serving"] = serving(P, torch, args.serve_requests)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle, 1 thread) ...")
-        out["cpu_baseline"] = cpu_baseline(pr, form)
+        out["cpu_baseline"] = cpu_baseline(pr, FORMS["fp64"])
         log(f"[bench] CPU baseline {out['cpu_baseline']['value']:.4f} solves/s")
     print(json.dumps(out))
 
