@@ -192,8 +192,9 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
 // leaves a staging buffer of at least max(largest level, min(24 KiB,
 // largest sweep)).  Returns false when not even R = 1 fits.
 bool b_lds_plan(const slr_ctx *c, int32_t nrhs, size_t tc_bytes, int32_t &R, int32_t &stage) {
-  const int64_t fixed = 16 * (int64_t)(c->b_max_lev + 1) + 16;
-  const int64_t need = std::max<int64_t>(c->b_max_level_bytes, std::min<int64_t>(24576, c->b_data_bytes));
+  const int64_t fixed = 16 * (int64_t)(c->b_max_lev + 1) + kStageDummyBytes;
+  // the fixed-width path double-buffers the stage: each half holds a level
+  const int64_t need = std::max<int64_t>(2 * (int64_t)c->b_max_level_bytes, std::min<int64_t>(24576, c->b_data_bytes));
   for (int32_t r = std::min<int32_t>(std::max(nrhs, 1), 16); r >= 1; --r) {
     const int64_t xb = pad16h((int64_t)tc_bytes * (std::max(c->b_max_m, 1) * r + 1));
     const int64_t rest = ((int64_t)c->lds_limit - fixed - xb) & ~int64_t(15);
@@ -214,7 +215,7 @@ int run_bsolve(slr_ctx *c, const BlockArrays<TS> &B, const BArgs &a0, hipStream_
     return fail(SLR_ERR_ARG, "a subdomain does not fit the LDS of one workgroup");
   a.R = R;
   a.stage_bytes = stage;
-  const size_t lds = (size_t)stage + 16 + pad16h((int64_t)sizeof(TC) * (c->b_max_m * R + 1)) +
+  const size_t lds = (size_t)stage + kStageDummyBytes + pad16h((int64_t)sizeof(TC) * (c->b_max_m * R + 1)) +
                     16 * (size_t)(c->b_max_lev + 1);
   launch_bsolve<TS, TC>(B, c->p, a, c->b_threads, lds, st);
   return SLR_OK;
@@ -466,8 +467,9 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   return finish_lowrank(c, st);
 }
 
-// Pack one sweep of one subdomain as the level-sliced ELL byte stream the
-// B kernel stages into LDS (layout documented with BlockDesc).
+// Pack one sweep of one subdomain as the level-sliced byte stream the B
+// kernel stages into LDS (layouts documented with BlockDesc): row records
+// when every row has the fixed width Kfix > 0, else the ELL form.
 template <typename TS>
 void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::vector<int32_t> &lvb, int32_t &K,
                 int32_t &max_level_bytes, int64_t &offset) {
@@ -477,25 +479,47 @@ void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::
   offset = (int64_t)data.size();
   int64_t pos = 0;
   lvb.push_back(0);
+  const int32_t KR = rec_width(K);
   for (int32_t l = 0; l < sw.nlev; ++l) {
     const int32_t a = sw.levptr[l], L = sw.levptr[l + 1] - a;
-    const int64_t o_sc = pad8h(2 * L), o_ci = o_sc + pad8h((int64_t)sizeof(TS) * L);
-    const int64_t o_w = o_ci + pad8h(2 * (int64_t)K * L);
-    const int64_t size = pad16h(o_w + (int64_t)sizeof(TS) * K * L);
-    data.resize(offset + pos + size, 0);
-    uint8_t *base = data.data() + offset + pos;
-    uint16_t *rows = reinterpret_cast<uint16_t *>(base);
-    TS *sc = reinterpret_cast<TS *>(base + o_sc);
-    uint16_t *ci = reinterpret_cast<uint16_t *>(base + o_ci);
-    TS *w = reinterpret_cast<TS *>(base + o_w);
-    for (int32_t j = 0; j < L; ++j) {
-      const int32_t t = a + j, row = sw.rows[t];
-      rows[j] = (uint16_t)row;
-      sc[j] = (TS)sw.sc[t];
-      const int32_t e0 = sw.rp[t], cnt = sw.rp[t + 1] - e0;
-      for (int32_t e = 0; e < K; ++e) {
-        ci[(int64_t)e * L + j] = (uint16_t)(e < cnt ? sw.ci[e0 + e] : row);
-        w[(int64_t)e * L + j] = e < cnt ? (TS)sw.w[e0 + e] : (TS)0;
+    int64_t size;
+    if (Kfix > 0) {
+      // row records: int32 [row, c_0 .. c_{K-1}, pad] then TS [sc, w_0 .. w_{K-1}, pad]
+      const int64_t o_w = 4 * (int64_t)KR * L;
+      size = o_w + (int64_t)sizeof(TS) * KR * L;
+      data.resize(offset + pos + size, 0);
+      uint8_t *base = data.data() + offset + pos;
+      int32_t *ix = reinterpret_cast<int32_t *>(base);
+      TS *wr = reinterpret_cast<TS *>(base + o_w);
+      for (int32_t j = 0; j < L; ++j) {
+        const int32_t t = a + j, row = sw.rows[t];
+        const int32_t e0 = sw.rp[t], cnt = sw.rp[t + 1] - e0;
+        ix[(int64_t)j * KR] = row;
+        wr[(int64_t)j * KR] = (TS)sw.sc[t];
+        for (int32_t e = 0; e + 1 < KR; ++e) {
+          ix[(int64_t)j * KR + 1 + e] = e < cnt ? sw.ci[e0 + e] : row;
+          wr[(int64_t)j * KR + 1 + e] = e < cnt ? (TS)sw.w[e0 + e] : (TS)0;
+        }
+      }
+    } else {
+      const int64_t o_sc = pad8h(2 * L), o_ci = o_sc + pad8h((int64_t)sizeof(TS) * L);
+      const int64_t o_w = o_ci + pad8h(2 * (int64_t)K * L);
+      size = pad16h(o_w + (int64_t)sizeof(TS) * K * L);
+      data.resize(offset + pos + size, 0);
+      uint8_t *base = data.data() + offset + pos;
+      uint16_t *rows = reinterpret_cast<uint16_t *>(base);
+      TS *sc = reinterpret_cast<TS *>(base + o_sc);
+      uint16_t *ci = reinterpret_cast<uint16_t *>(base + o_ci);
+      TS *w = reinterpret_cast<TS *>(base + o_w);
+      for (int32_t j = 0; j < L; ++j) {
+        const int32_t t = a + j, row = sw.rows[t];
+        rows[j] = (uint16_t)row;
+        sc[j] = (TS)sw.sc[t];
+        const int32_t e0 = sw.rp[t], cnt = sw.rp[t + 1] - e0;
+        for (int32_t e = 0; e < K; ++e) {
+          ci[(int64_t)e * L + j] = (uint16_t)(e < cnt ? sw.ci[e0 + e] : row);
+          w[(int64_t)e * L + j] = e < cnt ? (TS)sw.w[e0 + e] : (TS)0;
+        }
       }
     }
     max_level_bytes = std::max<int32_t>(max_level_bytes, (int32_t)size);

@@ -12,16 +12,21 @@ namespace slr {
 // Per-subdomain descriptor of the batched B_i solves (offsets into the
 // concatenated arrays of all subdomains).
 //
-// Each sweep of each subdomain is packed as a level-sliced ELL byte stream
-// (built on the host, 16-byte aligned): for level l with L rows and K
-// entries per row (the sweep's widest row; short rows padded with w = 0
-// pointing at their own row), the segment holds
+// Each sweep of each subdomain is packed as a level-sliced byte stream
+// (built on the host, 16-byte aligned segments); lvb[l] is the byte offset
+// of level l's segment (lvb[nlev] = total bytes).  For level l with L rows:
+//
+// Fixed width K (every row of every sweep padded to the problem's widest
+// row K <= 4; padding has w = 0 and points at the row itself), row records
+// of KR = rec_width(K) entries:
+//     idx   int32[L][KR]       [row, c_0, .., c_{K-1}, pad]  local indices
+//     wts   TS[L][KR]          [sc, w_0, .., w_{K-1}, pad]   scale, weights
+// Any width K (the sweep's widest row), ELL form:
 //     rows  uint16[L]          local row index
 //     sc    TS[L]              row scale
 //     ci    uint16[K*L]        column of entry e of row j at [e*L + j]
 //     w     TS[K*L]            pre-divided weight, same layout
-// each section padded to 8 bytes and the segment to 16.  lvb[l] is the
-// byte offset of level l's segment (lvb[nlev] = total bytes).
+// each ELL section padded to 8 bytes and the segment to 16.
 struct BlockDesc {
   int32_t m0, m;                   // interior range in the internal order
   int32_t f_nlev, f_K, f_lev, f_lvb;   // forward sweep: levels, width, levptr / lvb offsets
@@ -73,6 +78,15 @@ struct BlockArrays {
 //   z     = B_i^{-1} rhs                      (forward + backward sweep in LDS)
 //   u_i   = z                                 (if u != nullptr)
 //   gout_q = c_g * g_q + d_t * (E^T z)_q      (epilogue, q owned by i; if gout)
+// LDS bytes after the B kernel's stage that absorb the copy's stores past
+// the end: one 16-byte slot per lane of a wave, so that such stores from one
+// instruction never hit the same bank.
+constexpr int kStageDummyBytes = 1024;
+
+// Entries of a fixed-width row record: the row plus K columns, rounded up to
+// a multiple of 4 so that records are whole 16-byte vectors.
+__host__ __device__ constexpr int rec_width(int K) { return (K + 1 + 3) & ~3; }
+
 struct BArgs {
   const double *f = nullptr;  int64_t ldf = 0;  double a_f = 0.0;
   const double *y = nullptr;  int64_t ldy = 0;  double b_y = 0.0;

@@ -96,92 +96,288 @@ void launch_fold(const double *part, int32_t nb, int32_t ncol, double *out, doub
 __host__ __device__ constexpr int pad8(int x) { return (x + 7) & ~7; }
 __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
 
-// One level of a packed sweep, read from LDS (see BlockDesc).  KE > 0: every
-// packed row has exactly KE entries (the problem's widest row, padding has
-// w = 0), and the row's loads form one straight-line batch; KE == 0: any
-// width K.  R1: one right-hand side.  The subtraction order is the same in
-// every variant.
-template <typename TS, typename TC, int KE, bool R1>
-__device__ __forceinline__ void level_from_lds(const uint8_t *base, int L, int K, TC *xs, int R, int Rg) {
+// x lives in LDS column-major: column r of the workgroup's right-hand sides
+// at xs[r * XS + row], XS = the largest subdomain size; xs[XS * R] is a
+// dummy slot that absorbs stores past the end.
+//
+// One level of a packed sweep with any row width K, solved by the whole
+// workgroup (rows x columns spread over the threads), read from LDS.  The
+// subtraction order is the same in every variant.
+template <typename TS, typename TC>
+__device__ __forceinline__ void level_from_lds(const uint8_t *base, int L, int K, TC *xs, int XS, int Rg) {
   const uint16_t *rows = reinterpret_cast<const uint16_t *>(base);
   const int o_sc = pad8(2 * L);
   const TS *sc = reinterpret_cast<const TS *>(base + o_sc);
   const int o_ci = o_sc + pad8((int)sizeof(TS) * L);
   const uint16_t *ci = reinterpret_cast<const uint16_t *>(base + o_ci);
-  const int kk = KE > 0 ? KE : K;
-  const TS *w = reinterpret_cast<const TS *>(base + o_ci + pad8(2 * kk * L));
-  const int ntask = R1 ? L : L * Rg;
-  for (int t = threadIdx.x; t < ntask; t += blockDim.x) {
-    int j, r;
-    if (R1) {
-      j = t;
-      r = 0;
-    } else {
-      j = t / Rg;
-      r = t - j * Rg;
-    }
+  const TS *w = reinterpret_cast<const TS *>(base + o_ci + pad8(2 * K * L));
+  for (int t = threadIdx.x; t < L * Rg; t += blockDim.x) {
+    const int j = t / Rg, r = t - j * Rg;
+    TC *xc = xs + r * XS;
     const int row = rows[j];
-    if constexpr (KE > 0) {
-      int cv[KE];
-      TS wv[KE];
+    TC acc = cvt<TC>(sc[j]) * xc[row];
+    for (int e = 0; e < K; ++e) acc -= cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
+    xc[row] = acc;
+  }
+}
+
+// Copy nv 16-byte vectors into the LDS stage: vector i comes from src0[i]
+// for i < n0, else from src1[i - n0] (two byte streams staged back to back),
+// by the gn threads gt = 0 .. gn-1 of a group of whole waves.  U loads per
+// thread are issued as one batch before their LDS stores.  Neither is
+// predicated (a predicated store lets the compiler sink its load next to
+// it, one round trip each): past the end, loads clamp to the last vector and
+// stores go to the lane's own dummy slot after the stage.  U is chosen so
+// that one batch covers the copy when it can.
+template <int U>
+__device__ __forceinline__ void stage_batch(const uint4 *src0, int n0, const uint4 *src1, int nv, uint4 *dst,
+                                            uint4 *dummy, int gt, int gn) {
+  for (int i0 = gt; i0 < nv; i0 += U * gn) {
+    uint4 v[U];
 #pragma unroll
-      for (int e = 0; e < KE; ++e) {
-        cv[e] = ci[e * L + j];
-        wv[e] = w[e * L + j];
-      }
-      TC xv[KE];
+    for (int u = 0; u < U; ++u) {
+      const int i = min(i0 + u * gn, nv - 1);
+      v[u] = i < n0 ? src0[i] : src1[i - n0];
+    }
 #pragma unroll
-      for (int e = 0; e < KE; ++e) xv[e] = xs[cv[e] * R + r];
-      TC acc = cvt<TC>(sc[j]) * xs[row * R + r];
-#pragma unroll
-      for (int e = 0; e < KE; ++e) acc -= cvt<TC>(wv[e]) * xv[e];
-      xs[row * R + r] = acc;
-    } else {
-      TC acc = cvt<TC>(sc[j]) * xs[row * R + r];
-      for (int e = 0; e < K; ++e) acc -= cvt<TC>(w[e * L + j]) * xs[(int)ci[e * L + j] * R + r];
-      xs[row * R + r] = acc;
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * gn;
+      *(i < nv ? dst + i : dummy) = v[u];
     }
   }
 }
 
-// A whole sweep: stage as many consecutive level segments as fit into the
-// LDS buffer with 16-byte copies, run them from LDS, repeat.
-template <typename TS, typename TC, int KE, bool R1>
+// dummy: the kStageDummyBytes after the stage
+__device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, const uint8_t *src1, int bytes1,
+                                           uint8_t *stage, uint8_t *dummy, int gt, int gn) {
+  const int n0 = bytes0 >> 4, nv = n0 + (bytes1 >> 4);
+  const uint4 *s0 = reinterpret_cast<const uint4 *>(src0);
+  const uint4 *s1 = reinterpret_cast<const uint4 *>(src1);
+  uint4 *dst = reinterpret_cast<uint4 *>(stage);
+  uint4 *dm = reinterpret_cast<uint4 *>(dummy) + (threadIdx.x & 63);
+  if (nv <= 4 * gn)
+    stage_batch<4>(s0, n0, s1, nv, dst, dm, gt, gn);
+  else if (nv <= 8 * gn)
+    stage_batch<8>(s0, n0, s1, nv, dst, dm, gt, gn);
+  else
+    stage_batch<12>(s0, n0, s1, nv, dst, dm, gt, gn);
+}
+
+// A whole sweep of any width: stage as many consecutive level segments as
+// fit, solve them level by level with the whole workgroup, repeat.
+template <typename TS, typename TC>
 __device__ void sweep_staged(const uint8_t *data, const int32_t *lev, const int32_t *lvb, int nlev, int K,
-                             TC *xs, int R, int Rg, uint8_t *stage, int stage_bytes) {
+                             TC *xs, int XS, int Rg, uint8_t *stage, int stage_bytes) {
   int l0 = 0;
   while (l0 < nlev) {
     int l1 = l0 + 1;
     while (l1 < nlev && lvb[l1 + 1] - lvb[l0] <= stage_bytes) ++l1;
-    const int nv = (lvb[l1] - lvb[l0]) >> 4;
-    const uint4 *src = reinterpret_cast<const uint4 *>(data + lvb[l0]);
-    uint4 *dst = reinterpret_cast<uint4 *>(stage);
-    // U loads in flight per thread before their LDS stores.  Neither loads
-    // nor stores are predicated (loads clamp to the last vector, stores past
-    // the end go to the dummy slot dst[stage_bytes/16]), so the U loads
-    // issue as one batch.
-    constexpr int U = 12;
-    const int dummy = stage_bytes >> 4;
-    for (int i0 = threadIdx.x; i0 < nv; i0 += U * blockDim.x) {
-      uint4 v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = src[min(i0 + u * (int)blockDim.x, nv - 1)];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * blockDim.x;
-        dst[i < nv ? i : dummy] = v[u];
-      }
-    }
+    stage_copy(data + lvb[l0], lvb[l1] - lvb[l0], data, 0, stage, stage + stage_bytes, threadIdx.x, blockDim.x);
     __syncthreads();
     for (int l = l0; l < l1; ++l) {
-      level_from_lds<TS, TC, KE, R1>(stage + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], K, xs, R, Rg);
+      level_from_lds<TS, TC>(stage + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], K, xs, XS, Rg);
       __syncthreads();
     }
     l0 = l1;
   }
 }
 
-template <typename TS, typename TC, int KE, bool R1>
+// Fixed-width row records (see BlockDesc): KR int32 indices [row, columns,
+// pad] and KR scale/weights [sc, w, pad] per row, read as 16-byte vectors.
+template <int KR>
+struct RowIdx {
+  int v[KR];
+};
+
+template <int KR>
+__device__ __forceinline__ void load_ridx(const int32_t *ix, int j, RowIdx<KR> &r) {
+  const int4 *p = reinterpret_cast<const int4 *>(ix + j * KR);
+#pragma unroll
+  for (int q = 0; q < KR / 4; ++q) {
+    const int4 t = p[q];
+    r.v[4 * q] = t.x;
+    r.v[4 * q + 1] = t.y;
+    r.v[4 * q + 2] = t.z;
+    r.v[4 * q + 3] = t.w;
+  }
+}
+
+template <typename TS, int KR>
+__device__ __forceinline__ void load_rwts(const TS *wr, int j, TS (&w)[KR]) {
+  constexpr int per = 16 / (int)sizeof(TS);
+  const uint4 *p = reinterpret_cast<const uint4 *>(wr + j * KR);
+#pragma unroll
+  for (int q = 0; q < KR / per; ++q) {
+    const uint4 t = p[q];
+    __builtin_memcpy(&w[q * per], &t, 16);
+  }
+}
+
+// Levels [0, nl) of a staged chunk, one column xc, one wave.  Lane i of
+// mL / mOff holds the row count and stage offset of the chunk's level i.
+// Lane rows j = lane + 64u (u < NP) clamp to the level's last row: such a
+// lane recomputes that row from the same inputs and stores the same value,
+// so every pass is straight-line code.  Per level: the x gathers of all NP
+// passes together with their scale/weight records, then the next level's
+// index records (they do not depend on x), then the NP stores.  A wave's
+// LDS accesses take effect in program order and a level depends only on
+// earlier levels, so no barrier is needed.  Rows beyond 64 * NP (wider
+// levels) are solved after the passes.  Per row: x_row = sc x_row minus the
+// weighted columns in entry order.
+template <typename TS, typename TC, int KE, int NP>
+__device__ __forceinline__ void solve_chunk(const uint8_t *stage, int mL, int mOff, int nl, TC *xc, int lane) {
+  constexpr int KR = rec_width(KE);
+  RowIdx<KR> cur[NP];
+  {
+    const int L0 = __builtin_amdgcn_readlane(mL, 0);
+    const int32_t *ix = reinterpret_cast<const int32_t *>(stage + __builtin_amdgcn_readlane(mOff, 0));
+#pragma unroll
+    for (int u = 0; u < NP; ++u) load_ridx<KR>(ix, min(lane + 64 * u, L0 - 1), cur[u]);
+  }
+  for (int i = 0; i < nl; ++i) {
+    const int L = __builtin_amdgcn_readlane(mL, i);
+    const uint8_t *base = stage + __builtin_amdgcn_readlane(mOff, i);
+    const TS *wr = reinterpret_cast<const TS *>(base + 4 * KR * L);
+    TC xd[NP], xv[NP][KE];
+    TS wv[NP][KR];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      xd[u] = xc[cur[u].v[0]];
+#pragma unroll
+      for (int e = 0; e < KE; ++e) xv[u][e] = xc[cur[u].v[1 + e]];
+      load_rwts<TS, KR>(wr, min(lane + 64 * u, L - 1), wv[u]);
+    }
+    const int in = min(i + 1, nl - 1);
+    const int Ln = __builtin_amdgcn_readlane(mL, in);
+    const int32_t *ixn = reinterpret_cast<const int32_t *>(stage + __builtin_amdgcn_readlane(mOff, in));
+    RowIdx<KR> nxt[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) load_ridx<KR>(ixn, min(lane + 64 * u, Ln - 1), nxt[u]);
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      TC acc = cvt<TC>(wv[u][0]) * xd[u];
+#pragma unroll
+      for (int e = 0; e < KE; ++e) acc -= cvt<TC>(wv[u][1 + e]) * xv[u][e];
+      xc[cur[u].v[0]] = acc;
+    }
+    if (L > 64 * NP) {
+      const int32_t *ix = reinterpret_cast<const int32_t *>(base);
+      for (int j = lane + 64 * NP; j < L; j += 64) {
+        RowIdx<KR> r;
+        TS w[KR];
+        load_ridx<KR>(ix, j, r);
+        load_rwts<TS, KR>(wr, j, w);
+        TC acc = cvt<TC>(w[0]) * xc[r.v[0]];
+#pragma unroll
+        for (int e = 0; e < KE; ++e) acc -= cvt<TC>(w[1 + e]) * xc[r.v[1 + e]];
+        xc[r.v[0]] = acc;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) cur[u] = nxt[u];
+  }
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Levels [l0, l1) of one fixed-width sweep staged at sbase (level l's
+// segment at sbase + lvb[l] - lvb[l0], at most 64 levels), column xc, one
+// wave: lane i holds the row count and stage offset of level l0 + i, and
+// the chunk runs with as many row passes per lane as its widest level
+// needs (at most NPMAX, the rest in a tail loop).
+template <typename TS, typename TC, int KE>
+__device__ __forceinline__ void solve_staged(const uint8_t *sbase, const int32_t *lev, const int32_t *lvb, int l0,
+                                             int l1, TC *xc, int lane) {
+  constexpr int NPMAX = KE <= 2 ? 4 : (KE == 3 ? 3 : 2);
+  const int li = min(l0 + lane, l1 - 1);
+  const int mL = lev[li + 1] - lev[li];
+  const int mOff = lvb[li] - lvb[l0];
+  const int np = min(NPMAX, (wave_max_int(mL) + 63) >> 6);
+  switch (np) {
+    case 1: solve_chunk<TS, TC, KE, 1>(sbase, mL, mOff, l1 - l0, xc, lane); break;
+    case 2: solve_chunk<TS, TC, KE, 2>(sbase, mL, mOff, l1 - l0, xc, lane); break;
+    case 3:
+      if constexpr (NPMAX >= 3) solve_chunk<TS, TC, KE, 3>(sbase, mL, mOff, l1 - l0, xc, lane);
+      break;
+    default:
+      if constexpr (NPMAX >= 4) solve_chunk<TS, TC, KE, 4>(sbase, mL, mOff, l1 - l0, xc, lane);
+      break;
+  }
+}
+
+// Both fixed-width sweeps of one subdomain, one wave per right-hand side
+// column (wave w < Rg solves column w; its backward sweep follows its own
+// forward sweep, so the columns need no barrier between them).  The two
+// packed streams are cut into chunks of consecutive levels of one sweep
+// (at most 64 levels, fitting half the stage) and double-buffered: while the
+// solver waves run chunk c from one half, the other waves copy chunk c + 1
+// into the other half; a barrier separates the rounds.  When every wave
+// solves (Rg == waves) the copy runs after the solve instead.
+template <typename TS, typename TC, int KE>
+__device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int32_t *levf, const int32_t *lvbf,
+                                                 int fn, const uint8_t *bdata, const int32_t *levb,
+                                                 const int32_t *lvbb, int bn, TC *xs, int XS, int Rg,
+                                                 uint8_t *stage, int stage_bytes) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int half = (stage_bytes >> 1) & ~15;
+  uint8_t *dummy = stage + stage_bytes;
+  const bool stagers = Rg < nw;
+  auto chunk_end = [&](int sw, int l0) {
+    const int32_t *lvb = sw ? lvbb : lvbf;
+    const int nlev = sw ? bn : fn;
+    int l1 = l0 + 1;
+    while (l1 < nlev && l1 - l0 < 64 && lvb[l1 + 1] - lvb[l0] <= half) ++l1;
+    return l1;
+  };
+  auto copy_chunk = [&](int sw, int l0, int l1, uint8_t *dst, int gt, int gn) {
+    const int32_t *lvb = sw ? lvbb : lvbf;
+    const uint8_t *data = sw ? bdata : fdata;
+    stage_copy(data + lvb[l0], lvb[l1] - lvb[l0], data, 0, dst, dummy, gt, gn);
+  };
+  int sw = fn > 0 ? 0 : 1;
+  if (sw == 1 && bn == 0) return;
+  int l0 = 0, l1 = chunk_end(sw, 0), b = 0;
+  copy_chunk(sw, l0, l1, stage, threadIdx.x, blockDim.x);
+  __syncthreads();
+  while (true) {
+    int ns = sw, nl0 = l1;
+    if (nl0 >= (sw ? bn : fn)) {
+      ns = sw + 1;
+      nl0 = 0;
+      if (ns == 1 && bn == 0) ns = 2;
+    }
+    const bool more = ns < 2;
+    const int nl1 = more ? chunk_end(ns, nl0) : 0;
+    uint8_t *cur = stage + b * half, *nxt = stage + (b ^ 1) * half;
+    if (wv < Rg) {
+      for (int r = wv; r < Rg; r += nw)
+        solve_staged<TS, TC, KE>(cur, sw ? levb : levf, sw ? lvbb : lvbf, l0, l1, xs + r * XS, lane);
+    } else if (more) {
+      copy_chunk(ns, nl0, nl1, nxt, threadIdx.x - Rg * 64, blockDim.x - Rg * 64);
+    }
+    __syncthreads();
+    if (!more) break;
+    if (!stagers) {
+      copy_chunk(ns, nl0, nl1, nxt, threadIdx.x, blockDim.x);
+      __syncthreads();
+    }
+    sw = ns;
+    l0 = nl0;
+    l1 = nl1;
+    b ^= 1;
+  }
+}
+
+// One launch: for subdomain blockIdx.x and right-hand sides
+// [blockIdx.y * R, +Rg): prologue (f, E y) into LDS, forward and backward
+// sweeps in LDS, then u and the E^T epilogue.  KE > 0: every packed row has
+// exactly KE entries (padding has w = 0) and the sweeps run one wave per
+// column; KE == 0: any width, whole-workgroup levels.
+template <typename TS, typename TC, int KE>
 __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BlockDesc d = B.desc[blockIdx.x];
@@ -189,14 +385,16 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   const int c0 = blockIdx.y * R;
   const int Rg = min(R, a.nrhs - c0);
   const int m = d.m;
-  // LDS: [stage + 16 dummy bytes][x: max_m*R + 1 TC][levptr f, b][lvb f, b]
+  const int XS = B.max_m;
+  // LDS: [stage][dummy slots][x: XS*R + 1 TC][levptr f, b][lvb f, b]
   uint8_t *stage = smem;
-  TC *xs = reinterpret_cast<TC *>(smem + a.stage_bytes + 16);
-  int32_t *levf = reinterpret_cast<int32_t *>(smem + a.stage_bytes + 16 + pad16((int)sizeof(TC) * (B.max_m * R + 1)));
+  TC *xs = reinterpret_cast<TC *>(smem + a.stage_bytes + kStageDummyBytes);
+  int32_t *levf = reinterpret_cast<int32_t *>(smem + a.stage_bytes + kStageDummyBytes + pad16((int)sizeof(TC) * (XS * R + 1)));
   int32_t *levb = levf + B.max_lev + 1;
   int32_t *lvbf = levb + B.max_lev + 1;
   int32_t *lvbb = lvbf + B.max_lev + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
+  TC *xdummy = reinterpret_cast<TC *>(stage + a.stage_bytes) + (tid & 63);
   for (int i = tid; i <= d.f_nlev; i += nt) {
     levf[i] = B.lev[d.f_lev + i];
     lvbf[i] = B.lvb[d.f_lvb + i];
@@ -225,7 +423,7 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
       const int t = t0 + u * nt;
       const int tt = min(t, mt - 1);
       const int r = tt / m, row = tt - r * m;
-      xs[t < mt ? row * R + r : B.max_m * R] = (TC)v[u];   // past the end: dummy slot
+      *(t < mt ? xs + r * XS + row : xdummy) = (TC)v[u];   // past the end: the lane's dummy slot
     }
   }
   __syncthreads();
@@ -240,16 +438,21 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
         const int64_t x = d.e_ent + (int64_t)e * en + i;
         acc += cvt<TC>(B.e_val[x]) * (TC)yc[B.e_q[x]];
       }
-      xs[row * R + r] += (TC)a.b_y * acc;
+      xs[r * XS + row] += (TC)a.b_y * acc;
     }
     __syncthreads();
   }
-  sweep_staged<TS, TC, KE, R1>(B.data + d.f_data, levf, lvbf, d.f_nlev, d.f_K, xs, R, Rg, stage, a.stage_bytes);
-  sweep_staged<TS, TC, KE, R1>(B.data + d.b_data, levb, lvbb, d.b_nlev, d.b_K, xs, R, Rg, stage, a.stage_bytes);
+  if constexpr (KE > 0) {
+    sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, d.f_nlev, B.data + d.b_data, levb, lvbb, d.b_nlev,
+                                 xs, XS, Rg, stage, a.stage_bytes);
+  } else {
+    sweep_staged<TS, TC>(B.data + d.f_data, levf, lvbf, d.f_nlev, d.f_K, xs, XS, Rg, stage, a.stage_bytes);
+    sweep_staged<TS, TC>(B.data + d.b_data, levb, lvbb, d.b_nlev, d.b_K, xs, XS, Rg, stage, a.stage_bytes);
+  }
   if (a.u) {
     for (int t = tid; t < m * Rg; t += nt) {
       const int r = t / m, row = t - r * m;
-      a.u[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldu] = (double)xs[row * R + r];
+      a.u[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldu] = (double)xs[r * XS + row];
     }
   }
   if (a.gout) {
@@ -260,7 +463,7 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
       TC acc = 0;
       for (int e = 0; e < d.t_K; ++e) {
         const int64_t x = d.t_ent + (int64_t)e * tn + i;
-        acc += cvt<TC>(B.t_val[x]) * xs[(int)B.t_j[x] * R + r];
+        acc += cvt<TC>(B.t_val[x]) * xs[r * XS + (int)B.t_j[x]];
       }
       const double gv = a.c_g != 0.0 ? a.c_g * a.g[q + (int64_t)(c0 + r) * a.ldg] : 0.0;
       a.gout[q + (int64_t)(c0 + r) * a.ldgo] = gv + a.d_t * (double)acc;
@@ -268,26 +471,17 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   }
 }
 
-template <typename TS, typename TC, int KE, bool R1>
-void launch_bsolve_t(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
+template <typename TS, typename TC, int KE>
+void launch_bsolve_k(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
                      hipStream_t st) {
   static size_t attr_bytes = 0;
   if (lds_bytes > 65536 && lds_bytes > attr_bytes) {
-    (void)hipFuncSetAttribute((const void *)k_bsolve<TS, TC, KE, R1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_bsolve<TS, TC, KE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_bytes);
     attr_bytes = lds_bytes;
   }
   dim3 grid(p, (a.nrhs + a.R - 1) / a.R);
-  hipLaunchKernelGGL((k_bsolve<TS, TC, KE, R1>), grid, dim3(threads), lds_bytes, st, B, a);
-}
-
-template <typename TS, typename TC, int KE>
-void launch_bsolve_k(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
-                     hipStream_t st) {
-  if (a.R == 1)
-    launch_bsolve_t<TS, TC, KE, true>(B, p, a, threads, lds_bytes, st);
-  else
-    launch_bsolve_t<TS, TC, KE, false>(B, p, a, threads, lds_bytes, st);
+  hipLaunchKernelGGL((k_bsolve<TS, TC, KE>), grid, dim3(threads), lds_bytes, st, B, a);
 }
 
 // B.pack_K > 0: every packed row has exactly pack_K entries
