@@ -467,6 +467,22 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   return finish_lowrank(c, st);
 }
 
+// Fixed-width sweeps: levels wider than 64 * rec_passes(K) rows are cut into
+// consecutive sub-levels of at most that many rows (the rows of a level are
+// independent, so the schedule stays valid and the arithmetic unchanged).
+Sweep split_levels(const Sweep &sw, int32_t Kfix) {
+  Sweep out = sw;
+  if (Kfix <= 0) return out;
+  const int32_t cap = 64 * rec_passes(Kfix);
+  out.levptr.assign(1, 0);
+  for (int32_t l = 0; l < sw.nlev; ++l)
+    for (int32_t a = sw.levptr[l]; a < sw.levptr[l + 1]; a += cap)
+      out.levptr.push_back(std::min(a + cap, sw.levptr[l + 1]));
+  out.nlev = (int32_t)out.levptr.size() - 1;
+  if (sw.levptr.empty()) out.levptr.clear();
+  return out;
+}
+
 // Pack one sweep of one subdomain as the level-sliced byte stream the B
 // kernel stages into LDS (layouts documented with BlockDesc): row records
 // when every row has the fixed width Kfix > 0, else the ELL form.
@@ -552,19 +568,20 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
     d.m = b.m;
     if (b.m > 65535) ok = false;   // uint16 local indices
     max_m = std::max(max_m, b.m);
-    max_lev = std::max({max_lev, b.fwd.nlev, b.bwd.nlev});
-    d.f_nlev = b.fwd.nlev;
+    const Sweep fs = split_levels(b.fwd, Kfix), bs = split_levels(b.bwd, Kfix);
+    max_lev = std::max({max_lev, fs.nlev, bs.nlev});
+    d.f_nlev = fs.nlev;
     d.f_lev = (int32_t)lev.size();
-    lev.insert(lev.end(), b.fwd.levptr.begin(), b.fwd.levptr.end());
-    if (b.fwd.levptr.empty()) lev.push_back(0);
+    lev.insert(lev.end(), fs.levptr.begin(), fs.levptr.end());
+    if (fs.levptr.empty()) lev.push_back(0);
     d.f_lvb = (int32_t)lvb.size();
-    pack_sweep<TS>(b.fwd, Kfix, data, lvb, d.f_K, max_lb, d.f_data);
-    d.b_nlev = b.bwd.nlev;
+    pack_sweep<TS>(fs, Kfix, data, lvb, d.f_K, max_lb, d.f_data);
+    d.b_nlev = bs.nlev;
     d.b_lev = (int32_t)lev.size();
-    lev.insert(lev.end(), b.bwd.levptr.begin(), b.bwd.levptr.end());
-    if (b.bwd.levptr.empty()) lev.push_back(0);
+    lev.insert(lev.end(), bs.levptr.begin(), bs.levptr.end());
+    if (bs.levptr.empty()) lev.push_back(0);
     d.b_lvb = (int32_t)lvb.size();
-    pack_sweep<TS>(b.bwd, Kfix, data, lvb, d.b_K, max_lb, d.b_data);
+    pack_sweep<TS>(bs, Kfix, data, lvb, d.b_K, max_lb, d.b_data);
     max_K = std::max({max_K, d.f_K, d.b_K});
     // E rows as ELL (width = longest row)
     d.e_row = (int32_t)e_row.size();

@@ -17,8 +17,9 @@ namespace slr {
 // of level l's segment (lvb[nlev] = total bytes).  For level l with L rows:
 //
 // Fixed width K (every row of every sweep padded to the problem's widest
-// row K <= 4; padding has w = 0 and points at the row itself), row records
-// of KR = rec_width(K) entries:
+// row K <= 4; padding has w = 0 and points at the row itself; levels wider
+// than 64 * rec_passes(K) rows split), row records of KR = rec_width(K)
+// entries:
 //     idx   int32[L][KR]       [row, c_0, .., c_{K-1}, pad]  local indices
 //     wts   TS[L][KR]          [sc, w_0, .., w_{K-1}, pad]   scale, weights
 // Any width K (the sweep's widest row), ELL form:
@@ -86,6 +87,12 @@ constexpr int kStageDummyBytes = 1024;
 // Entries of a fixed-width row record: the row plus K columns, rounded up to
 // a multiple of 4 so that records are whole 16-byte vectors.
 __host__ __device__ constexpr int rec_width(int K) { return (K + 1 + 3) & ~3; }
+
+// Row passes per lane the fixed-width sweep kernel unrolls for rows of width
+// K (bounded by registers); the host splits wider levels into consecutive
+// sub-levels of at most 64 * rec_passes(K) rows (rows of one level are
+// independent, so any split of a level is a valid schedule).
+__host__ __device__ constexpr int rec_passes(int K) { return K <= 2 ? 4 : (K == 3 ? 3 : 2); }
 
 struct BArgs {
   const double *f = nullptr;  int64_t ldf = 0;  double a_f = 0.0;

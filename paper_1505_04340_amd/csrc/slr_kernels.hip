@@ -213,41 +213,43 @@ __device__ __forceinline__ void load_rwts(const TS *wr, int j, TS (&w)[KR]) {
   }
 }
 
-// Levels [0, nl) of a staged chunk, one column xc, one wave.  Lane i of
-// mL / mOff holds the row count and stage offset of the chunk's level i.
-// Lane rows j = lane + 64u (u < NP) clamp to the level's last row: such a
-// lane recomputes that row from the same inputs and stores the same value,
-// so every pass is straight-line code.  Per level: the x gathers of all NP
+// Levels [s, e) of a staged chunk, one column xc, one wave; lane i of mL /
+// mOff holds the row count and stage offset of the chunk's level i, and
+// every level in the range has at most 64 * NP rows.  Lane rows
+// j = lane + 64u (u < NP) clamp to the level's last row: such a lane
+// recomputes that row from the same inputs and stores the same value, so
+// every pass is straight-line code.  Per level: the x gathers of all NP
 // passes together with their scale/weight records, then the next level's
 // index records (they do not depend on x), then the NP stores.  A wave's
 // LDS accesses take effect in program order and a level depends only on
-// earlier levels, so no barrier is needed.  Rows beyond 64 * NP (wider
-// levels) are solved after the passes.  Per row: x_row = sc x_row minus the
-// weighted columns in entry order.
+// earlier levels, so no barrier is needed.  Per row: x_row = sc x_row minus
+// the weighted columns in entry order.
 template <typename TS, typename TC, int KE, int NP>
-__device__ __forceinline__ void solve_chunk(const uint8_t *stage, int mL, int mOff, int nl, TC *xc, int lane) {
+__device__ __forceinline__ void solve_chunk(const uint8_t *stage, int mL, int mOff, int s, int e, TC *xc,
+                                            int lane) {
   constexpr int KR = rec_width(KE);
+  s = __builtin_amdgcn_readfirstlane(s);
+  e = __builtin_amdgcn_readfirstlane(e);
   RowIdx<KR> cur[NP];
   {
-    const int L0 = __builtin_amdgcn_readlane(mL, 0);
-    const int32_t *ix = reinterpret_cast<const int32_t *>(stage + __builtin_amdgcn_readlane(mOff, 0));
+    const int L0 = __builtin_amdgcn_readlane(mL, s);
+    const int32_t *ix = reinterpret_cast<const int32_t *>(stage + __builtin_amdgcn_readlane(mOff, s));
 #pragma unroll
     for (int u = 0; u < NP; ++u) load_ridx<KR>(ix, min(lane + 64 * u, L0 - 1), cur[u]);
   }
-  for (int i = 0; i < nl; ++i) {
+  for (int i = s; i < e; ++i) {
     const int L = __builtin_amdgcn_readlane(mL, i);
-    const uint8_t *base = stage + __builtin_amdgcn_readlane(mOff, i);
-    const TS *wr = reinterpret_cast<const TS *>(base + 4 * KR * L);
+    const TS *wr = reinterpret_cast<const TS *>(stage + __builtin_amdgcn_readlane(mOff, i) + 4 * KR * L);
     TC xd[NP], xv[NP][KE];
     TS wv[NP][KR];
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       xd[u] = xc[cur[u].v[0]];
 #pragma unroll
-      for (int e = 0; e < KE; ++e) xv[u][e] = xc[cur[u].v[1 + e]];
+      for (int k = 0; k < KE; ++k) xv[u][k] = xc[cur[u].v[1 + k]];
       load_rwts<TS, KR>(wr, min(lane + 64 * u, L - 1), wv[u]);
     }
-    const int in = min(i + 1, nl - 1);
+    const int in = i + 1 < e ? i + 1 : i;
     const int Ln = __builtin_amdgcn_readlane(mL, in);
     const int32_t *ixn = reinterpret_cast<const int32_t *>(stage + __builtin_amdgcn_readlane(mOff, in));
     RowIdx<KR> nxt[NP];
@@ -257,55 +259,44 @@ __device__ __forceinline__ void solve_chunk(const uint8_t *stage, int mL, int mO
     for (int u = 0; u < NP; ++u) {
       TC acc = cvt<TC>(wv[u][0]) * xd[u];
 #pragma unroll
-      for (int e = 0; e < KE; ++e) acc -= cvt<TC>(wv[u][1 + e]) * xv[u][e];
+      for (int k = 0; k < KE; ++k) acc -= cvt<TC>(wv[u][1 + k]) * xv[u][k];
       xc[cur[u].v[0]] = acc;
-    }
-    if (L > 64 * NP) {
-      const int32_t *ix = reinterpret_cast<const int32_t *>(base);
-      for (int j = lane + 64 * NP; j < L; j += 64) {
-        RowIdx<KR> r;
-        TS w[KR];
-        load_ridx<KR>(ix, j, r);
-        load_rwts<TS, KR>(wr, j, w);
-        TC acc = cvt<TC>(w[0]) * xc[r.v[0]];
-#pragma unroll
-        for (int e = 0; e < KE; ++e) acc -= cvt<TC>(w[1 + e]) * xc[r.v[1 + e]];
-        xc[r.v[0]] = acc;
-      }
     }
 #pragma unroll
     for (int u = 0; u < NP; ++u) cur[u] = nxt[u];
   }
 }
 
-__device__ __forceinline__ int wave_max_int(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 // Levels [l0, l1) of one fixed-width sweep staged at sbase (level l's
 // segment at sbase + lvb[l] - lvb[l0], at most 64 levels), column xc, one
-// wave: lane i holds the row count and stage offset of level l0 + i, and
-// the chunk runs with as many row passes per lane as its widest level
-// needs (at most NPMAX, the rest in a tail loop).
+// wave.  Lane i holds the row count and stage offset of level l0 + i; the
+// levels run in maximal stretches that need the same number of row passes
+// per lane (levels are at most 64 * rec_passes(KE) rows wide).
 template <typename TS, typename TC, int KE>
 __device__ __forceinline__ void solve_staged(const uint8_t *sbase, const int32_t *lev, const int32_t *lvb, int l0,
                                              int l1, TC *xc, int lane) {
-  constexpr int NPMAX = KE <= 2 ? 4 : (KE == 3 ? 3 : 2);
+  constexpr int NPMAX = rec_passes(KE);
+  const int nl = l1 - l0;
   const int li = min(l0 + lane, l1 - 1);
   const int mL = lev[li + 1] - lev[li];
   const int mOff = lvb[li] - lvb[l0];
-  const int np = min(NPMAX, (wave_max_int(mL) + 63) >> 6);
-  switch (np) {
-    case 1: solve_chunk<TS, TC, KE, 1>(sbase, mL, mOff, l1 - l0, xc, lane); break;
-    case 2: solve_chunk<TS, TC, KE, 2>(sbase, mL, mOff, l1 - l0, xc, lane); break;
-    case 3:
-      if constexpr (NPMAX >= 3) solve_chunk<TS, TC, KE, 3>(sbase, mL, mOff, l1 - l0, xc, lane);
-      break;
-    default:
-      if constexpr (NPMAX >= 4) solve_chunk<TS, TC, KE, 4>(sbase, mL, mOff, l1 - l0, xc, lane);
-      break;
+  const int npl = (mL + 63) >> 6;
+  int s = 0;
+  while (s < nl) {
+    const int np = __builtin_amdgcn_readlane(npl, s);
+    const unsigned long long other = __ballot(lane > s && lane < nl && npl != np);
+    const int e = other ? __ffsll(other) - 1 : nl;
+    if (np <= 1)
+      solve_chunk<TS, TC, KE, 1>(sbase, mL, mOff, s, e, xc, lane);
+    else if (np == 2)
+      solve_chunk<TS, TC, KE, 2>(sbase, mL, mOff, s, e, xc, lane);
+    else if constexpr (NPMAX >= 3) {
+      if (np == 3)
+        solve_chunk<TS, TC, KE, 3>(sbase, mL, mOff, s, e, xc, lane);
+      else if constexpr (NPMAX >= 4)
+        solve_chunk<TS, TC, KE, 4>(sbase, mL, mOff, s, e, xc, lane);
+    }
+    s = e;
   }
 }
 
