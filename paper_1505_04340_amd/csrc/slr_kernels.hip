@@ -300,6 +300,22 @@ __device__ __forceinline__ void solve_staged(const uint8_t *sbase, const int32_t
   }
 }
 
+// The first chunk of a fixed-width sweep (the chunk sweeps_pipelined
+// starts with: levels [0, l1) fitting `half` bytes, at most 64 levels),
+// read straight from the global level offsets glvb, copied by the threads
+// gt = 0 .. gn-1 of a group of whole waves.
+__device__ __forceinline__ void stage_first(const uint8_t *data, const int32_t *glvb, int nlev, int half,
+                                            uint8_t *stage, uint8_t *dummy, int gt, int gn) {
+  const int lane = threadIdx.x & 63;
+  const int cand = 1 + lane;
+  const int b0 = glvb[0];
+  const int v = glvb[min(cand, nlev)];
+  const bool ok = cand <= nlev && (lane == 0 || v - b0 <= half);
+  const int l1 = (int)__popcll(__ballot(ok));
+  const int b1 = __builtin_amdgcn_readlane(v, l1 - 1);
+  stage_copy(data + b0, b1 - b0, data, 0, stage, dummy, gt, gn);
+}
+
 // Both fixed-width sweeps of one subdomain, one wave per right-hand side
 // column (wave w < Rg solves column w; its backward sweep follows its own
 // forward sweep, so the columns need no barrier between them).  The two
@@ -307,22 +323,26 @@ __device__ __forceinline__ void solve_staged(const uint8_t *sbase, const int32_t
 // (at most 64 levels, fitting half the stage) and double-buffered: while the
 // solver waves run chunk c from one half, the other waves copy chunk c + 1
 // into the other half; a barrier separates the rounds.  When every wave
-// solves (Rg == waves) the copy runs after the solve instead.
+// solves (Rg == waves) the copy runs after the solve instead.  staged0: the
+// first chunk is already in the first half (stage_first, before a barrier).
 template <typename TS, typename TC, int KE>
 __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int32_t *levf, const int32_t *lvbf,
                                                  int fn, const uint8_t *bdata, const int32_t *levb,
                                                  const int32_t *lvbb, int bn, TC *xs, int XS, int Rg,
-                                                 uint8_t *stage, int stage_bytes) {
+                                                 uint8_t *stage, int stage_bytes, bool staged0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int half = (stage_bytes >> 1) & ~15;
   uint8_t *dummy = stage + stage_bytes;
   const bool stagers = Rg < nw;
+  // end of the chunk starting at level l0: the largest l1 <= l0 + 64 with
+  // levels [l0, l1) fitting half the stage (at least one level); lane i
+  // tests l1 = l0 + 1 + i (the test is monotone in l1)
   auto chunk_end = [&](int sw, int l0) {
     const int32_t *lvb = sw ? lvbb : lvbf;
     const int nlev = sw ? bn : fn;
-    int l1 = l0 + 1;
-    while (l1 < nlev && l1 - l0 < 64 && lvb[l1 + 1] - lvb[l0] <= half) ++l1;
-    return l1;
+    const int cand = l0 + 1 + lane;
+    const bool ok = cand <= nlev && (lane == 0 || lvb[min(cand, nlev)] - lvb[l0] <= half);
+    return l0 + (int)__popcll(__ballot(ok));
   };
   auto copy_chunk = [&](int sw, int l0, int l1, uint8_t *dst, int gt, int gn) {
     const int32_t *lvb = sw ? lvbb : lvbf;
@@ -332,8 +352,10 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
   int sw = fn > 0 ? 0 : 1;
   if (sw == 1 && bn == 0) return;
   int l0 = 0, l1 = chunk_end(sw, 0), b = 0;
-  copy_chunk(sw, l0, l1, stage, threadIdx.x, blockDim.x);
-  __syncthreads();
+  if (!staged0) {
+    copy_chunk(sw, l0, l1, stage, threadIdx.x, blockDim.x);
+    __syncthreads();
+  }
   while (true) {
     int ns = sw, nl0 = l1;
     if (nl0 >= (sw ? bn : fn)) {
@@ -386,36 +408,53 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   int32_t *lvbb = lvbf + B.max_lev + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
   TC *xdummy = reinterpret_cast<TC *>(stage + a.stage_bytes) + (tid & 63);
-  for (int i = tid; i <= d.f_nlev; i += nt) {
-    levf[i] = B.lev[d.f_lev + i];
-    lvbf[i] = B.lvb[d.f_lvb + i];
-  }
-  for (int i = tid; i <= d.b_nlev; i += nt) {
-    levb[i] = B.lev[d.b_lev + i];
-    lvbb[i] = B.lvb[d.b_lvb + i];
-  }
-  // prologue: rhs = a_f f_i + b_y E_i y  (loads batched 4 per thread)
-  const int mt = m * Rg;
-  for (int t0 = tid; t0 < mt; t0 += 4 * nt) {
-    double v[4];
-    if (a.a_f != 0.0) {
+  // level pointers into LDS, then rhs = a_f f_i (loads batched 4 per
+  // thread), by the threads gt = 0 .. gn-1
+  auto prologue = [&](int gt, int gn) {
+    for (int i = gt; i <= d.f_nlev; i += gn) {
+      levf[i] = B.lev[d.f_lev + i];
+      lvbf[i] = B.lvb[d.f_lvb + i];
+    }
+    for (int i = gt; i <= d.b_nlev; i += gn) {
+      levb[i] = B.lev[d.b_lev + i];
+      lvbb[i] = B.lvb[d.b_lvb + i];
+    }
+    const int mt = m * Rg;
+    for (int t0 = gt; t0 < mt; t0 += 4 * gn) {
+      double v[4];
+      if (a.a_f != 0.0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = min(t0 + u * gn, mt - 1);
+          const int r = t / m, row = t - r * m;
+          v[u] = a.a_f * a.f[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldf];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = 0.0;
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int t = min(t0 + u * nt, mt - 1);
-        const int r = t / m, row = t - r * m;
-        v[u] = a.a_f * a.f[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldf];
+        const int t = t0 + u * gn;
+        const int tt = min(t, mt - 1);
+        const int r = tt / m, row = tt - r * m;
+        *(t < mt ? xs + r * XS + row : xdummy) = (TC)v[u];   // past the end: the lane's dummy slot
       }
+    }
+  };
+  if constexpr (KE > 0) {
+    // the upper half of the waves stages the first sweep chunk meanwhile
+    if (tid >= nt / 2) {
+      const int sw0 = d.f_nlev > 0 ? 0 : 1;
+      if (sw0 == 0 || d.b_nlev > 0)
+        stage_first(B.data + (sw0 ? d.b_data : d.f_data), B.lvb + (sw0 ? d.b_lvb : d.f_lvb),
+                    sw0 ? d.b_nlev : d.f_nlev, (a.stage_bytes >> 1) & ~15, stage, stage + a.stage_bytes,
+                    tid - nt / 2, nt - nt / 2);
     } else {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = 0.0;
+      prologue(tid, nt / 2);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = t0 + u * nt;
-      const int tt = min(t, mt - 1);
-      const int r = tt / m, row = tt - r * m;
-      *(t < mt ? xs + r * XS + row : xdummy) = (TC)v[u];   // past the end: the lane's dummy slot
-    }
+  } else {
+    prologue(tid, nt);
   }
   __syncthreads();
   if (a.b_y != 0.0 && d.e_n > 0) {
@@ -435,7 +474,7 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   }
   if constexpr (KE > 0) {
     sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, d.f_nlev, B.data + d.b_data, levb, lvbb, d.b_nlev,
-                                 xs, XS, Rg, stage, a.stage_bytes);
+                                 xs, XS, Rg, stage, a.stage_bytes, true);
   } else {
     sweep_staged<TS, TC>(B.data + d.f_data, levf, lvbf, d.f_nlev, d.f_K, xs, XS, Rg, stage, a.stage_bytes);
     sweep_staged<TS, TC>(B.data + d.b_data, levb, lvbb, d.b_nlev, d.b_K, xs, XS, Rg, stage, a.stage_bytes);
