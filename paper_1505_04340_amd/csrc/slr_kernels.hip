@@ -45,6 +45,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;  // valid in lane 0
 }
 
+// sum over the wave, valid in every lane
+__device__ __forceinline__ double wave_allsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Sum over the block (blockDim multiple of 64, <= 1024); result in thread 0.
 __device__ double block_sum(double v, double *sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1446,72 +1452,108 @@ void launch_div_scalar(int64_t n, const double *w, double *v, const double *scal
 constexpr int EIG_MAXM = 1024;
 constexpr int EIG_THREADS = 1024;
 
-// number of eigenvalues of T below x (Sturm count of the LDL^T of T - x I)
-__device__ __forceinline__ int sturm_count(const double *a, const double *b2, int m, double x, double pivmin) {
-  int cnt = 0;
-  double d = a[0] - x;
-  if (fabs(d) < pivmin) d = -pivmin;
-  cnt += d < 0.0;
-  for (int i = 1; i < m; ++i) {
-    d = a[i] - x - b2[i - 1] / d;
-    if (fabs(d) < pivmin) d = -pivmin;
-    cnt += d < 0.0;
-  }
-  return cnt;
+// Sturm counts (eigenvalues of T below x) at NPT points at once, from the
+// LDL^T pivots of T - x I: d_i = (a_i - x) - b_{i-1}^2 / d_{i-1}, a pivot
+// smaller than pivmin replaced by -pivmin.  The quotient uses the hardware
+// reciprocal refined by one Newton step (relative error of a few ulp,
+// which keeps each pivot backward stable); the NPT chains interleave.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, r, 1.0);
+  return fma(r, e, r);
 }
 
-// one inverse-iteration solve (T - lam I) x = x for vector t of K; factors
-// dl, dd, du, du2 and pivots in scratch with stride K (index i*K + t)
-__device__ void inv_iter(const double *a, const double *b, int m, double lam, double tiny, double *x, double *dl,
-                         double *dd, double *du, double *du2, double *piv, int K, int t) {
-  // factor
-  for (int i = 0; i < m; ++i) {
-    dd[i * K + t] = a[i] - lam;
-    if (i + 1 < m) {
-      dl[i * K + t] = b[i];
-      du[i * K + t] = b[i];
+template <int NPT>
+__device__ __forceinline__ void sturm_n(const double *a, const double *b2, int m, const double (&x)[NPT],
+                                        double pivmin, int (&c)[NPT]) {
+  double d[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    d[q] = a[0] - x[q];
+    if (fabs(d[q]) < pivmin) d[q] = -pivmin;
+    c[q] = d[q] < 0.0;
+  }
+  // a[i] and b2[i-1] are read one step ahead of their use
+  double an = a[min(1, m - 1)], bn = b2[0];
+  for (int i = 1; i < m; ++i) {
+    const double ai = an, bi = bn;
+    an = a[min(i + 1, m - 1)];
+    bn = b2[i];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      d[q] = fma(-bi, recip(d[q]), ai - x[q]);
+      if (fabs(d[q]) < pivmin) d[q] = -pivmin;
+      c[q] += d[q] < 0.0;
     }
   }
+}
+
+// One inverse-iteration solve (T - lam I) x <- x for column t of the
+// row-major m x K block X (entry i at X[i*K + t]): Gaussian elimination of
+// the tridiagonal with partial pivoting, the right-hand side eliminated
+// along the way; the current pivot row lives in registers and the finished
+// rows of U (diagonal, first and second superdiagonal, pivots below `tiny`
+// moved to +-tiny) go to F (3 per row, stride K).  Memory operands are read
+// one step ahead of the recurrence; quotients use the refined reciprocal.
+__device__ void inv_iter(const double *a, const double *b, int m, double lam, double tiny, double *X, double *F,
+                         int K, int t) {
+  double d = a[0] - lam;
+  double u = m > 1 ? b[0] : 0.0;
+  double xi = X[t];
+  double xnext = X[min(1, m - 1) * K + t];
+  auto guard = [&](double v) { return fabs(v) < tiny ? (v < 0.0 ? -tiny : tiny) : v; };
   for (int i = 0; i + 1 < m; ++i) {
-    const double di = dd[i * K + t], li = dl[i * K + t];
-    if (fabs(di) >= fabs(li)) {
-      const double f = di != 0.0 ? li / di : 0.0;
-      dl[i * K + t] = f;
-      dd[(i + 1) * K + t] -= f * du[i * K + t];
-      if (i + 2 < m) du2[i * K + t] = 0.0;
-      piv[i * K + t] = 0.0;
+    const double l = b[i];
+    double dn = a[i + 1] - lam;
+    double un = i + 2 < m ? b[i + 1] : 0.0;
+    double xn = xnext;
+    xnext = X[min(i + 2, m - 1) * K + t];
+    double r0, r1, r2, xo;
+    if (fabs(d) >= fabs(l)) {
+      const double f = d != 0.0 ? l * recip(d) : 0.0;
+      r0 = d;
+      r1 = u;
+      r2 = 0.0;
+      dn -= f * u;
+      xn -= f * xi;
+      xo = xi;
     } else {
-      const double f = di / li;
-      dd[i * K + t] = li;
-      dl[i * K + t] = f;
-      const double tmp = du[i * K + t];
-      du[i * K + t] = dd[(i + 1) * K + t];
-      dd[(i + 1) * K + t] = tmp - f * dd[(i + 1) * K + t];
-      if (i + 2 < m) {
-        du2[i * K + t] = du[(i + 1) * K + t];
-        du[(i + 1) * K + t] = -f * du[(i + 1) * K + t];
-      }
-      piv[i * K + t] = 1.0;
+      const double f = d * recip(l);
+      r0 = l;
+      r1 = dn;
+      r2 = un;
+      dn = u - f * dn;
+      un = -f * un;
+      xo = xn;
+      xn = xi - f * xn;
     }
+    F[(3 * i) * K + t] = guard(r0);
+    F[(3 * i + 1) * K + t] = r1;
+    F[(3 * i + 2) * K + t] = r2;
+    X[i * K + t] = xo;
+    d = dn;
+    u = un;
+    xi = xn;
   }
-  for (int i = 0; i < m; ++i)
-    if (fabs(dd[i * K + t]) < tiny) dd[i * K + t] = dd[i * K + t] < 0.0 ? -tiny : tiny;
-  // solve L U x = x
-  for (int i = 0; i + 1 < m; ++i) {
-    const double f = dl[i * K + t];
-    if (piv[i * K + t] == 0.0) {
-      x[(i + 1) * K + t] -= f * x[i * K + t];
-    } else {
-      const double xi = x[i * K + t];
-      x[i * K + t] = x[(i + 1) * K + t];
-      x[(i + 1) * K + t] = xi - f * x[(i + 1) * K + t];
-    }
+  // back substitution, last rows first
+  double x1 = xi * recip(guard(d));
+  X[(m - 1) * K + t] = x1;
+  double x2 = 0.0;
+  if (m < 2) return;
+  int i = m - 2;
+  double xv = X[i * K + t], f0 = F[(3 * i) * K + t], f1 = F[(3 * i + 1) * K + t], f2 = F[(3 * i + 2) * K + t];
+  for (; i >= 0; --i) {
+    const double cx = xv, c0 = f0, c1 = f1, c2 = f2;
+    const int ip = max(i - 1, 0);
+    xv = X[ip * K + t];
+    f0 = F[(3 * ip) * K + t];
+    f1 = F[(3 * ip + 1) * K + t];
+    f2 = F[(3 * ip + 2) * K + t];
+    const double v = (cx - c1 * x1 - c2 * x2) * recip(c0);
+    X[i * K + t] = v;
+    x2 = x1;
+    x1 = v;
   }
-  x[(m - 1) * K + t] /= dd[(m - 1) * K + t];
-  if (m > 1) x[(m - 2) * K + t] = (x[(m - 2) * K + t] - du[(m - 2) * K + t] * x[(m - 1) * K + t]) / dd[(m - 2) * K + t];
-  for (int i = m - 3; i >= 0; --i)
-    x[i * K + t] = (x[i * K + t] - du[i * K + t] * x[(i + 1) * K + t] - du2[i * K + t] * x[(i + 2) * K + t]) /
-                   dd[i * K + t];
 }
 
 // scale column t of X (stride K) to unit norm
@@ -1523,7 +1565,8 @@ __device__ void unit_col(double *x, int m, int K, int t) {
 }
 
 // classical Gram-Schmidt twice over the K columns of X (stride K), in
-// column order; the whole workgroup cooperates (one wave per dot product)
+// column order; the whole workgroup cooperates (one wave per dot product).
+// h: K + 1 doubles of LDS.
 __device__ void cgs2_cols(double *x, int m, int K, double *h) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int j = 0; j < K; ++j) {
@@ -1547,102 +1590,240 @@ __device__ void cgs2_cols(double *x, int m, int K, double *h) {
     if (wid == 0) {
       for (int r = lane; r < m; r += 64) v += x[r * K + j] * x[r * K + j];
       v = wave_sum(v);
-      if (lane == 0) h[EIG_MAXM] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+      if (lane == 0) h[K] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
     }
     __syncthreads();
-    const double sc = h[EIG_MAXM];
+    const double sc = h[K];
     for (int r = threadIdx.x; r < m; r += blockDim.x) x[r * K + j] *= sc;
     __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(EIG_THREADS) k_tridiag_eig(int m, const double *alpha, const double *beta,
-                                                             double *scratch, double *eval, double *Y, int K,
-                                                             int *info) {
-  __shared__ double a[EIG_MAXM], b[EIG_MAXM], b2[EIG_MAXM], lam[EIG_MAXM];
-  __shared__ double h[EIG_MAXM + 1];
-  __shared__ double bounds[2];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < m; i += nt) {
+// Orthonormalise the K columns of the row-major m x K block W in column
+// order by Cholesky QR, twice: G = W^T W, G = R^T R (R upper triangular),
+// W <- W R^{-1}.  In exact arithmetic this is the Gram-Schmidt result; the
+// second pass restores orthogonality to working accuracy.  A column that
+// is (nearly) in the span of the earlier ones (Cholesky pivot below 1e-8 of
+// the column's squared norm) sends the block to Gram-Schmidt twice instead.
+// G: K*K doubles of LDS, h: K + 1, flag: one int of LDS.
+__device__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *flag) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (tid == 0) *flag = 0;
+    // Gram matrix, upper triangle by pairs (i <= j), mirrored
+    const int npair = K * (K + 1) / 2;
+    for (int p = tid; p < npair; p += nt) {
+      int i = 0, rem = p;
+      while (rem >= K - i) {
+        rem -= K - i;
+        ++i;
+      }
+      const int j = i + rem;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int r = 0;
+      for (; r + 3 < m; r += 4) {
+        s0 += W[r * K + i] * W[r * K + j];
+        s1 += W[(r + 1) * K + i] * W[(r + 1) * K + j];
+        s2 += W[(r + 2) * K + i] * W[(r + 2) * K + j];
+        s3 += W[(r + 3) * K + i] * W[(r + 3) * K + j];
+      }
+      for (; r < m; ++r) s0 += W[r * K + i] * W[r * K + j];
+      const double v = (s0 + s1) + (s2 + s3);
+      G[i * K + j] = v;
+      G[j * K + i] = v;
+    }
+    __syncthreads();
+    // Cholesky G = R^T R by wave 0, R in the upper triangle (row-major);
+    // the lower triangle keeps the Gram matrix for the pivot test
+    if (tid < 64) {
+      for (int j = 0; j < K; ++j) {
+        for (int l = j + lane; l < K; l += 64) {
+          double v = G[j * K + l];
+          for (int q = 0; q < j; ++q) v -= G[q * K + j] * G[q * K + l];
+          h[l] = v;
+        }
+        const double piv = h[j];
+        if (!(piv > 1e-8 * G[j * K + j]) || !(piv > 0.0)) {
+          if (lane == 0) *flag = 1;
+          break;
+        }
+        const double rs = 1.0 / sqrt(piv);
+        for (int l = j + lane; l < K; l += 64) G[j * K + l] = h[l] * rs;
+      }
+    }
+    __syncthreads();
+    if (*flag) break;
+    // W <- W R^{-1}, one row per thread
+    for (int r = tid; r < m; r += nt) {
+      for (int j = 0; j < K; ++j) {
+        double v = W[r * K + j];
+        for (int q = 0; q < j; ++q) v -= W[r * K + q] * G[q * K + j];
+        W[r * K + j] = v / G[j * K + j];
+      }
+    }
+    __syncthreads();
+  }
+  if (*flag) cgs2_cols(W, m, K, h);
+}
+
+// Eigenvalues and the K leading eigenvectors of the symmetric tridiagonal
+// T (diagonal alpha, off-diagonal beta), in three kernels:
+//   k_eig_bisect  one wave per eigenvalue (the t-th largest, descending
+//                 output): multisection, each lane evaluates the Sturm count
+//                 at one of 64 interior points, so the bracket shrinks
+//                 65-fold per step, down to a width of 2 ulp;
+//   k_eig_invit   one wave per wanted eigenvector: inverse iteration from a
+//                 fixed pseudo-random start (or the current vector), the
+//                 factorisation and the vector in LDS, unit norm after each
+//                 solve;
+//   k_eig_ortho   one workgroup: orthonormalisation of the m x K block in
+//                 column order (ortho_cols), to X or, at the end, to Y.
+// Sequence: bisect; invit x3; ortho; invit x1; ortho.
+__device__ __forceinline__ void gershgorin(const double *a, const double *b, int m, double &glo, double &ghi) {
+  const int lane = threadIdx.x & 63;
+  double lo = 1e300, hi = -1e300;
+  for (int i = lane; i < m; i += 64) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  glo = lo;
+  ghi = hi;
+}
+
+__global__ void __launch_bounds__(64) k_eig_bisect(int m, const double *alpha, const double *beta, double *eval) {
+  extern __shared__ double eig_lds[];
+  double *a = eig_lds, *b = a + m, *b2 = b + m;
+  const int lane = threadIdx.x, t = blockIdx.x;
+  for (int i = lane; i < m; i += 64) {
     a[i] = alpha[i];
     b[i] = (i + 1 < m) ? beta[i] : 0.0;
     b2[i] = b[i] * b[i];
   }
   __syncthreads();
-  if (tid == 0) {
-    double lo = a[0], hi = a[0];
-    for (int i = 0; i < m; ++i) {
-      const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
-      lo = fmin(lo, a[i] - r);
-      hi = fmax(hi, a[i] + r);
-    }
-    bounds[0] = lo;
-    bounds[1] = hi;
-  }
-  __syncthreads();
-  const double glo = bounds[0], ghi = bounds[1];
+  double glo, ghi;
+  gershgorin(a, b, m, glo, ghi);
   const double tnorm = fmax(fabs(glo), fabs(ghi));
   const double eps = 2.220446049250313e-16;
   const double pivmin = 1e-290 + eps * eps * tnorm * tnorm;
-  // (1) bisection: thread t finds the t-th largest (ascending index m-1-t)
-  for (int t = tid; t < m; t += nt) {
-    const int j = m - 1 - t;
-    double lo = glo - eps * tnorm - 1e-300, hi = ghi + eps * tnorm + 1e-300;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      if (hi - lo <= 2.0 * eps * (fabs(lo) + fabs(hi))) break;
-      if (sturm_count(a, b2, m, mid, pivmin) >= j + 1)
-        hi = mid;
-      else
-        lo = mid;
+  const int want = m - t;   // the t-th largest is the (m - t)-th smallest
+  double lo = glo - eps * tnorm - 1e-300, hi = ghi + eps * tnorm + 1e-300;
+  for (int it = 0; it < 100; ++it) {
+    const double w = hi - lo;
+    if (!(w > 2.0 * eps * (fabs(lo) + fabs(hi)))) break;
+    double x[1];
+    int c[1];
+    x[0] = lo + w * (double)(lane + 1) / 65.0;
+    sturm_n<1>(a, b2, m, x, pivmin, c);
+    // new bracket: the largest point with fewer than `want` eigenvalues
+    // below it, and the smallest point with at least `want`
+    double nlo = c[0] < want ? x[0] : lo;
+    double nhi = c[0] >= want ? x[0] : hi;
+    for (int o = 32; o > 0; o >>= 1) {
+      nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
+      nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
     }
-    const double v = 0.5 * (lo + hi);
-    lam[t] = v;
-    eval[t] = v;
+    if (!(nlo > lo || nhi < hi) || !(nlo < nhi)) break;   // no representable progress
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) eval[t] = 0.5 * (lo + hi);
+}
+
+// X: row-major m x K (column q at X[i*K + q]); eval descending
+__global__ void __launch_bounds__(64) k_eig_invit(int m, const double *alpha, const double *beta,
+                                                 const double *eval, double *X, int K, int iters, int init) {
+  extern __shared__ double eig_lds[];
+  double *a = eig_lds, *b = a + m, *x = b + m, *F = x + m;
+  const int lane = threadIdx.x, q = blockIdx.x;
+  for (int i = lane; i < m; i += 64) {
+    a[i] = alpha[i];
+    b[i] = (i + 1 < m) ? beta[i] : 0.0;
+    if (init) {
+      uint32_t z = (uint32_t)(i * 2654435761u) ^ (uint32_t)((q + 1) * 40503u);
+      z ^= z >> 15;
+      z *= 2246822519u;
+      z ^= z >> 13;
+      x[i] = 0.5 + (double)(z & 0xFFFF) / 65536.0;
+    } else {
+      x[i] = X[(size_t)i * K + q];
+    }
   }
   __syncthreads();
-  if (K > 0) {
-    double *X = scratch;
-    double *dl = X + (size_t)m * K, *dd = dl + (size_t)m * K, *du = dd + (size_t)m * K;
-    double *du2 = du + (size_t)m * K, *piv = du2 + (size_t)m * K;
-    const double tiny = eps * tnorm + 1e-300;
-    // (2) inverse iteration from a fixed pseudo-random start
-    if (tid < K) {
-      for (int i = 0; i < m; ++i) {
-        uint32_t z = (uint32_t)(i * 2654435761u) ^ (uint32_t)((tid + 1) * 40503u);
-        z ^= z >> 15;
-        z *= 2246822519u;
-        z ^= z >> 13;
-        X[i * K + tid] = 0.5 + (double)(z & 0xFFFF) / 65536.0;
-      }
-      for (int rep = 0; rep < 3; ++rep) {
-        inv_iter(a, b, m, lam[tid], tiny, X, dl, dd, du, du2, piv, K, tid);
-        unit_col(X, m, K, tid);
-      }
-    }
+  double glo, ghi;
+  gershgorin(a, b, m, glo, ghi);
+  const double tnorm = fmax(fabs(glo), fabs(ghi));
+  const double tiny = 2.220446049250313e-16 * tnorm + 1e-300;
+  const double lam = eval[q];
+  for (int rep = 0; rep < iters; ++rep) {
+    if (lane == 0) inv_iter(a, b, m, lam, tiny, x, F, 1, 0);
     __syncthreads();
-    // (3) orthonormalise / refine
-    for (int round = 0; round < 2; ++round) {
-      cgs2_cols(X, m, K, h);
-      if (tid < K) {
-        inv_iter(a, b, m, lam[tid], tiny, X, dl, dd, du, du2, piv, K, tid);
-        unit_col(X, m, K, tid);
-      }
-      __syncthreads();
-    }
-    cgs2_cols(X, m, K, h);
-    for (int t = tid; t < m * K; t += nt) {
-      const int i = t / K, q = t - i * K;
-      Y[i + (int64_t)q * m] = X[i * K + q];
-    }
+    double nr = 0.0;
+    for (int i = lane; i < m; i += 64) nr += x[i] * x[i];
+    nr = wave_allsum(nr);
+    const double sc = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+    for (int i = lane; i < m; i += 64) x[i] *= sc;
+    __syncthreads();
   }
-  if (tid == 0) *info = 0;
+  for (int i = lane; i < m; i += 64) X[(size_t)i * K + q] = x[i];
+}
+
+// orthonormalise X (row-major m x K); final: write Y (column-major m x K)
+__global__ void __launch_bounds__(EIG_THREADS) k_eig_ortho(int m, int K, double *X, double *Y, int xs_lds, int final_,
+                                                          int *info) {
+  extern __shared__ double eig_lds[];
+  double *h = eig_lds, *G = h + (K + 1), *xl = G + (size_t)K * K;
+  __shared__ int flag;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double *W = xs_lds ? xl : X;
+  if (xs_lds) {
+    for (int i = tid; i < m * K; i += nt) xl[i] = X[i];
+    __syncthreads();
+  }
+  ortho_cols(W, m, K, G, h, &flag);
+  if (final_) {
+    for (int i = tid; i < m * K; i += nt) {
+      const int r = i / K, q = i - r * K;
+      Y[r + (int64_t)q * m] = W[i];
+    }
+    if (tid == 0) *info = 0;
+  } else if (xs_lds) {
+    for (int i = tid; i < m * K; i += nt) X[i] = xl[i];
+  }
 }
 
 void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, double *scratch, double *eval,
                         double *Y, int32_t K, int *info, hipStream_t st) {
-  hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(EIG_THREADS), 0, st, m, alpha, beta, scratch, eval, Y, K, info);
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_eig_bisect, dim3(m), dim3(64), sizeof(double) * 3 * m, st, m, alpha, beta, eval);
+  if (K <= 0) {
+    hipLaunchKernelGGL(k_eig_ortho, dim3(1), dim3(EIG_THREADS), sizeof(double) * 2, st, m, 0, scratch, Y, 0, 1,
+                       info);
+    return;
+  }
+  const size_t inv_lds = sizeof(double) * 6 * (size_t)m;
+  static size_t inv_attr = 0, ort_attr = 0;
+  if (inv_lds > 65536 && inv_lds > inv_attr) {
+    (void)hipFuncSetAttribute((const void *)k_eig_invit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)inv_lds);
+    inv_attr = inv_lds;
+  }
+  const size_t base = sizeof(double) * (K + 1 + (size_t)K * K);
+  const size_t xb = sizeof(double) * (size_t)m * K;
+  const int xs_lds = base + xb <= 128 * 1024 ? 1 : 0;
+  const size_t ort_lds = base + (xs_lds ? xb : 0);
+  if (ort_lds > 65536 && ort_lds > ort_attr) {
+    (void)hipFuncSetAttribute((const void *)k_eig_ortho, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ort_lds);
+    ort_attr = ort_lds;
+  }
+  double *X = scratch;
+  hipLaunchKernelGGL(k_eig_invit, dim3(K), dim3(64), inv_lds, st, m, alpha, beta, eval, X, K, 3, 1);
+  hipLaunchKernelGGL(k_eig_ortho, dim3(1), dim3(EIG_THREADS), ort_lds, st, m, K, X, Y, xs_lds, 0, info);
+  hipLaunchKernelGGL(k_eig_invit, dim3(K), dim3(64), inv_lds, st, m, alpha, beta, eval, X, K, 1, 0);
+  hipLaunchKernelGGL(k_eig_ortho, dim3(1), dim3(EIG_THREADS), ort_lds, st, m, K, X, Y, xs_lds, 1, info);
 }
 
 // Ritz vectors: U64[i, q] = sum_j V[i, j] Y[j, q]  (V: s x m col-major,
