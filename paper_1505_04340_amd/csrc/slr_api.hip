@@ -385,8 +385,9 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   double *al = tmp.alloc<double>(steps);
   double *be = tmp.alloc<double>(steps);
   double *part = tmp.alloc<double>((size_t)RED_NBLK * (steps + 1));
+  double *part2 = tmp.alloc<double>((size_t)(s + 255) / 256 + 1);
   unsigned int *cnt = tmp.alloc<unsigned int>(4);
-  if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !cnt) {
+  if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !part2 || !cnt) {
     tmp.release();
     return fail(SLR_ERR_OOM, "Lanczos basis");
   }
@@ -417,12 +418,16 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   for (int32_t j = 0; j < steps; ++j) {
     double *vj = V + (int64_t)j * s;
     if ((rc = apply_H(c, vj, Wl, T, T2, st))) return bail(rc);
+    int32_t rb = 0;
     for (int pass = 0; pass < 2; ++pass) {
-      launch_multidot(s, j + 1, V, s, Wl, part, RED_NBLK, pass == 0 ? h : h + 1024, cnt, st);
-      launch_gemv_sub(s, j + 1, V, s, pass == 0 ? h : h + 1024, Wl, st);
+      // coefficients V^T w as row-chunk partials, folded inside the update
+      // (the first pass's coefficients go to h: h[j] = alpha_j); the second
+      // pass also leaves the partial sums of ||w||^2 in part2
+      const int32_t rbh = launch_multidot_partial(s, j + 1, V, s, Wl, part, RED_NBLK, st);
+      rb = launch_gemv_sub_fold(s, j + 1, V, s, part, rbh, Wl, pass == 0 ? h : nullptr, pass == 1 ? part2 : nullptr,
+                                st);
     }
-    int32_t rb = launch_multidot_partial(s, 1, Wl, s, Wl, part, RED_NBLK, st);           // ||w||^2
-    launch_lanczos_next(s, j, Wl, j + 1 < steps ? V + (int64_t)(j + 1) * s : nullptr, sc, al, be, part, rb, h + j,
+    launch_lanczos_next(s, j, Wl, j + 1 < steps ? V + (int64_t)(j + 1) * s : nullptr, sc, al, be, part2, rb, h + j,
                         st);
   }
   std::vector<double> ah(steps), bh(steps);
@@ -1215,9 +1220,9 @@ int solve_fgmres(slr_ctx *c, const double *b_dev, double *x_dev, const slr_solve
       if ((rc = apply_dd(c, c->ws, vj, n, zj, n, 1, st))) return bail(rc);
       launch_spmv(n, c->a_rp, c->a_ci, c->a_v, zj, n, w, n, 1, st);
       launch_multidot(n, j + 1, V, n, w, part, RED_NBLK, h1, cnt, st);
-      launch_gemv_sub(n, j + 1, V, n, h1, w, st);
+      launch_gemv_sub(n, j + 1, V, n, h1, w, nullptr, st);
       launch_multidot(n, j + 1, V, n, w, part, RED_NBLK, h2, cnt, st);
-      launch_gemv_sub(n, j + 1, V, n, h2, w, st);
+      launch_gemv_sub(n, j + 1, V, n, h2, w, nullptr, st);
       launch_multidot(n, 1, w, n, w, part, RED_NBLK, sc + 1, cnt, st);
       launch_gmres_givens(j, mr + 1, Hm, h1, h2, sc + 1, cs, sn, g, tol, flags, sc + 2, st);
       launch_div_scalar(n, w, w, sc + 2, st);

@@ -70,8 +70,10 @@ void launch_relres(int64_t n, const double *B, int64_t ldb, const double *AX, in
                    int32_t c0, int32_t nc, hipStream_t st);
 void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
                      int32_t nblk, double *out, unsigned int *counter, hipStream_t st);
-void launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const double *h, double *w,
-                     hipStream_t st);
+// w -= V h; sqpart (optional) receives per-block sums of the updated w^2
+// (returns the number of blocks)
+int32_t launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const double *h, double *w,
+                        double *sqpart, hipStream_t st);
 void launch_gemv_add(int64_t n, int32_t J, const double *V, int64_t ldv, const double *y, double *x,
                      hipStream_t st);
 void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
@@ -81,8 +83,10 @@ void launch_lanczos_next(int64_t s, int32_t j, const double *w, double *vnext, d
                          double *beta, const double *bpart, int32_t rb, const double *aval, hipStream_t st);
 int32_t launch_multidot_partial(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
                                 int32_t nblk, hipStream_t st);
-void launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
-                          double *w, hipStream_t st);
+// w -= V h with h folded in each block from the rb multidot partials
+// (block 0 stores h to hout when given); sqpart as for launch_gemv_sub
+int32_t launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
+                             double *w, double *hout, double *sqpart, hipStream_t st);
 void launch_scale_inv_sqrt(int64_t s, const double *w, double *out, const double *nrm2, hipStream_t st);
 void launch_div_scalar(int64_t n, const double *w, double *v, const double *scale, hipStream_t st);
 void launch_gmres_givens(int32_t j, int32_t ldh, double *Hm, const double *h1, const double *h2,

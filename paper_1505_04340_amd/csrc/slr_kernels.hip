@@ -1233,35 +1233,60 @@ __global__ void __launch_bounds__(256) k_multidot(int64_t s, int J, const double
   if (threadIdx.x == 0) part[(int64_t)rb * J + j] = t;
 }
 
-// sum_j V[i + j*ldv] c[j] in column order, 16 loads in flight (the last
+// sum_j V[i + j*ldv] c[j] in column order, 32 loads in flight (the last
 // group clamps its column index and multiplies padding by zero)
-__device__ __forceinline__ double dot_rows16(const double *V, int64_t ldv, int64_t i, const double *c, int J) {
+__device__ __forceinline__ double dot_rows32(const double *V, int64_t ldv, int64_t i, const double *c, int J) {
   double acc = 0.0;
-  for (int j0 = 0; j0 < J; j0 += 16) {
-    double v[16];
+  for (int j0 = 0; j0 < J; j0 += 32) {
+    double v[32];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = V[i + (int64_t)min(j0 + e, J - 1) * ldv];
+    for (int e = 0; e < 32; ++e) v[e] = V[i + (int64_t)min(j0 + e, J - 1) * ldv];
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
+    for (int e = 0; e < 32; ++e)
       if (j0 + e < J) acc += v[e] * c[j0 + e];
   }
   return acc;
 }
 
 // w[i] -= sum_j V[i + j*ldv] h[j]   (J <= 1024).  h is either on the
-// device (hpart == nullptr) or folded here from the rb multidot partials.
+// device (hpart == nullptr) or folded here from the rb multidot partials
+// hpart[b*J + j] (one thread per coefficient, partials in block order; block
+// 0 also stores the folded h to hout when given).  sqpart (optional):
+// per-block sums of the updated w[i]^2, block b at sqpart[b].
 __global__ void __launch_bounds__(256) k_gemv_sub(int64_t s, int J, const double *V, int64_t ldv,
-                                                  const double *h, double *w, const double *hpart, int rb) {
+                                                  const double *h, double *w, const double *hpart, int rb,
+                                                  double *sqpart, double *hout) {
   __shared__ double hs[1024];
+  __shared__ double sh[4];
   if (hpart) {
-    fold_waves(hpart, rb, J, [&](int j, double v) { hs[j] = v; });
+    for (int j = threadIdx.x; j < J; j += blockDim.x) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int b = 0;
+      for (; b + 3 < rb; b += 4) {
+        a0 += hpart[(int64_t)b * J + j];
+        a1 += hpart[(int64_t)(b + 1) * J + j];
+        a2 += hpart[(int64_t)(b + 2) * J + j];
+        a3 += hpart[(int64_t)(b + 3) * J + j];
+      }
+      for (; b < rb; ++b) a0 += hpart[(int64_t)b * J + j];
+      const double v = (a0 + a1) + (a2 + a3);
+      hs[j] = v;
+      if (hout && blockIdx.x == 0) hout[j] = v;
+    }
   } else {
     for (int j = threadIdx.x; j < J; j += blockDim.x) hs[j] = h[j];
   }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= s) return;
-  w[i] -= dot_rows16(V, ldv, i, hs, J);
+  double wn = 0.0;
+  if (i < s) {
+    wn = w[i] - dot_rows32(V, ldv, i, hs, J);
+    w[i] = wn;
+  }
+  if (sqpart) {
+    const double t = block_sum(wn * wn, sh);
+    if (threadIdx.x == 0) sqpart[blockIdx.x] = t;
+  }
 }
 
 int32_t launch_multidot_partial(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
@@ -1281,16 +1306,20 @@ void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const d
   launch_fold(part, (int32_t)rb, J, out, 1.0, st);
 }
 
-void launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const double *h, double *w,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_gemv_sub, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, J, V, ldv, h, w,
-                     (const double *)nullptr, 0);
+int32_t launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, const double *h, double *w,
+                        double *sqpart, hipStream_t st) {
+  const unsigned nb = (unsigned)((s + 255) / 256);
+  hipLaunchKernelGGL(k_gemv_sub, dim3(nb), dim3(256), 0, st, s, J, V, ldv, h, w, (const double *)nullptr, 0,
+                     sqpart, (double *)nullptr);
+  return (int32_t)nb;
 }
 
-void launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
-                          double *w, hipStream_t st) {
-  hipLaunchKernelGGL(k_gemv_sub, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, J, V, ldv,
-                     (const double *)nullptr, w, hpart, rb);
+int32_t launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
+                             double *w, double *hout, double *sqpart, hipStream_t st) {
+  const unsigned nb = (unsigned)((s + 255) / 256);
+  hipLaunchKernelGGL(k_gemv_sub, dim3(nb), dim3(256), 0, st, s, J, V, ldv, (const double *)nullptr, w, hpart, rb,
+                     sqpart, hout);
+  return (int32_t)nb;
 }
 
 // Lanczos three-term step: alpha = v.w folded from the rb multidot
@@ -1363,7 +1392,7 @@ __global__ void __launch_bounds__(256) k_gemv_add(int64_t n, int J, const double
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  x[i] += dot_rows16(V, ldv, i, ys, J);
+  x[i] += dot_rows32(V, ldv, i, ys, J);
 }
 
 void launch_gemv_add(int64_t n, int32_t J, const double *V, int64_t ldv, const double *y, double *x,
