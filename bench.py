@@ -1,6 +1,6 @@
 """Benchmark of the SLR hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp64|mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form both|fp64] [--no-serve] [--no-cpu-baseline]
 
 Workload: 3-D 7-point Laplacian on a 64^3 grid (n = 262,144), 4x4x4 box
 decomposition (64 subdomains), IC(0) factors of the B_i and of C, rank
@@ -16,8 +16,10 @@ factorisation is setup and is not timed.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -187,6 +189,38 @@ def serving(P, torch, n_req, seed=13):
     return out
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bsolve_lap3d_64_hbm_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1505_04340_amd", "csrc", "slr_kernels.hip")
+
+
+def recorded_traffic():
+    """HBM bytes per k_bsolve launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel source has changed since the counters
+    were taken (the summary records the source's sha256)."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"slr_kernels\.hip sha256: ([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch [^\n]*: (\d+)", text)
+    if not m or not t or m.group(1) != sha:
+        return None
+    return int(t.group(1))
+
+
+def copy_calibration(nbytes=1 << 30, reps=4):
+    """A plain device-to-device copy of nbytes, reps times: the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters to HBM bytes."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,7 +230,14 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--config", default="lap3d_64")
+    ap.add_argument("--form", choices=("both", "fp64"), default="both",
+                    help="fp64: measure only the FP64 form (the headline), not the mixed one beside it")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is a design note, not a built path)", file=sys.stderr)
@@ -215,7 +256,7 @@ def main():
     v0 = pr.v0()
     forms = {}
     G = None
-    for name in ("fp64", "mixed"):
+    for name in ("fp64", "mixed") if args.form == "both" else ("fp64",):
         Gf, info, res, stages, bf = measure_form(P, pr, FORMS[name], args.steps, args.warmup, v0, bd, xs,
                                                  f"[bench:{name}]")
         forms[name] = res
@@ -227,7 +268,8 @@ def main():
     bb = bsolve_bytes(info64, 1, bf64)
     achieved = bb / (stages64["bsolve1"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": recorded_traffic() if args.config == "lap3d_64" else None,
             "kernel": "k_bsolve (batched B_i solves + E^T epilogue)",
             "algorithmic_bytes_per_launch": int(bb), "avg_launch_ms": round(stages64["bsolve1"], 5)}
     out = {

@@ -897,22 +897,42 @@ void launch_permute(int64_t n, const int64_t *idx, const double *src, int64_t ld
 // ---------------------------------------------------------------------------
 // K5: CSR SpMV y = A x (FP64, A in the internal order)
 // ---------------------------------------------------------------------------
+// y = A x for up to SPMV_T columns per thread (blockIdx.y picks the column
+// tile): each row's entries are read once per tile; every column sums its
+// row in entry order.
+constexpr int SPMV_T = 8;
+
+template <int T>
 __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *rp, const int32_t *ci,
                                               const double *v, const double *x, int64_t ldx, double *y,
-                                              int64_t ldy) {
+                                              int64_t ldy, int nrhs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double *xc = x + (int64_t)blockIdx.y * ldx;
-  double acc = 0.0;
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) acc += v[e] * xc[ci[e]];
-  y[i + (int64_t)blockIdx.y * ldy] = acc;
+  const int c0 = blockIdx.y * T, nct = min(T, nrhs - c0);
+  double acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = 0.0;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+    const double a = v[e];
+    const int64_t j = ci[e];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      if (t < nct) acc[t] += a * x[j + (int64_t)(c0 + t) * ldx];
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+    if (t < nct) y[i + (int64_t)(c0 + t) * ldy] = acc[t];
 }
 
 void launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
                  int64_t ldx, double *y, int64_t ldy, int32_t nrhs, hipStream_t st) {
   if (n == 0 || nrhs == 0) return;
-  hipLaunchKernelGGL(k_spmv, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, st, n, rp, ci, v, x, ldx,
-                     y, ldy);
+  const unsigned gx = (unsigned)((n + 255) / 256);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_spmv<1>, dim3(gx, 1), dim3(256), 0, st, n, rp, ci, v, x, ldx, y, ldy, nrhs);
+  else
+    hipLaunchKernelGGL(k_spmv<SPMV_T>, dim3(gx, (nrhs + SPMV_T - 1) / SPMV_T), dim3(256), 0, st, n, rp, ci, v, x,
+                       ldx, y, ldy, nrhs);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,25 +957,47 @@ __device__ __forceinline__ void chunk_rows(int64_t n, F f) {
   for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) f(i);
 }
 
-// (1) q = A p and partial p.q  -> part[b*nc + cc]
+// (1) q = A p and partial p.q  -> part[b*nc + cc].  Columns go in tiles of
+// TT (1 for a single column, SPMV_T otherwise) so that each row's entries
+// are read once per tile; a column's arithmetic (entry order, row order,
+// block sum) does not depend on the tile it falls in.
+template <int TT>
 __global__ void __launch_bounds__(RED_THREADS) k_cg_spmv(int64_t n, const int64_t *rp, const int32_t *ci,
                                                          const double *v, KArgs K, int c0, int nc) {
+  constexpr int SPMV_T = TT;
   __shared__ double sh[RED_THREADS / 64];
-  for (int cc = 0; cc < nc; ++cc) {
-    const int c = c0 + cc;
-    const double *pc = K.P + (int64_t)c * K.ld;
-    double *qc = K.Q + (int64_t)c * K.ld;
-    double acc = 0.0;
-    if (K.st[c].active) {
-      chunk_rows(n, [&](int64_t i) {
-        double sum = 0.0;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) sum += v[e] * pc[ci[e]];
-        qc[i] = sum;
-        acc += sum * pc[i];
-      });
+  for (int ct = 0; ct < nc; ct += SPMV_T) {
+    const int nct = min(SPMV_T, nc - ct);
+    bool act[SPMV_T];
+    double acc[SPMV_T];
+#pragma unroll
+    for (int t = 0; t < SPMV_T; ++t) {
+      act[t] = t < nct && K.st[c0 + ct + t].active;
+      acc[t] = 0.0;
     }
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + cc] = t;
+    chunk_rows(n, [&](int64_t i) {
+      double sum[SPMV_T];
+#pragma unroll
+      for (int t = 0; t < SPMV_T; ++t) sum[t] = 0.0;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const double a = v[e];
+        const int64_t j = ci[e];
+#pragma unroll
+        for (int t = 0; t < SPMV_T; ++t)
+          if (act[t]) sum[t] += a * K.P[j + (int64_t)(c0 + ct + t) * K.ld];
+      }
+#pragma unroll
+      for (int t = 0; t < SPMV_T; ++t)
+        if (act[t]) {
+          const int64_t o = i + (int64_t)(c0 + ct + t) * K.ld;
+          K.Q[o] = sum[t];
+          acc[t] += sum[t] * K.P[o];
+        }
+    });
+    for (int t = 0; t < nct; ++t) {
+      const double tt = block_sum(acc[t], sh);
+      if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + ct + t] = tt;
+    }
   }
 }
 
@@ -1182,7 +1224,10 @@ void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const do
       hipLaunchKernelGGL(k_cg_start2, dim3(1), dim3(RED_THREADS), 0, st, K, c0, nc, it);
       break;
     case CG_SPMV:
-      hipLaunchKernelGGL(k_cg_spmv, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc);
+      if (nc == 1)
+        hipLaunchKernelGGL(k_cg_spmv<1>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc);
+      else
+        hipLaunchKernelGGL(k_cg_spmv<SPMV_T>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc);
       break;
     case CG_UPDATE:
       hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, it);
