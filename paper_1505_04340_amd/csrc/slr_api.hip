@@ -123,7 +123,8 @@ struct slr_ctx {
   double *U64 = nullptr;        // s x k column-major, FP64 (export)
   double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
-  int32_t lr_nblk = 128;
+  int32_t lr_nblk = 128;       // row chunks of the scalar rank-k partials
+  int32_t lrm_nblk = 512;      // row chunks of the matrix-core rank-k partials
   // BF16 U_k always takes the matrix-core path, so a column's arithmetic
   // never depends on how many columns share the launch
   int32_t mfma_min_rhs = 1;
@@ -177,7 +178,7 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   int32_t cap = std::max<int32_t>(nrhs, 1);
   w.W = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
   w.W2 = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
-  w.lr_part = w.pool.alloc<double>((size_t)c->lr_nblk * cap * std::max(c->k, 1));
+  w.lr_part = w.pool.alloc<double>((size_t)std::max(c->lr_nblk, c->lrm_nblk) * cap * std::max(c->k, 1));
   w.cbuf = w.pool.alloc<double>((size_t)cap * std::max(c->k, 1));
   w.counter = w.pool.alloc<unsigned int>(16);
   if (!w.W || !w.W2 || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
@@ -267,7 +268,7 @@ void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wou
     default:
       if (nrhs >= c->mfma_min_rhs && k > 0)
         launch_lowrank_mfma((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo, nrhs,
-                            w.lr_part, c->lr_nblk, w.cbuf, st);
+                            w.lr_part, c->lrm_nblk, w.cbuf, st);
       else
         launch_lowrank<__hip_bfloat16>((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo,
                                        nrhs, w.lr_part, c->lr_nblk, w.cbuf, w.counter, st);
