@@ -1,0 +1,75 @@
+"""The 1024^2 diffusion and 128^3 shifted workloads at their full sizes.
+
+Apply parity: the device builds (U_k, Lambda_k, theta) with its own Lanczos;
+the oracle imports them (U_k rounded to the stored precision) together with
+its own factors rounded the same way, and applies the preconditioner in
+FP64 to the same columns.  Bar: 1e-5 relative per column (FP32 factors,
+BF16 or FP32 U_k).  Solves: every right-hand side reaches a true FP64
+relative residual <= 1e-8 (checked on the host).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import slr_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _relerr(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+@pytest.fixture(scope="module")
+def diffusion():
+    return si.make_config("diffusion2d_1024")
+
+
+def test_diffusion_1024_apply_32rhs_bf16_mfma(diffusion):
+    import paper_1505_04340_amd as P
+    pr = diffusion
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, c_order="multicolor",
+              fact_prec="fp32", uk_prec="bf16", v0=pr.v0())
+    ex = G.export()
+    Po = O.setup(pr.csr, pr.part, pr.nparts, pr.k, 0, b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor",
+                 fact_prec="fp32", lowrank=(O.round_bf16(ex["U"]), ex["lambda"], ex["theta"]))
+    assert (Po.perm == ex["perm"]).all()
+    r = np.random.default_rng(21).uniform(-1, 1, (pr.n, 32))
+    z = G.apply(torch.tensor(r, dtype=torch.float64, device="cuda")).cpu().numpy()
+    cols = [0, 7, 19, 31]
+    zo = Po.apply(r[:, cols])
+    err = _relerr(z[:, cols], zo)
+    assert err.max() <= 1e-5, err
+
+
+def test_diffusion_1024_fcg_32rhs_converges(diffusion):
+    import paper_1505_04340_amd as P
+    pr = diffusion
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, c_order="multicolor",
+              fact_prec="fp32", uk_prec="bf16", v0=pr.v0())
+    xs, b = pr.rhs()
+    x, infos = G.solve(torch.tensor(b, dtype=torch.float64, device="cuda"), "fcg", rtol=1e-8, maxit=3000)
+    assert all(i["status"] == 0 for i in infos)
+    A = pr.scipy()
+    xh = x.cpu().numpy().reshape(pr.n, -1)
+    rr = np.linalg.norm(b - A @ xh, axis=0) / np.linalg.norm(b, axis=0)
+    assert rr.max() <= 1e-8, rr.max()
+    assert max(i["relres"] for i in infos) <= 1e-8
+
+
+def test_shifted_128_apply_fp32_ildlt():
+    import paper_1505_04340_amd as P
+    pr = si.make_config("shifted3d_128")
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order="multicolor", fact_prec="fp32", uk_prec="fp32", v0=pr.v0())
+    ex = G.export()
+    Po = O.setup(pr.csr, pr.part, pr.nparts, pr.k, 0, b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor",
+                 fact_prec="fp32", lowrank=(O.round_fp32(ex["U"]), ex["lambda"], ex["theta"]))
+    r = np.random.default_rng(22).uniform(-1, 1, (pr.n, 2))
+    z = G.apply(torch.tensor(r, dtype=torch.float64, device="cuda")).cpu().numpy()
+    err = _relerr(z, Po.apply(r))
+    assert err.max() <= 1e-5, err
