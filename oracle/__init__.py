@@ -301,6 +301,7 @@ class SLR:
     U: np.ndarray = None        # s x k (C-factor order)
     lam: np.ndarray = None      # k Ritz values, descending
     theta: float = 0.0
+    eps: float = 0.0            # > 0: the eq. Lambda-2 choice of Lambda~ (theta unused)
     ritz: np.ndarray = None     # all Ritz values of T_m, descending
     steps: int = 0
     alpha: np.ndarray = None
@@ -333,11 +334,18 @@ class SLR:
         z = self.FB.solve(f)
         gp = g - self.E.T @ z
         w = self.FC.lower(gp)
-        rho = 1.0 / (1.0 - self.theta)
+        if self.eps > 0.0:
+            # eq. Lambda-2: 1 - lambda~_i = (1 - lambda_i)/eps for i <= k,
+            # lambda~_i = 0 beyond, so (I - Lambda~)^{-1} - I has the entries
+            # eps/(1 - lambda_i) - 1 on the captured directions and 0 elsewhere
+            rho, dsc = 1.0, (self.eps / (1.0 - self.lam) - 1.0) if self.k else None
+        else:
+            rho = 1.0 / (1.0 - self.theta)
+            dsc = (1.0 / (1.0 - self.lam) - rho) if self.k else None
         wp = rho * w
         if self.k:
             c = self.U.T @ w
-            c = c * (1.0 / (1.0 - self.lam) - rho)
+            c = c * dsc
             wp = wp + self.U @ c
         y = self.FC.upper(wp)
         u = self.FB.solve(f - self.E @ y)
@@ -356,13 +364,19 @@ class SLR:
 def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "ic0",
           c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
           fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
-          lowrank=None) -> SLR:
+          lowrank=None, eps: float = 0.0, cond_K: float = 0.0) -> SLR:
     """Build the SLR preconditioner (Sec. 4 and Sec. 5).
 
     A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
     (-1 = separator).  lanczos_steps 0 means 5k (Sec. 6).  v0: Lanczos start
     vector in original node order (its interface entries are used).
-    lowrank: optional (U, lam, theta) to use instead of running Lanczos."""
+    lowrank: optional (U, lam, theta) to use instead of running Lanczos.
+    theta_mode "lambda_k1" (theta = lambda_{k+1}, Sec. 4), "zero"
+    (eq. Lambda-1) or "eps" (eq. Lambda-2 with parameter eps > 0).
+    cond_K > 1: k becomes the smallest rank (at most the given k) with
+    lambda_{k+1} <= 1 - 1/K among the Ritz values (eq. condk)."""
+    if theta_mode == "eps" and not eps > 0.0:
+        raise OracleError("ARG", "theta_mode eps needs eps > 0")
     if isinstance(A, tuple):
         indptr, indices, data, n = A
         A = sp.csr_matrix((data, indices, indptr), shape=(n, n))
@@ -387,14 +401,18 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
         P.U = np.array(U, dtype=np.float64).reshape(s, -1)
         P.lam = np.array(lam, dtype=np.float64)
         P.k = P.U.shape[1]
-        P.theta = float(theta)
+        P.theta = 0.0 if theta_mode == "eps" else float(theta)
     elif k > 0:
         steps = lanczos_steps or 5 * k
         if v0 is None:
             v0 = np.random.Generator(np.random.PCG64(7)).uniform(-1, 1, A.shape[0])
-        lanczos_lowrank(P, k, steps, np.asarray(v0)[perm[m:]], theta_mode)
+        lanczos_lowrank(P, k, steps, np.asarray(v0)[perm[m:]], theta_mode, cond_K)
     else:
         P.theta = 0.0
+    if theta_mode == "eps":
+        P.eps = float(eps)
+        if P.k and np.any(np.abs(1.0 - P.lam) < 1e-12):
+            raise OracleError("RITZ_SINGULAR", "Ritz value too close to 1")
     if uk_prec == "fp32":
         P.U = round_fp32(P.U)
     elif uk_prec == "bf16":
@@ -435,12 +453,14 @@ def lanczos(G, v0: np.ndarray, steps: int):
         V[:, j + 1] = w / b
 
 
-def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode: str):
+def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode: str, cond_K: float = 0.0):
     """(U_k, Lambda_k, theta) from Lanczos on H (Sec. 5.1, eq. skt).
 
     The Ritz pairs of the tridiagonal T_m are sorted by decreasing value;
     the k largest give Lambda_k and U_k = V_m Y_k; theta = lambda_{k+1}
-    (Sec. 4, the paper's choice) or 0 (eq. Lambda-1, truncation)."""
+    (Sec. 4, the paper's choice) or 0 (eq. Lambda-1, truncation, and the
+    eq. Lambda-2 form).  cond_K > 1: the rank is the number of Ritz values
+    above 1 - 1/K, at most k (eq. condk: lambda_{k+1} <= 1 - 1/K)."""
     V, alpha, beta = lanczos(P.G, v0_iface, steps)
     mm = V.shape[1]
     T = np.diag(alpha) + np.diag(beta[:mm - 1], 1) + np.diag(beta[:mm - 1], -1)
@@ -449,6 +469,8 @@ def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode
     need = k + 1 if theta_mode == "lambda_k1" else k
     if mm < need:
         raise OracleError("LANCZOS_SHORT", f"{mm} Ritz pairs < {need}")
+    if cond_K > 1.0:
+        k = min(k, int(np.sum(ev > 1.0 - 1.0 / cond_K)))
     P.k = k
     P.lam = ev[:k].copy()
     P.U = V @ Y[:, :k]

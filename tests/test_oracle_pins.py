@@ -289,6 +289,57 @@ def test_P2_P7_spectrum_of_preconditioned_matrix(theta_mode):
         assert math.isclose(kappa, (1 - lam[-1]) / (1 - lam[k]), rel_tol=1e-12)
 
 
+@pytest.mark.parametrize("eps", [0.3, 1.0])
+def test_Lambda2_eps_spectrum_of_preconditioned_matrix(eps):
+    """eq. Lambda-2: lambda~_i = 1 - (1 - lambda_i)/eps for i <= k and 0
+    beyond make eig(S S~^{-1}) = {eps}^k U {1 - lambda_i}_{i>k}, so
+    eig(M^{-1}A) = {1}^m U {eps}^k U {1 - lambda_i}_{i>k}; eps = 1 is
+    eq. Lambda-1 (theta = 0)."""
+    csr, part, p = _tiny(10)
+    P0 = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol")
+    k = 5
+    H, L, lam, U, _ = _dense_lowrank(P0, k, "zero")
+    P = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol", lowrank=(U[:, :k], lam[:k], 0.0),
+                theta_mode="eps", eps=eps)
+    got = _spectrum_MinvA(P)
+    expect = np.sort(np.concatenate([np.ones(P.m), np.full(k, eps), 1 - lam[k:]]))
+    assert np.allclose(got, expect, atol=1e-9)
+    if eps == 1.0:
+        Pz = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol", lowrank=(U[:, :k], lam[:k], 0.0),
+                     theta_mode="zero")
+        r = np.random.default_rng(3).standard_normal(P.A.shape[0])
+        assert np.allclose(P.apply(r), Pz.apply(r), rtol=1e-13, atol=1e-13)
+
+
+def test_condk_rank_selection():
+    """eq. condk: with cond_K = K the rank is the number of eigenvalues of H
+    above 1 - 1/K, and then kappa(S S~^{-1}) = (1 - lambda_s)/(1 - lambda_{k+1})
+    <= K (theta = lambda_{k+1}).  Simple spectrum (random coefficients,
+    uneven cuts) and as many Lanczos steps as interface nodes, so the Ritz
+    values are the eigenvalues."""
+    N = 14
+    rng = np.random.default_rng(4)
+    csr = si.diffusion_2d(N, np.exp(rng.standard_normal((N + 2, N + 2))))
+    part = si.random_cuts_2d(N, 2, 2, 5)
+    P0 = O.setup(csr, part, 4, 0, b_fact="chol", c_fact="chol")
+    H, _ = _dense_H(P0)
+    ev = np.sort(np.linalg.eigvalsh(H))[::-1]
+    for K in (2.0, 5.0):
+        want = int(np.sum(ev > 1 - 1 / K))
+        P = O.setup(csr, part, 4, 20, P0.s, b_fact="chol", c_fact="chol", cond_K=K,
+                    v0=si.lanczos_start(csr[3], 9))
+        assert want < 20
+        assert P.k == want
+        assert np.allclose(P.ritz[:want + 1], ev[:want + 1], rtol=1e-9, atol=1e-12)
+        sig = (1 - ev[want:]) / (1 - P.theta)
+        kappa = max(sig.max(), 1.0) / min(sig.min(), 1.0)
+        assert kappa <= K * (1 + 1e-9)
+        assert math.isclose(kappa, (1 - ev[-1]) / (1 - ev[want]), rel_tol=1e-8)
+        # eig(M^{-1}A) = {1}^(m+k) U {(1 - lambda_i)/(1 - theta)}_{i>k}
+        spec = _spectrum_MinvA(P)
+        assert np.allclose(spec, np.sort(np.concatenate([np.ones(P.m + want), sig])), atol=1e-7)
+
+
 def test_P3prime_inertia_counts_negative_eigenvalues():
     """Indefinite A with SPD B (exact solves): by Sylvester's law on
     eq. Schur, #{lambda(H) > 1} = #negative eigenvalues of A."""
