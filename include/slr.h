@@ -58,7 +58,12 @@ enum {
 };
 
 /* ---- options -------------------------------------------------------------- */
-enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1 };
+/* Choice of the shift in eq. skt: theta = lambda_{k+1} (Sec. 4), theta = 0
+ * (truncation, eq. Lambda-1), or the eq. Lambda-2 form with parameter eps:
+ * on the k captured directions 1 - lambda_i is replaced by (1 - lambda_i)/eps,
+ * elsewhere theta = 0, i.e. rho = 1 and the diagonal scales become
+ * eps/(1 - lambda_i) - 1. */
+enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1, SLR_THETA_EPS = 2 };
 enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2 };
 enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1 };
 enum { SLR_FP64 = 0, SLR_FP32 = 1, SLR_BF16 = 2 };
@@ -75,7 +80,8 @@ typedef struct {
 typedef struct {
   int32_t k;              /* rank of the correction (Sec. 4); 0 = none        */
   int32_t lanczos_steps;  /* 0 => 5k (Sec. 6)                                 */
-  int32_t theta_mode;     /* SLR_THETA_LAMBDA_K1 (Sec. 4) | SLR_THETA_ZERO    */
+  int32_t theta_mode;     /* SLR_THETA_LAMBDA_K1 (Sec. 4) | SLR_THETA_ZERO |
+                             SLR_THETA_EPS (eq. Lambda-2, parameter eps)      */
   int32_t b_fact;         /* local solver of the B_i (Sec. 5.2): CHOL|IC0|ILDLT0 */
   int32_t c_fact;         /* factor of C = L L^T: CHOL | IC0                  */
   int32_t c_order;        /* ordering of the interface for C's factor         */
@@ -92,7 +98,17 @@ typedef struct {
   int32_t k_in;
   const double *U_in;
   const double *lambda_in;
-  double theta_in;
+  double theta_in;        /* ignored under SLR_THETA_EPS                     */
+  /* eq. Lambda-2 parameter, > 0 under SLR_THETA_EPS (SLR_ERR_ARG otherwise);
+     unused by the other modes.  eps = 1 gives the SLR_THETA_ZERO
+     preconditioner. */
+  double eps;
+  /* Rank from a target condition number (eq. condk): with cond_K > 1 the
+     Lanczos build keeps the Ritz values above 1 - 1/cond_K, at most k of
+     them (the rank in use, possibly 0, is reported in slr_info.k); 0
+     keeps k.  Values in (0, 1] are SLR_ERR_ARG.  Ignored for an imported
+     low-rank part. */
+  double cond_K;
 } slr_opts;
 
 typedef struct {

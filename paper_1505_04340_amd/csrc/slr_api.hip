@@ -348,13 +348,16 @@ int upload_lowrank_T(slr_ctx *c, hipStream_t st) {
 }
 
 int finish_lowrank(slr_ctx *c, hipStream_t st) {
-  // scales of eq. skt: (1 - lambda_i)^{-1} - (1 - theta)^{-1}
+  // scales of eq. skt: (1 - lambda_i)^{-1} - (1 - theta)^{-1}; under the
+  // eq. Lambda-2 form rho = 1 and eps (1 - lambda_i)^{-1} - 1
+  const bool eps_mode = c->opts.theta_mode == SLR_THETA_EPS;
+  if (eps_mode) c->theta = 0.0;
   if (std::fabs(1.0 - c->theta) < 1e-12) return fail(SLR_ERR_RITZ_SINGULAR, "|1 - theta| < 1e-12");
   c->rho = 1.0 / (1.0 - c->theta);
   std::vector<double> d(std::max(c->k, 1), 0.0);
   for (int i = 0; i < c->k; ++i) {
     if (std::fabs(1.0 - c->lam_h[i]) < 1e-12) return fail(SLR_ERR_RITZ_SINGULAR, "|1 - lambda_i| < 1e-12");
-    d[i] = 1.0 / (1.0 - c->lam_h[i]) - c->rho;
+    d[i] = eps_mode ? c->opts.eps / (1.0 - c->lam_h[i]) - 1.0 : 1.0 / (1.0 - c->lam_h[i]) - c->rho;
   }
   c->dsc = c->lrpool.upload(d);
   if (!c->dsc) return fail(SLR_ERR_OOM, "dsc");
@@ -467,8 +470,17 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
   tmp.release();
   if (info_h) return fail(SLR_ERR_BREAKDOWN, "tridiagonal eigensolve did not converge");
-  c->lam_h.assign(c->ritz_h.begin(), c->ritz_h.begin() + k);
-  c->theta = need_k1 ? c->ritz_h[k] : 0.0;
+  // eq. condk: keep the Ritz values above 1 - 1/K (at most k); the first
+  // k' columns of U are the Ritz vectors of the k' largest values
+  int32_t kk = k;
+  if (c->opts.cond_K > 1.0) {
+    const double cut = 1.0 - 1.0 / c->opts.cond_K;
+    kk = 0;
+    while (kk < k && c->ritz_h[kk] > cut) ++kk;
+  }
+  c->k = kk;
+  c->lam_h.assign(c->ritz_h.begin(), c->ritz_h.begin() + kk);
+  c->theta = need_k1 ? c->ritz_h[kk] : 0.0;
   c->info.lanczos_steps = mm;
   return finish_lowrank(c, st);
 }
@@ -703,6 +715,8 @@ void slr_default_opts(slr_opts *o) {
   o->fact_prec = SLR_FP64;
   o->uk_prec = SLR_FP64;
   o->seed = 7;
+  o->eps = 0.0;
+  o->cond_K = 0.0;
 }
 
 void slr_default_solve_opts(slr_solve_opts *o) {
@@ -746,6 +760,9 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   if (!A || !part || !o || !out || !A->rowptr || !A->col || !A->val) return fail(SLR_ERR_ARG, "null argument");
   *out = nullptr;
   if (o->k < 0 || o->k > 64) return fail(SLR_ERR_ARG, "k must be in [0, 64]");
+  if (o->theta_mode < SLR_THETA_LAMBDA_K1 || o->theta_mode > SLR_THETA_EPS) return fail(SLR_ERR_ARG, "theta_mode");
+  if (o->theta_mode == SLR_THETA_EPS && !(o->eps > 0.0)) return fail(SLR_ERR_ARG, "theta_mode eps needs eps > 0");
+  if (!(o->cond_K == 0.0 || o->cond_K > 1.0)) return fail(SLR_ERR_ARG, "cond_K must be 0 or > 1");
   if (o->fact_prec != SLR_FP64 && o->fact_prec != SLR_FP32) return fail(SLR_ERR_ARG, "fact_prec");
   if (o->uk_prec < SLR_FP64 || o->uk_prec > SLR_BF16) return fail(SLR_ERR_ARG, "uk_prec");
   if (o->b_fact < SLR_FACT_CHOL || o->b_fact > SLR_FACT_ILDLT0) return fail(SLR_ERR_ARG, "b_fact");

@@ -33,16 +33,16 @@ def test_binding_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "slr.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
         "sizeof(slr_csr), sizeof(slr_opts), sizeof(slr_solve_opts), sizeof(slr_solve_info),"
         "sizeof(slr_info), offsetof(slr_opts, lanczos_v0), offsetof(slr_opts, theta_in),"
-        "offsetof(slr_info, theta));return 0;}\n")
+        "offsetof(slr_opts, eps), offsetof(slr_opts, cond_K), offsetof(slr_info, theta));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(P.slr_csr), ctypes.sizeof(P.slr_opts), ctypes.sizeof(P.slr_solve_opts),
             ctypes.sizeof(P.slr_solve_info), ctypes.sizeof(P.slr_info), P.slr_opts.lanczos_v0.offset,
-            P.slr_opts.theta_in.offset, P.slr_info.theta.offset]
+            P.slr_opts.theta_in.offset, P.slr_opts.eps.offset, P.slr_opts.cond_K.offset, P.slr_info.theta.offset]
     assert got == want
 
 
@@ -52,6 +52,7 @@ def test_host_only_entry_points():
     P.slr_default_opts(ctypes.byref(o))
     assert (o.theta_mode, o.b_fact, o.c_fact, o.fact_prec) == (P.SLR_THETA_LAMBDA_K1, P.SLR_FACT_IC0,
                                                                P.SLR_FACT_IC0, P.SLR_FP64)
+    assert (o.eps, o.cond_K) == (0.0, 0.0)
     so = P.slr_solve_opts()
     P.slr_default_solve_opts(ctypes.byref(so))
     assert (so.restart, so.maxit, so.rtol) == (40, 300, 1e-8)
@@ -62,6 +63,19 @@ def test_host_only_entry_points():
     assert b"null" in P.slr_last_error()
     assert P.slr_apply(None, None, None, 1, None) == P.SLR_ERR_ARG
     assert P.slr_batch_active(None) == 0
+    # option checks come before any device work: eq. Lambda-2 needs eps > 0,
+    # eq. condk needs K > 1
+    import numpy as np
+    rp = np.array([0, 1], dtype=np.int64)
+    ci = np.array([0], dtype=np.int32)
+    va = np.array([1.0])
+    pa = np.array([0], dtype=np.int32)
+    csr = P.slr_csr(1, 1, rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    for mode, eps, K, what in ((P.SLR_THETA_EPS, 0.0, 0.0, b"eps"), (P.SLR_THETA_LAMBDA_K1, 0.0, 0.5, b"cond_K"),
+                               (7, 0.0, 0.0, b"theta_mode")):
+        o.theta_mode, o.eps, o.cond_K = mode, eps, K
+        assert P.slr_setup(ctypes.byref(csr), pa.ctypes.data, 1, ctypes.byref(o), None, ctypes.byref(h)) == P.SLR_ERR_ARG
+        assert what in P.slr_last_error()
 
 
 def test_build_sources_are_gfx950_hip():

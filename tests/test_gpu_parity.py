@@ -247,6 +247,57 @@ def test_edge_cases_apply(case):
     assert np.all(z0 == 0)
 
 
+@pytest.mark.parametrize("eps", [0.3, 2.0])
+def test_eps_form_apply(eps):
+    """eq. Lambda-2 form: rho = 1 and scales eps/(1 - lambda_i) - 1.  The
+    device takes the oracle's (U_k, Lambda_k) (FP64 bar), then builds its own
+    and is checked against the oracle fed with the exported part."""
+    pr = si.make_config("lap2d_64", N=40)
+    Po = _oracle(pr, k=8, lanczos_steps=40, theta_mode="eps", eps=eps)
+    assert Po.theta == 0.0
+    G = _slr(pr, k=8, lanczos_steps=40, theta_mode="eps", eps=eps, lowrank=(Po.U, Po.lam, 0.7))
+    assert G.info["theta"] == 0.0
+    r = _rand(pr.n, 2, 4)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max() <= 1e-12
+    G2 = _slr(pr, k=8, lanczos_steps=40, theta_mode="eps", eps=eps)
+    ex = G2.export()
+    assert ex["theta"] == 0.0 and G2.info["k"] == 8
+    Pi = _oracle(pr, theta_mode="eps", eps=eps, lowrank=(ex["U"], ex["lambda"], 0.0))
+    assert _relerr(G2.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= 1e-12
+
+
+def test_rank_from_condition_number():
+    """eq. condk: with target K the rank is the number of Ritz values above
+    1 - 1/K (at most k).  Cuts are placed midway in the widest gap between
+    converged Ritz values, so the device's and the oracle's choice must be
+    the same; theta = lambda_{k'+1} agrees to the Ritz-value bar and the
+    apply matches the oracle fed with the exported part.  A cut above every
+    Ritz value gives rank 0 with theta = lambda_1."""
+    pr = si.make_config("diffusion2d_1024", N=48, boxes=4)
+    full = _oracle(pr, k=16, lanczos_steps=150)
+    ev, bnd = _ritz_bounds(full.alpha, full.beta)
+    cand = [j for j in range(1, 12) if bnd[j] <= 1e-9 and bnd[j + 1] <= 1e-9]
+    j = max(cand, key=lambda i: (ev[i] - ev[i + 1]) / (1.0 - ev[i + 1]))
+    K = 1.0 / (1.0 - 0.5 * (ev[j] + ev[j + 1]))
+    Po = _oracle(pr, k=16, lanczos_steps=150, cond_K=K)
+    assert Po.k == j + 1
+    G = _slr(pr, k=16, lanczos_steps=150, cond_K=K)
+    assert G.info["k"] == Po.k
+    assert abs(G.info["theta"] - Po.theta) <= 1e-10 * abs(Po.theta)
+    ex = G.export()
+    assert ex["U"].shape[1] == Po.k
+    Pi = _oracle(pr, lowrank=(ex["U"], ex["lambda"], ex["theta"]))
+    r = _rand(pr.n, 2, 5)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= 1e-12
+    K0 = 1.0 / (1.0 - 0.5 * (1.0 + ev[0]))
+    assert _oracle(pr, k=16, lanczos_steps=150, cond_K=K0).k == 0
+    G0 = _slr(pr, k=16, lanczos_steps=150, cond_K=K0)
+    assert G0.info["k"] == 0
+    assert abs(G0.info["theta"] - ev[0]) <= 1e-10 * abs(ev[0])
+    Pz = _oracle(pr, lowrank=(np.zeros((Po.s, 0)), np.zeros(0), G0.info["theta"]))
+    assert _relerr(G0.apply(_dev(r)).cpu().numpy(), Pz.apply(r)).max() <= 1e-12
+
+
 def test_fgmres_indefinite():
     pr = si.make_config("shifted3d_128", N=24, boxes=4, neg=4)
     Po = _oracle(pr, k=16, lanczos_steps=80)
