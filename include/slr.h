@@ -58,12 +58,14 @@ enum {
 };
 
 /* ---- options -------------------------------------------------------------- */
-/* Choice of the shift in eq. skt: theta = lambda_{k+1} (Sec. 4), theta = 0
- * (truncation, eq. Lambda-1), or the eq. Lambda-2 form with parameter eps:
+/* Choice of the shift in eq. skt: theta = lambda_{k+1} (Sec. 4), theta = the
+ * smallest Ritz value of T_m (the lambda_s end of the interval of Sec. 4 on
+ * which the condition number does not change), theta = 0 (truncation,
+ * eq. Lambda-1), or the eq. Lambda-2 form with parameter eps:
  * on the k captured directions 1 - lambda_i is replaced by (1 - lambda_i)/eps,
  * elsewhere theta = 0, i.e. rho = 1 and the diagonal scales become
  * eps/(1 - lambda_i) - 1. */
-enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1, SLR_THETA_EPS = 2 };
+enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1, SLR_THETA_EPS = 2, SLR_THETA_LAMBDA_S = 3 };
 enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2 };
 enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1 };
 enum { SLR_FP64 = 0, SLR_FP32 = 1, SLR_BF16 = 2 };
@@ -81,7 +83,8 @@ typedef struct {
   int32_t k;              /* rank of the correction (Sec. 4); 0 = none        */
   int32_t lanczos_steps;  /* 0 => 5k (Sec. 6)                                 */
   int32_t theta_mode;     /* SLR_THETA_LAMBDA_K1 (Sec. 4) | SLR_THETA_ZERO |
-                             SLR_THETA_EPS (eq. Lambda-2, parameter eps)      */
+                             SLR_THETA_EPS (eq. Lambda-2, parameter eps) |
+                             SLR_THETA_LAMBDA_S (Sec. 4)                      */
   int32_t b_fact;         /* local solver of the B_i (Sec. 5.2): CHOL|IC0|ILDLT0 */
   int32_t c_fact;         /* factor of C = L L^T: CHOL | IC0                  */
   int32_t c_order;        /* ordering of the interface for C's factor         */

@@ -371,8 +371,9 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     (-1 = separator).  lanczos_steps 0 means 5k (Sec. 6).  v0: Lanczos start
     vector in original node order (its interface entries are used).
     lowrank: optional (U, lam, theta) to use instead of running Lanczos.
-    theta_mode "lambda_k1" (theta = lambda_{k+1}, Sec. 4), "zero"
-    (eq. Lambda-1) or "eps" (eq. Lambda-2 with parameter eps > 0).
+    theta_mode "lambda_k1" (theta = lambda_{k+1}, Sec. 4), "lambda_s"
+    (theta = smallest Ritz value, Sec. 4), "zero" (eq. Lambda-1) or "eps"
+    (eq. Lambda-2 with parameter eps > 0).
     cond_K > 1: k becomes the smallest rank (at most the given k) with
     lambda_{k+1} <= 1 - 1/K among the Ritz values (eq. condk)."""
     if theta_mode == "eps" and not eps > 0.0:
@@ -420,14 +421,16 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     return P
 
 
-def lanczos(G, v0: np.ndarray, steps: int):
+def lanczos(G, v0: np.ndarray, steps: int, Z: np.ndarray | None = None):
     """Lanczos with full reorthogonalisation (Sec. 5.1).
 
     READING: full classical Gram-Schmidt applied twice (CGS2) replaces the
     paper's partial reorthogonalisation; stop after ``steps`` steps or when
     beta_j <= 1e-14 ||T_j||_inf.  Returns (V, alpha, beta) with V the
     orthonormal basis actually built (s x m) and beta of length m (its last
-    entry is the residual norm beta_m of the final step)."""
+    entry is the residual norm beta_m of the final step).  Z (s x k0,
+    orthonormal columns, optional): directions already captured; both
+    Gram-Schmidt passes also run against them (deflation, Sec. 5.3)."""
     s = v0.shape[0]
     V = np.zeros((s, steps))
     alpha, beta = [], []
@@ -440,9 +443,10 @@ def lanczos(G, v0: np.ndarray, steps: int):
         w = w - a * v
         if j > 0:
             w = w - beta[j - 1] * V[:, j - 1]
+        Q = V[:, :j + 1] if Z is None else np.hstack([Z, V[:, :j + 1]])
         for _ in range(2):
-            h = V[:, :j + 1].T @ w
-            w = w - V[:, :j + 1] @ h
+            h = Q.T @ w
+            w = w - Q @ h
         b = float(np.linalg.norm(w))
         alpha.append(a)
         row = abs(a) + b + (beta[j - 1] if j > 0 else 0.0)
@@ -458,15 +462,16 @@ def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode
 
     The Ritz pairs of the tridiagonal T_m are sorted by decreasing value;
     the k largest give Lambda_k and U_k = V_m Y_k; theta = lambda_{k+1}
-    (Sec. 4, the paper's choice) or 0 (eq. Lambda-1, truncation, and the
-    eq. Lambda-2 form).  cond_K > 1: the rank is the number of Ritz values
+    (Sec. 4, the paper's choice), the smallest Ritz value (the lambda_s end
+    of the interval of Sec. 4 over which the condition number is flat) or 0
+    (eq. Lambda-1, truncation, and the eq. Lambda-2 form).  cond_K > 1: the rank is the number of Ritz values
     above 1 - 1/K, at most k (eq. condk: lambda_{k+1} <= 1 - 1/K)."""
     V, alpha, beta = lanczos(P.G, v0_iface, steps)
     mm = V.shape[1]
     T = np.diag(alpha) + np.diag(beta[:mm - 1], 1) + np.diag(beta[:mm - 1], -1)
     ev, Y = np.linalg.eigh(T)
     ev, Y = ev[::-1], Y[:, ::-1]
-    need = k + 1 if theta_mode == "lambda_k1" else k
+    need = k + 1 if theta_mode in ("lambda_k1", "lambda_s") else k
     if mm < need:
         raise OracleError("LANCZOS_SHORT", f"{mm} Ritz pairs < {need}")
     if cond_K > 1.0:
@@ -474,7 +479,61 @@ def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode
     P.k = k
     P.lam = ev[:k].copy()
     P.U = V @ Y[:, :k]
-    P.theta = float(ev[k]) if theta_mode == "lambda_k1" else 0.0
+    P.theta = float(ev[k]) if theta_mode == "lambda_k1" else float(ev[-1]) if theta_mode == "lambda_s" else 0.0
+    P.ritz = ev
+    P.steps = mm
+    P.alpha, P.beta = alpha, beta
+    if np.any(np.abs(1.0 - P.lam) < 1e-12) or abs(1.0 - P.theta) < 1e-12:
+        raise OracleError("RITZ_SINGULAR", "Ritz value too close to 1")
+    return P
+
+
+def _take_ritz(ev, k, theta_mode, cond_K):
+    """Rank and theta from descending Ritz values (Sec. 4, eq. condk)."""
+    if cond_K > 1.0:
+        k = min(k, int(np.sum(ev > 1.0 - 1.0 / cond_K)))
+    theta = float(ev[k]) if theta_mode == "lambda_k1" else float(ev[-1]) if theta_mode == "lambda_s" else 0.0
+    return k, theta
+
+
+def grow_lowrank(P: SLR, k_add: int, steps: int, v0_iface: np.ndarray, theta_mode: str = "lambda_k1",
+                 cond_K: float = 0.0):
+    """Add up to k_add vectors to (U_k, Lambda_k) without discarding them
+    (Sec. 5.3, improving an SLR preconditioner by deflation).
+
+    READING: deflated Lanczos.  The start vector (interface entries,
+    normalised) is orthogonalised twice against U_k, and every step's
+    Gram-Schmidt passes include U_k, so the run sees H on the orthogonal
+    complement of the captured directions.  Its k_add largest Ritz pairs
+    are appended: U = [U_k, V_m Y], Lambda = [Lambda_k, new values], and
+    theta follows theta_mode on the new run's Ritz values (lambda_{k+1} is
+    the largest one not taken).  cond_K as in lanczos_lowrank, applied to
+    the new values."""
+    Z = P.U if P.k else None
+    v = np.asarray(v0_iface, dtype=np.float64)
+    nv = np.linalg.norm(v)
+    if not nv > 0.0:
+        raise OracleError("ARG", "Lanczos start vector is zero on the interface")
+    v = v / nv
+    if Z is not None:
+        for _ in range(2):
+            v = v - Z @ (Z.T @ v)
+    if not np.linalg.norm(v) > 1e-12:
+        raise OracleError("ARG", "start vector lies in the span of U_k")
+    V, alpha, beta = lanczos(P.G, v, steps, Z)
+    mm = V.shape[1]
+    T = np.diag(alpha) + np.diag(beta[:mm - 1], 1) + np.diag(beta[:mm - 1], -1)
+    ev, Y = np.linalg.eigh(T)
+    ev, Y = ev[::-1], Y[:, ::-1]
+    need = k_add + 1 if theta_mode in ("lambda_k1", "lambda_s") else k_add
+    if mm < need:
+        raise OracleError("LANCZOS_SHORT", f"{mm} Ritz pairs < {need}")
+    ka, theta = _take_ritz(ev, k_add, theta_mode, cond_K)
+    Unew = V @ Y[:, :ka]
+    P.U = Unew if Z is None else np.hstack([Z, Unew])
+    P.lam = np.concatenate([P.lam[:P.k] if P.k else np.zeros(0), ev[:ka]])
+    P.k = P.U.shape[1]
+    P.theta = 0.0 if theta_mode == "eps" else theta
     P.ritz = ev
     P.steps = mm
     P.alpha, P.beta = alpha, beta

@@ -33,7 +33,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 SLR_OK, SLR_ERR_ARG, SLR_ERR_NOT_SYMMETRIC, SLR_ERR_PARTITION = 0, -1, -2, -3
 SLR_ERR_BREAKDOWN, SLR_ERR_C_NOT_SPD, SLR_ERR_RITZ_SINGULAR, SLR_ERR_LANCZOS_SHORT = -4, -5, -6, -7
 SLR_ERR_NOCONV, SLR_ERR_OOM, SLR_ERR_HIP, SLR_ERR_ADMIT = -8, -9, -10, -11
-SLR_THETA_LAMBDA_K1, SLR_THETA_ZERO, SLR_THETA_EPS = 0, 1, 2
+SLR_THETA_LAMBDA_K1, SLR_THETA_ZERO, SLR_THETA_EPS, SLR_THETA_LAMBDA_S = 0, 1, 2, 3
 SLR_FACT_CHOL, SLR_FACT_IC0, SLR_FACT_ILDLT0 = 0, 1, 2
 SLR_CORDER_SUBDOMAIN, SLR_CORDER_MULTICOLOR = 0, 1
 SLR_FP64, SLR_FP32, SLR_BF16 = 0, 1, 2
@@ -42,7 +42,7 @@ SLR_PCG, SLR_FCG, SLR_FGMRES = 0, 1, 2
 _FACT = {"chol": SLR_FACT_CHOL, "ic0": SLR_FACT_IC0, "ildlt0": SLR_FACT_ILDLT0}
 _PREC = {"fp64": SLR_FP64, "fp32": SLR_FP32, "bf16": SLR_BF16}
 _CORD = {"subdomain": SLR_CORDER_SUBDOMAIN, "multicolor": SLR_CORDER_MULTICOLOR}
-_THETA = {"lambda_k1": SLR_THETA_LAMBDA_K1, "zero": SLR_THETA_ZERO, "eps": SLR_THETA_EPS}
+_THETA = {"lambda_k1": SLR_THETA_LAMBDA_K1, "zero": SLR_THETA_ZERO, "eps": SLR_THETA_EPS, "lambda_s": SLR_THETA_LAMBDA_S}
 _METHOD = {"pcg": SLR_PCG, "fcg": SLR_FCG, "fgmres": SLR_FGMRES}
 
 _P = ctypes.c_void_p

@@ -379,6 +379,7 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   steps = (int32_t)std::min<int64_t>(steps, std::max<int64_t>(s, 1));
   if (steps > 1024) return fail(SLR_ERR_ARG, "at most 1024 Lanczos steps");
   const bool need_k1 = c->opts.theta_mode == SLR_THETA_LAMBDA_K1;
+  const bool lam_s = c->opts.theta_mode == SLR_THETA_LAMBDA_S;
   DevPool tmp;
   double *V = tmp.alloc<double>((size_t)s * steps);
   double *Wl = tmp.alloc<double>(s);
@@ -452,7 +453,7 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
     bprev = bh[j];
     if (bh[j] <= 1e-14 * tnorm) break;
   }
-  const int32_t need = need_k1 ? k + 1 : k;
+  const int32_t need = need_k1 || lam_s ? k + 1 : k;
   if (mm < need) return bail(fail(SLR_ERR_LANCZOS_SHORT, "Lanczos produced fewer Ritz pairs than needed"));
   double *Z = tmp.alloc<double>((size_t)6 * mm * std::max(k, 1));   // eigensolver scratch
   double *ev = tmp.alloc<double>(mm);
@@ -480,7 +481,7 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   }
   c->k = kk;
   c->lam_h.assign(c->ritz_h.begin(), c->ritz_h.begin() + kk);
-  c->theta = need_k1 ? c->ritz_h[kk] : 0.0;
+  c->theta = need_k1 ? c->ritz_h[kk] : lam_s ? c->ritz_h[mm - 1] : 0.0;
   c->info.lanczos_steps = mm;
   return finish_lowrank(c, st);
 }
@@ -760,7 +761,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   if (!A || !part || !o || !out || !A->rowptr || !A->col || !A->val) return fail(SLR_ERR_ARG, "null argument");
   *out = nullptr;
   if (o->k < 0 || o->k > 64) return fail(SLR_ERR_ARG, "k must be in [0, 64]");
-  if (o->theta_mode < SLR_THETA_LAMBDA_K1 || o->theta_mode > SLR_THETA_EPS) return fail(SLR_ERR_ARG, "theta_mode");
+  if (o->theta_mode < SLR_THETA_LAMBDA_K1 || o->theta_mode > SLR_THETA_LAMBDA_S) return fail(SLR_ERR_ARG, "theta_mode");
   if (o->theta_mode == SLR_THETA_EPS && !(o->eps > 0.0)) return fail(SLR_ERR_ARG, "theta_mode eps needs eps > 0");
   if (!(o->cond_K == 0.0 || o->cond_K > 1.0)) return fail(SLR_ERR_ARG, "cond_K must be 0 or > 1");
   if (o->fact_prec != SLR_FP64 && o->fact_prec != SLR_FP32) return fail(SLR_ERR_ARG, "fact_prec");

@@ -266,6 +266,22 @@ def test_eps_form_apply(eps):
     assert _relerr(G2.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= 1e-12
 
 
+def test_theta_lambda_s():
+    """theta = smallest Ritz value (the lambda_s end of Sec. 4's interval):
+    the device takes its own smallest Ritz value; the apply matches the
+    oracle fed with the exported part, and the oracle's own choice agrees
+    to the bar for Ritz values still converging."""
+    pr = si.make_config("lap2d_64", N=40)
+    G = _slr(pr, k=8, lanczos_steps=40, theta_mode="lambda_s")
+    ex = G.export()
+    assert ex["theta"] == ex["ritz"][-1] == G.info["theta"]
+    Po = _oracle(pr, k=8, lanczos_steps=40, theta_mode="lambda_s")
+    assert abs(Po.theta - ex["theta"]) <= 1e-6
+    Pi = _oracle(pr, lowrank=(ex["U"], ex["lambda"], ex["theta"]))
+    r = _rand(pr.n, 2, 6)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= 1e-12
+
+
 def test_rank_from_condition_number():
     """eq. condk: with target K the rank is the number of Ritz values above
     1 - 1/K (at most k).  Cuts are placed midway in the widest gap between

@@ -215,6 +215,8 @@ def _dense_lowrank(P, k, theta_mode="lambda_k1"):
     lam, U = np.linalg.eigh(H)
     lam, U = lam[::-1], U[:, ::-1]
     theta = lam[k] if (theta_mode == "lambda_k1" and k < len(lam)) else 0.0
+    if theta_mode == "lambda_s":
+        theta = lam[-1]
     return H, L, lam, U, theta
 
 
@@ -269,12 +271,13 @@ def _spectrum_MinvA(P):
     return np.sort(np.linalg.eigvals(MA).real)
 
 
-@pytest.mark.parametrize("theta_mode", ["lambda_k1", "zero"])
+@pytest.mark.parametrize("theta_mode", ["lambda_k1", "lambda_s", "zero"])
 def test_P2_P7_spectrum_of_preconditioned_matrix(theta_mode):
     """eig(M^{-1}A) = {1}^(m+k) U {(1 - lambda_i)/(1 - theta)}_{i>k}
     (Prop. eigSS with eq. main; theta = 0 is eq. Lambda-1), and
     kappa(S S~^{-1}) = (1-lambda_s)/(1-lambda_{k+1}) for theta = lambda_{k+1}
-    (Prop. kappa)."""
+    (Prop. kappa) and for theta = lambda_s alike (the condition number is
+    the same for every theta in [lambda_s, lambda_{k+1}], Sec. 4)."""
     csr, part, p = _tiny(10)
     P0 = O.setup(csr, part, p, 0, b_fact="chol", c_fact="chol")
     k = 5
@@ -283,7 +286,7 @@ def test_P2_P7_spectrum_of_preconditioned_matrix(theta_mode):
     got = _spectrum_MinvA(P)
     expect = np.sort(np.concatenate([np.ones(P.m + k), (1 - lam[k:]) / (1 - theta)]))
     assert np.allclose(got, expect, atol=1e-9)
-    if theta_mode == "lambda_k1":
+    if theta_mode in ("lambda_k1", "lambda_s"):
         sig = (1 - lam[k:]) / (1 - theta)
         kappa = max(sig.max(), 1.0) / min(sig.min(), 1.0)
         assert math.isclose(kappa, (1 - lam[-1]) / (1 - lam[k]), rel_tol=1e-12)
@@ -338,6 +341,68 @@ def test_condk_rank_selection():
         # eig(M^{-1}A) = {1}^(m+k) U {(1 - lambda_i)/(1 - theta)}_{i>k}
         spec = _spectrum_MinvA(P)
         assert np.allclose(spec, np.sort(np.concatenate([np.ones(P.m + want), sig])), atol=1e-7)
+
+
+def test_theta_lambda_s_from_lanczos():
+    """theta = lambda_s taken from Lanczos run to the full interface size is
+    the smallest eigenvalue of H, and the condition number of S S~^{-1} is
+    (1 - lambda_s)/(1 - lambda_{k+1}), as for theta = lambda_{k+1}.  The
+    separator model of Sec. 3.2 has lambda_s > 0 (a vertex-based split
+    usually has a singular H, lambda_s = 0, where this is eq. Lambda-1)."""
+    A, part = si.separator_model(20, 10)
+    P0 = O.setup(A, part, 2, 0, b_fact="chol", c_fact="chol")
+    H, _ = _dense_H(P0)
+    ev = np.sort(np.linalg.eigvalsh(H))[::-1]
+    assert ev[-1] > 1e-3
+    k = 6
+    P = O.setup(A, part, 2, k, P0.s, b_fact="chol", c_fact="chol", theta_mode="lambda_s",
+                v0=si.lanczos_start(A[3], 9))
+    assert math.isclose(P.theta, ev[-1], rel_tol=1e-9)
+    spec = _spectrum_MinvA(P)
+    sig = (1 - ev[k:]) / (1 - P.theta)
+    assert np.allclose(spec, np.sort(np.concatenate([np.ones(P.m + k), sig])), atol=1e-7)
+    assert math.isclose(spec.max() / spec.min(), (1 - ev[-1]) / (1 - ev[k]), rel_tol=1e-7)
+
+
+def test_grow_by_deflation_finds_the_next_eigenpairs():
+    """Sec. 5.3: starting from the exact top-3 eigenpairs of H, deflated
+    Lanczos run over the whole complement returns lambda_4..lambda_7 and
+    keeps the old vectors; the grown preconditioner has the spectrum of the
+    rank-7 one, {1}^(m+7) U {(1 - lambda_i)/(1 - lambda_8)}_{i>7}
+    (Prop. eigSS).  Simple spectrum, so single-vector Lanczos sees every
+    eigenvalue once."""
+    N = 14
+    rng = np.random.default_rng(4)
+    csr = si.diffusion_2d(N, np.exp(rng.standard_normal((N + 2, N + 2))))
+    part = si.random_cuts_2d(N, 2, 2, 5)
+    P0 = O.setup(csr, part, 4, 0, b_fact="chol", c_fact="chol")
+    H, L, lam, U, _ = _dense_lowrank(P0, 3)
+    P = O.setup(csr, part, 4, 0, b_fact="chol", c_fact="chol", lowrank=(U[:, :3], lam[:3], lam[3]))
+    v0 = si.lanczos_start(csr[3], 9)[P.perm[P.m:]]
+    O.grow_lowrank(P, 4, P.s - 3, v0)
+    assert P.k == 7
+    assert np.array_equal(P.U[:, :3], U[:, :3])
+    assert np.allclose(P.lam, lam[:7], rtol=1e-9, atol=1e-12)
+    assert math.isclose(P.theta, lam[7], rel_tol=1e-9)
+    assert np.allclose(P.U.T @ P.U, np.eye(7), atol=1e-10)
+    assert np.allclose(np.abs(np.sum(P.U[:, 3:] * U[:, 3:7], axis=0)), 1.0, atol=1e-8)
+    spec = _spectrum_MinvA(P)
+    expect = np.sort(np.concatenate([np.ones(P.m + 7), (1 - lam[7:]) / (1 - lam[7])]))
+    assert np.allclose(spec, expect, atol=1e-7)
+    # a start vector inside span(U_k) is refused
+    with pytest.raises(O.OracleError):
+        O.grow_lowrank(P, 2, 10, P.U[:, 0] + 0.5 * P.U[:, 5])
+
+
+def test_grow_from_nothing_is_plain_lanczos():
+    """With no captured directions deflated Lanczos is the plain build."""
+    csr, part, p = _tiny(12)
+    v0 = si.lanczos_start(csr[3], 4)
+    A = O.setup(csr, part, p, 5, 25, b_fact="ic0", c_fact="ic0", v0=v0)
+    B = O.setup(csr, part, p, 0, b_fact="ic0", c_fact="ic0")
+    O.grow_lowrank(B, 5, 25, v0[B.perm[B.m:]])
+    assert B.k == A.k and np.array_equal(B.lam, A.lam) and B.theta == A.theta
+    assert np.array_equal(B.U, A.U)
 
 
 def test_P3prime_inertia_counts_negative_eigenvalues():
