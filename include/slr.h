@@ -175,11 +175,28 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
 
 /* slr_update_lowrank: rebuild (U_k, Lambda_k, theta) on the device by a
  * fresh Lanczos run on H with the resident factors (Sec. 5.1); k <= 64,
- * lanczos_steps 0 => 5k, lanczos_v0 as in slr_opts (NULL => seed).  An
- * SLR preconditioner can be improved this way without refactoring
- * (Sec. 5.3).  Synchronises hip_stream.  Errors as slr_setup's Lanczos. */
+ * lanczos_steps 0 => 5k, lanczos_v0 as in slr_opts (NULL => seed); the
+ * context's theta_mode, eps and cond_K apply.  An SLR preconditioner can be
+ * improved this way without refactoring (Sec. 5.3).  SLR_ERR_ARG while
+ * batches (slr_batch_create) exist on the context.  Synchronises
+ * hip_stream.  Errors as slr_setup's Lanczos. */
 int slr_update_lowrank(slr_ctx *c, int32_t k, int32_t lanczos_steps, const double *lanczos_v0,
                        void *hip_stream);
+
+/* slr_grow_lowrank: add up to k_add vectors to the resident (U_k, Lambda_k)
+ * without discarding them (Sec. 5.3, by deflation).  A Lanczos run on H
+ * whose start vector (interface entries of lanczos_v0, or the seeded one)
+ * and Gram-Schmidt passes are also orthogonalised against the current U_k
+ * explores H on the complement of the captured directions; its k_add
+ * largest Ritz pairs are appended (fewer under cond_K > 1, eq. condk) and
+ * theta is recomputed from its Ritz values under the context's theta_mode
+ * (lambda_{k+1}: the largest one not taken).  k + k_add <= 64; steps 0 =>
+ * 5 k_add, at most min(s - k, 1024 - k).  A start vector inside span(U_k)
+ * (norm of its projection <= 1e-12 after normalising) is SLR_ERR_ARG.  On
+ * any error the resident low-rank part is unchanged.  SLR_ERR_ARG while
+ * batches exist on the context.  Synchronises hip_stream. */
+int slr_grow_lowrank(slr_ctx *c, int32_t k_add, int32_t lanczos_steps, const double *lanczos_v0,
+                     void *hip_stream);
 
 /* slr_time_kernel: average device time (ms, via HIP events on hip_stream)
  * of `reps` back-to-back launches of one hot-path stage on nrhs internal

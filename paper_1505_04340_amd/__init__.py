@@ -91,6 +91,7 @@ slr_setup = _sig("slr_setup", ctypes.c_int, [ctypes.POINTER(slr_csr), _P, _I32, 
 slr_analyze = _sig("slr_analyze", ctypes.c_int, [ctypes.POINTER(slr_csr), _P, _I32, ctypes.POINTER(slr_opts),
                                                  ctypes.POINTER(slr_info), _P])
 slr_update_lowrank = _sig("slr_update_lowrank", ctypes.c_int, [_P, _I32, _I32, _P, _P])
+slr_grow_lowrank = _sig("slr_grow_lowrank", ctypes.c_int, [_P, _I32, _I32, _P, _P])
 slr_time_kernel = _sig("slr_time_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P, ctypes.POINTER(_D)])
 slr_apply = _sig("slr_apply", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_apply_dd = _sig("slr_apply_dd", ctypes.c_int, [_P, _P, _P, _I32, _P])
@@ -113,6 +114,7 @@ slr_last_error = _sig("slr_last_error", ctypes.c_char_p, [])
 slr_device_lds_bytes = _sig("slr_device_lds_bytes", ctypes.c_int, [])
 
 EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_analyze", "slr_update_lowrank",
+            "slr_grow_lowrank",
             "slr_time_kernel", "slr_apply", "slr_apply_dd",
             "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_spmv",
             "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
@@ -240,6 +242,16 @@ class SLR:
             v0 = np.ascontiguousarray(v0, dtype=np.float64)
             p = v0.ctypes.data
         _check(slr_update_lowrank(self._h, k, lanczos_steps, p, _stream(stream)), "slr_update_lowrank")
+        self.info = self.query()
+
+    def grow_lowrank(self, k_add: int, lanczos_steps: int = 0, v0=None, stream=None):
+        """Append up to k_add Ritz pairs from a deflated Lanczos run, keeping
+        the current ones (slr_grow_lowrank)."""
+        p = None
+        if v0 is not None:
+            v0 = np.ascontiguousarray(v0, dtype=np.float64)
+            p = v0.ctypes.data
+        _check(slr_grow_lowrank(self._h, k_add, lanczos_steps, p, _stream(stream)), "slr_grow_lowrank")
         self.info = self.query()
 
     STAGES = {"bsolve1": 0, "cfwd": 1, "lowrank": 2, "cbwd": 3, "bsolve2": 4, "apply": 5, "spmv": 6}

@@ -79,6 +79,7 @@ std::vector<TS> conv(const std::vector<double> &v) {
 // Scratch of one apply pipeline (one per context, one per batch).
 struct ApplyWS {
   int32_t cap = 0;
+  int32_t k = 0;              // rank the rank-k scratch is sized for
   double *W = nullptr;        // s x cap interface temporary
   double *W2 = nullptr;       // second s x cap interface temporary
   double *lr_part = nullptr;  // lr_nblk x cap x k
@@ -129,6 +130,7 @@ struct slr_ctx {
   // never depends on how many columns share the launch
   int32_t mfma_min_rhs = 1;
   DevPool lrpool;               // U, U64, dsc
+  int32_t live_batches = 0;     // slr_batch objects on this context
   // stats
   slr_info info{};
   ApplyWS ws;
@@ -147,6 +149,7 @@ struct slr_ctx {
 
 struct slr_batch {
   slr_ctx *c = nullptr;
+  bool counted = false;         // included in c->live_batches
   int32_t cap = 0, method = SLR_PCG, maxit = 300;
   double rtol = 1e-8;
   DevPool pool;
@@ -173,7 +176,7 @@ namespace {
 constexpr int RED_NBLK = 512;   // blocks of the deterministic reductions
 
 int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
-  if (w.cap >= nrhs && w.W) return SLR_OK;
+  if (w.cap >= nrhs && w.W && w.k >= std::max(c->k, 1)) return SLR_OK;
   w.pool.release();
   int32_t cap = std::max<int32_t>(nrhs, 1);
   w.W = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
@@ -184,6 +187,7 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   if (!w.W || !w.W2 || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
   HIPCHK(hipMemset(w.counter, 0, 16 * sizeof(unsigned int)));
   w.cap = cap;
+  w.k = std::max(c->k, 1);
   return SLR_OK;
 }
 
@@ -371,17 +375,22 @@ int finish_lowrank(slr_ctx *c, hipStream_t st) {
 }
 
 // Lanczos on H with CGS2 full reorthogonalisation (Sec. 5.1), then the
-// tridiagonal eigensolve and the Ritz vectors U_k = V_m Y_k.
-int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
+// tridiagonal eigensolve and the Ritz vectors U_k = V_m Y_k.  With k0 > 0
+// the first k0 columns of c->U64 (and of c->lam_h) are kept and the run is
+// deflated (Sec. 5.3): the start vector and every Gram-Schmidt pass are
+// orthogonalised against them too, and up to kw new Ritz pairs are appended.
+// The new U64 lives in a fresh pool that replaces c->lrpool only on success,
+// so a failed growth leaves the resident low-rank part as it was.
+int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hipStream_t st) {
   const int64_t s = c->s;
-  const int32_t k = c->k;
-  int32_t steps = c->opts.lanczos_steps > 0 ? c->opts.lanczos_steps : 5 * k;
-  steps = (int32_t)std::min<int64_t>(steps, std::max<int64_t>(s, 1));
-  if (steps > 1024) return fail(SLR_ERR_ARG, "at most 1024 Lanczos steps");
+  int32_t steps = c->opts.lanczos_steps > 0 ? c->opts.lanczos_steps : 5 * kw;
+  steps = (int32_t)std::min<int64_t>(steps, std::max<int64_t>(s - k0, 1));
+  if (k0 + steps > 1024) return fail(SLR_ERR_ARG, "at most 1024 Lanczos steps plus kept vectors");
   const bool need_k1 = c->opts.theta_mode == SLR_THETA_LAMBDA_K1;
   const bool lam_s = c->opts.theta_mode == SLR_THETA_LAMBDA_S;
+  const int32_t nb = k0 + steps;   // basis columns: kept vectors, then the Lanczos vectors
   DevPool tmp;
-  double *V = tmp.alloc<double>((size_t)s * steps);
+  double *V = tmp.alloc<double>((size_t)s * nb);
   double *Wl = tmp.alloc<double>(s);
   double *T = tmp.alloc<double>(s);
   double *T2 = tmp.alloc<double>(s);
@@ -389,7 +398,7 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   double *sc = tmp.alloc<double>(4);
   double *al = tmp.alloc<double>(steps);
   double *be = tmp.alloc<double>(steps);
-  double *part = tmp.alloc<double>((size_t)RED_NBLK * (steps + 1));
+  double *part = tmp.alloc<double>((size_t)RED_NBLK * (nb + 1));
   double *part2 = tmp.alloc<double>((size_t)(s + 255) / 256 + 1);
   unsigned int *cnt = tmp.alloc<unsigned int>(4);
   if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !part2 || !cnt) {
@@ -411,77 +420,108 @@ int lanczos_build(slr_ctx *c, const double *v0_host, hipStream_t st) {
   nv = std::sqrt(nv);
   if (!(nv > 0.0)) return bail(fail(SLR_ERR_ARG, "Lanczos start vector is zero on the interface"));
   for (double &x : v0) x /= nv;
-  HIPCHK(hipMemcpyAsync(V, v0.data(), sizeof(double) * s, hipMemcpyHostToDevice, st));
+  double *V0 = V + (int64_t)k0 * s;
+  if (k0 > 0) {
+    // kept vectors first; the start vector loses its components along them
+    // (two passes) and is normalised again; its norm is checked afterwards
+    HIPCHK(hipMemcpyAsync(V, c->U64, sizeof(double) * s * k0, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(Wl, v0.data(), sizeof(double) * s, hipMemcpyHostToDevice, st));
+    int32_t rb = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int32_t rbh = launch_multidot_partial(s, k0, V, s, Wl, part, RED_NBLK, st);
+      rb = launch_gemv_sub_fold(s, k0, V, s, part, rbh, Wl, nullptr, pass == 1 ? part2 : nullptr, st);
+    }
+    launch_lanczos_next(s, 0, Wl, V0, sc, sc + 2, sc + 3, part2, rb, nullptr, st);
+  } else {
+    HIPCHK(hipMemcpyAsync(V0, v0.data(), sizeof(double) * s, hipMemcpyHostToDevice, st));
+  }
   // All steps are queued without host round-trips.  The stopping test
   // (beta_j <= 1e-14 ||T_j||_inf) is applied afterwards to the recorded
   // coefficients: steps after a breakdown only produce basis columns that
   // are never used.
   // Step j: w = H v_j; two classical Gram-Schmidt passes against
-  // [v_0 .. v_j].  The first pass's coefficient on v_j is v_j . H v_j =
-  // alpha_j (it also removes the beta_{j-1} v_{j-1} term), so the
-  // three-term recurrence is subsumed by the full reorthogonalisation.
+  // [kept vectors, v_0 .. v_j].  The first pass's coefficient on v_j is
+  // v_j . H v_j = alpha_j (it also removes the beta_{j-1} v_{j-1} term), so
+  // the three-term recurrence is subsumed by the full reorthogonalisation.
   for (int32_t j = 0; j < steps; ++j) {
-    double *vj = V + (int64_t)j * s;
+    double *vj = V0 + (int64_t)j * s;
     if ((rc = apply_H(c, vj, Wl, T, T2, st))) return bail(rc);
+    const int32_t J = k0 + j + 1;
     int32_t rb = 0;
     for (int pass = 0; pass < 2; ++pass) {
       // coefficients V^T w as row-chunk partials, folded inside the update
-      // (the first pass's coefficients go to h: h[j] = alpha_j); the second
-      // pass also leaves the partial sums of ||w||^2 in part2
-      const int32_t rbh = launch_multidot_partial(s, j + 1, V, s, Wl, part, RED_NBLK, st);
-      rb = launch_gemv_sub_fold(s, j + 1, V, s, part, rbh, Wl, pass == 0 ? h : nullptr, pass == 1 ? part2 : nullptr,
-                                st);
+      // (the first pass's coefficients go to h: h[k0 + j] = alpha_j); the
+      // second pass also leaves the partial sums of ||w||^2 in part2
+      const int32_t rbh = launch_multidot_partial(s, J, V, s, Wl, part, RED_NBLK, st);
+      rb = launch_gemv_sub_fold(s, J, V, s, part, rbh, Wl, pass == 0 ? h : nullptr, pass == 1 ? part2 : nullptr, st);
     }
-    launch_lanczos_next(s, j, Wl, j + 1 < steps ? V + (int64_t)(j + 1) * s : nullptr, sc, al, be, part2, rb, h + j,
-                        st);
+    launch_lanczos_next(s, j, Wl, j + 1 < steps ? vj + s : nullptr, sc, al, be, part2, rb, h + k0 + j, st);
   }
   std::vector<double> ah(steps), bh(steps);
+  double start_norm = 1.0;
   HIPCHK(hipMemcpyAsync(ah.data(), al, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(bh.data(), be, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+  if (k0 > 0) HIPCHK(hipMemcpyAsync(&start_norm, sc + 3, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  c->alpha_h.clear();
-  c->beta_h.clear();
+  if (!(start_norm > 1e-12)) return bail(fail(SLR_ERR_ARG, "start vector lies in the span of U_k"));
+  std::vector<double> alpha_h, beta_h;
   double tnorm = 0.0, bprev = 0.0;
   int32_t mm = 0;
   for (int32_t j = 0; j < steps; ++j) {
     if (!std::isfinite(ah[j]) || !std::isfinite(bh[j]))
       return bail(fail(SLR_ERR_BREAKDOWN, "non-finite Lanczos coefficients"));
-    c->alpha_h.push_back(ah[j]);
-    c->beta_h.push_back(bh[j]);
+    alpha_h.push_back(ah[j]);
+    beta_h.push_back(bh[j]);
     mm = j + 1;
     tnorm = std::max(tnorm, std::fabs(ah[j]) + bh[j] + bprev);
     bprev = bh[j];
     if (bh[j] <= 1e-14 * tnorm) break;
   }
-  const int32_t need = need_k1 || lam_s ? k + 1 : k;
+  const int32_t need = need_k1 || lam_s ? kw + 1 : kw;
   if (mm < need) return bail(fail(SLR_ERR_LANCZOS_SHORT, "Lanczos produced fewer Ritz pairs than needed"));
-  double *Z = tmp.alloc<double>((size_t)6 * mm * std::max(k, 1));   // eigensolver scratch
+  double *Z = tmp.alloc<double>((size_t)6 * mm * std::max(kw, 1));   // eigensolver scratch
   double *ev = tmp.alloc<double>(mm);
-  double *Y = tmp.alloc<double>((size_t)mm * std::max(k, 1));
+  double *Y = tmp.alloc<double>((size_t)mm * std::max(kw, 1));
   int *info = tmp.alloc<int>(1);
   if (!Z || !ev || !Y || !info) return bail(fail(SLR_ERR_OOM, "eigensolve"));
-  launch_tridiag_eig(mm, al, be, Z, ev, Y, k, info, st);
-  c->U64 = c->lrpool.alloc<double>((size_t)s * std::max(k, 1));
-  if (!c->U64) return bail(fail(SLR_ERR_OOM, "U"));
-  launch_ritz<double>(s, mm, k, V, s, Y, c->U64, c->U64, st);
+  launch_tridiag_eig(mm, al, be, Z, ev, Y, kw, info, st);
+  DevPool nl;
+  double *U64 = nl.alloc<double>((size_t)s * std::max(k0 + kw, 1));
+  if (!U64) return bail(fail(SLR_ERR_OOM, "U"));
+  if (k0 > 0) HIPCHK(hipMemcpyAsync(U64, V, sizeof(double) * s * k0, hipMemcpyDeviceToDevice, st));
+  launch_ritz<double>(s, mm, kw, V0, s, Y, U64 + (int64_t)k0 * s, U64 + (int64_t)k0 * s, st);
   int info_h = 0;
-  c->ritz_h.assign(mm, 0.0);
+  std::vector<double> ritz(mm, 0.0);
   HIPCHK(hipMemcpyAsync(&info_h, info, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(c->ritz_h.data(), ev, sizeof(double) * mm, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ritz.data(), ev, sizeof(double) * mm, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   tmp.release();
-  if (info_h) return fail(SLR_ERR_BREAKDOWN, "tridiagonal eigensolve did not converge");
-  // eq. condk: keep the Ritz values above 1 - 1/K (at most k); the first
-  // k' columns of U are the Ritz vectors of the k' largest values
-  int32_t kk = k;
+  if (info_h) {
+    nl.release();
+    return fail(SLR_ERR_BREAKDOWN, "tridiagonal eigensolve did not converge");
+  }
+  // eq. condk: keep the new Ritz values above 1 - 1/K (at most kw); the
+  // first k' new columns are the Ritz vectors of the k' largest values
+  int32_t kk = kw;
   if (c->opts.cond_K > 1.0) {
     const double cut = 1.0 - 1.0 / c->opts.cond_K;
     kk = 0;
-    while (kk < k && c->ritz_h[kk] > cut) ++kk;
+    while (kk < kw && ritz[kk] > cut) ++kk;
   }
-  c->k = kk;
-  c->lam_h.assign(c->ritz_h.begin(), c->ritz_h.begin() + kk);
-  c->theta = need_k1 ? c->ritz_h[kk] : lam_s ? c->ritz_h[mm - 1] : 0.0;
+  std::vector<double> lam(c->lam_h.begin(), c->lam_h.begin() + k0);
+  lam.insert(lam.end(), ritz.begin(), ritz.begin() + kk);
+  // commit: the new basis replaces the old low-rank part
+  c->lrpool.release();
+  c->lrpool = nl;
+  c->U64 = U64;
+  c->U = nullptr;
+  c->dsc = nullptr;
+  c->k = k0 + kk;
+  c->lam_h = lam;
+  c->ritz_h = ritz;
+  c->alpha_h = alpha_h;
+  c->beta_h = beta_h;
+  c->theta = need_k1 ? ritz[kk] : lam_s ? ritz[mm - 1] : 0.0;
   c->info.lanczos_steps = mm;
   return finish_lowrank(c, st);
 }
@@ -701,6 +741,18 @@ const double *seeded_v0(int64_t n, uint64_t seed, std::vector<double> &v0) {
   return v0.data();
 }
 
+// After a change of the low-rank part: workspace sized for the new k, stats.
+int lowrank_done(slr_ctx *c, double t1, hipStream_t st) {
+  int rc = ws_ensure(c, c->ws, std::max(c->ws.cap, 1));
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  c->info.k = c->k;
+  c->info.theta = c->theta;
+  c->info.setup_lanczos_s = now_s() - t1;
+  c->info.device_bytes = c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes;
+  return SLR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -856,7 +908,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
     c->k = o->k;
     std::vector<double> v0;
     const double *v0p = o->lanczos_v0 ? o->lanczos_v0 : seeded_v0(c->n, o->seed, v0);
-    if ((rc = lanczos_build(c, v0p, st))) return destroy_fail(rc);
+    if ((rc = lanczos_build(c, o->k, 0, v0p, st))) return destroy_fail(rc);
   } else {
     c->k = 0;
     c->theta = 0.0;
@@ -875,16 +927,9 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
 int slr_update_lowrank(slr_ctx *c, int32_t k, int32_t lanczos_steps, const double *lanczos_v0,
                        void *hip_stream) {
   if (!c || k < 0 || k > 64 || lanczos_steps < 0) return fail(SLR_ERR_ARG, "bad update arguments");
+  if (c->live_batches > 0) return fail(SLR_ERR_ARG, "the context still has batches");
   hipStream_t st = S(hip_stream);
   HIPCHK(hipStreamSynchronize(st));
-  c->lrpool.release();
-  c->U = nullptr;
-  c->U64 = nullptr;
-  c->dsc = nullptr;
-  c->ws.pool.release();
-  c->ws.cap = 0;
-  c->ws.W = nullptr;
-  c->k = k;
   c->opts.k = k;
   c->opts.lanczos_steps = lanczos_steps;
   const double t1 = now_s();
@@ -892,21 +937,38 @@ int slr_update_lowrank(slr_ctx *c, int32_t k, int32_t lanczos_steps, const doubl
   if (k > 0 && c->s > 0) {
     std::vector<double> v0;
     const double *v0p = lanczos_v0 ? lanczos_v0 : seeded_v0(c->n, c->opts.seed, v0);
-    rc = lanczos_build(c, v0p, st);
+    rc = lanczos_build(c, k, 0, v0p, st);
   } else {
+    c->lrpool.release();
+    c->U = nullptr;
+    c->U64 = nullptr;
+    c->dsc = nullptr;
     c->k = 0;
     c->theta = 0.0;
     c->lam_h.clear();
     c->ritz_h.clear();
     rc = finish_lowrank(c, st);
   }
-  if (rc) return rc;
-  if ((rc = ws_ensure(c, c->ws, 1))) return rc;
+  return rc ? rc : lowrank_done(c, t1, st);
+}
+
+int slr_grow_lowrank(slr_ctx *c, int32_t k_add, int32_t lanczos_steps, const double *lanczos_v0,
+                     void *hip_stream) {
+  if (!c || k_add <= 0 || lanczos_steps < 0 || c->k + k_add > 64) return fail(SLR_ERR_ARG, "bad grow arguments");
+  if (c->live_batches > 0) return fail(SLR_ERR_ARG, "the context still has batches");
+  if (c->s == 0) return fail(SLR_ERR_ARG, "no interface");
+  hipStream_t st = S(hip_stream);
   HIPCHK(hipStreamSynchronize(st));
-  c->info.k = c->k;
-  c->info.theta = c->theta;
-  c->info.setup_lanczos_s = now_s() - t1;
-  return SLR_OK;
+  const int32_t steps_keep = c->opts.lanczos_steps;
+  c->opts.lanczos_steps = lanczos_steps;
+  const double t1 = now_s();
+  std::vector<double> v0;
+  const double *v0p = lanczos_v0 ? lanczos_v0 : seeded_v0(c->n, c->opts.seed, v0);
+  const int rc = lanczos_build(c, k_add, c->k, v0p, st);
+  c->opts.lanczos_steps = steps_keep;
+  if (rc) return rc;
+  c->opts.k = c->k;
+  return lowrank_done(c, t1, st);
 }
 
 int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void *hip_stream, double *ms) {
@@ -1335,12 +1397,15 @@ int slr_batch_create(slr_ctx *c, int32_t max_cols, int32_t method, double rtol, 
   }
   b->owner.assign(max_cols, -1);
   b->st_h.resize(max_cols);
+  ++c->live_batches;
+  b->counted = true;
   *out = b;
   return SLR_OK;
 }
 
 void slr_batch_destroy(slr_batch *b) {
   if (!b) return;
+  if (b->counted) --b->c->live_batches;
   b->pool.release();
   b->ws.pool.release();
   delete b;
