@@ -18,6 +18,7 @@ triangular sweeps are the plain C loops in ``sparse_loops.c``.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass, field
 
@@ -304,6 +305,7 @@ class SLR:
     eps: float = 0.0            # > 0: the eq. Lambda-2 choice of Lambda~ (theta unused)
     ritz: np.ndarray = None     # all Ritz values of T_m, descending
     steps: int = 0
+    reorth_steps: list = field(default_factory=list)   # partial reorthogonalisation: steps cleaned
     alpha: np.ndarray = None
     beta: np.ndarray = None
     colors: np.ndarray = None
@@ -364,7 +366,7 @@ class SLR:
 def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "ic0",
           c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
           fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
-          lowrank=None, eps: float = 0.0, cond_K: float = 0.0) -> SLR:
+          lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "full") -> SLR:
     """Build the SLR preconditioner (Sec. 4 and Sec. 5).
 
     A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
@@ -375,7 +377,9 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     (theta = smallest Ritz value, Sec. 4), "zero" (eq. Lambda-1) or "eps"
     (eq. Lambda-2 with parameter eps > 0).
     cond_K > 1: k becomes the smallest rank (at most the given k) with
-    lambda_{k+1} <= 1 - 1/K among the Ritz values (eq. condk)."""
+    lambda_{k+1} <= 1 - 1/K among the Ritz values (eq. condk).  reorth:
+    Lanczos with full ("full") or partial ("partial", Sec. 5.1)
+    reorthogonalisation."""
     if theta_mode == "eps" and not eps > 0.0:
         raise OracleError("ARG", "theta_mode eps needs eps > 0")
     if isinstance(A, tuple):
@@ -407,7 +411,7 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
         steps = lanczos_steps or 5 * k
         if v0 is None:
             v0 = np.random.Generator(np.random.PCG64(7)).uniform(-1, 1, A.shape[0])
-        lanczos_lowrank(P, k, steps, np.asarray(v0)[perm[m:]], theta_mode, cond_K)
+        lanczos_lowrank(P, k, steps, np.asarray(v0)[perm[m:]], theta_mode, cond_K, reorth)
     else:
         P.theta = 0.0
     if theta_mode == "eps":
@@ -457,7 +461,93 @@ def lanczos(G, v0: np.ndarray, steps: int, Z: np.ndarray | None = None):
         V[:, j + 1] = w / b
 
 
-def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode: str, cond_K: float = 0.0):
+EPS = 2.0 ** -52
+
+
+def lanczos_pro(G, v0: np.ndarray, steps: int, stats: dict | None = None):
+    """Lanczos with partial reorthogonalisation (Sec. 5.1, the scheme of
+    Parlett and Simon): the three-term recurrence, plus a classical
+    Gram-Schmidt pass against all previous vectors only on steps where
+    estimated orthogonality is lost.
+
+    The estimates omega_{j+1,l} ~ v_{j+1}.v_l follow from the computed
+    recurrence beta_j v_{j+1} = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}
+    taken against v_l and the same relation for v_l:
+        beta_j om_{j+1,l} = beta_l om_{j,l+1} + (alpha_l - alpha_j) om_{j,l}
+                            + beta_{l-1} om_{j,l-1} - beta_{j-1} om_{j-1,l},
+    with om_{i,i} = 1.  READINGS (the paper only names the scheme): the
+    rounding term e = eps sqrt(s) ||T_j|| is added to each estimate with
+    its sign and om_{j+1,j} = e / beta_j (before the division); ||T_j|| is
+    the running max of |alpha_i| + beta_i + beta_{i-1} with beta_i taken
+    before any reorthogonalisation; when max_l |om_{j+1,l}| > sqrt(eps)
+    the new vector and the one after it are reorthogonalised (one pass
+    against all previous vectors) and their estimates reset to e / beta_j;
+    alpha_j is not updated by the pass, beta_j is the norm after it.
+    Stops as ``lanczos``.  stats (optional dict) receives "reorth", the
+    list of reorthogonalised steps."""
+    s = v0.shape[0]
+    V = np.zeros((s, steps))
+    alpha, beta = [], []
+    V[:, 0] = v0 / np.linalg.norm(v0)
+    tnorm = 0.0        # stopping test, as in lanczos
+    tpro = 0.0         # ||T_j|| of the rounding term
+    om_prev = np.zeros(0)      # om_{j-1, l}, l < j-1
+    om_cur = np.zeros(0)       # om_{j, l},   l < j
+    force = False
+    done = []
+    for j in range(steps):
+        v = V[:, j]
+        w = G(v)
+        a = float(v @ w)
+        w = w - a * v
+        bm = beta[j - 1] if j > 0 else 0.0
+        if j > 0:
+            w = w - bm * V[:, j - 1]
+        bpre = float(np.linalg.norm(w))
+        tpro = max(tpro, abs(a) + bpre + bm)
+        e = EPS * math.sqrt(s) * tpro
+
+        def cur(l):            # om_{j,l} with the unit diagonal
+            return 1.0 if l == j else om_cur[l]
+
+        def prev(l):           # om_{j-1,l}
+            return 1.0 if l == j - 1 else om_prev[l]
+
+        new = np.zeros(j + 1)
+        for l in range(j):
+            t = beta[l] * cur(l + 1) + (alpha[l] - a) * cur(l) - bm * prev(l)
+            if l > 0:
+                t += beta[l - 1] * cur(l - 1)
+            t += math.copysign(e, t)
+            new[l] = t / bpre if bpre > 0 else 1.0
+        psi = e / bpre if bpre > 0 else 1.0
+        new[j] = psi
+        big = bool(np.max(np.abs(new)) > math.sqrt(EPS))
+        if force:
+            do, force = True, False
+        elif big:
+            do, force = True, True
+        else:
+            do = False
+        if do:
+            Q = V[:, :j + 1]
+            w = w - Q @ (Q.T @ w)
+            new[:] = psi
+            done.append(j)
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        tnorm = max(tnorm, abs(a) + b + bm)
+        if j + 1 == steps or b <= 1e-14 * tnorm:
+            if stats is not None:
+                stats["reorth"] = done
+            return V[:, :j + 1], np.array(alpha), np.array(beta + [b])
+        beta.append(b)
+        V[:, j + 1] = w / b
+        om_prev, om_cur = om_cur, new
+
+
+def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode: str, cond_K: float = 0.0,
+                    reorth: str = "full"):
     """(U_k, Lambda_k, theta) from Lanczos on H (Sec. 5.1, eq. skt).
 
     The Ritz pairs of the tridiagonal T_m are sorted by decreasing value;
@@ -465,8 +555,14 @@ def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode
     (Sec. 4, the paper's choice), the smallest Ritz value (the lambda_s end
     of the interval of Sec. 4 over which the condition number is flat) or 0
     (eq. Lambda-1, truncation, and the eq. Lambda-2 form).  cond_K > 1: the rank is the number of Ritz values
-    above 1 - 1/K, at most k (eq. condk: lambda_{k+1} <= 1 - 1/K)."""
-    V, alpha, beta = lanczos(P.G, v0_iface, steps)
+    above 1 - 1/K, at most k (eq. condk: lambda_{k+1} <= 1 - 1/K).
+    reorth: "full" (CGS2 every step) or "partial" (lanczos_pro)."""
+    if reorth == "partial":
+        st = {}
+        V, alpha, beta = lanczos_pro(P.G, v0_iface, steps, st)
+        P.reorth_steps = st["reorth"]
+    else:
+        V, alpha, beta = lanczos(P.G, v0_iface, steps)
     mm = V.shape[1]
     T = np.diag(alpha) + np.diag(beta[:mm - 1], 1) + np.diag(beta[:mm - 1], -1)
     ev, Y = np.linalg.eigh(T)

@@ -405,6 +405,67 @@ def test_grow_from_nothing_is_plain_lanczos():
     assert np.array_equal(B.U, A.U)
 
 
+def _ritz_and_bounds(alpha, beta):
+    mm = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:mm - 1], 1) + np.diag(beta[:mm - 1], -1)
+    ev, Y = np.linalg.eigh(T)
+    return ev[::-1], beta[-1] * np.abs(Y[-1, ::-1])
+
+
+def test_partial_reorthogonalisation_keeps_semiorthogonality():
+    """Sec. 5.1: without reorthogonalisation the Lanczos vectors lose
+    orthogonality once Ritz values converge; the partial scheme keeps
+    max |V^T V - I| below sqrt(eps) while cleaning only a few steps, and its
+    converged Ritz values equal those of full reorthogonalisation (semi-
+    orthogonality makes T_m the projection of H up to O(eps ||H||))."""
+    pr = si.make_config("diffusion2d_1024", N=96, boxes=4)
+    P = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=pr.b_fact, c_fact=pr.c_fact)
+    v0 = pr.v0()[P.perm[P.m:]]
+    steps = 150
+    # no reorthogonalisation at all: the plain three-term recurrence
+    Vp = np.zeros((P.s, steps))
+    Vp[:, 0] = v0 / np.linalg.norm(v0)
+    bprev = 0.0
+    for j in range(steps - 1):
+        w = P.G(Vp[:, j])
+        a = Vp[:, j] @ w
+        w = w - a * Vp[:, j] - (bprev * Vp[:, j - 1] if j else 0.0)
+        bprev = np.linalg.norm(w)
+        Vp[:, j + 1] = w / bprev
+    assert np.abs(Vp.T @ Vp - np.eye(steps)).max() > 1e-4
+    st = {}
+    V, al, be = O.lanczos_pro(P.G, v0, steps, st)
+    assert V.shape[1] == steps
+    assert np.abs(V.T @ V - np.eye(steps)).max() <= math.sqrt(O.EPS)
+    assert 0 < len(st["reorth"]) < steps // 4
+    Vf, af, bf = O.lanczos(P.G, v0, steps)
+    ep, bp = _ritz_and_bounds(al, be)
+    ef, bfd = _ritz_and_bounds(af, bf)
+    conv = (bp[:20] <= 1e-9) & (bfd[:20] <= 1e-9)
+    assert conv.sum() >= 3
+    assert np.all(np.abs(ep[:20] - ef[:20])[conv] <= 1e-10 * np.abs(ef[:20])[conv])
+
+
+def test_partial_reorthogonalisation_spectrum_exact_problem():
+    """With exact B and C solves and as many steps as interface nodes, the
+    partial scheme's Ritz values are the eigenvalues of H (simple spectrum)
+    and the rank-k preconditioner has the spectrum of Prop. eigSS."""
+    N = 14
+    rng = np.random.default_rng(4)
+    csr = si.diffusion_2d(N, np.exp(rng.standard_normal((N + 2, N + 2))))
+    part = si.random_cuts_2d(N, 2, 2, 5)
+    P0 = O.setup(csr, part, 4, 0, b_fact="chol", c_fact="chol")
+    H, _ = _dense_H(P0)
+    ev = np.sort(np.linalg.eigvalsh(H))[::-1]
+    k = 6
+    P = O.setup(csr, part, 4, k, P0.s, b_fact="chol", c_fact="chol", v0=si.lanczos_start(csr[3], 9),
+                reorth="partial")
+    assert np.allclose(P.ritz[:k + 1], ev[:k + 1], rtol=1e-9, atol=1e-12)
+    spec = _spectrum_MinvA(P)
+    sig = (1 - ev[k:]) / (1 - P.theta)
+    assert np.allclose(spec, np.sort(np.concatenate([np.ones(P.m + k), sig])), atol=1e-7)
+
+
 def test_P3prime_inertia_counts_negative_eigenvalues():
     """Indefinite A with SPD B (exact solves): by Sylvester's law on
     eq. Schur, #{lambda(H) > 1} = #negative eigenvalues of A."""
