@@ -136,6 +136,7 @@ def measure_form(P, pr, form, steps, warmup, v0, bd, xs, log_prefix):
     res = {"steps_per_s": round(steps / el, 4), "ms_per_step": round(1e3 * el / steps, 3), "iters": iters[-1],
            "final_relres_fp64": relres, "max_abs_err_vs_xstar": err,
            "solve_only_solves_per_s": round(solve_only, 3), "lanczos_build_ms": round(lanczos_ms, 3),
+           "lanczos_reorth_steps": G.query()["lanczos_reorth"],
            "apply_ms": round(stages["apply"], 5),
            "apply_algorithmic_GBs": round(apply_bytes(info, 1, bf, bu, info["k"]) / (stages["apply"] * 1e-3) / 1e9, 2),
            "stage_ms": {k: round(v, 5) for k, v in stages.items()}}

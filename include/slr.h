@@ -70,6 +70,12 @@ enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2 };
 enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1 };
 enum { SLR_FP64 = 0, SLR_FP32 = 1, SLR_BF16 = 2 };
 enum { SLR_PCG = 0, SLR_FCG = 1, SLR_FGMRES = 2 };
+/* Reorthogonalisation of the Lanczos build (Sec. 5.1): two classical
+ * Gram-Schmidt passes against all previous vectors on every step, or the
+ * partial scheme of Parlett and Simon (one pass, only on steps where the
+ * omega recurrence estimates a loss of orthogonality beyond sqrt(eps), and
+ * on the step after). */
+enum { SLR_REORTH_FULL = 0, SLR_REORTH_PARTIAL = 1 };
 
 typedef struct {
   int64_t n;              /* order of A                                      */
@@ -112,6 +118,9 @@ typedef struct {
      keeps k.  Values in (0, 1] are SLR_ERR_ARG.  Ignored for an imported
      low-rank part. */
   double cond_K;
+  /* SLR_REORTH_FULL | SLR_REORTH_PARTIAL.  slr_grow_lowrank always uses
+     full reorthogonalisation (the omega estimates do not cover U_k). */
+  int32_t reorth;
 } slr_opts;
 
 typedef struct {
@@ -142,6 +151,7 @@ typedef struct {
   double setup_host_s;    /* host factorisation + analysis time              */
   double setup_lanczos_s; /* device Lanczos + eigensolve time                */
   int64_t device_bytes;   /* persistent device memory held by the context    */
+  int32_t lanczos_reorth; /* Lanczos steps that were reorthogonalised        */
 } slr_info;
 
 typedef struct slr_ctx slr_ctx;

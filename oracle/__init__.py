@@ -366,7 +366,7 @@ class SLR:
 def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "ic0",
           c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
           fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
-          lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "full") -> SLR:
+          lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "partial") -> SLR:
     """Build the SLR preconditioner (Sec. 4 and Sec. 5).
 
     A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
@@ -547,7 +547,7 @@ def lanczos_pro(G, v0: np.ndarray, steps: int, stats: dict | None = None):
 
 
 def lanczos_lowrank(P: SLR, k: int, steps: int, v0_iface: np.ndarray, theta_mode: str, cond_K: float = 0.0,
-                    reorth: str = "full"):
+                    reorth: str = "partial"):
     """(U_k, Lambda_k, theta) from Lanczos on H (Sec. 5.1, eq. skt).
 
     The Ritz pairs of the tridiagonal T_m are sorted by decreasing value;

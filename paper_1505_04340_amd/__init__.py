@@ -38,12 +38,14 @@ SLR_FACT_CHOL, SLR_FACT_IC0, SLR_FACT_ILDLT0 = 0, 1, 2
 SLR_CORDER_SUBDOMAIN, SLR_CORDER_MULTICOLOR = 0, 1
 SLR_FP64, SLR_FP32, SLR_BF16 = 0, 1, 2
 SLR_PCG, SLR_FCG, SLR_FGMRES = 0, 1, 2
+SLR_REORTH_FULL, SLR_REORTH_PARTIAL = 0, 1
 
 _FACT = {"chol": SLR_FACT_CHOL, "ic0": SLR_FACT_IC0, "ildlt0": SLR_FACT_ILDLT0}
 _PREC = {"fp64": SLR_FP64, "fp32": SLR_FP32, "bf16": SLR_BF16}
 _CORD = {"subdomain": SLR_CORDER_SUBDOMAIN, "multicolor": SLR_CORDER_MULTICOLOR}
 _THETA = {"lambda_k1": SLR_THETA_LAMBDA_K1, "zero": SLR_THETA_ZERO, "eps": SLR_THETA_EPS, "lambda_s": SLR_THETA_LAMBDA_S}
 _METHOD = {"pcg": SLR_PCG, "fcg": SLR_FCG, "fgmres": SLR_FGMRES}
+_REORTH = {"full": SLR_REORTH_FULL, "partial": SLR_REORTH_PARTIAL}
 
 _P = ctypes.c_void_p
 _I32, _I64, _D, _U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
@@ -57,7 +59,7 @@ class slr_opts(ctypes.Structure):
     _fields_ = [("k", _I32), ("lanczos_steps", _I32), ("theta_mode", _I32), ("b_fact", _I32),
                 ("c_fact", _I32), ("c_order", _I32), ("fact_prec", _I32), ("uk_prec", _I32),
                 ("seed", _U64), ("lanczos_v0", _P), ("k_in", _I32), ("U_in", _P),
-                ("lambda_in", _P), ("theta_in", _D), ("eps", _D), ("cond_K", _D)]
+                ("lambda_in", _P), ("theta_in", _D), ("eps", _D), ("cond_K", _D), ("reorth", _I32)]
 
 
 class slr_solve_opts(ctypes.Structure):
@@ -74,7 +76,8 @@ class slr_info(ctypes.Structure):
                 ("lanczos_steps", _I32), ("b_levels_max", _I32), ("c_levels", _I32),
                 ("c_colors", _I32), ("nnz_LB", _I64), ("nnz_LC", _I64), ("nnz_E", _I64),
                 ("nnz_A", _I64), ("m_min", _I64), ("m_max", _I64), ("theta", _D),
-                ("setup_host_s", _D), ("setup_lanczos_s", _D), ("device_bytes", _I64)]
+                ("setup_host_s", _D), ("setup_lanczos_s", _D), ("device_bytes", _I64),
+                ("lanczos_reorth", _I32)]
 
 
 def _sig(name, res, args):
@@ -161,7 +164,8 @@ def _csr_arrays(A):
 
 
 def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fact="ic0",
-               c_order="subdomain", fact_prec="fp64", uk_prec="fp64", seed=7, eps=0.0, cond_K=0.0):
+               c_order="subdomain", fact_prec="fp64", uk_prec="fp64", seed=7, eps=0.0, cond_K=0.0,
+               reorth=None):
     o = slr_opts()
     slr_default_opts(ctypes.byref(o))
     o.k = k
@@ -172,6 +176,8 @@ def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fa
     o.fact_prec, o.uk_prec = _PREC[fact_prec], _PREC[uk_prec]
     o.seed = seed
     o.eps, o.cond_K = float(eps), float(cond_K)
+    if reorth is not None:
+        o.reorth = _REORTH[reorth]
     return o
 
 
@@ -194,11 +200,13 @@ class SLR:
     def __init__(self, A, part, nparts: int, k: int = 16, lanczos_steps: int = 0,
                  theta_mode: str = "lambda_k1", b_fact: str = "ic0", c_fact: str = "ic0",
                  c_order: str = "subdomain", fact_prec: str = "fp64", uk_prec: str = "fp64",
-                 v0=None, seed: int = 7, lowrank=None, eps: float = 0.0, cond_K: float = 0.0, stream=None):
+                 v0=None, seed: int = 7, lowrank=None, eps: float = 0.0, cond_K: float = 0.0,
+                 reorth: str | None = None, stream=None):
         indptr, indices, data, n = _csr_arrays(A)
         self.n = n
         part = np.ascontiguousarray(part, dtype=np.int32)
-        o = _make_opts(k, lanczos_steps, theta_mode, b_fact, c_fact, c_order, fact_prec, uk_prec, seed, eps, cond_K)
+        o = _make_opts(k, lanczos_steps, theta_mode, b_fact, c_fact, c_order, fact_prec, uk_prec, seed, eps, cond_K,
+                       reorth)
         keep = []
         if v0 is not None:
             v0 = np.ascontiguousarray(v0, dtype=np.float64)

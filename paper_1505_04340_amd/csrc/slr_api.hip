@@ -389,6 +389,7 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   const bool need_k1 = c->opts.theta_mode == SLR_THETA_LAMBDA_K1;
   const bool lam_s = c->opts.theta_mode == SLR_THETA_LAMBDA_S;
   const int32_t nb = k0 + steps;   // basis columns: kept vectors, then the Lanczos vectors
+  const bool pro = c->opts.reorth == SLR_REORTH_PARTIAL && k0 == 0;
   DevPool tmp;
   double *V = tmp.alloc<double>((size_t)s * nb);
   double *Wl = tmp.alloc<double>(s);
@@ -401,7 +402,14 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   double *part = tmp.alloc<double>((size_t)RED_NBLK * (nb + 1));
   double *part2 = tmp.alloc<double>((size_t)(s + 255) / 256 + 1);
   unsigned int *cnt = tmp.alloc<unsigned int>(4);
-  if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !part2 || !cnt) {
+  // partial reorthogonalisation state: three omega rows, control words,
+  // running ||T||, per-step decisions
+  const int32_t ld_om = steps + 2;
+  double *om = tmp.alloc<double>((size_t)3 * ld_om);
+  int *ctl = tmp.alloc<int>(4);
+  double *tn = tmp.alloc<double>(1);
+  int *rflag = tmp.alloc<int>(steps);
+  if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !part2 || !cnt || !om || !ctl || !tn || !rflag) {
     tmp.release();
     return fail(SLR_ERR_OOM, "Lanczos basis");
   }
@@ -412,6 +420,9 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   };
   HIPCHK(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned int), st));
   HIPCHK(hipMemsetAsync(sc, 0, 4 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(ctl, 0, 4 * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(tn, 0, sizeof(double), st));
+  HIPCHK(hipMemsetAsync(rflag, 0, sizeof(int) * steps, st));
   // start vector: interface entries of v0 (original order), normalised
   std::vector<double> v0(s);
   for (int64_t q = 0; q < s; ++q) v0[q] = v0_host[c->perm_h[c->m + q]];
@@ -443,7 +454,21 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   // [kept vectors, v_0 .. v_j].  The first pass's coefficient on v_j is
   // v_j . H v_j = alpha_j (it also removes the beta_{j-1} v_{j-1} term), so
   // the three-term recurrence is subsumed by the full reorthogonalisation.
-  for (int32_t j = 0; j < steps; ++j) {
+  for (int32_t j = 0; j < steps && pro; ++j) {
+    // partial reorthogonalisation: three-term step, omega estimates, and a
+    // gated Gram-Schmidt pass against v_0 .. v_j that runs only when the
+    // control kernel asks for it; beta_j is folded from whichever of the
+    // two kernels wrote the ||w||^2 partials last
+    double *vj = V0 + (int64_t)j * s;
+    if ((rc = apply_H(c, vj, Wl, T, T2, st))) return bail(rc);
+    const int32_t rba = launch_multidot_partial(s, 1, vj, s, Wl, part, RED_NBLK, st);
+    const int32_t rb = launch_lanczos_axpy(s, Wl, vj, j > 0 ? vj - s : nullptr, sc, part, rba, part2, st);
+    launch_pro(j, s, al, be, sc, part2, rb, om, ld_om, ctl, tn, rflag, st);
+    const int32_t rbh = launch_multidot_partial(s, j + 1, V0, s, Wl, part, RED_NBLK, st, ctl);
+    launch_gemv_sub_fold(s, j + 1, V0, s, part, rbh, Wl, nullptr, part2, st, ctl);
+    launch_lanczos_next(s, j, Wl, j + 1 < steps ? vj + s : nullptr, sc, al, be, part2, rb, nullptr, st);
+  }
+  for (int32_t j = 0; j < steps && !pro; ++j) {
     double *vj = V0 + (int64_t)j * s;
     if ((rc = apply_H(c, vj, Wl, T, T2, st))) return bail(rc);
     const int32_t J = k0 + j + 1;
@@ -462,6 +487,8 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   HIPCHK(hipMemcpyAsync(ah.data(), al, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(bh.data(), be, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
   if (k0 > 0) HIPCHK(hipMemcpyAsync(&start_norm, sc + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+  std::vector<int> rf(steps, 0);
+  if (pro) HIPCHK(hipMemcpyAsync(rf.data(), rflag, sizeof(int) * steps, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (!(start_norm > 1e-12)) return bail(fail(SLR_ERR_ARG, "start vector lies in the span of U_k"));
   std::vector<double> alpha_h, beta_h;
@@ -477,6 +504,8 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
     bprev = bh[j];
     if (bh[j] <= 1e-14 * tnorm) break;
   }
+  int32_t nre = pro ? 0 : mm;
+  for (int32_t j = 0; pro && j < mm; ++j) nre += rf[j] != 0;
   const int32_t need = need_k1 || lam_s ? kw + 1 : kw;
   if (mm < need) return bail(fail(SLR_ERR_LANCZOS_SHORT, "Lanczos produced fewer Ritz pairs than needed"));
   double *Z = tmp.alloc<double>((size_t)6 * mm * std::max(kw, 1));   // eigensolver scratch
@@ -523,6 +552,7 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   c->beta_h = beta_h;
   c->theta = need_k1 ? ritz[kk] : lam_s ? ritz[mm - 1] : 0.0;
   c->info.lanczos_steps = mm;
+  c->info.lanczos_reorth = nre;
   return finish_lowrank(c, st);
 }
 
@@ -770,6 +800,7 @@ void slr_default_opts(slr_opts *o) {
   o->seed = 7;
   o->eps = 0.0;
   o->cond_K = 0.0;
+  o->reorth = SLR_REORTH_PARTIAL;
 }
 
 void slr_default_solve_opts(slr_solve_opts *o) {
@@ -816,6 +847,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   if (o->theta_mode < SLR_THETA_LAMBDA_K1 || o->theta_mode > SLR_THETA_LAMBDA_S) return fail(SLR_ERR_ARG, "theta_mode");
   if (o->theta_mode == SLR_THETA_EPS && !(o->eps > 0.0)) return fail(SLR_ERR_ARG, "theta_mode eps needs eps > 0");
   if (!(o->cond_K == 0.0 || o->cond_K > 1.0)) return fail(SLR_ERR_ARG, "cond_K must be 0 or > 1");
+  if (o->reorth != SLR_REORTH_FULL && o->reorth != SLR_REORTH_PARTIAL) return fail(SLR_ERR_ARG, "reorth");
   if (o->fact_prec != SLR_FP64 && o->fact_prec != SLR_FP32) return fail(SLR_ERR_ARG, "fact_prec");
   if (o->uk_prec < SLR_FP64 || o->uk_prec > SLR_BF16) return fail(SLR_ERR_ARG, "uk_prec");
   if (o->b_fact < SLR_FACT_CHOL || o->b_fact > SLR_FACT_ILDLT0) return fail(SLR_ERR_ARG, "b_fact");

@@ -76,17 +76,25 @@ int32_t launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, cons
                         double *sqpart, hipStream_t st);
 void launch_gemv_add(int64_t n, int32_t J, const double *V, int64_t ldv, const double *y, double *x,
                      hipStream_t st);
-void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
-                         const double *apart, int32_t rb, hipStream_t st);
+// w -= alpha v + beta_prev v_prev (alpha folded from the rb partials, kept in
+// sc[0]; beta_prev = sc[1]); per-block ||w||^2 partials to sqpart (returns
+// the block count, equal to launch_gemv_sub_fold's)
+int32_t launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
+                            const double *apart, int32_t rb, double *sqpart, hipStream_t st);
+// partial reorthogonalisation control of Lanczos step j (omega recurrence);
+// ctl[0] = reorthogonalise this step, ctl[1] = force the next, ctl[2] = count
+void launch_pro(int32_t j, int64_t s, const double *alpha, const double *beta, const double *sc, const double *bpart,
+                int32_t rb, double *om, int32_t ld, int *ctl, double *tn, int *rflag, hipStream_t st);
 // aval: device pointer to alpha_j (or nullptr: alpha_j is sc[0])
 void launch_lanczos_next(int64_t s, int32_t j, const double *w, double *vnext, double *sc, double *alpha,
                          double *beta, const double *bpart, int32_t rb, const double *aval, hipStream_t st);
+// gate (optional, device): the launch does nothing when *gate == 0
 int32_t launch_multidot_partial(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
-                                int32_t nblk, hipStream_t st);
+                                int32_t nblk, hipStream_t st, const int *gate = nullptr);
 // w -= V h with h folded in each block from the rb multidot partials
 // (block 0 stores h to hout when given); sqpart as for launch_gemv_sub
 int32_t launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
-                             double *w, double *hout, double *sqpart, hipStream_t st);
+                             double *w, double *hout, double *sqpart, hipStream_t st, const int *gate = nullptr);
 void launch_scale_inv_sqrt(int64_t s, const double *w, double *out, const double *nrm2, hipStream_t st);
 void launch_div_scalar(int64_t n, const double *w, double *v, const double *scale, hipStream_t st);
 void launch_gmres_givens(int32_t j, int32_t ldh, double *Hm, const double *h1, const double *h2,

@@ -51,6 +51,12 @@ __device__ __forceinline__ double wave_allsum(double v) {
   return v;
 }
 
+// max over the wave, valid in every lane
+__device__ __forceinline__ double wave_allmax(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // Sum over the block (blockDim multiple of 64, <= 1024); result in thread 0.
 __device__ double block_sum(double v, double *sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1258,7 +1264,8 @@ void launch_relres(int64_t n, const double *B, int64_t ldb, const double *AX, in
 // part[rb*J + j] (four independent accumulators per thread); k_fold then
 // sums the RB partials of every column.
 __global__ void __launch_bounds__(256) k_multidot(int64_t s, int J, const double *V, int64_t ldv,
-                                                  const double *w, double *part) {
+                                                  const double *w, double *part, const int *gate) {
+  if (gate && *gate == 0) return;   // skipped step (partial reorthogonalisation)
   __shared__ double sh[4];
   const int rb = blockIdx.x, nb = gridDim.x, j = blockIdx.y;
   const int64_t chunk = (s + nb - 1) / nb;
@@ -1297,10 +1304,12 @@ __device__ __forceinline__ double dot_rows32(const double *V, int64_t ldv, int64
 // device (hpart == nullptr) or folded here from the rb multidot partials
 // hpart[b*J + j] (one thread per coefficient, partials in block order; block
 // 0 also stores the folded h to hout when given).  sqpart (optional):
-// per-block sums of the updated w[i]^2, block b at sqpart[b].
+// per-block sums of the updated w[i]^2, block b at sqpart[b].  gate
+// (optional): the whole grid returns at once when *gate == 0.
 __global__ void __launch_bounds__(256) k_gemv_sub(int64_t s, int J, const double *V, int64_t ldv,
                                                   const double *h, double *w, const double *hpart, int rb,
-                                                  double *sqpart, double *hout) {
+                                                  double *sqpart, double *hout, const int *gate) {
+  if (gate && *gate == 0) return;
   __shared__ double hs[1024];
   __shared__ double sh[4];
   if (hpart) {
@@ -1335,10 +1344,10 @@ __global__ void __launch_bounds__(256) k_gemv_sub(int64_t s, int J, const double
 }
 
 int32_t launch_multidot_partial(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
-                                int32_t nblk, hipStream_t st) {
+                                int32_t nblk, hipStream_t st, const int *gate) {
   const int64_t rb =
       std::max<int64_t>(1, std::min<int64_t>({(int64_t)nblk, (1024 + J - 1) / J, (s + 1023) / 1024}));
-  hipLaunchKernelGGL(k_multidot, dim3((unsigned)rb, J), dim3(256), 0, st, s, J, V, ldv, w, part);
+  hipLaunchKernelGGL(k_multidot, dim3((unsigned)rb, J), dim3(256), 0, st, s, J, V, ldv, w, part, gate);
   return (int32_t)rb;
 }
 
@@ -1347,7 +1356,8 @@ void launch_multidot(int64_t s, int32_t J, const double *V, int64_t ldv, const d
   // row chunks: about 1024 blocks in total, at least 2048 rows per chunk
   int64_t rb = std::max<int64_t>(1, std::min<int64_t>({(int64_t)nblk, (1024 + J - 1) / J, (s + 1023) / 1024}));
   (void)counter;
-  hipLaunchKernelGGL(k_multidot, dim3((unsigned)rb, J), dim3(256), 0, st, s, J, V, ldv, w, part);
+  hipLaunchKernelGGL(k_multidot, dim3((unsigned)rb, J), dim3(256), 0, st, s, J, V, ldv, w, part,
+                     (const int *)nullptr);
   launch_fold(part, (int32_t)rb, J, out, 1.0, st);
 }
 
@@ -1355,39 +1365,114 @@ int32_t launch_gemv_sub(int64_t s, int32_t J, const double *V, int64_t ldv, cons
                         double *sqpart, hipStream_t st) {
   const unsigned nb = (unsigned)((s + 255) / 256);
   hipLaunchKernelGGL(k_gemv_sub, dim3(nb), dim3(256), 0, st, s, J, V, ldv, h, w, (const double *)nullptr, 0,
-                     sqpart, (double *)nullptr);
+                     sqpart, (double *)nullptr, (const int *)nullptr);
   return (int32_t)nb;
 }
 
 int32_t launch_gemv_sub_fold(int64_t s, int32_t J, const double *V, int64_t ldv, const double *hpart, int32_t rb,
-                             double *w, double *hout, double *sqpart, hipStream_t st) {
+                             double *w, double *hout, double *sqpart, hipStream_t st, const int *gate) {
   const unsigned nb = (unsigned)((s + 255) / 256);
   hipLaunchKernelGGL(k_gemv_sub, dim3(nb), dim3(256), 0, st, s, J, V, ldv, (const double *)nullptr, w, hpart, rb,
-                     sqpart, hout);
+                     sqpart, hout, gate);
   return (int32_t)nb;
 }
 
 // Lanczos three-term step: alpha = v.w folded from the rb multidot
 // partials (block 0 stores it in sc[0]);  w -= alpha v + b_prev v_prev
-// with b_prev = sc[1].
+// with b_prev = sc[1]; per-block sums of the new w^2 go to sqpart (same
+// grid as k_gemv_sub, so either kernel's partials can be folded alike).
 __global__ void __launch_bounds__(256) k_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev,
-                                                      double *sc, const double *apart, int rb) {
+                                                      double *sc, const double *apart, int rb, double *sqpart) {
   __shared__ double al;
+  __shared__ double sh[4];
   fold_waves(apart, rb, 1, [&](int, double x) { al = x; });
   __syncthreads();
   const double a = al;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[0] = a;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= s) return;
-  double t = w[i] - a * v[i];
-  if (vprev) t -= sc[1] * vprev[i];
-  w[i] = t;
+  double t = 0.0;
+  if (i < s) {
+    t = w[i] - a * v[i];
+    if (vprev) t -= sc[1] * vprev[i];
+    w[i] = t;
+  }
+  const double q = block_sum(t * t, sh);
+  if (threadIdx.x == 0) sqpart[blockIdx.x] = q;
 }
 
-void launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
-                         const double *apart, int32_t rb, hipStream_t st) {
-  hipLaunchKernelGGL(k_lanczos_axpy, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, w, v, vprev, sc,
-                     apart, rb);
+int32_t launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
+                            const double *apart, int32_t rb, double *sqpart, hipStream_t st) {
+  const unsigned nb = (unsigned)((s + 255) / 256);
+  hipLaunchKernelGGL(k_lanczos_axpy, dim3(nb), dim3(256), 0, st, s, w, v, vprev, sc, apart, rb, sqpart);
+  return (int32_t)nb;
+}
+
+// Partial reorthogonalisation control for Lanczos step j (Sec. 5.1, the
+// omega recurrence of Parlett and Simon).  One block; thread l < j
+// estimates om_{j+1,l} ~ v_{j+1}.v_l from rows om_j (row j % 3) and
+// om_{j-1} (row (j+2) % 3) of om (3 rows of ld):
+//   beta_j om_{j+1,l} = beta_l om_{j,l+1} + (alpha_l - alpha_j) om_{j,l}
+//                       + beta_{l-1} om_{j,l-1} - beta_{j-1} om_{j-1,l}
+// (unit diagonal), plus the rounding term e = eps sqrt(s) ||T_j|| with the
+// estimate's sign; om_{j+1,j} = e / beta_j.  beta_j is the norm before any
+// reorthogonalisation (folded from the rb partials bpart), alpha_j = sc[0],
+// alpha_l / beta_l (l < j) from the recorded coefficients, ||T_j|| the
+// running max of |alpha_i| + beta_i + beta_{i-1} kept in tn[0].
+// Decision (ctl[0], and rflag[j]): reorthogonalise when forced by the
+// previous step (ctl[1]) or when some |om_{j+1,l}| exceeds sqrt(eps); a
+// step triggered by the estimate forces the next one.  A reorthogonalised
+// row is reset to e / beta_j.
+__global__ void __launch_bounds__(1024) k_pro(int j, double sqrt_s, const double *alpha, const double *beta,
+                                              const double *sc, const double *bpart, int rb, double *om, int ld,
+                                              int *ctl, double *tn, int *rflag) {
+  __shared__ double bsh, red[16];
+  __shared__ int dosh;
+  fold_waves(bpart, rb, 1, [&](int, double x) { bsh = sqrt(x); });
+  __syncthreads();
+  const double eps = 0x1p-52;
+  const double bj = bsh, aj = sc[0], bm = j > 0 ? beta[j - 1] : 0.0;
+  const double tnorm = fmax(tn[0], fabs(aj) + bj + bm);
+  const double e = eps * sqrt_s * tnorm;
+  const double *W0 = om + (int64_t)(j % 3) * ld;
+  const double *Wm = om + (int64_t)((j + 2) % 3) * ld;
+  double *Wp = om + (int64_t)((j + 1) % 3) * ld;
+  const double psi = bj > 0.0 ? e / bj : 1.0;
+  const int l = threadIdx.x;
+  double x = 0.0;
+  if (l < j) {
+    const double up = l + 1 == j ? 1.0 : W0[l + 1];
+    const double prev = l == j - 1 ? 1.0 : Wm[l];
+    double t = beta[l] * up + (alpha[l] - aj) * W0[l] - bm * prev;
+    if (l > 0) t += beta[l - 1] * W0[l - 1];
+    t += copysign(e, t);
+    x = bj > 0.0 ? t / bj : 1.0;
+  } else if (l == j) {
+    x = psi;
+  }
+  double m = wave_allmax(fabs(x));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) mx = fmax(mx, red[i]);
+    const int force = ctl[1];
+    const int big = mx > 0x1p-26;
+    const int d = force || big;
+    ctl[1] = force ? 0 : big;
+    ctl[0] = d;
+    ctl[2] += d;
+    rflag[j] = d;
+    tn[0] = tnorm;
+    dosh = d;
+  }
+  __syncthreads();
+  if (l <= j) Wp[l] = dosh ? psi : x;
+}
+
+void launch_pro(int32_t j, int64_t s, const double *alpha, const double *beta, const double *sc, const double *bpart,
+                int32_t rb, double *om, int32_t ld, int *ctl, double *tn, int *rflag, hipStream_t st) {
+  hipLaunchKernelGGL(k_pro, dim3(1), dim3(1024), 0, st, j, std::sqrt((double)s), alpha, beta, sc, bpart, rb, om, ld,
+                     ctl, tn, rflag);
 }
 
 // End of Lanczos step j: beta_j = ||w|| folded from the rb multidot

@@ -360,6 +360,39 @@ def test_grow_lowrank_by_deflation():
     assert G.info["k"] == 10
 
 
+@pytest.mark.parametrize("reorth", ["partial", "full"])
+def test_lanczos_reorth_modes(reorth):
+    """Both reorthogonalisation schemes of Sec. 5.1 against the oracle run
+    with the same scheme: converged Ritz values agree to 1e-10 (also across
+    schemes), the partial scheme cleans only some steps and keeps the Ritz
+    vectors orthonormal to sqrt(eps) level, the apply matches the oracle fed
+    with the exported part, and PCG iteration counts agree to +-1."""
+    pr = si.make_config("diffusion2d_1024", N=96, boxes=4)
+    G = _slr(pr, k=16, lanczos_steps=150, reorth=reorth)
+    Po = _oracle(pr, k=16, lanczos_steps=150, reorth=reorth)
+    ex, gv, gb = _lanczos_parity(G, Po, 16)
+    if reorth == "partial":
+        assert 0 < G.info["lanczos_reorth"] < 150 // 4
+        assert abs(G.info["lanczos_reorth"] - len(Po.reorth_steps)) <= 4
+        Gf = _slr(pr, k=16, lanczos_steps=150, reorth="full")
+        exf = Gf.export()
+        fv, fb = _ritz_bounds(exf["alpha"], exf["beta"])
+        conv = (gb[:17] <= 1e-9) & (fb[:17] <= 1e-9)
+        assert conv.sum() >= 5
+        assert np.all(np.abs(gv[:17] - fv[:17])[conv] <= 1e-10 * np.abs(fv[:17])[conv])
+    else:
+        assert G.info["lanczos_reorth"] == G.info["lanczos_steps"]
+    assert np.abs(ex["U"].T @ ex["U"] - np.eye(16)).max() <= 1e-7
+    Pi = _oracle(pr, lowrank=(ex["U"], ex["lambda"], ex["theta"]))
+    r = _rand(pr.n, 2, 12)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= 1e-12
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "pcg")
+    x, info = G.solve(_dev(b[:, 0]), "pcg")
+    assert info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    assert abs(info[0]["iters"] - ro.iters) <= 1
+
+
 def test_fgmres_indefinite():
     pr = si.make_config("shifted3d_128", N=24, boxes=4, neg=4)
     Po = _oracle(pr, k=16, lanczos_steps=80)

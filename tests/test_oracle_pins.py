@@ -395,10 +395,11 @@ def test_grow_by_deflation_finds_the_next_eigenpairs():
 
 
 def test_grow_from_nothing_is_plain_lanczos():
-    """With no captured directions deflated Lanczos is the plain build."""
+    """With no captured directions deflated Lanczos is the plain build
+    (growth always reorthogonalises fully)."""
     csr, part, p = _tiny(12)
     v0 = si.lanczos_start(csr[3], 4)
-    A = O.setup(csr, part, p, 5, 25, b_fact="ic0", c_fact="ic0", v0=v0)
+    A = O.setup(csr, part, p, 5, 25, b_fact="ic0", c_fact="ic0", v0=v0, reorth="full")
     B = O.setup(csr, part, p, 0, b_fact="ic0", c_fact="ic0")
     O.grow_lowrank(B, 5, 25, v0[B.perm[B.m:]])
     assert B.k == A.k and np.array_equal(B.lam, A.lam) and B.theta == A.theta
