@@ -121,6 +121,11 @@ typedef struct {
   /* SLR_REORTH_FULL | SLR_REORTH_PARTIAL.  slr_grow_lowrank always uses
      full reorthogonalisation (the omega estimates do not cover U_k). */
   int32_t reorth;
+  /* 1: keep what slr_refactor needs (the input pattern, the factorisation
+     plans and the maps of every stored coefficient; about 24 bytes per
+     stored coefficient of device memory).  Needs incomplete factors (B:
+     IC0 | ILDLT0, C: IC0) and nnz < 2^31; SLR_ERR_ARG otherwise. */
+  int32_t refactor;
 } slr_opts;
 
 typedef struct {
@@ -207,6 +212,22 @@ int slr_update_lowrank(slr_ctx *c, int32_t k, int32_t lanczos_steps, const doubl
  * batches exist on the context.  Synchronises hip_stream. */
 int slr_grow_lowrank(slr_ctx *c, int32_t k_add, int32_t lanczos_steps, const double *lanczos_v0,
                      void *hip_stream);
+
+/* slr_refactor: new values for A with the pattern given to slr_setup (val:
+ * host, nnz, in that CSR's order), for a context set up with
+ * opts.refactor = 1.  The zero-fill factors of the B_i and of C (Sec. 5.2,
+ * IC(0) / ILDL^T(0)) are recomputed on the device, level by level with the
+ * schedules of the forward sweeps, and every stored coefficient of the
+ * apply (sweep scales and weights, E, E^T, A for the Krylov products) is
+ * rewritten in place in the context's storage precision; the results equal
+ * those of a fresh slr_setup with the new values.  The low-rank part
+ * (U_k, Lambda_k, theta) is kept: call slr_update_lowrank to rebuild it for
+ * the new H.  Errors: SLR_ERR_NOT_SYMMETRIC (checked on the host),
+ * SLR_ERR_BREAKDOWN (a B_i pivot), SLR_ERR_C_NOT_SPD (a C pivot) -- after
+ * which every stored coefficient is unchanged -- and SLR_ERR_ARG (no
+ * opts.refactor, or batches exist on the context).  Synchronises
+ * hip_stream. */
+int slr_refactor(slr_ctx *c, const double *val, void *hip_stream);
 
 /* slr_time_kernel: average device time (ms, via HIP events on hip_stream)
  * of `reps` back-to-back launches of one hot-path stage on nrhs internal

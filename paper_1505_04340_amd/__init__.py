@@ -59,7 +59,8 @@ class slr_opts(ctypes.Structure):
     _fields_ = [("k", _I32), ("lanczos_steps", _I32), ("theta_mode", _I32), ("b_fact", _I32),
                 ("c_fact", _I32), ("c_order", _I32), ("fact_prec", _I32), ("uk_prec", _I32),
                 ("seed", _U64), ("lanczos_v0", _P), ("k_in", _I32), ("U_in", _P),
-                ("lambda_in", _P), ("theta_in", _D), ("eps", _D), ("cond_K", _D), ("reorth", _I32)]
+                ("lambda_in", _P), ("theta_in", _D), ("eps", _D), ("cond_K", _D), ("reorth", _I32),
+                ("refactor", _I32)]
 
 
 class slr_solve_opts(ctypes.Structure):
@@ -95,6 +96,7 @@ slr_analyze = _sig("slr_analyze", ctypes.c_int, [ctypes.POINTER(slr_csr), _P, _I
                                                  ctypes.POINTER(slr_info), _P])
 slr_update_lowrank = _sig("slr_update_lowrank", ctypes.c_int, [_P, _I32, _I32, _P, _P])
 slr_grow_lowrank = _sig("slr_grow_lowrank", ctypes.c_int, [_P, _I32, _I32, _P, _P])
+slr_refactor = _sig("slr_refactor", ctypes.c_int, [_P, _P, _P])
 slr_time_kernel = _sig("slr_time_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P, ctypes.POINTER(_D)])
 slr_apply = _sig("slr_apply", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_apply_dd = _sig("slr_apply_dd", ctypes.c_int, [_P, _P, _P, _I32, _P])
@@ -117,7 +119,7 @@ slr_last_error = _sig("slr_last_error", ctypes.c_char_p, [])
 slr_device_lds_bytes = _sig("slr_device_lds_bytes", ctypes.c_int, [])
 
 EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_analyze", "slr_update_lowrank",
-            "slr_grow_lowrank",
+            "slr_grow_lowrank", "slr_refactor",
             "slr_time_kernel", "slr_apply", "slr_apply_dd",
             "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_spmv",
             "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
@@ -165,7 +167,7 @@ def _csr_arrays(A):
 
 def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fact="ic0",
                c_order="subdomain", fact_prec="fp64", uk_prec="fp64", seed=7, eps=0.0, cond_K=0.0,
-               reorth=None):
+               reorth=None, refactor=False):
     o = slr_opts()
     slr_default_opts(ctypes.byref(o))
     o.k = k
@@ -178,6 +180,7 @@ def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fa
     o.eps, o.cond_K = float(eps), float(cond_K)
     if reorth is not None:
         o.reorth = _REORTH[reorth]
+    o.refactor = 1 if refactor else 0
     return o
 
 
@@ -201,12 +204,12 @@ class SLR:
                  theta_mode: str = "lambda_k1", b_fact: str = "ic0", c_fact: str = "ic0",
                  c_order: str = "subdomain", fact_prec: str = "fp64", uk_prec: str = "fp64",
                  v0=None, seed: int = 7, lowrank=None, eps: float = 0.0, cond_K: float = 0.0,
-                 reorth: str | None = None, stream=None):
+                 reorth: str | None = None, refactor: bool = False, stream=None):
         indptr, indices, data, n = _csr_arrays(A)
         self.n = n
         part = np.ascontiguousarray(part, dtype=np.int32)
         o = _make_opts(k, lanczos_steps, theta_mode, b_fact, c_fact, c_order, fact_prec, uk_prec, seed, eps, cond_K,
-                       reorth)
+                       reorth, refactor)
         keep = []
         if v0 is not None:
             v0 = np.ascontiguousarray(v0, dtype=np.float64)
@@ -225,6 +228,7 @@ class SLR:
         h = _P()
         _check(slr_setup(ctypes.byref(csr), part.ctypes.data, nparts, ctypes.byref(o), _stream(stream),
                          ctypes.byref(h)), "slr_setup")
+        self._pattern = (indptr, indices) if refactor else None
         self._h = h
         self.info = self.query()
 
@@ -251,6 +255,18 @@ class SLR:
             p = v0.ctypes.data
         _check(slr_update_lowrank(self._h, k, lanczos_steps, p, _stream(stream)), "slr_update_lowrank")
         self.info = self.query()
+
+    def refactor(self, A, stream=None):
+        """New values of A with the pattern given at setup (slr_refactor):
+        the factors and stored coefficients are recomputed on the device;
+        the low-rank part is kept."""
+        if self._pattern is None:
+            raise ValueError("set up with refactor=True to refactor")
+        indptr, indices, data, n = _csr_arrays(A)
+        if n != self.n or not (np.array_equal(indptr, self._pattern[0])
+                               and np.array_equal(indices, self._pattern[1])):
+            raise ValueError("refactor needs the pattern given at setup")
+        _check(slr_refactor(self._h, data.ctypes.data, _stream(stream)), "slr_refactor")
 
     def grow_lowrank(self, k_add: int, lanczos_steps: int = 0, v0=None, stream=None):
         """Append up to k_add Ritz pairs from a deflated Lanczos run, keeping

@@ -131,6 +131,31 @@ struct slr_ctx {
   int32_t mfma_min_rhs = 1;
   DevPool lrpool;               // U, U64, dsc
   int32_t live_batches = 0;     // slr_batch objects on this context
+  // numeric refactorisation (slr_refactor): the input pattern, the factor
+  // plans and the coefficient maps, kept when opts.refactor is set
+  struct Refactor {
+    bool on = false;
+    DevPool pool;
+    std::vector<int64_t> in_rp;
+    std::vector<int32_t> in_ci;
+    int64_t nnz = 0;
+    double *val = nullptr;
+    int *err = nullptr;
+    int64_t *a_src = nullptr;
+    struct Plan {
+      int64_t *rp = nullptr;
+      int32_t *ci = nullptr, *rows = nullptr;
+      int64_t *src = nullptr;
+      double *v = nullptr;
+      int64_t nnz = 0;
+      std::vector<int32_t> lev;
+      int kind = 0;
+    } fb, fc;
+    struct Map {
+      RfMap *m = nullptr;
+      int64_t n = 0;
+    } bdata, ev, tv, cfsc, cfw, cfw2, cbsc, cbw, cbw2;
+  } rf;
   // stats
   slr_info info{};
   ApplyWS ws;
@@ -575,9 +600,29 @@ Sweep split_levels(const Sweep &sw, int32_t Kfix) {
 // Pack one sweep of one subdomain as the level-sliced byte stream the B
 // kernel stages into LDS (layouts documented with BlockDesc): row records
 // when every row has the fixed width Kfix > 0, else the ELL form.
+// Coefficient maps of a device refactorisation (built while packing).
+struct RfSweepMaps {
+  std::vector<RfMap> sc, w, w2;
+};
+struct RfMaps {
+  std::vector<RfMap> bdata, ev, tv;   // B sweep streams, E and E^T values
+  RfSweepMaps cf, cb;                 // interface sweeps
+};
+
+// Coefficient sources of the stored scale / weights of sweep row t (for the
+// device refactorisation; ebase = first entry of the factor).
+RfMap rf_scale(const Sweep &sw, int32_t t, int64_t off, int64_t ebase) {
+  if (sw.unit_sc) return RfMap{off, 0, 0, 0, RF_ONE};
+  return RfMap{off, (int32_t)(ebase + sw.sc_e[t]), 0, 0, RF_RECIP};
+}
+RfMap rf_weight(const Sweep &sw, int32_t t, int32_t e, int64_t off, int64_t ebase) {
+  if (sw.divided) return RfMap{off, (int32_t)(ebase + sw.w_e[e]), (int32_t)(ebase + sw.sc_e[t]), 0, RF_DIV};
+  return RfMap{off, (int32_t)(ebase + sw.w_e[e]), 0, 0, RF_RAW};
+}
+
 template <typename TS>
 void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::vector<int32_t> &lvb, int32_t &K,
-                int32_t &max_level_bytes, int64_t &offset) {
+                int32_t &max_level_bytes, int64_t &offset, std::vector<RfMap> *map = nullptr, int64_t ebase = 0) {
   K = 0;
   for (int32_t t = 0; t < sw.nrows; ++t) K = std::max(K, sw.rp[t + 1] - sw.rp[t]);
   if (Kfix > 0) K = Kfix;
@@ -596,14 +641,18 @@ void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::
       uint8_t *base = data.data() + offset + pos;
       int32_t *ix = reinterpret_cast<int32_t *>(base);
       TS *wr = reinterpret_cast<TS *>(base + o_w);
+      const int64_t wbase = offset + pos + o_w;
       for (int32_t j = 0; j < L; ++j) {
         const int32_t t = a + j, row = sw.rows[t];
         const int32_t e0 = sw.rp[t], cnt = sw.rp[t + 1] - e0;
         ix[(int64_t)j * KR] = row;
         wr[(int64_t)j * KR] = (TS)sw.sc[t];
+        if (map) map->push_back(rf_scale(sw, t, wbase + (int64_t)sizeof(TS) * j * KR, ebase));
         for (int32_t e = 0; e + 1 < KR; ++e) {
           ix[(int64_t)j * KR + 1 + e] = e < cnt ? sw.ci[e0 + e] : row;
           wr[(int64_t)j * KR + 1 + e] = e < cnt ? (TS)sw.w[e0 + e] : (TS)0;
+          if (map && e < cnt)
+            map->push_back(rf_weight(sw, t, e0 + e, wbase + (int64_t)sizeof(TS) * ((int64_t)j * KR + 1 + e), ebase));
         }
       }
     } else {
@@ -616,14 +665,18 @@ void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::
       TS *sc = reinterpret_cast<TS *>(base + o_sc);
       uint16_t *ci = reinterpret_cast<uint16_t *>(base + o_ci);
       TS *w = reinterpret_cast<TS *>(base + o_w);
+      const int64_t sbase = offset + pos + o_sc, wbase = offset + pos + o_w;
       for (int32_t j = 0; j < L; ++j) {
         const int32_t t = a + j, row = sw.rows[t];
         rows[j] = (uint16_t)row;
         sc[j] = (TS)sw.sc[t];
+        if (map) map->push_back(rf_scale(sw, t, sbase + (int64_t)sizeof(TS) * j, ebase));
         const int32_t e0 = sw.rp[t], cnt = sw.rp[t + 1] - e0;
         for (int32_t e = 0; e < K; ++e) {
           ci[(int64_t)e * L + j] = (uint16_t)(e < cnt ? sw.ci[e0 + e] : row);
           w[(int64_t)e * L + j] = e < cnt ? (TS)sw.w[e0 + e] : (TS)0;
+          if (map && e < cnt)
+            map->push_back(rf_weight(sw, t, e0 + e, wbase + (int64_t)sizeof(TS) * ((int64_t)e * L + j), ebase));
         }
       }
     }
@@ -635,7 +688,7 @@ void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::
 
 template <typename TS>
 void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArrays<TS> &Cf, SweepArrays<TS> &Cb,
-                   bool &ok) {
+                   bool &ok, RfMaps *rm) {
   std::vector<BlockDesc> desc(H.p);
   std::vector<int32_t> lev, lvb;
   std::vector<uint8_t> data;
@@ -664,13 +717,13 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
     lev.insert(lev.end(), fs.levptr.begin(), fs.levptr.end());
     if (fs.levptr.empty()) lev.push_back(0);
     d.f_lvb = (int32_t)lvb.size();
-    pack_sweep<TS>(fs, Kfix, data, lvb, d.f_K, max_lb, d.f_data);
+    pack_sweep<TS>(fs, Kfix, data, lvb, d.f_K, max_lb, d.f_data, rm ? &rm->bdata : nullptr, b.f_base);
     d.b_nlev = bs.nlev;
     d.b_lev = (int32_t)lev.size();
     lev.insert(lev.end(), bs.levptr.begin(), bs.levptr.end());
     if (bs.levptr.empty()) lev.push_back(0);
     d.b_lvb = (int32_t)lvb.size();
-    pack_sweep<TS>(bs, Kfix, data, lvb, d.b_K, max_lb, d.b_data);
+    pack_sweep<TS>(bs, Kfix, data, lvb, d.b_K, max_lb, d.b_data, rm ? &rm->bdata : nullptr, b.f_base);
     max_K = std::max({max_K, d.f_K, d.b_K});
     // E rows as ELL (width = longest row)
     d.e_row = (int32_t)e_row.size();
@@ -685,6 +738,9 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
       for (int32_t e = 0; e < b.e_ptr[i + 1] - b.e_ptr[i]; ++e) {
         e_q[d.e_ent + (size_t)e * d.e_n + i] = b.e_q[b.e_ptr[i] + e];
         e_val[d.e_ent + (size_t)e * d.e_n + i] = b.e_val[b.e_ptr[i] + e];
+        if (rm)
+          rm->ev.push_back(RfMap{(int64_t)sizeof(TS) * (int64_t)(d.e_ent + (size_t)e * d.e_n + i),
+                                 (int32_t)b.e_src[b.e_ptr[i] + e], 0, 0, RF_SRC});
       }
     // E^T rows as ELL
     d.t_row = (int32_t)t_q.size();
@@ -699,6 +755,9 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
       for (int32_t e = 0; e < b.t_ptr[i + 1] - b.t_ptr[i]; ++e) {
         t_j[d.t_ent + (size_t)e * d.t_n + i] = (uint16_t)b.t_j[b.t_ptr[i] + e];
         t_val[d.t_ent + (size_t)e * d.t_n + i] = b.t_val[b.t_ptr[i] + e];
+        if (rm)
+          rm->tv.push_back(RfMap{(int64_t)sizeof(TS) * (int64_t)(d.t_ent + (size_t)e * d.t_n + i),
+                                 (int32_t)b.t_src[b.t_ptr[i] + e], 0, 0, RF_SRC});
       }
   }
   if (data.empty()) data.resize(16, 0);
@@ -720,7 +779,19 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
   c->b_max_lev = max_lev;
   c->b_max_level_bytes = max_lb;
   c->b_data_bytes = (int64_t)data.size();
-  auto upc = [&](const Sweep &sw, SweepArrays<TS> &S) {
+  auto upc = [&](const Sweep &sw, SweepArrays<TS> &S, RfSweepMaps *sm) {
+    if (sm) {
+      std::vector<int32_t> tof(sw.nrows, 0);
+      for (int32_t t = 0; t < sw.nrows; ++t) tof[sw.rows[t]] = t;
+      for (int32_t t = 0; t < sw.nrows; ++t) {
+        sm->sc.push_back(rf_scale(sw, t, (int64_t)sizeof(TS) * t, 0));
+        for (int32_t e = sw.rp[t]; e < sw.rp[t + 1]; ++e) {
+          sm->w.push_back(rf_weight(sw, t, e, (int64_t)sizeof(TS) * e, 0));
+          if (sw.nlev <= 2)
+            sm->w2.push_back(RfMap{(int64_t)sizeof(TS) * e, sw.w_e[e], sw.sc_e[t], sw.sc_e[tof[sw.ci[e]]], RF_W2});
+        }
+      }
+    }
     std::vector<int32_t> lv = sw.levptr;
     if (lv.empty()) lv.push_back(0);
     S.lev = P.upload(lv);
@@ -742,7 +813,7 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
     return S.lev && S.rows && S.rp && S.ci && S.w && S.sc && okw2;
   };
   ok = ok && B.desc && B.lev && B.lvb && B.data && B.e_row && B.e_q && B.e_val && B.t_q && B.t_j && B.t_val;
-  ok = ok && upc(H.cfwd, Cf) && upc(H.cbwd, Cb);
+  ok = ok && upc(H.cfwd, Cf, rm ? &rm->cf : nullptr) && upc(H.cbwd, Cb, rm ? &rm->cb : nullptr);
 }
 
 int perm_ws(slr_ctx *c, int32_t nrhs) {
@@ -769,6 +840,60 @@ const double *seeded_v0(int64_t n, uint64_t seed, std::vector<double> &v0) {
     v0[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
   }
   return v0.data();
+}
+
+// Keep what slr_refactor needs: the input pattern (symmetry check), the
+// gather maps of A / E / E^T, the factor plans and the coefficient maps.
+bool rf_upload(slr_ctx *c, const HostSetup &H, const RfMaps &rm, const slr_csr *A) {
+  auto &R = c->rf;
+  auto &P = R.pool;
+  R.in_rp.assign(A->rowptr, A->rowptr + A->n + 1);
+  R.in_ci.assign(A->col, A->col + A->nnz);
+  R.nnz = A->nnz;
+  R.val = P.alloc<double>((size_t)std::max<int64_t>(A->nnz, 1));
+  R.err = P.alloc<int>(4);
+  R.a_src = P.upload(H.a_src);
+  auto plan = [&](const RefactorPlan &F, slr_ctx::Refactor::Plan &D) {
+    D.rp = P.upload(F.rp);
+    D.ci = P.upload(F.ci.empty() ? std::vector<int32_t>{0} : F.ci);
+    D.src = P.upload(F.src.empty() ? std::vector<int64_t>{0} : F.src);
+    D.rows = P.upload(F.rows.empty() ? std::vector<int32_t>{0} : F.rows);
+    D.nnz = (int64_t)F.ci.size();
+    D.v = P.alloc<double>((size_t)std::max<int64_t>(D.nnz, 1));
+    D.lev = F.lev;
+    D.kind = F.kind;
+    return D.rp && D.ci && D.src && D.rows && D.v;
+  };
+  auto map = [&](const std::vector<RfMap> &v, slr_ctx::Refactor::Map &D) {
+    D.n = (int64_t)v.size();
+    if (v.empty()) return true;
+    D.m = P.upload(v);
+    return D.m != nullptr;
+  };
+  bool ok = R.val && R.err && R.a_src && plan(H.fb, R.fb) && plan(H.fc, R.fc);
+  ok = ok && map(rm.bdata, R.bdata) && map(rm.ev, R.ev) && map(rm.tv, R.tv);
+  ok = ok && map(rm.cf.sc, R.cfsc) && map(rm.cf.w, R.cfw) && map(rm.cf.w2, R.cfw2);
+  ok = ok && map(rm.cb.sc, R.cbsc) && map(rm.cb.w, R.cbw) && map(rm.cb.w2, R.cbw2);
+  R.on = ok;
+  return ok;
+}
+
+template <typename TS>
+void rf_pack_all(slr_ctx *c, const BlockArrays<TS> &B, const SweepArrays<TS> &Cf, const SweepArrays<TS> &Cb,
+                 hipStream_t st) {
+  auto &R = c->rf;
+  auto run = [&](const slr_ctx::Refactor::Map &m, const double *V, const void *base) {
+    launch_rf_pack<TS>(m.n, m.m, V, R.val, const_cast<void *>(base), st);
+  };
+  run(R.bdata, R.fb.v, B.data);
+  run(R.ev, nullptr, B.e_val);
+  run(R.tv, nullptr, B.t_val);
+  run(R.cfsc, R.fc.v, Cf.sc);
+  run(R.cfw, R.fc.v, Cf.w);
+  run(R.cfw2, R.fc.v, Cf.w2);
+  run(R.cbsc, R.fc.v, Cb.sc);
+  run(R.cbw, R.fc.v, Cb.w);
+  run(R.cbw2, R.fc.v, Cb.w2);
 }
 
 // After a change of the low-rank part: workspace sized for the new k, stats.
@@ -801,6 +926,7 @@ void slr_default_opts(slr_opts *o) {
   o->eps = 0.0;
   o->cond_K = 0.0;
   o->reorth = SLR_REORTH_PARTIAL;
+  o->refactor = 0;
 }
 
 void slr_default_solve_opts(slr_solve_opts *o) {
@@ -861,6 +987,10 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   prm.c_fact = o->c_fact;
   prm.c_order = o->c_order;
   prm.fact_prec = o->fact_prec;
+  prm.plan = o->refactor != 0;
+  if (o->refactor && (o->b_fact == SLR_FACT_CHOL || o->c_fact == SLR_FACT_CHOL))
+    return fail(SLR_ERR_ARG, "refactor needs incomplete factors (IC0 / ILDLT0 for B, IC0 for C)");
+  if (o->refactor && A->nnz > INT32_MAX) return fail(SLR_ERR_ARG, "refactor takes at most 2^31-1 entries");
   std::string err;
   int rc = host_setup(A->n, A->rowptr, A->col, A->val, part, p, prm, H, err);
   if (rc) return fail(rc, err);
@@ -885,14 +1015,17 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->a_v = c->pool.upload(H.a_v);
   c->nnz_a = (int64_t)H.a_ci.size();
   bool ok = c->perm && c->a_rp && c->a_ci && c->a_v;
+  RfMaps rmaps;
+  RfMaps *rm = H.have_plan ? &rmaps : nullptr;
   if (c->fact_prec == SLR_FP64)
-    upload_blocks<double>(c, H, c->Bd, c->Cfd, c->Cbd, ok);
+    upload_blocks<double>(c, H, c->Bd, c->Cfd, c->Cbd, ok, rm);
   else {
     bool ok2 = true;
-    upload_blocks<float>(c, H, c->Bf, c->Cff, c->Cbf, ok2);
+    upload_blocks<float>(c, H, c->Bf, c->Cff, c->Cbf, ok2, rm);
     ok = ok && ok2;
   }
   if (!ok) return destroy_fail(fail(SLR_ERR_OOM, "factor upload (or a subdomain above 65535 rows)"));
+  if (rm && !rf_upload(c, H, *rm, A)) return destroy_fail(fail(SLR_ERR_OOM, "refactorisation plan"));
   c->cf_lev_h = H.cfwd.levptr;
   c->cb_lev_h = H.cbwd.levptr;
   c->cf_nlev = H.cfwd.nlev;
@@ -1003,6 +1136,38 @@ int slr_grow_lowrank(slr_ctx *c, int32_t k_add, int32_t lanczos_steps, const dou
   return lowrank_done(c, t1, st);
 }
 
+int slr_refactor(slr_ctx *c, const double *val, void *hip_stream) {
+  if (!c || !val) return fail(SLR_ERR_ARG, "null argument");
+  auto &R = c->rf;
+  if (!R.on) return fail(SLR_ERR_ARG, "the context was set up without opts.refactor");
+  if (c->live_batches > 0) return fail(SLR_ERR_ARG, "the context still has batches");
+  if (!is_symmetric(c->n, R.in_rp.data(), R.in_ci.data(), val))
+    return fail(SLR_ERR_NOT_SYMMETRIC, "A is not symmetric (pattern and values must match)");
+  hipStream_t st = S(hip_stream);
+  HIPCHK(hipMemcpyAsync(R.val, val, sizeof(double) * R.nnz, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(R.err, 0, 4 * sizeof(int), st));
+  // factors into their own value arrays (level by level)
+  launch_gather(R.fb.nnz, R.fb.src, R.val, R.fb.v, st);
+  launch_gather(R.fc.nnz, R.fc.src, R.val, R.fc.v, st);
+  for (size_t l = 0; l + 1 < R.fb.lev.size(); ++l)
+    launch_fact_level(R.fb.rp, R.fb.ci, R.fb.v, R.fb.rows, R.fb.lev[l], R.fb.lev[l + 1], R.fb.kind == 2, R.err, st);
+  for (size_t l = 0; l + 1 < R.fc.lev.size(); ++l)
+    launch_fact_level(R.fc.rp, R.fc.ci, R.fc.v, R.fc.rows, R.fc.lev[l], R.fc.lev[l + 1], 0, R.err + 1, st);
+  int e[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(e, R.err, sizeof(e), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // a failed pivot leaves every stored coefficient as it was
+  if (e[0]) return fail(SLR_ERR_BREAKDOWN, "refactorisation of a B_i failed (pivot)");
+  if (e[1]) return fail(SLR_ERR_C_NOT_SPD, "refactorisation of C failed (pivot)");
+  launch_gather(c->nnz_a, R.a_src, R.val, c->a_v, st);
+  if (c->fact_prec == SLR_FP64)
+    rf_pack_all<double>(c, c->Bd, c->Cfd, c->Cbd, st);
+  else
+    rf_pack_all<float>(c, c->Bf, c->Cff, c->Cbf, st);
+  HIPCHK(hipStreamSynchronize(st));
+  return SLR_OK;
+}
+
 int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void *hip_stream, double *ms) {
   if (!c || !ms || nrhs <= 0 || reps <= 0 || which < 0 || which > 6) return fail(SLR_ERR_ARG, "bad timing args");
   hipStream_t st = S(hip_stream);
@@ -1109,6 +1274,7 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
 
 void slr_destroy(slr_ctx *c) {
   if (!c) return;
+  c->rf.pool.release();
   c->pool.release();
   c->ws.pool.release();
   c->lrpool.release();
@@ -1120,7 +1286,8 @@ void slr_destroy(slr_ctx *c) {
 int slr_query(const slr_ctx *c, slr_info *info) {
   if (!c || !info) return fail(SLR_ERR_ARG, "null");
   *info = c->info;
-  info->device_bytes = c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes;
+  info->device_bytes =
+      c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes + c->rf.pool.bytes;
   return SLR_OK;
 }
 

@@ -105,6 +105,33 @@ struct BArgs {
   int32_t stage_bytes = 0;    // LDS staging buffer for the packed sweeps
 };
 
+// Numeric refactorisation on the device: one stored coefficient (TS) at
+// byte offset `off` of its array, computed from factor values V (rounded to
+// TS first when TS is FP32) or from the input matrix values:
+//   RF_SRC    val[a]                     (E, E^T entries)
+//   RF_ONE    1
+//   RF_RAW    V[a]                        (unit-L weights of L D L^T)
+//   RF_RECIP  rd(1 / V[a])                (row scales)
+//   RF_DIV    rd(V[a] / V[b])             (pre-divided weights)
+//   RF_W2     rd(rd(V[a] / V[b]) * rd(1 / V[c]))   (two-level interface weights)
+// rd() rounds to TS, exactly as the host packing does.
+enum { RF_SRC = 0, RF_ONE, RF_RAW, RF_RECIP, RF_DIV, RF_W2 };
+struct RfMap {
+  int64_t off;
+  int32_t a, b, c, op;
+};
+
+template <typename TS>
+void launch_rf_pack(int64_t nmap, const RfMap *map, const double *V, const double *val, void *base,
+                    hipStream_t st);
+// out[e] = val[src[e]]
+void launch_gather(int64_t n, const int64_t *src, const double *val, double *out, hipStream_t st);
+// IC(0) (ldl = 0) or ILDL^T(0) (ldl = 1) of the rows rows[r0 .. r1) of the
+// lower CSR (rp, ci, diagonal last) whose values V hold the matrix entries
+// on entry; earlier rows must be final.  *err is set to 1 on a failed pivot.
+void launch_fact_level(const int64_t *rp, const int32_t *ci, double *V, const int32_t *rows, int32_t r0, int32_t r1,
+                       int32_t ldl, int *err, hipStream_t st);
+
 template <typename TS, typename TC>
 void launch_bsolve(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads,
                    size_t lds_bytes, hipStream_t st);

@@ -14,9 +14,7 @@
 #include "slr.h"
 
 namespace slr {
-namespace {
 
-// A symmetric in pattern and value: every (i, j) has a matching (j, i).
 bool is_symmetric(int64_t n, const int64_t *rp, const int32_t *ci, const double *v) {
   for (int64_t i = 0; i < n; ++i) {
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
@@ -30,6 +28,8 @@ bool is_symmetric(int64_t n, const int64_t *rp, const int32_t *ci, const double 
   }
   return true;
 }
+
+namespace {
 
 // Build a level-scheduled sweep from per-row dependency lists.
 // deps(i) lists the rows whose solved values row i needs; `order` is the
@@ -57,12 +57,15 @@ void schedule(int32_t nrows, const std::vector<int32_t> &order, Deps deps, Emit 
   sw.rp.assign(nrows + 1, 0);
   sw.ci.clear();
   sw.w.clear();
+  sw.w_e.clear();
   sw.sc.assign(nrows, 0.0);
+  sw.sc_e.assign(nrows, 0);
   for (int32_t t = 0; t < nrows; ++t) {
     int32_t i = sw.rows[t];
-    emit(i, sw.sc[t], [&](int32_t j, double w) {
+    emit(i, sw.sc[t], sw.sc_e[t], [&](int32_t j, double w, int32_t src) {
       sw.ci.push_back(j);
       sw.w.push_back(w);
+      sw.w_e.push_back(src);
     });
     sw.rp[t + 1] = (int32_t)sw.ci.size();
   }
@@ -86,19 +89,21 @@ void build_sweeps(const LowerFactor &F, bool fp32, Sweep &fwd, Sweep &bwd) {
   const bool ldl = F.kind == 2;
   auto diag = [&](int32_t i) { return v[F.rp[i + 1] - 1]; };
   // transpose (strictly lower part) for the backward sweep
-  std::vector<int32_t> tp(n + 1, 0), tj;
+  std::vector<int32_t> tp(n + 1, 0), tj, te;
   std::vector<double> tv;
   for (int32_t i = 0; i < n; ++i)
     for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e) tp[F.ci[e] + 1]++;
   for (int32_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
   tj.resize(tp[n]);
   tv.resize(tp[n]);
+  te.resize(tp[n]);
   {
     std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
     for (int32_t i = 0; i < n; ++i)
       for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e) {
         int32_t c = F.ci[e];
         tj[fill[c]] = i;
+        te[fill[c]] = e;
         tv[fill[c]++] = v[e];
       }
   }
@@ -110,24 +115,30 @@ void build_sweeps(const LowerFactor &F, bool fp32, Sweep &fwd, Sweep &bwd) {
       [&](int32_t i, auto f) {
         for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e) f(F.ci[e]);
       },
-      [&](int32_t i, double &sc, auto put) {
+      [&](int32_t i, double &sc, int32_t &sce, auto put) {
         double d = diag(i);
         sc = ldl ? 1.0 : rd(1.0 / d);
+        sce = F.rp[i + 1] - 1;
         for (int32_t e = F.rp[i]; e < F.rp[i + 1] - 1; ++e)
-          put(F.ci[e], ldl ? v[e] : rd(v[e] / d));
+          put(F.ci[e], ldl ? v[e] : rd(v[e] / d), e);
       },
       fwd);
+  fwd.divided = !ldl;
+  fwd.unit_sc = ldl;
   schedule(
       n, down,
       [&](int32_t i, auto f) {
         for (int32_t e = tp[i]; e < tp[i + 1]; ++e) f(tj[e]);
       },
-      [&](int32_t i, double &sc, auto put) {
+      [&](int32_t i, double &sc, int32_t &sce, auto put) {
         double d = diag(i);
         sc = rd(1.0 / d);
-        for (int32_t e = tp[i]; e < tp[i + 1]; ++e) put(tj[e], ldl ? tv[e] : rd(tv[e] / d));
+        sce = F.rp[i + 1] - 1;
+        for (int32_t e = tp[i]; e < tp[i + 1]; ++e) put(tj[e], ldl ? tv[e] : rd(tv[e] / d), te[e]);
       },
       bwd);
+  bwd.divided = !ldl;
+  bwd.unit_sc = false;
 }
 
 // Zero-fill incomplete factorisation on the pattern of tril(M) (Sec. 5.2 /
@@ -317,22 +328,30 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
   H.a_v.clear();
   H.a_ci.reserve(rowptr[n]);
   H.a_v.reserve(rowptr[n]);
+  H.a_src.clear();
+  H.a_src.reserve(rowptr[n]);
   {
-    std::vector<std::pair<int32_t, double>> row;
+    std::vector<std::pair<int32_t, int64_t>> row;
     for (int64_t t = 0; t < n; ++t) {
       int64_t i = H.perm[t];
       row.clear();
-      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
-        row.emplace_back((int32_t)H.iperm[col[e]], val[e]);
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) row.emplace_back((int32_t)H.iperm[col[e]], e);
       std::sort(row.begin(), row.end());
       for (auto &pr : row) {
         H.a_ci.push_back(pr.first);
-        H.a_v.push_back(pr.second);
+        H.a_v.push_back(val[pr.second]);
+        H.a_src.push_back(pr.second);
       }
       H.a_rp[t + 1] = (int64_t)H.a_ci.size();
     }
   }
   const bool fp32 = prm.fact_prec == SLR_FP32;
+  H.have_plan = prm.plan && prm.b_fact != SLR_FACT_CHOL && prm.c_fact != SLR_FACT_CHOL;
+  if (H.have_plan) {
+    H.fb = RefactorPlan();
+    H.fb.kind = prm.b_fact == SLR_FACT_ILDLT0 ? 2 : 0;
+    H.fb.rp.assign(1, 0);
+  }
   // Blocks: B_i factor, E rows and E^T rows (vertex-based partitioning:
   // interior nodes of subdomain i couple only to the interface of i).
   H.nnz_E = 0;
@@ -340,6 +359,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     Block &b = H.blocks[q];
     std::vector<int32_t> rp(b.m + 1, 0), ci;
     std::vector<double> v;
+    std::vector<int64_t> src;
     for (int32_t r = 0; r < b.m; ++r) {
       int64_t t = b.m0 + r;
       bool has_e = false;
@@ -353,6 +373,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
           if (c <= t) {
             ci.push_back((int32_t)(c - b.m0));
             v.push_back(H.a_v[e]);
+            src.push_back(H.a_src[e]);
           }
         } else {
           if (!has_e) {
@@ -362,6 +383,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
           }
           b.e_q.push_back((int32_t)(c - m));
           b.e_val.push_back(H.a_v[e]);
+          b.e_src.push_back(H.a_src[e]);
         }
       }
       rp[r + 1] = (int32_t)ci.size();
@@ -377,6 +399,35 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     }
     b.nnz_L = (int64_t)F.v.size();
     build_sweeps(F, fp32, b.fwd, b.bwd);
+    if (H.have_plan) {
+      // incomplete factors keep the input pattern: entry e of the block's
+      // factor is entry f_base + e of the global one
+      RefactorPlan &P = H.fb;
+      b.f_base = (int64_t)P.ci.size();
+      for (int32_t r = 0; r < b.m; ++r) {
+        for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+          P.ci.push_back(b.m0 + ci[e]);
+          P.src.push_back(src[e]);
+        }
+        P.rp.push_back((int64_t)P.ci.size());
+      }
+    }
+  }
+  if (H.have_plan) {
+    // levels of the B factorisation: level l of every block together (the
+    // dependencies of a row are the columns of its factor row, as for the
+    // forward sweep)
+    int32_t nl = 0;
+    for (const Block &b : H.blocks) nl = std::max(nl, b.fwd.nlev);
+    std::vector<std::vector<int32_t>> by(nl);
+    for (const Block &b : H.blocks)
+      for (int32_t l = 0; l < b.fwd.nlev; ++l)
+        for (int32_t t = b.fwd.levptr[l]; t < b.fwd.levptr[l + 1]; ++t) by[l].push_back(b.m0 + b.fwd.rows[t]);
+    H.fb.lev.assign(1, 0);
+    for (auto &v : by) {
+      H.fb.rows.insert(H.fb.rows.end(), v.begin(), v.end());
+      H.fb.lev.push_back((int32_t)H.fb.rows.size());
+    }
   }
   // E^T rows grouped by owner subdomain
   for (int64_t t = 0; t < s; ++t) {
@@ -393,6 +444,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
         }
         b.t_j.push_back((int32_t)(c - b.m0));
         b.t_val.push_back(H.a_v[e]);
+        b.t_src.push_back(H.a_src[e]);
       }
     }
   }
@@ -401,12 +453,14 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
   {
     std::vector<int32_t> rp(s + 1, 0), ci;
     std::vector<double> v;
+    std::vector<int64_t> src;
     for (int64_t t = 0; t < s; ++t) {
       for (int64_t e = H.a_rp[m + t]; e < H.a_rp[m + t + 1]; ++e) {
         int64_t c = H.a_ci[e];
         if (c >= m && c <= m + t) {
           ci.push_back((int32_t)(c - m));
           v.push_back(H.a_v[e]);
+          src.push_back(H.a_src[e]);
         }
       }
       rp[t + 1] = (int32_t)ci.size();
@@ -420,6 +474,17 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     }
     H.nnz_LC = (int64_t)F.v.size();
     build_sweeps(F, fp32, H.cfwd, H.cbwd);
+    if (H.have_plan) {
+      RefactorPlan &P = H.fc;
+      P = RefactorPlan();
+      P.kind = 0;
+      P.rp.assign(rp.begin(), rp.end());
+      P.ci = ci;
+      P.src = src;
+      P.lev = H.cfwd.levptr;
+      P.rows = H.cfwd.rows;
+      if (P.lev.empty()) P.lev.push_back(0);
+    }
   }
   return SLR_OK;
 }

@@ -21,6 +21,12 @@ struct Sweep {
   std::vector<int32_t> ci;
   std::vector<double> w;
   std::vector<double> sc;
+  // Where the coefficients come from (entry indices of the factor's CSR
+  // values, for a numeric refactorisation on the device): sc[t] uses entry
+  // sc_e[t] (the row's diagonal), w[e] uses entry w_e[e] and, when
+  // `divided`, the row's diagonal as divisor.  sc is 1 when `unit_sc`.
+  std::vector<int32_t> sc_e, w_e;
+  bool divided = true, unit_sc = false;
 };
 
 // Lower factor in CSR (sorted columns, diagonal last in each row).
@@ -41,7 +47,21 @@ struct Block {            // one subdomain
   // E^T rows: interface rows owned by this subdomain
   std::vector<int32_t> t_q, t_ptr, t_j;     // t_j: local interior index
   std::vector<double> t_val;
+  std::vector<int64_t> e_src, t_src;        // entries of the input CSR behind e_val / t_val
   int64_t nnz_L = 0;
+  int64_t f_base = 0;                       // first entry of this block's factor in the global B factor
+};
+
+// Lower factor of a block-diagonal matrix for a device refactorisation:
+// rows in the internal order, diagonal last; src[e] is the entry of the
+// input CSR that holds the matrix value at e; rows[lev[l] .. lev[l+1]) are
+// independent once all earlier levels are done.
+struct RefactorPlan {
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<int64_t> src;
+  std::vector<int32_t> lev, rows;
+  int kind = 0;   // 0: IC(0), 2: ILDL^T(0)
 };
 
 struct HostSetup {
@@ -57,11 +77,20 @@ struct HostSetup {
   std::vector<int64_t> a_rp;
   std::vector<int32_t> a_ci;
   std::vector<double> a_v;
+  std::vector<int64_t> a_src;   // input CSR entry of each a_v
+  // device refactorisation plans (filled when the factors are incomplete
+  // and SetupParams::plan is set)
+  bool have_plan = false;
+  RefactorPlan fb, fc;
 };
 
 struct SetupParams {
   int b_fact = 1, c_fact = 1, c_order = 0, fact_prec = 0;
+  bool plan = false;   // build the refactorisation plans
 };
+
+// A symmetric in pattern and value: every (i, j) has a matching (j, i).
+bool is_symmetric(int64_t n, const int64_t *rp, const int32_t *ci, const double *v);
 
 // Returns 0 or an SLR_ERR_* code; `err` receives a message.
 int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,

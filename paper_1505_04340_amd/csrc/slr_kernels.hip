@@ -2043,8 +2043,107 @@ void launch_round_copy(int64_t n, const double *src, TU *dst, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Numeric refactorisation (same pattern, new values), Sec. 5.2 local solvers
+// restricted to no fill: IC(0) / ILDL^T(0) level by level, then the stored
+// sweep coefficients rewritten in place.
+// ---------------------------------------------------------------------------
+__global__ void k_gather(int64_t n, const int64_t *src, const double *val, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = val[src[i]];
+}
+
+void launch_gather(int64_t n, const int64_t *src, const double *val, double *out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, src, val, out);
+}
+
+// One thread per row of the level.  Row i, entries e (ascending columns j,
+// diagonal last):
+//   IC(0):    l_ij = (a_ij - sum_k l_ik l_jk) / l_jj,  l_ii = sqrt(a_ii - sum_j l_ij^2)
+//   ILDL(0):  l_ij = (a_ij - sum_k (l_ik l_jk) d_k) / d_j,  d_i = a_ii - sum_j (l_ij l_ij) d_j
+// with k over the columns that rows i and j share (k < j), summed in row
+// j's column order: the same operations, in the same order, as the host
+// factorisation (whose dense scatter adds exact zeros for the others).
+__global__ void k_fact_level(const int64_t *rp, const int32_t *ci, double *V, const int32_t *rows, int32_t r0,
+                             int32_t r1, int32_t ldl, int *err) {
+#pragma clang fp contract(off)
+  const int32_t r = r0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (r >= r1) return;
+  const int32_t i = rows[r];
+  const int64_t a = rp[i], b = rp[i + 1] - 1;
+  if (b < a || ci[b] != i) {
+    *err = 1;
+    return;
+  }
+  double acc = 0.0;
+  for (int64_t e = a; e < b; ++e) {
+    const int32_t j = ci[e];
+    const int64_t ja = rp[j], jb = rp[j + 1] - 1;
+    double s = 0.0;
+    int64_t q = a;
+    for (int64_t t = ja; t < jb; ++t) {
+      const int32_t k = ci[t];
+      while (q < e && ci[q] < k) ++q;
+      if (q < e && ci[q] == k) {
+        const double prod = V[q] * V[t];
+        s += ldl ? prod * V[rp[k + 1] - 1] : prod;
+      }
+    }
+    const double pj = V[jb];
+    const double l = (V[e] - s) / pj;
+    V[e] = l;
+    acc += ldl ? (l * l) * pj : l * l;
+  }
+  const double piv = V[b] - acc;
+  if (ldl) {
+    if (!(fabs(piv) >= 1e-300)) *err = 1;
+    V[b] = piv;
+  } else {
+    if (!(piv > 0.0)) *err = 1;
+    V[b] = sqrt(piv);
+  }
+}
+
+void launch_fact_level(const int64_t *rp, const int32_t *ci, double *V, const int32_t *rows, int32_t r0, int32_t r1,
+                       int32_t ldl, int *err, hipStream_t st) {
+  if (r1 <= r0) return;
+  hipLaunchKernelGGL(k_fact_level, dim3((unsigned)((r1 - r0 + 255) / 256)), dim3(256), 0, st, rp, ci, V, rows, r0,
+                     r1, ldl, err);
+}
+
+template <typename TS>
+__global__ void k_rf_pack(int64_t nmap, const RfMap *map, const double *V, const double *val, uint8_t *base) {
+#pragma clang fp contract(off)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nmap) return;
+  const RfMap m = map[t];
+  auto rd = [](double x) { return (double)(TS)x; };
+  double v = 0.0;
+  switch (m.op) {
+    case RF_SRC: v = val[m.a]; break;
+    case RF_ONE: v = 1.0; break;
+    case RF_RAW: v = rd(V[m.a]); break;
+    case RF_RECIP: v = rd(1.0 / rd(V[m.a])); break;
+    case RF_DIV: v = rd(rd(V[m.a]) / rd(V[m.b])); break;
+    case RF_W2: v = rd(rd(rd(V[m.a]) / rd(V[m.b])) * rd(1.0 / rd(V[m.c]))); break;
+    default: break;
+  }
+  *reinterpret_cast<TS *>(base + m.off) = (TS)v;
+}
+
+template <typename TS>
+void launch_rf_pack(int64_t nmap, const RfMap *map, const double *V, const double *val, void *base,
+                    hipStream_t st) {
+  if (nmap <= 0) return;
+  hipLaunchKernelGGL((k_rf_pack<TS>), dim3((unsigned)((nmap + 255) / 256)), dim3(256), 0, st, nmap, map, V, val,
+                     (uint8_t *)base);
+}
+
+// ---------------------------------------------------------------------------
 // explicit instantiations
 // ---------------------------------------------------------------------------
+template void launch_rf_pack<double>(int64_t, const RfMap *, const double *, const double *, void *, hipStream_t);
+template void launch_rf_pack<float>(int64_t, const RfMap *, const double *, const double *, void *, hipStream_t);
 template void launch_bsolve<double, double>(const BlockArrays<double> &, int32_t, const BArgs &, int32_t, size_t,
                                             hipStream_t);
 template void launch_bsolve<float, float>(const BlockArrays<float> &, int32_t, const BArgs &, int32_t, size_t,
