@@ -143,6 +143,27 @@ def measure_form(P, pr, form, steps, warmup, v0, bd, xs, log_prefix):
     return G, info, res, stages, bf
 
 
+def measure_refactor(P, pr, form, v0, reps=5):
+    """Device refactorisation (slr_refactor) of the workload's own values
+    against the host setup of the same preconditioner (factorisation,
+    analysis, packing and upload)."""
+    import torch
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order=form["c_order"], fact_prec=form["fact_prec"],
+              uk_prec=form["uk_prec"], v0=v0, refactor=True)
+    host_s = G.query()["setup_host_s"]
+    G.refactor(pr.csr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.refactor(pr.csr)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    log(f"[bench:refactor] device refactorisation {ms:.3f} ms vs host setup {1e3 * host_s:.1f} ms")
+    del G
+    return {"refactor_ms": round(ms, 3), "host_setup_ms": round(1e3 * host_s, 3)}
+
+
 SERVE_MAXIT = 1000
 
 
@@ -287,6 +308,7 @@ def main():
         "solve_only_solves_per_s": res["solve_only_solves_per_s"], "lanczos_build_ms": res["lanczos_build_ms"],
         "apply_ms": res["apply_ms"], "apply_algorithmic_GBs": res["apply_algorithmic_GBs"],
         "forms": forms,
+        "refactor": measure_refactor(P, pr, FORMS["fp64"], v0),
     }
     if not args.no_serve:
         del G

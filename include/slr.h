@@ -214,7 +214,8 @@ int slr_grow_lowrank(slr_ctx *c, int32_t k_add, int32_t lanczos_steps, const dou
                      void *hip_stream);
 
 /* slr_refactor: new values for A with the pattern given to slr_setup (val:
- * host, nnz, in that CSR's order), for a context set up with
+ * nnz values in that CSR's order, on the host, or on the device when
+ * on_device != 0; the call does not keep the pointer), for a context set up with
  * opts.refactor = 1.  The zero-fill factors of the B_i and of C (Sec. 5.2,
  * IC(0) / ILDL^T(0)) are recomputed on the device, level by level with the
  * schedules of the forward sweeps, and every stored coefficient of the
@@ -222,12 +223,13 @@ int slr_grow_lowrank(slr_ctx *c, int32_t k_add, int32_t lanczos_steps, const dou
  * rewritten in place in the context's storage precision; the results equal
  * those of a fresh slr_setup with the new values.  The low-rank part
  * (U_k, Lambda_k, theta) is kept: call slr_update_lowrank to rebuild it for
- * the new H.  Errors: SLR_ERR_NOT_SYMMETRIC (checked on the host),
+ * the new H.  Errors: SLR_ERR_NOT_SYMMETRIC (every value must equal its
+ * mirror's; checked where the values are),
  * SLR_ERR_BREAKDOWN (a B_i pivot), SLR_ERR_C_NOT_SPD (a C pivot) -- after
  * which every stored coefficient is unchanged -- and SLR_ERR_ARG (no
  * opts.refactor, or batches exist on the context).  Synchronises
  * hip_stream. */
-int slr_refactor(slr_ctx *c, const double *val, void *hip_stream);
+int slr_refactor(slr_ctx *c, const double *val, int32_t on_device, void *hip_stream);
 
 /* slr_time_kernel: average device time (ms, via HIP events on hip_stream)
  * of `reps` back-to-back launches of one hot-path stage on nrhs internal

@@ -96,7 +96,7 @@ slr_analyze = _sig("slr_analyze", ctypes.c_int, [ctypes.POINTER(slr_csr), _P, _I
                                                  ctypes.POINTER(slr_info), _P])
 slr_update_lowrank = _sig("slr_update_lowrank", ctypes.c_int, [_P, _I32, _I32, _P, _P])
 slr_grow_lowrank = _sig("slr_grow_lowrank", ctypes.c_int, [_P, _I32, _I32, _P, _P])
-slr_refactor = _sig("slr_refactor", ctypes.c_int, [_P, _P, _P])
+slr_refactor = _sig("slr_refactor", ctypes.c_int, [_P, _P, _I32, _P])
 slr_time_kernel = _sig("slr_time_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P, ctypes.POINTER(_D)])
 slr_apply = _sig("slr_apply", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_apply_dd = _sig("slr_apply_dd", ctypes.c_int, [_P, _P, _P, _I32, _P])
@@ -266,7 +266,18 @@ class SLR:
         if n != self.n or not (np.array_equal(indptr, self._pattern[0])
                                and np.array_equal(indices, self._pattern[1])):
             raise ValueError("refactor needs the pattern given at setup")
-        _check(slr_refactor(self._h, data.ctypes.data, _stream(stream)), "slr_refactor")
+        _check(slr_refactor(self._h, data.ctypes.data, 0, _stream(stream)), "slr_refactor")
+
+    def refactor_values(self, values, stream=None):
+        """As refactor, with the nnz values (setup's CSR order) given as an
+        FP64 tensor on the GPU."""
+        if self._pattern is None:
+            raise ValueError("set up with refactor=True to refactor")
+        import torch
+        if values.dtype != torch.float64 or not values.is_cuda or values.numel() != len(self._pattern[1]):
+            raise ValueError("values: FP64 CUDA tensor with one entry per stored entry of A")
+        v = values.contiguous()
+        _check(slr_refactor(self._h, ctypes.c_void_p(v.data_ptr()), 1, _stream(stream)), "slr_refactor")
 
     def grow_lowrank(self, k_add: int, lanczos_steps: int = 0, v0=None, stream=None):
         """Append up to k_add Ritz pairs from a deflated Lanczos run, keeping

@@ -136,8 +136,9 @@ struct slr_ctx {
   struct Refactor {
     bool on = false;
     DevPool pool;
-    std::vector<int64_t> in_rp;
-    std::vector<int32_t> in_ci;
+    std::vector<int64_t> tr_h;       // entry of A's mirror (j, i) of each entry (i, j)
+    int64_t *tr = nullptr;
+    double *stage = nullptr;         // pinned host staging of the values
     int64_t nnz = 0;
     double *val = nullptr;
     int *err = nullptr;
@@ -847,8 +848,18 @@ const double *seeded_v0(int64_t n, uint64_t seed, std::vector<double> &v0) {
 bool rf_upload(slr_ctx *c, const HostSetup &H, const RfMaps &rm, const slr_csr *A) {
   auto &R = c->rf;
   auto &P = R.pool;
-  R.in_rp.assign(A->rowptr, A->rowptr + A->n + 1);
-  R.in_ci.assign(A->col, A->col + A->nnz);
+  // mirror entries (the symmetry test of new values becomes one pass)
+  R.tr_h.assign(A->nnz, 0);
+  for (int64_t i = 0; i < A->n; ++i)
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) {
+      const int64_t j = A->col[e];
+      const int32_t *b = A->col + A->rowptr[j], *en = A->col + A->rowptr[j + 1];
+      R.tr_h[e] = A->rowptr[j] + (std::lower_bound(b, en, (int32_t)i) - b);
+    }
+  R.tr = P.upload(R.tr_h.empty() ? std::vector<int64_t>{0} : R.tr_h);
+  if (hipHostMalloc((void **)&R.stage, sizeof(double) * std::max<int64_t>(A->nnz, 1), hipHostMallocDefault) !=
+      hipSuccess)
+    R.stage = nullptr;
   R.nnz = A->nnz;
   R.val = P.alloc<double>((size_t)std::max<int64_t>(A->nnz, 1));
   R.err = P.alloc<int>(4);
@@ -870,7 +881,7 @@ bool rf_upload(slr_ctx *c, const HostSetup &H, const RfMaps &rm, const slr_csr *
     D.m = P.upload(v);
     return D.m != nullptr;
   };
-  bool ok = R.val && R.err && R.a_src && plan(H.fb, R.fb) && plan(H.fc, R.fc);
+  bool ok = R.val && R.err && R.a_src && R.tr && R.stage && plan(H.fb, R.fb) && plan(H.fc, R.fc);
   ok = ok && map(rm.bdata, R.bdata) && map(rm.ev, R.ev) && map(rm.tv, R.tv);
   ok = ok && map(rm.cf.sc, R.cfsc) && map(rm.cf.w, R.cfw) && map(rm.cf.w2, R.cfw2);
   ok = ok && map(rm.cb.sc, R.cbsc) && map(rm.cb.w, R.cbw) && map(rm.cb.w2, R.cbw2);
@@ -1136,16 +1147,24 @@ int slr_grow_lowrank(slr_ctx *c, int32_t k_add, int32_t lanczos_steps, const dou
   return lowrank_done(c, t1, st);
 }
 
-int slr_refactor(slr_ctx *c, const double *val, void *hip_stream) {
+int slr_refactor(slr_ctx *c, const double *val, int32_t on_device, void *hip_stream) {
   if (!c || !val) return fail(SLR_ERR_ARG, "null argument");
   auto &R = c->rf;
   if (!R.on) return fail(SLR_ERR_ARG, "the context was set up without opts.refactor");
   if (c->live_batches > 0) return fail(SLR_ERR_ARG, "the context still has batches");
-  if (!is_symmetric(c->n, R.in_rp.data(), R.in_ci.data(), val))
-    return fail(SLR_ERR_NOT_SYMMETRIC, "A is not symmetric (pattern and values must match)");
   hipStream_t st = S(hip_stream);
-  HIPCHK(hipMemcpyAsync(R.val, val, sizeof(double) * R.nnz, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(R.err, 0, 4 * sizeof(int), st));
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(R.val, val, sizeof(double) * R.nnz, hipMemcpyDeviceToDevice, st));
+    launch_mirror_check(R.nnz, R.tr, R.val, R.err + 2, st);
+  } else {
+    for (int64_t e = 0; e < R.nnz; ++e)
+      if (val[R.tr_h[e]] != val[e]) return fail(SLR_ERR_NOT_SYMMETRIC, "A is not symmetric (values must match)");
+    // the previous call's copy out of the staging buffer has completed (it
+    // synchronises before returning)
+    std::memcpy(R.stage, val, sizeof(double) * R.nnz);
+    HIPCHK(hipMemcpyAsync(R.val, R.stage, sizeof(double) * R.nnz, hipMemcpyHostToDevice, st));
+  }
   // factors into their own value arrays (level by level)
   launch_gather(R.fb.nnz, R.fb.src, R.val, R.fb.v, st);
   launch_gather(R.fc.nnz, R.fc.src, R.val, R.fc.v, st);
@@ -1157,6 +1176,7 @@ int slr_refactor(slr_ctx *c, const double *val, void *hip_stream) {
   HIPCHK(hipMemcpyAsync(e, R.err, sizeof(e), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   // a failed pivot leaves every stored coefficient as it was
+  if (e[2]) return fail(SLR_ERR_NOT_SYMMETRIC, "A is not symmetric (values must match)");
   if (e[0]) return fail(SLR_ERR_BREAKDOWN, "refactorisation of a B_i failed (pivot)");
   if (e[1]) return fail(SLR_ERR_C_NOT_SPD, "refactorisation of C failed (pivot)");
   launch_gather(c->nnz_a, R.a_src, R.val, c->a_v, st);
@@ -1274,6 +1294,7 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
 
 void slr_destroy(slr_ctx *c) {
   if (!c) return;
+  if (c->rf.stage) (void)hipHostFree(c->rf.stage);
   c->rf.pool.release();
   c->pool.release();
   c->ws.pool.release();

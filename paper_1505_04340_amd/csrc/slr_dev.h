@@ -124,6 +124,8 @@ struct RfMap {
 template <typename TS>
 void launch_rf_pack(int64_t nmap, const RfMap *map, const double *V, const double *val, void *base,
                     hipStream_t st);
+// *flag = 1 if some val[e] != val[tr[e]] (tr: the mirror entry of each entry)
+void launch_mirror_check(int64_t n, const int64_t *tr, const double *val, int *flag, hipStream_t st);
 // out[e] = val[src[e]]
 void launch_gather(int64_t n, const int64_t *src, const double *val, double *out, hipStream_t st);
 // IC(0) (ldl = 0) or ILDL^T(0) (ldl = 1) of the rows rows[r0 .. r1) of the

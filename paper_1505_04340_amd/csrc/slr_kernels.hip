@@ -2052,6 +2052,16 @@ __global__ void k_gather(int64_t n, const int64_t *src, const double *val, doubl
   if (i < n) out[i] = val[src[i]];
 }
 
+__global__ void k_mirror_check(int64_t n, const int64_t *tr, const double *val, int *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && val[tr[i]] != val[i]) *flag = 1;
+}
+
+void launch_mirror_check(int64_t n, const int64_t *tr, const double *val, int *flag, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mirror_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, tr, val, flag);
+}
+
 void launch_gather(int64_t n, const int64_t *src, const double *val, double *out, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, src, val, out);

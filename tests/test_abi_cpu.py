@@ -84,7 +84,7 @@ def test_host_only_entry_points():
     o.refactor, o.b_fact = 1, P.SLR_FACT_CHOL
     assert P.slr_setup(ctypes.byref(csr), pa.ctypes.data, 1, ctypes.byref(o), None, ctypes.byref(h)) == P.SLR_ERR_ARG
     assert b"refactor" in P.slr_last_error()
-    assert P.slr_refactor(None, None, None) == P.SLR_ERR_ARG
+    assert P.slr_refactor(None, None, 0, None) == P.SLR_ERR_ARG
 
 
 def test_build_sources_are_gfx950_hip():

@@ -60,6 +60,9 @@ def test_refactor_equals_fresh_setup(fact_prec, b_fact):
     zf = F.apply(_dev(r)).cpu().numpy()
     print(f"[refactor] {fact_prec}/{b_fact}: bitwise equal to a fresh setup: {np.array_equal(z, zf)}")
     assert np.array_equal(z, zf)
+    # the same values from device memory
+    G.refactor_values(torch.tensor(A2[2], dtype=torch.float64, device="cuda"))
+    assert np.array_equal(G.apply(_dev(r)).cpu().numpy(), zf)
     # the Krylov products use the new values
     x = np.random.default_rng(6).uniform(-1, 1, n)
     q = G.spmv(_dev(x)).cpu().numpy()
@@ -96,6 +99,17 @@ def test_refactor_failed_pivot_keeps_coefficients():
             G.refactor(Ab)
         assert ei.value.code == code
         assert np.array_equal(G.apply(_dev(r)).cpu().numpy(), z0)
+    # values that break symmetry, from the host and from device memory
+    vals = np.array(A1[2], dtype=np.float64)
+    off = int(np.flatnonzero(np.asarray(A1[1]) != np.repeat(np.arange(n), np.diff(A1[0])))[0])
+    vals[off] *= 1.5
+    with pytest.raises(P.SLRError) as ei:
+        G.refactor((A1[0], A1[1], vals, n))
+    assert ei.value.code == P.SLR_ERR_NOT_SYMMETRIC
+    with pytest.raises(P.SLRError) as ei:
+        G.refactor_values(torch.tensor(vals, device="cuda"))
+    assert ei.value.code == P.SLR_ERR_NOT_SYMMETRIC
+    assert np.array_equal(G.apply(_dev(r)).cpu().numpy(), z0)
     # refused: pattern change, no refactor option, live batch
     with pytest.raises(ValueError):
         G.refactor(_csr(A1) + sp.eye(n, format="csr") * 0 + sp.csr_matrix(([1.0], ([0], [n - 1])), shape=(n, n)))
