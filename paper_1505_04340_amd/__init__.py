@@ -20,6 +20,9 @@ import ctypes
 import os
 
 import numpy as np
+# PyTorch first: the library must bind to the HIP runtime that PyTorch
+# loads (loading the library first leaves device allocation failing).
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslr.so")

@@ -470,3 +470,19 @@ def test_multi_rhs_bf16_mfma_apply(fact_prec):
         assert _relerr(Z, Po.apply(r)).max() <= 1e-5
         z1 = np.column_stack([G.apply(_dev(r[:, j])).cpu().numpy() for j in (0, nr - 1)])
         assert _relerr(Z[:, [0, nr - 1]], z1).max() <= 1e-6
+
+
+def test_library_imported_before_torch():
+    """Importing the package before PyTorch still gives a working context
+    (the package loads PyTorch's HIP runtime first)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1505_04340_amd as P, slr_inputs as si\n"
+            "pr = si.make_config('lap2d_64', N=24)\n"
+            "G = P.SLR(pr.csr, pr.part, pr.nparts, k=4, lanczos_steps=20)\n"
+            "print('ok', G.info['k'])\n") % root
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and "ok 4" in r.stdout, r.stderr[-2000:]
