@@ -120,11 +120,12 @@ struct slr_ctx {
   // low-rank part
   int32_t k = 0;
   double theta = 0.0, rho = 1.0;
-  void *U = nullptr;            // s x k column-major, storage precision
+  void *U = nullptr;            // s x k column-major, storage precision (BF16: matrix-core path)
+  void *Urm = nullptr;          // FP64 / FP32 storage: row-major padded copy (U^T w)
   double *U64 = nullptr;        // s x k column-major, FP64 (export)
   double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
-  int32_t lr_nblk = 128;       // row chunks of the scalar rank-k partials
+  int32_t lr_nblk = 256;       // group chunks of the row-major rank-k partials
   int32_t lrm_nblk = 512;      // row chunks of the matrix-core rank-k partials
   // BF16 U_k always takes the matrix-core path, so a column's arithmetic
   // never depends on how many columns share the launch
@@ -288,12 +289,12 @@ void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wou
   const int k = c->k;
   switch (c->uk_prec) {
     case SLR_FP64:
-      launch_lowrank<double>((const double *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo, nrhs, w.lr_part,
-                             c->lr_nblk, w.cbuf, w.counter, st);
+      launch_lowrank_rm<double>((const double *)c->Urm, (const double *)c->U, c->s, k, c->dsc, c->rho, win, ldw,
+                                wout, ldo, nrhs, w.lr_part, c->lr_nblk, w.cbuf, st);
       break;
     case SLR_FP32:
-      launch_lowrank<float>((const float *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo, nrhs, w.lr_part,
-                            c->lr_nblk, w.cbuf, w.counter, st);
+      launch_lowrank_rm<float>((const float *)c->Urm, (const float *)c->U, c->s, k, c->dsc, c->rho, win, ldw,
+                               wout, ldo, nrhs, w.lr_part, c->lr_nblk, w.cbuf, st);
       break;
     default:
       if (nrhs >= c->mfma_min_rhs && k > 0)
@@ -377,6 +378,17 @@ int upload_lowrank_T(slr_ctx *c, hipStream_t st) {
   return SLR_OK;
 }
 
+template <typename TU>
+int upload_lowrank_rm(slr_ctx *c, hipStream_t st) {
+  int32_t ldk;
+  const int64_t n = lr_rm_groups<TU>(c->s, c->k, ldk) * 64 * (16 / (int64_t)sizeof(TU));
+  TU *U = c->lrpool.alloc<TU>((size_t)n);
+  if (!U) return fail(SLR_ERR_OOM, "U storage");
+  launch_lr_to_rm<TU>(c->U64, c->s, c->k, U, st);
+  c->Urm = U;
+  return SLR_OK;
+}
+
 int finish_lowrank(slr_ctx *c, hipStream_t st) {
   // scales of eq. skt: (1 - lambda_i)^{-1} - (1 - theta)^{-1}; under the
   // eq. Lambda-2 form rho = 1 and eps (1 - lambda_i)^{-1} - 1
@@ -392,11 +404,15 @@ int finish_lowrank(slr_ctx *c, hipStream_t st) {
   c->dsc = c->lrpool.upload(d);
   if (!c->dsc) return fail(SLR_ERR_OOM, "dsc");
   if (c->k == 0) return SLR_OK;
+  c->Urm = nullptr;
   if (c->uk_prec == SLR_FP64) {
     c->U = c->U64;
-    return SLR_OK;
+    return upload_lowrank_rm<double>(c, st);
   }
-  if (c->uk_prec == SLR_FP32) return upload_lowrank_T<float>(c, st);
+  if (c->uk_prec == SLR_FP32) {
+    const int rc = upload_lowrank_T<float>(c, st);
+    return rc ? rc : upload_lowrank_rm<float>(c, st);
+  }
   return upload_lowrank_T<__hip_bfloat16>(c, st);
 }
 
@@ -570,6 +586,7 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   c->lrpool = nl;
   c->U64 = U64;
   c->U = nullptr;
+  c->Urm = nullptr;
   c->dsc = nullptr;
   c->k = k0 + kk;
   c->lam_h = lam;
@@ -1117,6 +1134,7 @@ int slr_update_lowrank(slr_ctx *c, int32_t k, int32_t lanczos_steps, const doubl
   } else {
     c->lrpool.release();
     c->U = nullptr;
+  c->Urm = nullptr;
     c->U64 = nullptr;
     c->dsc = nullptr;
     c->k = 0;

@@ -109,6 +109,18 @@ void launch_ritz(int64_t s, int32_t m, int32_t k, const double *V, int64_t ldv, 
                  TU *U, hipStream_t st);
 template <typename TU>
 void launch_round_copy(int64_t n, const double *src, TU *dst, hipStream_t st);
+// rank-k block with U^T w from a row-major copy of U (FP64 / FP32): groups
+// of the padded layout (ldk receives the padded row length), the copy from
+// the column-major FP64 U (lr_rm_groups * 64 * (16 / sizeof(TU)) entries),
+// and the block itself (the update reads the column-major U)
+template <typename TU>
+int64_t lr_rm_groups(int64_t s, int32_t k, int32_t &ldk);
+template <typename TU>
+void launch_lr_to_rm(const double *U64, int64_t s, int32_t k, TU *Urm, hipStream_t st);
+template <typename TU>
+void launch_lowrank_rm(const TU *Urm, const TU *U, int64_t s, int32_t k, const double *dsc, double rho,
+                       const double *w, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs, double *part,
+                       int32_t nblk, double *cbuf, hipStream_t st);
 
 }  // namespace slr
 

@@ -699,6 +699,165 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
 }
 
 // ---------------------------------------------------------------------------
+// K4 with U_k row-major (FP64 / FP32 storage).  U holds s rows of ldk
+// entries (ldk: a power of two >= max(k, VEC); columns >= k and rows >= s
+// are zero; the array is padded to whole groups).  A group is what one
+// wave reads with one 16-byte load per lane: G = 64 VEC entries, lane l
+// holding entries VEC l .. VEC l + VEC - 1, i.e. columns (VEC l) % ldk + v
+// of row g RG + (VEC l) / ldk, RG = G / ldk.  Lanes with equal
+// l % (ldk / VEC) own the same columns, so a column's sum needs a shuffle
+// over only 64 VEC / ldk lanes.  The update U c reads the column-major U
+// (one row per thread, which measured faster than the row-major form).
+// ---------------------------------------------------------------------------
+constexpr int LRR_RT = 4;   // right-hand sides per register tile
+constexpr int LRR_GU = 4;   // groups in flight per lane
+
+template <typename TU>
+struct LrVec;
+template <>
+struct LrVec<double> {
+  static constexpr int V = 2;
+  typedef double2 T;
+};
+template <>
+struct LrVec<float> {
+  static constexpr int V = 4;
+  typedef float4 T;
+};
+
+template <typename TU>
+__device__ __forceinline__ void lr_unpack(const typename LrVec<TU>::T &x, double *u);
+template <>
+__device__ __forceinline__ void lr_unpack<double>(const double2 &x, double *u) {
+  u[0] = x.x;
+  u[1] = x.y;
+}
+template <>
+__device__ __forceinline__ void lr_unpack<float>(const float4 &x, double *u) {
+  u[0] = x.x;
+  u[1] = x.y;
+  u[2] = x.z;
+  u[3] = x.w;
+}
+
+// partial sums U^T w over the groups of block b -> part[(b nrhs + r) k + q]
+template <typename TU>
+__global__ void __launch_bounds__(256) k_lr_partial_rm(const TU *U, int ldk, int64_t ng, int64_t s, int k,
+                                                       const double *w, int64_t ldw, int nrhs, double *part) {
+  constexpr int VEC = LrVec<TU>::V;
+  typedef typename LrVec<TU>::T VT;
+  __shared__ double red[4][64 * LRR_RT];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t per = (ng + gridDim.x - 1) / gridDim.x;
+  const int64_t g0 = (int64_t)blockIdx.x * per, g1 = min(ng, g0 + per);
+  const int RG = 64 * VEC / ldk;
+  const int rof = VEC * lane / ldk;          // row of this lane inside a group
+  const int cw = ldk / VEC;                  // lanes per row
+  const VT *Uv = reinterpret_cast<const VT *>(U);
+  for (int r0 = 0; r0 < nrhs; r0 += LRR_RT) {
+    const int nr = min(LRR_RT, nrhs - r0);
+    double acc[LRR_RT][VEC];
+#pragma unroll
+    for (int r = 0; r < LRR_RT; ++r)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[r][v] = 0.0;
+    for (int64_t gb = g0 + wv; gb < g1; gb += 4 * LRR_GU) {
+      VT x[LRR_GU];
+      double wr[LRR_GU][LRR_RT];
+#pragma unroll
+      for (int j = 0; j < LRR_GU; ++j) {
+        const int64_t g = min(gb + 4 * j, g1 - 1);   // clamped groups add nothing (their weight is 0)
+        x[j] = Uv[g * 64 + lane];
+        const int64_t row = min(g * RG + rof, s - 1);
+#pragma unroll
+        for (int r = 0; r < LRR_RT; ++r)
+          wr[j][r] = (r < nr && gb + 4 * j < g1) ? w[row + (int64_t)(r0 + r) * ldw] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < LRR_GU; ++j) {
+        double u[VEC];
+        lr_unpack<TU>(x[j], u);
+#pragma unroll
+        for (int r = 0; r < LRR_RT; ++r)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[r][v] += u[v] * wr[j][r];
+      }
+    }
+    // lanes l, l + cw, l + 2 cw, ... own the same columns
+#pragma unroll
+    for (int r = 0; r < LRR_RT; ++r)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        double a = acc[r][v];
+        for (int o = cw; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+        acc[r][v] = a;
+      }
+    if (lane < cw) {
+#pragma unroll
+      for (int r = 0; r < LRR_RT; ++r)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) red[wv][r * 64 + VEC * lane + v] = acc[r][v];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nr * ldk; t += blockDim.x) {
+      const int r = t / ldk, q = t - r * ldk;
+      if (q < k) {
+        const double v = (red[0][r * 64 + q] + red[1][r * 64 + q]) + (red[2][r * 64 + q] + red[3][r * 64 + q]);
+        part[((int64_t)blockIdx.x * nrhs + r0 + r) * k + q] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// row-major padded copy of a column-major FP64 U (s x k)
+template <typename TU>
+__global__ void k_lr_to_rm(const double *U64, int64_t s, int k, int ldk, int64_t total, TU *Urm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t row = t / ldk;
+  const int q = (int)(t - row * ldk);
+  Urm[t] = (row < s && q < k) ? round_store<TU>(U64[row + (int64_t)q * s]) : (TU)0;
+}
+
+template <typename TU>
+int64_t lr_rm_groups(int64_t s, int32_t k, int32_t &ldk) {
+  constexpr int VEC = LrVec<TU>::V;
+  ldk = VEC;
+  while (ldk < k) ldk <<= 1;
+  const int64_t RG = 64 * VEC / ldk;
+  return (s + RG - 1) / RG;
+}
+
+template <typename TU>
+void launch_lr_to_rm(const double *U64, int64_t s, int32_t k, TU *Urm, hipStream_t st) {
+  int32_t ldk;
+  const int64_t total = lr_rm_groups<TU>(s, k, ldk) * 64 * LrVec<TU>::V;
+  if (total == 0) return;
+  hipLaunchKernelGGL((k_lr_to_rm<TU>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, U64, s, k, ldk, total,
+                     Urm);
+}
+
+// U^T w from the row-major copy Urm, the update from the column-major U
+template <typename TU>
+void launch_lowrank_rm(const TU *Urm, const TU *U, int64_t s, int32_t k, const double *dsc, double rho,
+                       const double *w, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs, double *part,
+                       int32_t nblk, double *cbuf, hipStream_t st) {
+  if (s == 0 || nrhs == 0) return;
+  if (k == 0) {
+    launch_axpby(s, nrhs, rho, w, ldw, 0.0, wout, ldo, st);
+    return;
+  }
+  int32_t ldk;
+  const int64_t ng = lr_rm_groups<TU>(s, k, ldk);
+  hipLaunchKernelGGL((k_lr_partial_rm<TU>), dim3(nblk), dim3(256), 0, st, Urm, ldk, ng, s, k, w, ldw, nrhs, part);
+  hipLaunchKernelGGL(k_lr_fold, dim3((unsigned)((k * nrhs + 3) / 4)), dim3(256), 0, st, part, nblk, k * nrhs, k,
+                     dsc, cbuf);
+  hipLaunchKernelGGL((k_lr_update<TU>), dim3((unsigned)((s + 255) / 256)), dim3(256), sizeof(double) * k * nrhs, st,
+                     U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+}
+
+// ---------------------------------------------------------------------------
 // K4 on matrix cores (BF16 U_k, several right-hand sides).
 // v_mfma_f32_16x16x16bf16_1k, one wave: D(16x16) += A(16x16) B(16x16) with
 //   A: lane l holds A[l%16][4(l/16) + 0..3], B: lane l holds B[4(l/16)+0..3][l%16],
@@ -2152,6 +2311,16 @@ void launch_rf_pack(int64_t nmap, const RfMap *map, const double *V, const doubl
 // ---------------------------------------------------------------------------
 // explicit instantiations
 // ---------------------------------------------------------------------------
+template int64_t lr_rm_groups<double>(int64_t, int32_t, int32_t &);
+template int64_t lr_rm_groups<float>(int64_t, int32_t, int32_t &);
+template void launch_lr_to_rm<double>(const double *, int64_t, int32_t, double *, hipStream_t);
+template void launch_lr_to_rm<float>(const double *, int64_t, int32_t, float *, hipStream_t);
+template void launch_lowrank_rm<double>(const double *, const double *, int64_t, int32_t, const double *, double,
+                                        const double *, int64_t, double *, int64_t, int32_t, double *, int32_t,
+                                        double *, hipStream_t);
+template void launch_lowrank_rm<float>(const float *, const float *, int64_t, int32_t, const double *, double,
+                                       const double *, int64_t, double *, int64_t, int32_t, double *, int32_t,
+                                       double *, hipStream_t);
 template void launch_rf_pack<double>(int64_t, const RfMap *, const double *, const double *, void *, hipStream_t);
 template void launch_rf_pack<float>(int64_t, const RfMap *, const double *, const double *, void *, hipStream_t);
 template void launch_bsolve<double, double>(const BlockArrays<double> &, int32_t, const BArgs &, int32_t, size_t,
