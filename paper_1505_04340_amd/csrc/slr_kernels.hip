@@ -1067,6 +1067,35 @@ void launch_permute(int64_t n, const int64_t *idx, const double *src, int64_t ld
 // row in entry order.
 constexpr int SPMV_T = 8;
 
+// acc[t] += sum_e v[e] x[ci[e] + (c0 + t) ldx] for the entries e0 <= e < e1
+// of one CSR row, in entry order, for the columns t < T with act[t].  The
+// value, index and gather loads of U entries at a time go out together
+// (loads past the row end are clamped to its last entry and not added).
+template <int T, int U>
+__device__ __forceinline__ void csr_row_acc(int64_t e0, int64_t e1, const int32_t *ci, const double *v,
+                                            const double *x, int64_t ldx, int c0, const bool *act, double *acc) {
+  for (int64_t e = e0; e < e1; e += U) {
+    double a[U], xv[U][T];
+    int64_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t ee = min(e + u, e1 - 1);
+      a[u] = v[ee];
+      j[u] = ci[ee];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < T; ++t) xv[u][t] = act[t] ? x[j[u] + (int64_t)(c0 + t) * ldx] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e + u < e1)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+          if (act[t]) acc[t] += a[u] * xv[u][t];
+  }
+}
+
 template <int T>
 __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *rp, const int32_t *ci,
                                               const double *v, const double *x, int64_t ldx, double *y,
@@ -1075,15 +1104,13 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *rp, cons
   if (i >= n) return;
   const int c0 = blockIdx.y * T, nct = min(T, nrhs - c0);
   double acc[T];
+  bool act[T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) acc[t] = 0.0;
-  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-    const double a = v[e];
-    const int64_t j = ci[e];
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-      if (t < nct) acc[t] += a * x[j + (int64_t)(c0 + t) * ldx];
+  for (int t = 0; t < T; ++t) {
+    acc[t] = 0.0;
+    act[t] = t < nct;
   }
+  csr_row_acc<T, T == 1 ? 8 : 2>(rp[i], rp[i + 1], ci, v, x, ldx, c0, act, acc);
 #pragma unroll
   for (int t = 0; t < T; ++t)
     if (t < nct) y[i + (int64_t)(c0 + t) * ldy] = acc[t];
@@ -1144,13 +1171,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_cg_spmv(int64_t n, const int64_
       double sum[SPMV_T];
 #pragma unroll
       for (int t = 0; t < SPMV_T; ++t) sum[t] = 0.0;
-      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-        const double a = v[e];
-        const int64_t j = ci[e];
-#pragma unroll
-        for (int t = 0; t < SPMV_T; ++t)
-          if (act[t]) sum[t] += a * K.P[j + (int64_t)(c0 + ct + t) * K.ld];
-      }
+      csr_row_acc<SPMV_T, SPMV_T == 1 ? 8 : 2>(rp[i], rp[i + 1], ci, v, K.P, K.ld, c0 + ct, act, sum);
 #pragma unroll
       for (int t = 0; t < SPMV_T; ++t)
         if (act[t]) {
