@@ -274,14 +274,14 @@ void csweep(slr_ctx *c, bool fwd, double *x, int64_t ldx, int32_t nrhs, bool com
 
 // out-of-place two-level interface sweep (multicolour schedules)
 void csweep2(slr_ctx *c, bool fwd, const double *x, int64_t ldx, double *y, int64_t ldy, int32_t nrhs,
-             bool compute64, hipStream_t st) {
+             bool compute64, hipStream_t st, const double *dv = nullptr, double *dpart = nullptr) {
   const int32_t s = (int32_t)c->s;
   if (c->fact_prec == SLR_FP64)
-    launch_sweep2<double, double>(fwd ? c->Cfd : c->Cbd, s, x, ldx, y, ldy, nrhs, st);
+    launch_sweep2<double, double>(fwd ? c->Cfd : c->Cbd, s, x, ldx, y, ldy, nrhs, st, dv, dpart);
   else if (compute64)
-    launch_sweep2<float, double>(fwd ? c->Cff : c->Cbf, s, x, ldx, y, ldy, nrhs, st);
+    launch_sweep2<float, double>(fwd ? c->Cff : c->Cbf, s, x, ldx, y, ldy, nrhs, st, dv, dpart);
   else
-    launch_sweep2<float, float>(fwd ? c->Cff : c->Cbf, s, x, ldx, y, ldy, nrhs, st);
+    launch_sweep2<float, float>(fwd ? c->Cff : c->Cbf, s, x, ldx, y, ldy, nrhs, st, dv, dpart);
 }
 
 void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs,
@@ -348,7 +348,12 @@ int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, in
 
 // w = H v = L^{-1} E^T B^{-1} E L^{-T} v (eq. H), FP64 arithmetic on the
 // stored factors; t: s-vector scratch.
-int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipStream_t st) {
+// w = H v.  With dv and a two-level interface schedule, the last sweep also
+// leaves the per-block partial sums of dv . w in dpart and *ndp receives
+// their count (0 otherwise).
+int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipStream_t st,
+            const double *dv = nullptr, double *dpart = nullptr, int32_t *ndp = nullptr) {
+  if (ndp) *ndp = 0;
   const int64_t s = c->s;
   if (c->c_two_level) {
     csweep2(c, false, v, s, t, s, 1, true, st);
@@ -362,10 +367,12 @@ int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipSt
   a.nrhs = 1;
   int rc = bsolve(c, a, true, st);
   if (rc) return rc;
-  if (c->c_two_level)
-    csweep2(c, true, t2, s, w, s, 1, true, st);
-  else
+  if (c->c_two_level) {
+    csweep2(c, true, t2, s, w, s, 1, true, st, dv, dpart);
+    if (dv && ndp) *ndp = (int32_t)((s + 255) / 256);
+  } else {
     csweep(c, true, w, s, 1, true, st);
+  }
   return SLR_OK;
 }
 
@@ -444,14 +451,14 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   double *part = tmp.alloc<double>((size_t)RED_NBLK * (nb + 1));
   double *part2 = tmp.alloc<double>((size_t)(s + 255) / 256 + 1);
   unsigned int *cnt = tmp.alloc<unsigned int>(4);
-  // partial reorthogonalisation state: three omega rows, control words,
-  // running ||T||, per-step decisions
+  // partial reorthogonalisation state: three omega rows, and per step the
+  // force flag, the running ||T|| and the decision
   const int32_t ld_om = steps + 2;
   double *om = tmp.alloc<double>((size_t)3 * ld_om);
-  int *ctl = tmp.alloc<int>(4);
-  double *tn = tmp.alloc<double>(1);
+  int *frc = tmp.alloc<int>(steps + 1);
+  double *tn = tmp.alloc<double>(steps + 1);
   int *rflag = tmp.alloc<int>(steps);
-  if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !part2 || !cnt || !om || !ctl || !tn || !rflag) {
+  if (!V || !Wl || !T || !T2 || !h || !sc || !al || !be || !part || !part2 || !cnt || !om || !frc || !tn || !rflag) {
     tmp.release();
     return fail(SLR_ERR_OOM, "Lanczos basis");
   }
@@ -462,8 +469,8 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   };
   HIPCHK(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned int), st));
   HIPCHK(hipMemsetAsync(sc, 0, 4 * sizeof(double), st));
-  HIPCHK(hipMemsetAsync(ctl, 0, 4 * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(tn, 0, sizeof(double), st));
+  HIPCHK(hipMemsetAsync(frc, 0, sizeof(int) * (steps + 1), st));
+  HIPCHK(hipMemsetAsync(tn, 0, sizeof(double) * (steps + 1), st));
   HIPCHK(hipMemsetAsync(rflag, 0, sizeof(int) * steps, st));
   // start vector: interface entries of v0 (original order), normalised
   std::vector<double> v0(s);
@@ -497,17 +504,20 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   // v_j . H v_j = alpha_j (it also removes the beta_{j-1} v_{j-1} term), so
   // the three-term recurrence is subsumed by the full reorthogonalisation.
   for (int32_t j = 0; j < steps && pro; ++j) {
-    // partial reorthogonalisation: three-term step, omega estimates, and a
-    // gated Gram-Schmidt pass against v_0 .. v_j that runs only when the
-    // control kernel asks for it; beta_j is folded from whichever of the
-    // two kernels wrote the ||w||^2 partials last
+    // partial reorthogonalisation: three-term step, then one Gram-Schmidt
+    // pass against v_0 .. v_j whose kernels first take the omega-recurrence
+    // decision and return at once when the step is not cleaned; beta_j is
+    // folded from whichever kernel wrote the ||w||^2 partials last
     double *vj = V0 + (int64_t)j * s;
-    if ((rc = apply_H(c, vj, Wl, T, T2, st))) return bail(rc);
-    const int32_t rba = launch_multidot_partial(s, 1, vj, s, Wl, part, RED_NBLK, st);
+    // alpha_j = v_j . H v_j: partial sums from the last interface sweep when
+    // it can give them, else a separate reduction
+    int32_t rba = 0;
+    if ((rc = apply_H(c, vj, Wl, T, T2, st, vj, part, &rba))) return bail(rc);
+    if (rba == 0) rba = launch_multidot_partial(s, 1, vj, s, Wl, part, RED_NBLK, st);
     const int32_t rb = launch_lanczos_axpy(s, Wl, vj, j > 0 ? vj - s : nullptr, sc, part, rba, part2, st);
-    launch_pro(j, s, al, be, sc, part2, rb, om, ld_om, ctl, tn, rflag, st);
-    const int32_t rbh = launch_multidot_partial(s, j + 1, V0, s, Wl, part, RED_NBLK, st, ctl);
-    launch_gemv_sub_fold(s, j + 1, V0, s, part, rbh, Wl, nullptr, part2, st, ctl);
+    const int32_t rbh = launch_multidot_pro(s, j + 1, V0, s, Wl, part, RED_NBLK, j, al, be, sc, part2, rb, om, ld_om,
+                                            frc, tn, rflag, st);
+    launch_gemv_sub_fold(s, j + 1, V0, s, part, rbh, Wl, nullptr, part2, st, rflag + j);
     launch_lanczos_next(s, j, Wl, j + 1 < steps ? vj + s : nullptr, sc, al, be, part2, rb, nullptr, st);
   }
   for (int32_t j = 0; j < steps && !pro; ++j) {

@@ -146,9 +146,11 @@ void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nle
                   double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st);
 
 // Out-of-place sweep of a schedule with at most two levels, one launch.
+// dv (optional, nrhs == 1): per-block partial sums of dv . y to dpart
+// ((nrows + 255) / 256 blocks).
 template <typename TS, typename TC>
 void launch_sweep2(const SweepArrays<TS> &S, int32_t nrows, const double *x, int64_t ldx, double *y, int64_t ldy,
-                   int32_t nrhs, hipStream_t st);
+                   int32_t nrhs, hipStream_t st, const double *dv = nullptr, double *dpart = nullptr);
 
 // Rank-k block of eq. skt on w (s x nrhs, ld ldw), output to wout (ldo);
 // U column-major s x k:

@@ -81,10 +81,15 @@ void launch_gemv_add(int64_t n, int32_t J, const double *V, int64_t ldv, const d
 // the block count, equal to launch_gemv_sub_fold's)
 int32_t launch_lanczos_axpy(int64_t s, double *w, const double *v, const double *vprev, double *sc,
                             const double *apart, int32_t rb, double *sqpart, hipStream_t st);
-// partial reorthogonalisation control of Lanczos step j (omega recurrence);
-// ctl[0] = reorthogonalise this step, ctl[1] = force the next, ctl[2] = count
-void launch_pro(int32_t j, int64_t s, const double *alpha, const double *beta, const double *sc, const double *bpart,
-                int32_t rb, double *om, int32_t ld, int *ctl, double *tn, int *rflag, hipStream_t st);
+// Gram-Schmidt coefficients V^T w (as launch_multidot_partial) of Lanczos
+// step j behind the partial reorthogonalisation decision (omega recurrence
+// from alpha, beta, sc[0] = alpha_j and the rbp partials of ||w||^2 in
+// bpart; state om (3 rows of ld), frc / tn per step); rflag[j] receives the
+// decision and the launch does nothing else when it is 0
+int32_t launch_multidot_pro(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
+                            int32_t nblk, int32_t j, const double *alpha, const double *beta, const double *sc,
+                            const double *bpart, int32_t rbp, double *om, int32_t ld, int *frc, double *tn,
+                            int *rflag, hipStream_t st);
 // aval: device pointer to alpha_j (or nullptr: alpha_j is sc[0])
 void launch_lanczos_next(int64_t s, int32_t j, const double *w, double *vnext, double *sc, double *alpha,
                          double *beta, const double *bpart, int32_t rb, const double *aval, hipStream_t st);

@@ -574,27 +574,37 @@ __global__ void __launch_bounds__(256) k_sweep_lvl(SweepArrays<TS> S, int a, int
 // Whole sweep of a schedule with at most two levels, out of place
 // (y = T^{-1} x): level-0 rows have no entries (y = sc x); level-1 rows
 // depend on level-0 rows only, whose values sc_j x_j are folded into the
-// stored weights w2 = w * sc_j, so every row reads x alone.
+// stored weights w2 = w * sc_j, so every row reads x alone.  dv (optional,
+// one column): per-block sums of dv[row] y[row] over the block's rows go to
+// dpart[blockIdx.x] (a dot product with y, folded by the consumer).
 template <typename TS, typename TC>
 __global__ void __launch_bounds__(256) k_sweep2(SweepArrays<TS> S, int nrows, const double *x, int64_t ldx, double *y,
-                                                int64_t ldy) {
+                                                int64_t ldy, const double *dv, double *dpart) {
+  __shared__ double sh[4];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrows) return;
   const double *xc = x + (int64_t)blockIdx.y * ldx;
   double *yc = y + (int64_t)blockIdx.y * ldy;
-  const int row = S.rows[t];
-  const int e0 = S.rp[t], e1 = S.rp[t + 1];
-  TC acc = cvt<TC>(S.sc[t]) * (TC)xc[row];
-  for (int e = e0; e < e1; ++e) acc -= cvt<TC>(S.w2[e]) * (TC)xc[S.ci[e]];
-  yc[row] = (double)acc;
+  double d = 0.0;
+  if (t < nrows) {
+    const int row = S.rows[t];
+    const int e0 = S.rp[t], e1 = S.rp[t + 1];
+    TC acc = cvt<TC>(S.sc[t]) * (TC)xc[row];
+    for (int e = e0; e < e1; ++e) acc -= cvt<TC>(S.w2[e]) * (TC)xc[S.ci[e]];
+    yc[row] = (double)acc;
+    if (dv) d = (double)acc * dv[row];
+  }
+  if (dv) {
+    const double b = block_sum(d, sh);
+    if (threadIdx.x == 0) dpart[blockIdx.x] = b;
+  }
 }
 
 template <typename TS, typename TC>
 void launch_sweep2(const SweepArrays<TS> &S, int32_t nrows, const double *x, int64_t ldx, double *y, int64_t ldy,
-                   int32_t nrhs, hipStream_t st) {
+                   int32_t nrhs, hipStream_t st, const double *dv, double *dpart) {
   if (nrows == 0 || nrhs == 0) return;
   hipLaunchKernelGGL((k_sweep2<TS, TC>), dim3((nrows + 255) / 256, nrhs), dim3(256), 0, st, S, nrows, x, ldx, y,
-                     ldy);
+                     ldy, nrhs == 1 ? dv : nullptr, dpart);
 }
 
 template <typename TS, typename TC>
@@ -1588,71 +1598,114 @@ int32_t launch_lanczos_axpy(int64_t s, double *w, const double *v, const double 
 }
 
 // Partial reorthogonalisation control for Lanczos step j (Sec. 5.1, the
-// omega recurrence of Parlett and Simon).  One block; thread l < j
-// estimates om_{j+1,l} ~ v_{j+1}.v_l from rows om_j (row j % 3) and
-// om_{j-1} (row (j+2) % 3) of om (3 rows of ld):
+// omega recurrence of Parlett and Simon), run at the start of every block
+// of the step's (gated) Gram-Schmidt coefficient kernel.  Every block takes
+// the same decision from the same data; the writer block records it.
+// Thread l < j estimates om_{j+1,l} ~ v_{j+1}.v_l from rows om_j (row j % 3)
+// and om_{j-1} (row (j+2) % 3) of om (3 rows of ld):
 //   beta_j om_{j+1,l} = beta_l om_{j,l+1} + (alpha_l - alpha_j) om_{j,l}
 //                       + beta_{l-1} om_{j,l-1} - beta_{j-1} om_{j-1,l}
 // (unit diagonal), plus the rounding term e = eps sqrt(s) ||T_j|| with the
 // estimate's sign; om_{j+1,j} = e / beta_j.  beta_j is the norm before any
 // reorthogonalisation (folded from the rb partials bpart), alpha_j = sc[0],
 // alpha_l / beta_l (l < j) from the recorded coefficients, ||T_j|| the
-// running max of |alpha_i| + beta_i + beta_{i-1} kept in tn[0].
-// Decision (ctl[0], and rflag[j]): reorthogonalise when forced by the
-// previous step (ctl[1]) or when some |om_{j+1,l}| exceeds sqrt(eps); a
-// step triggered by the estimate forces the next one.  A reorthogonalised
-// row is reset to e / beta_j.
-__global__ void __launch_bounds__(1024) k_pro(int j, double sqrt_s, const double *alpha, const double *beta,
-                                              const double *sc, const double *bpart, int rb, double *om, int ld,
-                                              int *ctl, double *tn, int *rflag) {
+// running max of |alpha_i| + beta_i + beta_{i-1} (tn[j] before the step,
+// tn[j+1] after).  Reorthogonalise when forced (frc[j]) or when some
+// |om_{j+1,l}| exceeds sqrt(eps); a step triggered by the estimate forces
+// the next one (frc[j+1]).  The decision goes to rflag[j]; a cleaned row is
+// reset to e / beta_j.
+struct ProArgs {
+  int j;
+  double sqrt_s;
+  const double *alpha, *beta, *sc, *bpart;
+  int rb;
+  double *om;
+  int ld;
+  int *frc;
+  double *tn;
+  int *rflag;
+};
+
+__device__ int pro_step(const ProArgs &P, bool writer) {
   __shared__ double bsh, red[16];
   __shared__ int dosh;
-  fold_waves(bpart, rb, 1, [&](int, double x) { bsh = sqrt(x); });
+  fold_waves(P.bpart, P.rb, 1, [&](int, double x) { bsh = sqrt(x); });
   __syncthreads();
+  const int j = P.j;
   const double eps = 0x1p-52;
-  const double bj = bsh, aj = sc[0], bm = j > 0 ? beta[j - 1] : 0.0;
-  const double tnorm = fmax(tn[0], fabs(aj) + bj + bm);
-  const double e = eps * sqrt_s * tnorm;
-  const double *W0 = om + (int64_t)(j % 3) * ld;
-  const double *Wm = om + (int64_t)((j + 2) % 3) * ld;
-  double *Wp = om + (int64_t)((j + 1) % 3) * ld;
+  const double bj = bsh, aj = P.sc[0], bm = j > 0 ? P.beta[j - 1] : 0.0;
+  const double tnorm = fmax(P.tn[j], fabs(aj) + bj + bm);
+  const double e = eps * P.sqrt_s * tnorm;
+  const double *W0 = P.om + (int64_t)(j % 3) * P.ld;
+  const double *Wm = P.om + (int64_t)((j + 2) % 3) * P.ld;
+  double *Wp = P.om + (int64_t)((j + 1) % 3) * P.ld;
   const double psi = bj > 0.0 ? e / bj : 1.0;
-  const int l = threadIdx.x;
-  double x = 0.0;
-  if (l < j) {
+  auto est = [&](int l) {
+    if (l == j) return psi;
     const double up = l + 1 == j ? 1.0 : W0[l + 1];
     const double prev = l == j - 1 ? 1.0 : Wm[l];
-    double t = beta[l] * up + (alpha[l] - aj) * W0[l] - bm * prev;
-    if (l > 0) t += beta[l - 1] * W0[l - 1];
+    double t = P.beta[l] * up + (P.alpha[l] - aj) * W0[l] - bm * prev;
+    if (l > 0) t += P.beta[l - 1] * W0[l - 1];
     t += copysign(e, t);
-    x = bj > 0.0 ? t / bj : 1.0;
-  } else if (l == j) {
-    x = psi;
-  }
-  double m = wave_allmax(fabs(x));
+    return bj > 0.0 ? t / bj : 1.0;
+  };
+  double m = 0.0;
+  for (int l = threadIdx.x; l <= j; l += blockDim.x) m = fmax(m, fabs(est(l)));
+  m = wave_allmax(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     double mx = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) mx = fmax(mx, red[i]);
-    const int force = ctl[1];
+    const int force = P.frc[j];
     const int big = mx > 0x1p-26;
-    const int d = force || big;
-    ctl[1] = force ? 0 : big;
-    ctl[0] = d;
-    ctl[2] += d;
-    rflag[j] = d;
-    tn[0] = tnorm;
-    dosh = d;
+    dosh = force || big;
+    if (writer) {
+      P.frc[j + 1] = force ? 0 : big;
+      P.tn[j + 1] = tnorm;
+      P.rflag[j] = dosh;
+    }
   }
   __syncthreads();
-  if (l <= j) Wp[l] = dosh ? psi : x;
+  const int d = dosh;
+  if (writer)
+    for (int l = threadIdx.x; l <= j; l += blockDim.x) Wp[l] = d ? psi : est(l);
+  return d;
 }
 
-void launch_pro(int32_t j, int64_t s, const double *alpha, const double *beta, const double *sc, const double *bpart,
-                int32_t rb, double *om, int32_t ld, int *ctl, double *tn, int *rflag, hipStream_t st) {
-  hipLaunchKernelGGL(k_pro, dim3(1), dim3(1024), 0, st, j, std::sqrt((double)s), alpha, beta, sc, bpart, rb, om, ld,
-                     ctl, tn, rflag);
+// k_multidot preceded by the partial reorthogonalisation decision; the
+// whole grid returns when the step is not cleaned
+__global__ void __launch_bounds__(256) k_multidot_pro(int64_t s, int J, const double *V, int64_t ldv,
+                                                      const double *w, double *part, ProArgs P) {
+  if (!pro_step(P, blockIdx.x == 0 && blockIdx.y == 0)) return;
+  __shared__ double sh[4];
+  const int rb = blockIdx.x, nb = gridDim.x, jj = blockIdx.y;
+  const int64_t chunk = (s + nb - 1) / nb;
+  const int64_t i0 = (int64_t)rb * chunk, i1 = min(s, i0 + chunk);
+  const double *vj = V + (int64_t)jj * ldv;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int64_t step = blockDim.x;
+  int64_t i = i0 + threadIdx.x;
+  for (; i + 3 * step < i1; i += 4 * step) {
+    a0 += vj[i] * w[i];
+    a1 += vj[i + step] * w[i + step];
+    a2 += vj[i + 2 * step] * w[i + 2 * step];
+    a3 += vj[i + 3 * step] * w[i + 3 * step];
+  }
+  for (; i < i1; i += step) a0 += vj[i] * w[i];
+  const double t = block_sum((a0 + a1) + (a2 + a3), sh);
+  if (threadIdx.x == 0) part[(int64_t)rb * J + jj] = t;
+}
+
+int32_t launch_multidot_pro(int64_t s, int32_t J, const double *V, int64_t ldv, const double *w, double *part,
+                            int32_t nblk, int32_t j, const double *alpha, const double *beta, const double *sc,
+                            const double *bpart, int32_t rbp, double *om, int32_t ld, int *frc, double *tn,
+                            int *rflag, hipStream_t st) {
+  const int64_t rb =
+      std::max<int64_t>(1, std::min<int64_t>({(int64_t)nblk, (1024 + J - 1) / J, (s + 1023) / 1024}));
+  ProArgs P{j, std::sqrt((double)s), alpha, beta, sc, bpart, rbp, om, ld, frc, tn, rflag};
+  hipLaunchKernelGGL(k_multidot_pro, dim3((unsigned)rb, J), dim3(256), 0, st, s, J, V, ldv, w, part, P);
+  return (int32_t)rb;
 }
 
 // End of Lanczos step j: beta_j = ||w|| folded from the rb multidot
@@ -2351,11 +2404,11 @@ template void launch_bsolve<float, float>(const BlockArrays<float> &, int32_t, c
 template void launch_bsolve<float, double>(const BlockArrays<float> &, int32_t, const BArgs &, int32_t, size_t,
                                            hipStream_t);
 template void launch_sweep2<double, double>(const SweepArrays<double> &, int32_t, const double *, int64_t, double *,
-                                            int64_t, int32_t, hipStream_t);
+                                            int64_t, int32_t, hipStream_t, const double *, double *);
 template void launch_sweep2<float, float>(const SweepArrays<float> &, int32_t, const double *, int64_t, double *,
-                                          int64_t, int32_t, hipStream_t);
+                                          int64_t, int32_t, hipStream_t, const double *, double *);
 template void launch_sweep2<float, double>(const SweepArrays<float> &, int32_t, const double *, int64_t, double *,
-                                           int64_t, int32_t, hipStream_t);
+                                           int64_t, int32_t, hipStream_t, const double *, double *);
 template void launch_sweep<double, double>(const SweepArrays<double> &, const int32_t *, int32_t, int32_t, double *,
                                            int64_t, int32_t, bool, hipStream_t);
 template void launch_sweep<float, float>(const SweepArrays<float> &, const int32_t *, int32_t, int32_t, double *,
