@@ -51,6 +51,8 @@ def _lib():
         lib.orc_ic0.restype = ctypes.c_int
         lib.orc_ildlt0.argtypes = [I64, P, P, P, P]
         lib.orc_ildlt0.restype = ctypes.c_int
+        lib.orc_ict.argtypes = [I64, P, P, P, ctypes.c_double, ctypes.c_int, I64, P, P, P, P]
+        lib.orc_ict.restype = ctypes.c_int
         lib.orc_lower_solve.argtypes = [I64, P, P, P, P, ctypes.c_int]
         lib.orc_upper_solve.argtypes = [I64, P, P, P, P, ctypes.c_int]
         lib.orc_diag_solve.argtypes = [I64, P, P, P]
@@ -178,7 +180,7 @@ class Factor:
         if self.kind == "chol":
             return self._band_solve(x, "N")
         _lib().orc_lower_solve(self.n, _p(self.rp), _p(self.ci), _p(self.v), _p(x),
-                               1 if self.kind == "ildlt0" else 0)
+                               1 if self.kind in ("ildlt0", "ildlt") else 0)
         return x
 
     def upper(self, x: np.ndarray) -> np.ndarray:
@@ -187,7 +189,7 @@ class Factor:
         if self.kind == "chol":
             return self._band_solve(x, "T")
         _lib().orc_upper_solve(self.n, _p(self.rp), _p(self.ci), _p(self.v), _p(x),
-                               1 if self.kind == "ildlt0" else 0)
+                               1 if self.kind in ("ildlt0", "ildlt") else 0)
         return x
 
     def dense_lower(self, a: int, b: int) -> np.ndarray:
@@ -207,7 +209,7 @@ class Factor:
     def solve(self, x: np.ndarray) -> np.ndarray:
         """x <- (L L^T)^{-1} x, or (L D L^T)^{-1} x."""
         y = self.lower(x)
-        if self.kind == "ildlt0":
+        if self.kind in ("ildlt0", "ildlt"):
             _lib().orc_diag_solve(self.n, _p(self.rp), _p(self.v), _p(y))
         return self.upper(y)
 
@@ -225,12 +227,16 @@ def _tril_csr(M: sp.csr_matrix):
     return rp, ci, v
 
 
-def factorize(M: sp.csr_matrix, kind: str, block_offsets=None, what: str = "B") -> Factor:
+def factorize(M: sp.csr_matrix, kind: str, block_offsets=None, what: str = "B", droptol: float = 0.0) -> Factor:
     """Factor a (block diagonal) symmetric matrix.
 
     'ic0'    incomplete Cholesky with zero fill: the unique lower L on the
              pattern of tril(M) with (L L^T)_ij = m_ij on that pattern.
     'ildlt0' incomplete L D L^T with zero fill, unit L.
+    'ict' / 'ildlt'  threshold dropping (the local solvers of Sec. 6):
+             left-looking by columns, an entry of column j is kept when its
+             updated value is at least droptol times the 1-norm of column j
+             of tril(M) (READING: the paper gives no dropping rule).
     'chol'   exact Cholesky of every diagonal block (banded LAPACK)."""
     n = M.shape[0]
     if kind == "chol":
@@ -252,6 +258,22 @@ def factorize(M: sp.csr_matrix, kind: str, block_offsets=None, what: str = "B") 
                                       "Cholesky failed")
         return Factor("chol", n, blocks=blocks)
     rp, ci, v = _tril_csr(M.tocsr())
+    if kind in ("ict", "ildlt"):
+        cap = 4 * len(ci) + n
+        while True:
+            orp = np.zeros(n + 1, dtype=np.int64)
+            oci = np.zeros(cap, dtype=np.int32)
+            ov = np.zeros(cap)
+            need = ctypes.c_int64(0)
+            rc = _lib().orc_ict(n, _p(rp), _p(ci), _p(v), float(droptol), 1 if kind == "ildlt" else 0, cap, _p(orp),
+                                _p(oci), _p(ov), ctypes.byref(need))
+            if rc != -(n + 1):
+                break
+            cap = int(need.value)
+        if rc != 0:
+            raise OracleError("C_NOT_SPD" if what == "C" else "BREAKDOWN", f"{kind} pivot failure in column {-rc - 1}")
+        nz = int(orp[-1])
+        return Factor(kind, n, orp, oci[:nz].copy(), ov[:nz].copy())
     if kind == "ic0":
         rc = _lib().orc_ic0(n, _p(rp), _p(ci), _p(v))
     elif kind == "ildlt0":
@@ -366,7 +388,8 @@ class SLR:
 def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "ic0",
           c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
           fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
-          lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "partial") -> SLR:
+          lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "partial",
+          droptol: float = 1e-3) -> SLR:
     """Build the SLR preconditioner (Sec. 4 and Sec. 5).
 
     A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
@@ -379,7 +402,8 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     cond_K > 1: k becomes the smallest rank (at most the given k) with
     lambda_{k+1} <= 1 - 1/K among the Ritz values (eq. condk).  reorth:
     Lanczos with full ("full") or partial ("partial", Sec. 5.1)
-    reorthogonalisation."""
+    reorthogonalisation.  b_fact / c_fact "ict" (and "ildlt" for B): threshold
+    factors with drop tolerance droptol (factorize)."""
     if theta_mode == "eps" and not eps > 0.0:
         raise OracleError("ARG", "theta_mode eps needs eps > 0")
     if isinstance(A, tuple):
@@ -395,9 +419,9 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     B = Ap[:m, :m].tocsr()
     E = Ap[:m, m:].tocsr()
     C = Ap[m:, m:].tocsr()
-    FB = factorize(B, b_fact, off_b, "B")
+    FB = factorize(B, b_fact, off_b, "B", droptol)
     # exact C solve: one dense block; otherwise IC(0)
-    FC = factorize(C, c_fact, [0, s], "C")
+    FC = factorize(C, c_fact, [0, s], "C", droptol)
     FB.round_to(fact_prec)
     FC.round_to(fact_prec)
     P = SLR(A, perm, off_b, off_y, m, s, Ap, E, C, FB, FC, colors=colors)

@@ -467,6 +467,78 @@ def test_partial_reorthogonalisation_spectrum_exact_problem():
     assert np.allclose(spec, np.sort(np.concatenate([np.ones(P.m + k), sig])), atol=1e-7)
 
 
+def _dense_threshold_factor(A, tau, ldl):
+    """Dense left-looking factorisation with the threshold rule written out
+    on full matrices (independent of the oracle's sparse loops)."""
+    n = A.shape[0]
+    L = np.zeros((n, n))
+    d = np.zeros(n)
+    for j in range(n):
+        w = A[j:, j].copy()
+        nrm = np.abs(A[j:, j]).sum()
+        for k in range(j):
+            if L[j, k] != 0.0:
+                f = L[j, k] * d[k] if ldl else L[j, k]
+                w -= L[j:, k] * f
+        d[j] = w[0] if ldl else np.sqrt(w[0])
+        keep = np.abs(w[1:]) >= tau * nrm
+        L[j + 1:, j] = np.where(keep, w[1:] / d[j], 0.0)
+    return L, d
+
+
+@pytest.mark.parametrize("kind", ["ict", "ildlt"])
+def test_threshold_factors(kind):
+    """ICT / ILDLT (Sec. 6 local solvers): no dropping is the exact
+    factorisation (L L^T = M, L D L^T = M); an infinite tolerance keeps the
+    diagonal only; the kept pattern and values follow the dense form of the
+    rule (1-norm of the column of tril(M), updated values compared); with
+    no fill possible (tridiagonal) they equal IC(0) / ILDL(0)."""
+    import scipy.sparse as sp
+    ldl = kind == "ildlt"
+    rng = np.random.default_rng(11)
+    N = 7
+    csr = si.diffusion_2d(N, np.exp(rng.standard_normal((N + 2, N + 2))))
+    M = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(csr[3], csr[3]))
+    Md = M.toarray()
+
+    def dense(F):
+        Lf = sp.csr_matrix((F.v, F.ci, F.rp), shape=M.shape).toarray()
+        dd = np.diag(Lf).copy()
+        return Lf - np.diag(dd), dd
+
+    Ls, dd = dense(O.factorize(M, kind, droptol=0.0))
+    if ldl:
+        Lu = Ls + np.eye(len(dd))
+        assert np.abs(Lu @ np.diag(dd) @ Lu.T - Md).max() <= 1e-13 * np.abs(Md).max()
+    else:
+        Lf = Ls + np.diag(dd)
+        assert np.allclose(Lf, np.linalg.cholesky(Md), rtol=1e-12, atol=1e-13)
+    Ls, dd = dense(O.factorize(M, kind, droptol=1e300))
+    assert not Ls.any()
+    assert np.allclose(dd, np.diag(Md) if ldl else np.sqrt(np.diag(Md)), rtol=0, atol=0)
+    for tau in (0.02, 0.1):
+        Ls, dd = dense(O.factorize(M, kind, droptol=tau))
+        Lr, dr = _dense_threshold_factor(Md, tau, ldl)
+        assert np.array_equal(Ls != 0.0, np.tril(Lr, -1) != 0.0)
+        assert np.allclose(Ls, np.tril(Lr, -1), rtol=1e-13, atol=1e-15)
+        assert np.allclose(dd, dr, rtol=1e-13)
+    T = si.laplacian_2d(1, Ny=30)
+    T = sp.csr_matrix((T[2], T[1], T[0]), shape=(T[3], T[3]))
+    Ft = O.factorize(T, kind, droptol=1e-12)
+    F0 = O.factorize(T, "ildlt0" if ldl else "ic0")
+    assert np.array_equal(Ft.ci, F0.ci) and np.allclose(Ft.v, F0.v, rtol=1e-15, atol=0)
+
+
+def test_threshold_factors_without_dropping_give_exact_solves():
+    """ICT for B and C with no dropping makes the SLR apply that of exact
+    solves (eq. M with exact B and C)."""
+    csr, part, p = _tiny(10)
+    Pe = O.setup(csr, part, p, 5, 0, b_fact="chol", c_fact="chol", v0=si.lanczos_start(csr[3], 3))
+    Pt = O.setup(csr, part, p, 0, b_fact="ict", c_fact="ict", droptol=0.0, lowrank=(Pe.U, Pe.lam, Pe.theta))
+    r = np.random.default_rng(2).standard_normal(csr[3])
+    assert np.allclose(Pt.apply(r), Pe.apply(r), rtol=1e-10, atol=1e-12)
+
+
 def test_P3prime_inertia_counts_negative_eigenvalues():
     """Indefinite A with SPD B (exact solves): by Sylvester's law on
     eq. Schur, #{lambda(H) > 1} = #negative eigenvalues of A."""
