@@ -66,7 +66,11 @@ enum {
  * elsewhere theta = 0, i.e. rho = 1 and the diagonal scales become
  * eps/(1 - lambda_i) - 1. */
 enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1, SLR_THETA_EPS = 2, SLR_THETA_LAMBDA_S = 3 };
-enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2 };
+/* Local solvers (Sec. 5.2, Sec. 6): exact Cholesky, zero-fill IC(0) /
+ * ILDL^T(0), or the threshold forms ICT / ILDLT (left-looking by columns; an
+ * entry of column j is kept when its updated value is at least droptol times
+ * the 1-norm of column j of the lower triangle). */
+enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2, SLR_FACT_ICT = 3, SLR_FACT_ILDLT = 4 };
 enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1 };
 enum { SLR_FP64 = 0, SLR_FP32 = 1, SLR_BF16 = 2 };
 enum { SLR_PCG = 0, SLR_FCG = 1, SLR_FGMRES = 2 };
@@ -91,8 +95,9 @@ typedef struct {
   int32_t theta_mode;     /* SLR_THETA_LAMBDA_K1 (Sec. 4) | SLR_THETA_ZERO |
                              SLR_THETA_EPS (eq. Lambda-2, parameter eps) |
                              SLR_THETA_LAMBDA_S (Sec. 4)                      */
-  int32_t b_fact;         /* local solver of the B_i (Sec. 5.2): CHOL|IC0|ILDLT0 */
-  int32_t c_fact;         /* factor of C = L L^T: CHOL | IC0                  */
+  int32_t b_fact;         /* local solver of the B_i (Sec. 5.2):
+                             CHOL | IC0 | ILDLT0 | ICT | ILDLT               */
+  int32_t c_fact;         /* factor of C = L L^T: CHOL | IC0 | ICT            */
   int32_t c_order;        /* ordering of the interface for C's factor         */
   int32_t fact_prec;      /* SLR_FP64 | SLR_FP32: storage and arithmetic of the
                              B_i / C solves inside the apply                   */
@@ -126,6 +131,9 @@ typedef struct {
      stored coefficient of device memory).  Needs incomplete factors (B:
      IC0 | ILDLT0, C: IC0) and nnz < 2^31; SLR_ERR_ARG otherwise. */
   int32_t refactor;
+  /* drop tolerance of the ICT / ILDLT factors (>= 0; 0 keeps every entry,
+     i.e. the exact factorisation).  Default 1e-3. */
+  double droptol;
 } slr_opts;
 
 typedef struct {

@@ -37,13 +37,14 @@ SLR_OK, SLR_ERR_ARG, SLR_ERR_NOT_SYMMETRIC, SLR_ERR_PARTITION = 0, -1, -2, -3
 SLR_ERR_BREAKDOWN, SLR_ERR_C_NOT_SPD, SLR_ERR_RITZ_SINGULAR, SLR_ERR_LANCZOS_SHORT = -4, -5, -6, -7
 SLR_ERR_NOCONV, SLR_ERR_OOM, SLR_ERR_HIP, SLR_ERR_ADMIT = -8, -9, -10, -11
 SLR_THETA_LAMBDA_K1, SLR_THETA_ZERO, SLR_THETA_EPS, SLR_THETA_LAMBDA_S = 0, 1, 2, 3
-SLR_FACT_CHOL, SLR_FACT_IC0, SLR_FACT_ILDLT0 = 0, 1, 2
+SLR_FACT_CHOL, SLR_FACT_IC0, SLR_FACT_ILDLT0, SLR_FACT_ICT, SLR_FACT_ILDLT = 0, 1, 2, 3, 4
 SLR_CORDER_SUBDOMAIN, SLR_CORDER_MULTICOLOR = 0, 1
 SLR_FP64, SLR_FP32, SLR_BF16 = 0, 1, 2
 SLR_PCG, SLR_FCG, SLR_FGMRES = 0, 1, 2
 SLR_REORTH_FULL, SLR_REORTH_PARTIAL = 0, 1
 
-_FACT = {"chol": SLR_FACT_CHOL, "ic0": SLR_FACT_IC0, "ildlt0": SLR_FACT_ILDLT0}
+_FACT = {"chol": SLR_FACT_CHOL, "ic0": SLR_FACT_IC0, "ildlt0": SLR_FACT_ILDLT0, "ict": SLR_FACT_ICT,
+         "ildlt": SLR_FACT_ILDLT}
 _PREC = {"fp64": SLR_FP64, "fp32": SLR_FP32, "bf16": SLR_BF16}
 _CORD = {"subdomain": SLR_CORDER_SUBDOMAIN, "multicolor": SLR_CORDER_MULTICOLOR}
 _THETA = {"lambda_k1": SLR_THETA_LAMBDA_K1, "zero": SLR_THETA_ZERO, "eps": SLR_THETA_EPS, "lambda_s": SLR_THETA_LAMBDA_S}
@@ -63,7 +64,7 @@ class slr_opts(ctypes.Structure):
                 ("c_fact", _I32), ("c_order", _I32), ("fact_prec", _I32), ("uk_prec", _I32),
                 ("seed", _U64), ("lanczos_v0", _P), ("k_in", _I32), ("U_in", _P),
                 ("lambda_in", _P), ("theta_in", _D), ("eps", _D), ("cond_K", _D), ("reorth", _I32),
-                ("refactor", _I32)]
+                ("refactor", _I32), ("droptol", _D)]
 
 
 class slr_solve_opts(ctypes.Structure):
@@ -170,7 +171,7 @@ def _csr_arrays(A):
 
 def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fact="ic0",
                c_order="subdomain", fact_prec="fp64", uk_prec="fp64", seed=7, eps=0.0, cond_K=0.0,
-               reorth=None, refactor=False):
+               reorth=None, refactor=False, droptol=1e-3):
     o = slr_opts()
     slr_default_opts(ctypes.byref(o))
     o.k = k
@@ -184,6 +185,7 @@ def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fa
     if reorth is not None:
         o.reorth = _REORTH[reorth]
     o.refactor = 1 if refactor else 0
+    o.droptol = float(droptol)
     return o
 
 
@@ -207,12 +209,12 @@ class SLR:
                  theta_mode: str = "lambda_k1", b_fact: str = "ic0", c_fact: str = "ic0",
                  c_order: str = "subdomain", fact_prec: str = "fp64", uk_prec: str = "fp64",
                  v0=None, seed: int = 7, lowrank=None, eps: float = 0.0, cond_K: float = 0.0,
-                 reorth: str | None = None, refactor: bool = False, stream=None):
+                 reorth: str | None = None, refactor: bool = False, droptol: float = 1e-3, stream=None):
         indptr, indices, data, n = _csr_arrays(A)
         self.n = n
         part = np.ascontiguousarray(part, dtype=np.int32)
         o = _make_opts(k, lanczos_steps, theta_mode, b_fact, c_fact, c_order, fact_prec, uk_prec, seed, eps, cond_K,
-                       reorth, refactor)
+                       reorth, refactor, droptol)
         keep = []
         if v0 is not None:
             v0 = np.ascontiguousarray(v0, dtype=np.float64)

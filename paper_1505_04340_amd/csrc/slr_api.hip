@@ -965,6 +965,7 @@ void slr_default_opts(slr_opts *o) {
   o->cond_K = 0.0;
   o->reorth = SLR_REORTH_PARTIAL;
   o->refactor = 0;
+  o->droptol = 1e-3;
 }
 
 void slr_default_solve_opts(slr_solve_opts *o) {
@@ -1014,8 +1015,10 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   if (o->reorth != SLR_REORTH_FULL && o->reorth != SLR_REORTH_PARTIAL) return fail(SLR_ERR_ARG, "reorth");
   if (o->fact_prec != SLR_FP64 && o->fact_prec != SLR_FP32) return fail(SLR_ERR_ARG, "fact_prec");
   if (o->uk_prec < SLR_FP64 || o->uk_prec > SLR_BF16) return fail(SLR_ERR_ARG, "uk_prec");
-  if (o->b_fact < SLR_FACT_CHOL || o->b_fact > SLR_FACT_ILDLT0) return fail(SLR_ERR_ARG, "b_fact");
-  if (o->c_fact != SLR_FACT_CHOL && o->c_fact != SLR_FACT_IC0) return fail(SLR_ERR_ARG, "c_fact");
+  if (o->b_fact < SLR_FACT_CHOL || o->b_fact > SLR_FACT_ILDLT) return fail(SLR_ERR_ARG, "b_fact");
+  if (o->c_fact != SLR_FACT_CHOL && o->c_fact != SLR_FACT_IC0 && o->c_fact != SLR_FACT_ICT)
+    return fail(SLR_ERR_ARG, "c_fact");
+  if (!(o->droptol >= 0.0)) return fail(SLR_ERR_ARG, "droptol must be >= 0");
   if (A->rowptr[A->n] != A->nnz) return fail(SLR_ERR_ARG, "rowptr[n] != nnz");
   hipStream_t st = S(hip_stream);
   const double t0 = now_s();
@@ -1025,9 +1028,10 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   prm.c_fact = o->c_fact;
   prm.c_order = o->c_order;
   prm.fact_prec = o->fact_prec;
+  prm.droptol = o->droptol;
   prm.plan = o->refactor != 0;
-  if (o->refactor && (o->b_fact == SLR_FACT_CHOL || o->c_fact == SLR_FACT_CHOL))
-    return fail(SLR_ERR_ARG, "refactor needs incomplete factors (IC0 / ILDLT0 for B, IC0 for C)");
+  if (o->refactor && !((o->b_fact == SLR_FACT_IC0 || o->b_fact == SLR_FACT_ILDLT0) && o->c_fact == SLR_FACT_IC0))
+    return fail(SLR_ERR_ARG, "refactor needs zero-fill factors (IC0 / ILDLT0 for B, IC0 for C)");
   if (o->refactor && A->nnz > INT32_MAX) return fail(SLR_ERR_ARG, "refactor takes at most 2^31-1 entries");
   std::string err;
   int rc = host_setup(A->n, A->rowptr, A->col, A->val, part, p, prm, H, err);
@@ -1290,6 +1294,7 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
   prm.c_fact = o->c_fact;
   prm.c_order = o->c_order;
   prm.fact_prec = o->fact_prec;
+  prm.droptol = o->droptol;
   std::string err;
   int rc = host_setup(A->n, A->rowptr, A->col, A->val, part, p, prm, H, err);
   if (rc) return fail(rc, err);

@@ -225,10 +225,97 @@ int envelope_cholesky(int32_t n, const std::vector<int32_t> &rp, const std::vect
   return 0;
 }
 
+// Threshold factorisation (ICT, or ILDLT when ldl), left-looking by
+// columns.  Column j starts from column j of tril(M) (w_i = m_ij, i >= j;
+// nrm = sum |m_ij|); each earlier column k with a kept l_jk (ascending k)
+// subtracts l_ik f from w_i for its kept rows i >= j, f = l_jk (IC) or
+// l_jk d_k (LDL); then l_jj = sqrt(w_j) (or d_j = w_j) and, for i > j in
+// ascending order, l_ij = w_i / l_jj (or / d_j) is kept when |w_i| >= tau
+// nrm.  The result is returned as row CSR with the diagonal last.
+int threshold_factor(bool ldl, int32_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                     const std::vector<double> &v, double tau, LowerFactor &F) {
+  // columns of tril(M)
+  std::vector<int32_t> cptr(n + 1, 0), crow(ci.size());
+  std::vector<double> cval(ci.size());
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) cptr[ci[e] + 1]++;
+  for (int32_t j = 0; j < n; ++j) cptr[j + 1] += cptr[j];
+  {
+    std::vector<int32_t> pos(cptr.begin(), cptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        crow[pos[ci[e]]] = i;
+        cval[pos[ci[e]]++] = v[e];
+      }
+  }
+  // kept entries by column (rows ascending) and by row (columns ascending)
+  std::vector<std::vector<std::pair<int32_t, double>>> col(n), row(n);
+  std::vector<double> dg(n, 0.0), w(n, 0.0);
+  std::vector<char> on(n, 0);
+  std::vector<int32_t> pat;
+  for (int32_t j = 0; j < n; ++j) {
+    pat.clear();
+    double nrm = 0.0;
+    for (int32_t e = cptr[j]; e < cptr[j + 1]; ++e) {
+      const int32_t i = crow[e];
+      w[i] = cval[e];
+      on[i] = 1;
+      pat.push_back(i);
+      nrm += std::fabs(cval[e]);
+    }
+    for (const auto &rk : row[j]) {
+      const int32_t k = rk.first;
+      const double f = ldl ? rk.second * dg[k] : rk.second;
+      for (const auto &ck : col[k]) {
+        const int32_t i = ck.first;
+        if (i < j) continue;
+        if (!on[i]) {
+          on[i] = 1;
+          w[i] = 0.0;
+          pat.push_back(i);
+        }
+        w[i] -= ck.second * f;
+      }
+    }
+    if (!on[j]) return -1 - j;
+    const double piv = w[j];
+    if (ldl ? !(std::fabs(piv) >= 1e-300) : !(piv > 0.0)) return -1 - j;
+    const double dj = ldl ? piv : std::sqrt(piv);
+    dg[j] = dj;
+    std::sort(pat.begin(), pat.end());
+    for (int32_t i : pat) {
+      if (i > j && std::fabs(w[i]) >= tau * nrm) {
+        const double l = w[i] / dj;
+        col[j].emplace_back(i, l);
+        row[i].emplace_back(j, l);
+      }
+      on[i] = 0;
+      w[i] = 0.0;
+    }
+  }
+  F.n = n;
+  F.kind = ldl ? 2 : 0;
+  F.rp.assign(n + 1, 0);
+  F.ci.clear();
+  F.v.clear();
+  for (int32_t i = 0; i < n; ++i) {
+    for (const auto &rk : row[i]) {
+      F.ci.push_back(rk.first);
+      F.v.push_back(rk.second);
+    }
+    F.ci.push_back(i);
+    F.v.push_back(dg[i]);
+    F.rp[i + 1] = (int32_t)F.ci.size();
+  }
+  return 0;
+}
+
 // factor a block given as the lower triangle (diag last) in local indices
 int factor_block(int kind, int32_t n, std::vector<int32_t> &rp, std::vector<int32_t> &ci,
-                 std::vector<double> &v, LowerFactor &F) {
+                 std::vector<double> &v, LowerFactor &F, double droptol) {
   if (kind == SLR_FACT_CHOL) return envelope_cholesky(n, rp, ci, v, F);
+  if (kind == SLR_FACT_ICT || kind == SLR_FACT_ILDLT) return threshold_factor(kind == SLR_FACT_ILDLT, n, rp, ci, v,
+                                                                              droptol, F);
   F.n = n;
   F.kind = kind == SLR_FACT_ILDLT0 ? 2 : 0;
   F.rp = rp;
@@ -346,7 +433,8 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     }
   }
   const bool fp32 = prm.fact_prec == SLR_FP32;
-  H.have_plan = prm.plan && prm.b_fact != SLR_FACT_CHOL && prm.c_fact != SLR_FACT_CHOL;
+  H.have_plan = prm.plan && (prm.b_fact == SLR_FACT_IC0 || prm.b_fact == SLR_FACT_ILDLT0) &&
+                prm.c_fact == SLR_FACT_IC0;
   if (H.have_plan) {
     H.fb = RefactorPlan();
     H.fb.kind = prm.b_fact == SLR_FACT_ILDLT0 ? 2 : 0;
@@ -391,7 +479,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     b.e_ptr.push_back((int32_t)b.e_q.size());
     H.nnz_E += (int64_t)b.e_q.size();
     LowerFactor F;
-    int rc = factor_block(prm.b_fact, b.m, rp, ci, v, F);
+    int rc = factor_block(prm.b_fact, b.m, rp, ci, v, F, prm.droptol);
     if (rc != 0) {
       err = "factorisation of B_" + std::to_string(q) + " failed at local row " +
             std::to_string(-1 - rc);
@@ -466,8 +554,8 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
       rp[t + 1] = (int32_t)ci.size();
     }
     LowerFactor F;
-    int kind = prm.c_fact == SLR_FACT_CHOL ? SLR_FACT_CHOL : SLR_FACT_IC0;
-    int rc = factor_block(kind, (int32_t)s, rp, ci, v, F);
+    int kind = prm.c_fact == SLR_FACT_CHOL || prm.c_fact == SLR_FACT_ICT ? prm.c_fact : SLR_FACT_IC0;
+    int rc = factor_block(kind, (int32_t)s, rp, ci, v, F, prm.droptol);
     if (rc != 0) {
       err = "factorisation of C failed at interface row " + std::to_string(-1 - rc);
       return SLR_ERR_C_NOT_SPD;

@@ -33,10 +33,11 @@ def test_binding_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "slr.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
         "sizeof(slr_csr), sizeof(slr_opts), sizeof(slr_solve_opts), sizeof(slr_solve_info),"
         "sizeof(slr_info), offsetof(slr_opts, lanczos_v0), offsetof(slr_opts, theta_in),"
         "offsetof(slr_opts, eps), offsetof(slr_opts, cond_K), offsetof(slr_opts, reorth), offsetof(slr_opts, refactor),"
+        "offsetof(slr_opts, droptol),"
         "offsetof(slr_info, theta), offsetof(slr_info, lanczos_reorth));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -44,7 +45,7 @@ def test_binding_struct_layout_matches_header(tmp_path):
     want = [ctypes.sizeof(P.slr_csr), ctypes.sizeof(P.slr_opts), ctypes.sizeof(P.slr_solve_opts),
             ctypes.sizeof(P.slr_solve_info), ctypes.sizeof(P.slr_info), P.slr_opts.lanczos_v0.offset,
             P.slr_opts.theta_in.offset, P.slr_opts.eps.offset, P.slr_opts.cond_K.offset,
-            P.slr_opts.reorth.offset, P.slr_opts.refactor.offset, P.slr_info.theta.offset,
+            P.slr_opts.reorth.offset, P.slr_opts.refactor.offset, P.slr_opts.droptol.offset, P.slr_info.theta.offset,
             P.slr_info.lanczos_reorth.offset]
     assert got == want
 

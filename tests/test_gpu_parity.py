@@ -393,6 +393,41 @@ def test_lanczos_reorth_modes(reorth):
     assert abs(info[0]["iters"] - ro.iters) <= 1
 
 
+@pytest.mark.parametrize("bf,cf,prec", [("ict", "ict", "fp64"), ("ildlt", "ict", "fp64"), ("ict", "ic0", "fp32")])
+def test_threshold_factor_apply(bf, cf, prec):
+    """ICT / ILDLT local solvers (wider rows: the any-width packed sweeps,
+    and C's deeper level schedule): apply parity with the oracle's own
+    threshold factors and the same low-rank part."""
+    pr = si.make_config("lap3d_64", N=16, boxes=2)
+    Po = _oracle(pr, k=8, lanczos_steps=40, b_fact=bf, c_fact=cf, droptol=1e-3, fact_prec=prec,
+                 c_order="multicolor")
+    G = _slr(pr, k=8, lanczos_steps=40, b_fact=bf, c_fact=cf, droptol=1e-3, fact_prec=prec, uk_prec=prec,
+             c_order="multicolor", lowrank=(Po.U, Po.lam, Po.theta))
+    assert G.info["nnz_LB"] == Po.FB.v.size and G.info["nnz_LC"] == Po.FC.v.size
+    rnd = O.round_fp32 if prec == "fp32" else (lambda u: u)
+    Pi = _oracle(pr, b_fact=bf, c_fact=cf, droptol=1e-3, fact_prec=prec, c_order="multicolor",
+                 lowrank=(rnd(Po.U), Po.lam, Po.theta))
+    r = _rand(pr.n, 2, 13)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_fgmres_indefinite_threshold_factors():
+    """With ILDLT for the B_i and ICT for C (drop tolerance 1e-4) the
+    shifted problem with 20 negative eigenvalues converges; the zero-fill
+    factors stagnate on it."""
+    pr = si.make_config("shifted3d_128", N=32, boxes=4, neg=20)
+    kw = dict(k=32, lanczos_steps=160, b_fact="ildlt", c_fact="ict", droptol=1e-4)
+    Po = _oracle(pr, **kw)
+    G = _slr(pr, **kw)
+    ex, gv, gb = _lanczos_parity(G, Po, 32)
+    assert int(np.sum(gv > 1.0)) >= 10
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "fgmres")
+    x, info = G.solve(_dev(b[:, 0]), "fgmres")
+    assert ro.converged and info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    assert abs(info[0]["iters"] - ro.iters) <= 2
+
+
 def test_fgmres_indefinite():
     pr = si.make_config("shifted3d_128", N=24, boxes=4, neg=4)
     Po = _oracle(pr, k=16, lanczos_steps=80)

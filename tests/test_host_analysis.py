@@ -14,6 +14,10 @@ CASES = [
     ("lap3d_64", {"N": 18, "boxes": 4}, "ic0", "ic0", "multicolor"),   # ragged boxes 4/5 wide
     ("shifted3d_128", {"N": 16, "boxes": 2, "neg": 3}, "ildlt0", "ic0", "subdomain"),
     ("diffusion2d_1024", {"N": 96, "boxes": 4}, "ic0", "ic0", "multicolor"),
+    # threshold factors (drop tolerance 1e-3 on both sides): identical fill
+    ("lap3d_64", {"N": 12, "boxes": 2}, "ict", "ict", "subdomain"),
+    ("shifted3d_128", {"N": 12, "boxes": 2, "neg": 4}, "ildlt", "ict", "subdomain"),
+    ("diffusion2d_1024", {"N": 48, "boxes": 3}, "ict", "ic0", "multicolor"),
 ]
 
 
