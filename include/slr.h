@@ -307,6 +307,9 @@ size_t slr_batch_bytes(const slr_batch *b);     /* device bytes held */
 void slr_batch_destroy(slr_batch *b);
 
 /* ---- misc ------------------------------------------------------------- */
+/* slr_destroy: frees the context and its device memory; NULL is a no-op.
+ * Destroy the context's batches first (they refer to it) and let its
+ * streams' work finish. */
 void slr_destroy(slr_ctx *c);
 const char *slr_strerror(int code);
 const char *slr_last_error(void);
