@@ -168,7 +168,7 @@ struct slr_ctx {
   // solve workspace
   DevPool spool;
   int32_t scap = 0;
-  double *sX = nullptr, *sR = nullptr, *sZ = nullptr, *sP = nullptr, *sQ = nullptr, *sB = nullptr;
+  double *sX = nullptr, *sR = nullptr, *sZ = nullptr, *sP = nullptr, *sQ = nullptr, *sS = nullptr, *sB = nullptr;
   KState *sst = nullptr;
   double *spart = nullptr, *spart2 = nullptr;
   unsigned int *scnt = nullptr;
@@ -181,7 +181,7 @@ struct slr_batch {
   double rtol = 1e-8;
   DevPool pool;
   ApplyWS ws;
-  double *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr, *B = nullptr;
+  double *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr, *S = nullptr, *B = nullptr;
   KState *st = nullptr;
   double *part = nullptr, *part2 = nullptr;
   unsigned int *counter = nullptr;
@@ -1391,7 +1391,7 @@ size_t slr_solve_workspace_bytes(const slr_ctx *c, int32_t nrhs, int32_t method)
   if (!c) return 0;
   size_t n = (size_t)c->n;
   if (method == SLR_FGMRES) return sizeof(double) * n * (2 * 41 + 4) + sizeof(double) * RED_NBLK * 48;
-  return sizeof(double) * n * nrhs * 6 + sizeof(KState) * nrhs + sizeof(double) * RED_NBLK * nrhs * 2 +
+  return sizeof(double) * n * nrhs * 7 + sizeof(KState) * nrhs + sizeof(double) * RED_NBLK * nrhs * 5 +
          sizeof(double) * (size_t)c->s * nrhs;
 }
 
@@ -1408,22 +1408,24 @@ int solve_ws(slr_ctx *c, int32_t nrhs) {
   c->sZ = c->spool.alloc<double>(n * nrhs);
   c->sP = c->spool.alloc<double>(n * nrhs);
   c->sQ = c->spool.alloc<double>(n * nrhs);
+  c->sS = c->spool.alloc<double>(n * nrhs);
   c->sB = c->spool.alloc<double>(n * nrhs);
   c->sst = c->spool.alloc<KState>(nrhs);
-  c->spart = c->spool.alloc<double>((size_t)RED_NBLK * nrhs * 2);
+  c->spart = c->spool.alloc<double>((size_t)RED_NBLK * nrhs * 4);
   c->spart2 = c->spool.alloc<double>((size_t)RED_NBLK * nrhs);
   c->scnt = c->spool.alloc<unsigned int>(4);
-  if (!c->sX || !c->sR || !c->sZ || !c->sP || !c->sQ || !c->sB || !c->sst || !c->spart || !c->spart2 || !c->scnt)
+  if (!c->sX || !c->sR || !c->sZ || !c->sP || !c->sQ || !c->sS || !c->sB || !c->sst || !c->spart || !c->spart2 ||
+      !c->scnt)
     return fail(SLR_ERR_OOM, "solve workspace");
   HIPCHK(hipMemset(c->scnt, 0, 4 * sizeof(unsigned int)));
   c->scap = nrhs;
   return SLR_OK;
 }
 
-KArgs kargs(double *X, double *R, double *Z, double *P, double *Q, int64_t ld, KState *st, double *part,
+KArgs kargs(double *X, double *R, double *Z, double *P, double *Q, double *S, int64_t ld, KState *st, double *part,
             double *part2, int maxit, double rtol) {
   KArgs K;
-  K.X = X; K.R = R; K.Z = Z; K.P = P; K.Q = Q;
+  K.X = X; K.R = R; K.Z = Z; K.P = P; K.Q = Q; K.S = S;
   K.ld = ld;
   K.st = st;
   K.part = part;
@@ -1435,27 +1437,24 @@ KArgs kargs(double *X, double *R, double *Z, double *P, double *Q, int64_t ld, K
   return K;
 }
 
-// CG / flexible CG start on columns [c0, c0+nc) whose R holds b (internal
-// order); it0 is the global index of their first iteration.
-int cg_start(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, int32_t it0,
-             hipStream_t st) {
+// CG / flexible CG (one reduction phase per iteration) start on columns
+// [c0, c0+nc) whose R holds b (internal order): x = 0 and the state; it0 is
+// the global index of their first iteration, which applies the
+// preconditioner to r = b like every other.
+int cg_start(slr_ctx *c, const KArgs &K, int32_t c0, int32_t nc, int flexible, int32_t it0, hipStream_t st) {
   launch_cg(CG_INIT, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it0, st);
-  int rc = apply_dd(c, w, K.R + (int64_t)c0 * K.ld, K.ld, K.Z + (int64_t)c0 * K.ld, K.ld, nc, st);
-  if (rc) return rc;
   launch_cg(CG_START, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it0, st);
-  launch_axpby(c->n, nc, 1.0, K.Z + (int64_t)c0 * K.ld, K.ld, 0.0, K.P + (int64_t)c0 * K.ld, K.ld, st);
   return SLR_OK;
 }
 
-// one iteration (global index it) of every column in [c0, c0+nc)
+// one iteration (global index it) of every column in [c0, c0+nc):
+// z = M^{-1} r, then w = A z with the partials, then the update
 int cg_iter(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, int32_t it,
             hipStream_t st) {
-  launch_cg(CG_SPMV, c->n, c->a_rp, c->a_ci, c->a_v, K, c0, nc, flexible, it, st);
-  launch_cg(CG_UPDATE, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
   int rc = apply_dd(c, w, K.R + (int64_t)c0 * K.ld, K.ld, K.Z + (int64_t)c0 * K.ld, K.ld, nc, st);
   if (rc) return rc;
-  launch_cg(CG_BETA, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
-  launch_cg(CG_P, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
+  launch_cg(CG_SPMV, c->n, c->a_rp, c->a_ci, c->a_v, K, c0, nc, flexible, it, st);
+  launch_cg(CG_UPDATE, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
   return SLR_OK;
 }
 
@@ -1465,10 +1464,10 @@ int solve_cg(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const
   if (rc) return rc;
   const int64_t n = c->n;
   const int flexible = so.method == SLR_FCG;
-  KArgs K = kargs(c->sX, c->sR, c->sZ, c->sP, c->sQ, n, c->sst, c->spart, c->spart2, so.maxit, so.rtol);
+  KArgs K = kargs(c->sX, c->sR, c->sZ, c->sP, c->sQ, c->sS, n, c->sst, c->spart, c->spart2, so.maxit, so.rtol);
   launch_permute(n, c->perm, b_dev, n, c->sB, n, nrhs, false, st);
   launch_axpby(n, nrhs, 1.0, c->sB, n, 0.0, c->sR, n, st);
-  if ((rc = cg_start(c, c->ws, K, 0, nrhs, flexible, 1, st))) return rc;
+  if ((rc = cg_start(c, K, 0, nrhs, flexible, 1, st))) return rc;
   std::vector<KState> h(nrhs);
   const int every = std::max(1, so.check_every);
   for (int it = 0; it < so.maxit; it += every) {
@@ -1629,12 +1628,14 @@ int slr_batch_create(slr_ctx *c, int32_t max_cols, int32_t method, double rtol, 
   b->Z = b->pool.alloc<double>(n * max_cols);
   b->P = b->pool.alloc<double>(n * max_cols);
   b->Q = b->pool.alloc<double>(n * max_cols);
+  b->S = b->pool.alloc<double>(n * max_cols);
   b->B = b->pool.alloc<double>(n * max_cols);
   b->st = b->pool.alloc<KState>(max_cols);
-  b->part = b->pool.alloc<double>((size_t)RED_NBLK * max_cols * 2);
+  b->part = b->pool.alloc<double>((size_t)RED_NBLK * max_cols * 4);
   b->part2 = b->pool.alloc<double>((size_t)RED_NBLK * max_cols);
   b->counter = b->pool.alloc<unsigned int>(4);
-  if (!b->X || !b->R || !b->Z || !b->P || !b->Q || !b->B || !b->st || !b->part || !b->part2 || !b->counter) {
+  if (!b->X || !b->R || !b->Z || !b->P || !b->Q || !b->S || !b->B || !b->st || !b->part || !b->part2 ||
+      !b->counter) {
     slr_batch_destroy(b);
     return fail(SLR_ERR_OOM, "batch state");
   }
@@ -1689,10 +1690,10 @@ int slr_batch_admit(slr_batch *b, const double *b_dev, double *x_dev, int32_t nr
   slr_ctx *c = b->c;
   hipStream_t st = S(hip_stream);
   const int64_t n = c->n;
-  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->part2, b->maxit, b->rtol);
+  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, b->S, n, b->st, b->part, b->part2, b->maxit, b->rtol);
   launch_permute(n, c->perm, b_dev, n, b->B + (int64_t)c0 * n, n, nrhs, false, st);
   launch_axpby(n, nrhs, 1.0, b->B + (int64_t)c0 * n, n, 0.0, b->R + (int64_t)c0 * n, n, st);
-  int rc = cg_start(c, b->ws, K, c0, nrhs, b->method == SLR_FCG, b->it + 1, st);
+  int rc = cg_start(c, K, c0, nrhs, b->method == SLR_FCG, b->it + 1, st);
   if (rc) return rc;
   const int64_t rid = (int64_t)b->reqs.size();
   b->reqs.push_back({tag, c0, nrhs, x_dev, true});
@@ -1706,7 +1707,7 @@ int slr_batch_step(slr_batch *b, int32_t iters, void *hip_stream) {
   if (b->hi == 0) return SLR_OK;
   slr_ctx *c = b->c;
   hipStream_t st = S(hip_stream);
-  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, c->n, b->st, b->part, b->part2, b->maxit, b->rtol);
+  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, b->S, c->n, b->st, b->part, b->part2, b->maxit, b->rtol);
   for (int32_t i = 0; i < iters; ++i) {
     int rc = cg_iter(c, b->ws, K, 0, b->hi, b->method == SLR_FCG, ++b->it, st);
     if (rc) return rc;
@@ -1723,7 +1724,7 @@ int slr_batch_poll(slr_batch *b, int64_t *tags, slr_solve_info *info, int32_t ma
   if (hipMemcpyAsync(b->st_h.data(), b->st, sizeof(KState) * b->hi, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(SLR_ERR_HIP, "poll copy");
-  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, n, b->st, b->part, b->part2, b->maxit, b->rtol);
+  KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, b->S, n, b->st, b->part, b->part2, b->maxit, b->rtol);
   int32_t done = 0;
   std::vector<int64_t> fin;
   for (int64_t rid = 0; rid < (int64_t)b->reqs.size() && done < max_done; ++rid) {

@@ -10,21 +10,25 @@ namespace slr {
 // Per-column Krylov state kept on the device (CG / flexible CG).
 struct KState {
   double rz[2];   // r . z, double-buffered by iteration parity
+  double al[2];   // alpha, double-buffered likewise
+  double pq[2];   // p . A p (flexible CG), double-buffered likewise
   double alpha, beta;
   double rr;      // ||r||^2 of the recurrence residual
   double bb;      // ||b||^2
   double relres;  // final true relative residual
   int32_t active; // 1 while iterating
   int32_t status; // 0 converged, -8 not converged / broken down
-  int32_t iters;  // products with A
+  int32_t iters;  // iterations (updates of x and r) done
   int32_t start_it; // global iteration index of the column's first iteration
 };
 
 struct KArgs {
-  double *X, *R, *Z, *P, *Q;  // n x ncols, leading dimension ld (internal order)
+  double *X, *R, *Z, *P;      // n x ncols, leading dimension ld (internal order)
+  double *Q;                  // w = A z (same layout)
+  double *S;                  // s = A p (same layout)
   int64_t ld;
   KState *st;
-  double *part;               // nblk x 2 ncols partials
+  double *part;               // nblk x 4 ncols partials
   double *part2;              // nblk x ncols partials
   unsigned int *counter;      // unused
   int32_t nblk;
@@ -32,7 +36,10 @@ struct KArgs {
   double rtol2;
 };
 
-enum { CG_INIT = 0, CG_START, CG_SPMV, CG_UPDATE, CG_BETA, CG_P };
+// Krylov kernels of CG / flexible CG (one reduction phase per iteration):
+// CG_INIT (x = 0, partial b.b), CG_START (state), then per iteration, after
+// the preconditioner, CG_SPMV (w = A z and the partials) and CG_UPDATE.
+enum { CG_INIT = 0, CG_START, CG_SPMV, CG_UPDATE };
 
 // Round an FP64 value for storage: FP32 is round-to-nearest-even; BF16 is
 // round-to-nearest-even of the FP32-rounded value.

@@ -72,6 +72,46 @@ __device__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// Lane `lane`'s share of a fold: part[b*ld + col] summed over b = lane,
+// lane + 64, ... < nb, added in that order.  The loads go out eight at a
+// time, so a fold of up to 512 partials costs one memory round trip.
+__device__ __forceinline__ double lane_fold(const double *part, int nb, int64_t ld, int col, int lane) {
+  double v = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += 8 * 64) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + lane + u * 64;
+      t[u] = b < nb ? part[(int64_t)b * ld + col] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + lane + u * 64 < nb) v += t[u];
+  }
+  return v;
+}
+
+// N block sums at once (the same arithmetic as N calls of block_sum, with
+// one pair of barriers); sh holds N * nw values, results in thread 0's v.
+template <int N>
+__device__ void block_sums(double *v, double *sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < N; ++j) sh[j * nw + wid] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double r = 0.0;
+      for (int i = 0; i < nw; ++i) r += sh[j * nw + i];
+      v[j] = r;
+    }
+}
+
 // Deterministic parallel fold of per-block partials laid out part[b*ncol+col]:
 // each wave folds whole columns (lanes stride over b, then a shuffle tree);
 // f(col, value) runs in lane 0 of the folding wave.
@@ -79,9 +119,7 @@ template <class F>
 __device__ __forceinline__ void fold_waves(const double *part, int nb, int ncol, F f) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int col = wid; col < ncol; col += nw) {
-    double v = 0.0;
-    for (int b = lane; b < nb; b += 64) v += part[(int64_t)b * ncol + col];
-    v = wave_sum(v);
+    const double v = wave_sum(lane_fold(part, nb, ncol, col, lane));
     if (lane == 0) f(col, v);
   }
 }
@@ -91,9 +129,7 @@ __global__ void __launch_bounds__(256) k_fold(const double *part, int nb, int nc
   const int lane = threadIdx.x & 63;
   const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (col >= ncol) return;
-  double v = 0.0;
-  for (int b = lane; b < nb; b += 64) v += part[(int64_t)b * ncol + col];
-  v = wave_sum(v);
+  const double v = wave_sum(lane_fold(part, nb, ncol, col, lane));
   if (lane == 0) out[col] = v * scale;
 }
 
@@ -678,9 +714,7 @@ __global__ void __launch_bounds__(256) k_lr_fold(const double *part, int nb, int
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= kn) return;
-  double v = 0.0;
-  for (int b = lane; b < nb; b += 64) v += part[(int64_t)b * kn + t];
-  v = wave_sum(v);
+  const double v = wave_sum(lane_fold(part, nb, kn, t, lane));
   if (lane == 0) cbuf[t] = v * dsc[t % k];
 }
 
@@ -1142,184 +1176,107 @@ void launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *
 // Every reduction writes per-block partials part[b*width + col]; the next
 // kernel's blocks each fold them (identically) in LDS.  No kernel reads a
 // state field that a block of the same kernel writes, except `active`,
-// whose update (active && !stop) gives the same answer before and after.
+// whose update (active && !stop) gives the same answer before and after;
+// the scalars carried between iterations are double-buffered by iteration
+// parity (read from one slot, written to the other).
 // ---------------------------------------------------------------------------
 constexpr int RED_THREADS = 256;
-constexpr int MAX_FOLD = 256;   // folded values per launch (2 per column)
+constexpr int MAX_FOLD = 512;   // folded values per launch (up to 4 per column, 128 columns)
 
 __device__ __forceinline__ void fold_to_lds(const double *part, int nb, int width, double *fin) {
   fold_waves(part, nb, width, [&](int col, double v) { fin[col] = v; });
   __syncthreads();
 }
 
+// Row chunks of the reduction kernels, which run RED_THREADS threads per
+// block (a constant here, so that no row index waits for the launch's block
+// size to be read).
 template <class F>
 __device__ __forceinline__ void chunk_rows(int64_t n, F f) {
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) f(i);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) f(i);
 }
 
-// (1) q = A p and partial p.q  -> part[b*nc + cc].  Columns go in tiles of
-// TT (1 for a single column, SPMV_T otherwise) so that each row's entries
-// are read once per tile; a column's arithmetic (entry order, row order,
-// block sum) does not depend on the tile it falls in.
-template <int TT>
-__global__ void __launch_bounds__(RED_THREADS) k_cg_spmv(int64_t n, const int64_t *rp, const int32_t *ci,
-                                                         const double *v, KArgs K, int c0, int nc) {
-  constexpr int SPMV_T = TT;
-  __shared__ double sh[RED_THREADS / 64];
-  for (int ct = 0; ct < nc; ct += SPMV_T) {
-    const int nct = min(SPMV_T, nc - ct);
-    bool act[SPMV_T];
-    double acc[SPMV_T];
+// The rows chunk_rows gives this thread, i0 + t + j * blockDim.x, in
+// batches of RPT: ld(r, i) issues row i's loads into register slot r, op(r,
+// i) consumes them, rows in ascending order (so per-thread sums come out as
+// with chunk_rows).  mid() runs once in every thread, after the first
+// batch's loads went out and before any op: a fold whose result op needs
+// overlaps with them.
+template <int RPT, class Ld, class Mid, class Op>
+__device__ __forceinline__ void chunk_rows_pf(int64_t n, Ld ld, Mid mid, Op op) {
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  constexpr int64_t bd = RED_THREADS;
+  int64_t b = i0 + threadIdx.x;
 #pragma unroll
-    for (int t = 0; t < SPMV_T; ++t) {
-      act[t] = t < nct && K.st[c0 + ct + t].active;
-      acc[t] = 0.0;
-    }
-    chunk_rows(n, [&](int64_t i) {
-      double sum[SPMV_T];
+  for (int r = 0; r < RPT; ++r)
+    if (b + r * bd < i1) ld(r, b + r * bd);
+  mid();
+  while (b < i1) {
 #pragma unroll
-      for (int t = 0; t < SPMV_T; ++t) sum[t] = 0.0;
-      csr_row_acc<SPMV_T, SPMV_T == 1 ? 8 : 2>(rp[i], rp[i + 1], ci, v, K.P, K.ld, c0 + ct, act, sum);
+    for (int r = 0; r < RPT; ++r)
+      if (b + r * bd < i1) op(r, b + r * bd);
+    b += RPT * bd;
+    if (b >= i1) break;
 #pragma unroll
-      for (int t = 0; t < SPMV_T; ++t)
-        if (act[t]) {
-          const int64_t o = i + (int64_t)(c0 + ct + t) * K.ld;
-          K.Q[o] = sum[t];
-          acc[t] += sum[t] * K.P[o];
-        }
-    });
-    for (int t = 0; t < nct; ++t) {
-      const double tt = block_sum(acc[t], sh);
-      if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + ct + t] = tt;
-    }
+    for (int r = 0; r < RPT; ++r)
+      if (b + r * bd < i1) ld(r, b + r * bd);
   }
 }
 
-// alpha from the folded p.q; a non-positive p.q stops the column
-__device__ __forceinline__ double cg_alpha(const KState &s, double pq, int it, bool &brk) {
-  brk = !(pq > 0.0) || !isfinite(pq);
-  return (s.active && !brk) ? s.rz[(it - 1) & 1] / pq : 0.0;
-}
+constexpr int CG_RPT = 4;   // rows per thread whose loads go out together
 
-// (2) fold p.q -> alpha ; x += alpha p ; r -= alpha q ; partial r.r -> part2
-__global__ void __launch_bounds__(RED_THREADS) k_cg_update(int64_t n, KArgs K, int c0, int nc, int it) {
-  __shared__ double sh[RED_THREADS / 64];
-  __shared__ double fin[MAX_FOLD];
-  fold_to_lds(K.part, K.nblk, nc, fin);
-  for (int cc = 0; cc < nc; ++cc) {
-    const int c = c0 + cc;
-    const KState &s = K.st[c];
-    bool brk;
-    const double al = cg_alpha(s, fin[cc], it, brk);
-    double acc = 0.0;
-    if (s.active && !brk) {
-      double *xc = K.X + (int64_t)c * K.ld;
-      double *rc = K.R + (int64_t)c * K.ld;
-      const double *pc = K.P + (int64_t)c * K.ld;
-      const double *qc = K.Q + (int64_t)c * K.ld;
-      chunk_rows(n, [&](int64_t i) {
-        xc[i] += al * pc[i];
-        const double r = rc[i] - al * qc[i];
-        rc[i] = r;
-        acc += r * r;
-      });
-    }
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) K.part2[(int64_t)blockIdx.x * nc + cc] = t;
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      KState &s = K.st[c0 + cc];
-      bool brk;
-      const double al = cg_alpha(s, fin[cc], it, brk);
-      if (s.active) {
-        s.alpha = al;
-        if (brk) {
-          s.active = 0;
-          s.status = -8;
-          s.iters = it - s.start_it + 1;
-        }
+// One column, y = A x: a thread takes two of its rows at a time and issues
+// both rows' pointer, entry and gather loads together, U entries per round.
+// A load past a row's end is clamped to the row's last entry (to entry 0 for
+// an empty row; some row is not empty while the loop runs) and not added;
+// each row sums its entries in entry order.  own(i, h) issues the loads of
+// row i's own vector entries (slot h = 0, 1) with the row pointers, and
+// emit(i, h, y_i) consumes them, rows in ascending order.
+template <int U, class Own, class Emit>
+__device__ __forceinline__ void spmv_pair(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                                          const double *x, Own own, Emit emit) {
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  constexpr int64_t bd = RED_THREADS;
+  for (int64_t ia = i0 + threadIdx.x; ia < i1; ia += 2 * bd) {
+    const int64_t ib = ia + bd;
+    const bool hb = ib < i1;
+    const int64_t ibc = hb ? ib : ia;
+    const int64_t ea = rp[ia], fa = rp[ia + 1];
+    const int64_t eb0 = rp[ibc], fb0 = rp[ibc + 1];
+    const int64_t eb = hb ? eb0 : ea, fb = hb ? fb0 : ea;   // a missing second row is empty
+    own(ia, 0);
+    own(ibc, 1);
+    const int64_t la = fa - 1 > 0 ? fa - 1 : 0, lb = fb - 1 > 0 ? fb - 1 : 0;
+    const int64_t len = max(fa - ea, fb - eb);
+    double sa = 0.0, sb = 0.0;
+    for (int64_t o = 0; o < len; o += U) {
+      double av[U], bv[U], ax[U], bx[U];
+      int32_t aj[U], bj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t xa = min(ea + o + u, la), xb = min(eb + o + u, lb);
+        av[u] = v[xa];
+        aj[u] = ci[xa];
+        bv[u] = v[xb];
+        bj[u] = ci[xb];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ax[u] = x[aj[u]];
+        bx[u] = x[bj[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ea + o + u < fa) sa += av[u] * ax[u];
+        if (eb + o + u < fb) sb += bv[u] * bx[u];
       }
     }
-  }
-}
-
-// convergence of column c after the update of iteration `it`
-__device__ __forceinline__ bool cg_stop(const KState &s, double rr, int it, int maxit, double rtol2, bool &ok) {
-  ok = rr <= rtol2 * s.bb;
-  return ok || (it - s.start_it + 1) >= maxit || !isfinite(rr);
-}
-
-// (3) fold r.r -> convergence ; partials r.z and z.q -> part[b*2nc + 2cc (+1)]
-__global__ void __launch_bounds__(RED_THREADS) k_cg_beta(int64_t n, KArgs K, int c0, int nc, int flexible, int it) {
-  __shared__ double sh[RED_THREADS / 64];
-  __shared__ double fin[MAX_FOLD];
-  fold_to_lds(K.part2, K.nblk, nc, fin);
-  for (int cc = 0; cc < nc; ++cc) {
-    const int c = c0 + cc;
-    const KState &s = K.st[c];
-    bool ok;
-    const bool go = s.active && !cg_stop(s, fin[cc], it, K.maxit, K.rtol2, ok);
-    double a1 = 0.0, a2 = 0.0;
-    if (go) {
-      const double *rc = K.R + (int64_t)c * K.ld;
-      const double *zc = K.Z + (int64_t)c * K.ld;
-      const double *qc = K.Q + (int64_t)c * K.ld;
-      chunk_rows(n, [&](int64_t i) {
-        a1 += rc[i] * zc[i];
-        if (flexible) a2 += zc[i] * qc[i];
-      });
-    }
-    const double t1 = block_sum(a1, sh);
-    const double t2 = block_sum(a2, sh);
-    if (threadIdx.x == 0) {
-      K.part[(int64_t)blockIdx.x * 2 * nc + 2 * cc] = t1;
-      K.part[(int64_t)blockIdx.x * 2 * nc + 2 * cc + 1] = t2;
-    }
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      KState &s = K.st[c0 + cc];
-      if (!s.active) continue;
-      bool ok;
-      const double rr = fin[cc];
-      const bool stop = cg_stop(s, rr, it, K.maxit, K.rtol2, ok);
-      s.rr = rr;
-      s.iters = it - s.start_it + 1;
-      if (stop) {
-        s.active = 0;
-        s.status = ok ? 0 : -8;
-      }
-    }
-  }
-}
-
-// (4) fold r.z, z.q -> beta ; p = z + beta p ; rz stored for iteration it+1
-__global__ void __launch_bounds__(RED_THREADS) k_cg_p(int64_t n, KArgs K, int c0, int nc, int flexible, int it) {
-  __shared__ double fin[MAX_FOLD];
-  fold_to_lds(K.part, K.nblk, 2 * nc, fin);
-  for (int cc = 0; cc < nc; ++cc) {
-    const int c = c0 + cc;
-    const KState &s = K.st[c];
-    if (!s.active) continue;
-    const double rzo = s.rz[(it - 1) & 1];
-    const double beta = flexible ? (-s.alpha * fin[2 * cc + 1]) / rzo : fin[2 * cc] / rzo;
-    double *pc = K.P + (int64_t)c * K.ld;
-    const double *zc = K.Z + (int64_t)c * K.ld;
-    chunk_rows(n, [&](int64_t i) { pc[i] = zc[i] + beta * pc[i]; });
-  }
-  if (blockIdx.x == 0) {
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      KState &s = K.st[c0 + cc];
-      if (!s.active) continue;
-      const double rzo = s.rz[(it - 1) & 1];
-      s.beta = flexible ? (-s.alpha * fin[2 * cc + 1]) / rzo : fin[2 * cc] / rzo;
-      s.rz[it & 1] = fin[2 * cc];
-    }
+    emit(ia, 0, sa);
+    if (hb) emit(ib, 1, sb);
   }
 }
 
@@ -1338,49 +1295,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_cg_init(int64_t n, KArgs K, int
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) K.part2[(int64_t)blockIdx.x * nc + cc] = t;
   }
-}
-
-// after z0 = M^{-1} r0: fold b.b (part2); partial r.z -> part; block 0
-// initialises the state (start iteration it0 = the next iteration index)
-__global__ void __launch_bounds__(RED_THREADS) k_cg_start(int64_t n, KArgs K, int c0, int nc, int it0) {
-  __shared__ double sh[RED_THREADS / 64];
-  __shared__ double fin[MAX_FOLD];
-  fold_to_lds(K.part2, K.nblk, nc, fin);
-  for (int cc = 0; cc < nc; ++cc) {
-    const int c = c0 + cc;
-    const double *rc = K.R + (int64_t)c * K.ld;
-    const double *zc = K.Z + (int64_t)c * K.ld;
-    double acc = 0.0;
-    chunk_rows(n, [&](int64_t i) { acc += rc[i] * zc[i]; });
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) K.part[(int64_t)blockIdx.x * nc + cc] = t;
-  }
-  if (blockIdx.x == 0) {
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      KState &s = K.st[c0 + cc];
-      const double bb = fin[cc];
-      s.bb = bb;
-      s.rr = bb;
-      s.iters = 0;
-      s.start_it = it0;
-      s.alpha = s.beta = 0.0;
-      s.relres = 0.0;
-      if (bb > 0.0 && isfinite(bb)) {
-        s.active = 1;
-        s.status = -8;
-      } else {
-        s.active = 0;
-        s.status = isfinite(bb) ? 0 : -8;
-      }
-    }
-  }
-}
-
-// rz of the start, stored where iteration it0 reads it
-__global__ void __launch_bounds__(RED_THREADS) k_cg_start2(KArgs K, int c0, int nc, int it0) {
-  __shared__ double fin[MAX_FOLD];
-  fold_to_lds(K.part, K.nblk, nc, fin);
-  for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) K.st[c0 + cc].rz[(it0 - 1) & 1] = fin[cc];
 }
 
 // true residual: partial ||b - A x||^2 (AX holds A x) -> part2; then fold
@@ -1407,6 +1321,218 @@ __global__ void __launch_bounds__(RED_THREADS) k_relres2(KArgs K, int c0, int nc
   }
 }
 
+// ---------------------------------------------------------------------------
+// CG and flexible CG with one reduction phase per iteration.  With z =
+// M^{-1} r and w = A z of the current r, and s = A p kept beside p:
+//   gamma = r.z, delta = z.w, and for the flexible form eps = z.s_prev;
+//   plain (Chronopoulos and Gear):  beta = gamma / gamma_prev,
+//                                   p.Ap = delta - beta gamma / alpha_prev
+//   flexible (beta makes p A-orthogonal to p_prev):
+//                                   beta = -eps / (p.Ap)_prev,
+//                                   p.Ap = delta + beta eps
+//   (beta = 0 and p.Ap = delta at a column's first iteration);
+//   alpha = gamma / p.Ap ; p = z + beta p ; s = w + beta s ;
+//   x += alpha p ; r -= alpha s.
+// In exact arithmetic these are the iterates of the two-reduction forms (the
+// flexible p.Ap uses p_prev . A z = z . A p_prev, A symmetric).  r.r of the
+// current r is summed in the same pass, so the convergence test of r_i comes
+// just before update i.  One iteration: preconditioner (z), k_cg_spmv (w
+// and the partials), k_cg_update.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int cg_np(int flexible) { return flexible ? 4 : 3; }
+
+// w = A z ; partials gamma, delta, rho = r.r (, eps) ->
+// part[b*np*nc + np*cc + (0, 1, 2 (, 3))]
+template <int TT>
+__global__ void __launch_bounds__(RED_THREADS) k_cg_spmv(int64_t n, const int64_t *rp, const int32_t *ci,
+                                                          const double *v, KArgs K, int c0, int nc, int flexible) {
+  __shared__ double sh[4 * (RED_THREADS / 64)];
+  const int np = cg_np(flexible);
+  if (TT == 1 && nc == 1) {
+    // no load waits for the column's state: an inactive column's w and
+    // partials are never used
+    const double *Z = K.Z + (int64_t)c0 * K.ld, *R = K.R + (int64_t)c0 * K.ld, *S = K.S + (int64_t)c0 * K.ld;
+    double *W = K.Q + (int64_t)c0 * K.ld;
+    double g = 0.0, d = 0.0, rr = 0.0, ep = 0.0, zv[2], rv[2], sv[2];
+    spmv_pair<8>(
+        n, rp, ci, v, Z,
+        [&](int64_t i, int h) {
+          zv[h] = Z[i];
+          rv[h] = R[i];
+          if (flexible) sv[h] = S[i];
+        },
+        [&](int64_t i, int h, double w) {
+          W[i] = w;
+          g += rv[h] * zv[h];
+          d += zv[h] * w;
+          rr += rv[h] * rv[h];
+          if (flexible) ep += zv[h] * sv[h];
+        });
+    double t[4] = {g, d, rr, ep};
+    block_sums<4>(t, sh);
+    if (threadIdx.x == 0)
+      for (int j = 0; j < np; ++j) K.part[(int64_t)blockIdx.x * np + j] = t[j];
+    return;
+  }
+  for (int ct = 0; ct < nc; ct += TT) {
+    const int nct = min(TT, nc - ct);
+    bool act[TT];
+    double g[TT], d[TT], rr[TT], ep[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      act[t] = t < nct && K.st[c0 + ct + t].active;
+      g[t] = d[t] = rr[t] = ep[t] = 0.0;
+    }
+    chunk_rows(n, [&](int64_t i) {
+      double sum[TT];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) sum[t] = 0.0;
+      csr_row_acc<TT, TT == 1 ? 8 : 2>(rp[i], rp[i + 1], ci, v, K.Z, K.ld, c0 + ct, act, sum);
+#pragma unroll
+      for (int t = 0; t < TT; ++t)
+        if (act[t]) {
+          const int64_t o = i + (int64_t)(c0 + ct + t) * K.ld;
+          const double zi = K.Z[o], ri = K.R[o];
+          K.Q[o] = sum[t];
+          g[t] += ri * zi;
+          d[t] += zi * sum[t];
+          rr[t] += ri * ri;
+          if (flexible) ep[t] += zi * K.S[o];
+        }
+    });
+    for (int t = 0; t < nct; ++t) {
+      double u[4] = {g[t], d[t], rr[t], ep[t]};
+      block_sums<4>(u, sh);
+      if (threadIdx.x == 0)
+        for (int j = 0; j < np; ++j) K.part[(int64_t)blockIdx.x * np * nc + np * (ct + t) + j] = u[j];
+    }
+  }
+}
+
+// The decision of iteration `it` for one column from its folded partials f
+// (gamma, delta, rho, eps): stop (converged, iteration limit, or a
+// non-finite residual), break down (no positive curvature), or update with
+// alpha, beta; pap = p.Ap of the new p.
+struct CgStep {
+  bool stop, ok, brk, first;
+  int done;
+  double alpha, beta, pap;
+};
+
+__device__ __forceinline__ CgStep cg_step(const KState &s, const double *f, int it, int maxit, double rtol2,
+                                            int flexible) {
+  CgStep q;
+  const double gam = f[0], del = f[1], rho = f[2];
+  q.done = it - s.start_it;
+  q.ok = rho <= rtol2 * s.bb;
+  q.stop = q.ok || q.done >= maxit || !isfinite(rho);
+  q.first = q.done == 0;
+  if (q.first) {
+    q.beta = 0.0;
+    q.pap = del;
+  } else if (flexible) {
+    q.beta = -f[3] / s.pq[(it - 1) & 1];
+    q.pap = del + q.beta * f[3];
+  } else {
+    q.beta = gam / s.rz[(it - 1) & 1];
+    q.pap = del - q.beta * gam / s.al[(it - 1) & 1];
+  }
+  q.alpha = gam / q.pap;
+  q.brk = !(q.pap > 0.0) || !isfinite(q.alpha);
+  return q;
+}
+
+// fold ; stop or p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s
+// (the first column's vectors are loaded while the partials are folded)
+__global__ void __launch_bounds__(RED_THREADS) k_cg_update(int64_t n, KArgs K, int c0, int nc, int flexible,
+                                                            int it) {
+  __shared__ double fin[MAX_FOLD];
+  const int np = cg_np(flexible);
+  for (int cc = 0; cc < nc; ++cc) {
+    const int c = c0 + cc;
+    const KState &s = K.st[c];
+    const bool live = s.active;
+    const int64_t o = (int64_t)c * K.ld;
+    double *X = K.X + o, *R = K.R + o, *P = K.P + o, *S = K.S + o;
+    const double *Z = K.Z + o, *W = K.Q + o;
+    double xv[CG_RPT], rv[CG_RPT], pv[CG_RPT], sv[CG_RPT], zv[CG_RPT], wv[CG_RPT];
+    CgStep q{};
+    bool go = false;
+    chunk_rows_pf<CG_RPT>(
+        n,
+        [&](int r, int64_t i) {
+          if (cc == 0 || live) {
+            xv[r] = X[i];
+            rv[r] = R[i];
+            pv[r] = P[i];
+            sv[r] = S[i];
+            zv[r] = Z[i];
+            wv[r] = W[i];
+          }
+        },
+        [&]() {
+          if (cc == 0) fold_to_lds(K.part, K.nblk, np * nc, fin);
+          q = cg_step(s, fin + np * cc, it, K.maxit, K.rtol2, flexible);
+          go = live && !q.stop && !q.brk;
+        },
+        [&](int r, int64_t i) {
+          if (go) {
+            const double pn = q.first ? zv[r] : zv[r] + q.beta * pv[r];
+            const double sn = q.first ? wv[r] : wv[r] + q.beta * sv[r];
+            P[i] = pn;
+            S[i] = sn;
+            X[i] = xv[r] + q.alpha * pn;
+            R[i] = rv[r] - q.alpha * sn;
+          }
+        });
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int cc = threadIdx.x; cc < nc; cc += RED_THREADS) {
+      KState &s = K.st[c0 + cc];
+      if (!s.active) continue;
+      const CgStep q = cg_step(s, fin + np * cc, it, K.maxit, K.rtol2, flexible);
+      s.rr = fin[np * cc + 2];
+      if (q.stop || q.brk) {
+        s.active = 0;
+        s.status = (q.stop && q.ok) ? 0 : -8;
+        s.iters = q.done;
+      } else {
+        s.rz[it & 1] = fin[np * cc];
+        s.al[it & 1] = q.alpha;
+        s.pq[it & 1] = q.pap;
+        s.alpha = q.alpha;
+        s.beta = q.beta;
+        s.iters = q.done + 1;
+      }
+    }
+  }
+}
+
+// start of columns [c0, c0+nc) after k_cg_init (x = 0, partial b.b): fold
+// b.b and set the state; the first iteration index is it0
+__global__ void __launch_bounds__(RED_THREADS) k_cg_start(KArgs K, int c0, int nc, int it0) {
+  __shared__ double fin[MAX_FOLD];
+  fold_to_lds(K.part2, K.nblk, nc, fin);
+  for (int cc = threadIdx.x; cc < nc; cc += RED_THREADS) {
+    KState &s = K.st[c0 + cc];
+    const double bb = fin[cc];
+    s.bb = bb;
+    s.rr = bb;
+    s.iters = 0;
+    s.start_it = it0;
+    s.alpha = s.beta = 0.0;
+    s.relres = 0.0;
+    if (bb > 0.0 && isfinite(bb)) {
+      s.active = 1;
+      s.status = -8;
+    } else {
+      s.active = 0;
+      s.status = isfinite(bb) ? 0 : -8;
+    }
+  }
+}
+
 void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const KArgs &K,
                int32_t c0, int32_t nc, int32_t flexible, int32_t it, hipStream_t st) {
   if (nc == 0) return;
@@ -1416,23 +1542,17 @@ void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const do
       hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc);
       break;
     case CG_START:
-      hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, it);
-      hipLaunchKernelGGL(k_cg_start2, dim3(1), dim3(RED_THREADS), 0, st, K, c0, nc, it);
+      hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(RED_THREADS), 0, st, K, c0, nc, it);
       break;
     case CG_SPMV:
       if (nc == 1)
-        hipLaunchKernelGGL(k_cg_spmv<1>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc);
+        hipLaunchKernelGGL(k_cg_spmv<1>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc, flexible);
       else
-        hipLaunchKernelGGL(k_cg_spmv<SPMV_T>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc);
+        hipLaunchKernelGGL(k_cg_spmv<SPMV_T>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc,
+                           flexible);
       break;
     case CG_UPDATE:
-      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, it);
-      break;
-    case CG_BETA:
-      hipLaunchKernelGGL(k_cg_beta, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, it);
-      break;
-    case CG_P:
-      hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, it);
+      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, it);
       break;
     default:
       break;
@@ -1575,15 +1695,25 @@ __global__ void __launch_bounds__(256) k_lanczos_axpy(int64_t s, double *w, cons
                                                       double *sc, const double *apart, int rb, double *sqpart) {
   __shared__ double al;
   __shared__ double sh[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the vectors do not depend on alpha: their loads overlap with the fold
+  double wi = 0.0, vi = 0.0, pi = 0.0, bp = 0.0;
+  if (i < s) {
+    wi = w[i];
+    vi = v[i];
+    if (vprev) {
+      pi = vprev[i];
+      bp = sc[1];
+    }
+  }
   fold_waves(apart, rb, 1, [&](int, double x) { al = x; });
   __syncthreads();
   const double a = al;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[0] = a;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double t = 0.0;
   if (i < s) {
-    t = w[i] - a * v[i];
-    if (vprev) t -= sc[1] * vprev[i];
+    t = wi - a * vi;
+    if (vprev) t -= bp * pi;
     w[i] = t;
   }
   const double q = block_sum(t * t, sh);
@@ -1716,6 +1846,8 @@ __global__ void __launch_bounds__(256) k_lanczos_next(int64_t s, int j, const do
                                                       double *alpha, double *beta, const double *bpart, int rb,
                                                       const double *aval) {
   __shared__ double bt;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double wi = (i < s && vnext) ? w[i] : 0.0;   // loaded while the norm is folded
   fold_waves(bpart, rb, 1, [&](int, double x) { bt = sqrt(x); });
   __syncthreads();
   const double b = bt;
@@ -1724,9 +1856,8 @@ __global__ void __launch_bounds__(256) k_lanczos_next(int64_t s, int j, const do
     beta[j] = b;
     sc[1] = b;
   }
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s || !vnext) return;
-  vnext[i] = b > 0.0 ? w[i] / b : 0.0;
+  vnext[i] = b > 0.0 ? wi / b : 0.0;
 }
 
 void launch_lanczos_next(int64_t s, int32_t j, const double *w, double *vnext, double *sc, double *alpha,
@@ -1841,7 +1972,6 @@ void launch_div_scalar(int64_t n, const double *w, double *v, const double *scal
 // Outputs: eval (descending, all m), Y (m x K column-major), info (0).
 // scratch: 6 m K doubles.
 // ---------------------------------------------------------------------------
-constexpr int EIG_MAXM = 1024;
 constexpr int EIG_THREADS = 1024;
 
 // Sturm counts (eigenvalues of T below x) at NPT points at once, from the
