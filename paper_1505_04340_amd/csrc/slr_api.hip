@@ -111,6 +111,7 @@ struct slr_ctx {
   SweepArrays<float> Cff, Cbf;
   std::vector<int32_t> cf_lev_h, cb_lev_h;
   int32_t cf_nlev = 0, cb_nlev = 0;
+  int64_t cb_nnz = 0;           // weight entries of the backward interface schedule
   bool c_one_wg = true;
   bool c_two_level = false;     // interface schedules of <= 2 levels: one launch per sweep
   int32_t b_threads = 1024;
@@ -350,13 +351,14 @@ int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, in
 // stored factors; t: s-vector scratch.
 // w = H v.  With dv and a two-level interface schedule, the last sweep also
 // leaves the per-block partial sums of dv . w in dpart and *ndp receives
-// their count (0 otherwise).
+// their count (0 otherwise).  t_ready (two-level schedules): t already
+// holds L^{-T} v (computed with the previous Lanczos step's end).
 int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipStream_t st,
-            const double *dv = nullptr, double *dpart = nullptr, int32_t *ndp = nullptr) {
+            const double *dv = nullptr, double *dpart = nullptr, int32_t *ndp = nullptr, bool t_ready = false) {
   if (ndp) *ndp = 0;
   const int64_t s = c->s;
   if (c->c_two_level) {
-    csweep2(c, false, v, s, t, s, 1, true, st);
+    if (!t_ready) csweep2(c, false, v, s, t, s, 1, true, st);
   } else {
     launch_axpby(s, 1, 1.0, v, s, 0.0, t, s, st);
     csweep(c, false, t, s, 1, true, st);
@@ -430,6 +432,21 @@ int finish_lowrank(slr_ctx *c, hipStream_t st) {
 // orthogonalised against them too, and up to kw new Ritz pairs are appended.
 // The new U64 lives in a fresh pool that replaces c->lrpool only on success,
 // so a failed growth leaves the resident low-rank part as it was.
+// End of Lanczos step j: beta_j, v_{j+1} = w / beta_j (when vnext) and the
+// recorded coefficients; with a two-level interface schedule the next
+// step's first sweep t = L^{-T} v_{j+1} is computed in the same launch.
+void lanczos_step_end(slr_ctx *c, int32_t j, const double *w, double *vnext, double *sc, double *al, double *be,
+                      const double *bpart, int32_t rb, const double *aval, double *t, hipStream_t st) {
+  if (vnext && c->c_two_level) {
+    if (c->fact_prec == SLR_FP64)
+      launch_lanczos_next_sweep<double>(c->s, j, w, vnext, sc, al, be, bpart, rb, aval, c->Cbd, c->cb_nnz, t, st);
+    else
+      launch_lanczos_next_sweep<float>(c->s, j, w, vnext, sc, al, be, bpart, rb, aval, c->Cbf, c->cb_nnz, t, st);
+  } else {
+    launch_lanczos_next(c->s, j, w, vnext, sc, al, be, bpart, rb, aval, st);
+  }
+}
+
 int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hipStream_t st) {
   const int64_t s = c->s;
   int32_t steps = c->opts.lanczos_steps > 0 ? c->opts.lanczos_steps : 5 * kw;
@@ -512,17 +529,17 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
     // alpha_j = v_j . H v_j: partial sums from the last interface sweep when
     // it can give them, else a separate reduction
     int32_t rba = 0;
-    if ((rc = apply_H(c, vj, Wl, T, T2, st, vj, part, &rba))) return bail(rc);
+    if ((rc = apply_H(c, vj, Wl, T, T2, st, vj, part, &rba, j > 0))) return bail(rc);
     if (rba == 0) rba = launch_multidot_partial(s, 1, vj, s, Wl, part, RED_NBLK, st);
     const int32_t rb = launch_lanczos_axpy(s, Wl, vj, j > 0 ? vj - s : nullptr, sc, part, rba, part2, st);
     const int32_t rbh = launch_multidot_pro(s, j + 1, V0, s, Wl, part, RED_NBLK, j, al, be, sc, part2, rb, om, ld_om,
                                             frc, tn, rflag, st);
     launch_gemv_sub_fold(s, j + 1, V0, s, part, rbh, Wl, nullptr, part2, st, rflag + j);
-    launch_lanczos_next(s, j, Wl, j + 1 < steps ? vj + s : nullptr, sc, al, be, part2, rb, nullptr, st);
+    lanczos_step_end(c, j, Wl, j + 1 < steps ? vj + s : nullptr, sc, al, be, part2, rb, nullptr, T, st);
   }
   for (int32_t j = 0; j < steps && !pro; ++j) {
     double *vj = V0 + (int64_t)j * s;
-    if ((rc = apply_H(c, vj, Wl, T, T2, st))) return bail(rc);
+    if ((rc = apply_H(c, vj, Wl, T, T2, st, nullptr, nullptr, nullptr, j > 0))) return bail(rc);
     const int32_t J = k0 + j + 1;
     int32_t rb = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -532,7 +549,7 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
       const int32_t rbh = launch_multidot_partial(s, J, V, s, Wl, part, RED_NBLK, st);
       rb = launch_gemv_sub_fold(s, J, V, s, part, rbh, Wl, pass == 0 ? h : nullptr, pass == 1 ? part2 : nullptr, st);
     }
-    launch_lanczos_next(s, j, Wl, j + 1 < steps ? vj + s : nullptr, sc, al, be, part2, rb, h + k0 + j, st);
+    lanczos_step_end(c, j, Wl, j + 1 < steps ? vj + s : nullptr, sc, al, be, part2, rb, h + k0 + j, T, st);
   }
   std::vector<double> ah(steps), bh(steps);
   double start_norm = 1.0;
@@ -1072,6 +1089,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->cb_lev_h = H.cbwd.levptr;
   c->cf_nlev = H.cfwd.nlev;
   c->cb_nlev = H.cbwd.nlev;
+  c->cb_nnz = (int64_t)H.cbwd.ci.size();
   // shallow interface schedules (multicolour) run one launch per level
   c->c_one_wg = std::max(c->cf_nlev, c->cb_nlev) > 8;
   c->c_two_level = std::max(c->cf_nlev, c->cb_nlev) <= 2;

@@ -152,6 +152,15 @@ template <typename TS, typename TC>
 void launch_sweep2(const SweepArrays<TS> &S, int32_t nrows, const double *x, int64_t ldx, double *y, int64_t ldy,
                    int32_t nrhs, hipStream_t st, const double *dv = nullptr, double *dpart = nullptr);
 
+// End of Lanczos step j (k_lanczos_next: beta_j from the partials bpart,
+// v_{j+1} = w / beta_j, the recorded coefficients) together with the next
+// step's first sweep: tout = L^{-T} v_{j+1} by the two-level backward
+// schedule S (nw2 weight entries), equal to launch_sweep2 of v_{j+1}.
+template <typename TS>
+void launch_lanczos_next_sweep(int64_t s, int32_t j, const double *w, double *vnext, double *sc, double *alpha,
+                               double *beta, const double *bpart, int32_t rb, const double *aval,
+                               const SweepArrays<TS> &S, int64_t nw2, double *tout, hipStream_t st);
+
 // Rank-k block of eq. skt on w (s x nrhs, ld ldw), output to wout (ldo);
 // U column-major s x k:
 //   c = U^T w ;  c_i <- c_i * dsc_i ;  wout = rho * w + U c

@@ -1866,6 +1866,87 @@ void launch_lanczos_next(int64_t s, int32_t j, const double *w, double *vnext, d
                      beta, bpart, rb, aval);
 }
 
+// k_lanczos_next with the next step's first interface sweep fused: thread
+// t also computes slot t of the two-level backward sweep y = L^{-T} v_{j+1}
+// (out of place into tout) from w / beta_j at the slot's row and its
+// dependencies, which are the stored v_{j+1} values, with the operations of
+// k_sweep2 in its order, so tout equals that sweep of v_{j+1} bit for bit.
+// The sweep row's loads (and those of its first LN_U dependencies) go out
+// before beta_j is folded.  nw2: entries of the sweep's weight arrays.
+constexpr int LN_U = 8;
+
+template <typename TS>
+__global__ void __launch_bounds__(256) k_lanczos_next_sweep(int64_t s, int j, const double *w, double *vnext,
+                                                            double *sc, double *alpha, double *beta,
+                                                            const double *bpart, int rb, const double *aval,
+                                                            SweepArrays<TS> S, int64_t nw2, double *tout) {
+  __shared__ double bt;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t ic = i < s ? i : s - 1;   // threads past the end load slot s - 1 and store nothing
+  // wave 0 issues the fold's first 512 loads before the sweep row's chain
+  // of loads, and adds them (in lane_fold's order) after it
+  const int lane = threadIdx.x & 63;
+  double fp[8];
+  if (threadIdx.x < 64)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) fp[u] = bpart[min(lane + u * 64, rb - 1)];
+  const double wi = w[ic];
+  const int row = S.rows[ic];
+  const int e0 = S.rp[ic], e1 = S.rp[ic + 1];
+  const double scv = cvt<double>(S.sc[ic]);
+  const double wr = w[row];
+  double wv[LN_U], xv[LN_U];
+  if (nw2 > 0) {
+    // padding repeats a valid entry of the array and is not used
+    const int last = e1 > e0 ? e1 - 1 : (e0 > 0 ? e0 - 1 : 0);
+#pragma unroll
+    for (int u = 0; u < LN_U; ++u) {
+      const int ee = min(e0 + u, last);
+      wv[u] = cvt<double>(S.w2[ee]);
+      xv[u] = w[S.ci[ee]];
+    }
+  }
+  if (threadIdx.x < 64) {
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (lane + u * 64 < rb) v += fp[u];
+    for (int b = lane + 512; b < rb; b += 64) v += bpart[b];
+    v = wave_sum(v);
+    if (lane == 0) bt = sqrt(v);
+  }
+  __syncthreads();
+  const double b = bt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    alpha[j] = aval ? *aval : sc[0];
+    beta[j] = b;
+    sc[1] = b;
+  }
+  if (i >= s) return;
+  vnext[i] = b > 0.0 ? wi / b : 0.0;
+  auto vs = [&](double x) { return b > 0.0 ? x / b : 0.0; };
+  double acc = scv * vs(wr);
+#pragma unroll
+  for (int u = 0; u < LN_U; ++u)
+    if (e0 + u < e1) acc -= wv[u] * vs(xv[u]);
+  for (int e = e0 + LN_U; e < e1; ++e) acc -= cvt<double>(S.w2[e]) * vs(w[S.ci[e]]);
+  tout[row] = acc;
+}
+
+template <typename TS>
+void launch_lanczos_next_sweep(int64_t s, int32_t j, const double *w, double *vnext, double *sc, double *alpha,
+                               double *beta, const double *bpart, int32_t rb, const double *aval,
+                               const SweepArrays<TS> &S, int64_t nw2, double *tout, hipStream_t st) {
+  hipLaunchKernelGGL((k_lanczos_next_sweep<TS>), dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, s, j, w, vnext,
+                     sc, alpha, beta, bpart, rb, aval, S, nw2, tout);
+}
+template void launch_lanczos_next_sweep<double>(int64_t, int32_t, const double *, double *, double *, double *,
+                                                double *, const double *, int32_t, const double *,
+                                                const SweepArrays<double> &, int64_t, double *, hipStream_t);
+template void launch_lanczos_next_sweep<float>(int64_t, int32_t, const double *, double *, double *, double *,
+                                               double *, const double *, int32_t, const double *,
+                                               const SweepArrays<float> &, int64_t, double *, hipStream_t);
+
 // v_next = w / beta, beta = sqrt(sc[2]) (sc[2] holds w.w)
 __global__ void k_scale_inv_sqrt(int64_t s, const double *w, double *out, const double *nrm2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
