@@ -1466,12 +1466,14 @@ int cg_start(slr_ctx *c, const KArgs &K, int32_t c0, int32_t nc, int flexible, i
 }
 
 // one iteration (global index it) of every column in [c0, c0+nc):
-// z = M^{-1} r, then w = A z with the partials, then the update
+// z = M^{-1} r, then w = A z with the partials, then the update.  tiles:
+// the column-tile SpMV for any nc (batches, whose results must not depend
+// on how many columns are in flight).
 int cg_iter(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int flexible, int32_t it,
-            hipStream_t st) {
+            hipStream_t st, bool tiles = false) {
   int rc = apply_dd(c, w, K.R + (int64_t)c0 * K.ld, K.ld, K.Z + (int64_t)c0 * K.ld, K.ld, nc, st);
   if (rc) return rc;
-  launch_cg(CG_SPMV, c->n, c->a_rp, c->a_ci, c->a_v, K, c0, nc, flexible, it, st);
+  launch_cg(tiles ? CG_SPMV_TILES : CG_SPMV, c->n, c->a_rp, c->a_ci, c->a_v, K, c0, nc, flexible, it, st);
   launch_cg(CG_UPDATE, c->n, nullptr, nullptr, nullptr, K, c0, nc, flexible, it, st);
   return SLR_OK;
 }
@@ -1727,7 +1729,7 @@ int slr_batch_step(slr_batch *b, int32_t iters, void *hip_stream) {
   hipStream_t st = S(hip_stream);
   KArgs K = kargs(b->X, b->R, b->Z, b->P, b->Q, b->S, c->n, b->st, b->part, b->part2, b->maxit, b->rtol);
   for (int32_t i = 0; i < iters; ++i) {
-    int rc = cg_iter(c, b->ws, K, 0, b->hi, b->method == SLR_FCG, ++b->it, st);
+    int rc = cg_iter(c, b->ws, K, 0, b->hi, b->method == SLR_FCG, ++b->it, st, true);
     if (rc) return rc;
   }
   return SLR_OK;

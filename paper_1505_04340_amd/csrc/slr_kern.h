@@ -39,7 +39,10 @@ struct KArgs {
 // Krylov kernels of CG / flexible CG (one reduction phase per iteration):
 // CG_INIT (x = 0, partial b.b), CG_START (state), then per iteration, after
 // the preconditioner, CG_SPMV (w = A z and the partials) and CG_UPDATE.
-enum { CG_INIT = 0, CG_START, CG_SPMV, CG_UPDATE };
+// CG_SPMV takes a one-column kernel when nc == 1; CG_SPMV_TILES always
+// takes the column-tile kernel, whose column arithmetic does not depend on
+// the number of columns (batches).
+enum { CG_INIT = 0, CG_START, CG_SPMV, CG_UPDATE, CG_SPMV_TILES };
 
 // Round an FP64 value for storage: FP32 is round-to-nearest-even; BF16 is
 // round-to-nearest-even of the FP32-rounded value.

@@ -1191,11 +1191,11 @@ __device__ __forceinline__ void fold_to_lds(const double *part, int nb, int widt
 // Row chunks of the reduction kernels, which run RED_THREADS threads per
 // block (a constant here, so that no row index waits for the launch's block
 // size to be read).
-template <class F>
+template <int BD = RED_THREADS, class F>
 __device__ __forceinline__ void chunk_rows(int64_t n, F f) {
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += RED_THREADS) f(i);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += BD) f(i);
 }
 
 // The rows chunk_rows gives this thread, i0 + t + j * blockDim.x, in
@@ -1228,55 +1228,36 @@ __device__ __forceinline__ void chunk_rows_pf(int64_t n, Ld ld, Mid mid, Op op) 
 
 constexpr int CG_RPT = 4;   // rows per thread whose loads go out together
 
-// One column, y = A x: a thread takes two of its rows at a time and issues
-// both rows' pointer, entry and gather loads together, U entries per round.
-// A load past a row's end is clamped to the row's last entry (to entry 0 for
-// an empty row; some row is not empty while the loop runs) and not added;
-// each row sums its entries in entry order.  own(i, h) issues the loads of
-// row i's own vector entries (slot h = 0, 1) with the row pointers, and
-// emit(i, h, y_i) consumes them, rows in ascending order.
-template <int U, class Own, class Emit>
-__device__ __forceinline__ void spmv_pair(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+// One column, y = A x, the rows of this thread's chunk one at a time (BD
+// threads per block): a row's pointer loads and own(i) (the loads of the
+// row's own vector entries) go out together, then its entry loads, U per
+// round (past the row's end clamped to its last entry, not added), then
+// the gathers; emit(i, y_i) consumes them.  Entries are summed in order.
+template <int U, int BD, class Own, class Emit>
+__device__ __forceinline__ void spmv_rows(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                                           const double *x, Own own, Emit emit) {
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-  constexpr int64_t bd = RED_THREADS;
-  for (int64_t ia = i0 + threadIdx.x; ia < i1; ia += 2 * bd) {
-    const int64_t ib = ia + bd;
-    const bool hb = ib < i1;
-    const int64_t ibc = hb ? ib : ia;
-    const int64_t ea = rp[ia], fa = rp[ia + 1];
-    const int64_t eb0 = rp[ibc], fb0 = rp[ibc + 1];
-    const int64_t eb = hb ? eb0 : ea, fb = hb ? fb0 : ea;   // a missing second row is empty
-    own(ia, 0);
-    own(ibc, 1);
-    const int64_t la = fa - 1 > 0 ? fa - 1 : 0, lb = fb - 1 > 0 ? fb - 1 : 0;
-    const int64_t len = max(fa - ea, fb - eb);
-    double sa = 0.0, sb = 0.0;
-    for (int64_t o = 0; o < len; o += U) {
-      double av[U], bv[U], ax[U], bx[U];
-      int32_t aj[U], bj[U];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += BD) {
+    const int64_t e0 = rp[i], e1 = rp[i + 1];
+    own(i);
+    double y = 0.0;
+    for (int64_t e = e0; e < e1; e += U) {
+      double a[U], xv[U];
+      int32_t j[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t xa = min(ea + o + u, la), xb = min(eb + o + u, lb);
-        av[u] = v[xa];
-        aj[u] = ci[xa];
-        bv[u] = v[xb];
-        bj[u] = ci[xb];
+        const int64_t ee = min(e + u, e1 - 1);
+        a[u] = v[ee];
+        j[u] = ci[ee];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        ax[u] = x[aj[u]];
-        bx[u] = x[bj[u]];
-      }
+      for (int u = 0; u < U; ++u) xv[u] = x[j[u]];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (ea + o + u < fa) sa += av[u] * ax[u];
-        if (eb + o + u < fb) sb += bv[u] * bx[u];
-      }
+      for (int u = 0; u < U; ++u)
+        if (e + u < e1) y += a[u] * xv[u];
     }
-    emit(ia, 0, sa);
-    if (hb) emit(ib, 1, sb);
+    emit(i, y);
   }
 }
 
@@ -1343,37 +1324,48 @@ __host__ __device__ constexpr int cg_np(int flexible) { return flexible ? 4 : 3;
 
 // w = A z ; partials gamma, delta, rho = r.r (, eps) ->
 // part[b*np*nc + np*cc + (0, 1, 2 (, 3))]
+// One column (slr_solve with one right-hand side): 512 threads per block,
+// one row per thread at 512 rows per block, for the loads in flight.  No
+// load waits for the column's state: an inactive column's w and partials
+// are never used.
+constexpr int CG_SPMV1_THREADS = 512;
+
+__global__ void __launch_bounds__(CG_SPMV1_THREADS) k_cg_spmv1(int64_t n, const int64_t *rp, const int32_t *ci,
+                                                                const double *v, KArgs K, int c0, int flexible) {
+  __shared__ double sh[4 * (CG_SPMV1_THREADS / 64)];
+  const int np = cg_np(flexible);
+  const double *Z = K.Z + (int64_t)c0 * K.ld, *R = K.R + (int64_t)c0 * K.ld, *S = K.S + (int64_t)c0 * K.ld;
+  double *W = K.Q + (int64_t)c0 * K.ld;
+  double g = 0.0, d = 0.0, rr = 0.0, ep = 0.0, zv = 0.0, rv = 0.0, sv = 0.0;
+  spmv_rows<8, CG_SPMV1_THREADS>(
+      n, rp, ci, v, Z,
+      [&](int64_t i) {
+        zv = Z[i];
+        rv = R[i];
+        if (flexible) sv = S[i];
+      },
+      [&](int64_t i, double w) {
+        W[i] = w;
+        g += rv * zv;
+        d += zv * w;
+        rr += rv * rv;
+        if (flexible) ep += zv * sv;
+      });
+  double t[4] = {g, d, rr, ep};
+  block_sums<4>(t, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < np; ++j) K.part[(int64_t)blockIdx.x * np + j] = t[j];
+}
+
+// Column tiles of TT (several right-hand sides, and every batch): each row's
+// entries are read once per tile, and a column's arithmetic (entry order,
+// row order, block sums) does not depend on the tile it falls in or on the
+// number of columns.
 template <int TT>
 __global__ void __launch_bounds__(RED_THREADS) k_cg_spmv(int64_t n, const int64_t *rp, const int32_t *ci,
-                                                          const double *v, KArgs K, int c0, int nc, int flexible) {
+                                                         const double *v, KArgs K, int c0, int nc, int flexible) {
   __shared__ double sh[4 * (RED_THREADS / 64)];
   const int np = cg_np(flexible);
-  if (TT == 1 && nc == 1) {
-    // no load waits for the column's state: an inactive column's w and
-    // partials are never used
-    const double *Z = K.Z + (int64_t)c0 * K.ld, *R = K.R + (int64_t)c0 * K.ld, *S = K.S + (int64_t)c0 * K.ld;
-    double *W = K.Q + (int64_t)c0 * K.ld;
-    double g = 0.0, d = 0.0, rr = 0.0, ep = 0.0, zv[2], rv[2], sv[2];
-    spmv_pair<8>(
-        n, rp, ci, v, Z,
-        [&](int64_t i, int h) {
-          zv[h] = Z[i];
-          rv[h] = R[i];
-          if (flexible) sv[h] = S[i];
-        },
-        [&](int64_t i, int h, double w) {
-          W[i] = w;
-          g += rv[h] * zv[h];
-          d += zv[h] * w;
-          rr += rv[h] * rv[h];
-          if (flexible) ep += zv[h] * sv[h];
-        });
-    double t[4] = {g, d, rr, ep};
-    block_sums<4>(t, sh);
-    if (threadIdx.x == 0)
-      for (int j = 0; j < np; ++j) K.part[(int64_t)blockIdx.x * np + j] = t[j];
-    return;
-  }
   for (int ct = 0; ct < nc; ct += TT) {
     const int nct = min(TT, nc - ct);
     bool act[TT];
@@ -1545,11 +1537,13 @@ void launch_cg(int op, int64_t n, const int64_t *rp, const int32_t *ci, const do
       hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(RED_THREADS), 0, st, K, c0, nc, it);
       break;
     case CG_SPMV:
-      if (nc == 1)
-        hipLaunchKernelGGL(k_cg_spmv<1>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc, flexible);
-      else
-        hipLaunchKernelGGL(k_cg_spmv<SPMV_T>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc,
-                           flexible);
+      if (nc == 1) {
+        hipLaunchKernelGGL(k_cg_spmv1, dim3(nb), dim3(CG_SPMV1_THREADS), 0, st, n, rp, ci, v, K, c0, flexible);
+        break;
+      }
+      [[fallthrough]];
+    case CG_SPMV_TILES:
+      hipLaunchKernelGGL(k_cg_spmv<SPMV_T>, dim3(nb), dim3(RED_THREADS), 0, st, n, rp, ci, v, K, c0, nc, flexible);
       break;
     case CG_UPDATE:
       hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RED_THREADS), 0, st, n, K, c0, nc, flexible, it);
