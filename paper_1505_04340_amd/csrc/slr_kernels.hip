@@ -2047,7 +2047,7 @@ void launch_div_scalar(int64_t n, const double *w, double *v, const double *scal
 // Outputs: eval (descending, all m), Y (m x K column-major), info (0).
 // scratch: 6 m K doubles.
 // ---------------------------------------------------------------------------
-constexpr int EIG_THREADS = 1024;
+constexpr int EIG_THREADS = 256;
 
 // Sturm counts (eigenvalues of T below x) at NPT points at once, from the
 // LDL^T pivots of T - x I: d_i = (a_i - x) - b_{i-1}^2 / d_{i-1}, a pivot
@@ -2196,6 +2196,72 @@ __device__ void cgs2_cols(double *x, int m, int K, double *h) {
   }
 }
 
+// Register forms of ortho_cols' Cholesky and triangular solve for
+// K <= ORTHO_KR (loops unrolled to ORTHO_KR, columns past K idle).
+constexpr int ORTHO_KR = 32;
+
+// v of lane l (l uniform across the wave)
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave 0: G (row-major K x K Gram matrix) = R^T R.  Lane l holds column l;
+// step j takes the pivot from lane j, writes row j of R over G's upper
+// triangle (R[j][l] = h_l / sqrt(pivot), as the left-looking form), reads
+// it back (a wave's LDS accesses take effect in order) and subtracts
+// R[j][q] R[j][l] from entry (q, l) for q > j, so every entry receives its
+// updates in ascending j.  A pivot at or below 1e-8 of the Gram diagonal
+// sets *flag.
+__device__ __forceinline__ void chol_regs(double *G, int K, int *flag) {
+  const int l = threadIdx.x & 63;
+  const bool own = l < K;
+  double c[ORTHO_KR];
+#pragma unroll
+  for (int q = 0; q < ORTHO_KR; ++q) c[q] = (own && q < K) ? G[q * K + l] : 0.0;
+  const double dg = own ? G[l * K + l] : 0.0;
+  bool ok = true;
+  for (int j = 0; j < K; ++j) {
+    double cj = 0.0;
+#pragma unroll
+    for (int q = 0; q < ORTHO_KR; ++q)
+      if (q == j) cj = c[q];
+    const double piv = readlane_d(cj, j);
+    const double gjj = readlane_d(dg, j);
+    if (!(piv > 1e-8 * gjj) || !(piv > 0.0)) {
+      ok = false;
+      break;
+    }
+    const double rs = 1.0 / sqrt(piv);
+    const double rjl = cj * rs;
+    if (own && l >= j) G[j * K + l] = rjl;
+#pragma unroll
+    for (int q = 0; q < ORTHO_KR; ++q)
+      if (q > j && q < K) c[q] -= G[j * K + q] * rjl;
+  }
+  if (!ok && l == 0) *flag = 1;
+}
+
+// One row w of W (K entries): w <- w R^{-1} by forward substitution in
+// column order, R (upper triangle of G) read by broadcast.
+__device__ __forceinline__ void solve_row_regs(double *w, const double *G, int K) {
+  double x[ORTHO_KR];
+#pragma unroll
+  for (int q = 0; q < ORTHO_KR; ++q) x[q] = q < K ? w[q] : 0.0;
+#pragma unroll
+  for (int j = 0; j < ORTHO_KR; ++j)
+    if (j < K) {
+      double v = x[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) v -= x[q] * G[q * K + j];
+      x[j] = v / G[j * K + j];
+    }
+#pragma unroll
+  for (int q = 0; q < ORTHO_KR; ++q)
+    if (q < K) w[q] = x[q];
+}
+
 // Orthonormalise the K columns of the row-major m x K block W in column
 // order by Cholesky QR, twice: G = W^T W, G = R^T R (R upper triangular),
 // W <- W R^{-1}.  In exact arithmetic this is the Gram-Schmidt result; the
@@ -2230,6 +2296,18 @@ __device__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *f
       G[j * K + i] = v;
     }
     __syncthreads();
+    if (K <= ORTHO_KR) {
+      // the same arithmetic in registers: wave 0 factors right-looking with
+      // lane l holding column l (entry (j, l) takes the same updates, in the
+      // same order, as the left-looking form below), then one row of W per
+      // thread
+      if (tid < 64) chol_regs(G, K, flag);
+      __syncthreads();
+      if (*flag) break;
+      for (int r = tid; r < m; r += nt) solve_row_regs(W + (int64_t)r * K, G, K);
+      __syncthreads();
+      continue;
+    }
     // Cholesky G = R^T R by wave 0, R in the upper triangle (row-major);
     // the lower triangle keeps the Gram matrix for the pivot test
     if (tid < 64) {
@@ -2426,33 +2504,43 @@ void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, doub
 // Ritz vectors: U64[i, q] = sum_j V[i, j] Y[j, q]  (V: s x m col-major,
 // Y: m x K col-major, U64 column-major s x k, k <= K).  Also writes the
 // storage copy U (column-major, rounded to TU).
-template <typename TU>
+// U = V Y (s x k), one row per thread, QT columns of Y per pass staged in
+// LDS; a row's V loads go out eight at a time and each output sums over j in
+// ascending order.
+template <typename TU, int QT>
 __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const double *V, int64_t ldv,
                                               const double *Y, double *U64, TU *U) {
-  extern __shared__ double ys[];  // m x 16 tile (m <= 1024: 128 KiB)
+  extern __shared__ double ys[];  // m x QT tile
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int q0 = 0; q0 < k; q0 += 16) {
-    const int nq = min(16, k - q0);
+  const int64_t ic = i < s ? i : s - 1;   // rows past the end load row s - 1 and store nothing
+  for (int q0 = 0; q0 < k; q0 += QT) {
+    const int nq = min(QT, k - q0);
     __syncthreads();
-    for (int t = threadIdx.x; t < m * nq; t += blockDim.x) {
+    for (int t = threadIdx.x; t < m * QT; t += blockDim.x) {
       const int q = t / m, j = t - q * m;
-      ys[j * 16 + q] = Y[j + (int64_t)(q0 + q) * m];
+      ys[j * QT + q] = q < nq ? Y[j + (int64_t)(q0 + q) * m] : 0.0;
     }
     __syncthreads();
-    if (i < s) {
-      double acc[16];
+    double acc[QT];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-      for (int j = 0; j < m; ++j) {
-        const double vj = V[i + (int64_t)j * ldv];
+    for (int q = 0; q < QT; ++q) acc[q] = 0.0;
+    for (int j0 = 0; j0 < m; j0 += 8) {
+      double vj[8];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += vj * ys[j * 16 + q];
-      }
-      for (int q = 0; q < nq; ++q) {
-        U64[i + (int64_t)(q0 + q) * s] = acc[q];
-        U[i + (int64_t)(q0 + q) * s] = round_store<TU>(acc[q]);
-      }
+      for (int u = 0; u < 8; ++u) vj[u] = V[ic + (int64_t)min(j0 + u, m - 1) * ldv];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < m)
+#pragma unroll
+          for (int q = 0; q < QT; ++q) acc[q] += vj[u] * ys[(j0 + u) * QT + q];
     }
+    if (i < s)
+#pragma unroll
+      for (int q = 0; q < QT; ++q)
+        if (q < nq) {
+          U64[i + (int64_t)(q0 + q) * s] = acc[q];
+          U[i + (int64_t)(q0 + q) * s] = round_store<TU>(acc[q]);
+        }
   }
 }
 
@@ -2460,11 +2548,17 @@ template <typename TU>
 void launch_ritz(int64_t s, int32_t m, int32_t k, const double *V, int64_t ldv, const double *Y, double *U64,
                  TU *U, hipStream_t st) {
   if (s == 0 || k == 0) return;
-  const size_t lds = sizeof(double) * m * 16;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void *)k_ritz<TU>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_ritz<TU>), dim3((unsigned)((s + 255) / 256)), dim3(256), lds, st, s, m, k, V, ldv, Y,
-                     U64, U);
+  // 32 columns per pass when the tile fits 64 KiB, else 16 (m <= 1024)
+  const bool wide = (size_t)m * 32 * sizeof(double) <= 65536;
+  const size_t lds = sizeof(double) * m * (wide ? 32 : 16);
+  const unsigned nb = (unsigned)((s + 255) / 256);
+  if (wide) {
+    hipLaunchKernelGGL((k_ritz<TU, 32>), dim3(nb), dim3(256), lds, st, s, m, k, V, ldv, Y, U64, U);
+  } else {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void *)k_ritz<TU, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_ritz<TU, 16>), dim3(nb), dim3(256), lds, st, s, m, k, V, ldv, Y, U64, U);
+  }
 }
 
 // storage copy of a row-major FP64 U (import path)
