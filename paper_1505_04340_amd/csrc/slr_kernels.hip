@@ -1753,26 +1753,45 @@ struct ProArgs {
 __device__ int pro_step(const ProArgs &P, bool writer) {
   __shared__ double bsh, red[16];
   __shared__ int dosh;
-  fold_waves(P.bpart, P.rb, 1, [&](int, double x) { bsh = sqrt(x); });
-  __syncthreads();
   const int j = P.j;
-  const double eps = 0x1p-52;
-  const double bj = bsh, aj = P.sc[0], bm = j > 0 ? P.beta[j - 1] : 0.0;
-  const double tnorm = fmax(P.tn[j], fabs(aj) + bj + bm);
-  const double e = eps * P.sqrt_s * tnorm;
   const double *W0 = P.om + (int64_t)(j % 3) * P.ld;
   const double *Wm = P.om + (int64_t)((j + 2) % 3) * P.ld;
   double *Wp = P.om + (int64_t)((j + 1) % 3) * P.ld;
+  // the recurrence inputs of entry l = threadIdx.x do not depend on beta_j:
+  // their loads go out before the fold
+  struct EstIn {
+    double up, prev, bl, al, w0, bl1, wl1;
+  };
+  auto est_in = [&](int l) {
+    EstIn q;
+    q.up = l + 1 == j ? 1.0 : W0[l + 1];
+    q.prev = l == j - 1 ? 1.0 : Wm[l];
+    q.bl = P.beta[l];
+    q.al = P.alpha[l];
+    q.w0 = W0[l];
+    q.bl1 = l > 0 ? P.beta[l - 1] : 0.0;
+    q.wl1 = l > 0 ? W0[l - 1] : 0.0;
+    return q;
+  };
+  const int l0 = threadIdx.x;
+  EstIn q0{};
+  if (l0 < j) q0 = est_in(l0);
+  const double aj = P.sc[0], bm = j > 0 ? P.beta[j - 1] : 0.0, tnj = P.tn[j];
+  fold_waves(P.bpart, P.rb, 1, [&](int, double x) { bsh = sqrt(x); });
+  __syncthreads();
+  const double eps = 0x1p-52;
+  const double bj = bsh;
+  const double tnorm = fmax(tnj, fabs(aj) + bj + bm);
+  const double e = eps * P.sqrt_s * tnorm;
   const double psi = bj > 0.0 ? e / bj : 1.0;
-  auto est = [&](int l) {
+  auto est_of = [&](int l, const EstIn &q) {
     if (l == j) return psi;
-    const double up = l + 1 == j ? 1.0 : W0[l + 1];
-    const double prev = l == j - 1 ? 1.0 : Wm[l];
-    double t = P.beta[l] * up + (P.alpha[l] - aj) * W0[l] - bm * prev;
-    if (l > 0) t += P.beta[l - 1] * W0[l - 1];
+    double t = q.bl * q.up + (q.al - aj) * q.w0 - bm * q.prev;
+    if (l > 0) t += q.bl1 * q.wl1;
     t += copysign(e, t);
     return bj > 0.0 ? t / bj : 1.0;
   };
+  auto est = [&](int l) { return l == j ? psi : est_of(l, l == l0 ? q0 : est_in(l)); };
   double m = 0.0;
   for (int l = threadIdx.x; l <= j; l += blockDim.x) m = fmax(m, fabs(est(l)));
   m = wave_allmax(m);
@@ -2456,7 +2475,16 @@ __global__ void __launch_bounds__(EIG_THREADS) k_eig_ortho(int m, int K, double 
   const int tid = threadIdx.x, nt = blockDim.x;
   double *W = xs_lds ? xl : X;
   if (xs_lds) {
-    for (int i = tid; i < m * K; i += nt) xl[i] = X[i];
+    // eight loads per thread in flight
+    const int mk = m * K;
+    for (int i0 = tid; i0 < mk; i0 += 8 * nt) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = X[min(i0 + u * nt, mk - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u * nt < mk) xl[i0 + u * nt] = t[u];
+    }
     __syncthreads();
   }
   ortho_cols(W, m, K, G, h, &flag);
@@ -2510,7 +2538,7 @@ void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, doub
 template <typename TU, int QT>
 __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const double *V, int64_t ldv,
                                               const double *Y, double *U64, TU *U) {
-  extern __shared__ double ys[];  // m x QT tile
+  extern __shared__ __align__(16) double ys[];  // m x QT tile
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ic = i < s ? i : s - 1;   // rows past the end load row s - 1 and store nothing
   for (int q0 = 0; q0 < k; q0 += QT) {
@@ -2530,9 +2558,15 @@ __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const dou
       for (int u = 0; u < 8; ++u) vj[u] = V[ic + (int64_t)min(j0 + u, m - 1) * ldv];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (j0 + u < m)
+        if (j0 + u < m) {
+          const double2 *yr = reinterpret_cast<const double2 *>(ys + (j0 + u) * QT);
 #pragma unroll
-          for (int q = 0; q < QT; ++q) acc[q] += vj[u] * ys[(j0 + u) * QT + q];
+          for (int q = 0; q < QT / 2; ++q) {
+            const double2 y = yr[q];
+            acc[2 * q] += vj[u] * y.x;
+            acc[2 * q + 1] += vj[u] * y.y;
+          }
+        }
     }
     if (i < s)
 #pragma unroll
