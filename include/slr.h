@@ -145,7 +145,8 @@ typedef struct {
 } slr_solve_opts;
 
 typedef struct {
-  int32_t iters;          /* products with A                                 */
+  int32_t iters;          /* iterations: updates of x (CG, FCG), Arnoldi     */
+                          /* steps (FGMRES)                                  */
   int32_t status;         /* SLR_OK or SLR_ERR_NOCONV                        */
   double relres;          /* final true ||b - A x|| / ||b||, FP64            */
 } slr_solve_info;
