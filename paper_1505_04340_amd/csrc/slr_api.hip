@@ -82,7 +82,8 @@ struct ApplyWS {
   int32_t k = 0;              // rank the rank-k scratch is sized for
   double *W = nullptr;        // s x cap interface temporary
   double *W2 = nullptr;       // second s x cap interface temporary
-  double *lr_part = nullptr;  // lr_nblk x cap x k
+  double *lr_part = nullptr;  // nblk x cap x k
+  int32_t nblk = 0;            // rank-k partial chunks lr_part was sized for
   double *cbuf = nullptr;     // k x cap
   unsigned int *counter = nullptr;
   DevPool pool;
@@ -115,6 +116,7 @@ struct slr_ctx {
   bool c_one_wg = true;
   bool c_two_level = false;     // interface schedules of <= 2 levels: one launch per sweep
   int32_t b_threads = 1024;
+  int32_t n_cu = 256;           // compute units of the device
   int32_t b_max_m = 0, b_max_lev = 0, b_max_level_bytes = 0;
   int64_t b_data_bytes = 0;
   size_t lds_limit = 65536;
@@ -126,7 +128,7 @@ struct slr_ctx {
   double *U64 = nullptr;        // s x k column-major, FP64 (export)
   double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
-  int32_t lr_nblk = 256;       // group chunks of the row-major rank-k partials
+  int32_t lr_nblk = 256;       // group chunks of the row-major rank-k partials (set with U_k)
   int32_t lrm_nblk = 512;      // row chunks of the matrix-core rank-k partials
   // BF16 U_k always takes the matrix-core path, so a column's arithmetic
   // never depends on how many columns share the launch
@@ -204,18 +206,20 @@ namespace {
 constexpr int RED_NBLK = 512;   // blocks of the deterministic reductions
 
 int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
-  if (w.cap >= nrhs && w.W && w.k >= std::max(c->k, 1)) return SLR_OK;
+  const int32_t nb = std::max(c->lr_nblk, c->lrm_nblk);
+  if (w.cap >= nrhs && w.W && w.k >= std::max(c->k, 1) && w.nblk >= nb) return SLR_OK;
   w.pool.release();
   int32_t cap = std::max<int32_t>(nrhs, 1);
   w.W = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
   w.W2 = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
-  w.lr_part = w.pool.alloc<double>((size_t)std::max(c->lr_nblk, c->lrm_nblk) * cap * std::max(c->k, 1));
+  w.lr_part = w.pool.alloc<double>((size_t)nb * cap * std::max(c->k, 1));
   w.cbuf = w.pool.alloc<double>((size_t)cap * std::max(c->k, 1));
   w.counter = w.pool.alloc<unsigned int>(16);
   if (!w.W || !w.W2 || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
   HIPCHK(hipMemset(w.counter, 0, 16 * sizeof(unsigned int)));
   w.cap = cap;
   w.k = std::max(c->k, 1);
+  w.nblk = nb;
   return SLR_OK;
 }
 
@@ -224,13 +228,14 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
 // 16 (max_lev + 1).  R is the largest value (<= nrhs, <= 16) that still
 // leaves a staging buffer of at least max(largest level, min(24 KiB,
 // largest sweep)).  Returns false when not even R = 1 fits.
-bool b_lds_plan(const slr_ctx *c, int32_t nrhs, size_t tc_bytes, int32_t &R, int32_t &stage) {
+bool b_lds_plan(const slr_ctx *c, int32_t nrhs, size_t tc_bytes, int32_t &R, int32_t &stage, size_t limit = 0) {
+  if (limit == 0) limit = c->lds_limit;
   const int64_t fixed = 16 * (int64_t)(c->b_max_lev + 1) + kStageDummyBytes;
   // the fixed-width path double-buffers the stage: each half holds a level
   const int64_t need = std::max<int64_t>(2 * (int64_t)c->b_max_level_bytes, std::min<int64_t>(24576, c->b_data_bytes));
   for (int32_t r = std::min<int32_t>(std::max(nrhs, 1), 16); r >= 1; --r) {
     const int64_t xb = pad16h((int64_t)tc_bytes * (std::max(c->b_max_m, 1) * r + 1));
-    const int64_t rest = ((int64_t)c->lds_limit - fixed - xb) & ~int64_t(15);
+    const int64_t rest = ((int64_t)limit - fixed - xb) & ~int64_t(15);
     if (rest >= need) {
       R = r;
       stage = (int32_t)std::min<int64_t>(rest, pad16h(c->b_data_bytes));
@@ -240,17 +245,26 @@ bool b_lds_plan(const slr_ctx *c, int32_t nrhs, size_t tc_bytes, int32_t &R, int
   return false;
 }
 
+// With more subdomains than compute units and one right-hand side, the B
+// kernel runs two workgroups per CU: half the threads (one solver wave,
+// the rest staging) and at most half the LDS each, so that the second
+// round of subdomains runs beside the first instead of after it.
 template <typename TS, typename TC>
 int run_bsolve(slr_ctx *c, const BlockArrays<TS> &B, const BArgs &a0, hipStream_t st) {
   BArgs a = a0;
   int32_t R = 0, stage = 0;
-  if (!b_lds_plan(c, a.nrhs, sizeof(TC), R, stage))
+  int32_t threads = c->b_threads;
+  const bool pair = a.nrhs == 1 && (int64_t)c->p > (int64_t)c->n_cu;
+  if (pair && b_lds_plan(c, a.nrhs, sizeof(TC), R, stage, c->lds_limit / 2)) {
+    threads = c->b_threads / 2;
+  } else if (!b_lds_plan(c, a.nrhs, sizeof(TC), R, stage)) {
     return fail(SLR_ERR_ARG, "a subdomain does not fit the LDS of one workgroup");
+  }
   a.R = R;
   a.stage_bytes = stage;
   const size_t lds = (size_t)stage + kStageDummyBytes + pad16h((int64_t)sizeof(TC) * (c->b_max_m * R + 1)) +
                     16 * (size_t)(c->b_max_lev + 1);
-  launch_bsolve<TS, TC>(B, c->p, a, c->b_threads, lds, st);
+  launch_bsolve<TS, TC>(B, c->p, a, threads, lds, st);
   return SLR_OK;
 }
 
@@ -390,7 +404,11 @@ int upload_lowrank_T(slr_ctx *c, hipStream_t st) {
 template <typename TU>
 int upload_lowrank_rm(slr_ctx *c, hipStream_t st) {
   int32_t ldk;
-  const int64_t n = lr_rm_groups<TU>(c->s, c->k, ldk) * 64 * (16 / (int64_t)sizeof(TU));
+  const int64_t ng = lr_rm_groups<TU>(c->s, c->k, ldk);
+  const int64_t n = ng * 64 * (16 / (int64_t)sizeof(TU));
+  // chunks of U^T w: about 128 row groups each (a few rounds of loads per
+  // wave), at least 256 and at most 2048 (the fold reads chunks x k)
+  c->lr_nblk = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(256, ng / 128));
   TU *U = c->lrpool.alloc<TU>((size_t)n);
   if (!U) return fail(SLR_ERR_OOM, "U storage");
   launch_lr_to_rm<TU>(c->U64, c->s, c->k, U, st);
@@ -1014,6 +1032,13 @@ const char *slr_strerror(int code) {
 
 const char *slr_last_error(void) { return g_err.c_str(); }
 
+static int device_cu_count(void) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+  return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+}
+
 int slr_device_lds_bytes(void) {
   int dev = 0;
   hipDeviceProp_t prop;
@@ -1063,6 +1088,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->fact_prec = o->fact_prec;
   c->uk_prec = o->uk_prec;
   c->lds_limit = (size_t)slr_device_lds_bytes();
+  c->n_cu = device_cu_count();
   c->perm_h = H.perm;
   auto destroy_fail = [&](int code) {
     slr_destroy(c);
