@@ -1,6 +1,7 @@
 """Benchmark of the SLR hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form both|fp64] [--no-serve] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form both|fp64] [--no-serve] [--no-large]
+                    [--no-cpu-baseline]
 
 Workload: 3-D 7-point Laplacian on a 64^3 grid (n = 262,144), 4x4x4 box
 decomposition (64 subdomains), IC(0) factors of the B_i and of C, rank
@@ -12,6 +13,11 @@ of (U_k, Lambda_k, theta) on H with the resident factors, then the
 preconditioned Krylov solve (every iteration: SpMV, BLAS-1, the SLR apply
 with its two batched B solves, interface sweeps and rank-k block).  Host
 factorisation is setup and is not timed.  Prints one JSON line.
+
+Beside the step rate the line carries the 64^3 apply and B-kernel
+rooflines, the serving comparison, the oracle's rate on a host core and
+(large_apply) the apply bandwidth on the shifted 128^3 workload, where the
+apply is bound by bytes rather than by dependency chains.
 """
 from __future__ import annotations
 
@@ -167,6 +173,34 @@ def measure_refactor(P, pr, form, v0, reps=5):
 SERVE_MAXIT = 1000
 
 
+def large_apply(P, torch, reps=20):
+    """Apply bandwidth on the shifted 3-D 128^3 workload (n = 2.1M, 512
+    subdomains, ILDL^T(0) B_i, IC(0) C, k = 64 from 320 Lanczos steps), one
+    right-hand side: the problem where the apply's bytes, not its dependency
+    chains, set the time.  Both storage forms; algorithmic bytes as for the
+    64^3 apply."""
+    import slr_inputs as si
+    pr = si.make_config("shifted3d_128")
+    out = {"workload": "shifted 3-D 7-point Laplacian 128^3 (n=2097152), 8x8x8 boxes (512 subdomains), "
+                       "ILDL^T(0) B_i, IC(0) C (multicolour), k=64 from 320 Lanczos steps, 1 RHS"}
+    for name, fp, up in (("fp64", "fp64", "fp64"), ("fp32", "fp32", "fp32")):
+        G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+                  c_fact=pr.c_fact, c_order="multicolor", fact_prec=fp, uk_prec=up, v0=pr.v0())
+        torch.cuda.synchronize()
+        info = G.query()
+        ms = G.time_kernel("apply", 1, reps)
+        bf = 8 if fp == "fp64" else 4
+        bu = 8 if up == "fp64" else 4
+        ab = apply_bytes(info, 1, bf, bu, info["k"])
+        gbs = ab / (ms * 1e-3) / 1e9
+        out[name] = {"apply_us": round(ms * 1e3, 2), "algorithmic_bytes": int(ab), "GBs": round(gbs, 1),
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"[bench:large] {name}: apply {ms * 1e3:.1f} us = {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of peak)")
+        del G
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(P, torch, n_req, seed=13):
     """Continuous batching (mixed form, flexible CG) vs one-request-at-a-time
     plain FP64 PCG over four resident preconditioners."""
@@ -250,6 +284,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 128^3 apply-bandwidth measurement")
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--config", default="lap3d_64")
     ap.add_argument("--form", choices=("both", "fp64"), default="both",
@@ -310,9 +345,11 @@ def main():
         "forms": forms,
         "refactor": measure_refactor(P, pr, FORMS["fp64"], v0),
     }
+    del G
+    torch.cuda.empty_cache()
+    if not args.no_large:
+        out["large_apply"] = large_apply(P, torch)
     if not args.no_serve:
-        del G
-        torch.cuda.empty_cache()
         out["serving"] = serving(P, torch, args.serve_requests)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle, 1 thread) ...")
