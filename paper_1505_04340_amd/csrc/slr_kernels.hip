@@ -2215,51 +2215,39 @@ __device__ void cgs2_cols(double *x, int m, int K, double *h) {
   }
 }
 
-// Register forms of ortho_cols' Cholesky and triangular solve for
-// K <= ORTHO_KR (loops unrolled to ORTHO_KR, columns past K idle).
+// ortho_cols' Cholesky (LDS, all threads) and its triangular solve with a
+// row of W in registers for K <= ORTHO_KR (loops unrolled to ORTHO_KR,
+// columns past K idle).
 constexpr int ORTHO_KR = 32;
 
-// v of lane l (l uniform across the wave)
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
-// Wave 0: G (row-major K x K Gram matrix) = R^T R.  Lane l holds column l;
-// step j takes the pivot from lane j, writes row j of R over G's upper
-// triangle (R[j][l] = h_l / sqrt(pivot), as the left-looking form), reads
-// it back (a wave's LDS accesses take effect in order) and subtracts
-// R[j][q] R[j][l] from entry (q, l) for q > j, so every entry receives its
-// updates in ascending j.  A pivot at or below 1e-8 of the Gram diagonal
-// sets *flag.
-__device__ __forceinline__ void chol_regs(double *G, int K, int *flag) {
-  const int l = threadIdx.x & 63;
-  const bool own = l < K;
-  double c[ORTHO_KR];
-#pragma unroll
-  for (int q = 0; q < ORTHO_KR; ++q) c[q] = (own && q < K) ? G[q * K + l] : 0.0;
-  const double dg = own ? G[l * K + l] : 0.0;
-  bool ok = true;
+// All threads: G (row-major K x K Gram matrix) = R^T R, right-looking in
+// LDS.  Step j takes the pivot (the updated G[j][j]), writes row j of R over
+// row j of G (R[j][l] = h_l / sqrt(pivot), h_l the updated entry, as the
+// left-looking form) and subtracts R[j][q] R[j][l] from every entry (q, l)
+// with j < q <= l, so each entry receives its updates in ascending j.  dg (K
+// doubles) keeps the Gram diagonal for the pivot test; a pivot at or below
+// 1e-8 of it sets *flag.
+__device__ __forceinline__ void chol_lds(double *G, int K, double *dg, int *flag) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = tid; l < K; l += nt) dg[l] = G[l * K + l];
+  __syncthreads();
   for (int j = 0; j < K; ++j) {
-    double cj = 0.0;
-#pragma unroll
-    for (int q = 0; q < ORTHO_KR; ++q)
-      if (q == j) cj = c[q];
-    const double piv = readlane_d(cj, j);
-    const double gjj = readlane_d(dg, j);
-    if (!(piv > 1e-8 * gjj) || !(piv > 0.0)) {
-      ok = false;
-      break;
+    const double piv = G[j * K + j];
+    if (!(piv > 1e-8 * dg[j]) || !(piv > 0.0)) {
+      if (tid == 0) *flag = 1;
+      return;   // every thread takes the same exit
     }
     const double rs = 1.0 / sqrt(piv);
-    const double rjl = cj * rs;
-    if (own && l >= j) G[j * K + l] = rjl;
-#pragma unroll
-    for (int q = 0; q < ORTHO_KR; ++q)
-      if (q > j && q < K) c[q] -= G[j * K + q] * rjl;
+    __syncthreads();
+    for (int l = j + tid; l < K; l += nt) G[j * K + l] = G[j * K + l] * rs;
+    __syncthreads();
+    const int nq = K - 1 - j;
+    for (int p = tid; p < nq * nq; p += nt) {
+      const int q = j + 1 + p / nq, l = j + 1 + p % nq;
+      if (q <= l) G[q * K + l] -= G[j * K + q] * G[j * K + l];
+    }
+    __syncthreads();
   }
-  if (!ok && l == 0) *flag = 1;
 }
 
 // One row w of W (K entries): w <- w R^{-1} by forward substitution in
@@ -2289,7 +2277,7 @@ __device__ __forceinline__ void solve_row_regs(double *w, const double *G, int K
 // the column's squared norm) sends the block to Gram-Schmidt twice instead.
 // G: K*K doubles of LDS, h: K + 1, flag: one int of LDS.
 __device__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *flag) {
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  const int tid = threadIdx.x, nt = blockDim.x;
   for (int pass = 0; pass < 2; ++pass) {
     if (tid == 0) *flag = 0;
     // Gram matrix, upper triangle by pairs (i <= j), mirrored
@@ -2315,44 +2303,21 @@ __device__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *f
       G[j * K + i] = v;
     }
     __syncthreads();
-    if (K <= ORTHO_KR) {
-      // the same arithmetic in registers: wave 0 factors right-looking with
-      // lane l holding column l (entry (j, l) takes the same updates, in the
-      // same order, as the left-looking form below), then one row of W per
-      // thread
-      if (tid < 64) chol_regs(G, K, flag);
-      __syncthreads();
-      if (*flag) break;
-      for (int r = tid; r < m; r += nt) solve_row_regs(W + (int64_t)r * K, G, K);
-      __syncthreads();
-      continue;
-    }
-    // Cholesky G = R^T R by wave 0, R in the upper triangle (row-major);
-    // the lower triangle keeps the Gram matrix for the pivot test
-    if (tid < 64) {
-      for (int j = 0; j < K; ++j) {
-        for (int l = j + lane; l < K; l += 64) {
-          double v = G[j * K + l];
-          for (int q = 0; q < j; ++q) v -= G[q * K + j] * G[q * K + l];
-          h[l] = v;
-        }
-        const double piv = h[j];
-        if (!(piv > 1e-8 * G[j * K + j]) || !(piv > 0.0)) {
-          if (lane == 0) *flag = 1;
-          break;
-        }
-        const double rs = 1.0 / sqrt(piv);
-        for (int l = j + lane; l < K; l += 64) G[j * K + l] = h[l] * rs;
-      }
-    }
+    // Cholesky G = R^T R, R in the upper triangle (row-major)
+    chol_lds(G, K, h, flag);
     __syncthreads();
     if (*flag) break;
-    // W <- W R^{-1}, one row per thread
-    for (int r = tid; r < m; r += nt) {
-      for (int j = 0; j < K; ++j) {
-        double v = W[r * K + j];
-        for (int q = 0; q < j; ++q) v -= W[r * K + q] * G[q * K + j];
-        W[r * K + j] = v / G[j * K + j];
+    // W <- W R^{-1}, one row per thread, by forward substitution in column
+    // order (the row in registers when K <= ORTHO_KR)
+    if (K <= ORTHO_KR) {
+      for (int r = tid; r < m; r += nt) solve_row_regs(W + (int64_t)r * K, G, K);
+    } else {
+      for (int r = tid; r < m; r += nt) {
+        for (int j = 0; j < K; ++j) {
+          double v = W[r * K + j];
+          for (int q = 0; q < j; ++q) v -= W[r * K + q] * G[q * K + j];
+          W[r * K + j] = v / G[j * K + j];
+        }
       }
     }
     __syncthreads();
