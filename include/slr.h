@@ -140,7 +140,9 @@ typedef struct {
   int32_t method;         /* SLR_PCG | SLR_FCG (flexible CG) | SLR_FGMRES   */
   int32_t restart;        /* FGMRES restart length (default 40, Sec. 6)      */
   int32_t maxit;          /* default 300 (Sec. 6)                            */
-  int32_t check_every;    /* host convergence poll period in iterations      */
+  int32_t check_every;    /* CG / FCG: most iterations between host polls of
+                             convergence (default 8; shorter near the end,
+                             from the residual's decay)                    */
   double rtol;            /* ||r_j|| <= rtol ||b|| (default 1e-8, Sec. 6)     */
 } slr_solve_opts;
 

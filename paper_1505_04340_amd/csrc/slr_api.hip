@@ -175,6 +175,11 @@ struct slr_ctx {
   KState *sst = nullptr;
   double *spart = nullptr, *spart2 = nullptr;
   unsigned int *scnt = nullptr;
+  // convergence polls of CG / FCG: two pinned slots of scap states each, and
+  // the events that mark their copies done
+  KState *hst = nullptr;
+  int32_t hcap = 0;
+  hipEvent_t pev[2] = {nullptr, nullptr};
 };
 
 struct slr_batch {
@@ -1372,6 +1377,9 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
 void slr_destroy(slr_ctx *c) {
   if (!c) return;
   if (c->rf.stage) (void)hipHostFree(c->rf.stage);
+  if (c->hst) (void)hipHostFree(c->hst);
+  for (hipEvent_t e : c->pev)
+    if (e) (void)hipEventDestroy(e);
   c->rf.pool.release();
   c->pool.release();
   c->ws.pool.release();
@@ -1514,17 +1522,80 @@ int solve_cg(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const
   launch_permute(n, c->perm, b_dev, n, c->sB, n, nrhs, false, st);
   launch_axpby(n, nrhs, 1.0, c->sB, n, 0.0, c->sR, n, st);
   if ((rc = cg_start(c, K, 0, nrhs, flexible, 1, st))) return rc;
-  std::vector<KState> h(nrhs);
-  const int every = std::max(1, so.check_every);
-  for (int it = 0; it < so.maxit; it += every) {
-    for (int j = 0; j < every && it + j < so.maxit; ++j)
-      if ((rc = cg_iter(c, c->ws, K, 0, nrhs, flexible, it + j + 1, st))) return rc;
-    HIPCHK(hipMemcpyAsync(h.data(), c->sst, sizeof(KState) * nrhs, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    bool any = false;
-    for (auto &x : h) any |= x.active != 0;
-    if (!any) break;
+  if (c->hcap < nrhs) {
+    if (c->hst) (void)hipHostFree(c->hst);
+    c->hst = nullptr;
+    c->hcap = 0;
+    HIPCHK(hipHostMalloc((void **)&c->hst, sizeof(KState) * 2 * (size_t)nrhs, hipHostMallocDefault));
+    c->hcap = nrhs;
   }
+  for (hipEvent_t &e : c->pev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // Iterations launched after a column has converged still run the whole
+  // preconditioner (only the Krylov update is gated), and a poll that finds
+  // the stream empty lets the device idle until the next launch.  So the
+  // state is copied to pinned memory after each block of iterations, the
+  // next block is queued before the host waits for the previous copy, and
+  // block lengths follow what the residual's decay between polls predicts:
+  // queued work stops short of the predicted end and shrinks towards it.
+  // The iterates do not depend on the block lengths.
+  const int every = std::max(1, so.check_every);
+  const double unknown = 1e30;
+  std::vector<double> rr_prev(nrhs, -1.0);
+  int launched = 0, npoll = 0, poll_it[2] = {0, 0};
+  auto queue_block = [&](int nb) -> int {
+    for (int j = 0; j < nb; ++j) {
+      const int r = cg_iter(c, c->ws, K, 0, nrhs, flexible, launched + j + 1, st);
+      if (r) return r;
+    }
+    launched += nb;
+    const int sl = npoll & 1;
+    poll_it[sl] = launched;
+    HIPCHK(hipMemcpyAsync(c->hst + (size_t)sl * c->hcap, c->sst, sizeof(KState) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(c->pev[sl], st));
+    ++npoll;
+    return SLR_OK;
+  };
+  auto block_len = [&](double ahead) {
+    return std::min(so.maxit - launched, (int)std::min<double>(every, std::floor(0.8 * ahead)));
+  };
+  if ((rc = queue_block(std::min(every, so.maxit)))) return rc;
+  // need: iterations still wanted after the newest poll read, it_read
+  double need = unknown;
+  int it_read = 1;  // r_0 = b (x starts at zero) is tested by iteration 1
+  for (int seen = 0;; ++seen) {
+    // poll `seen` is the newest queued; queue one more block behind it
+    int nb = block_len(need - (launched - it_read));
+    if (nb > 0 && (rc = queue_block(nb))) return rc;
+    const int sl = seen & 1;
+    HIPCHK(hipEventSynchronize(c->pev[sl]));
+    const KState *h = c->hst + (size_t)sl * c->hcap;
+    const int it = poll_it[sl];  // the update of iteration it tested r_{it-1}
+    bool any = false;
+    double nd = 0.0;
+    for (int j = 0; j < nrhs; ++j) {
+      const KState &x = h[j];
+      if (!x.active) continue;
+      any = true;
+      const double prev = rr_prev[j] < 0.0 ? x.bb : rr_prev[j];
+      const double tol = K.rtol2 * x.bb;
+      double est = unknown;
+      if (x.rr > tol && x.rr < prev && tol > 0.0 && it > it_read)
+        est = std::log(tol / x.rr) / (std::log(x.rr / prev) / (it - it_read));
+      nd = std::max(nd, est);
+      rr_prev[j] = x.rr;
+    }
+    if (!any) break;
+    need = nd;
+    it_read = it;
+    if (npoll == seen + 1) {
+      // nothing queued behind this poll
+      if (launched >= so.maxit) break;
+      nb = std::max(1, block_len(need));
+      if ((rc = queue_block(nb))) return rc;
+    }
+  }
+  std::vector<KState> h(nrhs);
   // true residual ||b - A x|| / ||b|| in FP64
   launch_spmv(n, c->a_rp, c->a_ci, c->a_v, c->sX, n, c->sQ, n, nrhs, st);
   launch_relres(n, c->sB, n, c->sQ, n, K, 0, nrhs, st);
