@@ -69,6 +69,41 @@ struct DevPool {
   }
 };
 
+// Sub-allocations (256-byte aligned) from a device buffer that its owner
+// keeps between calls.  A request that does not fit gets an allocation of
+// its own, freed at release(); release() then regrows the kept buffer to
+// the whole size seen, so that the next call with the same sizes allocates
+// nothing.  Contents are not preserved between calls.
+struct Arena {
+  char *&base;
+  size_t &cap;
+  size_t used = 0, want = 0;
+  DevPool extra;
+  Arena(char *&b, size_t &c) : base(b), cap(c) {}
+  template <typename T>
+  T *alloc(size_t n) {
+    if (n == 0) n = 1;
+    const size_t b = (n * sizeof(T) + 255) & ~(size_t)255;
+    want += b;
+    if (used + b <= cap) {
+      T *p = (T *)(base + used);
+      used += b;
+      return p;
+    }
+    return extra.alloc<T>(n);
+  }
+  void release() {
+    extra.release();
+    if (want > cap) {
+      if (base) (void)hipFree(base);
+      base = nullptr;
+      cap = 0;
+      if (hipMalloc((void **)&base, want) == hipSuccess) cap = want;
+    }
+    used = want = 0;
+  }
+};
+
 template <typename TS>
 std::vector<TS> conv(const std::vector<double> &v) {
   std::vector<TS> o(v.size());
@@ -180,6 +215,9 @@ struct slr_ctx {
   KState *hst = nullptr;
   int32_t hcap = 0;
   hipEvent_t pev[2] = {nullptr, nullptr};
+  // scratch of the Lanczos build, kept between builds
+  char *lz_base = nullptr;
+  size_t lz_cap = 0;
 };
 
 struct slr_batch {
@@ -479,7 +517,7 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   const bool lam_s = c->opts.theta_mode == SLR_THETA_LAMBDA_S;
   const int32_t nb = k0 + steps;   // basis columns: kept vectors, then the Lanczos vectors
   const bool pro = c->opts.reorth == SLR_REORTH_PARTIAL && k0 == 0;
-  DevPool tmp;
+  Arena tmp(c->lz_base, c->lz_cap);
   double *V = tmp.alloc<double>((size_t)s * nb);
   double *Wl = tmp.alloc<double>(s);
   double *T = tmp.alloc<double>(s);
@@ -1378,6 +1416,7 @@ void slr_destroy(slr_ctx *c) {
   if (!c) return;
   if (c->rf.stage) (void)hipHostFree(c->rf.stage);
   if (c->hst) (void)hipHostFree(c->hst);
+  if (c->lz_base) (void)hipFree(c->lz_base);
   for (hipEvent_t e : c->pev)
     if (e) (void)hipEventDestroy(e);
   c->rf.pool.release();
@@ -1393,7 +1432,8 @@ int slr_query(const slr_ctx *c, slr_info *info) {
   if (!c || !info) return fail(SLR_ERR_ARG, "null");
   *info = c->info;
   info->device_bytes =
-      c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes + c->rf.pool.bytes;
+      c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes + c->rf.pool.bytes +
+      (int64_t)c->lz_cap;
   return SLR_OK;
 }
 
