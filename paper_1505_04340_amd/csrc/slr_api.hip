@@ -215,6 +215,9 @@ struct slr_ctx {
   KState *hst = nullptr;
   int32_t hcap = 0;
   hipEvent_t pev[2] = {nullptr, nullptr};
+  // FGMRES: per-step (converged, breakdown) flags of a cycle, pinned
+  int *hfl = nullptr;
+  int32_t hfl_cap = 0;
   // scratch of the Lanczos build, kept between builds
   char *lz_base = nullptr;
   size_t lz_cap = 0;
@@ -1417,6 +1420,7 @@ void slr_destroy(slr_ctx *c) {
   if (c->rf.stage) (void)hipHostFree(c->rf.stage);
   if (c->hst) (void)hipHostFree(c->hst);
   if (c->lz_base) (void)hipFree(c->lz_base);
+  if (c->hfl) (void)hipHostFree(c->hfl);
   for (hipEvent_t e : c->pev)
     if (e) (void)hipEventDestroy(e);
   c->rf.pool.release();
@@ -1552,6 +1556,12 @@ int cg_iter(slr_ctx *c, ApplyWS &w, const KArgs &K, int32_t c0, int32_t nc, int 
   return SLR_OK;
 }
 
+int poll_events(slr_ctx *c) {
+  for (hipEvent_t &e : c->pev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return SLR_OK;
+}
+
 int solve_cg(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const slr_solve_opts &so,
              slr_solve_info *info, hipStream_t st) {
   int rc = solve_ws(c, nrhs);
@@ -1569,8 +1579,7 @@ int solve_cg(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const
     HIPCHK(hipHostMalloc((void **)&c->hst, sizeof(KState) * 2 * (size_t)nrhs, hipHostMallocDefault));
     c->hcap = nrhs;
   }
-  for (hipEvent_t &e : c->pev)
-    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if ((rc = poll_events(c))) return rc;
   // Iterations launched after a column has converged still run the whole
   // preconditioner (only the Krylov update is gated), and a poll that finds
   // the stream empty lets the device idle until the next launch.  So the
@@ -1675,7 +1684,7 @@ int solve_fgmres(slr_ctx *c, const double *b_dev, double *x_dev, const slr_solve
   double *sc = tmp.alloc<double>(4);
   double *part = tmp.alloc<double>((size_t)RED_NBLK * (mr + 1));
   unsigned int *cnt = tmp.alloc<unsigned int>(4);
-  int *flags = tmp.alloc<int>(2);
+  int *flags = tmp.alloc<int>(2 * (size_t)mr);
   if (!V || !Zb || !Bd || !X || !T || !Hm || !h1 || !h2 || !cs || !sn || !g || !y || !sc || !part || !cnt ||
       !flags) {
     tmp.release();
@@ -1686,6 +1695,15 @@ int solve_fgmres(slr_ctx *c, const double *b_dev, double *x_dev, const slr_solve
     tmp.release();
     return code;
   };
+  if ((rc = poll_events(c))) return bail(rc);
+  if (c->hfl_cap < mr) {
+    if (c->hfl) (void)hipHostFree(c->hfl);
+    c->hfl = nullptr;
+    c->hfl_cap = 0;
+    if (hipHostMalloc((void **)&c->hfl, sizeof(int) * 2 * (size_t)mr, hipHostMallocDefault) != hipSuccess)
+      return bail(fail(SLR_ERR_HIP, "FGMRES flags"));
+    c->hfl_cap = mr;
+  }
   HIPCHK(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned int), st));
   HIPCHK(hipMemsetAsync(X, 0, sizeof(double) * n, st));
   launch_permute(n, c->perm, b_dev, n, Bd, n, 1, false, st);
@@ -1704,25 +1722,40 @@ int solve_fgmres(slr_ctx *c, const double *b_dev, double *x_dev, const slr_solve
     launch_multidot(n, 1, T, n, T, part, RED_NBLK, sc, cnt, st);
     launch_scale_inv_sqrt(n, T, V, sc, st);
     launch_gmres_g0(mr + 1, sc, g, st);
-    int jj = 0;
-    for (int j = 0; j < mr; ++j) {
+    // Step j's flags go to pinned memory, and step j + 1 is queued before
+    // the host waits for them, so the device does not idle at each test.
+    // A step queued past the end of a cycle writes only basis, Hessenberg
+    // and rotation entries beyond the jj that the solve and update use.
+    auto queue_step = [&](int j) -> int {
       double *vj = V + (int64_t)j * n, *zj = Zb + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
-      if ((rc = apply_dd(c, c->ws, vj, n, zj, n, 1, st))) return bail(rc);
+      const int r = apply_dd(c, c->ws, vj, n, zj, n, 1, st);
+      if (r) return r;
       launch_spmv(n, c->a_rp, c->a_ci, c->a_v, zj, n, w, n, 1, st);
       launch_multidot(n, j + 1, V, n, w, part, RED_NBLK, h1, cnt, st);
       launch_gemv_sub(n, j + 1, V, n, h1, w, nullptr, st);
       launch_multidot(n, j + 1, V, n, w, part, RED_NBLK, h2, cnt, st);
       launch_gemv_sub(n, j + 1, V, n, h2, w, nullptr, st);
       launch_multidot(n, 1, w, n, w, part, RED_NBLK, sc + 1, cnt, st);
-      launch_gmres_givens(j, mr + 1, Hm, h1, h2, sc + 1, cs, sn, g, tol, flags, sc + 2, st);
+      launch_gmres_givens(j, mr + 1, Hm, h1, h2, sc + 1, cs, sn, g, tol, flags + 2 * j, sc + 2, st);
       launch_div_scalar(n, w, w, sc + 2, st);
+      HIPCHK(hipMemcpyAsync(c->hfl + 2 * j, flags + 2 * j, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipEventRecord(c->pev[j & 1], st));
+      return SLR_OK;
+    };
+    const int cyc = std::min(mr, so.maxit - its);  // steps this cycle may take
+    int jj = 0, queued = 1;
+    if ((rc = queue_step(0))) return bail(rc);
+    for (int j = 0; j < cyc; ++j) {
+      if (queued < cyc) {
+        if ((rc = queue_step(queued))) return bail(rc);
+        ++queued;
+      }
+      HIPCHK(hipEventSynchronize(c->pev[j & 1]));
       ++its;
       jj = j + 1;
-      int fl[2];
-      HIPCHK(hipMemcpyAsync(fl, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
+      const int *fl = c->hfl + 2 * j;
       if (fl[0]) conv = true;
-      if (fl[0] || fl[1] || its >= so.maxit) break;
+      if (fl[0] || fl[1]) break;
     }
     launch_gmres_solve(jj, mr + 1, Hm, g, y, st);
     launch_gemv_add(n, jj, Zb, n, y, X, st);
