@@ -80,3 +80,29 @@ def test_zero_column_and_columns_alone(lap3d32):
         x1, i1 = G.solve(_dev(B[:, j]), "pcg", rtol=1e-8, maxit=300)
         assert info[j]["status"] == 0 and info[j]["iters"] == i1[0]["iters"]
         assert _rel(X[:, j], x1.cpu().numpy()) <= 1e-12
+
+
+@pytest.mark.parametrize("method", ["pcg", "fcg"])
+def test_poll_period_does_not_change_the_solve(lap3d32, method):
+    """The host polls convergence between blocks of iterations whose lengths
+    follow the residual's decay, with the next block queued before each poll.
+    Iterations queued past convergence must leave x, the count and the
+    residual as they were: every poll period gives the same bits, converged
+    or stopped by maxit (also at a maxit that ends inside a block)."""
+    P, pr, Po, G, b = lap3d32
+    _, b3 = si.rhs_from_solution(pr.csr, 3, 91)
+    for rhs in (b, np.array(b3)):
+        for maxit in (300, 13):
+            ref = None
+            for every in (1, 3, 8, 100):
+                x, info = G.solve(_dev(rhs), method, rtol=1e-8, maxit=maxit, check_every=every)
+                got = (x.cpu().numpy(), [(i["iters"], i["status"], i["relres"]) for i in info])
+                if maxit == 13:
+                    assert all(i["iters"] == 13 and i["status"] == P.SLR_ERR_NOCONV for i in info)
+                else:
+                    assert all(i["status"] == 0 for i in info)
+                if ref is None:
+                    ref = got
+                    continue
+                assert got[1] == ref[1], (every, got[1], ref[1])
+                assert np.array_equal(got[0], ref[0]), every
