@@ -221,6 +221,9 @@ struct slr_ctx {
   // scratch of the Lanczos build, kept between builds
   char *lz_base = nullptr;
   size_t lz_cap = 0;
+  // scratch of FGMRES, kept between solves
+  char *gm_base = nullptr;
+  size_t gm_cap = 0;
 };
 
 struct slr_batch {
@@ -1420,6 +1423,7 @@ void slr_destroy(slr_ctx *c) {
   if (c->rf.stage) (void)hipHostFree(c->rf.stage);
   if (c->hst) (void)hipHostFree(c->hst);
   if (c->lz_base) (void)hipFree(c->lz_base);
+  if (c->gm_base) (void)hipFree(c->gm_base);
   if (c->hfl) (void)hipHostFree(c->hfl);
   for (hipEvent_t e : c->pev)
     if (e) (void)hipEventDestroy(e);
@@ -1437,7 +1441,7 @@ int slr_query(const slr_ctx *c, slr_info *info) {
   *info = c->info;
   info->device_bytes =
       c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes + c->rf.pool.bytes +
-      (int64_t)c->lz_cap;
+      (int64_t)(c->lz_cap + c->gm_cap);
   return SLR_OK;
 }
 
@@ -1668,7 +1672,7 @@ int solve_fgmres(slr_ctx *c, const double *b_dev, double *x_dev, const slr_solve
                  hipStream_t st) {
   const int64_t n = c->n;
   const int32_t mr = std::max(1, std::min(so.restart, 200));
-  DevPool tmp;
+  Arena tmp(c->gm_base, c->gm_cap);
   double *V = tmp.alloc<double>((size_t)n * (mr + 1));
   double *Zb = tmp.alloc<double>((size_t)n * mr);
   double *Bd = tmp.alloc<double>(n);
