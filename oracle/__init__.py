@@ -389,12 +389,13 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
           c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
           fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
           lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "partial",
-          droptol: float = 1e-3) -> SLR:
+          droptol: float = 1e-3, seed: int = 7) -> SLR:
     """Build the SLR preconditioner (Sec. 4 and Sec. 5).
 
     A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
     (-1 = separator).  lanczos_steps 0 means 5k (Sec. 6).  v0: Lanczos start
-    vector in original node order (its interface entries are used).
+    vector in original node order (its interface entries are used); when
+    it is None the start vector is splitmix64_uniform(n, seed).
     lowrank: optional (U, lam, theta) to use instead of running Lanczos.
     theta_mode "lambda_k1" (theta = lambda_{k+1}, Sec. 4), "lambda_s"
     (theta = smallest Ritz value, Sec. 4), "zero" (eq. Lambda-1) or "eps"
@@ -434,7 +435,7 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     elif k > 0:
         steps = lanczos_steps or 5 * k
         if v0 is None:
-            v0 = np.random.Generator(np.random.PCG64(7)).uniform(-1, 1, A.shape[0])
+            v0 = splitmix64_uniform(A.shape[0], seed)
         lanczos_lowrank(P, k, steps, np.asarray(v0)[perm[m:]], theta_mode, cond_K, reorth)
     else:
         P.theta = 0.0
@@ -447,6 +448,26 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     elif uk_prec == "bf16":
         P.U = round_bf16(P.U)
     return P
+
+
+def splitmix64_uniform(n: int, seed: int) -> np.ndarray:
+    """Default Lanczos start vector (Sec. 5.1 leaves the start vector open).
+
+    READING: U[-1, 1) values from SplitMix64 (Steele, Lea and Flood,
+    "Fast splittable pseudorandom number generators", OOPSLA 2014), used as
+    a counter-based generator: the value of node i (original order) comes
+    from the (i+1)-th output of the stream started at ``seed``, i.e. from the
+    state seed + (i+1) * 0x9E3779B97F4A7C15 (mod 2^64) passed through the
+    generator's mixing function; its top 53 bits give u in [0, 1) and the
+    entry is 2u - 1.  Written from the published definition."""
+    gamma = np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + gamma * (np.arange(n, dtype=np.uint64) + np.uint64(1))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return 2.0 * u - 1.0
 
 
 def lanczos(G, v0: np.ndarray, steps: int, Z: np.ndarray | None = None):
@@ -681,10 +702,12 @@ def _true_relres(A, x, b):
     return float(np.linalg.norm(b - A @ x) / nb) if nb > 0 else 0.0
 
 
-def pcg(A, M, b, rtol=1e-8, maxit=300, flexible=False) -> SolveResult:
+def pcg(A, M, b, rtol=1e-8, maxit=300, flexible=False, record: dict | None = None) -> SolveResult:
     """Preconditioned CG, x0 = 0.  READING: stop on the recurrence residual
     ||r_j|| <= rtol ||b||; the iteration count is the number of products
-    with A.  flexible=True uses the Polak-Ribiere beta (flexible CG)."""
+    with A.  flexible=True uses the Polak-Ribiere beta (flexible CG).
+    record (optional dict) receives "p", the list of search directions in
+    the order they are used (for the pins)."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b)
     r = b.copy()
@@ -696,6 +719,8 @@ def pcg(A, M, b, rtol=1e-8, maxit=300, flexible=False) -> SolveResult:
     p = z.copy()
     rz = float(r @ z)
     for it in range(1, maxit + 1):
+        if record is not None:
+            record.setdefault("p", []).append(p.copy())
         q = A @ p
         alpha = rz / float(p @ q)
         x += alpha * p
@@ -713,11 +738,15 @@ def pcg(A, M, b, rtol=1e-8, maxit=300, flexible=False) -> SolveResult:
     return SolveResult(x, maxit, False, _true_relres(A, x, b), hist)
 
 
-def fgmres(A, M, b, rtol=1e-8, maxit=300, restart=40) -> SolveResult:
+def fgmres(A, M, b, rtol=1e-8, maxit=300, restart=40, record: dict | None = None) -> SolveResult:
     """Right-preconditioned flexible GMRES(restart) (Saad 1993), x0 = 0,
     modified Gram-Schmidt Arnoldi, Givens rotations.  READING: stop when the
     least-squares residual estimate falls to rtol ||b||; the iteration count
-    is the number of products with A."""
+    is the number of products with A.  record (optional dict) receives
+    "cycles": per restart cycle the start x0, the bases V (n x (m+1)) and
+    Z (n x m), the Hessenberg block Hbar ((m+1) x m) before the rotations,
+    the least-squares solution y, the residual estimate |g_{m+1}| and the
+    updated x (for the pins)."""
     b = np.asarray(b, dtype=np.float64)
     n = b.shape[0]
     x = np.zeros(n)
@@ -738,6 +767,7 @@ def fgmres(A, M, b, rtol=1e-8, maxit=300, restart=40) -> SolveResult:
         V[:, 0] = r / beta
         j_done = 0
         done = False
+        Hbar = np.zeros((restart + 1, restart)) if record is not None else None
         for j in range(restart):
             Z[:, j] = M(V[:, j])
             w = A @ Z[:, j]
@@ -748,6 +778,8 @@ def fgmres(A, M, b, rtol=1e-8, maxit=300, restart=40) -> SolveResult:
             H[j + 1, j] = np.linalg.norm(w)
             if H[j + 1, j] > 0:
                 V[:, j + 1] = w / H[j + 1, j]
+            if Hbar is not None:
+                Hbar[:j + 2, j] = H[:j + 2, j]
             for i in range(j):
                 t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
                 H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
@@ -764,7 +796,12 @@ def fgmres(A, M, b, rtol=1e-8, maxit=300, restart=40) -> SolveResult:
                 done = True
                 break
         y = sla.solve_triangular(H[:j_done, :j_done], gvec[:j_done])
+        x0 = x
         x = x + Z[:, :j_done] @ y
+        if record is not None:
+            record.setdefault("cycles", []).append(dict(
+                x0=x0, V=V[:, :j_done + 1].copy(), Z=Z[:, :j_done].copy(), Hbar=Hbar[:j_done + 1, :j_done].copy(),
+                y=y, g=abs(gvec[j_done]), x=x.copy()))
         if done:
             conv = hist[-1] <= rtol
             return SolveResult(x, it, conv, _true_relres(A, x, b), hist)

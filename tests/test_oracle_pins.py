@@ -633,6 +633,104 @@ def test_krylov_iteration_counts_on_known_spectra():
     assert r.converged and r.iters > 3
 
 
+class _VariableJacobi:
+    """A preconditioner that changes at every call: the j-th call applies
+    diag(w_i / a_ii) with w_i = 1 + 0.3 ((i + j) mod 3), so the weights move
+    between components from one call to the next (a plain rescaling of one
+    fixed M would not test flexibility: CG absorbs it into the step
+    length).  Flexible CG and flexible GMRES must keep their defining
+    relations with it; the plain forms only keep them for a fixed M."""
+
+    def __init__(self, A):
+        self.d = A.diagonal()
+        self.i = np.arange(A.shape[0])
+        self.j = 0
+
+    def __call__(self, v):
+        w = 1.0 + 0.3 * ((self.i + self.j) % 3)
+        self.j += 1
+        return w * v / self.d
+
+
+def _anorm(A, v):
+    return math.sqrt(float(v @ (A @ v)))
+
+
+def _local_a_orthogonality(A, ps):
+    """max_j |p_j^T A p_{j-1}| / (||p_j||_A ||p_{j-1}||_A)."""
+    return max(abs(float(ps[j] @ (A @ ps[j - 1]))) / (_anorm(A, ps[j]) * _anorm(A, ps[j - 1]))
+               for j in range(1, len(ps)))
+
+
+def test_flexible_cg_keeps_local_a_orthogonality_with_a_variable_preconditioner():
+    """Flexible CG (Polak-Ribiere beta; Sec. 6 uses flexible outer iterations
+    for the reduced-precision form): with a preconditioner that changes at
+    every iteration, each search direction stays A-orthogonal to the
+    previous one, |p_j^T A p_{j-1}| <= 1e-12 ||p_j||_A ||p_{j-1}||_A, and
+    the iteration still converges.  The Fletcher-Reeves beta (the plain CG
+    branch, the planted mistake) loses this property by orders of magnitude
+    with the same preconditioner."""
+    A = si.make_config("diffusion2d_1024", N=20, boxes=2).scipy()
+    b = np.random.default_rng(31).uniform(-1, 1, A.shape[0])
+    rec = {}
+    r = O.pcg(A, _VariableJacobi(A), b, rtol=1e-10, maxit=400, flexible=True, record=rec)
+    assert r.converged and r.true_relres <= 1e-9
+    assert len(rec["p"]) == r.iters
+    assert _local_a_orthogonality(A, rec["p"][:40]) <= 1e-12
+    bad = {}
+    O.pcg(A, _VariableJacobi(A), b, rtol=1e-10, maxit=40, flexible=False, record=bad)
+    assert _local_a_orthogonality(A, bad["p"]) > 1e-4
+    # with a fixed preconditioner both betas keep the property (consistency)
+    fixed = {}
+    O.pcg(A, lambda v: v / A.diagonal(), b, rtol=1e-10, maxit=40, flexible=False, record=fixed)
+    assert _local_a_orthogonality(A, fixed["p"]) <= 1e-10
+
+
+@pytest.mark.parametrize("restart", [60, 20])
+def test_fgmres_arnoldi_relation_with_a_variable_preconditioner(restart):
+    """Flexible GMRES stores the preconditioned vectors Z (Saad 1993): with a
+    preconditioner that changes at every step, each cycle satisfies
+    A Z_m = V_{m+1} Hbar_m, and the true residual of the updated iterate
+    equals the least-squares estimate, ||b - A x_m|| = |g_{m+1}|, both to
+    1e-12.  Updating with M(V_m y) instead of Z_m y (the planted mistake)
+    breaks the second relation."""
+    A = si.make_config("diffusion2d_1024", N=20, boxes=2).scipy()
+    b = np.random.default_rng(32).uniform(-1, 1, A.shape[0])
+    M = _VariableJacobi(A)
+    rec = {}
+    r = O.fgmres(A, M, b, rtol=1e-10, maxit=3000, restart=restart, record=rec)
+    assert r.converged and r.true_relres <= 1e-9
+    nb = np.linalg.norm(b)
+    assert len(rec["cycles"]) >= 2
+    for cy in rec["cycles"]:
+        V, Z, Hb = cy["V"], cy["Z"], cy["Hbar"]
+        assert np.abs(V.T @ V - np.eye(V.shape[1])).max() <= 1e-10
+        lhs = A @ Z
+        assert np.linalg.norm(lhs - V @ Hb) <= 1e-12 * np.linalg.norm(lhs)
+        true = np.linalg.norm(b - A @ cy["x"])
+        assert abs(true - cy["g"]) <= 1e-12 * nb, (true, cy["g"])
+    # planted mistake on the first cycle: x0 + M(V y) with the
+    # preconditioner's next state instead of x0 + Z y
+    cy = rec["cycles"][0]
+    wrong = cy["x0"] + M(cy["V"][:, :-1] @ cy["y"])
+    assert abs(np.linalg.norm(b - A @ wrong) - cy["g"]) > 1e-3 * nb
+
+
+def test_splitmix64_start_vector_matches_published_outputs():
+    """The default Lanczos start vector (reading: SplitMix64 used as a
+    counter-based generator keyed by node index) reproduces the published
+    first outputs of the generator (tests/golden/splitmix64.json): entry i
+    is 2 u - 1 with u the top 53 bits of output i + 1, over 2^53."""
+    with open(os.path.join(GOLDEN, "splitmix64.json")) as f:
+        g = json.load(f)
+    outs = [int(x) for x in g["outputs"]]
+    expect = np.array([2.0 * ((z >> 11) / 9007199254740992.0) - 1.0 for z in outs])
+    got = O.splitmix64_uniform(len(outs), g["seed"])
+    assert np.array_equal(got, expect)
+    v = O.splitmix64_uniform(200000, 7)
+    assert v.min() >= -1.0 and v.max() < 1.0 and abs(v.mean()) < 0.01 and abs(v.var() - 1.0 / 3.0) < 0.01
+
+
 def test_pcg_solves_the_small_configuration():
     pr = si.make_config("lap2d_64")
     P = O.setup(pr.csr, pr.part, pr.nparts, pr.k, pr.lanczos_steps, "chol", "chol", v0=pr.v0())
