@@ -73,3 +73,49 @@ def test_shifted_128_apply_fp32_ildlt():
     z = G.apply(torch.tensor(r, dtype=torch.float64, device="cuda")).cpu().numpy()
     err = _relerr(z, Po.apply(r))
     assert err.max() <= 1e-5, err
+
+
+def test_shifted_128_apply_fp64_pair_path():
+    """The shifted 128^3 workload with FP64 factors and U_k: 512 subdomains,
+    so the one-column apply takes the two-workgroups-per-CU B solves.  The
+    oracle imports the device's (U_k, Lambda_k, theta) with its own FP64
+    factors; bar 1e-12 per column, for one and for two columns."""
+    import paper_1505_04340_amd as P
+    print("shifted 128^3 fp64 apply", flush=True)
+    pr = si.make_config("shifted3d_128")
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order="multicolor", v0=pr.v0())
+    ex = G.export()
+    Po = O.setup(pr.csr, pr.part, pr.nparts, pr.k, 0, b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor",
+                 lowrank=(ex["U"], ex["lambda"], ex["theta"]))
+    rng = np.random.default_rng(23)
+    r1 = rng.uniform(-1, 1, pr.n)
+    z1 = G.apply(torch.tensor(r1, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert _relerr(z1, Po.apply(r1)).max() <= 1e-12
+    r2 = rng.uniform(-1, 1, (pr.n, 2))
+    z2 = G.apply(torch.tensor(r2, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert _relerr(z2, Po.apply(r2)).max() <= 1e-12
+
+
+def test_lap3d_64_mixed_form_fcg_full_size():
+    """The 64^3 workload in the mixed form (FP32 factors, BF16 U_k on matrix
+    cores, flexible CG in FP64): the oracle runs flexible CG with its FP64
+    apply on the same rounded data (the device's exported U_k rounded to
+    BF16).  Both reach a true FP64 relative residual <= 1e-8; the counts
+    agree to +-1."""
+    import paper_1505_04340_amd as P
+    print("lap3d 64^3 mixed fcg", flush=True)
+    pr = si.make_config("lap3d_64")
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order="multicolor", fact_prec="fp32", uk_prec="bf16", v0=pr.v0())
+    ex = G.export()
+    Po = O.setup(pr.csr, pr.part, pr.nparts, pr.k, 0, b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor",
+                 fact_prec="fp32", lowrank=(O.round_bf16(ex["U"]), ex["lambda"], ex["theta"]))
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "fcg")
+    x, info = G.solve(torch.tensor(b[:, 0], dtype=torch.float64, device="cuda"), "fcg")
+    A = pr.scipy()
+    rr = np.linalg.norm(b[:, 0] - A @ x.cpu().numpy()) / np.linalg.norm(b[:, 0])
+    assert ro.converged and ro.true_relres <= 1e-8
+    assert info[0]["status"] == 0 and info[0]["relres"] <= 1e-8 and rr <= 1e-8
+    assert abs(info[0]["iters"] - ro.iters) <= 1, (info[0]["iters"], ro.iters)

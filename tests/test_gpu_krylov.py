@@ -106,3 +106,28 @@ def test_poll_period_does_not_change_the_solve(lap3d32, method):
                     continue
                 assert got[1] == ref[1], (every, got[1], ref[1])
                 assert np.array_equal(got[0], ref[0]), every
+
+
+def test_fgmres_iterate_inside_a_cycle_matches_oracle(lap3d32):
+    """FGMRES with a restart shorter than the iteration limit, stopped by
+    maxit inside the third cycle: the device iterate equals the oracle's
+    (MGS Arnoldi there, CGS2 on the device: equal in exact arithmetic) to
+    1e-10.  The device queues Arnoldi steps ahead of the host's flag reads
+    and keeps its workspace between solves: a second solve on the same
+    context with another restart gives the bits of a fresh context."""
+    P, pr, Po, G, b = lap3d32
+    print("fgmres inside a cycle: lap3d N=32", flush=True)
+    ro = O.fgmres(Po.A, Po.apply, b, rtol=1e-12, maxit=23, restart=10)
+    assert not ro.converged and ro.iters == 23
+    x, info = G.solve(_dev(b), "fgmres", rtol=1e-12, maxit=23, restart=10)
+    assert info[0]["iters"] == 23 and info[0]["status"] == P.SLR_ERR_NOCONV
+    assert _rel(x.cpu().numpy(), ro.x) <= 1e-10
+    x7, i7 = G.solve(_dev(b), "fgmres", rtol=1e-8, maxit=300, restart=7)
+    Gf = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+               c_fact=pr.c_fact, v0=pr.v0(), c_order="multicolor", lowrank=(Po.U, Po.lam, Po.theta))
+    xf, if_ = Gf.solve(_dev(b), "fgmres", rtol=1e-8, maxit=300, restart=7)
+    assert i7 == if_
+    assert np.array_equal(x7.cpu().numpy(), xf.cpu().numpy())
+    ro7 = O.fgmres(Po.A, Po.apply, b, rtol=1e-8, maxit=300, restart=7)
+    assert ro7.converged and i7[0]["status"] == 0 and i7[0]["relres"] <= 1e-8
+    assert abs(i7[0]["iters"] - ro7.iters) <= 1

@@ -425,7 +425,7 @@ def test_fgmres_indefinite_threshold_factors():
     ro = O.solve(Po, b[:, 0], "fgmres")
     x, info = G.solve(_dev(b[:, 0]), "fgmres")
     assert ro.converged and info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
-    assert abs(info[0]["iters"] - ro.iters) <= 2
+    assert abs(info[0]["iters"] - ro.iters) <= 1
 
 
 def test_fgmres_indefinite():
@@ -521,3 +521,77 @@ def test_library_imported_before_torch():
             "print('ok', G.info['k'])\n") % root
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
     assert r.returncode == 0 and "ok 4" in r.stdout, r.stderr[-2000:]
+
+
+# ------------------------------------- more subdomains than compute units
+@pytest.fixture(scope="module")
+def lap3d_512():
+    """48^3 Laplacian in 8x8x8 boxes: 512 subdomains, more than the 256
+    compute units, so a one-column B solve runs two workgroups per CU (half
+    the threads, half the LDS each)."""
+    pr = si.make_config("lap3d_64", N=48, boxes=8)
+    return pr, _oracle(pr, k=8, lanczos_steps=240, c_order="multicolor")
+
+
+def test_pair_path_one_column_apply_fp64(lap3d_512):
+    pr, Po = lap3d_512
+    print("pair path fp64: lap3d N=48 boxes=8 (512 subdomains)", flush=True)
+    assert Po.off_b.shape[0] - 1 == 512
+    G = _slr(pr, k=8, lanczos_steps=240, c_order="multicolor", lowrank=(Po.U, Po.lam, Po.theta))
+    r = _rand(pr.n, 1, 71)[:, 0]
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max() <= 1e-12
+    # the two-column form (one workgroup per CU) gives the same columns
+    r2 = _rand(pr.n, 2, 72)
+    Z2 = G.apply(_dev(r2)).cpu().numpy()
+    assert _relerr(Z2, Po.apply(r2)).max() <= 1e-12
+    assert _relerr(G.apply(_dev(r2[:, 1])).cpu().numpy(), Z2[:, 1]).max() <= 1e-14
+
+
+def test_pair_path_one_column_apply_fp32():
+    pr = si.make_config("lap3d_64", N=48, boxes=8)
+    print("pair path fp32: lap3d N=48 boxes=8 (512 subdomains)", flush=True)
+    Po = _oracle(pr, k=8, lanczos_steps=40, c_order="multicolor", fact_prec="fp32", uk_prec="fp32")
+    G = _slr(pr, k=8, lanczos_steps=40, c_order="multicolor", fact_prec="fp32", uk_prec="fp32",
+             lowrank=(O.round_fp32(Po.U), Po.lam, Po.theta))
+    r = _rand(pr.n, 1, 73)[:, 0]
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max() <= 1e-5
+
+
+def test_pair_path_device_lanczos_matches_oracle_lanczos(lap3d_512):
+    """Every B solve of the device Lanczos runs on the pair path here: its
+    converged Ritz values agree with the oracle's own Lanczos (eq. H,
+    Sec. 5.1) to 1e-10, theta = lambda_{k+1} (converged at 240 steps) is one
+    of the oracle's converged values to 1e-10 (H has close pairs here, so a
+    value's position depends on whether a pair is seen once or twice), the
+    top Ritz vector matches the oracle's, and the apply with the device's own
+    low-rank part matches the oracle fed with it."""
+    pr, Po = lap3d_512
+    print("pair path lanczos: lap3d N=48 boxes=8", flush=True)
+    G = _slr(pr, k=8, lanczos_steps=240, c_order="multicolor")
+    ex, gv, gb = _lanczos_parity(G, Po, 8)
+    assert gb[0] <= 1e-9 and gb[8] <= 1e-9
+    ov, ob = _ritz_bounds(Po.alpha, Po.beta)
+    oc = ov[:12][ob[:12] <= 1e-9]
+    assert np.min(np.abs(oc - ex["theta"])) <= 1e-10 * abs(ex["theta"]), (ex["theta"], oc)
+    assert abs(abs(float(ex["U"][:, 0] @ Po.U[:, 0])) - 1.0) <= 1e-8
+    Pi = _oracle(pr, c_order="multicolor", lowrank=(ex["U"], ex["lambda"], ex["theta"]))
+    r = _rand(pr.n, 1, 74)[:, 0]
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= 1e-12
+
+
+def test_seeded_start_vector_matches_oracle():
+    """With no start vector both sides draw it from the seed (SplitMix64
+    keyed by node index): the Lanczos runs, and so the Ritz values and
+    the PCG solve, agree as with an explicit start vector."""
+    pr = si.make_config("lap2d_64")
+    print("seeded start vector: lap2d_64", flush=True)
+    Po = O.setup(pr.csr, pr.part, pr.nparts, pr.k, pr.lanczos_steps, b_fact=pr.b_fact, c_fact=pr.c_fact, seed=29)
+    import paper_1505_04340_amd as P
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, seed=29)
+    _lanczos_parity(G, Po, pr.k)
+    ex = G.export()
+    assert np.allclose(ex["alpha"][:5], Po.alpha[:5], rtol=1e-12, atol=0)
+    G7 = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+               c_fact=pr.c_fact, seed=7)
+    assert not np.allclose(G7.export()["alpha"][:5], ex["alpha"][:5], rtol=1e-6)
