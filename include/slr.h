@@ -260,6 +260,23 @@ int slr_apply(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void
  * order (interiors by subdomain, then interface; slr_export perm). */
 int slr_apply_dd(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream);
 
+/* slr_apply_dd_noalloc: slr_apply_dd for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layout and results
+ * (the same kernels in the same order, so the output equals slr_apply_dd's
+ * bit for bit); the call allocates nothing.  The apply's scratch (two
+ * s x nrhs interface blocks, the rank-k partials and coefficients, in all
+ * 2 * 8 s nrhs + 8 k nrhs (chunks + 1) bytes, each part rounded up to 256)
+ * comes from one fixed device array of 64 MiB per GPU, which the library
+ * holds from its first slr_setup on that GPU until the process ends.
+ * nrhs whose scratch exceeds 64 MiB is SLR_ERR_ARG (the message gives the
+ * bytes needed); the context's device must be the current one (SLR_ERR_ARG
+ * otherwise).  Every call on a GPU, from any context or stream, shares that
+ * GPU's array and leaves its contents behind: calls that overlap on one GPU
+ * (concurrent streams, threads) race and give wrong results; serialise
+ * them.  Asynchronous on hip_stream. */
+int slr_apply_dd_noalloc(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream);
+
 /* slr_solve: preconditioned Krylov solve A x = b (Sec. 6: CG for SPD,
  * GMRES(40) for indefinite; flexible CG for reduced-precision factors).
  * b_dev, x_dev: device n x nrhs (original order); x0 = 0.  Stops when

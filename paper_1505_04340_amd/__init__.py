@@ -104,6 +104,7 @@ slr_refactor = _sig("slr_refactor", ctypes.c_int, [_P, _P, _I32, _P])
 slr_time_kernel = _sig("slr_time_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P, ctypes.POINTER(_D)])
 slr_apply = _sig("slr_apply", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_apply_dd = _sig("slr_apply_dd", ctypes.c_int, [_P, _P, _P, _I32, _P])
+slr_apply_dd_noalloc = _sig("slr_apply_dd_noalloc", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_solve = _sig("slr_solve", ctypes.c_int, [_P, _P, _P, _I32, ctypes.POINTER(slr_solve_opts),
                                              ctypes.POINTER(slr_solve_info), _P])
 slr_solve_workspace_bytes = _sig("slr_solve_workspace_bytes", ctypes.c_size_t, [_P, _I32, _I32])
@@ -124,7 +125,7 @@ slr_device_lds_bytes = _sig("slr_device_lds_bytes", ctypes.c_int, [])
 
 EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_analyze", "slr_update_lowrank",
             "slr_grow_lowrank", "slr_refactor",
-            "slr_time_kernel", "slr_apply", "slr_apply_dd",
+            "slr_time_kernel", "slr_apply", "slr_apply_dd", "slr_apply_dd_noalloc",
             "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_spmv",
             "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
             "slr_batch_active", "slr_batch_bytes", "slr_batch_destroy", "slr_destroy",
@@ -337,6 +338,18 @@ class SLR:
     def apply_dd(self, r, stream=None):
         """z = M^{-1} r in the internal DD order."""
         return self._call(slr_apply_dd, r, "slr_apply_dd", stream)
+
+    def apply_dd_noalloc(self, r, out=None, stream=None):
+        """z = M^{-1} r in the internal DD order without any device
+        allocation in the library (slr_apply_dd_noalloc); out (optional)
+        receives z and must be an FP64 CUDA tensor shaped like r's
+        column-major copy."""
+        import torch
+        rc_, vec = _colmajor(r)
+        z = torch.empty_like(rc_) if out is None else out
+        _check(slr_apply_dd_noalloc(self._h, ctypes.c_void_p(rc_.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                    rc_.shape[0], _stream(stream)), "slr_apply_dd_noalloc")
+        return z.view(-1) if vec else z.t()
 
     def spmv(self, x, stream=None):
         return self._call(slr_spmv, x, "slr_spmv", stream)

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,17 @@ using namespace slr;
 namespace {
 
 thread_local std::string g_err;
+
+// Scratch of slr_apply_dd_noalloc: one fixed array per GPU, held until the
+// process ends, so that the call allocates nothing.  Host code never passes
+// `scratch` itself to a kernel (on the host it names a stand-in, not device
+// memory): it uses the device address that hipGetSymbolAddress returns for
+// the current GPU, kept per device in g_scratch_dev.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices] = {};
 
 constexpr int64_t pad8h(int64_t x) { return (x + 7) & ~int64_t(7); }
 constexpr int64_t pad16h(int64_t x) { return (x + 15) & ~int64_t(15); }
@@ -39,6 +51,23 @@ int fail(int code, const std::string &msg) {
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device address of `scratch` on `dev`, which must be the current device:
+// looked up once per device (hipGetSymbolAddress) and kept.
+int scratch_address(int dev, char **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return fail(SLR_ERR_ARG, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SLR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (char *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return SLR_OK;
 }
 
 // Device allocations owned by one object, freed together.
@@ -1129,6 +1158,12 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   if (rc) return fail(rc, err);
   slr_ctx *c = new slr_ctx();
   (void)hipGetDevice(&c->device);
+  {
+    // set-up of slr_apply_dd_noalloc's scratch on this device (a failure
+    // here only disables that entry point; it retries on its first call)
+    char *sp = nullptr;
+    (void)scratch_address(c->device, &sp);
+  }
   c->opts = *o;
   c->n = H.n;
   c->m = H.m;
@@ -1461,6 +1496,40 @@ int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda, do
 int slr_apply_dd(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream) {
   if (!c || !r_dev || !z_dev || nrhs < 0) return fail(SLR_ERR_ARG, "bad apply arguments");
   return apply_dd(c, c->ws, r_dev, c->n, z_dev, c->n, nrhs, S(hip_stream));
+}
+
+int slr_apply_dd_noalloc(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream) {
+  if (!c || !r_dev || !z_dev || nrhs < 0) return fail(SLR_ERR_ARG, "bad apply arguments");
+  if (nrhs == 0) return SLR_OK;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != c->device) return fail(SLR_ERR_ARG, "the context's device must be current");
+  char *base = nullptr;
+  int rc = scratch_address(dev, &base);
+  if (rc) return rc;
+  // the apply's scratch, carved as apply_dd's workspace would allocate it
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const int32_t nb = std::max(c->lr_nblk, c->lrm_nblk);
+  const int32_t kk = std::max(c->k, 1);
+  const size_t s1 = (size_t)std::max<int64_t>(c->s, 1);
+  const size_t bW = al(sizeof(double) * s1 * nrhs);
+  const size_t bP = al(sizeof(double) * (size_t)nb * nrhs * kk);
+  const size_t bC = al(sizeof(double) * (size_t)kk * nrhs);
+  const size_t need = 2 * bW + bP + bC + 256;
+  if (need > kNoAllocScratchBytes)
+    return fail(SLR_ERR_ARG, "slr_apply_dd_noalloc needs " + std::to_string(need) + " bytes of scratch for " +
+                                 std::to_string(nrhs) + " columns; the fixed scratch holds " +
+                                 std::to_string(kNoAllocScratchBytes));
+  ApplyWS w;
+  w.W = (double *)base;
+  w.W2 = (double *)(base + bW);
+  w.lr_part = (double *)(base + 2 * bW);
+  w.cbuf = (double *)(base + 2 * bW + bP);
+  w.counter = (unsigned int *)(base + 2 * bW + bP + bC);   // unused by the apply's kernels
+  w.cap = nrhs;
+  w.k = kk;
+  w.nblk = nb;
+  return apply_dd(c, w, r_dev, c->n, z_dev, c->n, nrhs, S(hip_stream));
 }
 
 int slr_apply(slr_ctx *c, const double *r_dev, double *z_dev, int32_t nrhs, void *hip_stream) {
