@@ -223,7 +223,7 @@ def serving(P, torch, n_req, seed=13):
         if kind == "mixed_batched":
             svc = serve.Service(mixed, "fcg", maxit=SERVE_MAXIT)
             svc.run(reqs)
-            dev = svc.device_bytes()
+            dev = svc.peak_bytes
             svc.close()
         else:
             serve.serve_plain(plain, reqs, "pcg", maxit=SERVE_MAXIT)

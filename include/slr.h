@@ -286,8 +286,22 @@ int slr_apply_dd_noalloc(slr_ctx *c, const double *r_dev, double *z_dev, int32_t
 int slr_solve(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs,
               const slr_solve_opts *so, slr_solve_info *info, void *hip_stream);
 
-/* slr_solve_workspace_bytes: device bytes slr_solve needs for nrhs. */
-size_t slr_solve_workspace_bytes(const slr_ctx *c, int32_t nrhs, int32_t method);
+/* slr_solve_workspace_bytes: device bytes of the workspace slr_solve
+ * allocates for nrhs columns with the options `so` (NULL: the defaults);
+ * for FGMRES it depends on the restart length (the basis and the
+ * preconditioned basis: 2 restart + 1 vectors of n).  The context keeps
+ * this workspace after the solve (see slr_trim). */
+size_t slr_solve_workspace_bytes(const slr_ctx *c, int32_t nrhs, const slr_solve_opts *so);
+
+/* slr_trim: release the scratch buffers a context keeps between calls to
+ * avoid allocating again (the Lanczos build's basis and work vectors, the
+ * FGMRES and CG workspaces, the original-order staging of slr_apply /
+ * slr_spmv, and the apply workspace beyond one column).  The next call
+ * that needs them allocates them again.  slr_query's device_bytes counts
+ * them while they are kept; without slr_trim they live until slr_destroy.
+ * Synchronises the device when the memory came from an allocator set with
+ * slr_set_allocator. */
+int slr_trim(slr_ctx *c);
 
 /* slr_query: sizes, level depths, theta, timings, memory. */
 int slr_query(const slr_ctx *c, slr_info *info);
@@ -299,6 +313,41 @@ int slr_query(const slr_ctx *c, slr_info *info);
  * the final residual norm). */
 int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda,
                double *U, double *alpha, double *beta);
+
+/* slr_export_setup: serialise the whole resident preconditioner -- the
+ * DD ordering, A in that order, the packed B_i sweeps with E and E^T
+ * (Sec. 2.1, Sec. 5.2), C's sweeps, the low-rank part (U_k in FP64,
+ * Lambda_k, theta; Sec. 4, Sec. 5.1), the Lanczos coefficients and the
+ * options -- into buf (host, cap bytes).  *bytes receives the size; with
+ * buf == NULL only the size is returned.  cap < *bytes is SLR_ERR_ARG.
+ * Current values are taken (after slr_refactor, the refactored ones).  The
+ * layout is this library build's own (magic, length, records, FNV-1a
+ * checksum), native byte order. */
+int slr_export_setup(const slr_ctx *c, void *buf, size_t cap, size_t *bytes);
+
+/* slr_import: a new context on the current device from slr_export_setup's
+ * bytes (host; not retained), without the host analysis or the Lanczos
+ * build.  Its apply and solves equal those of the exported context bit for
+ * bit.  The imported context cannot slr_refactor (no refactorisation plan
+ * is serialised).  Errors: SLR_ERR_ARG (wrong magic, length, checksum or
+ * inconsistent sizes), SLR_ERR_OOM, SLR_ERR_HIP.  The content beyond its
+ * structure is trusted: pass only bytes that slr_export_setup wrote. */
+int slr_import(const void *buf, size_t bytes, void *hip_stream, slr_ctx **out);
+
+/* slr_set_allocator: route every device allocation of the library (all
+ * contexts and batches created or grown afterwards) through alloc(bytes,
+ * user), which returns device memory of the current device or NULL
+ * (reported as SLR_ERR_OOM), and free_(ptr, user) -- e.g. PyTorch's caching
+ * allocator, so that PyTorch owns the memory.  Memory keeps the allocator
+ * that made it: a later change frees older blocks through their own
+ * free_.  The library synchronises the device before it hands memory back
+ * through free_.  alloc == NULL or free_ == NULL restores hipMalloc /
+ * hipFree.  Process-wide; call it while no other thread is inside the
+ * library.  (Pinned host staging still uses hipHostMalloc; the 64 MiB
+ * array of slr_apply_dd_noalloc is static.) */
+typedef void *(*slr_alloc_fn)(size_t bytes, void *user);
+typedef void (*slr_free_fn)(void *ptr, void *user);
+void slr_set_allocator(slr_alloc_fn alloc, slr_free_fn free_, void *user);
 
 /* slr_spmv: y = A x in the original order (device n x nrhs), FP64. */
 int slr_spmv(slr_ctx *c, const double *x_dev, double *y_dev, int32_t nrhs, void *hip_stream);

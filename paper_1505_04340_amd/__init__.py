@@ -107,7 +107,14 @@ slr_apply_dd = _sig("slr_apply_dd", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_apply_dd_noalloc = _sig("slr_apply_dd_noalloc", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_solve = _sig("slr_solve", ctypes.c_int, [_P, _P, _P, _I32, ctypes.POINTER(slr_solve_opts),
                                              ctypes.POINTER(slr_solve_info), _P])
-slr_solve_workspace_bytes = _sig("slr_solve_workspace_bytes", ctypes.c_size_t, [_P, _I32, _I32])
+slr_solve_workspace_bytes = _sig("slr_solve_workspace_bytes", ctypes.c_size_t,
+                                 [_P, _I32, ctypes.POINTER(slr_solve_opts)])
+slr_trim = _sig("slr_trim", ctypes.c_int, [_P])
+slr_export_setup = _sig("slr_export_setup", ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)])
+slr_import = _sig("slr_import", ctypes.c_int, [_P, ctypes.c_size_t, _P, ctypes.POINTER(_P)])
+SLR_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+SLR_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+slr_set_allocator = _sig("slr_set_allocator", None, [SLR_ALLOC_FN, SLR_FREE_FN, _P])
 slr_query = _sig("slr_query", ctypes.c_int, [_P, ctypes.POINTER(slr_info)])
 slr_export = _sig("slr_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P])
 slr_spmv = _sig("slr_spmv", ctypes.c_int, [_P, _P, _P, _I32, _P])
@@ -127,6 +134,7 @@ EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_anal
             "slr_grow_lowrank", "slr_refactor",
             "slr_time_kernel", "slr_apply", "slr_apply_dd", "slr_apply_dd_noalloc",
             "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_spmv",
+            "slr_trim", "slr_export_setup", "slr_import", "slr_set_allocator",
             "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
             "slr_batch_active", "slr_batch_bytes", "slr_batch_destroy", "slr_destroy",
             "slr_strerror", "slr_last_error", "slr_device_lds_bytes")
@@ -190,6 +198,60 @@ def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fa
     return o
 
 
+class TorchAllocator:
+    """Routes the library's device allocations through PyTorch's caching
+    allocator (slr_set_allocator), so that PyTorch owns that memory.  Keeps
+    count of the calls and of the bytes it holds for the library."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.allocs = 0
+        self.frees = 0
+        self.live = {}
+        self._afn = SLR_ALLOC_FN(self._alloc)
+        self._ffn = SLR_FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self._torch
+            p = t.cuda.caching_allocator_alloc(int(nbytes), t.cuda.current_device(), t.cuda.current_stream())
+        except Exception:
+            return None
+        self.allocs += 1
+        self.live[p] = int(nbytes)
+        return p
+
+    def _free(self, ptr, user):
+        self.frees += 1
+        self.live.pop(ptr, None)
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
+
+    def install(self):
+        slr_set_allocator(self._afn, self._ffn, None)
+        return self
+
+
+_ALLOCATOR = None
+
+
+def use_torch_allocator() -> TorchAllocator:
+    """Install (once) and return the PyTorch allocator hook."""
+    global _ALLOCATOR
+    if _ALLOCATOR is None:
+        _ALLOCATOR = TorchAllocator()
+    return _ALLOCATOR.install()
+
+
+def use_hip_allocator():
+    """Back to hipMalloc / hipFree for new allocations (blocks made through
+    the PyTorch hook are still freed through it)."""
+    slr_set_allocator(SLR_ALLOC_FN(0), SLR_FREE_FN(0), None)
+
+
 def analyze(A, part, nparts: int, **opts):
     """Host-only analysis (slr_analyze): (info dict, perm internal->original)."""
     indptr, indices, data, n = _csr_arrays(A)
@@ -236,6 +298,32 @@ class SLR:
                          ctypes.byref(h)), "slr_setup")
         self._pattern = (indptr, indices) if refactor else None
         self._h = h
+        self.info = self.query()
+
+    @classmethod
+    def import_setup(cls, blob: bytes, stream=None) -> "SLR":
+        """A context rebuilt from export_setup()'s bytes (slr_import)."""
+        obj = cls.__new__(cls)
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        h = _P()
+        _check(slr_import(buf, len(blob), _stream(stream), ctypes.byref(h)), "slr_import")
+        obj._h = h
+        obj._pattern = None
+        obj.info = obj.query()
+        obj.n = obj.info["n"]
+        return obj
+
+    def export_setup(self) -> bytes:
+        """The serialised preconditioner (slr_export_setup)."""
+        nb = ctypes.c_size_t(0)
+        _check(slr_export_setup(self._h, None, 0, ctypes.byref(nb)), "slr_export_setup")
+        buf = ctypes.create_string_buffer(nb.value)
+        _check(slr_export_setup(self._h, buf, nb.value, ctypes.byref(nb)), "slr_export_setup")
+        return buf.raw[:nb.value]
+
+    def trim(self):
+        """Release the scratch kept between calls (slr_trim)."""
+        _check(slr_trim(self._h), "slr_trim")
         self.info = self.query()
 
     def close(self):
@@ -373,8 +461,11 @@ class SLR:
         out = [{"iters": i.iters, "status": i.status, "relres": i.relres} for i in infos]
         return (x.view(-1) if vec else x.t()), out
 
-    def workspace_bytes(self, nrhs: int, method: str = "pcg") -> int:
-        return int(slr_solve_workspace_bytes(self._h, nrhs, _METHOD[method]))
+    def workspace_bytes(self, nrhs: int, method: str = "pcg", restart: int = 40) -> int:
+        so = slr_solve_opts()
+        slr_default_solve_opts(ctypes.byref(so))
+        so.method, so.restart = _METHOD[method], restart
+        return int(slr_solve_workspace_bytes(self._h, nrhs, ctypes.byref(so)))
 
 
 class Batch:

@@ -53,6 +53,14 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// compute units of the current device
+int device_cu_count(void) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+  return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+}
+
 // Device address of `scratch` on `dev`, which must be the current device:
 // looked up once per device (hipGetSymbolAddress) and kept.
 int scratch_address(int dev, char **out) {
@@ -70,18 +78,74 @@ int scratch_address(int dev, char **out) {
   return SLR_OK;
 }
 
+// Device memory of the library: hipMalloc / hipFree, or the caller's
+// allocator (slr_set_allocator).  Each block remembers the allocator that
+// made it, so that a change of allocator never frees memory through the
+// wrong one.  Freeing through a caller's allocator first synchronises the
+// device (hipFree's own behaviour), so that the caller may hand the memory
+// out again at once.
+struct AllocHook {
+  slr_alloc_fn alloc = nullptr;
+  slr_free_fn free_ = nullptr;
+  void *user = nullptr;
+};
+std::mutex g_alloc_mu;
+AllocHook g_alloc;
+
+struct DevBlock {
+  void *p = nullptr;
+  size_t bytes = 0;
+  AllocHook by;          // alloc == nullptr: hipMalloc
+};
+
+bool dev_malloc(size_t bytes, DevBlock &b) {
+  AllocHook h;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    h = g_alloc;
+  }
+  b = DevBlock{};
+  void *p = nullptr;
+  if (h.alloc) {
+    p = h.alloc(bytes, h.user);
+    if (!p) return false;
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    return false;
+  }
+  b.p = p;
+  b.bytes = bytes;
+  b.by = h;
+  return true;
+}
+
+void dev_free_all(std::vector<DevBlock> &v) {
+  bool hooked = false;
+  for (const DevBlock &b : v) hooked = hooked || (b.p && b.by.alloc);
+  if (hooked) (void)hipDeviceSynchronize();
+  for (DevBlock &b : v) {
+    if (!b.p) continue;
+    if (b.by.alloc) {
+      if (b.by.free_) b.by.free_(b.p, b.by.user);
+    } else {
+      (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+  }
+  v.clear();
+}
+
 // Device allocations owned by one object, freed together.
 struct DevPool {
-  std::vector<void *> ptrs;
+  std::vector<DevBlock> blocks;
   int64_t bytes = 0;
   template <typename T>
   T *alloc(size_t n) {
     if (n == 0) n = 1;
-    void *p = nullptr;
-    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
-    ptrs.push_back(p);
+    DevBlock b;
+    if (!dev_malloc(n * sizeof(T), b)) return nullptr;
+    blocks.push_back(b);
     bytes += (int64_t)(n * sizeof(T));
-    return (T *)p;
+    return (T *)b.p;
   }
   template <typename T>
   T *upload(const std::vector<T> &v) {
@@ -92,9 +156,20 @@ struct DevPool {
     return p;
   }
   void release() {
-    for (void *p : ptrs) (void)hipFree(p);
-    ptrs.clear();
+    dev_free_all(blocks);
     bytes = 0;
+  }
+};
+
+// A device buffer kept by its owner between calls (Arena).
+struct KeptBuf {
+  std::vector<DevBlock> blk;   // at most one block
+  char *base = nullptr;
+  size_t cap = 0;
+  void release() {
+    dev_free_all(blk);
+    base = nullptr;
+    cap = 0;
   }
 };
 
@@ -104,18 +179,17 @@ struct DevPool {
 // the whole size seen, so that the next call with the same sizes allocates
 // nothing.  Contents are not preserved between calls.
 struct Arena {
-  char *&base;
-  size_t &cap;
+  KeptBuf &kb;
   size_t used = 0, want = 0;
   DevPool extra;
-  Arena(char *&b, size_t &c) : base(b), cap(c) {}
+  explicit Arena(KeptBuf &k) : kb(k) {}
   template <typename T>
   T *alloc(size_t n) {
     if (n == 0) n = 1;
     const size_t b = (n * sizeof(T) + 255) & ~(size_t)255;
     want += b;
-    if (used + b <= cap) {
-      T *p = (T *)(base + used);
+    if (used + b <= kb.cap) {
+      T *p = (T *)(kb.base + used);
       used += b;
       return p;
     }
@@ -123,11 +197,14 @@ struct Arena {
   }
   void release() {
     extra.release();
-    if (want > cap) {
-      if (base) (void)hipFree(base);
-      base = nullptr;
-      cap = 0;
-      if (hipMalloc((void **)&base, want) == hipSuccess) cap = want;
+    if (want > kb.cap) {
+      kb.release();
+      DevBlock b;
+      if (dev_malloc(want, b)) {
+        kb.blk.push_back(b);
+        kb.base = (char *)b.p;
+        kb.cap = want;
+      }
     }
     used = want = 0;
   }
@@ -248,11 +325,9 @@ struct slr_ctx {
   int *hfl = nullptr;
   int32_t hfl_cap = 0;
   // scratch of the Lanczos build, kept between builds
-  char *lz_base = nullptr;
-  size_t lz_cap = 0;
+  KeptBuf lz;
   // scratch of FGMRES, kept between solves
-  char *gm_base = nullptr;
-  size_t gm_cap = 0;
+  KeptBuf gm;
 };
 
 struct slr_batch {
@@ -282,6 +357,42 @@ struct slr_batch {
 namespace {
 
 constexpr int RED_NBLK = 512;   // blocks of the deterministic reductions
+
+// The FGMRES workspace, carved from an Arena (or counted by ArenaCount).
+struct FgmresWS {
+  double *V, *Zb, *Bd, *X, *T, *Hm, *h1, *h2, *cs, *sn, *g, *y, *sc, *part;
+  unsigned int *cnt;
+  int *flags;
+};
+struct ArenaCount {
+  size_t want = 0;
+  template <typename T>
+  T *alloc(size_t n) {
+    want += (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255;
+    return nullptr;
+  }
+};
+template <class AR>
+void fgmres_layout(AR &a, int64_t n, int32_t mr, FgmresWS &w) {
+  w.V = a.template alloc<double>((size_t)n * (mr + 1));
+  w.Zb = a.template alloc<double>((size_t)n * mr);
+  w.Bd = a.template alloc<double>(n);
+  w.X = a.template alloc<double>(n);
+  w.T = a.template alloc<double>(n);
+  w.Hm = a.template alloc<double>((size_t)(mr + 1) * mr);
+  w.h1 = a.template alloc<double>(mr + 1);
+  w.h2 = a.template alloc<double>(mr + 1);
+  w.cs = a.template alloc<double>(mr);
+  w.sn = a.template alloc<double>(mr);
+  w.g = a.template alloc<double>(mr + 1);
+  w.y = a.template alloc<double>(mr);
+  w.sc = a.template alloc<double>(4);
+  w.part = a.template alloc<double>((size_t)RED_NBLK * (mr + 1));
+  w.cnt = a.template alloc<unsigned int>(4);
+  w.flags = a.template alloc<int>(2 * (size_t)mr);
+}
+int32_t fgmres_restart(int32_t restart) { return std::max(1, std::min(restart, 200)); }
+
 
 int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   const int32_t nb = std::max(c->lr_nblk, c->lrm_nblk);
@@ -552,7 +663,7 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   const bool lam_s = c->opts.theta_mode == SLR_THETA_LAMBDA_S;
   const int32_t nb = k0 + steps;   // basis columns: kept vectors, then the Lanczos vectors
   const bool pro = c->opts.reorth == SLR_REORTH_PARTIAL && k0 == 0;
-  Arena tmp(c->lz_base, c->lz_cap);
+  Arena tmp(c->lz);
   double *V = tmp.alloc<double>((size_t)s * nb);
   double *Wl = tmp.alloc<double>(s);
   double *T = tmp.alloc<double>(s);
@@ -1059,6 +1170,222 @@ int lowrank_done(slr_ctx *c, double t1, hipStream_t st) {
   return SLR_OK;
 }
 
+// ---- serialised setups (slr_export_setup / slr_import) -------------------
+// Layout: the 8-byte magic, a u64 payload length, the payload, and the
+// FNV-1a 64 hash of the payload.  The payload is a sequence of records:
+// scalars as their bytes, host arrays and device arrays as a u64 byte count
+// followed by the bytes.  Device arrays are written in a fixed order (the
+// list below), so import can allocate and fill them in that order and
+// point the same fields at them.
+constexpr char kSetupMagic[8] = {'S', 'L', 'R', 'S', 'E', 'T', 'v', '1'};
+
+uint64_t fnv1a(const uint8_t *p, size_t n) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+struct Writer {
+  std::vector<uint8_t> out;
+  void raw(const void *p, size_t n) {
+    const uint8_t *b = (const uint8_t *)p;
+    out.insert(out.end(), b, b + n);
+  }
+  template <typename T>
+  void pod(const T &x) {
+    raw(&x, sizeof(T));
+  }
+  template <typename T>
+  void vec(const std::vector<T> &v) {
+    pod<uint64_t>(v.size() * sizeof(T));
+    raw(v.data(), v.size() * sizeof(T));
+  }
+};
+
+struct Reader {
+  const uint8_t *p;
+  size_t n, pos = 0;
+  bool ok = true;
+  bool take(void *dst, size_t k) {
+    if (!ok || k > n - pos) return ok = false;
+    if (k) std::memcpy(dst, p + pos, k);
+    pos += k;
+    return true;
+  }
+  template <typename T>
+  bool pod(T &x) {
+    return take(&x, sizeof(T));
+  }
+  template <typename T>
+  bool vec(std::vector<T> &v, uint64_t max_bytes = UINT64_MAX) {
+    uint64_t b = 0;
+    if (!pod(b) || b % sizeof(T) != 0 || b > n - pos || b > max_bytes) return ok = false;
+    v.resize(b / sizeof(T));
+    return take(v.data(), b);
+  }
+  // a device-array record: byte count and where its bytes are
+  bool span(const uint8_t *&q, uint64_t &b) {
+    if (!pod(b) || b > n - pos) return ok = false;
+    q = p + pos;
+    pos += b;
+    return true;
+  }
+};
+
+// The device arrays of a context that make up its preconditioner (not the
+// low-rank part, not scratch), in serialisation order.  Absent arrays (w2
+// of a deep interface schedule) are null.
+template <typename TS>
+std::vector<const void **> setup_fields(slr_ctx *c, BlockArrays<TS> &B, SweepArrays<TS> &Cf, SweepArrays<TS> &Cb) {
+  auto f = [](auto &ptr) { return reinterpret_cast<const void **>(const_cast<void *>((const void *)&ptr)); };
+  std::vector<const void **> v = {f(c->perm), f(c->a_rp), f(c->a_ci), f(c->a_v),
+                                  f(B.desc), f(B.lev), f(B.lvb), f(B.data), f(B.e_row), f(B.e_q), f(B.e_val),
+                                  f(B.t_q), f(B.t_j), f(B.t_val)};
+  for (SweepArrays<TS> *S : {&Cf, &Cb})
+    for (const void **q : {f(S->lev), f(S->rows), f(S->rp), f(S->ci), f(S->w), f(S->sc), f(S->w2)}) v.push_back(q);
+  return v;
+}
+
+size_t pool_block_bytes(const DevPool &P, const void *ptr) {
+  for (const DevBlock &b : P.blocks)
+    if (b.p == ptr) return b.bytes;
+  return 0;
+}
+
+int export_setup(const slr_ctx *cc, std::vector<uint8_t> &blob) {
+  slr_ctx *c = const_cast<slr_ctx *>(cc);
+  Writer w;
+  slr_opts o = c->opts;
+  o.lanczos_v0 = nullptr;
+  o.U_in = nullptr;
+  o.lambda_in = nullptr;
+  o.k_in = 0;
+  o.refactor = 0;
+  w.pod(o);
+  w.pod(c->n); w.pod(c->m); w.pod(c->s); w.pod(c->p);
+  w.pod(c->fact_prec); w.pod(c->uk_prec);
+  w.vec(c->cf_lev_h); w.vec(c->cb_lev_h);
+  w.pod(c->cf_nlev); w.pod(c->cb_nlev); w.pod(c->cb_nnz);
+  w.pod(c->c_one_wg); w.pod(c->c_two_level); w.pod(c->nnz_a);
+  w.pod(c->b_max_m); w.pod(c->b_max_lev); w.pod(c->b_max_level_bytes); w.pod(c->b_data_bytes);
+  auto dump = [&](auto &B, auto &Cf, auto &Cb) -> int {
+    w.pod(B.max_m); w.pod(B.max_lev); w.pod(B.max_level_bytes); w.pod(B.max_K); w.pod(B.pack_K);
+    for (const void **q : setup_fields(c, B, Cf, Cb)) {
+      const size_t b = *q ? pool_block_bytes(c->pool, *q) : 0;
+      if (*q && b == 0) return fail(SLR_ERR_ARG, "an array of the context is not in its pool");
+      w.pod<uint64_t>(b);
+      const size_t at = w.out.size();
+      w.out.resize(at + b);
+      if (b) HIPCHK(hipMemcpy(w.out.data() + at, *q, b, hipMemcpyDeviceToHost));
+    }
+    return SLR_OK;
+  };
+  int rc = c->fact_prec == SLR_FP64 ? dump(c->Bd, c->Cfd, c->Cbd) : dump(c->Bf, c->Cff, c->Cbf);
+  if (rc) return rc;
+  // low-rank part (FP64; the stored precision is rebuilt from it on import)
+  w.pod(c->k); w.pod(c->theta);
+  std::vector<double> U((size_t)c->s * c->k);
+  if (!U.empty()) HIPCHK(hipMemcpy(U.data(), c->U64, sizeof(double) * U.size(), hipMemcpyDeviceToHost));
+  w.vec(U); w.vec(c->lam_h); w.vec(c->ritz_h); w.vec(c->alpha_h); w.vec(c->beta_h);
+  w.pod(c->info);
+  blob.clear();
+  blob.insert(blob.end(), kSetupMagic, kSetupMagic + 8);
+  const uint64_t len = w.out.size();
+  blob.insert(blob.end(), (const uint8_t *)&len, (const uint8_t *)&len + 8);
+  blob.insert(blob.end(), w.out.begin(), w.out.end());
+  const uint64_t h = fnv1a(w.out.data(), w.out.size());
+  blob.insert(blob.end(), (const uint8_t *)&h, (const uint8_t *)&h + 8);
+  return SLR_OK;
+}
+
+int import_setup(const uint8_t *buf, size_t bytes, hipStream_t st, slr_ctx **out) {
+  if (bytes < 24 || std::memcmp(buf, kSetupMagic, 8) != 0) return fail(SLR_ERR_ARG, "not a serialised SLR setup");
+  uint64_t len = 0, h = 0;
+  std::memcpy(&len, buf + 8, 8);
+  if (len != bytes - 24) return fail(SLR_ERR_ARG, "serialised setup: length mismatch");
+  std::memcpy(&h, buf + 16 + len, 8);
+  if (h != fnv1a(buf + 16, len)) return fail(SLR_ERR_ARG, "serialised setup: checksum mismatch");
+  Reader r{buf + 16, (size_t)len};
+  slr_ctx *c = new slr_ctx();
+  auto bad = [&](const char *what) {
+    slr_destroy(c);
+    return fail(SLR_ERR_ARG, std::string("serialised setup: ") + what);
+  };
+  (void)hipGetDevice(&c->device);
+  {
+    char *sp = nullptr;
+    (void)scratch_address(c->device, &sp);
+  }
+  r.pod(c->opts);
+  r.pod(c->n); r.pod(c->m); r.pod(c->s); r.pod(c->p);
+  r.pod(c->fact_prec); r.pod(c->uk_prec);
+  r.vec(c->cf_lev_h); r.vec(c->cb_lev_h);
+  r.pod(c->cf_nlev); r.pod(c->cb_nlev); r.pod(c->cb_nnz);
+  r.pod(c->c_one_wg); r.pod(c->c_two_level); r.pod(c->nnz_a);
+  r.pod(c->b_max_m); r.pod(c->b_max_lev); r.pod(c->b_max_level_bytes); r.pod(c->b_data_bytes);
+  if (!r.ok) return bad("truncated header");
+  if (c->n < 0 || c->m < 0 || c->s < 0 || c->m + c->s != c->n || c->p < 1 ||
+      (c->fact_prec != SLR_FP64 && c->fact_prec != SLR_FP32) || c->uk_prec < SLR_FP64 || c->uk_prec > SLR_BF16 ||
+      (int64_t)c->cf_lev_h.size() != c->cf_nlev + 1 || (int64_t)c->cb_lev_h.size() != c->cb_nlev + 1)
+    return bad("inconsistent sizes");
+  c->lds_limit = (size_t)slr_device_lds_bytes();
+  c->n_cu = device_cu_count();
+  auto load = [&](auto &B, auto &Cf, auto &Cb) -> bool {
+    r.pod(B.max_m); r.pod(B.max_lev); r.pod(B.max_level_bytes); r.pod(B.max_K); r.pod(B.pack_K);
+    for (const void **q : setup_fields(c, B, Cf, Cb)) {
+      const uint8_t *src = nullptr;
+      uint64_t b = 0;
+      if (!r.span(src, b)) return false;
+      if (b == 0) {
+        *q = nullptr;
+        continue;
+      }
+      uint8_t *d = c->pool.alloc<uint8_t>(b);
+      if (!d || hipMemcpy(d, src, b, hipMemcpyHostToDevice) != hipSuccess) return false;
+      *q = d;
+    }
+    return true;
+  };
+  const bool ok = c->fact_prec == SLR_FP64 ? load(c->Bd, c->Cfd, c->Cbd) : load(c->Bf, c->Cff, c->Cbf);
+  if (!ok) return bad("device arrays (truncated, or device memory exhausted)");
+  if (pool_block_bytes(c->pool, c->perm) != sizeof(int64_t) * (size_t)std::max<int64_t>(c->n, 1) ||
+      pool_block_bytes(c->pool, c->a_v) != sizeof(double) * (size_t)std::max<int64_t>(c->nnz_a, 1))
+    return bad("array sizes do not match the problem");
+  c->perm_h.resize(c->n);
+  if (c->n) HIPCHK(hipMemcpy(c->perm_h.data(), c->perm, sizeof(int64_t) * c->n, hipMemcpyDeviceToHost));
+  std::vector<double> U;
+  r.pod(c->k); r.pod(c->theta);
+  r.vec(U); r.vec(c->lam_h); r.vec(c->ritz_h); r.vec(c->alpha_h); r.vec(c->beta_h);
+  slr_info info{};
+  r.pod(info);
+  if (!r.ok || r.pos != r.n) return bad("truncated low-rank part");
+  if (c->k < 0 || c->k > 64 || U.size() != (size_t)c->s * c->k || (int32_t)c->lam_h.size() != c->k)
+    return bad("low-rank part does not match the problem");
+  c->info = info;
+  c->U64 = c->lrpool.upload(U.empty() ? std::vector<double>{0.0} : U);
+  if (!c->U64) {
+    slr_destroy(c);
+    return fail(SLR_ERR_OOM, "U");
+  }
+  int rc = finish_lowrank(c, st);
+  if (!rc) rc = ws_ensure(c, c->ws, 1);
+  if (rc) {
+    slr_destroy(c);
+    return rc;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    slr_destroy(c);
+    return fail(SLR_ERR_HIP, "hipStreamSynchronize");
+  }
+  c->info.k = c->k;
+  c->info.theta = c->theta;
+  *out = c;
+  return SLR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1109,13 +1436,6 @@ const char *slr_strerror(int code) {
 }
 
 const char *slr_last_error(void) { return g_err.c_str(); }
-
-static int device_cu_count(void) {
-  int dev = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-  return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-}
 
 int slr_device_lds_bytes(void) {
   int dev = 0;
@@ -1457,8 +1777,8 @@ void slr_destroy(slr_ctx *c) {
   if (!c) return;
   if (c->rf.stage) (void)hipHostFree(c->rf.stage);
   if (c->hst) (void)hipHostFree(c->hst);
-  if (c->lz_base) (void)hipFree(c->lz_base);
-  if (c->gm_base) (void)hipFree(c->gm_base);
+  c->lz.release();
+  c->gm.release();
   if (c->hfl) (void)hipHostFree(c->hfl);
   for (hipEvent_t e : c->pev)
     if (e) (void)hipEventDestroy(e);
@@ -1476,7 +1796,7 @@ int slr_query(const slr_ctx *c, slr_info *info) {
   *info = c->info;
   info->device_bytes =
       c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes + c->rf.pool.bytes +
-      (int64_t)(c->lz_cap + c->gm_cap);
+      (int64_t)(c->lz.cap + c->gm.cap);
   return SLR_OK;
 }
 
@@ -1490,6 +1810,58 @@ int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda, do
   if (beta) std::copy(c->beta_h.begin(), c->beta_h.end(), beta);
   if (U && c->k > 0)
     HIPCHK(hipMemcpy(U, c->U64, sizeof(double) * (size_t)c->s * c->k, hipMemcpyDeviceToHost));
+  return SLR_OK;
+}
+
+int slr_export_setup(const slr_ctx *c, void *buf, size_t cap, size_t *bytes) {
+  if (!c || !bytes) return fail(SLR_ERR_ARG, "null");
+  std::vector<uint8_t> blob;
+  const int rc = export_setup(c, blob);
+  if (rc) return rc;
+  *bytes = blob.size();
+  if (!buf) return SLR_OK;
+  if (cap < blob.size()) return fail(SLR_ERR_ARG, "buffer smaller than the serialised setup (see *bytes)");
+  std::memcpy(buf, blob.data(), blob.size());
+  return SLR_OK;
+}
+
+int slr_import(const void *buf, size_t bytes, void *hip_stream, slr_ctx **out) {
+  if (!buf || !out) return fail(SLR_ERR_ARG, "null");
+  *out = nullptr;
+  return import_setup((const uint8_t *)buf, bytes, S(hip_stream), out);
+}
+
+void slr_set_allocator(slr_alloc_fn alloc, slr_free_fn free_, void *user) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (alloc && free_) {
+    g_alloc.alloc = alloc;
+    g_alloc.free_ = free_;
+    g_alloc.user = user;
+  } else {
+    g_alloc = AllocHook{};
+  }
+}
+
+int slr_trim(slr_ctx *c) {
+  if (!c) return fail(SLR_ERR_ARG, "null");
+  c->lz.release();
+  c->gm.release();
+  c->spool.release();
+  c->scap = 0;
+  c->sX = c->sR = c->sZ = c->sP = c->sQ = c->sS = c->sB = nullptr;
+  c->sst = nullptr;
+  c->spart = c->spart2 = nullptr;
+  c->scnt = nullptr;
+  c->ppool.release();
+  c->pcap = 0;
+  c->pr = c->pz = nullptr;
+  if (c->ws.cap > 1) {
+    c->ws.pool.release();
+    c->ws.W = nullptr;
+    c->ws.cap = 0;
+    const int rc = ws_ensure(c, c->ws, 1);
+    if (rc) return rc;
+  }
   return SLR_OK;
 }
 
@@ -1556,10 +1928,18 @@ int slr_spmv(slr_ctx *c, const double *x_dev, double *y_dev, int32_t nrhs, void 
   return SLR_OK;
 }
 
-size_t slr_solve_workspace_bytes(const slr_ctx *c, int32_t nrhs, int32_t method) {
+size_t slr_solve_workspace_bytes(const slr_ctx *c, int32_t nrhs, const slr_solve_opts *so) {
   if (!c) return 0;
+  slr_solve_opts d;
+  slr_default_solve_opts(&d);
+  if (!so) so = &d;
   size_t n = (size_t)c->n;
-  if (method == SLR_FGMRES) return sizeof(double) * n * (2 * 41 + 4) + sizeof(double) * RED_NBLK * 48;
+  if (so->method == SLR_FGMRES) {
+    ArenaCount ac;
+    FgmresWS fw;
+    fgmres_layout(ac, c->n, fgmres_restart(so->restart), fw);
+    return ac.want;
+  }
   return sizeof(double) * n * nrhs * 7 + sizeof(KState) * nrhs + sizeof(double) * RED_NBLK * nrhs * 5 +
          sizeof(double) * (size_t)c->s * nrhs;
 }
@@ -1740,24 +2120,14 @@ int solve_cg(slr_ctx *c, const double *b_dev, double *x_dev, int32_t nrhs, const
 int solve_fgmres(slr_ctx *c, const double *b_dev, double *x_dev, const slr_solve_opts &so, slr_solve_info *info,
                  hipStream_t st) {
   const int64_t n = c->n;
-  const int32_t mr = std::max(1, std::min(so.restart, 200));
-  Arena tmp(c->gm_base, c->gm_cap);
-  double *V = tmp.alloc<double>((size_t)n * (mr + 1));
-  double *Zb = tmp.alloc<double>((size_t)n * mr);
-  double *Bd = tmp.alloc<double>(n);
-  double *X = tmp.alloc<double>(n);
-  double *T = tmp.alloc<double>(n);
-  double *Hm = tmp.alloc<double>((size_t)(mr + 1) * mr);
-  double *h1 = tmp.alloc<double>(mr + 1);
-  double *h2 = tmp.alloc<double>(mr + 1);
-  double *cs = tmp.alloc<double>(mr);
-  double *sn = tmp.alloc<double>(mr);
-  double *g = tmp.alloc<double>(mr + 1);
-  double *y = tmp.alloc<double>(mr);
-  double *sc = tmp.alloc<double>(4);
-  double *part = tmp.alloc<double>((size_t)RED_NBLK * (mr + 1));
-  unsigned int *cnt = tmp.alloc<unsigned int>(4);
-  int *flags = tmp.alloc<int>(2 * (size_t)mr);
+  const int32_t mr = fgmres_restart(so.restart);
+  Arena tmp(c->gm);
+  FgmresWS fw;
+  fgmres_layout(tmp, n, mr, fw);
+  double *V = fw.V, *Zb = fw.Zb, *Bd = fw.Bd, *X = fw.X, *T = fw.T, *Hm = fw.Hm, *h1 = fw.h1, *h2 = fw.h2;
+  double *cs = fw.cs, *sn = fw.sn, *g = fw.g, *y = fw.y, *sc = fw.sc, *part = fw.part;
+  unsigned int *cnt = fw.cnt;
+  int *flags = fw.flags;
   if (!V || !Zb || !Bd || !X || !T || !Hm || !h1 || !h2 || !cs || !sn || !g || !y || !sc || !part || !cnt ||
       !flags) {
     tmp.release();
