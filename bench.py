@@ -69,29 +69,148 @@ def apply_bytes(info, nrhs, bf, bu, k):
             + nrhs * (2 * info["n"] * 8 + 2 * info["m"] * 8 + 8 * info["s"] * 8))
 
 
-def cpu_baseline(pr, form, budget_s=30.0):
-    """The oracle, single-threaded, on a bounded sample of the same workload:
-    one full step (Lanczos build + PCG solve of the one right-hand side)."""
-    from threadpoolctl import threadpool_limits
+def _oracle_step(pr, form):
+    """One oracle step on the workload: Lanczos build on the resident
+    factors, then the solve of the one right-hand side.  Returns
+    (seconds of the Lanczos build, seconds of the solve, result)."""
     import oracle as O
+    P = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=pr.b_fact, c_fact=pr.c_fact,
+                c_order=form["c_order"], fact_prec=form["fact_prec"])
+    v0 = pr.v0()[P.perm[P.m:]]
+    xs, b = pr.rhs()
+    t0 = time.perf_counter()
+    O.lanczos_lowrank(P, pr.k, pr.lanczos_steps, v0, "lambda_k1")
+    if form["uk_prec"] == "fp32":
+        P.U = O.round_fp32(P.U)
+    elif form["uk_prec"] == "bf16":
+        P.U = O.round_bf16(P.U)
+    t1 = time.perf_counter()
+    res = O.solve(P, b[:, 0], "fcg" if form["method"] == "fcg" else "pcg")
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1, res
+
+
+def _oracle_step_1t(args):
+    from threadpoolctl import threadpool_limits
+    import slr_inputs as si
+    name, form = args
     with threadpool_limits(1):
-        P = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=pr.b_fact, c_fact=pr.c_fact,
-                    c_order=form["c_order"], fact_prec=form["fact_prec"])
-        v0 = pr.v0()[P.perm[P.m:]]
-        xs, b = pr.rhs()
-        t0 = time.perf_counter()
-        O.lanczos_lowrank(P, pr.k, pr.lanczos_steps, v0, "lambda_k1")
-        if form["uk_prec"] == "fp32":
-            P.U = O.round_fp32(P.U)
-        elif form["uk_prec"] == "bf16":
-            P.U = O.round_bf16(P.U)
-        t1 = time.perf_counter()
-        res = O.solve(P, b[:, 0], "fcg" if form["method"] == "fcg" else "pcg")
-        t2 = time.perf_counter()
-    return {"value": 1.0 / (t2 - t0), "unit": "solves/s", "cores": 1, "kind": "oracle",
+        tl, ts, res = _oracle_step(si.make_config(name), form)
+    return tl + ts
+
+
+def host_cpu():
+    """Model name and usable cores of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def cpu_baseline(pr, form, runs=3, max_procs=15):
+    """The oracle as it stands, on the GPU machine's host, on a bounded sample of
+    the same workload: one full step (Lanczos build + PCG solve of the one
+    right-hand side).  Two legs: one thread (median of `runs` steps), and
+    all usable cores as independent oracle processes, one step each, one
+    thread each (whole-job throughput; the oracle's loops are serial, so
+    cores add throughput over right-hand sides, not speed per solve)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    from threadpoolctl import threadpool_limits
+    model, cores = host_cpu()
+    times, lan, sol = [], [], []
+    res = None
+    with threadpool_limits(1):
+        for _ in range(runs):
+            tl, ts, res = _oracle_step(pr, form)
+            times.append(tl + ts)
+            lan.append(tl)
+            sol.append(ts)
+    med = float(np.median(times))
+    procs = max(1, min(cores, max_procs))
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=procs, mp_context=multiprocessing.get_context("fork")) as ex:
+        per = list(ex.map(_oracle_step_1t, [(pr.name, form)] * procs))
+    wall = time.perf_counter() - t0
+    return {"value": round(1.0 / med, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": (f"one full step on the same workload (oracle Lanczos {pr.lanczos_steps} steps "
-                       f"{t1 - t0:.2f} s + PCG {res.iters} its {t2 - t1:.2f} s), 1 thread"),
-            "oracle_iters": res.iters, "oracle_relres": res.true_relres}
+                       f"{np.median(lan):.2f} s + PCG {res.iters} its {np.median(sol):.2f} s), 1 thread, "
+                       f"median of {runs}"),
+            "host_cpu": model, "host_cores": cores, "runs_s": [round(t, 3) for t in times],
+            "oracle_iters": res.iters, "oracle_relres": res.true_relres,
+            "all_cores": {"value": round(procs / wall, 4), "unit": "solves/s", "cores": procs,
+                          "sample": f"{procs} independent oracle steps in {procs} processes (1 thread each), "
+                                    f"wall {wall:.2f} s incl. process start and setup; per-step "
+                                    f"median {np.median(per):.2f} s"}}
+
+
+def roofline_block(achieved_gbs, ab, ms, kernel):
+    return {"bound": "hbm", "achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": kernel,
+            "algorithmic_bytes_per_launch": int(ab), "avg_launch_ms": round(ms, 5)}
+
+
+def multi_rhs_apply(P, torch, nrhs=32, reps=10):
+    """The 2-D diffusion 1024^2 workload (n = 1.05M, 256 uneven subdomains,
+    k = 64 from 320 Lanczos steps): one apply of 32 right-hand sides in one
+    launch sequence, mixed form (FP32 factors, BF16 U_k on matrix cores) and
+    FP64 form; algorithmic bytes as for the 64^3 apply."""
+    import slr_inputs as si
+    pr = si.make_config("diffusion2d_1024")
+    out = {"workload": "2-D diffusion -div(e^g grad u) 1024^2 (n=1048576), 16x16 random cuts (256 subdomains), "
+                       f"IC(0) B_i and C (multicolour), k=64 from 320 Lanczos steps, {nrhs} RHS in one apply"}
+    for name, fp, up in (("mixed", "fp32", "bf16"), ("fp64", "fp64", "fp64")):
+        G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+                  c_fact=pr.c_fact, c_order="multicolor", fact_prec=fp, uk_prec=up, v0=pr.v0())
+        torch.cuda.synchronize()
+        info = G.query()
+        ms = G.time_kernel("apply", nrhs, reps)
+        st = {s: round(G.time_kernel(s, nrhs, reps), 5) for s in ("bsolve1", "lowrank", "bsolve2")}
+        bf = 8 if fp == "fp64" else 4
+        bu = {"fp64": 8, "fp32": 4, "bf16": 2}[up]
+        ab = apply_bytes(info, nrhs, bf, bu, info["k"])
+        gbs = ab / (ms * 1e-3) / 1e9
+        out[name] = {"apply_us": round(ms * 1e3, 2), "algorithmic_bytes": int(ab), "GBs": round(gbs, 1),
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "stage_ms": st,
+                     "roofline": roofline_block(gbs, ab, ms, "whole apply (B solves, sweeps, rank-k)")}
+        log(f"[bench:multi] {name}: apply {ms * 1e3:.1f} us = {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% "
+            f"of peak); stages {st}")
+        del G
+        torch.cuda.empty_cache()
+    return out
+
+
+def apply_profile(P, torch, name, form, nrhs, reps):
+    """Only set up one workload and time its apply (for profiler runs)."""
+    import slr_inputs as si
+    pr = si.make_config(name)
+    fp, up = {"fp64": ("fp64", "fp64"), "fp32": ("fp32", "fp32"), "mixed": ("fp32", "bf16")}[form]
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order="multicolor", fact_prec=fp, uk_prec=up, v0=pr.v0())
+    torch.cuda.synchronize()
+    info = G.query()
+    ms = G.time_kernel("apply", nrhs, reps)
+    stages = {s: round(G.time_kernel(s, nrhs, reps), 5) for s in ("bsolve1", "cfwd", "lowrank", "cbwd", "bsolve2")}
+    bf = 8 if fp == "fp64" else 4
+    bu = {"fp64": 8, "fp32": 4, "bf16": 2}[up]
+    ab = apply_bytes(info, nrhs, bf, bu, info["k"])
+    bb = bsolve_bytes(info, nrhs, bf)
+    print(json.dumps({"workload": name, "form": form, "nrhs": nrhs, "apply_ms": round(ms, 5),
+                      "apply_algorithmic_bytes": int(ab), "apply_GBs": round(ab / (ms * 1e-3) / 1e9, 1),
+                      "bsolve1_algorithmic_bytes": int(bb),
+                      "bsolve1_GBs": round(bb / (stages["bsolve1"] * 1e-3) / 1e9, 1),
+                      "stage_ms": stages, "s": info["s"], "m": info["m"], "p": info["p"], "k": info["k"],
+                      "nnz_LB": info["nnz_LB"], "nnz_LC": info["nnz_LC"], "nnz_E": info["nnz_E"]}))
 
 
 def measure_form(P, pr, form, steps, warmup, v0, bd, xs, log_prefix):
@@ -193,8 +312,13 @@ def large_apply(P, torch, reps=20):
         bu = 8 if up == "fp64" else 4
         ab = apply_bytes(info, 1, bf, bu, info["k"])
         gbs = ab / (ms * 1e-3) / 1e9
+        bb = bsolve_bytes(info, 1, bf)
+        bms = G.time_kernel("bsolve1", 1, reps)
         out[name] = {"apply_us": round(ms * 1e3, 2), "algorithmic_bytes": int(ab), "GBs": round(gbs, 1),
-                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "roofline": roofline_block(gbs, ab, ms, "whole apply (B solves, sweeps, rank-k)"),
+                     "bsolve_roofline": roofline_block(bb / (bms * 1e-3) / 1e9, bb, bms,
+                                                       "k_bsolve (batched B_i solves + E^T epilogue)")}
         log(f"[bench:large] {name}: apply {ms * 1e3:.1f} us = {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of peak)")
         del G
         torch.cuda.empty_cache()
@@ -291,20 +415,42 @@ def main():
                     help="fp64: measure only the FP64 form (the headline), not the mixed one beside it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--no-multi", action="store_true", help="skip the 1024^2 32-RHS apply measurement")
+    ap.add_argument("--apply-profile", default=None,
+                    help="only set up this workload and time its apply (for profiler runs)")
+    ap.add_argument("--apply-form", choices=("fp64", "fp32", "mixed"), default="fp64")
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.apply_profile:
+        import torch
+        import paper_1505_04340_amd as P
+        torch.cuda.set_device(0)
+        apply_profile(P, torch, args.apply_profile, args.apply_form, args.nrhs, args.reps)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is a design note, not a built path)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    import paper_1505_04340_amd as P
     import slr_inputs as si
 
     pr = si.make_config(args.config)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the all-cores leg forks oracle
+        # processes, which must not inherit an open device
+        log("[bench] CPU baseline (oracle: 1 thread, then all cores) ...")
+        cpu = cpu_baseline(pr, FORMS["fp64"])
+        log(f"[bench] CPU baseline {cpu['value']:.4f} solves/s (1 thread), "
+            f"{cpu['all_cores']['value']:.3f} solves/s ({cpu['all_cores']['cores']} processes)")
+
+    import torch
+    import paper_1505_04340_amd as P
+
     torch.cuda.set_device(0)
     log(f"[bench] {pr.name} n={pr.n} p={pr.nparts} k={pr.k}; device LDS per workgroup "
         f"{P.slr_device_lds_bytes()} bytes")
@@ -349,12 +495,12 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_large:
         out["large_apply"] = large_apply(P, torch)
+    if not args.no_multi:
+        out["multi_rhs_apply"] = multi_rhs_apply(P, torch)
     if not args.no_serve:
         out["serving"] = serving(P, torch, args.serve_requests)
-    if not args.no_cpu_baseline:
-        log("[bench] CPU baseline (oracle, 1 thread) ...")
-        out["cpu_baseline"] = cpu_baseline(pr, FORMS["fp64"])
-        log(f"[bench] CPU baseline {out['cpu_baseline']['value']:.4f} solves/s")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
