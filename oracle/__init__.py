@@ -111,17 +111,54 @@ def greedy_colors(C: sp.csr_matrix) -> np.ndarray:
     return col
 
 
-def dd_ordering(A: sp.csr_matrix, part: np.ndarray, nparts: int, c_order: str = "subdomain"):
+def min_degree_order(M: sp.csr_matrix) -> np.ndarray:
+    """READING for the AMD ordering of each B_i before ICT / ILDLT (Sec. 6
+    reorders every B_i by approximate minimum degree to reduce fill): the
+    minimum degree ordering that AMD approximates, with exact degrees.
+    Eliminating a node joins its remaining neighbours into a clique (the
+    elimination graph); each step eliminates the remaining node of smallest
+    degree in that graph, the smallest index among equal degrees.  Returns
+    the elimination order (new -> old local index)."""
+    import heapq
+    n = M.shape[0]
+    adj = [set(M.indices[M.indptr[i]:M.indptr[i + 1]].tolist()) - {i} for i in range(n)]
+    heap = [(len(adj[i]), i) for i in range(n)]
+    heapq.heapify(heap)
+    done = np.zeros(n, dtype=bool)
+    order = []
+    while heap:
+        d, p = heapq.heappop(heap)
+        if done[p] or d != len(adj[p]):
+            continue            # stale entry
+        done[p] = True
+        order.append(p)
+        nb = adj[p]
+        for u in nb:
+            adj[u].discard(p)
+            adj[u] |= nb - {u}
+            heapq.heappush(heap, (len(adj[u]), u))
+        adj[p] = set()
+    return np.array(order, dtype=np.int64)
+
+
+def dd_ordering(A: sp.csr_matrix, part: np.ndarray, nparts: int, c_order: str = "subdomain",
+                b_order: str = "natural"):
     """Global DD ordering of eq. (Global): interiors u_1..u_p by subdomain,
     then the interface y.  READING: ascending original index inside each
     group; interface grouped by owner subdomain 0..p-1 with separator nodes
     last (eq. Global2 with y = [y_1; ...; y_p]).  With c_order='multicolor'
-    the interface is additionally stably sorted by greedy colour.
+    the interface is additionally stably sorted by greedy colour.  With
+    b_order='mindeg' the interior of each subdomain is in the minimum degree
+    order of its B_i (min_degree_order) instead of ascending index.
     Returns (perm new->old, interior offsets [p+1], interface offsets
     [p+2] (last group = separator), colours or None)."""
     iface, owner = classify(A, part, nparts)
     idx = np.arange(A.shape[0])
     inter = [idx[(~iface) & (owner == q)] for q in range(nparts)]
+    if b_order == "mindeg":
+        inter = [g[min_degree_order(A[g][:, g].tocsr())] for g in inter]
+    elif b_order != "natural":
+        raise OracleError("ARG", b_order)
     ifc = [idx[iface & (owner == q)] for q in range(nparts)] + [idx[iface & (owner < 0)]]
     off_b = np.concatenate([[0], np.cumsum([len(a) for a in inter])])
     off_y = np.concatenate([[0], np.cumsum([len(a) for a in ifc])])
@@ -389,7 +426,7 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
           c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
           fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
           lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "partial",
-          droptol: float = 1e-3, seed: int = 7) -> SLR:
+          droptol: float = 1e-3, seed: int = 7, b_order: str = "natural") -> SLR:
     """Build the SLR preconditioner (Sec. 4 and Sec. 5).
 
     A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
@@ -404,7 +441,8 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     lambda_{k+1} <= 1 - 1/K among the Ritz values (eq. condk).  reorth:
     Lanczos with full ("full") or partial ("partial", Sec. 5.1)
     reorthogonalisation.  b_fact / c_fact "ict" (and "ildlt" for B): threshold
-    factors with drop tolerance droptol (factorize)."""
+    factors with drop tolerance droptol (factorize).  b_order "natural" or
+    "mindeg" (the minimum degree order of each B_i, dd_ordering)."""
     if theta_mode == "eps" and not eps > 0.0:
         raise OracleError("ARG", "theta_mode eps needs eps > 0")
     if isinstance(A, tuple):
@@ -413,7 +451,7 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     A = sp.csr_matrix(A)
     if abs(A - A.T).max() > 0:
         raise OracleError("NOT_SYMMETRIC", "A must be symmetric")
-    perm, off_b, off_y, colors = dd_ordering(A, part, nparts, c_order)
+    perm, off_b, off_y, colors = dd_ordering(A, part, nparts, c_order, b_order)
     m = int(off_b[-1])
     s = A.shape[0] - m
     Ap = A[perm][:, perm].tocsr()
