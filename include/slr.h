@@ -72,6 +72,11 @@ enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1, SLR_THETA_EPS = 2, SLR_THETA
  * the 1-norm of column j of the lower triangle). */
 enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2, SLR_FACT_ICT = 3, SLR_FACT_ILDLT = 4 };
 enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1 };
+/* Order of each subdomain's interior (the rows of B_i): ascending original
+ * index, or the minimum degree order of B_i's graph (Sec. 6 reorders every
+ * B_i by approximate minimum degree before ICT / ILDLT; here exact degrees
+ * on the elimination graph, the smallest index among equal degrees). */
+enum { SLR_BORDER_NATURAL = 0, SLR_BORDER_MINDEG = 1 };
 enum { SLR_FP64 = 0, SLR_FP32 = 1, SLR_BF16 = 2 };
 enum { SLR_PCG = 0, SLR_FCG = 1, SLR_FGMRES = 2 };
 /* Reorthogonalisation of the Lanczos build (Sec. 5.1): two classical
@@ -134,6 +139,10 @@ typedef struct {
   /* drop tolerance of the ICT / ILDLT factors (>= 0; 0 keeps every entry,
      i.e. the exact factorisation).  Default 1e-3. */
   double droptol;
+  /* SLR_BORDER_NATURAL | SLR_BORDER_MINDEG: order of the rows of each B_i
+     (default NATURAL); every factor, level schedule and refactorisation
+     plan follows it.  Other values are SLR_ERR_ARG. */
+  int32_t b_order;
 } slr_opts;
 
 typedef struct {

@@ -47,6 +47,8 @@ _FACT = {"chol": SLR_FACT_CHOL, "ic0": SLR_FACT_IC0, "ildlt0": SLR_FACT_ILDLT0, 
          "ildlt": SLR_FACT_ILDLT}
 _PREC = {"fp64": SLR_FP64, "fp32": SLR_FP32, "bf16": SLR_BF16}
 _CORD = {"subdomain": SLR_CORDER_SUBDOMAIN, "multicolor": SLR_CORDER_MULTICOLOR}
+SLR_BORDER_NATURAL, SLR_BORDER_MINDEG = 0, 1
+_BORD = {"natural": SLR_BORDER_NATURAL, "mindeg": SLR_BORDER_MINDEG}
 _THETA = {"lambda_k1": SLR_THETA_LAMBDA_K1, "zero": SLR_THETA_ZERO, "eps": SLR_THETA_EPS, "lambda_s": SLR_THETA_LAMBDA_S}
 _METHOD = {"pcg": SLR_PCG, "fcg": SLR_FCG, "fgmres": SLR_FGMRES}
 _REORTH = {"full": SLR_REORTH_FULL, "partial": SLR_REORTH_PARTIAL}
@@ -64,7 +66,7 @@ class slr_opts(ctypes.Structure):
                 ("c_fact", _I32), ("c_order", _I32), ("fact_prec", _I32), ("uk_prec", _I32),
                 ("seed", _U64), ("lanczos_v0", _P), ("k_in", _I32), ("U_in", _P),
                 ("lambda_in", _P), ("theta_in", _D), ("eps", _D), ("cond_K", _D), ("reorth", _I32),
-                ("refactor", _I32), ("droptol", _D)]
+                ("refactor", _I32), ("droptol", _D), ("b_order", _I32)]
 
 
 class slr_solve_opts(ctypes.Structure):
@@ -180,7 +182,7 @@ def _csr_arrays(A):
 
 def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fact="ic0",
                c_order="subdomain", fact_prec="fp64", uk_prec="fp64", seed=7, eps=0.0, cond_K=0.0,
-               reorth=None, refactor=False, droptol=1e-3):
+               reorth=None, refactor=False, droptol=1e-3, b_order="natural"):
     o = slr_opts()
     slr_default_opts(ctypes.byref(o))
     o.k = k
@@ -195,6 +197,7 @@ def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fa
         o.reorth = _REORTH[reorth]
     o.refactor = 1 if refactor else 0
     o.droptol = float(droptol)
+    o.b_order = _BORD[b_order]
     return o
 
 
@@ -272,12 +275,13 @@ class SLR:
                  theta_mode: str = "lambda_k1", b_fact: str = "ic0", c_fact: str = "ic0",
                  c_order: str = "subdomain", fact_prec: str = "fp64", uk_prec: str = "fp64",
                  v0=None, seed: int = 7, lowrank=None, eps: float = 0.0, cond_K: float = 0.0,
-                 reorth: str | None = None, refactor: bool = False, droptol: float = 1e-3, stream=None):
+                 reorth: str | None = None, refactor: bool = False, droptol: float = 1e-3,
+                 b_order: str = "natural", stream=None):
         indptr, indices, data, n = _csr_arrays(A)
         self.n = n
         part = np.ascontiguousarray(part, dtype=np.int32)
         o = _make_opts(k, lanczos_steps, theta_mode, b_fact, c_fact, c_order, fact_prec, uk_prec, seed, eps, cond_K,
-                       reorth, refactor, droptol)
+                       reorth, refactor, droptol, b_order)
         keep = []
         if v0 is not None:
             v0 = np.ascontiguousarray(v0, dtype=np.float64)

@@ -836,14 +836,39 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
 // Fixed-width sweeps: levels wider than 64 * rec_passes(K) rows are cut into
 // consecutive sub-levels of at most that many rows (the rows of a level are
 // independent, so the schedule stays valid and the arithmetic unchanged).
-Sweep split_levels(const Sweep &sw, int32_t Kfix) {
+// Bytes of one ELL level segment of L rows of width K (layout in pack_sweep).
+int64_t ell_segment_bytes(int64_t L, int64_t K, int64_t ts) {
+  return pad16h(kEllHeaderBytes + pad8h(2 * L) + pad8h(ts * L) + pad8h(2 * K * L) + ts * K * L);
+}
+
+// Rows of one level are independent, so any split of a level is a valid
+// schedule.  Fixed-width records: levels wider than 64 * rec_passes(K) rows
+// are split (one straight-line pass per lane).  ELL form: each level is cut
+// into consecutive pieces of at most kEllLevelBytes (or one row), each
+// padded only to its own widest row.
+Sweep split_levels(const Sweep &sw, int32_t Kfix, int64_t ts) {
   Sweep out = sw;
-  if (Kfix <= 0) return out;
-  const int32_t cap = 64 * rec_passes(Kfix);
   out.levptr.assign(1, 0);
-  for (int32_t l = 0; l < sw.nlev; ++l)
-    for (int32_t a = sw.levptr[l]; a < sw.levptr[l + 1]; a += cap)
-      out.levptr.push_back(std::min(a + cap, sw.levptr[l + 1]));
+  for (int32_t l = 0; l < sw.nlev; ++l) {
+    const int32_t a = sw.levptr[l], b = sw.levptr[l + 1];
+    if (Kfix > 0) {
+      const int32_t cap = 64 * rec_passes(Kfix);
+      for (int32_t t = a; t < b; t += cap) out.levptr.push_back(std::min(t + cap, b));
+      continue;
+    }
+    int32_t t0 = a, K = 0;
+    for (int32_t t = a; t < b; ++t) {
+      const int32_t Kt = std::max(K, sw.rp[t + 1] - sw.rp[t]);
+      if (t > t0 && ell_segment_bytes(t + 1 - t0, Kt, ts) > kEllLevelBytes) {
+        out.levptr.push_back(t);
+        t0 = t;
+        K = sw.rp[t + 1] - sw.rp[t];
+      } else {
+        K = Kt;
+      }
+    }
+    out.levptr.push_back(b);
+  }
   out.nlev = (int32_t)out.levptr.size() - 1;
   if (sw.levptr.empty()) out.levptr.clear();
   return out;
@@ -908,12 +933,18 @@ void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::
         }
       }
     } else {
-      const int64_t o_sc = pad8h(2 * L), o_ci = o_sc + pad8h((int64_t)sizeof(TS) * L);
+      // this level's own width
+      int32_t Kl = 0;
+      for (int32_t j = 0; j < L; ++j) Kl = std::max(Kl, sw.rp[a + j + 1] - sw.rp[a + j]);
+      const int32_t K = Kl;
+      const int64_t o_rows = kEllHeaderBytes;
+      const int64_t o_sc = o_rows + pad8h(2 * L), o_ci = o_sc + pad8h((int64_t)sizeof(TS) * L);
       const int64_t o_w = o_ci + pad8h(2 * (int64_t)K * L);
-      size = pad16h(o_w + (int64_t)sizeof(TS) * K * L);
+      size = ell_segment_bytes(L, K, sizeof(TS));
       data.resize(offset + pos + size, 0);
       uint8_t *base = data.data() + offset + pos;
-      uint16_t *rows = reinterpret_cast<uint16_t *>(base);
+      *reinterpret_cast<int32_t *>(base) = K;
+      uint16_t *rows = reinterpret_cast<uint16_t *>(base + o_rows);
       TS *sc = reinterpret_cast<TS *>(base + o_sc);
       uint16_t *ci = reinterpret_cast<uint16_t *>(base + o_ci);
       TS *w = reinterpret_cast<TS *>(base + o_w);
@@ -962,7 +993,7 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
     d.m = b.m;
     if (b.m > 65535) ok = false;   // uint16 local indices
     max_m = std::max(max_m, b.m);
-    const Sweep fs = split_levels(b.fwd, Kfix), bs = split_levels(b.bwd, Kfix);
+    const Sweep fs = split_levels(b.fwd, Kfix, sizeof(TS)), bs = split_levels(b.bwd, Kfix, sizeof(TS));
     max_lev = std::max({max_lev, fs.nlev, bs.nlev});
     d.f_nlev = fs.nlev;
     d.f_lev = (int32_t)lev.size();
@@ -1469,6 +1500,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   prm.c_order = o->c_order;
   prm.fact_prec = o->fact_prec;
   prm.droptol = o->droptol;
+  prm.b_order = o->b_order;
   prm.plan = o->refactor != 0;
   if (o->refactor && !((o->b_fact == SLR_FACT_IC0 || o->b_fact == SLR_FACT_ILDLT0) && o->c_fact == SLR_FACT_IC0))
     return fail(SLR_ERR_ARG, "refactor needs zero-fill factors (IC0 / ILDLT0 for B, IC0 for C)");
@@ -1743,6 +1775,7 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
   prm.c_order = o->c_order;
   prm.fact_prec = o->fact_prec;
   prm.droptol = o->droptol;
+  prm.b_order = o->b_order;
   std::string err;
   int rc = host_setup(A->n, A->rowptr, A->col, A->val, part, p, prm, H, err);
   if (rc) return fail(rc, err);

@@ -22,7 +22,9 @@ namespace slr {
 // entries:
 //     idx   int32[L][KR]       [row, c_0, .., c_{K-1}, pad]  local indices
 //     wts   TS[L][KR]          [sc, w_0, .., w_{K-1}, pad]   scale, weights
-// Any width K (the sweep's widest row), ELL form:
+// Any width, ELL form, K = the widest row of the level (levels are cut into
+// pieces of at most kEllLevelBytes on the host):
+//     K     int32 (in a 16-byte header)
 //     rows  uint16[L]          local row index
 //     sc    TS[L]              row scale
 //     ci    uint16[K*L]        column of entry e of row j at [e*L + j]
@@ -83,6 +85,9 @@ struct BlockArrays {
 // the end: one 16-byte slot per lane of a wave, so that such stores from one
 // instruction never hit the same bank.
 constexpr int kStageDummyBytes = 1024;
+// ELL level segments: header bytes and the largest piece of a level
+constexpr int kEllHeaderBytes = 16;
+constexpr int kEllLevelBytes = 8192;
 
 // Entries of a fixed-width row record: the row plus K columns, rounded up to
 // a multiple of 4 so that records are whole 16-byte vectors.

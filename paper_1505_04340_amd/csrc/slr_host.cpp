@@ -8,8 +8,12 @@
 #include "slr_host.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <iterator>
 #include <numeric>
+#include <set>
+#include <thread>
 
 #include "slr.h"
 
@@ -324,6 +328,38 @@ int factor_block(int kind, int32_t n, std::vector<int32_t> &rp, std::vector<int3
   return incomplete_factor(F);
 }
 
+// Minimum degree ordering (the ordering that AMD approximates, Sec. 6 uses it
+// on every B_i before ICT / ILDLT) with exact degrees: eliminating a node
+// joins its remaining neighbours into a clique, and each step takes the
+// remaining node of smallest degree, the smallest index among equal
+// degrees.  adj: sorted neighbour lists without the node itself.  Returns
+// the elimination order (new -> old local index).
+std::vector<int32_t> min_degree_order(std::vector<std::vector<int32_t>> adj) {
+  const int32_t n = (int32_t)adj.size();
+  std::set<std::pair<int32_t, int32_t>> ready;   // (degree, node)
+  for (int32_t i = 0; i < n; ++i) ready.insert({(int32_t)adj[i].size(), i});
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<int32_t> merged;
+  while (!ready.empty()) {
+    const int32_t p = ready.begin()->second;
+    ready.erase(ready.begin());
+    order.push_back(p);
+    const std::vector<int32_t> nb = std::move(adj[p]);
+    adj[p].clear();
+    for (int32_t u : nb) {
+      ready.erase({(int32_t)adj[u].size(), u});
+      merged.clear();
+      std::set_union(adj[u].begin(), adj[u].end(), nb.begin(), nb.end(), std::back_inserter(merged));
+      merged.erase(std::remove_if(merged.begin(), merged.end(), [&](int32_t x) { return x == u || x == p; }),
+                   merged.end());
+      adj[u].swap(merged);
+      ready.insert({(int32_t)adj[u].size(), u});
+    }
+  }
+  return order;
+}
+
 }  // namespace
 
 int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
@@ -361,6 +397,42 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
   // ascending original index inside each group
   std::vector<std::vector<int64_t>> inner(p), ifc(p);
   for (int64_t i = 0; i < n; ++i) (iface[i] ? ifc : inner)[part[i]].push_back(i);
+  if (prm.b_order == SLR_BORDER_MINDEG) {
+    // each interior in the minimum degree order of its B_i (the subdomains
+    // are independent: one host thread per subdomain at a time)
+    std::vector<int32_t> loc(n, -1);
+    for (int32_t q = 0; q < p; ++q)
+      for (size_t t = 0; t < inner[q].size(); ++t) loc[inner[q][t]] = (int32_t)t;
+    auto order_block = [&](int32_t q) {
+      const std::vector<int64_t> &g = inner[q];
+      std::vector<std::vector<int32_t>> adj(g.size());
+      for (size_t t = 0; t < g.size(); ++t) {
+        for (int64_t e = rowptr[g[t]]; e < rowptr[g[t] + 1]; ++e) {
+          const int64_t j = col[e];
+          if (j != g[t] && !iface[j] && part[j] == q) adj[t].push_back(loc[j]);
+        }
+        std::sort(adj[t].begin(), adj[t].end());
+      }
+      const std::vector<int32_t> o = min_degree_order(std::move(adj));
+      std::vector<int64_t> g2(g.size());
+      for (size_t t = 0; t < g.size(); ++t) g2[t] = g[o[t]];
+      return g2;
+    };
+    std::vector<std::vector<int64_t>> ordered(p);
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+      for (int32_t q = next++; q < p; q = next++) ordered[q] = order_block(q);
+    };
+    const int32_t nth = (int32_t)std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+    std::vector<std::thread> pool;
+    for (int32_t t = 1; t < std::min(nth, p); ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
+    inner.swap(ordered);
+  } else if (prm.b_order != SLR_BORDER_NATURAL) {
+    err = "unknown b_order";
+    return SLR_ERR_ARG;
+  }
   H.perm.clear();
   H.blocks.assign(p, Block());
   for (int32_t q = 0; q < p; ++q) {

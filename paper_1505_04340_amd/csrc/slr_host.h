@@ -86,6 +86,7 @@ struct HostSetup {
 
 struct SetupParams {
   int b_fact = 1, c_fact = 1, c_order = 0, fact_prec = 0;
+  int b_order = 0;         // SLR_BORDER_NATURAL | SLR_BORDER_MINDEG
   double droptol = 1e-3;   // threshold factors (ICT / ILDLT)
   bool plan = false;   // build the refactorisation plans
 };

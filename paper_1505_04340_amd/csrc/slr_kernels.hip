@@ -152,7 +152,9 @@ __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
 // workgroup (rows x columns spread over the threads), read from LDS.  The
 // subtraction order is the same in every variant.
 template <typename TS, typename TC>
-__device__ __forceinline__ void level_from_lds(const uint8_t *base, int L, int K, TC *xs, int XS, int Rg) {
+__device__ __forceinline__ void level_from_lds(const uint8_t *seg, int L, TC *xs, int XS, int Rg) {
+  const int K = *reinterpret_cast<const int32_t *>(seg);
+  const uint8_t *base = seg + kEllHeaderBytes;
   const uint16_t *rows = reinterpret_cast<const uint16_t *>(base);
   const int o_sc = pad8(2 * L);
   const TS *sc = reinterpret_cast<const TS *>(base + o_sc);
@@ -214,7 +216,7 @@ __device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, cons
 // A whole sweep of any width: stage as many consecutive level segments as
 // fit, solve them level by level with the whole workgroup, repeat.
 template <typename TS, typename TC>
-__device__ void sweep_staged(const uint8_t *data, const int32_t *lev, const int32_t *lvb, int nlev, int K,
+__device__ void sweep_staged(const uint8_t *data, const int32_t *lev, const int32_t *lvb, int nlev,
                              TC *xs, int XS, int Rg, uint8_t *stage, int stage_bytes) {
   int l0 = 0;
   while (l0 < nlev) {
@@ -223,7 +225,7 @@ __device__ void sweep_staged(const uint8_t *data, const int32_t *lev, const int3
     stage_copy(data + lvb[l0], lvb[l1] - lvb[l0], data, 0, stage, stage + stage_bytes, threadIdx.x, blockDim.x);
     __syncthreads();
     for (int l = l0; l < l1; ++l) {
-      level_from_lds<TS, TC>(stage + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], K, xs, XS, Rg);
+      level_from_lds<TS, TC>(stage + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], xs, XS, Rg);
       __syncthreads();
     }
     l0 = l1;
@@ -524,8 +526,8 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
     sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, d.f_nlev, B.data + d.b_data, levb, lvbb, d.b_nlev,
                                  xs, XS, Rg, stage, a.stage_bytes, true);
   } else {
-    sweep_staged<TS, TC>(B.data + d.f_data, levf, lvbf, d.f_nlev, d.f_K, xs, XS, Rg, stage, a.stage_bytes);
-    sweep_staged<TS, TC>(B.data + d.b_data, levb, lvbb, d.b_nlev, d.b_K, xs, XS, Rg, stage, a.stage_bytes);
+    sweep_staged<TS, TC>(B.data + d.f_data, levf, lvbf, d.f_nlev, xs, XS, Rg, stage, a.stage_bytes);
+    sweep_staged<TS, TC>(B.data + d.b_data, levb, lvbb, d.b_nlev, xs, XS, Rg, stage, a.stage_bytes);
   }
   if (a.u) {
     for (int t = tid; t < m * Rg; t += nt) {

@@ -29,25 +29,24 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_binding_struct_layout_matches_header(tmp_path):
+    """Every field offset and every struct size of the ctypes structs equals
+    the C compiler's for include/slr.h."""
     import paper_1505_04340_amd as P
+    structs = [P.slr_csr, P.slr_opts, P.slr_solve_opts, P.slr_solve_info, P.slr_info]
+    exprs, want = [], []
+    for st in structs:
+        exprs.append(f"sizeof({st.__name__})")
+        want.append(ctypes.sizeof(st))
+        for f, _ in st._fields_:
+            exprs.append(f"offsetof({st.__name__}, {f})")
+            want.append(getattr(st, f).offset)
     src = tmp_path / "sz.c"
-    src.write_text(
-        '#include <stdio.h>\n#include <stddef.h>\n#include "slr.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
-        "sizeof(slr_csr), sizeof(slr_opts), sizeof(slr_solve_opts), sizeof(slr_solve_info),"
-        "sizeof(slr_info), offsetof(slr_opts, lanczos_v0), offsetof(slr_opts, theta_in),"
-        "offsetof(slr_opts, eps), offsetof(slr_opts, cond_K), offsetof(slr_opts, reorth), offsetof(slr_opts, refactor),"
-        "offsetof(slr_opts, droptol),"
-        "offsetof(slr_info, theta), offsetof(slr_info, lanczos_reorth));return 0;}\n")
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "slr.h"\nint main(void){\n' +
+                   "".join(f'printf("%zu\\n", (size_t){e});\n' for e in exprs) + "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
-    want = [ctypes.sizeof(P.slr_csr), ctypes.sizeof(P.slr_opts), ctypes.sizeof(P.slr_solve_opts),
-            ctypes.sizeof(P.slr_solve_info), ctypes.sizeof(P.slr_info), P.slr_opts.lanczos_v0.offset,
-            P.slr_opts.theta_in.offset, P.slr_opts.eps.offset, P.slr_opts.cond_K.offset,
-            P.slr_opts.reorth.offset, P.slr_opts.refactor.offset, P.slr_opts.droptol.offset, P.slr_info.theta.offset,
-            P.slr_info.lanczos_reorth.offset]
-    assert got == want
+    assert got == want, [(e, g, w) for e, g, w in zip(exprs, got, want) if g != w]
 
 
 def test_host_only_entry_points():

@@ -595,3 +595,45 @@ def test_seeded_start_vector_matches_oracle():
     G7 = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
                c_fact=pr.c_fact, seed=7)
     assert not np.allclose(G7.export()["alpha"][:5], ex["alpha"][:5], rtol=1e-6)
+
+
+# ------------------------------ minimum degree order of the B_i (Sec. 6)
+@pytest.mark.parametrize("bf,cf,prec,name", [("ict", "ict", "fp64", "lap3d_64"), ("ildlt", "ic0", "fp64", "shifted3d_128"),
+                                             ("ict", "ic0", "fp32", "diffusion2d_1024")])
+def test_mindeg_order_threshold_factor_apply(bf, cf, prec, name):
+    """Each B_i in its minimum degree order, then ICT / ILDLT: the device's
+    ordering and fill equal the oracle's exactly, and the apply matches the
+    oracle's own factors with the same low-rank part."""
+    over = {"lap3d_64": dict(N=16, boxes=2), "shifted3d_128": dict(N=20, boxes=2, neg=4),
+            "diffusion2d_1024": dict(N=96, boxes=4)}[name]
+    pr = si.make_config(name, **over)
+    print(f"mindeg apply: {name} {over} {bf}/{cf} {prec}", flush=True)
+    kw = dict(k=8, lanczos_steps=40, b_fact=bf, c_fact=cf, droptol=1e-3, fact_prec=prec, c_order="multicolor",
+              b_order="mindeg")
+    Po = _oracle(pr, **kw)
+    G = _slr(pr, uk_prec=prec, lowrank=(O.round_fp32(Po.U) if prec == "fp32" else Po.U, Po.lam, Po.theta), **kw)
+    ex = G.export()
+    assert (ex["perm"] == Po.perm).all()
+    assert G.info["nnz_LB"] == Po.FB.v.size and G.info["nnz_LC"] == Po.FC.v.size
+    Pi = _oracle(pr, lowrank=(O.round_fp32(Po.U) if prec == "fp32" else Po.U, Po.lam, Po.theta),
+                 **{k: v for k, v in kw.items() if k not in ("k", "lanczos_steps")})
+    r = _rand(pr.n, 2, 17)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_mindeg_order_fgmres_indefinite():
+    """The indefinite shifted problem with minimum degree ordered ILDLT B_i
+    and ICT C (drop tolerance 1e-4): device Lanczos against the oracle's,
+    FGMRES(40) converges with the oracle's iteration count +-1."""
+    pr = si.make_config("shifted3d_128", N=24, boxes=3, neg=10)
+    print("mindeg fgmres: shifted N=24 boxes=3", flush=True)
+    kw = dict(k=24, lanczos_steps=120, b_fact="ildlt", c_fact="ict", droptol=1e-4, c_order="multicolor",
+              b_order="mindeg")
+    Po = _oracle(pr, **kw)
+    G = _slr(pr, **kw)
+    _lanczos_parity(G, Po, 24)
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "fgmres")
+    x, info = G.solve(_dev(b[:, 0]), "fgmres")
+    assert ro.converged and info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    assert abs(info[0]["iters"] - ro.iters) <= 1, (info[0]["iters"], ro.iters)

@@ -18,15 +18,20 @@ CASES = [
     ("lap3d_64", {"N": 12, "boxes": 2}, "ict", "ict", "subdomain"),
     ("shifted3d_128", {"N": 12, "boxes": 2, "neg": 4}, "ildlt", "ict", "subdomain"),
     ("diffusion2d_1024", {"N": 48, "boxes": 3}, "ict", "ic0", "multicolor"),
+    # minimum degree order of each B_i (Sec. 6), then threshold factors
+    ("lap3d_64", {"N": 16, "boxes": 2}, "ict", "ic0", "multicolor", "mindeg"),
+    ("shifted3d_128", {"N": 20, "boxes": 2, "neg": 4}, "ildlt", "ict", "subdomain", "mindeg"),
+    ("diffusion2d_1024", {"N": 96, "boxes": 4}, "ict", "ic0", "multicolor", "mindeg"),
+    ("lap3d_64", {"N": 18, "boxes": 4}, "ic0", "ic0", "multicolor", "mindeg"),
 ]
 
 
-@pytest.mark.parametrize("name,over,bf,cf,co", CASES)
-def test_analysis_matches_oracle(name, over, bf, cf, co):
+@pytest.mark.parametrize("name,over,bf,cf,co,bo", [c if len(c) == 6 else c + ("natural",) for c in CASES])
+def test_analysis_matches_oracle(name, over, bf, cf, co, bo):
     import paper_1505_04340_amd as P
     pr = si.make_config(name, **over)
-    info, perm = P.analyze(pr.csr, pr.part, pr.nparts, k=4, b_fact=bf, c_fact=cf, c_order=co)
-    Ps = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=bf, c_fact=cf, c_order=co)
+    info, perm = P.analyze(pr.csr, pr.part, pr.nparts, k=4, b_fact=bf, c_fact=cf, c_order=co, b_order=bo)
+    Ps = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=bf, c_fact=cf, c_order=co, b_order=bo)
     assert (perm == Ps.perm).all()
     assert info["m"] == Ps.m and info["s"] == Ps.s and info["p"] == pr.nparts
     if bf != "chol":
