@@ -71,7 +71,12 @@ enum { SLR_THETA_LAMBDA_K1 = 0, SLR_THETA_ZERO = 1, SLR_THETA_EPS = 2, SLR_THETA
  * entry of column j is kept when its updated value is at least droptol times
  * the 1-norm of column j of the lower triangle). */
 enum { SLR_FACT_CHOL = 0, SLR_FACT_IC0 = 1, SLR_FACT_ILDLT0 = 2, SLR_FACT_ICT = 3, SLR_FACT_ILDLT = 4 };
-enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1 };
+/* Ordering of the interface for C's factor: by owner subdomain (eq. Global2),
+ * greedy multicolour, or HID connectors (Sec. 5.2 names the Hierarchical
+ * Interface Decomposition, which makes C's leading block block diagonal:
+ * a node's key is the set of subdomains met in its closed neighbourhood;
+ * by key size, then key, then original index). */
+enum { SLR_CORDER_SUBDOMAIN = 0, SLR_CORDER_MULTICOLOR = 1, SLR_CORDER_HID = 2 };
 /* Order of each subdomain's interior (the rows of B_i): ascending original
  * index, or the minimum degree order of B_i's graph (Sec. 6 reorders every
  * B_i by approximate minimum degree before ICT / ILDLT; here exact degrees

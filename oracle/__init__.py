@@ -164,7 +164,23 @@ def dd_ordering(A: sp.csr_matrix, part: np.ndarray, nparts: int, c_order: str = 
     off_y = np.concatenate([[0], np.cumsum([len(a) for a in ifc])])
     perm = np.concatenate(inter + ifc).astype(np.int64)
     colors = None
-    if c_order == "multicolor":
+    if c_order == "hid":
+        # READING of the HID ordering (Sec. 5.2 names the Hierarchical
+        # Interface Decomposition of Henon and Saad for making C's leading
+        # block block diagonal): the key of an interface node is the set of
+        # subdomains met in its closed neighbourhood; nodes with equal keys
+        # form a connector, whose level is the key's size.  Connectors are
+        # taken by level, then by key, nodes by ascending index.
+        m = off_b[-1]
+        y = perm[m:]
+        keys = []
+        for i in y:
+            nb = A.indices[A.indptr[i]:A.indptr[i + 1]]
+            keys.append(tuple(sorted(set(np.asarray(part)[nb].tolist()) | {int(part[i])})))
+        order = sorted(range(len(y)), key=lambda t: (len(keys[t]), keys[t], int(y[t])))
+        perm = np.concatenate([perm[:m], y[order]])
+        colors = np.array([len(keys[t]) for t in order], dtype=np.int64)
+    elif c_order == "multicolor":
         m = off_b[-1]
         y = perm[m:]
         C = A[y][:, y].tocsr()

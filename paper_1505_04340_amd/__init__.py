@@ -46,7 +46,8 @@ SLR_REORTH_FULL, SLR_REORTH_PARTIAL = 0, 1
 _FACT = {"chol": SLR_FACT_CHOL, "ic0": SLR_FACT_IC0, "ildlt0": SLR_FACT_ILDLT0, "ict": SLR_FACT_ICT,
          "ildlt": SLR_FACT_ILDLT}
 _PREC = {"fp64": SLR_FP64, "fp32": SLR_FP32, "bf16": SLR_BF16}
-_CORD = {"subdomain": SLR_CORDER_SUBDOMAIN, "multicolor": SLR_CORDER_MULTICOLOR}
+SLR_CORDER_HID = 2
+_CORD = {"subdomain": SLR_CORDER_SUBDOMAIN, "multicolor": SLR_CORDER_MULTICOLOR, "hid": SLR_CORDER_HID}
 SLR_BORDER_NATURAL, SLR_BORDER_MINDEG = 0, 1
 _BORD = {"natural": SLR_BORDER_NATURAL, "mindeg": SLR_BORDER_MINDEG}
 _THETA = {"lambda_k1": SLR_THETA_LAMBDA_K1, "zero": SLR_THETA_ZERO, "eps": SLR_THETA_EPS, "lambda_s": SLR_THETA_LAMBDA_S}

@@ -473,6 +473,29 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     for (int64_t t = 0; t < s; ++t) y2[t] = y[idx[t]];
     y.swap(y2);
     H.c_colors = ncol;
+  } else if (prm.c_order == SLR_CORDER_HID && s > 0) {
+    // HID connectors (Sec. 5.2): key = the subdomains met in the node's
+    // closed neighbourhood; by key size (the connector's level), then key,
+    // then original index
+    std::vector<std::vector<int32_t>> key(s);
+    for (int64_t t = 0; t < s; ++t) {
+      const int64_t i = y[t];
+      std::vector<int32_t> &k = key[t];
+      k.push_back(part[i]);
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) k.push_back(part[col[e]]);
+      std::sort(k.begin(), k.end());
+      k.erase(std::unique(k.begin(), k.end()), k.end());
+    }
+    std::vector<int64_t> idx(s);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      if (key[a].size() != key[b].size()) return key[a].size() < key[b].size();
+      if (key[a] != key[b]) return key[a] < key[b];
+      return y[a] < y[b];
+    });
+    std::vector<int64_t> y2(s);
+    for (int64_t t = 0; t < s; ++t) y2[t] = y[idx[t]];
+    y.swap(y2);
   } else if (prm.c_order != SLR_CORDER_SUBDOMAIN) {
     err = "unknown c_order";
     return SLR_ERR_ARG;

@@ -637,3 +637,42 @@ def test_mindeg_order_fgmres_indefinite():
     x, info = G.solve(_dev(b[:, 0]), "fgmres")
     assert ro.converged and info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
     assert abs(info[0]["iters"] - ro.iters) <= 1, (info[0]["iters"], ro.iters)
+
+
+# ------------------------------------------- HID order of the interface (Sec. 5.2)
+@pytest.mark.parametrize("cf,prec", [("ict", "fp64"), ("ic0", "fp64"), ("ict", "fp32")])
+def test_hid_order_apply(cf, prec):
+    """The interface in HID order, C factored by ICT or IC(0) in that order
+    (a deep level schedule on the device): ordering and fill equal the
+    oracle's, and the apply matches the oracle with the same low-rank
+    part."""
+    pr = si.make_config("shifted3d_128", N=24, boxes=3, neg=10)
+    print(f"hid apply: {cf} {prec}", flush=True)
+    kw = dict(k=8, lanczos_steps=40, b_fact="ildlt", c_fact=cf, droptol=1e-3, fact_prec=prec, c_order="hid",
+              b_order="mindeg")
+    Po = _oracle(pr, **kw)
+    U = O.round_fp32(Po.U) if prec == "fp32" else Po.U
+    G = _slr(pr, uk_prec=prec, lowrank=(U, Po.lam, Po.theta), **kw)
+    assert (G.export()["perm"] == Po.perm).all()
+    assert G.info["nnz_LC"] == Po.FC.v.size and G.info["c_levels"] > 8
+    Pi = _oracle(pr, lowrank=(U, Po.lam, Po.theta), **{k: v for k, v in kw.items() if k not in ("k", "lanczos_steps")})
+    r = _rand(pr.n, 2, 19)
+    assert _relerr(G.apply(_dev(r)).cpu().numpy(), Pi.apply(r)).max() <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_hid_order_fgmres_indefinite():
+    """Shifted problem with 20 negative eigenvalues on 16^3 boxes (the box
+    geometry of the 128^3 workload): ILDLT B_i in minimum degree order and
+    ICT C in HID order, drop tolerance 1e-4.  Device Lanczos against the
+    oracle's, FGMRES(40) converges to 1e-8 with the oracle's count +-1."""
+    pr = si.make_config("shifted3d_128", N=48, boxes=3, neg=20)
+    print("hid fgmres: shifted N=48 boxes=3", flush=True)
+    kw = dict(k=32, lanczos_steps=160, b_fact="ildlt", c_fact="ict", droptol=1e-4, c_order="hid", b_order="mindeg")
+    Po = _oracle(pr, **kw)
+    G = _slr(pr, **kw)
+    _lanczos_parity(G, Po, 32)
+    xs, b = pr.rhs()
+    ro = O.solve(Po, b[:, 0], "fgmres", maxit=600)
+    x, info = G.solve(_dev(b[:, 0]), "fgmres", maxit=600)
+    assert ro.converged and info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    assert abs(info[0]["iters"] - ro.iters) <= 1, (info[0]["iters"], ro.iters)

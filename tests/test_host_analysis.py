@@ -23,6 +23,10 @@ CASES = [
     ("shifted3d_128", {"N": 20, "boxes": 2, "neg": 4}, "ildlt", "ict", "subdomain", "mindeg"),
     ("diffusion2d_1024", {"N": 96, "boxes": 4}, "ict", "ic0", "multicolor", "mindeg"),
     ("lap3d_64", {"N": 18, "boxes": 4}, "ic0", "ic0", "multicolor", "mindeg"),
+    # HID order of the interface (Sec. 5.2), zero-fill and threshold C
+    ("lap3d_64", {"N": 16, "boxes": 2}, "ic0", "ic0", "hid"),
+    ("shifted3d_128", {"N": 24, "boxes": 3, "neg": 10}, "ildlt", "ict", "hid", "mindeg"),
+    ("diffusion2d_1024", {"N": 96, "boxes": 4}, "ic0", "ict", "hid"),
 ]
 
 

@@ -687,6 +687,39 @@ def test_mindeg_interior_order_in_the_dd_ordering():
     assert np.abs(P.apply(A @ x) - x).max() < 1e-10
 
 
+# ------------------------------------------------ HID ordering of C
+
+@pytest.mark.parametrize("dim,N,q", [(3, 16, 2), (3, 18, 3), (3, 20, 4), (2, 40, 4), (2, 41, 5)])
+def test_hid_order_makes_the_leading_block_of_C_block_diagonal(dim, N, q):
+    """Sec. 5.2: for a recursive treatment C must have A's structure, its
+    leading block block diagonal, which the HID ordering provides.  With
+    the oracle's HID reading, the level-1 part of C splits into connected
+    pieces that are contiguous in the order (so that block is block
+    diagonal), one per pair of boxes sharing a face (3 q^2 (q-1) in 3-D,
+    2 q (q-1) in 2-D);
+    the interiors keep their order and the interface is a permutation of
+    the natural one."""
+    import scipy.sparse.csgraph  # noqa: F401
+    csr = si.laplacian_3d(N) if dim == 3 else si.laplacian_2d(N)
+    part = si.box_partition_3d(N, q) if dim == 3 else si.box_partition_2d(N, q, q)
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(csr[3], csr[3]))
+    pn, ob, oy, _ = O.dd_ordering(A, part, q ** dim)
+    ph, ob2, _, lev = O.dd_ordering(A, part, q ** dim, c_order="hid")
+    m = int(ob[-1])
+    assert (ph[:m] == pn[:m]).all() and sorted(ph[m:]) == sorted(pn[m:])
+    assert np.all(np.diff(lev) >= 0) and lev.min() == 2
+    # the level-1 block: its connected components are the faces (a closed
+    # count), and each is one contiguous range of the order (so the block
+    # is block diagonal in this order)
+    y = ph[m:]
+    lvl1 = y[lev == 2]
+    C1 = A[lvl1][:, lvl1].tocsr()
+    ncomp, lab = sp.csgraph.connected_components(C1, directed=False)
+    assert ncomp == (3 * q * q * (q - 1) if dim == 3 else 2 * q * (q - 1))
+    starts = np.flatnonzero(np.concatenate([[True], np.diff(lab) != 0]))
+    assert len(starts) == ncomp
+
+
 # --------------------------------------------------------------- Krylov
 
 def test_krylov_iteration_counts_on_known_spectra():
