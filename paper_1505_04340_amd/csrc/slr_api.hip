@@ -264,16 +264,13 @@ struct slr_ctx {
   // low-rank part
   int32_t k = 0;
   double theta = 0.0, rho = 1.0;
-  void *U = nullptr;            // s x k column-major, storage precision (BF16: matrix-core path)
-  void *Urm = nullptr;          // FP64 / FP32 storage: row-major padded copy (U^T w)
+  void *U = nullptr;            // FP64 / FP32: s x k column-major; BF16: tiles of U^T W (matrix cores)
+  void *Urm = nullptr;          // FP64 / FP32: row-major padded copy (U^T w); BF16: tiles of the update
   double *U64 = nullptr;        // s x k column-major, FP64 (export)
   double *dsc = nullptr;        // k scales (1-lambda)^{-1} - rho
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
   int32_t lr_nblk = 256;       // group chunks of the row-major rank-k partials (set with U_k)
   int32_t lrm_nblk = 512;      // row chunks of the matrix-core rank-k partials
-  // BF16 U_k always takes the matrix-core path, so a column's arithmetic
-  // never depends on how many columns share the launch
-  int32_t mfma_min_rhs = 1;
   DevPool lrpool;               // U, U64, dsc
   int32_t live_batches = 0;     // slr_batch objects on this context
   // numeric refactorisation (slr_refactor): the input pattern, the factor
@@ -501,12 +498,13 @@ void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wou
                                wout, ldo, nrhs, w.lr_part, c->lr_nblk, w.cbuf, st);
       break;
     default:
-      if (nrhs >= c->mfma_min_rhs && k > 0)
-        launch_lowrank_mfma((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo, nrhs,
-                            w.lr_part, c->lrm_nblk, w.cbuf, st);
+      // BF16 U_k always takes the matrix-core kernels, so that a column's
+      // arithmetic never depends on how many columns share the launch
+      if (k > 0)
+        launch_lowrank_mfma((const __hip_bfloat16 *)c->U, (const __hip_bfloat16 *)c->Urm, c->s, k, c->dsc, c->rho,
+                            win, ldw, wout, ldo, nrhs, w.lr_part, c->lrm_nblk, w.cbuf, st);
       else
-        launch_lowrank<__hip_bfloat16>((const __hip_bfloat16 *)c->U, c->s, k, c->dsc, c->rho, win, ldw, wout, ldo,
-                                       nrhs, w.lr_part, c->lr_nblk, w.cbuf, w.counter, st);
+        launch_axpby(c->s, nrhs, c->rho, win, ldw, 0.0, wout, ldo, st);
   }
 }
 
@@ -629,7 +627,15 @@ int finish_lowrank(slr_ctx *c, hipStream_t st) {
     const int rc = upload_lowrank_T<float>(c, st);
     return rc ? rc : upload_lowrank_rm<float>(c, st);
   }
-  return upload_lowrank_T<__hip_bfloat16>(c, st);
+  // BF16: the two tile layouts of the matrix-core kernels (U: U^T W, Urm: update)
+  const int64_t ne = lr_tile_entries(c->s, c->k);
+  __hip_bfloat16 *Upt = c->lrpool.alloc<__hip_bfloat16>((size_t)ne);
+  __hip_bfloat16 *Uup = c->lrpool.alloc<__hip_bfloat16>((size_t)ne);
+  if (!Upt || !Uup) return fail(SLR_ERR_OOM, "U storage");
+  launch_lr_to_tiles(c->U64, c->s, c->k, Upt, Uup, st);
+  c->U = Upt;
+  c->Urm = Uup;
+  return SLR_OK;
 }
 
 // Lanczos on H with CGS2 full reorthogonalisation (Sec. 5.1), then the

@@ -142,9 +142,14 @@ void launch_lowrank_rm(const TU *Urm, const TU *U, int64_t s, int32_t k, const d
 namespace slr {
 void launch_lanczos_record(int32_t j, double *sc, double *alpha, double *beta, hipStream_t st);
 void launch_lanczos_alpha(int32_t j, const double *h, double *sc, hipStream_t st);
-// rank-k block on matrix cores (BF16 U, column-major s x k)
-void launch_lowrank_mfma(const __hip_bfloat16 *U, int64_t s, int32_t k, const double *dsc, double rho,
-                         const double *w, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs, double *part,
-                         int32_t nblk, double *cbuf, hipStream_t st);
+// rank-k block on matrix cores: BF16 U (k <= 64) in 16 x 16 tiles, one copy
+// in the layout of U^T W's A operand (Upt) and one in that of the update's
+// B operand (Uup), lr_tile_entries(s, k) entries each
+int64_t lr_tile_entries(int64_t s, int32_t k);
+void launch_lr_to_tiles(const double *U64, int64_t s, int32_t k, __hip_bfloat16 *Upt, __hip_bfloat16 *Uup,
+                        hipStream_t st);
+void launch_lowrank_mfma(const __hip_bfloat16 *Upt, const __hip_bfloat16 *Uup, int64_t s, int32_t k,
+                         const double *dsc, double rho, const double *w, int64_t ldw, double *wout, int64_t ldo,
+                         int32_t nrhs, double *part, int32_t nblk, double *cbuf, hipStream_t st);
 void launch_gmres_g0(int32_t len, const double *nrm2, double *g, hipStream_t st);
 }  // namespace slr

@@ -934,118 +934,202 @@ __device__ __forceinline__ void split3(double x, short &hi, short &mid, short &l
 }
 
 constexpr int LRM_THREADS = 256;
+constexpr int LRM_CT = 4;     // column tiles per pass (accumulators: kt x LRM_CT)
 
-// part[b][c][q] = sum_{i in chunk b} U[i,q] W[i,c], for all q < k, c < nrhs.
-// Pairs (q-tile, c-tile) are dealt round-robin to the 4 waves; each wave
-// walks the block's row chunk in steps of 16.
-__global__ void __launch_bounds__(LRM_THREADS) k_lr_partial_mfma(const __hip_bfloat16 *U, int64_t s, int k,
-                                                                 const double *W, int64_t ldw, int nrhs,
-                                                                 double *part) {
-  const int nb = gridDim.x;
-  const int64_t chunk = (((s + nb - 1) / nb) + 15) & ~int64_t(15);
-  const int64_t i0 = (int64_t)blockIdx.x * chunk;
-  const int64_t i1 = min(s, i0 + chunk);
+// BF16 U_k in 16 x 16 tiles of 512 bytes, each in the register layout of one
+// MFMA operand, so that a lane loads its 4 entries as one 8-byte vector and
+// a wave reads a whole tile in one coalesced 512-byte load.  Tile (b, t)
+// covers rows 16 b .. 16 b + 15 and columns 16 t .. 16 t + 15 (zero
+// padding past s and k) and sits at (b * kt + t) * 256 entries:
+//   partial layout (A operand of U^T W): lane l, entry j = U[16 b + 4 (l/16) + j][16 t + l%16]
+//   update layout (B operand of c^T U^T): lane l, entry j = U[16 b + l%16][16 t + 4 (l/16) + j]
+__global__ void k_lr_to_tiles(const double *U64, int64_t s, int k, int kt, int64_t ntiles, short *Upt, short *Uup) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one thread per (tile, lane)
+  if (g >= ntiles * 64) return;
+  const int64_t tile = g >> 6;
+  const int l = (int)(g & 63);
+  const int64_t b = tile / kt;
+  const int t = (int)(tile - b * kt);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t rp = 16 * b + 4 * (l >> 4) + j, ru = 16 * b + (l & 15);
+    const int qp = 16 * t + (l & 15), qu = 16 * t + 4 * (l >> 4) + j;
+    const double vp = (rp < s && qp < k) ? U64[rp + (int64_t)qp * s] : 0.0;
+    const double vu = (ru < s && qu < k) ? U64[ru + (int64_t)qu * s] : 0.0;
+    __hip_bfloat16 hp = round_store<__hip_bfloat16>(vp), hu = round_store<__hip_bfloat16>(vu);
+    short sp, su;
+    __builtin_memcpy(&sp, &hp, 2);
+    __builtin_memcpy(&su, &hu, 2);
+    Upt[g * 4 + j] = sp;
+    Uup[g * 4 + j] = su;
+  }
+}
+
+// part[b][c][q] = sum over the rows of chunk b of U[i,q] W[i,c], for all
+// q < k, c < nrhs.  A block's chunk is a run of 16-row blocks (the split
+// depends on s and the block count only); its 4 waves take every 4th row
+// block, each accumulating all (q-tile, c-tile) pairs of a pass of up to
+// LRM_CT column tiles: per row block W is loaded and split into its three
+// BF16 terms once, and every U tile once.  The waves' sums are added in
+// wave order through LDS.  A column's sums never depend on other columns.
+__global__ void __launch_bounds__(LRM_THREADS) k_lr_partial_tiles(const short *Upt, int64_t s, int k,
+                                                                  const double *W, int64_t ldw, int nrhs,
+                                                                  double *part) {
+  __shared__ float red[LRM_THREADS / 64][64][4];   // one (q-tile, c-tile) pair of every wave at a time
+  const int kt = (k + 15) >> 4, nt = (nrhs + 15) >> 4;
+  const int64_t nrb = (s + 15) >> 4;
+  const int64_t per = (nrb + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(nrb, b0 + per);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int kt = (k + 15) / 16, nt = (nrhs + 15) / 16;
-  const uint16_t *Ub = reinterpret_cast<const uint16_t *>(U);
-  for (int pair = wid; pair < kt * nt; pair += LRM_THREADS / 64) {
-    const int mt = pair / nt, ntl = pair - mt * nt;
-    const int q = mt * 16 + (lane & 15);        // this lane's U column (A row)
-    const int c = ntl * 16 + (lane & 15);       // this lane's W column (B column)
-    const bool qok = q < k, cok = c < nrhs;
-    const int qc = qok ? q : k - 1, cc = cok ? c : nrhs - 1;
-    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t r0 = i0; r0 < i1; r0 += 16) {
-      const int64_t rb = r0 + 4 * (lane >> 4);
-      bf16x4_t a, bh, bm, bl;
+  const uint64_t *U8 = reinterpret_cast<const uint64_t *>(Upt);
+  for (int ct0 = 0; ct0 < nt; ct0 += LRM_CT) {
+    const int nct = min(LRM_CT, nt - ct0);
+    f32x4_t acc[4][LRM_CT];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t row = rb + j;
-        const bool rok = row < i1;
-        const int64_t rr = rok ? row : i1 - 1;
-        const uint16_t uv = Ub[rr + (int64_t)qc * s];
-        a[j] = (rok && qok) ? (short)uv : (short)0;
-        const double wv = (rok && cok) ? W[rr + (int64_t)cc * ldw] : 0.0;
-        short h, m, l;
-        split3(wv, h, m, l);
-        bh[j] = h;
-        bm[j] = m;
-        bl[j] = l;
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < LRM_CT; ++u) acc[t][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int64_t b = b0 + wid; b < b1; b += LRM_THREADS / 64) {
+      bf16x4_t a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint64_t v = t < kt ? U8[(b * kt + t) * 64 + lane] : 0ull;
+        __builtin_memcpy(&a[t], &v, 8);
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc, 0, 0, 0);
-    }
-    // D[qrow][ccol]: qrow = mt*16 + 4(l/16) + i, ccol = ntl*16 + l%16
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int qq = mt * 16 + 4 * (lane >> 4) + i;
-      if (qq < k && cok) part[((int64_t)blockIdx.x * nrhs + c) * k + qq] = (double)acc[i];
+      for (int u = 0; u < LRM_CT; ++u) {
+        if (u >= nct) break;
+        const int c = (ct0 + u) * 16 + (lane & 15);
+        const bool cok = c < nrhs;
+        bf16x4_t bh, bm, bl;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t row = 16 * b + 4 * (lane >> 4) + j;
+          const double wv = (cok && row < s) ? W[row + (int64_t)c * ldw] : 0.0;
+          short h, m, l;
+          split3(wv, h, m, l);
+          bh[j] = h;
+          bm[j] = m;
+          bl[j] = l;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (t >= kt) break;
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], bh, acc[t][u], 0, 0, 0);
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], bm, acc[t][u], 0, 0, 0);
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], bl, acc[t][u], 0, 0, 0);
+        }
+      }
+    }
+    // D[q][c]: q = 16 t + 4 (l/16) + i, c = 16 u + l%16; waves added in order
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= kt) break;
+#pragma unroll
+      for (int u = 0; u < LRM_CT; ++u) {
+        if (u >= nct) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[wid][lane][i] = acc[t][u][i];
+        __syncthreads();
+        {
+          const int l = threadIdx.x >> 2, i = threadIdx.x & 3;
+          const int q = 16 * t + 4 * (l >> 4) + i, c = (ct0 + u) * 16 + (l & 15);
+          if (q < k && c < nrhs) {
+            const float v = ((red[0][l][i] + red[1][l][i]) + red[2][l][i]) + red[3][l][i];
+            part[((int64_t)blockIdx.x * nrhs + c) * k + q] = (double)v;
+          }
+        }
+        __syncthreads();
+      }
     }
   }
 }
 
-// wout[i,c] = rho w[i,c] + sum_q U[i,q] cbuf[c*k + q]; one wave per 16 rows,
-// all column tiles; cbuf split into three BF16 terms in LDS.
-__global__ void __launch_bounds__(LRM_THREADS) k_lr_update_mfma(const __hip_bfloat16 *U, int64_t s, int k,
-                                                                const double *w, int64_t ldw, double *wout,
-                                                                int64_t ldo, int nrhs, const double *cbuf,
-                                                                double rho) {
-  extern __shared__ short cs3[];   // 3 x (kpad x npad), [term][q][c]
-  const int kpad = ((k + 15) / 16) * 16, npad = ((nrhs + 15) / 16) * 16;
-  for (int t = threadIdx.x; t < kpad * npad; t += blockDim.x) {
-    const int q = t / npad, c = t - q * npad;
+// wout[i,c] = rho w[i,c] + sum_q U[i,q] cbuf[c*k + q], as the transposed
+// product (c x i) = c^T U^T: A = the coefficients (c-tile x q-tile, split
+// into three BF16 terms in LDS), B = U tiles in the update layout; lane l
+// register j then holds row 16 b + l%16 of column 16 u + 4 (l/16) + j, so
+// 16 lanes store 16 consecutive rows of one column.  One wave per 16-row
+// block; every column tile; U tiles loaded once per row block.
+__global__ void __launch_bounds__(LRM_THREADS) k_lr_update_tiles(const short *Uup, int64_t s, int k,
+                                                                 const double *w, int64_t ldw, double *wout,
+                                                                 int64_t ldo, int nrhs, const double *cbuf,
+                                                                 double rho) {
+  extern __shared__ short cs3[];   // 3 x (npad x kpad), [term][c][q]
+  const int kt = (k + 15) >> 4, kpad = kt * 16, npad = ((nrhs + 15) >> 4) * 16;
+  for (int e = threadIdx.x; e < kpad * npad; e += blockDim.x) {
+    const int c = e / kpad, q = e - c * kpad;
     const double v = (q < k && c < nrhs) ? cbuf[c * k + q] : 0.0;
     short h, m, l;
     split3(v, h, m, l);
-    cs3[t] = h;
-    cs3[kpad * npad + t] = m;
-    cs3[2 * kpad * npad + t] = l;
+    cs3[e] = h;
+    cs3[kpad * npad + e] = m;
+    cs3[2 * kpad * npad + e] = l;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t m0 = ((int64_t)blockIdx.x * (LRM_THREADS / 64) + wid) * 16;
-  if (m0 >= s) return;
-  const uint16_t *Ub = reinterpret_cast<const uint16_t *>(U);
-  const int64_t row = min(m0 + (lane & 15), s - 1);   // this lane's A row
-  for (int ntl = 0; ntl < npad / 16; ++ntl) {
+  const int64_t b = (int64_t)blockIdx.x * (LRM_THREADS / 64) + wid;
+  if (16 * b >= s) return;
+  const uint64_t *U8 = reinterpret_cast<const uint64_t *>(Uup);
+  bf16x4_t ub[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const uint64_t v = t < kt ? U8[(b * kt + t) * 64 + lane] : 0ull;
+    __builtin_memcpy(&ub[t], &v, 8);
+  }
+  const int64_t row = 16 * b + (lane & 15);
+  for (int u = 0; u < npad / 16; ++u) {
     f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int q0 = 0; q0 < kpad; q0 += 16) {
-      bf16x4_t a, bh, bm, bl;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= kt) break;
+      bf16x4_t ah, am, al;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int q = q0 + 4 * (lane >> 4) + j;
-        a[j] = q < k ? (short)Ub[row + (int64_t)q * s] : (short)0;
-        const int t = q * npad + ntl * 16 + (lane & 15);
-        bh[j] = cs3[t];
-        bm[j] = cs3[kpad * npad + t];
-        bl[j] = cs3[2 * kpad * npad + t];
+        // A[m = c][kk = q]: lane l holds A[l%16][4 (l/16) + j]
+        const int e = (16 * u + (lane & 15)) * kpad + 16 * t + 4 * (lane >> 4) + j;
+        ah[j] = cs3[e];
+        am[j] = cs3[kpad * npad + e];
+        al[j] = cs3[2 * kpad * npad + e];
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, ub[t], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, ub[t], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, ub[t], acc, 0, 0, 0);
     }
-    const int c = ntl * 16 + (lane & 15);
+    if (row < s) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = m0 + 4 * (lane >> 4) + i;
-      if (r < s && c < nrhs) wout[r + (int64_t)c * ldo] = rho * w[r + (int64_t)c * ldw] + (double)acc[i];
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * u + 4 * (lane >> 4) + i;
+        if (c < nrhs) wout[row + (int64_t)c * ldo] = rho * w[row + (int64_t)c * ldw] + (double)acc[i];
+      }
     }
   }
 }
 
-void launch_lowrank_mfma(const __hip_bfloat16 *U, int64_t s, int32_t k, const double *dsc, double rho,
-                         const double *w, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs, double *part,
-                         int32_t nblk, double *cbuf, hipStream_t st) {
+int64_t lr_tile_entries(int64_t s, int32_t k) { return ((s + 15) / 16) * (int64_t)((k + 15) / 16) * 256; }
+
+void launch_lr_to_tiles(const double *U64, int64_t s, int32_t k, __hip_bfloat16 *Upt, __hip_bfloat16 *Uup,
+                        hipStream_t st) {
+  const int kt = (k + 15) / 16;
+  const int64_t ntiles = ((s + 15) / 16) * kt;
+  if (ntiles == 0) return;
+  hipLaunchKernelGGL(k_lr_to_tiles, dim3((unsigned)((ntiles * 64 + 255) / 256)), dim3(256), 0, st, U64, s, k, kt,
+                     ntiles, reinterpret_cast<short *>(Upt), reinterpret_cast<short *>(Uup));
+}
+
+void launch_lowrank_mfma(const __hip_bfloat16 *Upt, const __hip_bfloat16 *Uup, int64_t s, int32_t k,
+                         const double *dsc, double rho, const double *w, int64_t ldw, double *wout, int64_t ldo,
+                         int32_t nrhs, double *part, int32_t nblk, double *cbuf, hipStream_t st) {
   if (s == 0 || nrhs == 0 || k == 0) return;
-  hipLaunchKernelGGL(k_lr_partial_mfma, dim3(nblk), dim3(LRM_THREADS), 0, st, U, s, k, w, ldw, nrhs, part);
+  hipLaunchKernelGGL(k_lr_partial_tiles, dim3(nblk), dim3(LRM_THREADS), 0, st, reinterpret_cast<const short *>(Upt),
+                     s, k, w, ldw, nrhs, part);
   hipLaunchKernelGGL(k_lr_fold, dim3((unsigned)((k * nrhs + 3) / 4)), dim3(256), 0, st, part, nblk, k * nrhs, k,
                      dsc, cbuf);
   const int kpad = ((k + 15) / 16) * 16, npad = ((nrhs + 15) / 16) * 16;
   const size_t lds = sizeof(short) * 3 * (size_t)kpad * npad;
-  const unsigned nblk_u = (unsigned)((s + 63) / 64);
-  hipLaunchKernelGGL(k_lr_update_mfma, dim3(nblk_u), dim3(LRM_THREADS), lds, st, U, s, k, w, ldw, wout, ldo, nrhs,
-                     cbuf, rho);
+  const int64_t nrb = (s + 15) / 16;
+  hipLaunchKernelGGL(k_lr_update_tiles, dim3((unsigned)((nrb + 3) / 4)), dim3(LRM_THREADS), lds, st,
+                     reinterpret_cast<const short *>(Uup), s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
 }
 
 template <typename TU>
