@@ -174,13 +174,16 @@ def multi_rhs_apply(P, torch, nrhs=32, reps=10):
                   c_fact=pr.c_fact, c_order="multicolor", fact_prec=fp, uk_prec=up, v0=pr.v0())
         torch.cuda.synchronize()
         info = G.query()
+        ms0 = G.time_kernel("apply", nrhs, reps)
+        tune = G.autotune(nrhs)
         ms = G.time_kernel("apply", nrhs, reps)
         st = {s: round(G.time_kernel(s, nrhs, reps), 5) for s in ("bsolve1", "lowrank", "bsolve2")}
         bf = 8 if fp == "fp64" else 4
         bu = {"fp64": 8, "fp32": 4, "bf16": 2}[up]
         ab = apply_bytes(info, nrhs, bf, bu, info["k"])
         gbs = ab / (ms * 1e-3) / 1e9
-        out[name] = {"apply_us": round(ms * 1e3, 2), "algorithmic_bytes": int(ab), "GBs": round(gbs, 1),
+        out[name] = {"apply_us": round(ms * 1e3, 2), "apply_us_built_in_plan": round(ms0 * 1e3, 2), "autotune": tune,
+                     "algorithmic_bytes": int(ab), "GBs": round(gbs, 1),
                      "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "stage_ms": st,
                      "roofline": roofline_block(gbs, ab, ms, "whole apply (B solves, sweeps, rank-k)")}
         log(f"[bench:multi] {name}: apply {ms * 1e3:.1f} us = {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% "
@@ -190,7 +193,7 @@ def multi_rhs_apply(P, torch, nrhs=32, reps=10):
     return out
 
 
-def apply_profile(P, torch, name, form, nrhs, reps):
+def apply_profile(P, torch, name, form, nrhs, reps, autotune=False):
     """Only set up one workload and time its apply (for profiler runs)."""
     import slr_inputs as si
     pr = si.make_config(name)
@@ -198,6 +201,7 @@ def apply_profile(P, torch, name, form, nrhs, reps):
     G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
               c_fact=pr.c_fact, c_order="multicolor", fact_prec=fp, uk_prec=up, v0=pr.v0())
     torch.cuda.synchronize()
+    tune = G.autotune(nrhs) if autotune else None
     info = G.query()
     ms = G.time_kernel("apply", nrhs, reps)
     stages = {s: round(G.time_kernel(s, nrhs, reps), 5) for s in ("bsolve1", "cfwd", "lowrank", "cbwd", "bsolve2")}
@@ -209,7 +213,7 @@ def apply_profile(P, torch, name, form, nrhs, reps):
                       "apply_algorithmic_bytes": int(ab), "apply_GBs": round(ab / (ms * 1e-3) / 1e9, 1),
                       "bsolve1_algorithmic_bytes": int(bb),
                       "bsolve1_GBs": round(bb / (stages["bsolve1"] * 1e-3) / 1e9, 1),
-                      "stage_ms": stages, "s": info["s"], "m": info["m"], "p": info["p"], "k": info["k"],
+                      "stage_ms": stages, "autotune": tune, "s": info["s"], "m": info["m"], "p": info["p"], "k": info["k"],
                       "nnz_LB": info["nnz_LB"], "nnz_LC": info["nnz_LC"], "nnz_E": info["nnz_E"]}))
 
 
@@ -421,6 +425,7 @@ def main():
     ap.add_argument("--apply-form", choices=("fp64", "fp32", "mixed"), default="fp64")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--autotune", action="store_true", help="with --apply-profile: slr_autotune first")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -429,7 +434,7 @@ def main():
         import torch
         import paper_1505_04340_amd as P
         torch.cuda.set_device(0)
-        apply_profile(P, torch, args.apply_profile, args.apply_form, args.nrhs, args.reps)
+        apply_profile(P, torch, args.apply_profile, args.apply_form, args.nrhs, args.reps, args.autotune)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -182,6 +182,13 @@ typedef struct {
   double setup_lanczos_s; /* device Lanczos + eigensolve time                */
   int64_t device_bytes;   /* persistent device memory held by the context    */
   int32_t lanczos_reorth; /* Lanczos steps that were reorthogonalised        */
+  /* launch shapes chosen by slr_autotune (0: the built-in plan): B kernel
+     threads per workgroup and LDS share 1/div, for one column and for
+     several (with the most columns per workgroup); chunks of the rank-k
+     partial sums */
+  int32_t tune_b_threads1, tune_b_lds_div1;
+  int32_t tune_b_threadsM, tune_b_lds_divM, tune_b_rmaxM;
+  int32_t lr_chunks;
 } slr_info;
 
 typedef struct slr_ctx slr_ctx;
@@ -264,6 +271,20 @@ int slr_refactor(slr_ctx *c, const double *val, int32_t on_device, void *hip_str
  * sweep, 4 = second batched B solve (E y prologue), 5 = whole apply,
  * 6 = SpMV with A.  Inputs are deterministic filler values. */
 int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void *hip_stream, double *ms);
+
+/* slr_autotune: time the batched B solve (first half of the apply, with its
+ * E^T epilogue) for nrhs columns under every candidate launch shape --
+ * threads per workgroup (1024, 512, 256), share of the LDS per workgroup
+ * (1, 1/2, 1/4: that many workgroups fit a CU) and most columns per
+ * workgroup -- and keep the fastest for one column (nrhs == 1) or for
+ * several (nrhs > 1); then the number of row chunks of the rank-k partial
+ * sums (128 ... 2048).  reps launches per candidate (0: 3), HIP events on
+ * hip_stream.  The B kernel's results do not depend on the launch shape;
+ * the rank-k chunks set the grouping of its sums, the same for every later
+ * apply of the context (alone or in a batch).  The choices are reported in
+ * slr_info (tune_*, lr_chunks) and kept by slr_export_setup.  SLR_ERR_ARG
+ * while batches exist.  Synchronises hip_stream. */
+int slr_autotune(slr_ctx *c, int32_t nrhs, int32_t reps, void *hip_stream);
 
 /* slr_apply: z = M^{-1} r for nrhs vectors (eq. M with eq. skt).  r_dev,
  * z_dev: device, n x nrhs column-major, original order; may not alias.

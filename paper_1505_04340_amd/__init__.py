@@ -85,7 +85,9 @@ class slr_info(ctypes.Structure):
                 ("c_colors", _I32), ("nnz_LB", _I64), ("nnz_LC", _I64), ("nnz_E", _I64),
                 ("nnz_A", _I64), ("m_min", _I64), ("m_max", _I64), ("theta", _D),
                 ("setup_host_s", _D), ("setup_lanczos_s", _D), ("device_bytes", _I64),
-                ("lanczos_reorth", _I32)]
+                ("lanczos_reorth", _I32), ("tune_b_threads1", _I32), ("tune_b_lds_div1", _I32),
+                ("tune_b_threadsM", _I32), ("tune_b_lds_divM", _I32), ("tune_b_rmaxM", _I32),
+                ("lr_chunks", _I32)]
 
 
 def _sig(name, res, args):
@@ -113,6 +115,7 @@ slr_solve = _sig("slr_solve", ctypes.c_int, [_P, _P, _P, _I32, ctypes.POINTER(sl
 slr_solve_workspace_bytes = _sig("slr_solve_workspace_bytes", ctypes.c_size_t,
                                  [_P, _I32, ctypes.POINTER(slr_solve_opts)])
 slr_trim = _sig("slr_trim", ctypes.c_int, [_P])
+slr_autotune = _sig("slr_autotune", ctypes.c_int, [_P, _I32, _I32, _P])
 slr_export_setup = _sig("slr_export_setup", ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)])
 slr_import = _sig("slr_import", ctypes.c_int, [_P, ctypes.c_size_t, _P, ctypes.POINTER(_P)])
 SLR_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -137,7 +140,7 @@ EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_anal
             "slr_grow_lowrank", "slr_refactor",
             "slr_time_kernel", "slr_apply", "slr_apply_dd", "slr_apply_dd_noalloc",
             "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_spmv",
-            "slr_trim", "slr_export_setup", "slr_import", "slr_set_allocator",
+            "slr_trim", "slr_export_setup", "slr_import", "slr_set_allocator", "slr_autotune",
             "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
             "slr_batch_active", "slr_batch_bytes", "slr_batch_destroy", "slr_destroy",
             "slr_strerror", "slr_last_error", "slr_device_lds_bytes")
@@ -325,6 +328,14 @@ class SLR:
         buf = ctypes.create_string_buffer(nb.value)
         _check(slr_export_setup(self._h, buf, nb.value, ctypes.byref(nb)), "slr_export_setup")
         return buf.raw[:nb.value]
+
+    def autotune(self, nrhs: int = 1, reps: int = 3, stream=None) -> dict:
+        """Pick the B kernel's launch shape for nrhs columns and the rank-k
+        chunks by timing candidates (slr_autotune); returns the choice."""
+        _check(slr_autotune(self._h, nrhs, reps, _stream(stream)), "slr_autotune")
+        self.info = self.query()
+        return {k: self.info[k] for k in ("tune_b_threads1", "tune_b_lds_div1", "tune_b_threadsM",
+                                          "tune_b_lds_divM", "tune_b_rmaxM", "lr_chunks")}
 
     def trim(self):
         """Release the scratch kept between calls (slr_trim)."""

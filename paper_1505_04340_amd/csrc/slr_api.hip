@@ -271,6 +271,13 @@ struct slr_ctx {
   std::vector<double> lam_h, ritz_h, alpha_h, beta_h;
   int32_t lr_nblk = 256;       // group chunks of the row-major rank-k partials (set with U_k)
   int32_t lrm_nblk = 512;      // row chunks of the matrix-core rank-k partials
+  int32_t lr_nblk_tuned = 0;   // slr_autotune's choice of lr_nblk (0: by the size of U_k)
+  // launch shapes of the B kernel chosen by slr_autotune (threads == 0: the
+  // built-in plan): threads per workgroup, the share of the LDS limit a
+  // workgroup may take (1/lds_div), and the most columns per workgroup
+  struct BTune {
+    int32_t threads = 0, lds_div = 1, rmax = 16;
+  } tune1, tuneM;              // one column; several columns
   DevPool lrpool;               // U, U64, dsc
   int32_t live_batches = 0;     // slr_batch objects on this context
   // numeric refactorisation (slr_refactor): the input pattern, the factor
@@ -440,8 +447,11 @@ int run_bsolve(slr_ctx *c, const BlockArrays<TS> &B, const BArgs &a0, hipStream_
   BArgs a = a0;
   int32_t R = 0, stage = 0;
   int32_t threads = c->b_threads;
+  const slr_ctx::BTune &tu = a.nrhs == 1 ? c->tune1 : c->tuneM;
   const bool pair = a.nrhs == 1 && (int64_t)c->p > (int64_t)c->n_cu;
-  if (pair && b_lds_plan(c, a.nrhs, sizeof(TC), R, stage, c->lds_limit / 2)) {
+  if (tu.threads > 0 && b_lds_plan(c, std::min(a.nrhs, tu.rmax), sizeof(TC), R, stage, c->lds_limit / tu.lds_div)) {
+    threads = tu.threads;
+  } else if (pair && b_lds_plan(c, a.nrhs, sizeof(TC), R, stage, c->lds_limit / 2)) {
     threads = c->b_threads / 2;
   } else if (!b_lds_plan(c, a.nrhs, sizeof(TC), R, stage)) {
     return fail(SLR_ERR_ARG, "a subdomain does not fit the LDS of one workgroup");
@@ -595,7 +605,8 @@ int upload_lowrank_rm(slr_ctx *c, hipStream_t st) {
   const int64_t n = ng * 64 * (16 / (int64_t)sizeof(TU));
   // chunks of U^T w: about 128 row groups each (a few rounds of loads per
   // wave), at least 256 and at most 2048 (the fold reads chunks x k)
-  c->lr_nblk = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(256, ng / 128));
+  c->lr_nblk = c->lr_nblk_tuned > 0 ? c->lr_nblk_tuned
+                                     : (int32_t)std::min<int64_t>(2048, std::max<int64_t>(256, ng / 128));
   TU *U = c->lrpool.alloc<TU>((size_t)n);
   if (!U) return fail(SLR_ERR_OOM, "U storage");
   launch_lr_to_rm<TU>(c->U64, c->s, c->k, U, st);
@@ -1322,6 +1333,8 @@ int export_setup(const slr_ctx *cc, std::vector<uint8_t> &blob) {
   };
   int rc = c->fact_prec == SLR_FP64 ? dump(c->Bd, c->Cfd, c->Cbd) : dump(c->Bf, c->Cff, c->Cbf);
   if (rc) return rc;
+  // launch shapes and rank-k chunks (slr_autotune)
+  w.pod(c->tune1); w.pod(c->tuneM); w.pod(c->lr_nblk_tuned); w.pod(c->lrm_nblk);
   // low-rank part (FP64; the stored precision is rebuilt from it on import)
   w.pod(c->k); w.pod(c->theta);
   std::vector<double> U((size_t)c->s * c->k);
@@ -1394,6 +1407,10 @@ int import_setup(const uint8_t *buf, size_t bytes, hipStream_t st, slr_ctx **out
   c->perm_h.resize(c->n);
   if (c->n) HIPCHK(hipMemcpy(c->perm_h.data(), c->perm, sizeof(int64_t) * c->n, hipMemcpyDeviceToHost));
   std::vector<double> U;
+  r.pod(c->tune1); r.pod(c->tuneM); r.pod(c->lr_nblk_tuned); r.pod(c->lrm_nblk);
+  if (c->tune1.lds_div < 1 || c->tuneM.lds_div < 1 || c->tune1.threads < 0 || c->tune1.threads > 1024 ||
+      c->tuneM.threads < 0 || c->tuneM.threads > 1024 || c->lrm_nblk < 1 || c->lr_nblk_tuned < 0)
+    return bad("launch shapes");
   r.pod(c->k); r.pod(c->theta);
   r.vec(U); r.vec(c->lam_h); r.vec(c->ritz_h); r.vec(c->alpha_h); r.vec(c->beta_h);
   slr_info info{};
@@ -1585,6 +1602,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   I.nnz_E = H.nnz_E;
   I.nnz_A = c->nnz_a;
   I.setup_host_s = now_s() - t0;
+  I.tune_b_lds_div1 = I.tune_b_lds_divM = 1;
   // low-rank part
   const double t1 = now_s();
   if (o->U_in && o->k_in > 0) {
@@ -1769,6 +1787,83 @@ int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void 
   return SLR_OK;
 }
 
+int slr_autotune(slr_ctx *c, int32_t nrhs, int32_t reps, void *hip_stream) {
+  if (!c || nrhs <= 0 || nrhs > 128) return fail(SLR_ERR_ARG, "bad autotune arguments");
+  if (c->live_batches > 0) return fail(SLR_ERR_ARG, "the context still has batches");
+  if (reps <= 0) reps = 3;
+  const bool one = nrhs == 1;
+  slr_ctx::BTune &tu = one ? c->tune1 : c->tuneM;
+  const slr_ctx::BTune keep = tu;
+  const size_t tcb = (c->fact_prec == SLR_FP64) ? 8 : 4;
+  // candidates: threads per workgroup, LDS share, most columns per workgroup
+  std::vector<slr_ctx::BTune> cand;
+  for (int32_t th : {1024, 512, 256})
+    for (int32_t div : {1, 2, 4}) {
+      if (th * div > 2048 || th * div < 512) continue;   // at most 32 waves per CU, at least 8 resident
+      int32_t R = 0, stage = 0;
+      if (!b_lds_plan(c, one ? 1 : std::min(nrhs, 16), tcb, R, stage, c->lds_limit / div)) continue;
+      for (int32_t r = R; r >= 1; r = (r > 1 ? std::max(1, r / 2) : 0)) {
+        cand.push_back(slr_ctx::BTune{th, div, r});
+        if (one || r == 1) break;
+      }
+    }
+  double best = 1e30;
+  slr_ctx::BTune pick = keep;
+  // the built-in plan first, as the reference
+  tu = slr_ctx::BTune{};
+  double ms = 0.0;
+  int rc = slr_time_kernel(c, 0, nrhs, reps, hip_stream, &ms);
+  if (rc) {
+    tu = keep;
+    return rc;
+  }
+  best = ms;
+  pick = tu;
+  for (const auto &cd : cand) {
+    tu = cd;
+    rc = slr_time_kernel(c, 0, nrhs, reps, hip_stream, &ms);
+    if (rc) {
+      tu = keep;
+      return rc;
+    }
+    if (ms < best * 0.98) {
+      best = ms;
+      pick = cd;
+    }
+  }
+  tu = pick;
+  // chunks of the rank-k partials (the sums' grouping: every later apply of
+  // this context, alone or in a batch, uses the same value)
+  if (c->k > 0) {
+    int32_t *nb = c->uk_prec == SLR_BF16 ? &c->lrm_nblk : &c->lr_nblk;
+    const int32_t nb0 = *nb;
+    double bl = 1e30;
+    int32_t bnb = nb0;
+    for (int32_t v : {nb0, 128, 256, 512, 1024, 2048}) {
+      *nb = v;
+      if ((rc = ws_ensure(c, c->ws, nrhs))) return rc;
+      if ((rc = slr_time_kernel(c, 2, nrhs, reps, hip_stream, &ms))) {
+        *nb = nb0;
+        return rc;
+      }
+      if (ms < bl * (v == nb0 ? 1.0 : 0.98)) {
+        bl = ms;
+        bnb = v;
+      }
+    }
+    *nb = bnb;
+    if (c->uk_prec != SLR_BF16) c->lr_nblk_tuned = bnb;
+    if ((rc = ws_ensure(c, c->ws, nrhs))) return rc;
+  }
+  c->info.tune_b_threads1 = c->tune1.threads;
+  c->info.tune_b_lds_div1 = c->tune1.lds_div;
+  c->info.tune_b_threadsM = c->tuneM.threads;
+  c->info.tune_b_lds_divM = c->tuneM.lds_div;
+  c->info.tune_b_rmaxM = c->tuneM.threads ? c->tuneM.rmax : 0;
+  c->info.lr_chunks = c->uk_prec == SLR_BF16 ? c->lrm_nblk : c->lr_nblk;
+  return SLR_OK;
+}
+
 int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *o, slr_info *info,
                 int64_t *perm) {
   if (!A || !part || !o || !info || !A->rowptr || !A->col || !A->val) return fail(SLR_ERR_ARG, "null argument");
@@ -1833,6 +1928,7 @@ void slr_destroy(slr_ctx *c) {
 int slr_query(const slr_ctx *c, slr_info *info) {
   if (!c || !info) return fail(SLR_ERR_ARG, "null");
   *info = c->info;
+  info->lr_chunks = c->uk_prec == SLR_BF16 ? c->lrm_nblk : c->lr_nblk;
   info->device_bytes =
       c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes + c->rf.pool.bytes +
       (int64_t)(c->lz.cap + c->gm.cap);

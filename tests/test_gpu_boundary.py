@@ -175,3 +175,33 @@ def test_service_admits_by_bytes_under_a_shared_budget():
         bt.close()
         assert out[0][2]["iters"] == rq.info["iters"]
         assert torch.equal(out[0][1].reshape(rq.x.shape), rq.x)
+
+
+@pytest.mark.parametrize("prec", [("fp64", "fp64"), ("fp32", "bf16")])
+def test_autotune_keeps_results(prec):
+    """slr_autotune picks the B kernel's launch shape for one and for several
+    columns and the rank-k chunks: the apply still matches the oracle, and a
+    column applied alone (the one-column shape) equals, bit for bit, the
+    same column inside a 12-column apply (the several-column shape)."""
+    import oracle as O
+    fp, up = prec
+    print(f"autotune: {fp}/{up}", flush=True)
+    pr = si.make_config("diffusion2d_1024", N=192, boxes=6)
+    Po = O.setup(pr.csr, pr.part, pr.nparts, 16, 80, b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor",
+                 fact_prec=fp, uk_prec=up, v0=pr.v0())
+    G = _slr(pr, k=16, lanczos_steps=80, c_order="multicolor", fact_prec=fp, uk_prec=up,
+             lowrank=(Po.U, Po.lam, Po.theta))
+    t12 = G.autotune(12)
+    t1 = G.autotune(1)
+    assert t12["tune_b_threadsM"] in (0, 256, 512, 1024) and t1["tune_b_threads1"] in (0, 256, 512, 1024)
+    assert t1["lr_chunks"] >= 128
+    r = np.random.default_rng(9).uniform(-1, 1, (pr.n, 12))
+    Z = G.apply(_dev(r)).cpu().numpy()
+    zo = Po.apply(r)
+    err = (np.linalg.norm(Z - zo, axis=0) / np.linalg.norm(zo, axis=0)).max()
+    assert err <= (1e-12 if fp == "fp64" else 1e-5), err
+    for j in (0, 5, 11):
+        assert np.array_equal(G.apply(_dev(r[:, j])).cpu().numpy(), Z[:, j])
+    Gi = type(G).import_setup(G.export_setup())
+    assert Gi.info["lr_chunks"] == G.info["lr_chunks"]
+    assert np.array_equal(Gi.apply(_dev(r)).cpu().numpy(), Z)
