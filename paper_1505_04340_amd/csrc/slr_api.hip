@@ -255,6 +255,10 @@ struct slr_ctx {
   int32_t cf_nlev = 0, cb_nlev = 0;
   int64_t cb_nnz = 0;           // weight entries of the backward interface schedule
   bool c_one_wg = true;
+  // lanes per row of the interface sweeps (> 1: rows long enough that one
+  // launch per level with a group of lanes per row wins; set from the mean
+  // row length of each sweep)
+  int32_t cf_group = 1, cb_group = 1;
   bool c_two_level = false;     // interface schedules of <= 2 levels: one launch per sweep
   int32_t b_threads = 1024;
   int32_t n_cu = 256;           // compute units of the device
@@ -474,12 +478,13 @@ int bsolve(slr_ctx *c, const BArgs &a, bool compute64, hipStream_t st) {
 void csweep(slr_ctx *c, bool fwd, double *x, int64_t ldx, int32_t nrhs, bool compute64, hipStream_t st) {
   const int32_t nlev = fwd ? c->cf_nlev : c->cb_nlev;
   const int32_t *lev = fwd ? c->cf_lev_h.data() : c->cb_lev_h.data();
+  const int32_t G = fwd ? c->cf_group : c->cb_group;
   if (c->fact_prec == SLR_FP64) {
-    launch_sweep<double, double>(fwd ? c->Cfd : c->Cbd, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st);
+    launch_sweep<double, double>(fwd ? c->Cfd : c->Cbd, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st, G);
   } else if (compute64) {
-    launch_sweep<float, double>(fwd ? c->Cff : c->Cbf, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st);
+    launch_sweep<float, double>(fwd ? c->Cff : c->Cbf, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st, G);
   } else {
-    launch_sweep<float, float>(fwd ? c->Cff : c->Cbf, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st);
+    launch_sweep<float, float>(fwd ? c->Cff : c->Cbf, lev, nlev, (int32_t)c->s, x, ldx, nrhs, c->c_one_wg, st, G);
   }
 }
 
@@ -1317,7 +1322,7 @@ int export_setup(const slr_ctx *cc, std::vector<uint8_t> &blob) {
   w.pod(c->fact_prec); w.pod(c->uk_prec);
   w.vec(c->cf_lev_h); w.vec(c->cb_lev_h);
   w.pod(c->cf_nlev); w.pod(c->cb_nlev); w.pod(c->cb_nnz);
-  w.pod(c->c_one_wg); w.pod(c->c_two_level); w.pod(c->nnz_a);
+  w.pod(c->c_one_wg); w.pod(c->c_two_level); w.pod(c->nnz_a); w.pod(c->cf_group); w.pod(c->cb_group);
   w.pod(c->b_max_m); w.pod(c->b_max_lev); w.pod(c->b_max_level_bytes); w.pod(c->b_data_bytes);
   auto dump = [&](auto &B, auto &Cf, auto &Cb) -> int {
     w.pod(B.max_m); w.pod(B.max_lev); w.pod(B.max_level_bytes); w.pod(B.max_K); w.pod(B.pack_K);
@@ -1374,7 +1379,7 @@ int import_setup(const uint8_t *buf, size_t bytes, hipStream_t st, slr_ctx **out
   r.pod(c->fact_prec); r.pod(c->uk_prec);
   r.vec(c->cf_lev_h); r.vec(c->cb_lev_h);
   r.pod(c->cf_nlev); r.pod(c->cb_nlev); r.pod(c->cb_nnz);
-  r.pod(c->c_one_wg); r.pod(c->c_two_level); r.pod(c->nnz_a);
+  r.pod(c->c_one_wg); r.pod(c->c_two_level); r.pod(c->nnz_a); r.pod(c->cf_group); r.pod(c->cb_group);
   r.pod(c->b_max_m); r.pod(c->b_max_lev); r.pod(c->b_max_level_bytes); r.pod(c->b_data_bytes);
   if (!r.ok) return bad("truncated header");
   if (c->n < 0 || c->m < 0 || c->s < 0 || c->m + c->s != c->n || c->p < 1 ||
@@ -1577,6 +1582,17 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->cb_nnz = (int64_t)H.cbwd.ci.size();
   // shallow interface schedules (multicolour) run one launch per level
   c->c_one_wg = std::max(c->cf_nlev, c->cb_nlev) > 8;
+  {
+    // mean entries per row >= 8: one launch per level, lanes per row by length
+    auto group = [](const Sweep &sw) {
+      const double mean = sw.nrows > 0 ? (double)sw.ci.size() / sw.nrows : 0.0;
+      return mean < 8.0 ? 1 : (mean < 24.0 ? 4 : (mean < 64.0 ? 8 : 16));
+    };
+    if (!(std::max(c->cf_nlev, c->cb_nlev) <= 2)) {
+      c->cf_group = group(H.cfwd);
+      c->cb_group = group(H.cbwd);
+    }
+  }
   c->c_two_level = std::max(c->cf_nlev, c->cb_nlev) <= 2;
   if (c->c_one_wg && sizeof(int32_t) * (size_t)(std::max(c->cf_nlev, c->cb_nlev) + 1) > c->lds_limit)
     return destroy_fail(fail(SLR_ERR_ARG, "interface level schedule too deep for one workgroup"));

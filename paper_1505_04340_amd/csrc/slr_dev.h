@@ -146,9 +146,10 @@ void launch_bsolve(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t 
 // In-place level-scheduled sweep of one (interface) block on a global
 // vector: x (ld, nrhs columns).  Deep schedules run in one workgroup per
 // column; shallow ones launch once per level over the whole device.
+// G > 1 (sweeps with long rows): one launch per level, G lanes per row.
 template <typename TS, typename TC>
 void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nlev, int32_t nrows,
-                  double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st);
+                  double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st, int32_t G = 1);
 
 // Out-of-place sweep of a schedule with at most two levels, one launch.
 // dv (optional, nrhs == 1): per-block partial sums of dv . y to dpart

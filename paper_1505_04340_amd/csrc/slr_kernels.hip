@@ -151,6 +151,28 @@ __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
 // One level of a packed sweep with any row width K, solved by the whole
 // workgroup (rows x columns spread over the threads), read from LDS.  The
 // subtraction order is the same in every variant.
+// Rows of an ELL level with long rows (width K > 8): G lanes per row and
+// column, lane g summing the entries g, g + G, ..., the partial sums added
+// by a butterfly, then x_row = sc x_row - sum.  Whole groups iterate
+// together (blockDim.x is a multiple of G).
+template <typename TS, typename TC, int G>
+__device__ __forceinline__ void level_group(const uint16_t *rows, const TS *sc, const uint16_t *ci, const TS *w,
+                                            int L, int K, TC *xs, int XS, int Rg) {
+  const int g = threadIdx.x % G;
+  for (int t = threadIdx.x / G; t < L * Rg; t += blockDim.x / G) {
+    const int j = t / Rg, r = t - j * Rg;
+    TC *xc = xs + r * XS;
+    TC part = 0;
+    for (int e = g; e < K; e += G) part += cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, G);
+    if (g == 0) {
+      const int row = rows[j];
+      xc[row] = cvt<TC>(sc[j]) * xc[row] - part;
+    }
+  }
+}
+
 template <typename TS, typename TC>
 __device__ __forceinline__ void level_from_lds(const uint8_t *seg, int L, TC *xs, int XS, int Rg) {
   const int K = *reinterpret_cast<const int32_t *>(seg);
@@ -161,13 +183,21 @@ __device__ __forceinline__ void level_from_lds(const uint8_t *seg, int L, TC *xs
   const int o_ci = o_sc + pad8((int)sizeof(TS) * L);
   const uint16_t *ci = reinterpret_cast<const uint16_t *>(base + o_ci);
   const TS *w = reinterpret_cast<const TS *>(base + o_ci + pad8(2 * K * L));
-  for (int t = threadIdx.x; t < L * Rg; t += blockDim.x) {
-    const int j = t / Rg, r = t - j * Rg;
-    TC *xc = xs + r * XS;
-    const int row = rows[j];
-    TC acc = cvt<TC>(sc[j]) * xc[row];
-    for (int e = 0; e < K; ++e) acc -= cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
-    xc[row] = acc;
+  if (K <= 8) {
+    for (int t = threadIdx.x; t < L * Rg; t += blockDim.x) {
+      const int j = t / Rg, r = t - j * Rg;
+      TC *xc = xs + r * XS;
+      const int row = rows[j];
+      TC acc = cvt<TC>(sc[j]) * xc[row];
+      for (int e = 0; e < K; ++e) acc -= cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
+      xc[row] = acc;
+    }
+  } else if (K <= 32) {
+    level_group<TS, TC, 4>(rows, sc, ci, w, L, K, xs, XS, Rg);
+  } else if (K <= 128) {
+    level_group<TS, TC, 16>(rows, sc, ci, w, L, K, xs, XS, Rg);
+  } else {
+    level_group<TS, TC, 64>(rows, sc, ci, w, L, K, xs, XS, Rg);
   }
 }
 
@@ -609,6 +639,38 @@ __global__ void __launch_bounds__(256) k_sweep_lvl(SweepArrays<TS> S, int a, int
   sweep_row<TS, TC>(S, t, x + (int64_t)blockIdx.y * ldx);
 }
 
+// One level of a sweep with long rows: G lanes per row, lane g summing the
+// entries g, g + G, ... (loads of a lane issued four at a time), the G
+// partial sums added by a butterfly, then x_row = sc x_row - sum.
+template <typename TS, typename TC, int G>
+__global__ void __launch_bounds__(256) k_sweep_lvl_g(SweepArrays<TS> S, int a, int b, double *x, int64_t ldx) {
+  const int g = threadIdx.x % G;
+  const int t = a + (blockIdx.x * blockDim.x + threadIdx.x) / G;
+  if (t >= b) return;   // whole groups leave together
+  double *xc = x + (int64_t)blockIdx.y * ldx;
+  const int e0 = S.rp[t], e1 = S.rp[t + 1];
+  TC part = 0;
+  for (int e = e0 + g; e < e1; e += 4 * G) {
+    TC wv[4], xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ee = e + u * G;
+      const bool ok = ee < e1;
+      const int ec = ok ? ee : e0;
+      wv[u] = ok ? cvt<TC>(S.w[ec]) : (TC)0;
+      xv[u] = (TC)xc[S.ci[ec]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) part += wv[u] * xv[u];
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, G);
+  if (g == 0) {
+    const int row = S.rows[t];
+    xc[row] = (double)(cvt<TC>(S.sc[t]) * (TC)xc[row] - part);
+  }
+}
+
 // Whole sweep of a schedule with at most two levels, out of place
 // (y = T^{-1} x): level-0 rows have no entries (y = sc x); level-1 rows
 // depend on level-0 rows only, whose values sc_j x_j are folded into the
@@ -647,8 +709,23 @@ void launch_sweep2(const SweepArrays<TS> &S, int32_t nrows, const double *x, int
 
 template <typename TS, typename TC>
 void launch_sweep(const SweepArrays<TS> &S, const int32_t *lev_host, int32_t nlev, int32_t nrows,
-                  double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st) {
+                  double *x, int64_t ldx, int32_t nrhs, bool one_wg, hipStream_t st, int32_t G) {
   if (nlev == 0 || nrhs == 0) return;
+  if (G > 1) {
+    // long rows: one launch per level, G lanes per row
+    for (int l = 0; l < nlev; ++l) {
+      const int a = lev_host[l], b = lev_host[l + 1];
+      if (b <= a) continue;
+      dim3 grid((unsigned)(((int64_t)(b - a) * G + 255) / 256), nrhs);
+      if (G == 4)
+        hipLaunchKernelGGL((k_sweep_lvl_g<TS, TC, 4>), grid, dim3(256), 0, st, S, a, b, x, ldx);
+      else if (G == 8)
+        hipLaunchKernelGGL((k_sweep_lvl_g<TS, TC, 8>), grid, dim3(256), 0, st, S, a, b, x, ldx);
+      else
+        hipLaunchKernelGGL((k_sweep_lvl_g<TS, TC, 16>), grid, dim3(256), 0, st, S, a, b, x, ldx);
+    }
+    return;
+  }
   if (one_wg) {
     hipLaunchKernelGGL((k_sweep_wg<TS, TC>), dim3(nrhs), dim3(512), sizeof(int32_t) * (nlev + 1), st, S,
                        nlev, x, ldx);
@@ -2794,11 +2871,11 @@ template void launch_sweep2<float, float>(const SweepArrays<float> &, int32_t, c
 template void launch_sweep2<float, double>(const SweepArrays<float> &, int32_t, const double *, int64_t, double *,
                                            int64_t, int32_t, hipStream_t, const double *, double *);
 template void launch_sweep<double, double>(const SweepArrays<double> &, const int32_t *, int32_t, int32_t, double *,
-                                           int64_t, int32_t, bool, hipStream_t);
+                                           int64_t, int32_t, bool, hipStream_t, int32_t);
 template void launch_sweep<float, float>(const SweepArrays<float> &, const int32_t *, int32_t, int32_t, double *,
-                                         int64_t, int32_t, bool, hipStream_t);
+                                         int64_t, int32_t, bool, hipStream_t, int32_t);
 template void launch_sweep<float, double>(const SweepArrays<float> &, const int32_t *, int32_t, int32_t, double *,
-                                          int64_t, int32_t, bool, hipStream_t);
+                                          int64_t, int32_t, bool, hipStream_t, int32_t);
 template void launch_lowrank<double>(const double *, int64_t, int32_t, const double *, double, const double *,
                                      int64_t, double *, int64_t, int32_t, double *, int32_t, double *,
                                      unsigned int *, hipStream_t);
