@@ -193,13 +193,22 @@ def multi_rhs_apply(P, torch, nrhs=32, reps=10):
     return out
 
 
-def apply_profile(P, torch, name, form, nrhs, reps, autotune=False):
-    """Only set up one workload and time its apply (for profiler runs)."""
+def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=False):
+    """Only set up one workload and time its apply (for profiler runs).
+    threshold: ILDLT / ICT local solvers with drop tolerance 1e-4, B_i in
+    minimum degree order and C in HID order (the form in which the shifted
+    128^3 workload converges) instead of the zero-fill ones in multicolour
+    order."""
     import slr_inputs as si
     pr = si.make_config(name)
     fp, up = {"fp64": ("fp64", "fp64"), "fp32": ("fp32", "fp32"), "mixed": ("fp32", "bf16")}[form]
-    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
-              c_fact=pr.c_fact, c_order="multicolor", fact_prec=fp, uk_prec=up, v0=pr.v0())
+    if threshold:
+        kw = dict(b_fact="ildlt" if pr.b_fact.startswith("ildlt") else "ict", c_fact="ict", droptol=1e-4,
+                  c_order="hid", b_order="mindeg")
+    else:
+        kw = dict(b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor")
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, fact_prec=fp, uk_prec=up,
+              v0=pr.v0(), **kw)
     torch.cuda.synchronize()
     tune = G.autotune(nrhs) if autotune else None
     info = G.query()
@@ -209,7 +218,8 @@ def apply_profile(P, torch, name, form, nrhs, reps, autotune=False):
     bu = {"fp64": 8, "fp32": 4, "bf16": 2}[up]
     ab = apply_bytes(info, nrhs, bf, bu, info["k"])
     bb = bsolve_bytes(info, nrhs, bf)
-    print(json.dumps({"workload": name, "form": form, "nrhs": nrhs, "apply_ms": round(ms, 5),
+    print(json.dumps({"workload": name, "form": form, "nrhs": nrhs, "threshold_hid": threshold,
+                      "apply_ms": round(ms, 5),
                       "apply_algorithmic_bytes": int(ab), "apply_GBs": round(ab / (ms * 1e-3) / 1e9, 1),
                       "bsolve1_algorithmic_bytes": int(bb),
                       "bsolve1_GBs": round(bb / (stages["bsolve1"] * 1e-3) / 1e9, 1),
@@ -426,6 +436,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--autotune", action="store_true", help="with --apply-profile: slr_autotune first")
+    ap.add_argument("--threshold", action="store_true",
+                    help="with --apply-profile: ILDLT/ICT (1e-4), minimum degree B_i, HID C")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -434,7 +446,8 @@ def main():
         import torch
         import paper_1505_04340_amd as P
         torch.cuda.set_device(0)
-        apply_profile(P, torch, args.apply_profile, args.apply_form, args.nrhs, args.reps, args.autotune)
+        apply_profile(P, torch, args.apply_profile, args.apply_form, args.nrhs, args.reps, args.autotune,
+                      args.threshold)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

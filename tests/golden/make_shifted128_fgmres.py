@@ -1,0 +1,47 @@
+"""Writes tests/golden/shifted128_fgmres.json: the oracle's FGMRES(40) run on
+the shifted 3-D 128^3 workload (20 negative eigenvalues, 8x8x8 boxes) with
+the threshold local solvers of Sec. 6 -- ILDLT B_i after a minimum degree
+ordering, ICT C in HID order (Sec. 5.2), drop tolerance 1e-4 -- k = 64 from
+320 Lanczos steps (5k, Sec. 6), rtol 1e-8, at most 1000 iterations.
+
+Calls only the oracle and the input generators; about 25 minutes on one
+core.  Run from the repository root: python tests/golden/make_shifted128_fgmres.py
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+import slr_inputs as si  # noqa: E402
+
+
+def main():
+    pr = si.make_config("shifted3d_128")
+    t0 = time.time()
+    P = O.setup(pr.csr, pr.part, pr.nparts, pr.k, pr.lanczos_steps, b_fact="ildlt", c_fact="ict", droptol=1e-4,
+                c_order="hid", b_order="mindeg", v0=pr.v0())
+    t1 = time.time()
+    xs, b = pr.rhs()
+    r = O.solve(P, b[:, 0], "fgmres", rtol=1e-8, maxit=1000, restart=40)
+    t2 = time.time()
+    out = {
+        "workload": "shifted 3-D 7-point Laplacian 128^3, 20 negative eigenvalues, 8x8x8 boxes",
+        "method": "ILDLT B_i (minimum degree order), ICT C (HID order), droptol 1e-4, k=64, 320 Lanczos steps, "
+                  "FGMRES(40), rtol 1e-8, maxit 1000",
+        "iters": int(r.iters), "converged": bool(r.converged), "true_relres": float(r.true_relres),
+        "ritz_above_1": int(np.sum(P.ritz > 1.0)), "nnz_LB": int(P.FB.v.size), "nnz_LC": int(P.FC.v.size),
+        "theta": float(P.theta), "setup_s": round(t1 - t0, 1), "solve_s": round(t2 - t1, 1),
+    }
+    with open(os.path.join(ROOT, "tests", "golden", "shifted128_fgmres.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(out)
+
+
+if __name__ == "__main__":
+    main()
