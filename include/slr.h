@@ -148,6 +148,25 @@ typedef struct {
      (default NATURAL); every factor, level schedule and refactorisation
      plan follows it.  Other values are SLR_ERR_ARG. */
   int32_t b_order;
+  /* Interface solver.  1 (default): C = L L^T from c_fact.  2: the recursive
+     SLR on C of Sec. 5.2 -- with C in HID order (c_order must be
+     SLR_CORDER_HID) C = [C1 F; F^T C2], C1 the nodes of the lowest connector
+     level (block diagonal: its connected pieces, which must each be a
+     contiguous range of the order), and C's solve is itself an SLR
+     preconditioner with B := C1, E := F, C := C2 (both factored with
+     c_fact), rank k2 from lanczos_steps2 inner Lanczos steps (full
+     reorthogonalisation, started from the start vector's entries on C2) and
+     theta2 = lambda_{k2+1}.  That inner preconditioner is used in the
+     factored form K K^T (K^T in place of L^{-1}, K in place of L^{-T}):
+       K^T v = (L1^{-1} v1, Q2 L2^{-1}(v2 - F^T C1^{-1} v1)),
+       K w   = (L1^{-T}(w1 - L1^{-1} F b2), b2 = L2^{-T} Q2 w2),
+     Q2 = G2^{1/2}, G2 = rho2 I + U2 D2 U2^T of eq. skt one level down; G2 must
+     be positive definite (every inner Ritz value kept and theta2 below 1,
+     else SLR_ERR_C_NOT_SPD).  Not with refactor; a single connector level
+     is SLR_ERR_ARG. */
+  int32_t c_levels;
+  int32_t k2;             /* inner rank (0 => k), at most 64                 */
+  int32_t lanczos_steps2; /* inner Lanczos steps (0 => 5 k2)                 */
 } slr_opts;
 
 typedef struct {
@@ -189,6 +208,13 @@ typedef struct {
   int32_t tune_b_threads1, tune_b_lds_div1;
   int32_t tune_b_threadsM, tune_b_lds_divM, tune_b_rmaxM;
   int32_t lr_chunks;
+  /* recursive interface solver (c_levels 2; zero otherwise): nodes of C1,
+     inner rank, inner Lanczos steps taken, deepest C1 block sweep, level
+     count of C2's forward sweep, theta2 */
+  int64_t s1;
+  int32_t k2, lanczos_steps2;
+  int32_t c1_levels, c2_levels;
+  double theta2;
 } slr_info;
 
 typedef struct slr_ctx slr_ctx;
@@ -349,6 +375,14 @@ int slr_query(const slr_ctx *c, slr_info *info);
 int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda,
                double *U, double *alpha, double *beta);
 
+/* slr_export_inner: the recursive interface solver's inner low-rank part
+ * (c_levels 2, Sec. 5.2 with Sec. 5.1 one level down) to host buffers (any
+ * may be NULL): ritz2 (slr_info.lanczos_steps2 values, descending), lambda2
+ * (k2), U2 (s2 x k2 column-major FP64, s2 = s - s1, rows in the interface
+ * order after the s1 nodes of C1); theta2 is in slr_info.  SLR_ERR_ARG for
+ * a context without it. */
+int slr_export_inner(const slr_ctx *c, double *ritz2, double *lambda2, double *U2);
+
 /* slr_export_setup: serialise the whole resident preconditioner -- the
  * DD ordering, A in that order, the packed B_i sweeps with E and E^T
  * (Sec. 2.1, Sec. 5.2), C's sweeps, the low-rank part (U_k in FP64,
@@ -357,7 +391,8 @@ int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda,
  * buf == NULL only the size is returned.  cap < *bytes is SLR_ERR_ARG.
  * Current values are taken (after slr_refactor, the refactored ones).  The
  * layout is this library build's own (magic, length, records, FNV-1a
- * checksum), native byte order. */
+ * checksum), native byte order.  A context with the recursive interface
+ * solver (c_levels 2) is SLR_ERR_ARG. */
 int slr_export_setup(const slr_ctx *c, void *buf, size_t cap, size_t *bytes);
 
 /* slr_import: a new context on the current device from slr_export_setup's

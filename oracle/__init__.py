@@ -438,11 +438,117 @@ class SLR:
         return out
 
 
+class MultilevelC:
+    """Interface factor of the recursive SLR method (Sec. 5.2): instead of a
+    factor of C, the SLR preconditioner is applied to C itself.
+
+    In HID order C = [C1 F; F^T C2] with C1 the nodes of the lowest
+    connector level, block diagonal (one block per connector).  The inner
+    SLR takes B := C1, E := F and C := C2 = L2 L2^T, H2 = L2^{-1} F^T C1^{-1}
+    F L2^{-T} (eq. H one level down) and (I - H2)^{-1} ~ G2 = rho2 I + U2 D2
+    U2^T (eq. skt with theta2 = lambda_{k2+1}).  READING (the paper leaves
+    the multilevel scheme to future work): so that the outer Lanczos keeps
+    running on a symmetric operator, the inner preconditioner is written as
+    M_C^{-1} = K K^T with
+        K^T = [ L1^{-1}                          0          ]
+              [ -Q2 L2^{-1} F^T C1^{-1} L1       Q2 L2^{-1} ],  applied as
+    a1 = L1^{-1} v1, a2 = Q2 L2^{-1} (v2 - F^T L1^{-T} a1), and
+    K w = (L1^{-T}(w1 - L1^{-1} F b2), b2 = L2^{-T} Q2 w2), where
+    Q2 = G2^{1/2} = sqrt(rho2) I + U2 diag(sqrt(rho2 + d_i) - sqrt(rho2)) U2^T
+    (U2 has orthonormal columns).  K K^T is the eq. M block inverse of the
+    inner SLR, and the outer method uses K^T and K where a plain SLR uses
+    L^{-1} and L^{-T}.  G2 must be positive definite: every lambda2_i and
+    theta2 below 1."""
+
+    def __init__(self, inner: "SLR"):
+        self.inner = inner
+        self.s1, self.s2 = inner.m, inner.s
+        self.n = self.s1 + self.s2
+        rho2 = 1.0 / (1.0 - inner.theta)
+        if not rho2 > 0.0 or (inner.k and np.any(inner.lam >= 1.0)):
+            raise OracleError("C_NOT_SPD", "inner low-rank correction is not positive definite (a Ritz value >= 1)")
+        self.sq = math.sqrt(rho2)
+        self.qd = (np.sqrt(1.0 / (1.0 - inner.lam)) - self.sq) if inner.k else np.zeros(0)
+
+    def _q(self, x: np.ndarray) -> np.ndarray:
+        """Q2 x = sqrt(rho2) x + U2 diag(qd) U2^T x."""
+        out = self.sq * x
+        if self.inner.k:
+            out = out + self.inner.U @ (self.qd * (self.inner.U.T @ x))
+        return out
+
+    def lower(self, v: np.ndarray) -> np.ndarray:
+        """K^T v (takes the place of L^{-1} v)."""
+        P = self.inner
+        v = np.asarray(v, dtype=np.float64)
+        a1 = P.FB.lower(v[:self.s1])
+        t = v[self.s1:] - P.E.T @ P.FB.upper(a1)
+        return np.concatenate([a1, self._q(P.FC.lower(t))])
+
+    def upper(self, w: np.ndarray) -> np.ndarray:
+        """K w (takes the place of L^{-T} w)."""
+        P = self.inner
+        w = np.asarray(w, dtype=np.float64)
+        b2 = P.FC.upper(self._q(w[self.s1:]))
+        b1 = P.FB.upper(w[:self.s1] - P.FB.lower(P.E @ b2))
+        return np.concatenate([b1, b2])
+
+    def solve(self, x: np.ndarray) -> np.ndarray:
+        """M_C^{-1} x = K K^T x."""
+        return self.upper(self.lower(x))
+
+    def round_to(self, prec: str):
+        """The inner factors are rounded when they are built (before the
+        inner Lanczos run), so there is nothing left to do here."""
+
+
+def multilevel_c(C: sp.csr_matrix, lev: np.ndarray, c_fact: str, droptol: float, k2: int, steps2: int,
+                 v0_2: np.ndarray, fact_prec: str = "fp64", lowrank2=None) -> MultilevelC:
+    """Build the recursive interface solver of Sec. 5.2 from C in HID order
+    (lev: the connector level of every interface node, non-decreasing).
+    The nodes of the lowest level are C1, whose blocks (the connectors) are
+    the connected pieces of its graph, each a contiguous range; both C1 and
+    C2 are factored with c_fact and rounded to fact_prec; the inner Lanczos
+    (full reorthogonalisation, steps2 steps from v0_2, the C2 entries of the
+    outer start vector) gives U2, Lambda2 and theta2 = lambda_{k2+1}.
+    lowrank2: optional (U2, lam2, theta2) used instead of that run."""
+    from scipy.sparse import csgraph
+    s = C.shape[0]
+    lev = np.asarray(lev)
+    s1 = int(np.sum(lev == lev.min())) if s else 0
+    if s1 == 0 or s1 == s:
+        raise OracleError("ARG", "the HID order has a single connector level: nothing to recurse on")
+    C1 = C[:s1, :s1].tocsr()
+    F = C[:s1, s1:].tocsr()
+    C2 = C[s1:, s1:].tocsr()
+    ncomp, lab = csgraph.connected_components(C1, directed=False)
+    starts = np.flatnonzero(np.concatenate([[True], lab[1:] != lab[:-1]]))
+    if len(starts) != ncomp:
+        raise OracleError("ARG", "a connector of the leading level is not contiguous")
+    off1 = np.concatenate([starts, [s1]])
+    FB2 = factorize(C1, c_fact, off1, "C", droptol)
+    FC2 = factorize(C2, c_fact, [0, s - s1], "C", droptol)
+    FB2.round_to(fact_prec)
+    FC2.round_to(fact_prec)
+    inner = SLR(C, np.arange(s), off1, np.array([0, s - s1]), s1, s - s1, C, F, C2, FB2, FC2)
+    if lowrank2 is not None:
+        U2, lam2, th2 = lowrank2
+        inner.U = np.array(U2, dtype=np.float64).reshape(s - s1, -1)
+        inner.lam = np.array(lam2, dtype=np.float64)
+        inner.k = inner.U.shape[1]
+        inner.theta = float(th2)
+    elif k2 > 0:
+        lanczos_lowrank(inner, k2, steps2 or 5 * k2, np.asarray(v0_2, dtype=np.float64), "lambda_k1",
+                        reorth="full")
+    return MultilevelC(inner)
+
+
 def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "ic0",
           c_fact: str = "ic0", c_order: str = "subdomain", theta_mode: str = "lambda_k1",
           fact_prec: str = "fp64", uk_prec: str = "fp64", v0: np.ndarray | None = None,
           lowrank=None, eps: float = 0.0, cond_K: float = 0.0, reorth: str = "partial",
-          droptol: float = 1e-3, seed: int = 7, b_order: str = "natural") -> SLR:
+          droptol: float = 1e-3, seed: int = 7, b_order: str = "natural", c_levels: int = 1,
+          k2: int = 0, lanczos_steps2: int = 0, lowrank2=None) -> SLR:
     """Build the SLR preconditioner (Sec. 4 and Sec. 5).
 
     A: scipy CSR or (indptr, indices, data, n).  part: subdomain labels
@@ -458,7 +564,12 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     Lanczos with full ("full") or partial ("partial", Sec. 5.1)
     reorthogonalisation.  b_fact / c_fact "ict" (and "ildlt" for B): threshold
     factors with drop tolerance droptol (factorize).  b_order "natural" or
-    "mindeg" (the minimum degree order of each B_i, dd_ordering)."""
+    "mindeg" (the minimum degree order of each B_i, dd_ordering).
+    c_levels 2: the recursive SLR on C of Sec. 5.2 (MultilevelC, C in HID
+    order) replaces the factor of C, with rank k2 (default k) from
+    lanczos_steps2 (default 5 k2) inner Lanczos steps started from the
+    start vector's entries on the inner interface; lowrank2 as lowrank for
+    the inner level."""
     if theta_mode == "eps" and not eps > 0.0:
         raise OracleError("ARG", "theta_mode eps needs eps > 0")
     if isinstance(A, tuple):
@@ -475,8 +586,20 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
     E = Ap[:m, m:].tocsr()
     C = Ap[m:, m:].tocsr()
     FB = factorize(B, b_fact, off_b, "B", droptol)
-    # exact C solve: one dense block; otherwise IC(0)
-    FC = factorize(C, c_fact, [0, s], "C", droptol)
+    if v0 is None and (k > 0 or c_levels == 2):
+        v0 = splitmix64_uniform(A.shape[0], seed)
+    if c_levels == 2:
+        if c_order != "hid":
+            raise OracleError("ARG", "the recursive interface solver needs the HID order of C")
+        kk2 = k2 if k2 > 0 else k
+        s1 = int(np.sum(colors == colors.min())) if s else 0
+        FC = multilevel_c(C, colors, c_fact, droptol, kk2, lanczos_steps2, np.asarray(v0)[perm[m + s1:]],
+                          fact_prec, lowrank2)
+    elif c_levels == 1:
+        # exact C solve: one dense block; otherwise IC(0)
+        FC = factorize(C, c_fact, [0, s], "C", droptol)
+    else:
+        raise OracleError("ARG", "c_levels is 1 or 2")
     FB.round_to(fact_prec)
     FC.round_to(fact_prec)
     P = SLR(A, perm, off_b, off_y, m, s, Ap, E, C, FB, FC, colors=colors)
@@ -488,8 +611,6 @@ def setup(A, part, nparts: int, k: int, lanczos_steps: int = 0, b_fact: str = "i
         P.theta = 0.0 if theta_mode == "eps" else float(theta)
     elif k > 0:
         steps = lanczos_steps or 5 * k
-        if v0 is None:
-            v0 = splitmix64_uniform(A.shape[0], seed)
         lanczos_lowrank(P, k, steps, np.asarray(v0)[perm[m:]], theta_mode, cond_K, reorth)
     else:
         P.theta = 0.0

@@ -67,7 +67,8 @@ class slr_opts(ctypes.Structure):
                 ("c_fact", _I32), ("c_order", _I32), ("fact_prec", _I32), ("uk_prec", _I32),
                 ("seed", _U64), ("lanczos_v0", _P), ("k_in", _I32), ("U_in", _P),
                 ("lambda_in", _P), ("theta_in", _D), ("eps", _D), ("cond_K", _D), ("reorth", _I32),
-                ("refactor", _I32), ("droptol", _D), ("b_order", _I32)]
+                ("refactor", _I32), ("droptol", _D), ("b_order", _I32), ("c_levels", _I32), ("k2", _I32),
+                ("lanczos_steps2", _I32)]
 
 
 class slr_solve_opts(ctypes.Structure):
@@ -87,7 +88,8 @@ class slr_info(ctypes.Structure):
                 ("setup_host_s", _D), ("setup_lanczos_s", _D), ("device_bytes", _I64),
                 ("lanczos_reorth", _I32), ("tune_b_threads1", _I32), ("tune_b_lds_div1", _I32),
                 ("tune_b_threadsM", _I32), ("tune_b_lds_divM", _I32), ("tune_b_rmaxM", _I32),
-                ("lr_chunks", _I32)]
+                ("lr_chunks", _I32), ("s1", _I64), ("k2", _I32), ("lanczos_steps2", _I32), ("c1_levels", _I32),
+                ("c2_levels", _I32), ("theta2", _D)]
 
 
 def _sig(name, res, args):
@@ -123,6 +125,7 @@ SLR_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 slr_set_allocator = _sig("slr_set_allocator", None, [SLR_ALLOC_FN, SLR_FREE_FN, _P])
 slr_query = _sig("slr_query", ctypes.c_int, [_P, ctypes.POINTER(slr_info)])
 slr_export = _sig("slr_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P])
+slr_export_inner = _sig("slr_export_inner", ctypes.c_int, [_P, _P, _P, _P])
 slr_spmv = _sig("slr_spmv", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_batch_create = _sig("slr_batch_create", ctypes.c_int, [_P, _I32, _I32, _D, _I32, ctypes.POINTER(_P)])
 slr_batch_admit = _sig("slr_batch_admit", ctypes.c_int, [_P, _P, _P, _I32, _I64, _P])
@@ -139,7 +142,7 @@ slr_device_lds_bytes = _sig("slr_device_lds_bytes", ctypes.c_int, [])
 EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_analyze", "slr_update_lowrank",
             "slr_grow_lowrank", "slr_refactor",
             "slr_time_kernel", "slr_apply", "slr_apply_dd", "slr_apply_dd_noalloc",
-            "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_spmv",
+            "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_export_inner", "slr_spmv",
             "slr_trim", "slr_export_setup", "slr_import", "slr_set_allocator", "slr_autotune",
             "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
             "slr_batch_active", "slr_batch_bytes", "slr_batch_destroy", "slr_destroy",
@@ -186,7 +189,7 @@ def _csr_arrays(A):
 
 def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fact="ic0",
                c_order="subdomain", fact_prec="fp64", uk_prec="fp64", seed=7, eps=0.0, cond_K=0.0,
-               reorth=None, refactor=False, droptol=1e-3, b_order="natural"):
+               reorth=None, refactor=False, droptol=1e-3, b_order="natural", c_levels=1, k2=0, lanczos_steps2=0):
     o = slr_opts()
     slr_default_opts(ctypes.byref(o))
     o.k = k
@@ -202,6 +205,7 @@ def _make_opts(k=16, lanczos_steps=0, theta_mode="lambda_k1", b_fact="ic0", c_fa
     o.refactor = 1 if refactor else 0
     o.droptol = float(droptol)
     o.b_order = _BORD[b_order]
+    o.c_levels, o.k2, o.lanczos_steps2 = int(c_levels), int(k2), int(lanczos_steps2)
     return o
 
 
@@ -280,12 +284,13 @@ class SLR:
                  c_order: str = "subdomain", fact_prec: str = "fp64", uk_prec: str = "fp64",
                  v0=None, seed: int = 7, lowrank=None, eps: float = 0.0, cond_K: float = 0.0,
                  reorth: str | None = None, refactor: bool = False, droptol: float = 1e-3,
-                 b_order: str = "natural", stream=None):
+                 b_order: str = "natural", c_levels: int = 1, k2: int = 0, lanczos_steps2: int = 0,
+                 stream=None):
         indptr, indices, data, n = _csr_arrays(A)
         self.n = n
         part = np.ascontiguousarray(part, dtype=np.int32)
         o = _make_opts(k, lanczos_steps, theta_mode, b_fact, c_fact, c_order, fact_prec, uk_prec, seed, eps, cond_K,
-                       reorth, refactor, droptol, b_order)
+                       reorth, refactor, droptol, b_order, c_levels, k2, lanczos_steps2)
         keep = []
         if v0 is not None:
             v0 = np.ascontiguousarray(v0, dtype=np.float64)
@@ -426,6 +431,18 @@ class SLR:
                           U.ctypes.data if k else None, al.ctypes.data, be.ctypes.data), "slr_export")
         return {"perm": perm, "ritz": ritz[:st] if st else ritz[:k], "lambda": lam, "U": U,
                 "alpha": al, "beta": be, "theta": inf["theta"], "m": inf["m"], "s": s}
+
+    def export_inner(self) -> dict:
+        """The recursive interface solver's inner low-rank part
+        (slr_export_inner): Ritz values, Lambda2, U2 and theta2."""
+        inf = self.query()
+        s2, k2, st = inf["s"] - inf["s1"], inf["k2"], inf["lanczos_steps2"]
+        ritz = np.empty(max(st, 1), dtype=np.float64)
+        lam = np.empty(max(k2, 1), dtype=np.float64)
+        U = np.empty((s2, k2), dtype=np.float64, order="F")
+        _check(slr_export_inner(self._h, ritz.ctypes.data, lam.ctypes.data, U.ctypes.data if k2 else None),
+               "slr_export_inner")
+        return {"ritz": ritz[:st], "lambda": lam[:k2], "U": U, "theta": inf["theta2"], "s1": inf["s1"]}
 
     def _call(self, fn, r, name, stream=None):
         import torch

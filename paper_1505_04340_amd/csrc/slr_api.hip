@@ -283,6 +283,34 @@ struct slr_ctx {
     int32_t threads = 0, lds_div = 1, rmax = 16;
   } tune1, tuneM;              // one column; several columns
   DevPool lrpool;               // U, U64, dsc
+  // Recursive interface solver (opts.c_levels == 2, Sec. 5.2): C = [C1 F;
+  // F^T C2] in HID order.  The connectors of C1 form a block-diagonal
+  // matrix solved by the B kernel (with only one of its sweeps where only
+  // L1^{-1} or L1^{-T} is wanted; their E rows are F), C2 = L2 L2^T has
+  // interface sweeps of its own, F^T is kept as CSR, and the inner rank-k2
+  // correction enters through its square root Q2 = sq I + U2 diag(qd) U2^T.
+  struct Inner {
+    bool on = false;
+    int64_t s1 = 0, s2 = 0;
+    int32_t nb = 0;                 // connectors (blocks of C1)
+    BlockArrays<double> Bd;
+    BlockArrays<float> Bf;
+    int32_t max_m = 0, max_lev = 0, max_level_bytes = 0;
+    int64_t data_bytes = 0;
+    SweepArrays<double> C2fd, C2bd;
+    SweepArrays<float> C2ff, C2bf;
+    std::vector<int32_t> f_lev_h, b_lev_h;
+    int32_t f_nlev = 0, b_nlev = 0, f_group = 1, b_group = 1;
+    bool one_wg = true;
+    int64_t *ft_rp = nullptr;
+    int32_t *ft_ci = nullptr;
+    double *ft_v = nullptr;
+    int32_t k2 = 0, steps = 0, nblk = 256;
+    double theta2 = 0.0, sq = 1.0;
+    double *U2 = nullptr, *U2rm = nullptr, *qd = nullptr;
+    std::vector<double> lam_h, ritz_h;
+    int64_t nnz_L1 = 0, nnz_L2 = 0;
+  } ml;
   int32_t live_batches = 0;     // slr_batch objects on this context
   // numeric refactorisation (slr_refactor): the input pattern, the factor
   // plans and the coefficient maps, kept when opts.refactor is set
@@ -402,20 +430,25 @@ void fgmres_layout(AR &a, int64_t n, int32_t mr, FgmresWS &w) {
 int32_t fgmres_restart(int32_t restart) { return std::max(1, std::min(restart, 200)); }
 
 
+// rank and chunk count the rank-k scratch of an apply must cover (the
+// outer correction and, with the recursive interface solver, the inner one)
+int32_t ws_rank(const slr_ctx *c) { return std::max({c->k, c->ml.k2, 1}); }
+int32_t ws_chunks(const slr_ctx *c) { return std::max({c->lr_nblk, c->lrm_nblk, c->ml.on ? c->ml.nblk : 0}); }
+
 int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
-  const int32_t nb = std::max(c->lr_nblk, c->lrm_nblk);
-  if (w.cap >= nrhs && w.W && w.k >= std::max(c->k, 1) && w.nblk >= nb) return SLR_OK;
+  const int32_t nb = ws_chunks(c), kk = ws_rank(c);
+  if (w.cap >= nrhs && w.W && w.k >= kk && w.nblk >= nb) return SLR_OK;
   w.pool.release();
   int32_t cap = std::max<int32_t>(nrhs, 1);
   w.W = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
   w.W2 = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
-  w.lr_part = w.pool.alloc<double>((size_t)nb * cap * std::max(c->k, 1));
-  w.cbuf = w.pool.alloc<double>((size_t)cap * std::max(c->k, 1));
+  w.lr_part = w.pool.alloc<double>((size_t)nb * cap * kk);
+  w.cbuf = w.pool.alloc<double>((size_t)cap * kk);
   w.counter = w.pool.alloc<unsigned int>(16);
   if (!w.W || !w.W2 || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
   HIPCHK(hipMemset(w.counter, 0, 16 * sizeof(unsigned int)));
   w.cap = cap;
-  w.k = std::max(c->k, 1);
+  w.k = kk;
   w.nblk = nb;
   return SLR_OK;
 }
@@ -425,21 +458,26 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
 // 16 (max_lev + 1).  R is the largest value (<= nrhs, <= 16) that still
 // leaves a staging buffer of at least max(largest level, min(24 KiB,
 // largest sweep)).  Returns false when not even R = 1 fits.
-bool b_lds_plan(const slr_ctx *c, int32_t nrhs, size_t tc_bytes, int32_t &R, int32_t &stage, size_t limit = 0) {
-  if (limit == 0) limit = c->lds_limit;
-  const int64_t fixed = 16 * (int64_t)(c->b_max_lev + 1) + kStageDummyBytes;
+bool b_lds_plan_sz(int32_t max_m, int32_t max_lev, int32_t max_level_bytes, int64_t data_bytes, int32_t nrhs,
+                   size_t tc_bytes, int32_t &R, int32_t &stage, size_t limit) {
+  const int64_t fixed = 16 * (int64_t)(max_lev + 1) + kStageDummyBytes;
   // the fixed-width path double-buffers the stage: each half holds a level
-  const int64_t need = std::max<int64_t>(2 * (int64_t)c->b_max_level_bytes, std::min<int64_t>(24576, c->b_data_bytes));
+  const int64_t need = std::max<int64_t>(2 * (int64_t)max_level_bytes, std::min<int64_t>(24576, data_bytes));
   for (int32_t r = std::min<int32_t>(std::max(nrhs, 1), 16); r >= 1; --r) {
-    const int64_t xb = pad16h((int64_t)tc_bytes * (std::max(c->b_max_m, 1) * r + 1));
+    const int64_t xb = pad16h((int64_t)tc_bytes * (std::max(max_m, 1) * r + 1));
     const int64_t rest = ((int64_t)limit - fixed - xb) & ~int64_t(15);
     if (rest >= need) {
       R = r;
-      stage = (int32_t)std::min<int64_t>(rest, pad16h(c->b_data_bytes));
+      stage = (int32_t)std::min<int64_t>(rest, pad16h(data_bytes));
       return true;
     }
   }
   return false;
+}
+
+bool b_lds_plan(const slr_ctx *c, int32_t nrhs, size_t tc_bytes, int32_t &R, int32_t &stage, size_t limit = 0) {
+  return b_lds_plan_sz(c->b_max_m, c->b_max_lev, c->b_max_level_bytes, c->b_data_bytes, nrhs, tc_bytes, R, stage,
+                       limit == 0 ? c->lds_limit : limit);
 }
 
 // With more subdomains than compute units and one right-hand side, the B
@@ -500,6 +538,95 @@ void csweep2(slr_ctx *c, bool fwd, const double *x, int64_t ldx, double *y, int6
     launch_sweep2<float, float>(fwd ? c->Cff : c->Cbf, s, x, ldx, y, ldy, nrhs, st, dv, dpart);
 }
 
+// ---- recursive interface solver (Sec. 5.2) --------------------------------
+// C1 solves: the B kernel over the connectors (sweeps: 1 = L1^{-1} only,
+// 2 = L1^{-T} only, 3 = both); a quarter of the LDS per workgroup when the
+// connectors fit it, so that several share a compute unit.
+int c1solve(slr_ctx *c, BArgs a, int32_t sweeps, bool compute64, hipStream_t st) {
+  const slr_ctx::Inner &I = c->ml;
+  a.sweeps = sweeps;
+  const size_t tcb = (c->fact_prec == SLR_FP64 || compute64) ? 8 : 4;
+  int32_t R = 0, stage = 0;
+  if (!b_lds_plan_sz(I.max_m, I.max_lev, I.max_level_bytes, I.data_bytes, a.nrhs, tcb, R, stage, c->lds_limit / 4) &&
+      !b_lds_plan_sz(I.max_m, I.max_lev, I.max_level_bytes, I.data_bytes, a.nrhs, tcb, R, stage, c->lds_limit))
+    return fail(SLR_ERR_ARG, "a connector does not fit the LDS of one workgroup");
+  a.R = R;
+  a.stage_bytes = stage;
+  const size_t lds = (size_t)stage + kStageDummyBytes + pad16h((int64_t)tcb * ((int64_t)I.max_m * R + 1)) +
+                     16 * (size_t)(I.max_lev + 1);
+  const int32_t threads = 256;
+  if (c->fact_prec == SLR_FP64)
+    launch_bsolve<double, double>(I.Bd, I.nb, a, threads, lds, st);
+  else if (compute64)
+    launch_bsolve<float, double>(I.Bf, I.nb, a, threads, lds, st);
+  else
+    launch_bsolve<float, float>(I.Bf, I.nb, a, threads, lds, st);
+  return SLR_OK;
+}
+
+// x <- L2^{-1} x (fwd) or L2^{-T} x over the inner interface, in place
+void c2sweep(slr_ctx *c, bool fwd, double *x, int64_t ldx, int32_t nrhs, bool compute64, hipStream_t st) {
+  const slr_ctx::Inner &I = c->ml;
+  const int32_t nlev = fwd ? I.f_nlev : I.b_nlev;
+  const int32_t *lev = fwd ? I.f_lev_h.data() : I.b_lev_h.data();
+  const int32_t G = fwd ? I.f_group : I.b_group;
+  const int32_t s2 = (int32_t)I.s2;
+  if (c->fact_prec == SLR_FP64)
+    launch_sweep<double, double>(fwd ? I.C2fd : I.C2bd, lev, nlev, s2, x, ldx, nrhs, I.one_wg, st, G);
+  else if (compute64)
+    launch_sweep<float, double>(fwd ? I.C2ff : I.C2bf, lev, nlev, s2, x, ldx, nrhs, I.one_wg, st, G);
+  else
+    launch_sweep<float, float>(fwd ? I.C2ff : I.C2bf, lev, nlev, s2, x, ldx, nrhs, I.one_wg, st, G);
+}
+
+// x <- Q2 x = sq x + U2 diag(qd) U2^T x over the inner interface, in place
+void q2(slr_ctx *c, double *x, int64_t ldx, int32_t nrhs, ApplyWS &w, hipStream_t st) {
+  const slr_ctx::Inner &I = c->ml;
+  launch_lowrank_rm<double>(I.U2rm, I.U2, I.s2, I.k2, I.qd, I.sq, x, ldx, x, ldx, nrhs, w.lr_part, I.nblk, w.cbuf,
+                            st);
+}
+
+// x <- K^T x (in place of L^{-1} x; x: s x nrhs):
+//   a1 = L1^{-1} x1,  x2 <- Q2 L2^{-1} (x2 - F^T L1^{-T} a1)
+// scr: s1 x nrhs scratch (leading dimension lds).
+int c_lower(slr_ctx *c, double *x, int64_t ldx, int32_t nrhs, bool compute64, double *scr, int64_t lds, ApplyWS &w,
+            hipStream_t st) {
+  const slr_ctx::Inner &I = c->ml;
+  BArgs a;
+  a.f = x; a.ldf = ldx; a.a_f = 1.0;
+  a.u = x; a.ldu = ldx;
+  a.nrhs = nrhs;
+  int rc = c1solve(c, a, 1, compute64, st);
+  if (rc) return rc;
+  a.u = scr; a.ldu = lds;
+  if ((rc = c1solve(c, a, 2, compute64, st))) return rc;
+  launch_spmv_axpby(I.s2, I.ft_rp, I.ft_ci, I.ft_v, scr, lds, x + I.s1, ldx, nrhs, 1.0, -1.0, st);
+  c2sweep(c, true, x + I.s1, ldx, nrhs, compute64, st);
+  q2(c, x + I.s1, ldx, nrhs, w, st);
+  return SLR_OK;
+}
+
+// x <- K x (in place of L^{-T} x):
+//   x2 <- L2^{-T} Q2 x2,  x1 <- L1^{-T} (x1 - L1^{-1} F x2)
+int c_upper(slr_ctx *c, double *x, int64_t ldx, int32_t nrhs, bool compute64, double *scr, int64_t lds, ApplyWS &w,
+            hipStream_t st) {
+  const slr_ctx::Inner &I = c->ml;
+  q2(c, x + I.s1, ldx, nrhs, w, st);
+  c2sweep(c, false, x + I.s1, ldx, nrhs, compute64, st);
+  BArgs a;
+  a.y = x + I.s1; a.ldy = ldx; a.b_y = 1.0;
+  a.u = scr; a.ldu = lds;
+  a.nrhs = nrhs;
+  int rc = c1solve(c, a, 1, compute64, st);
+  if (rc) return rc;
+  launch_axpby(I.s1, nrhs, -1.0, scr, lds, 1.0, x, ldx, st);
+  BArgs b;
+  b.f = x; b.ldf = ldx; b.a_f = 1.0;
+  b.u = x; b.ldu = ldx;
+  b.nrhs = nrhs;
+  return c1solve(c, b, 2, compute64, st);
+}
+
 void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wout, int64_t ldo, int32_t nrhs,
              hipStream_t st) {
   const int k = c->k;
@@ -529,6 +656,8 @@ void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wou
 //   (3) y' = rho W + U_k D U_k^T W                 (rank-k block)
 //   (4) y = L^{-T} y'                              (interface backward sweep)
 //   (5) u = B^{-1}(f - E y)                        (B kernel, prologue)
+// With the recursive interface solver K^T and K take the place of L^{-1}
+// and L^{-T} in (2) and (4).
 int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, int64_t ldz, int32_t nrhs,
              hipStream_t st) {
   if (nrhs <= 0) return SLR_OK;
@@ -542,7 +671,11 @@ int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, in
     a.gout = w.W; a.ldgo = s; a.d_t = -1.0;
     a.nrhs = nrhs;
     if ((rc = bsolve(c, a, false, st))) return rc;
-    if (c->c_two_level) {
+    if (c->ml.on) {
+      if ((rc = c_lower(c, w.W, s, nrhs, false, w.W2, s, w, st))) return rc;
+      lowrank(c, w, w.W, s, z + m, ldz, nrhs, st);
+      if ((rc = c_upper(c, z + m, ldz, nrhs, false, w.W2, s, w, st))) return rc;
+    } else if (c->c_two_level) {
       csweep2(c, true, w.W, s, w.W2, s, nrhs, false, st);
       lowrank(c, w, w.W2, s, w.W, s, nrhs, st);
       csweep2(c, false, w.W, s, z + m, ldz, nrhs, false, st);
@@ -573,6 +706,18 @@ int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipSt
             const double *dv = nullptr, double *dpart = nullptr, int32_t *ndp = nullptr, bool t_ready = false) {
   if (ndp) *ndp = 0;
   const int64_t s = c->s;
+  if (c->ml.on) {
+    // H = K^T E^T B^{-1} E K (t2: scratch of the interface solves)
+    launch_axpby(s, 1, 1.0, v, s, 0.0, t, s, st);
+    int rc = c_upper(c, t, s, 1, true, t2, s, c->ws, st);
+    if (rc) return rc;
+    BArgs a;
+    a.y = t; a.ldy = s; a.b_y = 1.0;
+    a.gout = w; a.ldgo = s; a.d_t = 1.0;
+    a.nrhs = 1;
+    if ((rc = bsolve(c, a, true, st))) return rc;
+    return c_lower(c, w, s, 1, true, t2, s, c->ws, st);
+  }
   if (c->c_two_level) {
     if (!t_ready) csweep2(c, false, v, s, t, s, 1, true, st);
   } else {
@@ -855,6 +1000,128 @@ int lanczos_build(slr_ctx *c, int32_t kw, int32_t k0, const double *v0_host, hip
   return finish_lowrank(c, st);
 }
 
+// The recursive interface solver's inner low-rank part (Sec. 5.2 with
+// Sec. 5.1 one level down): Lanczos with full reorthogonalisation (two
+// classical Gram-Schmidt passes every step) on
+//   H2 = L2^{-1} F^T C1^{-1} F L2^{-T}
+// from the start vector's entries on the inner interface, the k2 largest
+// Ritz pairs, theta2 = lambda_{k2+1}, and the square root Q2 of
+// G2 = rho2 I + U2 D2 U2^T (eq. skt): sq = rho2^{1/2}, qd_i =
+// (1 - lambda_i)^{-1/2} - sq.  G2 must be positive definite.
+int lanczos_inner(slr_ctx *c, const double *v0_host, hipStream_t st) {
+  slr_ctx::Inner &I = c->ml;
+  const int64_t s1 = I.s1, s2 = I.s2;
+  const int32_t kw = I.k2;
+  I.theta2 = 0.0;
+  I.sq = 1.0;
+  I.steps = 0;
+  if (kw == 0) {
+    I.qd = c->pool.upload(std::vector<double>(1, 0.0));
+    return I.qd ? SLR_OK : fail(SLR_ERR_OOM, "inner scales");
+  }
+  int32_t steps = c->opts.lanczos_steps2 > 0 ? c->opts.lanczos_steps2 : 5 * kw;
+  steps = (int32_t)std::min<int64_t>(steps, std::max<int64_t>(s2, 1));
+  if (steps > 1024) return fail(SLR_ERR_ARG, "at most 1024 inner Lanczos steps");
+  Arena tmp(c->lz);
+  double *V = tmp.alloc<double>((size_t)s2 * steps);
+  double *Wl = tmp.alloc<double>(s2);
+  double *T = tmp.alloc<double>(s2);
+  double *Tu = tmp.alloc<double>(s1);
+  double *h = tmp.alloc<double>(2048);
+  double *sc = tmp.alloc<double>(4);
+  double *al = tmp.alloc<double>(steps);
+  double *be = tmp.alloc<double>(steps);
+  double *part = tmp.alloc<double>((size_t)RED_NBLK * (steps + 1));
+  double *part2 = tmp.alloc<double>((size_t)(s2 + 255) / 256 + 1);
+  if (!V || !Wl || !T || !Tu || !h || !sc || !al || !be || !part || !part2) {
+    tmp.release();
+    return fail(SLR_ERR_OOM, "inner Lanczos basis");
+  }
+  auto bail = [&](int code) {
+    tmp.release();
+    return code;
+  };
+  HIPCHK(hipMemsetAsync(sc, 0, 4 * sizeof(double), st));
+  std::vector<double> v0(s2);
+  for (int64_t q = 0; q < s2; ++q) v0[q] = v0_host[c->perm_h[c->m + s1 + q]];
+  double nv = 0.0;
+  for (double x : v0) nv += x * x;
+  nv = std::sqrt(nv);
+  if (!(nv > 0.0)) return bail(fail(SLR_ERR_ARG, "Lanczos start vector is zero on the inner interface"));
+  for (double &x : v0) x /= nv;
+  HIPCHK(hipMemcpyAsync(V, v0.data(), sizeof(double) * s2, hipMemcpyHostToDevice, st));
+  int rc = SLR_OK;
+  for (int32_t j = 0; j < steps; ++j) {
+    double *vj = V + (int64_t)j * s2;
+    // w = H2 v_j: T = L2^{-T} v_j, Tu = C1^{-1} F T, w = L2^{-1} F^T Tu
+    launch_axpby(s2, 1, 1.0, vj, s2, 0.0, T, s2, st);
+    c2sweep(c, false, T, s2, 1, true, st);
+    BArgs a;
+    a.y = T; a.ldy = s2; a.b_y = 1.0;
+    a.u = Tu; a.ldu = s1;
+    a.nrhs = 1;
+    if ((rc = c1solve(c, a, 3, true, st))) return bail(rc);
+    launch_spmv_axpby(s2, I.ft_rp, I.ft_ci, I.ft_v, Tu, s1, Wl, s2, 1, 0.0, 1.0, st);
+    c2sweep(c, true, Wl, s2, 1, true, st);
+    int32_t rb = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int32_t rbh = launch_multidot_partial(s2, j + 1, V, s2, Wl, part, RED_NBLK, st);
+      rb = launch_gemv_sub_fold(s2, j + 1, V, s2, part, rbh, Wl, pass == 0 ? h : nullptr, pass == 1 ? part2 : nullptr,
+                                st);
+    }
+    launch_lanczos_next(s2, j, Wl, j + 1 < steps ? vj + s2 : nullptr, sc, al, be, part2, rb, h + j, st);
+  }
+  std::vector<double> ah(steps), bh(steps);
+  HIPCHK(hipMemcpyAsync(ah.data(), al, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(bh.data(), be, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double tnorm = 0.0, bprev = 0.0;
+  int32_t mm = 0;
+  for (int32_t j = 0; j < steps; ++j) {
+    if (!std::isfinite(ah[j]) || !std::isfinite(bh[j]))
+      return bail(fail(SLR_ERR_BREAKDOWN, "non-finite inner Lanczos coefficients"));
+    mm = j + 1;
+    tnorm = std::max(tnorm, std::fabs(ah[j]) + bh[j] + bprev);
+    bprev = bh[j];
+    if (bh[j] <= 1e-14 * tnorm) break;
+  }
+  if (mm < kw + 1) return bail(fail(SLR_ERR_LANCZOS_SHORT, "inner Lanczos produced fewer Ritz pairs than needed"));
+  double *Z = tmp.alloc<double>((size_t)6 * mm * kw);
+  double *ev = tmp.alloc<double>(mm);
+  double *Y = tmp.alloc<double>((size_t)mm * kw);
+  int *info = tmp.alloc<int>(1);
+  if (!Z || !ev || !Y || !info) return bail(fail(SLR_ERR_OOM, "inner eigensolve"));
+  launch_tridiag_eig(mm, al, be, Z, ev, Y, kw, info, st);
+  I.U2 = c->pool.alloc<double>((size_t)s2 * kw);
+  if (!I.U2) return bail(fail(SLR_ERR_OOM, "U2"));
+  launch_ritz<double>(s2, mm, kw, V, s2, Y, I.U2, I.U2, st);
+  int info_h = 0;
+  std::vector<double> ritz(mm, 0.0);
+  HIPCHK(hipMemcpyAsync(&info_h, info, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ritz.data(), ev, sizeof(double) * mm, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  tmp.release();
+  if (info_h) return fail(SLR_ERR_BREAKDOWN, "inner tridiagonal eigensolve did not converge");
+  I.ritz_h = ritz;
+  I.lam_h.assign(ritz.begin(), ritz.begin() + kw);
+  I.theta2 = ritz[kw];
+  I.steps = mm;
+  if (!(I.theta2 < 1.0)) return fail(SLR_ERR_C_NOT_SPD, "inner correction not positive definite (theta2 >= 1)");
+  for (double l : I.lam_h)
+    if (!(l < 1.0)) return fail(SLR_ERR_C_NOT_SPD, "inner correction not positive definite (a Ritz value >= 1)");
+  I.sq = std::sqrt(1.0 / (1.0 - I.theta2));
+  std::vector<double> q(kw);
+  for (int32_t i = 0; i < kw; ++i) q[i] = std::sqrt(1.0 / (1.0 - I.lam_h[i])) - I.sq;
+  I.qd = c->pool.upload(q);
+  int32_t ldk;
+  const int64_t ng = lr_rm_groups<double>(s2, kw, ldk);
+  I.nblk = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(256, ng / 128));
+  I.U2rm = c->pool.alloc<double>((size_t)ng * 64 * 2);
+  if (!I.qd || !I.U2rm) return fail(SLR_ERR_OOM, "U2");
+  launch_lr_to_rm<double>(I.U2, s2, kw, I.U2rm, st);
+  return SLR_OK;
+}
+
 // Fixed-width sweeps: levels wider than 64 * rec_passes(K) rows are cut into
 // consecutive sub-levels of at most that many rows (the rows of a level are
 // independent, so the schedule stays valid and the arithmetic unchanged).
@@ -991,25 +1258,33 @@ void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::
   }
 }
 
+// Sizes of a packed block set that the B kernel's LDS plan needs.
+struct BSizes {
+  int32_t max_m = 0, max_lev = 0, max_level_bytes = 0;
+  int64_t data_bytes = 0;
+};
+
+// Pack and upload a set of diagonal blocks (factor sweeps, E and E^T rows)
+// for the B kernel.
 template <typename TS>
-void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArrays<TS> &Cf, SweepArrays<TS> &Cb,
-                   bool &ok, RfMaps *rm) {
-  std::vector<BlockDesc> desc(H.p);
+bool pack_blocks(DevPool &P, const std::vector<Block> &blocks, BlockArrays<TS> &B, BSizes &sz, RfMaps *rm) {
+  const int32_t nbk = (int32_t)blocks.size();
+  std::vector<BlockDesc> desc(nbk);
   std::vector<int32_t> lev, lvb;
   std::vector<uint8_t> data;
   std::vector<uint16_t> e_row, t_j;
   std::vector<int32_t> e_q, t_q;
   std::vector<double> e_val, t_val;
   int32_t max_m = 0, max_lev = 0, max_lb = 0, max_K = 0;
-  ok = true;
+  bool ok = true;
   // widest row of any sweep; rows are padded to it when it is small
   int32_t widest = 0;
-  for (const Block &b : H.blocks)
+  for (const Block &b : blocks)
     for (const Sweep *sw : {&b.fwd, &b.bwd})
       for (int32_t t = 0; t < sw->nrows; ++t) widest = std::max(widest, sw->rp[t + 1] - sw->rp[t]);
   const int32_t Kfix = (widest >= 1 && widest <= 4) ? widest : 0;
-  for (int32_t q = 0; q < H.p; ++q) {
-    const Block &b = H.blocks[q];
+  for (int32_t q = 0; q < nbk; ++q) {
+    const Block &b = blocks[q];
     BlockDesc &d = desc[q];
     d.m0 = b.m0;
     d.m = b.m;
@@ -1066,7 +1341,6 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
       }
   }
   if (data.empty()) data.resize(16, 0);
-  auto &P = c->pool;
   B.desc = P.upload(desc);
   B.lev = P.upload(lev);
   B.lvb = P.upload(lvb);
@@ -1080,45 +1354,86 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
   B.max_level_bytes = max_lb;
   B.max_K = max_K;
   B.pack_K = Kfix;
-  c->b_max_m = max_m;
-  c->b_max_lev = max_lev;
-  c->b_max_level_bytes = max_lb;
-  c->b_data_bytes = (int64_t)data.size();
-  auto upc = [&](const Sweep &sw, SweepArrays<TS> &S, RfSweepMaps *sm) {
-    if (sm) {
-      std::vector<int32_t> tof(sw.nrows, 0);
-      for (int32_t t = 0; t < sw.nrows; ++t) tof[sw.rows[t]] = t;
-      for (int32_t t = 0; t < sw.nrows; ++t) {
-        sm->sc.push_back(rf_scale(sw, t, (int64_t)sizeof(TS) * t, 0));
-        for (int32_t e = sw.rp[t]; e < sw.rp[t + 1]; ++e) {
-          sm->w.push_back(rf_weight(sw, t, e, (int64_t)sizeof(TS) * e, 0));
-          if (sw.nlev <= 2)
-            sm->w2.push_back(RfMap{(int64_t)sizeof(TS) * e, sw.w_e[e], sw.sc_e[t], sw.sc_e[tof[sw.ci[e]]], RF_W2});
-        }
+  sz.max_m = max_m;
+  sz.max_lev = max_lev;
+  sz.max_level_bytes = max_lb;
+  sz.data_bytes = (int64_t)data.size();
+  return ok && B.desc && B.lev && B.lvb && B.data && B.e_row && B.e_q && B.e_val && B.t_q && B.t_j && B.t_val;
+}
+
+// Upload one interface sweep (level-sorted rows, CSR weights, scales and,
+// for schedules of at most two levels, the pre-multiplied weights w2).
+template <typename TS>
+bool upload_sweep(DevPool &P, const Sweep &sw, SweepArrays<TS> &S, RfSweepMaps *sm) {
+  if (sm) {
+    std::vector<int32_t> tof(sw.nrows, 0);
+    for (int32_t t = 0; t < sw.nrows; ++t) tof[sw.rows[t]] = t;
+    for (int32_t t = 0; t < sw.nrows; ++t) {
+      sm->sc.push_back(rf_scale(sw, t, (int64_t)sizeof(TS) * t, 0));
+      for (int32_t e = sw.rp[t]; e < sw.rp[t + 1]; ++e) {
+        sm->w.push_back(rf_weight(sw, t, e, (int64_t)sizeof(TS) * e, 0));
+        if (sw.nlev <= 2)
+          sm->w2.push_back(RfMap{(int64_t)sizeof(TS) * e, sw.w_e[e], sw.sc_e[t], sw.sc_e[tof[sw.ci[e]]], RF_W2});
       }
     }
-    std::vector<int32_t> lv = sw.levptr;
-    if (lv.empty()) lv.push_back(0);
-    S.lev = P.upload(lv);
-    S.rows = P.upload(sw.rows);
-    S.rp = P.upload(sw.rp.empty() ? std::vector<int32_t>{0} : sw.rp);
-    S.ci = P.upload(sw.ci);
-    S.w = P.upload(conv<TS>(sw.w));
-    S.sc = P.upload(conv<TS>(sw.sc));
-    bool okw2 = true;
-    if (sw.nlev <= 2) {
-      // weights times the (stored) scale of the dependency row, rounded to TS
-      std::vector<double> scr(sw.nrows, 0.0);
-      for (int32_t t = 0; t < sw.nrows; ++t) scr[sw.rows[t]] = (double)(TS)sw.sc[t];
-      std::vector<double> w2(sw.w.size());
-      for (size_t e = 0; e < sw.w.size(); ++e) w2[e] = (double)(TS)sw.w[e] * scr[sw.ci[e]];
-      S.w2 = P.upload(conv<TS>(w2));
-      okw2 = S.w2 != nullptr;
-    }
-    return S.lev && S.rows && S.rp && S.ci && S.w && S.sc && okw2;
-  };
-  ok = ok && B.desc && B.lev && B.lvb && B.data && B.e_row && B.e_q && B.e_val && B.t_q && B.t_j && B.t_val;
-  ok = ok && upc(H.cfwd, Cf, rm ? &rm->cf : nullptr) && upc(H.cbwd, Cb, rm ? &rm->cb : nullptr);
+  }
+  std::vector<int32_t> lv = sw.levptr;
+  if (lv.empty()) lv.push_back(0);
+  S.lev = P.upload(lv);
+  S.rows = P.upload(sw.rows);
+  S.rp = P.upload(sw.rp.empty() ? std::vector<int32_t>{0} : sw.rp);
+  S.ci = P.upload(sw.ci);
+  S.w = P.upload(conv<TS>(sw.w));
+  S.sc = P.upload(conv<TS>(sw.sc));
+  bool okw2 = true;
+  if (sw.nlev <= 2) {
+    // weights times the (stored) scale of the dependency row, rounded to TS
+    std::vector<double> scr(sw.nrows, 0.0);
+    for (int32_t t = 0; t < sw.nrows; ++t) scr[sw.rows[t]] = (double)(TS)sw.sc[t];
+    std::vector<double> w2(sw.w.size());
+    for (size_t e = 0; e < sw.w.size(); ++e) w2[e] = (double)(TS)sw.w[e] * scr[sw.ci[e]];
+    S.w2 = P.upload(conv<TS>(w2));
+    okw2 = S.w2 != nullptr;
+  }
+  return S.lev && S.rows && S.rp && S.ci && S.w && S.sc && okw2;
+}
+
+template <typename TS>
+void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArrays<TS> &Cf, SweepArrays<TS> &Cb,
+                   bool &ok, RfMaps *rm) {
+  BSizes sz;
+  ok = pack_blocks<TS>(c->pool, H.blocks, B, sz, rm);
+  c->b_max_m = sz.max_m;
+  c->b_max_lev = sz.max_lev;
+  c->b_max_level_bytes = sz.max_level_bytes;
+  c->b_data_bytes = sz.data_bytes;
+  if (H.s1 > 0) return;   // the recursive interface solver has no single factor of C
+  ok = ok && upload_sweep<TS>(c->pool, H.cfwd, Cf, rm ? &rm->cf : nullptr) &&
+       upload_sweep<TS>(c->pool, H.cbwd, Cb, rm ? &rm->cb : nullptr);
+}
+
+// Lanes per row of an interface sweep launched one level at a time: by the
+// mean row length (entries per row < 8: one lane per row).
+int32_t sweep_group(const Sweep &sw) {
+  const double mean = sw.nrows > 0 ? (double)sw.ci.size() / sw.nrows : 0.0;
+  return mean < 8.0 ? 1 : (mean < 24.0 ? 4 : (mean < 64.0 ? 8 : 16));
+}
+
+// Upload the recursive interface solver's C1 blocks, C2 sweeps and F^T.
+template <typename TS>
+bool upload_inner(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArrays<TS> &Cf, SweepArrays<TS> &Cb) {
+  slr_ctx::Inner &I = c->ml;
+  BSizes sz;
+  bool ok = pack_blocks<TS>(c->pool, H.c1blocks, B, sz, nullptr);
+  I.max_m = sz.max_m;
+  I.max_lev = sz.max_lev;
+  I.max_level_bytes = sz.max_level_bytes;
+  I.data_bytes = sz.data_bytes;
+  ok = ok && upload_sweep<TS>(c->pool, H.c2fwd, Cf, nullptr) && upload_sweep<TS>(c->pool, H.c2bwd, Cb, nullptr);
+  I.ft_rp = c->pool.upload(H.ft_rp);
+  I.ft_ci = c->pool.upload(H.ft_ci.empty() ? std::vector<int32_t>{0} : H.ft_ci);
+  I.ft_v = c->pool.upload(H.ft_v.empty() ? std::vector<double>{0.0} : H.ft_v);
+  return ok && I.ft_rp && I.ft_ci && I.ft_v;
 }
 
 int perm_ws(slr_ctx *c, int32_t nrhs) {
@@ -1465,6 +1780,10 @@ void slr_default_opts(slr_opts *o) {
   o->reorth = SLR_REORTH_PARTIAL;
   o->refactor = 0;
   o->droptol = 1e-3;
+  o->b_order = SLR_BORDER_NATURAL;
+  o->c_levels = 1;
+  o->k2 = 0;
+  o->lanczos_steps2 = 0;
 }
 
 void slr_default_solve_opts(slr_solve_opts *o) {
@@ -1518,6 +1837,13 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   if (o->c_fact != SLR_FACT_CHOL && o->c_fact != SLR_FACT_IC0 && o->c_fact != SLR_FACT_ICT)
     return fail(SLR_ERR_ARG, "c_fact");
   if (!(o->droptol >= 0.0)) return fail(SLR_ERR_ARG, "droptol must be >= 0");
+  if (o->c_levels != 1 && o->c_levels != 2) return fail(SLR_ERR_ARG, "c_levels must be 1 or 2");
+  if (o->c_levels == 2) {
+    if (o->c_order != SLR_CORDER_HID) return fail(SLR_ERR_ARG, "c_levels 2 needs the HID order of C");
+    if (o->refactor) return fail(SLR_ERR_ARG, "refactor is not available with c_levels 2");
+    if (o->k2 < 0 || o->k2 > 64) return fail(SLR_ERR_ARG, "k2 must be in [0, 64]");
+    if (o->lanczos_steps2 < 0) return fail(SLR_ERR_ARG, "lanczos_steps2 must be >= 0");
+  }
   if (A->rowptr[A->n] != A->nnz) return fail(SLR_ERR_ARG, "rowptr[n] != nnz");
   hipStream_t st = S(hip_stream);
   const double t0 = now_s();
@@ -1529,6 +1855,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   prm.fact_prec = o->fact_prec;
   prm.droptol = o->droptol;
   prm.b_order = o->b_order;
+  prm.c_levels = o->c_levels;
   prm.plan = o->refactor != 0;
   if (o->refactor && !((o->b_fact == SLR_FACT_IC0 || o->b_fact == SLR_FACT_ILDLT0) && o->c_fact == SLR_FACT_IC0))
     return fail(SLR_ERR_ARG, "refactor needs zero-fill factors (IC0 / ILDLT0 for B, IC0 for C)");
@@ -1575,6 +1902,35 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   }
   if (!ok) return destroy_fail(fail(SLR_ERR_OOM, "factor upload (or a subdomain above 65535 rows)"));
   if (rm && !rf_upload(c, H, *rm, A)) return destroy_fail(fail(SLR_ERR_OOM, "refactorisation plan"));
+  if (H.s1 > 0) {
+    slr_ctx::Inner &I = c->ml;
+    I.on = true;
+    I.s1 = H.s1;
+    I.s2 = H.s - H.s1;
+    I.nb = (int32_t)H.c1blocks.size();
+    for (const Block &b : H.c1blocks)
+      if (b.m > 65535) return destroy_fail(fail(SLR_ERR_ARG, "a connector above 65535 rows"));
+    const bool ok2 = c->fact_prec == SLR_FP64 ? upload_inner<double>(c, H, I.Bd, I.C2fd, I.C2bd)
+                                              : upload_inner<float>(c, H, I.Bf, I.C2ff, I.C2bf);
+    if (!ok2) return destroy_fail(fail(SLR_ERR_OOM, "inner interface solver upload"));
+    I.f_lev_h = H.c2fwd.levptr;
+    I.b_lev_h = H.c2bwd.levptr;
+    I.f_nlev = H.c2fwd.nlev;
+    I.b_nlev = H.c2bwd.nlev;
+    I.one_wg = std::max(I.f_nlev, I.b_nlev) > 8;
+    if (std::max(I.f_nlev, I.b_nlev) > 2) {
+      I.f_group = sweep_group(H.c2fwd);
+      I.b_group = sweep_group(H.c2bwd);
+    }
+    if (I.one_wg && sizeof(int32_t) * (size_t)(std::max(I.f_nlev, I.b_nlev) + 1) > c->lds_limit)
+      return destroy_fail(fail(SLR_ERR_ARG, "inner level schedule too deep for one workgroup"));
+    I.nnz_L1 = H.nnz_LC1;
+    I.nnz_L2 = H.nnz_LC2;
+    I.k2 = o->k2 > 0 ? o->k2 : o->k;
+    int32_t R1 = 0, st1 = 0;
+    if (!b_lds_plan_sz(I.max_m, I.max_lev, I.max_level_bytes, I.data_bytes, 1, 8, R1, st1, c->lds_limit))
+      return destroy_fail(fail(SLR_ERR_ARG, "largest connector does not fit one workgroup's LDS"));
+  }
   c->cf_lev_h = H.cfwd.levptr;
   c->cb_lev_h = H.cbwd.levptr;
   c->cf_nlev = H.cfwd.nlev;
@@ -1582,18 +1938,12 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->cb_nnz = (int64_t)H.cbwd.ci.size();
   // shallow interface schedules (multicolour) run one launch per level
   c->c_one_wg = std::max(c->cf_nlev, c->cb_nlev) > 8;
-  {
-    // mean entries per row >= 8: one launch per level, lanes per row by length
-    auto group = [](const Sweep &sw) {
-      const double mean = sw.nrows > 0 ? (double)sw.ci.size() / sw.nrows : 0.0;
-      return mean < 8.0 ? 1 : (mean < 24.0 ? 4 : (mean < 64.0 ? 8 : 16));
-    };
-    if (!(std::max(c->cf_nlev, c->cb_nlev) <= 2)) {
-      c->cf_group = group(H.cfwd);
-      c->cb_group = group(H.cbwd);
-    }
+  // mean entries per row >= 8: one launch per level, lanes per row by length
+  if (!(std::max(c->cf_nlev, c->cb_nlev) <= 2)) {
+    c->cf_group = sweep_group(H.cfwd);
+    c->cb_group = sweep_group(H.cbwd);
   }
-  c->c_two_level = std::max(c->cf_nlev, c->cb_nlev) <= 2;
+  c->c_two_level = !c->ml.on && std::max(c->cf_nlev, c->cb_nlev) <= 2;
   if (c->c_one_wg && sizeof(int32_t) * (size_t)(std::max(c->cf_nlev, c->cb_nlev) + 1) > c->lds_limit)
     return destroy_fail(fail(SLR_ERR_ARG, "interface level schedule too deep for one workgroup"));
   {
@@ -1619,8 +1969,20 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   I.nnz_A = c->nnz_a;
   I.setup_host_s = now_s() - t0;
   I.tune_b_lds_div1 = I.tune_b_lds_divM = 1;
-  // low-rank part
+  // low-rank part(s)
   const double t1 = now_s();
+  std::vector<double> v0s;
+  const double *v0p = o->lanczos_v0 ? o->lanczos_v0 : seeded_v0(c->n, o->seed, v0s);
+  if (c->ml.on) {
+    if ((rc = lanczos_inner(c, v0p, st))) return destroy_fail(rc);
+    if ((rc = ws_ensure(c, c->ws, 1))) return destroy_fail(rc);
+    I.s1 = c->ml.s1;
+    I.k2 = c->ml.k2;
+    I.lanczos_steps2 = c->ml.steps;
+    I.c1_levels = c->ml.max_lev;
+    I.c2_levels = c->ml.f_nlev;
+    I.theta2 = c->ml.theta2;
+  }
   if (o->U_in && o->k_in > 0) {
     if (o->k_in > 64 || !o->lambda_in) return destroy_fail(fail(SLR_ERR_ARG, "imported low-rank part"));
     c->k = o->k_in;
@@ -1633,8 +1995,6 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
     if ((rc = finish_lowrank(c, st))) return destroy_fail(rc);
   } else if (o->k > 0 && c->s > 0) {
     c->k = o->k;
-    std::vector<double> v0;
-    const double *v0p = o->lanczos_v0 ? o->lanczos_v0 : seeded_v0(c->n, o->seed, v0);
     if ((rc = lanczos_build(c, o->k, 0, v0p, st))) return destroy_fail(rc);
   } else {
     c->k = 0;
@@ -1765,6 +2125,8 @@ int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void 
         return bsolve(c, a, false, st);
       }
       case 1:
+        if (c->ml.on)
+          return c_lower(c, c->ws.W, s, nrhs, false, c->ws.W2, s, c->ws, st);
         if (c->c_two_level)
           csweep2(c, true, c->ws.W, s, c->ws.W2, s, nrhs, false, st);
         else
@@ -1772,6 +2134,8 @@ int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void 
         return SLR_OK;
       case 2: lowrank(c, c->ws, c->ws.W2, s, c->ws.W, s, nrhs, st); return SLR_OK;
       case 3:
+        if (c->ml.on)
+          return c_upper(c, c->pz + m, n, nrhs, false, c->ws.W2, s, c->ws, st);
         if (c->c_two_level)
           csweep2(c, false, c->ws.W, s, c->pz + m, n, nrhs, false, st);
         else
@@ -1893,6 +2257,8 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
   prm.fact_prec = o->fact_prec;
   prm.droptol = o->droptol;
   prm.b_order = o->b_order;
+  prm.c_levels = o->c_levels;
+  if (o->c_levels != 1 && o->c_levels != 2) return fail(SLR_ERR_ARG, "c_levels must be 1 or 2");
   std::string err;
   int rc = host_setup(A->n, A->rowptr, A->col, A->val, part, p, prm, H, err);
   if (rc) return fail(rc, err);
@@ -1915,6 +2281,20 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
              (int64_t)(b.e_q.size() + b.t_j.size()) * (4 + fb);
   }
   bytes += (int64_t)(H.cfwd.ci.size() + H.cbwd.ci.size()) * (4 + fb) + H.s * 2 * (8 + fb);
+  if (H.s1 > 0) {
+    // the recursive interface solver: C1 blocks, C2 sweeps, F^T and U2
+    const int32_t k2 = o->k2 > 0 ? o->k2 : o->k;
+    info->s1 = H.s1;
+    info->k2 = k2;
+    info->c2_levels = H.c2fwd.nlev;
+    for (const auto &b : H.c1blocks) {
+      info->c1_levels = std::max({info->c1_levels, b.fwd.nlev, b.bwd.nlev});
+      bytes += (int64_t)(b.fwd.ci.size() + b.bwd.ci.size()) * (4 + fb) + (int64_t)b.m * 2 * (8 + fb) +
+               (int64_t)b.e_q.size() * (4 + fb);
+    }
+    bytes += (int64_t)(H.c2fwd.ci.size() + H.c2bwd.ci.size()) * (4 + fb) + (H.s - H.s1) * 2 * (8 + fb) +
+             (int64_t)H.ft_ci.size() * 12 + (H.s - H.s1) * (int64_t)k2 * 16;
+  }
   const int64_t ub = o->uk_prec == SLR_FP64 ? 8 : (o->uk_prec == SLR_FP32 ? 4 : 2);
   bytes += H.s * (int64_t)o->k * (8 + (o->uk_prec == SLR_FP64 ? 0 : ub));
   info->device_bytes = bytes;
@@ -1964,8 +2344,19 @@ int slr_export(const slr_ctx *c, int64_t *perm, double *ritz, double *lambda, do
   return SLR_OK;
 }
 
+int slr_export_inner(const slr_ctx *c, double *ritz2, double *lambda2, double *U2) {
+  if (!c) return fail(SLR_ERR_ARG, "null");
+  if (!c->ml.on) return fail(SLR_ERR_ARG, "the context has no recursive interface solver");
+  const slr_ctx::Inner &I = c->ml;
+  if (ritz2) std::copy(I.ritz_h.begin(), I.ritz_h.end(), ritz2);
+  if (lambda2) std::copy(I.lam_h.begin(), I.lam_h.end(), lambda2);
+  if (U2 && I.k2 > 0) HIPCHK(hipMemcpy(U2, I.U2, sizeof(double) * (size_t)I.s2 * I.k2, hipMemcpyDeviceToHost));
+  return SLR_OK;
+}
+
 int slr_export_setup(const slr_ctx *c, void *buf, size_t cap, size_t *bytes) {
   if (!c || !bytes) return fail(SLR_ERR_ARG, "null");
+  if (c->ml.on) return fail(SLR_ERR_ARG, "a context with the recursive interface solver cannot be serialised");
   std::vector<uint8_t> blob;
   const int rc = export_setup(c, blob);
   if (rc) return rc;
@@ -2032,8 +2423,8 @@ int slr_apply_dd_noalloc(slr_ctx *c, const double *r_dev, double *z_dev, int32_t
   if (rc) return rc;
   // the apply's scratch, carved as apply_dd's workspace would allocate it
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const int32_t nb = std::max(c->lr_nblk, c->lrm_nblk);
-  const int32_t kk = std::max(c->k, 1);
+  const int32_t nb = ws_chunks(c);
+  const int32_t kk = ws_rank(c);
   const size_t s1 = (size_t)std::max<int64_t>(c->s, 1);
   const size_t bW = al(sizeof(double) * s1 * nrhs);
   const size_t bP = al(sizeof(double) * (size_t)nb * nrhs * kk);

@@ -108,6 +108,7 @@ struct BArgs {
   int32_t nrhs = 1;
   int32_t R = 1;              // right-hand sides per workgroup
   int32_t stage_bytes = 0;    // LDS staging buffer for the packed sweeps
+  int32_t sweeps = 3;         // bit 0: forward sweep, bit 1: backward sweep
 };
 
 // Numeric refactorisation on the device: one stored coefficient (TS) at

@@ -360,6 +360,149 @@ std::vector<int32_t> min_degree_order(std::vector<std::vector<int32_t>> adj) {
   return order;
 }
 
+// The recursive interface solver's analysis (Sec. 5.2), from C in HID
+// order (lev: connector level of each interface position).  C1 = the nodes
+// of the lowest level; its connected pieces must each be a contiguous
+// range (so that C1 is block diagonal in this order).
+int inner_setup(HostSetup &H, const std::vector<int32_t> &lev, int kind, bool fp32, double droptol,
+                std::string &err) {
+  const int64_t m = H.m, s = H.s;
+  H.have_plan = false;
+  if (s == 0 || (int64_t)lev.size() != s) {
+    err = "the recursive interface solver needs an interface";
+    return SLR_ERR_ARG;
+  }
+  const int32_t lmin = *std::min_element(lev.begin(), lev.end());
+  int64_t s1 = 0;
+  while (s1 < s && lev[s1] == lmin) ++s1;
+  if (s1 == s) {
+    err = "the HID order has a single connector level: nothing to recurse on";
+    return SLR_ERR_ARG;
+  }
+  H.s1 = s1;
+  const int64_t s2 = s - s1;
+  // connected pieces of C1 (union-find), each a contiguous range
+  std::vector<int64_t> root(s1);
+  std::iota(root.begin(), root.end(), 0);
+  auto find = [&](int64_t x) {
+    while (root[x] != x) x = root[x] = root[root[x]];
+    return x;
+  };
+  for (int64_t t = 0; t < s1; ++t)
+    for (int64_t e = H.a_rp[m + t]; e < H.a_rp[m + t + 1]; ++e) {
+      const int64_t c = H.a_ci[e] - m;
+      if (c >= 0 && c < s1) {
+        const int64_t a = find(t), b = find(c);
+        if (a != b) root[std::max(a, b)] = std::min(a, b);
+      }
+    }
+  std::vector<int64_t> starts;
+  std::vector<char> seen(s1, 0);
+  for (int64_t t = 0; t < s1; ++t) {
+    const int64_t r = find(t);
+    if (t == 0 || find(t - 1) != r) {
+      if (seen[r]) {
+        err = "a connector of the leading HID level is not contiguous";
+        return SLR_ERR_ARG;
+      }
+      seen[r] = 1;
+      starts.push_back(t);
+    }
+  }
+  starts.push_back(s1);
+  const int32_t nb = (int32_t)starts.size() - 1;
+  H.c1blocks.assign(nb, Block());
+  std::vector<int> rcs(nb, 0);
+  auto build_block = [&](int32_t q) {
+    Block &b = H.c1blocks[q];
+    b.m0 = (int32_t)starts[q];
+    b.m = (int32_t)(starts[q + 1] - starts[q]);
+    std::vector<int32_t> rp(b.m + 1, 0), ci;
+    std::vector<double> v;
+    for (int32_t r = 0; r < b.m; ++r) {
+      const int64_t t = m + b.m0 + r;
+      bool has_e = false;
+      for (int64_t e = H.a_rp[t]; e < H.a_rp[t + 1]; ++e) {
+        const int64_t c = H.a_ci[e] - m;
+        if (c < 0) continue;
+        if (c < s1) {
+          if (c <= t - m) {
+            ci.push_back((int32_t)(c - b.m0));
+            v.push_back(H.a_v[e]);
+          }
+        } else {
+          if (!has_e) {
+            b.e_row.push_back(r);
+            b.e_ptr.push_back((int32_t)b.e_q.size());
+            has_e = true;
+          }
+          b.e_q.push_back((int32_t)(c - s1));
+          b.e_val.push_back(H.a_v[e]);
+        }
+      }
+      rp[r + 1] = (int32_t)ci.size();
+    }
+    b.e_ptr.push_back((int32_t)b.e_q.size());
+    b.t_ptr.assign(1, 0);
+    LowerFactor F;
+    rcs[q] = factor_block(kind, b.m, rp, ci, v, F, droptol);
+    if (rcs[q] != 0) return;
+    b.nnz_L = (int64_t)F.v.size();
+    build_sweeps(F, fp32, b.fwd, b.bwd);
+  };
+  {
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+      for (int32_t q = next++; q < nb; q = next++) build_block(q);
+    };
+    const int32_t nth = (int32_t)std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+    std::vector<std::thread> pool;
+    for (int32_t t = 1; t < std::min(nth, nb); ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
+  }
+  H.nnz_LC1 = 0;
+  for (int32_t q = 0; q < nb; ++q) {
+    if (rcs[q] != 0) {
+      err = "factorisation of the inner block C1 failed at interface row " +
+            std::to_string(H.c1blocks[q].m0 + (-1 - rcs[q]));
+      return SLR_ERR_C_NOT_SPD;
+    }
+    H.nnz_LC1 += H.c1blocks[q].nnz_L;
+  }
+  // C2 = L2 L2^T and F^T (rows of C2, columns in C1)
+  std::vector<int32_t> rp(s2 + 1, 0), ci;
+  std::vector<double> v;
+  H.ft_rp.assign(1, 0);
+  H.ft_ci.clear();
+  H.ft_v.clear();
+  for (int64_t t = 0; t < s2; ++t) {
+    for (int64_t e = H.a_rp[m + s1 + t]; e < H.a_rp[m + s1 + t + 1]; ++e) {
+      const int64_t c = H.a_ci[e] - m;
+      if (c < 0) continue;
+      if (c < s1) {
+        H.ft_ci.push_back((int32_t)c);
+        H.ft_v.push_back(H.a_v[e]);
+      } else if (c - s1 <= t) {
+        ci.push_back((int32_t)(c - s1));
+        v.push_back(H.a_v[e]);
+      }
+    }
+    rp[t + 1] = (int32_t)ci.size();
+    H.ft_rp.push_back((int64_t)H.ft_ci.size());
+  }
+  LowerFactor F2;
+  const int rc = factor_block(kind, (int32_t)s2, rp, ci, v, F2, droptol);
+  if (rc != 0) {
+    err = "factorisation of the inner block C2 failed at interface row " + std::to_string(s1 + (-1 - rc));
+    return SLR_ERR_C_NOT_SPD;
+  }
+  H.nnz_LC2 = (int64_t)F2.v.size();
+  build_sweeps(F2, fp32, H.c2fwd, H.c2bwd);
+  H.nnz_LC = H.nnz_LC1 + H.nnz_LC2;
+  return SLR_OK;
+}
+
 }  // namespace
 
 int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
@@ -449,6 +592,11 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
   std::vector<int64_t> ypos(n, -1);
   for (int64_t t = 0; t < s; ++t) ypos[y[t]] = t;
   H.c_colors = 0;
+  std::vector<int32_t> hid_lev;   // connector level of every interface position (HID order)
+  if (prm.c_levels == 2 && prm.c_order != SLR_CORDER_HID) {
+    err = "the recursive interface solver needs the HID order of C";
+    return SLR_ERR_ARG;
+  }
   if (prm.c_order == SLR_CORDER_MULTICOLOR && s > 0) {
     // greedy colouring in interface order, then a stable sort by colour
     std::vector<int32_t> color(s, -1);
@@ -494,7 +642,11 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
       return y[a] < y[b];
     });
     std::vector<int64_t> y2(s);
-    for (int64_t t = 0; t < s; ++t) y2[t] = y[idx[t]];
+    hid_lev.resize(s);
+    for (int64_t t = 0; t < s; ++t) {
+      y2[t] = y[idx[t]];
+      hid_lev[t] = (int32_t)key[idx[t]].size();
+    }
     y.swap(y2);
   } else if (prm.c_order != SLR_CORDER_SUBDOMAIN) {
     err = "unknown c_order";
@@ -632,6 +784,8 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     }
   }
   for (auto &b : H.blocks) b.t_ptr.push_back((int32_t)b.t_j.size());
+  const int c_kind = prm.c_fact == SLR_FACT_CHOL || prm.c_fact == SLR_FACT_ICT ? prm.c_fact : SLR_FACT_IC0;
+  if (prm.c_levels == 2) return inner_setup(H, hid_lev, c_kind, fp32, prm.droptol, err);
   // C and its factor (Sec. 3.1: C = L L^T), in the interface order
   {
     std::vector<int32_t> rp(s + 1, 0), ci;
@@ -649,8 +803,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
       rp[t + 1] = (int32_t)ci.size();
     }
     LowerFactor F;
-    int kind = prm.c_fact == SLR_FACT_CHOL || prm.c_fact == SLR_FACT_ICT ? prm.c_fact : SLR_FACT_IC0;
-    int rc = factor_block(kind, (int32_t)s, rp, ci, v, F, prm.droptol);
+    int rc = factor_block(c_kind, (int32_t)s, rp, ci, v, F, prm.droptol);
     if (rc != 0) {
       err = "factorisation of C failed at interface row " + std::to_string(-1 - rc);
       return SLR_ERR_C_NOT_SPD;

@@ -82,6 +82,19 @@ struct HostSetup {
   // and SetupParams::plan is set)
   bool have_plan = false;
   RefactorPlan fb, fc;
+  // Recursive interface solver (SetupParams::c_levels == 2, Sec. 5.2): in
+  // HID order C = [C1 F; F^T C2] with C1 the s1 nodes of the lowest
+  // connector level.  c1blocks: the connected pieces of C1's graph (each a
+  // contiguous range; m0 / m local to C1), their factors' sweeps, and as E
+  // rows their couplings F to C2 (e_q: index in C2).  C2's factor sweeps
+  // in c2fwd / c2bwd; F^T as CSR over the C2 rows with C1 columns.
+  int64_t s1 = 0;
+  std::vector<Block> c1blocks;
+  Sweep c2fwd, c2bwd;
+  std::vector<int64_t> ft_rp;
+  std::vector<int32_t> ft_ci;
+  std::vector<double> ft_v;
+  int64_t nnz_LC1 = 0, nnz_LC2 = 0;
 };
 
 struct SetupParams {
@@ -89,6 +102,7 @@ struct SetupParams {
   int b_order = 0;         // SLR_BORDER_NATURAL | SLR_BORDER_MINDEG
   double droptol = 1e-3;   // threshold factors (ICT / ILDLT)
   bool plan = false;   // build the refactorisation plans
+  int c_levels = 1;    // 2: recursive interface solver (needs the HID order)
 };
 
 // A symmetric in pattern and value: every (i, j) has a matching (j, i).

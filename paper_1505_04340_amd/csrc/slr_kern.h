@@ -67,6 +67,9 @@ __device__ __forceinline__ __hip_bfloat16 round_store<__hip_bfloat16>(double x) 
   return r;
 }
 
+// y = a y + b M x for CSR M with int64 row pointers (a == 0: y only written)
+void launch_spmv_axpby(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+                       int64_t ldx, double *y, int64_t ldy, int32_t nrhs, double a, double b, hipStream_t st);
 void launch_axpby(int64_t n, int32_t nrhs, double a, const double *x, int64_t ldx, double b, double *y,
                   int64_t ldy, hipStream_t st);
 void launch_permute(int64_t n, const int64_t *idx, const double *src, int64_t lds, double *dst, int64_t ldd,

@@ -467,7 +467,8 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
 
 // One launch: for subdomain blockIdx.x and right-hand sides
 // [blockIdx.y * R, +Rg): prologue (f, E y) into LDS, forward and backward
-// sweeps in LDS, then u and the E^T epilogue.  KE > 0: every packed row has
+// sweeps in LDS (or only one of them, by a.sweeps), then u and the E^T
+// epilogue.  KE > 0: every packed row has
 // exactly KE entries (padding has w = 0) and the sweeps run one wave per
 // column; KE == 0: any width, whole-workgroup levels.
 template <typename TS, typename TC, int KE>
@@ -522,13 +523,15 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
       }
     }
   };
+  // the sweeps this launch runs (a.sweeps: bit 0 forward, bit 1 backward)
+  const int fn = (a.sweeps & 1) ? d.f_nlev : 0, bn = (a.sweeps & 2) ? d.b_nlev : 0;
   if constexpr (KE > 0) {
     // the upper half of the waves stages the first sweep chunk meanwhile
     if (tid >= nt / 2) {
-      const int sw0 = d.f_nlev > 0 ? 0 : 1;
-      if (sw0 == 0 || d.b_nlev > 0)
+      const int sw0 = fn > 0 ? 0 : 1;
+      if (sw0 == 0 || bn > 0)
         stage_first(B.data + (sw0 ? d.b_data : d.f_data), B.lvb + (sw0 ? d.b_lvb : d.f_lvb),
-                    sw0 ? d.b_nlev : d.f_nlev, (a.stage_bytes >> 1) & ~15, stage, stage + a.stage_bytes,
+                    sw0 ? bn : fn, (a.stage_bytes >> 1) & ~15, stage, stage + a.stage_bytes,
                     tid - nt / 2, nt - nt / 2);
     } else {
       prologue(tid, nt / 2);
@@ -553,11 +556,11 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
     __syncthreads();
   }
   if constexpr (KE > 0) {
-    sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, d.f_nlev, B.data + d.b_data, levb, lvbb, d.b_nlev,
-                                 xs, XS, Rg, stage, a.stage_bytes, true);
+    sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, fn, B.data + d.b_data, levb, lvbb, bn, xs, XS, Rg,
+                                 stage, a.stage_bytes, true);
   } else {
-    sweep_staged<TS, TC>(B.data + d.f_data, levf, lvbf, d.f_nlev, xs, XS, Rg, stage, a.stage_bytes);
-    sweep_staged<TS, TC>(B.data + d.b_data, levb, lvbb, d.b_nlev, xs, XS, Rg, stage, a.stage_bytes);
+    sweep_staged<TS, TC>(B.data + d.f_data, levf, lvbf, fn, xs, XS, Rg, stage, a.stage_bytes);
+    sweep_staged<TS, TC>(B.data + d.b_data, levb, lvbb, bn, xs, XS, Rg, stage, a.stage_bytes);
   }
   if (a.u) {
     for (int t = tid; t < m * Rg; t += nt) {
@@ -1332,6 +1335,42 @@ void launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *
   else
     hipLaunchKernelGGL(k_spmv<SPMV_T>, dim3(gx, (nrhs + SPMV_T - 1) / SPMV_T), dim3(256), 0, st, n, rp, ci, v, x,
                        ldx, y, ldy, nrhs);
+}
+
+// y = a y + b M x for CSR M (int64 row pointers), SPMV_T columns per thread;
+// with a == 0 y is only written.  Every column sums its row in entry order.
+template <int T>
+__global__ void __launch_bounds__(256) k_spmv_axpby(int64_t n, const int64_t *rp, const int32_t *ci,
+                                                    const double *v, const double *x, int64_t ldx, double *y,
+                                                    int64_t ldy, int nrhs, double a, double b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c0 = blockIdx.y * T, nct = min(T, nrhs - c0);
+  double acc[T];
+  bool act[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    acc[t] = 0.0;
+    act[t] = t < nct;
+  }
+  csr_row_acc<T, T == 1 ? 8 : 2>(rp[i], rp[i + 1], ci, v, x, ldx, c0, act, acc);
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+    if (t < nct) {
+      double *yp = y + i + (int64_t)(c0 + t) * ldy;
+      *yp = (a != 0.0 ? a * *yp : 0.0) + b * acc[t];
+    }
+}
+
+void launch_spmv_axpby(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+                       int64_t ldx, double *y, int64_t ldy, int32_t nrhs, double a, double b, hipStream_t st) {
+  if (n == 0 || nrhs == 0) return;
+  const unsigned gx = (unsigned)((n + 255) / 256);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_spmv_axpby<1>, dim3(gx, 1), dim3(256), 0, st, n, rp, ci, v, x, ldx, y, ldy, nrhs, a, b);
+  else
+    hipLaunchKernelGGL(k_spmv_axpby<SPMV_T>, dim3(gx, (nrhs + SPMV_T - 1) / SPMV_T), dim3(256), 0, st, n, rp, ci,
+                       v, x, ldx, y, ldy, nrhs, a, b);
 }
 
 // ---------------------------------------------------------------------------

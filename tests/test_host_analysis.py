@@ -49,6 +49,49 @@ def test_analysis_matches_oracle(name, over, bf, cf, co, bo):
     assert info["device_bytes"] > 0
 
 
+@pytest.mark.parametrize("name,over,bf,cf,bo", [
+    ("lap3d_64", {"N": 16, "boxes": 2}, "ic0", "ic0", "natural"),
+    ("lap3d_64", {"N": 18, "boxes": 3}, "chol", "chol", "natural"),
+    ("shifted3d_128", {"N": 24, "boxes": 3, "neg": 10}, "ildlt", "ict", "mindeg"),
+    ("diffusion2d_1024", {"N": 96, "boxes": 4}, "ic0", "ict", "natural"),
+])
+def test_recursive_interface_analysis_matches_oracle(name, over, bf, cf, bo):
+    """The recursive interface solver's split of C (Sec. 5.2): the nodes of
+    the lowest HID level, and the fill of the two inner factors, exactly as
+    the oracle's."""
+    import paper_1505_04340_amd as P
+    pr = si.make_config(name, **over)
+    info, perm = P.analyze(pr.csr, pr.part, pr.nparts, k=4, b_fact=bf, c_fact=cf, c_order="hid", b_order=bo,
+                           c_levels=2)
+    Ps = O.setup(pr.csr, pr.part, pr.nparts, 0, b_fact=bf, c_fact=cf, c_order="hid", b_order=bo, c_levels=2,
+                 lowrank2=(np.zeros((0, 0)), np.zeros(0), 0.0))
+    assert (perm == Ps.perm).all()
+    ML = Ps.FC
+    assert info["s1"] == ML.s1 and info["s"] == ML.s1 + ML.s2
+    if cf != "chol":
+        assert info["nnz_LC"] == ML.inner.FB.v.size + ML.inner.FC.v.size
+    assert info["c1_levels"] > 0 and info["c2_levels"] > 0 and info["k2"] == 4
+
+
+def test_recursive_interface_errors():
+    """c_levels 2 needs the HID order; an interface of one connector level
+    (two subdomains) leaves nothing to recurse on; the oracle agrees."""
+    import paper_1505_04340_amd as P
+    pr = si.make_config("lap3d_64", N=16, boxes=2)
+    with pytest.raises(P.SLRError) as e:
+        P.analyze(pr.csr, pr.part, pr.nparts, c_order="multicolor", c_levels=2)
+    assert e.value.code == P.SLR_ERR_ARG
+    with pytest.raises(O.OracleError):
+        O.setup(pr.csr, pr.part, pr.nparts, 0, c_order="multicolor", c_levels=2)
+    pr2 = si.make_config("lap2d_64", N=12)
+    part2 = (np.arange(144) % 12 >= 6).astype(np.int32)
+    with pytest.raises(P.SLRError) as e:
+        P.analyze(pr2.csr, part2, 2, c_order="hid", c_levels=2)
+    assert e.value.code == P.SLR_ERR_ARG
+    with pytest.raises(O.OracleError):
+        O.setup(pr2.csr, part2, 2, 0, c_order="hid", c_levels=2)
+
+
 def test_analysis_errors_are_reported():
     import paper_1505_04340_amd as P
     pr = si.make_config("lap2d_64", N=12)

@@ -720,6 +720,120 @@ def test_hid_order_makes_the_leading_block_of_C_block_diagonal(dim, N, q):
     assert len(starts) == ncomp
 
 
+# ------------------------------------------- recursive SLR on C (HID)
+
+def _ml_problem(dim, N, q, **kw):
+    csr = si.laplacian_3d(N) if dim == 3 else si.laplacian_2d(N)
+    part = si.box_partition_3d(N, q) if dim == 3 else si.box_partition_2d(N, q, q)
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(csr[3], csr[3]))
+    return A, part, q ** dim
+
+
+@pytest.mark.parametrize("dim,N,q,cf", [(3, 16, 2, "ic0"), (2, 40, 4, "ic0"), (3, 18, 3, "chol")])
+def test_multilevel_c_factored_form_is_the_inner_slr_preconditioner(dim, N, q, cf):
+    """Sec. 5.2: the recursive scheme applies SLR to C with C's leading HID
+    level as the block diagonal B.  K K^T (K^T, K: what the outer level uses
+    in place of L^{-1}, L^{-T}) must equal the eq. M preconditioner that
+    setup builds for the matrix C on its own, with the connectors of that
+    level as subdomains and every other interface node a separator node
+    (Sec. 2.1, edge-based form) -- including its own Lanczos run from the
+    same start vector; and K^T must be the transpose of K."""
+    from scipy.sparse import csgraph
+    A, part, p = _ml_problem(dim, N, q)
+    P = O.setup(A, part, p, k=6, c_order="hid", c_levels=2, k2=4, c_fact=cf, b_fact=cf)
+    ML = P.FC
+    s1 = ML.s1
+    assert 0 < s1 < P.s and ML.inner.k == 4
+    nc, lab = csgraph.connected_components(P.C[:s1, :s1], directed=False)
+    part2 = np.concatenate([lab, -np.ones(P.s - s1, dtype=np.int64)])
+    v0 = O.splitmix64_uniform(A.shape[0], 7)
+    P2 = O.setup(P.C, part2, nc, k=4, c_fact=cf, b_fact=cf, reorth="full",
+                 v0=np.concatenate([np.zeros(s1), v0[P.perm[P.m + s1:]]]))
+    assert (P2.perm == np.arange(P.s)).all()
+    assert np.allclose(P2.lam, ML.inner.lam, rtol=0, atol=1e-13) and abs(P2.theta - ML.inner.theta) < 1e-13
+    rng = np.random.default_rng(3)
+    x, y = rng.standard_normal(P.s), rng.standard_normal(P.s)
+    ref = P2.apply(x)
+    assert np.abs(ML.upper(ML.lower(x)) - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(x @ ML.lower(y) - ML.upper(x) @ y) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y) * 10
+
+
+def test_multilevel_exact_levels_make_M_equal_A():
+    """With exact factors at both levels and every inner eigenpair, the inner
+    SLR reproduces C (K^T C K = I); with every outer eigenpair as well,
+    M = A (the P1 identity through the recursion)."""
+    A, part, p = _ml_problem(2, 21, 3)
+    P0 = O.setup(A, part, p, k=0, c_order="hid", c_levels=2, c_fact="chol", b_fact="chol",
+                 lowrank2=(np.zeros((0, 0)), np.zeros(0), 0.0))
+    s2 = P0.FC.s2
+    inner = P0.FC.inner
+    H2 = np.column_stack([inner.G(e) for e in np.eye(s2)])
+    lam2, V2 = np.linalg.eigh(0.5 * (H2 + H2.T))
+    lam2, V2 = lam2[::-1], V2[:, ::-1]
+    assert lam2.max() < 1.0
+    P1 = O.setup(A, part, p, k=0, c_order="hid", c_levels=2, c_fact="chol", b_fact="chol",
+                 lowrank2=(V2, lam2, 0.0))
+    ML = P1.FC
+    K = np.column_stack([ML.upper(e) for e in np.eye(P1.s)])
+    assert np.abs(K.T @ P1.C.toarray() @ K - np.eye(P1.s)).max() < 1e-10
+    H = np.column_stack([P1.G(e) for e in np.eye(P1.s)])
+    lam, U = np.linalg.eigh(0.5 * (H + H.T))
+    lam, U = lam[::-1], U[:, ::-1]
+    P = O.setup(A, part, p, k=0, c_order="hid", c_levels=2, c_fact="chol", b_fact="chol",
+                lowrank2=(V2, lam2, 0.0), lowrank=(U, lam, 0.0))
+    x = np.random.default_rng(5).uniform(-1, 1, A.shape[0])
+    assert np.abs(P.apply(A @ x) - x).max() < 1e-10
+    res = O.solve(P, A @ x, "pcg")
+    assert res.iters == 1 and res.true_relres < 1e-11
+
+
+def test_multilevel_planted_mistakes_fail_the_pins(monkeypatch):
+    """The inner correction used as G2 instead of its square root, the
+    F^T C1^{-1} coupling dropped from K^T, or L1^{-1} and L1^{-T} exchanged:
+    each breaks the identity with the inner SLR preconditioner."""
+    from scipy.sparse import csgraph
+    A, part, p = _ml_problem(3, 16, 2)
+    P = O.setup(A, part, p, k=4, c_order="hid", c_levels=2, k2=4)
+    ML = P.FC
+    s1 = ML.s1
+    nc, lab = csgraph.connected_components(P.C[:s1, :s1], directed=False)
+    part2 = np.concatenate([lab, -np.ones(P.s - s1, dtype=np.int64)])
+    v0 = O.splitmix64_uniform(A.shape[0], 7)
+    P2 = O.setup(P.C, part2, nc, k=4, reorth="full", v0=np.concatenate([np.zeros(s1), v0[P.perm[P.m + s1:]]]))
+    x = np.random.default_rng(4).standard_normal(P.s)
+    ref = P2.apply(x)
+
+    def err():
+        return np.abs(ML.upper(ML.lower(x)) - ref).max() / np.abs(ref).max()
+
+    assert err() < 1e-12
+    good_q = O.MultilevelC._q
+
+    def q_without_root(self, v):
+        # G2 itself: rho2 v + U2 D2 U2^T v
+        d2 = (self.qd + self.sq) ** 2 - self.sq ** 2
+        return self.sq ** 2 * v + self.inner.U @ (d2 * (self.inner.U.T @ v))
+    monkeypatch.setattr(O.MultilevelC, "_q", q_without_root)
+    assert err() > 1e-6
+    monkeypatch.setattr(O.MultilevelC, "_q", good_q)
+    good_lower = O.MultilevelC.lower
+
+    def lower_no_coupling(self, v):
+        a1 = self.inner.FB.lower(v[:self.s1])
+        return np.concatenate([a1, self._q(self.inner.FC.lower(v[self.s1:]))])
+    monkeypatch.setattr(O.MultilevelC, "lower", lower_no_coupling)
+    assert err() > 1e-6
+    monkeypatch.setattr(O.MultilevelC, "lower", good_lower)
+    FB = ML.inner.FB
+    lo, up = FB.lower, FB.upper
+    monkeypatch.setattr(FB, "lower", up)
+    monkeypatch.setattr(FB, "upper", lo)
+    assert err() > 1e-6
+    monkeypatch.setattr(FB, "lower", lo)
+    monkeypatch.setattr(FB, "upper", up)
+    assert err() < 1e-12
+
+
 # --------------------------------------------------------------- Krylov
 
 def test_krylov_iteration_counts_on_known_spectra():
