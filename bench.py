@@ -63,7 +63,16 @@ def bsolve_bytes(info, nrhs, bf):
 
 def apply_bytes(info, nrhs, bf, bu, k):
     """Algorithmic bytes of one whole apply: four B sweeps, two interface
-    sweeps, E and E^T once each, U_k read twice, vectors once each."""
+    sweeps, E and E^T once each, U_k read twice, vectors once each.  With
+    the recursive interface solver the two interface sweeps become K^T and
+    K: four half solves over C1's blocks, two C2 sweeps, F and F^T once
+    each, U2 read four times (FP64) and the inner vectors."""
+    if info.get("s1", 0) > 0:
+        s1, s2, k2 = info["s1"], info["s"] - info["s1"], info["k2"]
+        return ((4 * info["nnz_LB"] + 4 * info["nnz_LC1"] + 2 * info["nnz_LC2"] + 2 * info["nnz_E"]
+                 + 2 * info["nnz_F"]) * (bf + 4)
+                + 2 * info["s"] * k * bu + 4 * s2 * k2 * 8
+                + nrhs * (2 * info["n"] * 8 + 2 * info["m"] * 8 + 4 * info["s"] * 8 + 11 * s1 * 8 + 12 * s2 * 8))
     return ((4 * info["nnz_LB"] + 2 * info["nnz_LC"] + 2 * info["nnz_E"]) * (bf + 4)
             + 2 * info["s"] * k * bu
             + nrhs * (2 * info["n"] * 8 + 2 * info["m"] * 8 + 8 * info["s"] * 8))
@@ -193,33 +202,59 @@ def multi_rhs_apply(P, torch, nrhs=32, reps=10):
     return out
 
 
-def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=False):
+def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=False, recursive=False,
+                  solve=False):
     """Only set up one workload and time its apply (for profiler runs).
     threshold: ILDLT / ICT local solvers with drop tolerance 1e-4, B_i in
     minimum degree order and C in HID order (the form in which the shifted
     128^3 workload converges) instead of the zero-fill ones in multicolour
-    order."""
+    order.  recursive (with threshold): the recursive SLR on C (inner rank
+    16) in place of C's ICT factor.  solve: one FGMRES(40) solve of the
+    workload's right-hand side afterwards (iterations, seconds, true
+    relative residual)."""
     import slr_inputs as si
     pr = si.make_config(name)
     fp, up = {"fp64": ("fp64", "fp64"), "fp32": ("fp32", "fp32"), "mixed": ("fp32", "bf16")}[form]
     if threshold:
         kw = dict(b_fact="ildlt" if pr.b_fact.startswith("ildlt") else "ict", c_fact="ict", droptol=1e-4,
                   c_order="hid", b_order="mindeg")
+        if recursive:
+            kw.update(c_levels=2, k2=16)
     else:
         kw = dict(b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor")
+    t0 = time.perf_counter()
     G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, fact_prec=fp, uk_prec=up,
               v0=pr.v0(), **kw)
     torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"{name} set up in {setup_s:.1f} s")
     tune = G.autotune(nrhs) if autotune else None
     info = G.query()
     ms = G.time_kernel("apply", nrhs, reps)
     stages = {s: round(G.time_kernel(s, nrhs, reps), 5) for s in ("bsolve1", "cfwd", "lowrank", "cbwd", "bsolve2")}
+    sol = None
+    if solve:
+        xs, b = pr.rhs()
+        bd = torch.tensor(b[:, :1], dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, sinfo = G.solve(bd[:, 0], "fgmres", rtol=1e-8, maxit=1000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        rr = float(np.linalg.norm(b[:, 0] - pr.scipy() @ x.cpu().numpy()) / np.linalg.norm(b[:, 0]))
+        sol = {"method": "fgmres(40)", "iters": sinfo[0]["iters"], "status": sinfo[0]["status"],
+               "solve_s": round(t2 - t1, 3), "true_relres": rr}
     bf = 8 if fp == "fp64" else 4
     bu = {"fp64": 8, "fp32": 4, "bf16": 2}[up]
     ab = apply_bytes(info, nrhs, bf, bu, info["k"])
     bb = bsolve_bytes(info, nrhs, bf)
+    rec = {k_: info[k_] for k_ in ("s1", "k2", "theta2", "c1_levels", "c2_levels", "nnz_LC1", "nnz_LC2", "nnz_F")} \
+        if recursive else None
     print(json.dumps({"workload": name, "form": form, "nrhs": nrhs, "threshold_hid": threshold,
-                      "apply_ms": round(ms, 5),
+                      "recursive_c": rec, "setup_s": round(setup_s, 2),
+                      "setup_host_s": round(info["setup_host_s"], 2),
+                      "setup_lanczos_s": round(info["setup_lanczos_s"], 3), "solve": sol,
+                      "c_levels": info["c_levels"], "apply_ms": round(ms, 5),
                       "apply_algorithmic_bytes": int(ab), "apply_GBs": round(ab / (ms * 1e-3) / 1e9, 1),
                       "bsolve1_algorithmic_bytes": int(bb),
                       "bsolve1_GBs": round(bb / (stages["bsolve1"] * 1e-3) / 1e9, 1),
@@ -438,6 +473,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="with --apply-profile: slr_autotune first")
     ap.add_argument("--threshold", action="store_true",
                     help="with --apply-profile: ILDLT/ICT (1e-4), minimum degree B_i, HID C")
+    ap.add_argument("--recursive", action="store_true",
+                    help="with --threshold: the recursive SLR on C (inner rank 16)")
+    ap.add_argument("--solve", action="store_true", help="with --apply-profile: one FGMRES(40) solve as well")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -447,7 +485,7 @@ def main():
         import paper_1505_04340_amd as P
         torch.cuda.set_device(0)
         apply_profile(P, torch, args.apply_profile, args.apply_form, args.nrhs, args.reps, args.autotune,
-                      args.threshold)
+                      args.threshold, args.recursive, args.solve)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -215,6 +215,7 @@ typedef struct {
   int32_t k2, lanczos_steps2;
   int32_t c1_levels, c2_levels;
   double theta2;
+  int64_t nnz_LC1, nnz_LC2, nnz_F;  /* entries of L1, L2 and of F         */
 } slr_info;
 
 typedef struct slr_ctx slr_ctx;

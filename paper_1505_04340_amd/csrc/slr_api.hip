@@ -1982,6 +1982,9 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
     I.c1_levels = c->ml.max_lev;
     I.c2_levels = c->ml.f_nlev;
     I.theta2 = c->ml.theta2;
+    I.nnz_LC1 = H.nnz_LC1;
+    I.nnz_LC2 = H.nnz_LC2;
+    I.nnz_F = (int64_t)H.ft_ci.size();
   }
   if (o->U_in && o->k_in > 0) {
     if (o->k_in > 64 || !o->lambda_in) return destroy_fail(fail(SLR_ERR_ARG, "imported low-rank part"));
@@ -2287,6 +2290,9 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
     info->s1 = H.s1;
     info->k2 = k2;
     info->c2_levels = H.c2fwd.nlev;
+    info->nnz_LC1 = H.nnz_LC1;
+    info->nnz_LC2 = H.nnz_LC2;
+    info->nnz_F = (int64_t)H.ft_ci.size();
     for (const auto &b : H.c1blocks) {
       info->c1_levels = std::max({info->c1_levels, b.fwd.nlev, b.bwd.nlev});
       bytes += (int64_t)(b.fwd.ci.size() + b.bwd.ci.size()) * (4 + fb) + (int64_t)b.m * 2 * (8 + fb) +

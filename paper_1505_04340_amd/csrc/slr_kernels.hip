@@ -148,20 +148,17 @@ __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
 // at xs[r * XS + row], XS = the largest subdomain size; xs[XS * R] is a
 // dummy slot that absorbs stores past the end.
 //
-// One level of a packed sweep with any row width K, solved by the whole
-// workgroup (rows x columns spread over the threads), read from LDS.  The
-// subtraction order is the same in every variant.
-// Rows of an ELL level with long rows (width K > 8): G lanes per row and
-// column, lane g summing the entries g, g + G, ..., the partial sums added
-// by a butterfly, then x_row = sc x_row - sum.  Whole groups iterate
-// together (blockDim.x is a multiple of G).
+// One level of an ELL-packed sweep (any row width K) for one column, solved
+// by one wave.  Rows of width K <= 8: one lane per row, entries subtracted
+// in order.  Longer rows: G lanes per row (G = 4, 16, 64 for K <= 32, 128,
+// beyond), lane g summing the entries g, g + G, ..., the partial sums added
+// by a butterfly inside the group, then x_row = sc x_row - sum.  A group is
+// active or idle as a whole, so its butterfly never mixes in an idle lane.
 template <typename TS, typename TC, int G>
-__device__ __forceinline__ void level_group(const uint16_t *rows, const TS *sc, const uint16_t *ci, const TS *w,
-                                            int L, int K, TC *xs, int XS, int Rg) {
-  const int g = threadIdx.x % G;
-  for (int t = threadIdx.x / G; t < L * Rg; t += blockDim.x / G) {
-    const int j = t / Rg, r = t - j * Rg;
-    TC *xc = xs + r * XS;
+__device__ __forceinline__ void ell_rows_group(const uint16_t *rows, const TS *sc, const uint16_t *ci, const TS *w,
+                                               int L, int K, TC *xc, int lane) {
+  const int g = lane % G;
+  for (int j = lane / G; j < L; j += 64 / G) {
     TC part = 0;
     for (int e = g; e < K; e += G) part += cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
 #pragma unroll
@@ -174,7 +171,7 @@ __device__ __forceinline__ void level_group(const uint16_t *rows, const TS *sc, 
 }
 
 template <typename TS, typename TC>
-__device__ __forceinline__ void level_from_lds(const uint8_t *seg, int L, TC *xs, int XS, int Rg) {
+__device__ __forceinline__ void ell_level_wave(const uint8_t *seg, int L, TC *xc, int lane) {
   const int K = *reinterpret_cast<const int32_t *>(seg);
   const uint8_t *base = seg + kEllHeaderBytes;
   const uint16_t *rows = reinterpret_cast<const uint16_t *>(base);
@@ -184,21 +181,28 @@ __device__ __forceinline__ void level_from_lds(const uint8_t *seg, int L, TC *xs
   const uint16_t *ci = reinterpret_cast<const uint16_t *>(base + o_ci);
   const TS *w = reinterpret_cast<const TS *>(base + o_ci + pad8(2 * K * L));
   if (K <= 8) {
-    for (int t = threadIdx.x; t < L * Rg; t += blockDim.x) {
-      const int j = t / Rg, r = t - j * Rg;
-      TC *xc = xs + r * XS;
+    for (int j = lane; j < L; j += 64) {
       const int row = rows[j];
       TC acc = cvt<TC>(sc[j]) * xc[row];
       for (int e = 0; e < K; ++e) acc -= cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
       xc[row] = acc;
     }
   } else if (K <= 32) {
-    level_group<TS, TC, 4>(rows, sc, ci, w, L, K, xs, XS, Rg);
+    ell_rows_group<TS, TC, 4>(rows, sc, ci, w, L, K, xc, lane);
   } else if (K <= 128) {
-    level_group<TS, TC, 16>(rows, sc, ci, w, L, K, xs, XS, Rg);
+    ell_rows_group<TS, TC, 16>(rows, sc, ci, w, L, K, xc, lane);
   } else {
-    level_group<TS, TC, 64>(rows, sc, ci, w, L, K, xs, XS, Rg);
+    ell_rows_group<TS, TC, 64>(rows, sc, ci, w, L, K, xc, lane);
   }
+}
+
+// Levels [l0, l1) of an ELL-packed sweep staged at sbase, for one column, by
+// one wave with no barrier between levels: a wave's LDS accesses take
+// effect in program order, and a level reads only rows of earlier levels.
+template <typename TS, typename TC>
+__device__ __forceinline__ void solve_staged_ell(const uint8_t *sbase, const int32_t *lev, const int32_t *lvb, int l0,
+                                                 int l1, TC *xc, int lane) {
+  for (int l = l0; l < l1; ++l) ell_level_wave<TS, TC>(sbase + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], xc, lane);
 }
 
 // Copy nv 16-byte vectors into the LDS stage: vector i comes from src0[i]
@@ -241,25 +245,6 @@ __device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, cons
     stage_batch<8>(s0, n0, s1, nv, dst, dm, gt, gn);
   else
     stage_batch<12>(s0, n0, s1, nv, dst, dm, gt, gn);
-}
-
-// A whole sweep of any width: stage as many consecutive level segments as
-// fit, solve them level by level with the whole workgroup, repeat.
-template <typename TS, typename TC>
-__device__ void sweep_staged(const uint8_t *data, const int32_t *lev, const int32_t *lvb, int nlev,
-                             TC *xs, int XS, int Rg, uint8_t *stage, int stage_bytes) {
-  int l0 = 0;
-  while (l0 < nlev) {
-    int l1 = l0 + 1;
-    while (l1 < nlev && lvb[l1 + 1] - lvb[l0] <= stage_bytes) ++l1;
-    stage_copy(data + lvb[l0], lvb[l1] - lvb[l0], data, 0, stage, stage + stage_bytes, threadIdx.x, blockDim.x);
-    __syncthreads();
-    for (int l = l0; l < l1; ++l) {
-      level_from_lds<TS, TC>(stage + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], xs, XS, Rg);
-      __syncthreads();
-    }
-    l0 = l1;
-  }
 }
 
 // Fixed-width row records (see BlockDesc): KR int32 indices [row, columns,
@@ -396,9 +381,10 @@ __device__ __forceinline__ void stage_first(const uint8_t *data, const int32_t *
   stage_copy(data + b0, b1 - b0, data, 0, stage, dummy, gt, gn);
 }
 
-// Both fixed-width sweeps of one subdomain, one wave per right-hand side
-// column (wave w < Rg solves column w; its backward sweep follows its own
-// forward sweep, so the columns need no barrier between them).  The two
+// Both sweeps of one subdomain (fixed-width records for KE > 0, the ELL form
+// for KE == 0), one wave per right-hand side column (wave w < Rg solves
+// column w; its backward sweep follows its own forward sweep, so the
+// columns need no barrier between them).  The two
 // packed streams are cut into chunks of consecutive levels of one sweep
 // (at most 64 levels, fitting half the stage) and double-buffered: while the
 // solver waves run chunk c from one half, the other waves copy chunk c + 1
@@ -447,8 +433,12 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
     const int nl1 = more ? chunk_end(ns, nl0) : 0;
     uint8_t *cur = stage + b * half, *nxt = stage + (b ^ 1) * half;
     if (wv < Rg) {
-      for (int r = wv; r < Rg; r += nw)
-        solve_staged<TS, TC, KE>(cur, sw ? levb : levf, sw ? lvbb : lvbf, l0, l1, xs + r * XS, lane);
+      for (int r = wv; r < Rg; r += nw) {
+        if constexpr (KE > 0)
+          solve_staged<TS, TC, KE>(cur, sw ? levb : levf, sw ? lvbb : lvbf, l0, l1, xs + r * XS, lane);
+        else
+          solve_staged_ell<TS, TC>(cur, sw ? levb : levf, sw ? lvbb : lvbf, l0, l1, xs + r * XS, lane);
+      }
     } else if (more) {
       copy_chunk(ns, nl0, nl1, nxt, threadIdx.x - Rg * 64, blockDim.x - Rg * 64);
     }
@@ -468,9 +458,9 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
 // One launch: for subdomain blockIdx.x and right-hand sides
 // [blockIdx.y * R, +Rg): prologue (f, E y) into LDS, forward and backward
 // sweeps in LDS (or only one of them, by a.sweeps), then u and the E^T
-// epilogue.  KE > 0: every packed row has
-// exactly KE entries (padding has w = 0) and the sweeps run one wave per
-// column; KE == 0: any width, whole-workgroup levels.
+// epilogue.  KE > 0: every packed row has exactly KE entries (padding has
+// w = 0); KE == 0: the ELL form of any width.  Either way the sweeps run
+// one wave per column with double-buffered staging.
 template <typename TS, typename TC, int KE>
 __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -525,7 +515,7 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   };
   // the sweeps this launch runs (a.sweeps: bit 0 forward, bit 1 backward)
   const int fn = (a.sweeps & 1) ? d.f_nlev : 0, bn = (a.sweeps & 2) ? d.b_nlev : 0;
-  if constexpr (KE > 0) {
+  {
     // the upper half of the waves stages the first sweep chunk meanwhile
     if (tid >= nt / 2) {
       const int sw0 = fn > 0 ? 0 : 1;
@@ -536,8 +526,6 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
     } else {
       prologue(tid, nt / 2);
     }
-  } else {
-    prologue(tid, nt);
   }
   __syncthreads();
   if (a.b_y != 0.0 && d.e_n > 0) {
@@ -555,13 +543,8 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
     }
     __syncthreads();
   }
-  if constexpr (KE > 0) {
-    sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, fn, B.data + d.b_data, levb, lvbb, bn, xs, XS, Rg,
-                                 stage, a.stage_bytes, true);
-  } else {
-    sweep_staged<TS, TC>(B.data + d.f_data, levf, lvbf, fn, xs, XS, Rg, stage, a.stage_bytes);
-    sweep_staged<TS, TC>(B.data + d.b_data, levb, lvbb, bn, xs, XS, Rg, stage, a.stage_bytes);
-  }
+  sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, fn, B.data + d.b_data, levb, lvbb, bn, xs, XS, Rg,
+                               stage, a.stage_bytes, true);
   if (a.u) {
     for (int t = tid; t < m * Rg; t += nt) {
       const int r = t / m, row = t - r * m;
