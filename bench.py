@@ -209,7 +209,7 @@ def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=Fa
     minimum degree order and C in HID order (the form in which the shifted
     128^3 workload converges) instead of the zero-fill ones in multicolour
     order.  recursive (with threshold): the recursive SLR on C (inner rank
-    16) in place of C's ICT factor.  solve: one FGMRES(40) solve of the
+    64) in place of C's ICT factor.  solve: one FGMRES(40) solve of the
     workload's right-hand side afterwards (iterations, seconds, true
     relative residual)."""
     import slr_inputs as si
@@ -219,7 +219,7 @@ def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=Fa
         kw = dict(b_fact="ildlt" if pr.b_fact.startswith("ildlt") else "ict", c_fact="ict", droptol=1e-4,
                   c_order="hid", b_order="mindeg")
         if recursive:
-            kw.update(c_levels=2, k2=16)
+            kw.update(c_levels=2, k2=64)
     else:
         kw = dict(b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor")
     t0 = time.perf_counter()
@@ -238,7 +238,7 @@ def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=Fa
         bd = torch.tensor(b[:, :1], dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, sinfo = G.solve(bd[:, 0], "fgmres", rtol=1e-8, maxit=1000)
+        x, sinfo = G.solve(bd[:, 0], "fgmres", rtol=1e-8, maxit=3000)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         rr = float(np.linalg.norm(b[:, 0] - pr.scipy() @ x.cpu().numpy()) / np.linalg.norm(b[:, 0]))
@@ -474,7 +474,7 @@ def main():
     ap.add_argument("--threshold", action="store_true",
                     help="with --apply-profile: ILDLT/ICT (1e-4), minimum degree B_i, HID C")
     ap.add_argument("--recursive", action="store_true",
-                    help="with --threshold: the recursive SLR on C (inner rank 16)")
+                    help="with --threshold: the recursive SLR on C (inner rank 64)")
     ap.add_argument("--solve", action="store_true", help="with --apply-profile: one FGMRES(40) solve as well")
     args = ap.parse_args()
     if args.copy_calibration:

@@ -7,7 +7,8 @@ ordering, ICT C in HID order (Sec. 5.2), drop tolerance 1e-4 -- k = 64 from
 With --recursive it writes tests/golden/shifted128_fgmres_recursive.json
 instead: the same run with the recursive SLR on C of Sec. 5.2 (the
 leading HID level as the inner block diagonal, ICT at both levels, inner
-rank 16 from 80 Lanczos steps) in place of the ICT factor of C.
+rank 64 from 320 Lanczos steps) in place of the ICT factor of C, and at
+most 3000 iterations.
 
 Calls only the oracle and the input generators; about 25 minutes on one
 core.  Run from the repository root: python tests/golden/make_shifted128_fgmres.py
@@ -29,12 +30,13 @@ import slr_inputs as si  # noqa: E402
 def main(recursive: bool):
     pr = si.make_config("shifted3d_128")
     t0 = time.time()
-    rec = dict(c_levels=2, k2=16) if recursive else {}
+    rec = dict(c_levels=2, k2=64) if recursive else {}
+    maxit = 3000 if recursive else 1000
     P = O.setup(pr.csr, pr.part, pr.nparts, pr.k, pr.lanczos_steps, b_fact="ildlt", c_fact="ict", droptol=1e-4,
                 c_order="hid", b_order="mindeg", v0=pr.v0(), **rec)
     t1 = time.time()
     xs, b = pr.rhs()
-    r = O.solve(P, b[:, 0], "fgmres", rtol=1e-8, maxit=1000, restart=40)
+    r = O.solve(P, b[:, 0], "fgmres", rtol=1e-8, maxit=maxit, restart=40)
     t2 = time.time()
     out = {
         "workload": "shifted 3-D 7-point Laplacian 128^3, 20 negative eigenvalues, 8x8x8 boxes",
@@ -47,7 +49,8 @@ def main(recursive: bool):
     if recursive:
         inner = P.FC.inner
         out["method"] = out["method"].replace("ICT C (HID order)", "recursive SLR on C (HID order; ICT C1 and C2, "
-                                              "inner k=16 from 80 Lanczos steps)")
+                                              "inner k=64 from 320 Lanczos steps)").replace("maxit 1000",
+                                                                                            "maxit 3000")
         out.update({"s1": int(P.FC.s1), "k2": int(inner.k), "theta2": float(inner.theta),
                     "lambda2": [float(v) for v in inner.lam],
                     "nnz_LC": int(inner.FB.v.size + inner.FC.v.size)})
