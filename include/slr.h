@@ -227,14 +227,22 @@ typedef struct slr_batch slr_batch;
 void slr_default_opts(slr_opts *o);
 void slr_default_solve_opts(slr_solve_opts *o);
 
-/* slr_setup: build the preconditioner for A and partition `part`
- * (host, n labels in 0..p-1; vertex-based partitioning of Sec. 2.1).
- * Classification, DD ordering (eq. Global), the B_i and C factorisations
- * and level schedules run on the host; the factors are uploaded and the
- * Lanczos build of (U_k, Lambda_k, theta) on H (eq. H, Sec. 5.1) runs on
- * the device.  Errors: ARG, NOT_SYMMETRIC, PARTITION (labels out of range
- * or separator labels -1, which the device path does not take),
- * BREAKDOWN, C_NOT_SPD, RITZ_SINGULAR, LANCZOS_SHORT, OOM, HIP. */
+/* slr_setup: build the preconditioner for A and partition `part` (host, n
+ * labels in -1..p-1; Sec. 2.1).  A node labelled q >= 0 coupled to a node
+ * labelled r >= 0, r != q, is an interface node of q (vertex-based
+ * partitioning); nodes labelled -1 are separator nodes (edge-based
+ * partitioning: a vertex separator, all interface), and coupling to one
+ * does not make a node interface.  Both kinds may be mixed; interior nodes
+ * of two subdomains must not be coupled.  The interface is ordered by owner
+ * subdomain with the separator nodes last (eq. Global2).  With separator
+ * nodes E^T is applied as a CSR product after the B kernel (a separator row
+ * couples to several subdomains).  Classification, DD ordering (eq.
+ * Global), the B_i and C factorisations and level schedules run on the
+ * host; the factors are uploaded and the Lanczos build of (U_k, Lambda_k,
+ * theta) on H (eq. H, Sec. 5.1) runs on the device.  Errors: ARG (also
+ * refactor with separator labels), NOT_SYMMETRIC, PARTITION (labels out of
+ * range, coupled interiors), BREAKDOWN, C_NOT_SPD, RITZ_SINGULAR,
+ * LANCZOS_SHORT, OOM, HIP. */
 int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *o,
               void *hip_stream, slr_ctx **out);
 
@@ -393,7 +401,7 @@ int slr_export_inner(const slr_ctx *c, double *ritz2, double *lambda2, double *U
  * Current values are taken (after slr_refactor, the refactored ones).  The
  * layout is this library build's own (magic, length, records, FNV-1a
  * checksum), native byte order.  A context with the recursive interface
- * solver (c_levels 2) is SLR_ERR_ARG. */
+ * solver (c_levels 2) or with separator labels is SLR_ERR_ARG. */
 int slr_export_setup(const slr_ctx *c, void *buf, size_t cap, size_t *bytes);
 
 /* slr_import: a new context on the current device from slr_export_setup's

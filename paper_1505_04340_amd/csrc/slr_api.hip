@@ -226,6 +226,7 @@ struct ApplyWS {
   double *lr_part = nullptr;  // nblk x cap x k
   int32_t nblk = 0;            // rank-k partial chunks lr_part was sized for
   double *cbuf = nullptr;     // k x cap
+  double *Z = nullptr;        // m x cap interior solution (edge-based partitions only)
   unsigned int *counter = nullptr;
   DevPool pool;
 };
@@ -246,6 +247,12 @@ struct slr_ctx {
   int32_t *a_ci = nullptr;
   double *a_v = nullptr;
   int64_t nnz_a = 0;
+  // edge-based partitions (separator nodes): E^T as CSR over all interface
+  // rows, applied after the B kernel instead of in its epilogue
+  bool sep = false;
+  int64_t *et_rp = nullptr;
+  int32_t *et_ci = nullptr;
+  double *et_v = nullptr;
   // B blocks and interface sweeps (one of the two precisions is used)
   BlockArrays<double> Bd;
   BlockArrays<float> Bf;
@@ -437,15 +444,17 @@ int32_t ws_chunks(const slr_ctx *c) { return std::max({c->lr_nblk, c->lrm_nblk, 
 
 int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   const int32_t nb = ws_chunks(c), kk = ws_rank(c);
-  if (w.cap >= nrhs && w.W && w.k >= kk && w.nblk >= nb) return SLR_OK;
+  if (w.cap >= nrhs && w.W && w.k >= kk && w.nblk >= nb && (!c->sep || w.Z)) return SLR_OK;
   w.pool.release();
   int32_t cap = std::max<int32_t>(nrhs, 1);
   w.W = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
   w.W2 = w.pool.alloc<double>((size_t)std::max<int64_t>(c->s, 1) * cap);
   w.lr_part = w.pool.alloc<double>((size_t)nb * cap * kk);
   w.cbuf = w.pool.alloc<double>((size_t)cap * kk);
+  w.Z = c->sep ? w.pool.alloc<double>((size_t)std::max<int64_t>(c->m, 1) * cap) : nullptr;
   w.counter = w.pool.alloc<unsigned int>(16);
-  if (!w.W || !w.W2 || !w.lr_part || !w.cbuf || !w.counter) return fail(SLR_ERR_OOM, "apply workspace");
+  if (!w.W || !w.W2 || !w.lr_part || !w.cbuf || !w.counter || (c->sep && !w.Z))
+    return fail(SLR_ERR_OOM, "apply workspace");
   HIPCHK(hipMemset(w.counter, 0, 16 * sizeof(unsigned int)));
   w.cap = cap;
   w.k = kk;
@@ -650,6 +659,28 @@ void lowrank(slr_ctx *c, ApplyWS &w, const double *win, int64_t ldw, double *wou
   }
 }
 
+// First B solve of the apply: W = g - E^T B^{-1} f for nrhs columns of r
+// (ld ldr), into w.W (ld s).  Vertex-based partitions: the B kernel's
+// epilogue; with separator nodes the B kernel leaves z = B^{-1} f in w.Z and
+// W = g - E^T z follows as a CSR product over all interface rows.
+int bsolve_first(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, int32_t nrhs, hipStream_t st) {
+  const int64_t m = c->m, s = c->s;
+  BArgs a;
+  a.f = r; a.ldf = ldr; a.a_f = 1.0;
+  a.nrhs = nrhs;
+  if (!c->sep) {
+    a.g = r + m; a.ldg = ldr; a.c_g = 1.0;
+    a.gout = w.W; a.ldgo = s; a.d_t = -1.0;
+    return bsolve(c, a, false, st);
+  }
+  a.u = w.Z; a.ldu = m;
+  int rc = bsolve(c, a, false, st);
+  if (rc) return rc;
+  launch_axpby(s, nrhs, 1.0, r + m, ldr, 0.0, w.W, s, st);
+  launch_spmv_axpby(s, c->et_rp, c->et_ci, c->et_v, w.Z, m, w.W, s, nrhs, 1.0, -1.0, st);
+  return SLR_OK;
+}
+
 // z = M^{-1} r in the internal order, eq. M with S~^{-1} of eq. skt:
 //   (1) z_B = B^{-1} f ; W = g - E^T z_B          (B kernel, epilogue)
 //   (2) W <- L^{-1} W                              (interface forward sweep)
@@ -665,12 +696,7 @@ int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, in
   if (rc) return rc;
   const int64_t m = c->m, s = c->s;
   if (s > 0) {
-    BArgs a;
-    a.f = r; a.ldf = ldr; a.a_f = 1.0;
-    a.g = r + m; a.ldg = ldr; a.c_g = 1.0;
-    a.gout = w.W; a.ldgo = s; a.d_t = -1.0;
-    a.nrhs = nrhs;
-    if ((rc = bsolve(c, a, false, st))) return rc;
+    if ((rc = bsolve_first(c, w, r, ldr, nrhs, st))) return rc;
     if (c->ml.on) {
       if ((rc = c_lower(c, w.W, s, nrhs, false, w.W2, s, w, st))) return rc;
       lowrank(c, w, w.W, s, z + m, ldz, nrhs, st);
@@ -696,6 +722,24 @@ int apply_dd(slr_ctx *c, ApplyWS &w, const double *r, int64_t ldr, double *z, in
   return SLR_OK;
 }
 
+// out = E^T B^{-1} E t for one interface vector (FP64 arithmetic on the
+// stored factors); with separator nodes through c->ws.Z and the E^T CSR.
+int bsolve_et(slr_ctx *c, const double *t, double *out, hipStream_t st) {
+  const int64_t s = c->s;
+  BArgs a;
+  a.y = t; a.ldy = s; a.b_y = 1.0;
+  a.nrhs = 1;
+  if (!c->sep) {
+    a.gout = out; a.ldgo = s; a.d_t = 1.0;
+    return bsolve(c, a, true, st);
+  }
+  a.u = c->ws.Z; a.ldu = c->m;
+  int rc = bsolve(c, a, true, st);
+  if (rc) return rc;
+  launch_spmv_axpby(s, c->et_rp, c->et_ci, c->et_v, c->ws.Z, c->m, out, s, 1, 0.0, 1.0, st);
+  return SLR_OK;
+}
+
 // w = H v = L^{-1} E^T B^{-1} E L^{-T} v (eq. H), FP64 arithmetic on the
 // stored factors; t: s-vector scratch.
 // w = H v.  With dv and a two-level interface schedule, the last sweep also
@@ -711,11 +755,7 @@ int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipSt
     launch_axpby(s, 1, 1.0, v, s, 0.0, t, s, st);
     int rc = c_upper(c, t, s, 1, true, t2, s, c->ws, st);
     if (rc) return rc;
-    BArgs a;
-    a.y = t; a.ldy = s; a.b_y = 1.0;
-    a.gout = w; a.ldgo = s; a.d_t = 1.0;
-    a.nrhs = 1;
-    if ((rc = bsolve(c, a, true, st))) return rc;
+    if ((rc = bsolve_et(c, t, w, st))) return rc;
     return c_lower(c, w, s, 1, true, t2, s, c->ws, st);
   }
   if (c->c_two_level) {
@@ -724,11 +764,7 @@ int apply_H(slr_ctx *c, const double *v, double *w, double *t, double *t2, hipSt
     launch_axpby(s, 1, 1.0, v, s, 0.0, t, s, st);
     csweep(c, false, t, s, 1, true, st);
   }
-  BArgs a;
-  a.y = t; a.ldy = s; a.b_y = 1.0;
-  a.gout = c->c_two_level ? t2 : w; a.ldgo = s; a.d_t = 1.0;
-  a.nrhs = 1;
-  int rc = bsolve(c, a, true, st);
+  int rc = bsolve_et(c, t, c->c_two_level ? t2 : w, st);
   if (rc) return rc;
   if (c->c_two_level) {
     csweep2(c, true, t2, s, w, s, 1, true, st, dv, dpart);
@@ -1845,6 +1881,9 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
     if (o->lanczos_steps2 < 0) return fail(SLR_ERR_ARG, "lanczos_steps2 must be >= 0");
   }
   if (A->rowptr[A->n] != A->nnz) return fail(SLR_ERR_ARG, "rowptr[n] != nnz");
+  if (o->refactor)
+    for (int64_t i = 0; i < A->n; ++i)
+      if (part[i] == -1) return fail(SLR_ERR_ARG, "refactor is not available with separator labels");
   hipStream_t st = S(hip_stream);
   const double t0 = now_s();
   HostSetup H;
@@ -1891,6 +1930,13 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   c->a_v = c->pool.upload(H.a_v);
   c->nnz_a = (int64_t)H.a_ci.size();
   bool ok = c->perm && c->a_rp && c->a_ci && c->a_v;
+  if (H.has_sep) {
+    c->sep = true;
+    c->et_rp = c->pool.upload(H.et_rp);
+    c->et_ci = c->pool.upload(H.et_ci.empty() ? std::vector<int32_t>{0} : H.et_ci);
+    c->et_v = c->pool.upload(H.et_v.empty() ? std::vector<double>{0.0} : H.et_v);
+    ok = ok && c->et_rp && c->et_ci && c->et_v;
+  }
   RfMaps rmaps;
   RfMaps *rm = H.have_plan ? &rmaps : nullptr;
   if (c->fact_prec == SLR_FP64)
@@ -1973,6 +2019,7 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
   const double t1 = now_s();
   std::vector<double> v0s;
   const double *v0p = o->lanczos_v0 ? o->lanczos_v0 : seeded_v0(c->n, o->seed, v0s);
+  if ((rc = ws_ensure(c, c->ws, 1))) return destroy_fail(rc);
   if (c->ml.on) {
     if ((rc = lanczos_inner(c, v0p, st))) return destroy_fail(rc);
     if ((rc = ws_ensure(c, c->ws, 1))) return destroy_fail(rc);
@@ -2119,14 +2166,7 @@ int slr_time_kernel(slr_ctx *c, int32_t which, int32_t nrhs, int32_t reps, void 
   HIPCHK(hipEventCreate(&e1));
   auto one = [&]() -> int {
     switch (which) {
-      case 0: {
-        BArgs a;
-        a.f = c->pr; a.ldf = n; a.a_f = 1.0;
-        a.g = c->pr + m; a.ldg = n; a.c_g = 1.0;
-        a.gout = c->ws.W; a.ldgo = s; a.d_t = -1.0;
-        a.nrhs = nrhs;
-        return bsolve(c, a, false, st);
-      }
+      case 0: return bsolve_first(c, c->ws, c->pr, n, nrhs, st);
       case 1:
         if (c->ml.on)
           return c_lower(c, c->ws.W, s, nrhs, false, c->ws.W2, s, c->ws, st);
@@ -2363,6 +2403,7 @@ int slr_export_inner(const slr_ctx *c, double *ritz2, double *lambda2, double *U
 int slr_export_setup(const slr_ctx *c, void *buf, size_t cap, size_t *bytes) {
   if (!c || !bytes) return fail(SLR_ERR_ARG, "null");
   if (c->ml.on) return fail(SLR_ERR_ARG, "a context with the recursive interface solver cannot be serialised");
+  if (c->sep) return fail(SLR_ERR_ARG, "a context of an edge-based partition cannot be serialised");
   std::vector<uint8_t> blob;
   const int rc = export_setup(c, blob);
   if (rc) return rc;
@@ -2435,7 +2476,8 @@ int slr_apply_dd_noalloc(slr_ctx *c, const double *r_dev, double *z_dev, int32_t
   const size_t bW = al(sizeof(double) * s1 * nrhs);
   const size_t bP = al(sizeof(double) * (size_t)nb * nrhs * kk);
   const size_t bC = al(sizeof(double) * (size_t)kk * nrhs);
-  const size_t need = 2 * bW + bP + bC + 256;
+  const size_t bZ = c->sep ? al(sizeof(double) * (size_t)std::max<int64_t>(c->m, 1) * nrhs) : 0;
+  const size_t need = 2 * bW + bP + bC + bZ + 256;
   if (need > kNoAllocScratchBytes)
     return fail(SLR_ERR_ARG, "slr_apply_dd_noalloc needs " + std::to_string(need) + " bytes of scratch for " +
                                  std::to_string(nrhs) + " columns; the fixed scratch holds " +
@@ -2445,7 +2487,8 @@ int slr_apply_dd_noalloc(slr_ctx *c, const double *r_dev, double *z_dev, int32_t
   w.W2 = (double *)(base + bW);
   w.lr_part = (double *)(base + 2 * bW);
   w.cbuf = (double *)(base + 2 * bW + bP);
-  w.counter = (unsigned int *)(base + 2 * bW + bP + bC);   // unused by the apply's kernels
+  w.Z = c->sep ? (double *)(base + 2 * bW + bP + bC) : nullptr;
+  w.counter = (unsigned int *)(base + 2 * bW + bP + bC + bZ);   // unused by the apply's kernels
   w.cap = nrhs;
   w.k = kk;
   w.nblk = nb;

@@ -516,30 +516,41 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     err = "A is not symmetric (pattern and values must match)";
     return SLR_ERR_NOT_SYMMETRIC;
   }
+  H.has_sep = false;
   for (int64_t i = 0; i < n; ++i) {
-    if (part[i] == -1) {
-      err = "separator labels (-1, edge-based partitioning) are not taken by the device path";
-      return SLR_ERR_PARTITION;
-    }
-    if (part[i] < 0 || part[i] >= p) {
+    if (part[i] < -1 || part[i] >= p) {
       err = "partition label out of range";
       return SLR_ERR_PARTITION;
     }
+    if (part[i] == -1) H.has_sep = true;
   }
   H.n = n;
   H.p = p;
   // Sec. 2.1: local interface = coupled to a node of another subdomain
+  // (vertex-based); nodes labelled -1 are separator nodes (edge-based), and
+  // coupling to one does not make a node interface
   std::vector<char> iface(n, 0);
-  for (int64_t i = 0; i < n; ++i)
+  for (int64_t i = 0; i < n; ++i) {
+    if (part[i] < 0) {
+      iface[i] = 1;
+      continue;
+    }
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
-      if (part[col[e]] != part[i]) {
+      if (part[col[e]] >= 0 && part[col[e]] != part[i]) {
         iface[i] = 1;
         break;
       }
-  // eq. Global: interiors by subdomain, then interface by owner;
-  // ascending original index inside each group
+  }
+  // eq. Global: interiors by subdomain, then interface by owner, separator
+  // nodes last; ascending original index inside each group
   std::vector<std::vector<int64_t>> inner(p), ifc(p);
-  for (int64_t i = 0; i < n; ++i) (iface[i] ? ifc : inner)[part[i]].push_back(i);
+  std::vector<int64_t> sep;
+  for (int64_t i = 0; i < n; ++i) {
+    if (part[i] < 0)
+      sep.push_back(i);
+    else
+      (iface[i] ? ifc : inner)[part[i]].push_back(i);
+  }
   if (prm.b_order == SLR_BORDER_MINDEG) {
     // each interior in the minimum degree order of its B_i (the subdomains
     // are independent: one host thread per subdomain at a time)
@@ -586,6 +597,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
   H.m = (int64_t)H.perm.size();
   std::vector<int64_t> y;
   for (int32_t q = 0; q < p; ++q) y.insert(y.end(), ifc[q].begin(), ifc[q].end());
+  y.insert(y.end(), sep.begin(), sep.end());
   H.s = (int64_t)y.size();
   const int64_t s = H.s, m = H.m;
   // interface positions before any colouring
@@ -764,8 +776,23 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
       H.fb.lev.push_back((int32_t)H.fb.rows.size());
     }
   }
-  // E^T rows grouped by owner subdomain
-  for (int64_t t = 0; t < s; ++t) {
+  // E^T: with separator nodes one CSR over all interface rows (a separator
+  // row couples to the interiors of several subdomains); otherwise rows
+  // grouped by owner subdomain for the B kernel's epilogue
+  if (H.has_sep) {
+    H.et_rp.assign(1, 0);
+    H.et_ci.clear();
+    H.et_v.clear();
+    for (int64_t t = 0; t < s; ++t) {
+      for (int64_t e = H.a_rp[m + t]; e < H.a_rp[m + t + 1]; ++e)
+        if (H.a_ci[e] < m) {
+          H.et_ci.push_back(H.a_ci[e]);
+          H.et_v.push_back(H.a_v[e]);
+        }
+      H.et_rp.push_back((int64_t)H.et_ci.size());
+    }
+  }
+  for (int64_t t = 0; t < s && !H.has_sep; ++t) {
     int64_t i = H.perm[m + t];
     Block &b = H.blocks[part[i]];
     b.t_q.push_back((int32_t)t);
@@ -784,6 +811,7 @@ int host_setup(int64_t n, const int64_t *rowptr, const int32_t *col, const doubl
     }
   }
   for (auto &b : H.blocks) b.t_ptr.push_back((int32_t)b.t_j.size());
+  if (H.has_sep) H.have_plan = false;
   const int c_kind = prm.c_fact == SLR_FACT_CHOL || prm.c_fact == SLR_FACT_ICT ? prm.c_fact : SLR_FACT_IC0;
   if (prm.c_levels == 2) return inner_setup(H, hid_lev, c_kind, fp32, prm.droptol, err);
   // C and its factor (Sec. 3.1: C = L L^T), in the interface order

@@ -88,6 +88,12 @@ struct HostSetup {
   // contiguous range; m0 / m local to C1), their factors' sweeps, and as E
   // rows their couplings F to C2 (e_q: index in C2).  C2's factor sweeps
   // in c2fwd / c2bwd; F^T as CSR over the C2 rows with C1 columns.
+  // edge-based partitions (labels -1): E^T over all interface rows as CSR
+  // (columns: interior indices), used instead of the blocks' E^T rows
+  bool has_sep = false;
+  std::vector<int64_t> et_rp;
+  std::vector<int32_t> et_ci;
+  std::vector<double> et_v;
   int64_t s1 = 0;
   std::vector<Block> c1blocks;
   Sweep c2fwd, c2bwd;

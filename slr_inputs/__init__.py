@@ -162,6 +162,34 @@ def random_cuts_2d(N: int, px: int, py: int, seed: int) -> np.ndarray:
     return (ox[None, :] + px * oy[:, None]).astype(np.int32).ravel()
 
 
+def _separator_cuts(N: int, q: int) -> np.ndarray:
+    """Strip (0..q-1) of every coordinate 0..N-1, or -1 on the q-1 cut
+    coordinates between strips (spread evenly)."""
+    cut = [((k * (N + 1)) // q) - 1 for k in range(1, q)]
+    own = np.empty(N, dtype=np.int32)
+    strip = 0
+    for x in range(N):
+        if strip < q - 1 and x == cut[strip]:
+            own[x] = -1
+            strip += 1
+        else:
+            own[x] = strip
+    return own
+
+
+def separator_partition(N: int, q: int, dim: int) -> np.ndarray:
+    """Edge-based partition of an N^dim grid into q^dim boxes: nodes on the
+    cut lines (2-D) or planes (3-D) are separator nodes (label -1), the
+    others carry their box's label (x fastest)."""
+    o = _separator_cuts(N, q)
+    if dim == 2:
+        lab = np.where((o[None, :] < 0) | (o[:, None] < 0), -1, o[None, :] + q * o[:, None])
+    else:
+        lab = np.where((o[None, None, :] < 0) | (o[None, :, None] < 0) | (o[:, None, None] < 0), -1,
+                       o[None, None, :] + q * o[None, :, None] + q * q * o[:, None, None])
+    return lab.astype(np.int32).ravel()
+
+
 def separator_model(nx: int, ny: int):
     """Two-domain model of Sec. 3.2: an nx x (2 ny + 1) grid split by the
     middle grid line.  Returns (csr, part) with part = -1 on the separator

@@ -73,6 +73,35 @@ def test_recursive_interface_analysis_matches_oracle(name, over, bf, cf, bo):
     assert info["c1_levels"] > 0 and info["c2_levels"] > 0 and info["k2"] == 4
 
 
+@pytest.mark.parametrize("dim,N,q,bf,cf,co", [
+    (2, 33, 2, "chol", "chol", "subdomain"),
+    (2, 40, 4, "ic0", "ic0", "multicolor"),
+    (3, 17, 2, "ic0", "ic0", "subdomain"),
+    (3, 20, 3, "ict", "ict", "hid"),
+])
+def test_separator_partition_analysis_matches_oracle(dim, N, q, bf, cf, co):
+    """Edge-based partitions (Sec. 2.1: nodes labelled -1 form a vertex
+    separator, the shared interface): the same classification, ordering
+    (separator nodes last) and fill as the oracle's."""
+    import paper_1505_04340_amd as P
+    csr = si.laplacian_3d(N) if dim == 3 else si.laplacian_2d(N)
+    part = si.separator_partition(N, q, dim)
+    p = q ** dim
+    info, perm = P.analyze(csr, part, p, k=4, b_fact=bf, c_fact=cf, c_order=co)
+    Ps = O.setup(csr, part, p, 0, b_fact=bf, c_fact=cf, c_order=co)
+    assert (perm == Ps.perm).all()
+    assert info["m"] == Ps.m and info["s"] == Ps.s == int(np.sum(part < 0))
+    if bf != "chol":
+        assert info["nnz_LB"] == Ps.FB.v.size
+    if cf != "chol":
+        assert info["nnz_LC"] == Ps.FC.v.size
+    assert info["nnz_E"] == Ps.E.nnz
+    A, part2 = si.separator_model(6, 3)
+    info, perm = P.analyze(A, part2, 2, b_fact="chol", c_fact="chol")
+    Ps = O.setup(A, part2, 2, 0, b_fact="chol", c_fact="chol")
+    assert (perm == Ps.perm).all() and info["s"] == 6
+
+
 def test_recursive_interface_errors():
     """c_levels 2 needs the HID order; an interface of one connector level
     (two subdomains) leaves nothing to recurse on; the oracle agrees."""
@@ -100,9 +129,10 @@ def test_analysis_errors_are_reported():
     with pytest.raises(P.SLRError) as e:
         P.analyze(pr.csr, bad, 4)
     assert e.value.code == P.SLR_ERR_PARTITION
-    A, part = si.separator_model(6, 3)
+    bad2 = pr.part.copy()
+    bad2[5] = -2
     with pytest.raises(P.SLRError) as e:
-        P.analyze(A, part, 2)
+        P.analyze(pr.csr, bad2, 4)
     assert e.value.code == P.SLR_ERR_PARTITION
     indptr, indices, data, n = pr.csr
     d2 = data.copy()
