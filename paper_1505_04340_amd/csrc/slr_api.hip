@@ -1294,7 +1294,175 @@ void pack_sweep(const Sweep &sw, int32_t Kfix, std::vector<uint8_t> &data, std::
   }
 }
 
-// Sizes of a packed block set that the B kernel's LDS plan needs.
+// ELL-form sweep (any width) packed with its near-chains solved by
+// columns.  A run of at least kColRunMin consecutive levels of at most
+// kColRunRows rows each -- typically the long rows at the end of a minimum
+// degree or threshold factor, each waiting for the previous one -- is
+// packed as (1) ELL pieces holding the run's rows with their scale and the
+// entries to rows before the run (independent rows: those rows are final),
+// then (2) column segments: for each run row in order, the run rows after
+// it that use it, with their weights.  The kernel then finishes a run row
+// by a read of its value and updates the rows that use it, instead of one
+// reduction per level.  Other levels are cut into ELL pieces as
+// split_levels does.  Appends the segments' byte offsets to lvb and their
+// row counts (prefix sums, from 0) to lev; returns the segment count.
+constexpr int32_t kColRunRows = 8, kColRunMin = 8;
+
+int64_t csc_segment_bytes(int64_t ncol, int64_t nnz, int64_t ts) {
+  return pad16h(kEllHeaderBytes + pad8h(2 * ncol) + pad8h(2 * (ncol + 1)) + pad8h(2 * nnz) + ts * nnz);
+}
+
+template <typename TS>
+int32_t pack_sweep_runs(const Sweep &sw, std::vector<uint8_t> &data, std::vector<int32_t> &lvb,
+                        std::vector<int32_t> &lev, int32_t &K, int32_t &max_level_bytes, int64_t &offset) {
+  const int64_t ts = sizeof(TS);
+  K = 0;
+  for (int32_t t = 0; t < sw.nrows; ++t) K = std::max(K, sw.rp[t + 1] - sw.rp[t]);
+  offset = (int64_t)data.size();
+  int64_t pos = 0;
+  int32_t rows_done = 0, nseg = 0;
+  lvb.push_back(0);
+  lev.push_back(0);
+  auto close_seg = [&](int64_t size, int32_t rows) {
+    max_level_bytes = std::max<int32_t>(max_level_bytes, (int32_t)size);
+    pos += size;
+    lvb.push_back((int32_t)pos);
+    rows_done += rows;
+    lev.push_back(rows_done);
+    ++nseg;
+  };
+  // one ELL piece: rows at sweep positions tl[a .. b), entries kept by keep(column)
+  auto emit_ell = [&](const std::vector<int32_t> &tl, size_t a, size_t b, const std::vector<char> *skip) {
+    const int32_t L = (int32_t)(b - a);
+    auto keep = [&](int32_t col) { return !skip || !(*skip)[col]; };
+    int32_t Kl = 0;
+    for (size_t j = a; j < b; ++j) {
+      int32_t c = 0;
+      for (int32_t e = sw.rp[tl[j]]; e < sw.rp[tl[j] + 1]; ++e) c += keep(sw.ci[e]);
+      Kl = std::max(Kl, c);
+    }
+    const int64_t o_sc = kEllHeaderBytes + pad8h(2 * L), o_ci = o_sc + pad8h(ts * L);
+    const int64_t o_w = o_ci + pad8h(2 * (int64_t)Kl * L);
+    const int64_t size = ell_segment_bytes(L, Kl, ts);
+    data.resize(offset + pos + size, 0);
+    uint8_t *base = data.data() + offset + pos;
+    *reinterpret_cast<int32_t *>(base) = Kl;
+    uint16_t *rows = reinterpret_cast<uint16_t *>(base + kEllHeaderBytes);
+    TS *sc = reinterpret_cast<TS *>(base + o_sc);
+    uint16_t *ci = reinterpret_cast<uint16_t *>(base + o_ci);
+    TS *w = reinterpret_cast<TS *>(base + o_w);
+    for (int32_t j = 0; j < L; ++j) {
+      const int32_t t = tl[a + j], row = sw.rows[t];
+      rows[j] = (uint16_t)row;
+      sc[j] = (TS)sw.sc[t];
+      int32_t e2 = 0;
+      for (int32_t e = sw.rp[t]; e < sw.rp[t + 1]; ++e) {
+        if (!keep(sw.ci[e])) continue;
+        ci[(int64_t)e2 * L + j] = (uint16_t)sw.ci[e];
+        w[(int64_t)e2 * L + j] = (TS)sw.w[e];
+        ++e2;
+      }
+      for (; e2 < Kl; ++e2) {
+        ci[(int64_t)e2 * L + j] = (uint16_t)row;
+        w[(int64_t)e2 * L + j] = (TS)0;
+      }
+    }
+    close_seg(size, L);
+  };
+  // ELL pieces of at most kEllLevelBytes (or one row) over tl
+  auto emit_ell_cut = [&](const std::vector<int32_t> &tl, const std::vector<char> *skip) {
+    size_t a = 0;
+    int32_t Kc = 0;
+    for (size_t j = 0; j < tl.size(); ++j) {
+      int32_t c = 0;
+      for (int32_t e = sw.rp[tl[j]]; e < sw.rp[tl[j] + 1]; ++e) c += !skip || !(*skip)[sw.ci[e]];
+      const int32_t K2 = std::max(Kc, c);
+      if (j > a && ell_segment_bytes((int64_t)(j + 1 - a), K2, ts) > kEllLevelBytes) {
+        emit_ell(tl, a, j, skip);
+        a = j;
+        Kc = c;
+      } else {
+        Kc = K2;
+      }
+    }
+    if (a < tl.size()) emit_ell(tl, a, tl.size(), skip);
+  };
+  std::vector<char> in_run(std::max(sw.nrows, 1), 0);
+  std::vector<int32_t> tl;
+  int32_t l = 0;
+  while (l < sw.nlev) {
+    int32_t r = l;
+    while (r < sw.nlev && sw.levptr[r + 1] - sw.levptr[r] <= kColRunRows) ++r;
+    if (r - l >= kColRunMin) {
+      // run of levels [l, r): pre pieces, then column segments
+      const int32_t t0 = sw.levptr[l], t1 = sw.levptr[r];
+      tl.clear();
+      for (int32_t t = t0; t < t1; ++t) {
+        tl.push_back(t);
+        in_run[sw.rows[t]] = 1;
+      }
+      emit_ell_cut(tl, &in_run);
+      // columns: run row k (position t0 + k) -> (later run row, weight)
+      const int32_t R = t1 - t0;
+      std::vector<int32_t> cpos(std::max(sw.nrows, 1), -1);
+      for (int32_t k = 0; k < R; ++k) cpos[sw.rows[t0 + k]] = k;
+      std::vector<std::vector<std::pair<uint16_t, double>>> col(R);
+      for (int32_t k = 0; k < R; ++k) {
+        const int32_t t = t0 + k;
+        for (int32_t e = sw.rp[t]; e < sw.rp[t + 1]; ++e)
+          if (in_run[sw.ci[e]]) col[cpos[sw.ci[e]]].emplace_back((uint16_t)sw.rows[t], sw.w[e]);
+      }
+      int32_t c0 = 0;
+      while (c0 < R) {
+        int32_t c1 = c0 + 1;
+        int64_t nnz = (int64_t)col[c0].size();
+        while (c1 < R && csc_segment_bytes(c1 + 1 - c0, nnz + (int64_t)col[c1].size(), ts) <= kEllLevelBytes) {
+          nnz += (int64_t)col[c1].size();
+          ++c1;
+        }
+        const int32_t nc = c1 - c0;
+        const int64_t size = csc_segment_bytes(nc, nnz, ts);
+        data.resize(offset + pos + size, 0);
+        uint8_t *base = data.data() + offset + pos;
+        int32_t *hdr = reinterpret_cast<int32_t *>(base);
+        hdr[0] = -2;
+        hdr[1] = nc;
+        hdr[2] = (int32_t)nnz;
+        uint16_t *crow = reinterpret_cast<uint16_t *>(base + kEllHeaderBytes);
+        uint16_t *cptr = reinterpret_cast<uint16_t *>(base + kEllHeaderBytes + pad8h(2 * nc));
+        uint16_t *tgt = reinterpret_cast<uint16_t *>(base + kEllHeaderBytes + pad8h(2 * nc) + pad8h(2 * (nc + 1)));
+        TS *w = reinterpret_cast<TS *>(base + kEllHeaderBytes + pad8h(2 * nc) + pad8h(2 * (nc + 1)) + pad8h(2 * nnz));
+        int32_t e = 0;
+        for (int32_t c = c0; c < c1; ++c) {
+          crow[c - c0] = (uint16_t)sw.rows[t0 + c];
+          cptr[c - c0] = (uint16_t)e;
+          for (const auto &pr : col[c]) {
+            tgt[e] = pr.first;
+            w[e] = (TS)pr.second;
+            ++e;
+          }
+        }
+        cptr[nc] = (uint16_t)e;
+        close_seg(size, nc);
+        c0 = c1;
+      }
+      for (int32_t t = t0; t < t1; ++t) in_run[sw.rows[t]] = 0;
+      l = r;
+      continue;
+    }
+    // ordinary levels [l, max(r, l + 1))
+    const int32_t le = std::max(r, l + 1);
+    for (int32_t ll = l; ll < le; ++ll) {
+      tl.clear();
+      for (int32_t t = sw.levptr[ll]; t < sw.levptr[ll + 1]; ++t) tl.push_back(t);
+      emit_ell_cut(tl, nullptr);
+    }
+    l = le;
+  }
+  return nseg;
+}
+
+// Sizes of a packed block set that the B kernel's LDS plan needs.// Sizes of a packed block set that the B kernel's LDS plan needs.
 struct BSizes {
   int32_t max_m = 0, max_lev = 0, max_level_bytes = 0;
   int64_t data_bytes = 0;
@@ -1326,20 +1494,31 @@ bool pack_blocks(DevPool &P, const std::vector<Block> &blocks, BlockArrays<TS> &
     d.m = b.m;
     if (b.m > 65535) ok = false;   // uint16 local indices
     max_m = std::max(max_m, b.m);
-    const Sweep fs = split_levels(b.fwd, Kfix, sizeof(TS)), bs = split_levels(b.bwd, Kfix, sizeof(TS));
-    max_lev = std::max({max_lev, fs.nlev, bs.nlev});
-    d.f_nlev = fs.nlev;
-    d.f_lev = (int32_t)lev.size();
-    lev.insert(lev.end(), fs.levptr.begin(), fs.levptr.end());
-    if (fs.levptr.empty()) lev.push_back(0);
-    d.f_lvb = (int32_t)lvb.size();
-    pack_sweep<TS>(fs, Kfix, data, lvb, d.f_K, max_lb, d.f_data, rm ? &rm->bdata : nullptr, b.f_base);
-    d.b_nlev = bs.nlev;
-    d.b_lev = (int32_t)lev.size();
-    lev.insert(lev.end(), bs.levptr.begin(), bs.levptr.end());
-    if (bs.levptr.empty()) lev.push_back(0);
-    d.b_lvb = (int32_t)lvb.size();
-    pack_sweep<TS>(bs, Kfix, data, lvb, d.b_K, max_lb, d.b_data, rm ? &rm->bdata : nullptr, b.f_base);
+    if (Kfix == 0 && !rm) {
+      // ELL form with near-chains by columns
+      d.f_lev = (int32_t)lev.size();
+      d.f_lvb = (int32_t)lvb.size();
+      d.f_nlev = pack_sweep_runs<TS>(b.fwd, data, lvb, lev, d.f_K, max_lb, d.f_data);
+      d.b_lev = (int32_t)lev.size();
+      d.b_lvb = (int32_t)lvb.size();
+      d.b_nlev = pack_sweep_runs<TS>(b.bwd, data, lvb, lev, d.b_K, max_lb, d.b_data);
+      max_lev = std::max({max_lev, d.f_nlev, d.b_nlev});
+    } else {
+      const Sweep fs = split_levels(b.fwd, Kfix, sizeof(TS)), bs = split_levels(b.bwd, Kfix, sizeof(TS));
+      max_lev = std::max({max_lev, fs.nlev, bs.nlev});
+      d.f_nlev = fs.nlev;
+      d.f_lev = (int32_t)lev.size();
+      lev.insert(lev.end(), fs.levptr.begin(), fs.levptr.end());
+      if (fs.levptr.empty()) lev.push_back(0);
+      d.f_lvb = (int32_t)lvb.size();
+      pack_sweep<TS>(fs, Kfix, data, lvb, d.f_K, max_lb, d.f_data, rm ? &rm->bdata : nullptr, b.f_base);
+      d.b_nlev = bs.nlev;
+      d.b_lev = (int32_t)lev.size();
+      lev.insert(lev.end(), bs.levptr.begin(), bs.levptr.end());
+      if (bs.levptr.empty()) lev.push_back(0);
+      d.b_lvb = (int32_t)lvb.size();
+      pack_sweep<TS>(bs, Kfix, data, lvb, d.b_K, max_lb, d.b_data, rm ? &rm->bdata : nullptr, b.f_base);
+    }
     max_K = std::max({max_K, d.f_K, d.b_K});
     // E rows as ELL (width = longest row)
     d.e_row = (int32_t)e_row.size();

@@ -29,7 +29,15 @@ namespace slr {
 //     sc    TS[L]              row scale
 //     ci    uint16[K*L]        column of entry e of row j at [e*L + j]
 //     w     TS[K*L]            pre-divided weight, same layout
-// each ELL section padded to 8 bytes and the segment to 16.
+// each ELL section padded to 8 bytes and the segment to 16.  A run of
+// consecutive levels of at most a few rows (a near-chain) is packed as ELL
+// pieces holding the run's rows with their entries to rows before the run,
+// then column segments (header int32 -2, ncol, nnz):
+//     crow  uint16[ncol]       the run row finished by column c
+//     cptr  uint16[ncol + 1]   its entries [cptr[c], cptr[c+1])
+//     tgt   uint16[nnz]        a later run row that uses it
+//     w     TS[nnz]            that row's pre-divided weight
+// solved column by column (x[tgt] -= w x[crow]).
 struct BlockDesc {
   int32_t m0, m;                   // interior range in the internal order
   int32_t f_nlev, f_K, f_lev, f_lvb;   // forward sweep: levels, width, levptr / lvb offsets

@@ -160,7 +160,24 @@ __device__ __forceinline__ void ell_rows_group(const uint16_t *rows, const TS *s
   const int g = lane % G;
   for (int j = lane / G; j < L; j += 64 / G) {
     TC part = 0;
-    for (int e = g; e < K; e += G) part += cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
+    // four entries per lane in flight: index and weight loads, then the
+    // gathers, then the sums in entry order (entries past the row end are
+    // clamped to its last one and not added, so no lane takes another path)
+    for (int e0 = g; e0 < K; e0 += 4 * G) {
+      int c[4];
+      TC wv[4], xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * G, K - 1);
+        c[u] = ci[e * L + j];
+        wv[u] = cvt<TC>(w[e * L + j]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = xc[c[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * G < K) part += wv[u] * xv[u];
+    }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, G);
     if (g == 0) {
@@ -170,9 +187,43 @@ __device__ __forceinline__ void ell_rows_group(const uint16_t *rows, const TS *s
   }
 }
 
+// A column segment of a near-chain run (marker -2 in the header, then the
+// column count and entry count): for each column in order, its row's value
+// is final; every later run row that uses it subtracts weight x value.
+// Within a column each target row appears once, so the lanes' updates
+// never collide, and the wave's program order carries them to the next
+// column.
+template <typename TS, typename TC>
+__device__ __forceinline__ void csc_segment_wave(const uint8_t *seg, TC *xc, int lane) {
+  const int32_t *hdr = reinterpret_cast<const int32_t *>(seg);
+  const int nc = hdr[1], nnz = hdr[2];
+  const uint16_t *crow = reinterpret_cast<const uint16_t *>(seg + kEllHeaderBytes);
+  const uint16_t *cptr = reinterpret_cast<const uint16_t *>(seg + kEllHeaderBytes + pad8(2 * nc));
+  const uint16_t *tgt = reinterpret_cast<const uint16_t *>(seg + kEllHeaderBytes + pad8(2 * nc) + pad8(2 * (nc + 1)));
+  const TS *w = reinterpret_cast<const TS *>(seg + kEllHeaderBytes + pad8(2 * nc) + pad8(2 * (nc + 1)) +
+                                             pad8(2 * nnz));
+  // the next column's row and entry range are read one column ahead
+  int r = crow[0], e0 = cptr[0], e1 = cptr[1];
+  for (int c = 0; c < nc; ++c) {
+    const int rn = crow[min(c + 1, nc - 1)], en = cptr[min(c + 2, nc)];
+    const TC xj = xc[r];
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const int i = tgt[e];
+      xc[i] -= cvt<TC>(w[e]) * xj;
+    }
+    r = rn;
+    e0 = e1;
+    e1 = en;
+  }
+}
+
 template <typename TS, typename TC>
 __device__ __forceinline__ void ell_level_wave(const uint8_t *seg, int L, TC *xc, int lane) {
   const int K = *reinterpret_cast<const int32_t *>(seg);
+  if (K < 0) {
+    csc_segment_wave<TS, TC>(seg, xc, lane);
+    return;
+  }
   const uint8_t *base = seg + kEllHeaderBytes;
   const uint16_t *rows = reinterpret_cast<const uint16_t *>(base);
   const int o_sc = pad8(2 * L);
@@ -180,16 +231,21 @@ __device__ __forceinline__ void ell_level_wave(const uint8_t *seg, int L, TC *xc
   const int o_ci = o_sc + pad8((int)sizeof(TS) * L);
   const uint16_t *ci = reinterpret_cast<const uint16_t *>(base + o_ci);
   const TS *w = reinterpret_cast<const TS *>(base + o_ci + pad8(2 * K * L));
-  if (K <= 8) {
+  // lanes per row: enough that each lane holds few entries, no more than
+  // the level's rows leave room for
+  const int gk = K <= 4 ? 1 : (K <= 16 ? 4 : (K <= 64 ? 16 : 64));
+  const int gl = L >= 64 ? 1 : (L >= 16 ? 4 : (L >= 4 ? 16 : 64));
+  const int G = min(gk, gl);
+  if (G == 1) {
     for (int j = lane; j < L; j += 64) {
       const int row = rows[j];
       TC acc = cvt<TC>(sc[j]) * xc[row];
       for (int e = 0; e < K; ++e) acc -= cvt<TC>(w[e * L + j]) * xc[(int)ci[e * L + j]];
       xc[row] = acc;
     }
-  } else if (K <= 32) {
+  } else if (G == 4) {
     ell_rows_group<TS, TC, 4>(rows, sc, ci, w, L, K, xc, lane);
-  } else if (K <= 128) {
+  } else if (G == 16) {
     ell_rows_group<TS, TC, 16>(rows, sc, ci, w, L, K, xc, lane);
   } else {
     ell_rows_group<TS, TC, 64>(rows, sc, ci, w, L, K, xc, lane);

@@ -80,3 +80,26 @@ def test_noalloc_apply_second_context_and_size_limit():
         Ga.apply_dd_noalloc(rbig)
     assert e.value.code == P.SLR_ERR_ARG
     assert np.array_equal(Ga.apply_dd_noalloc(ra).cpu().numpy(), za)
+
+
+@pytest.mark.parametrize("form", ["recursive", "separator"])
+def test_noalloc_apply_recursive_and_separator(form):
+    """The recursive interface solver (its scratch: the second interface
+    block and the inner rank-k partials) and an edge-based partition (the
+    interior block z that the E^T product reads) on the fixed array."""
+    import paper_1505_04340_amd as P
+    print(f"noalloc apply: {form}", flush=True)
+    if form == "recursive":
+        pr = si.make_config("shifted3d_128", N=24, boxes=3, neg=10)
+        G = P.SLR(pr.csr, pr.part, pr.nparts, k=8, lanczos_steps=40, b_fact="ildlt", c_fact="ict", c_order="hid",
+                  c_levels=2, k2=4, v0=pr.v0())
+        n = pr.n
+    else:
+        csr = si.laplacian_3d(25)
+        part = si.separator_partition(25, 3, 3)
+        G = P.SLR(csr, part, 27, k=8, lanczos_steps=40, v0=si.lanczos_start(csr[3]))
+        n = csr[3]
+    rng = np.random.default_rng(8)
+    for nr in (4, 1):
+        r = _dev(rng.uniform(-1, 1, (n, nr)))
+        assert np.array_equal(G.apply_dd_noalloc(r).cpu().numpy(), G.apply_dd(r).cpu().numpy()), nr
