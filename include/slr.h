@@ -216,6 +216,9 @@ typedef struct {
   int32_t c1_levels, c2_levels;
   double theta2;
   int64_t nnz_LC1, nnz_LC2, nnz_F;  /* entries of L1, L2 and of F         */
+  /* 1: several-column B solves run as a persistent grid (slr_autotune's
+     or slr_set_bsolve_plan's choice) */
+  int32_t tune_b_persistentM;
 } slr_info;
 
 typedef struct slr_ctx slr_ctx;
@@ -245,6 +248,22 @@ void slr_default_solve_opts(slr_solve_opts *o);
  * LANCZOS_SHORT, OOM, HIP. */
 int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *o,
               void *hip_stream, slr_ctx **out);
+
+/* slr_set_bsolve_plan: set the B kernel's launch shape for one column
+ * (several == 0) or several columns (several != 0) instead of slr_autotune:
+ * threads per workgroup (256, 512 or 1024; 0 restores the built-in plan
+ * and ignores the rest), the share 1/lds_div of the LDS limit a workgroup
+ * may take (1..8), the most columns per workgroup (1..16), and persistent =
+ * 1 for a resident grid (as many workgroups as fit the compute units at
+ * once) walking a schedule of (subdomain, column group) items, longest
+ * first by each subdomain's levels and entries, each item given to the
+ * workgroup with the least work so far; the batching form with subdomains
+ * of uneven size (a launch with no more items than workgroups stays a plain
+ * grid).  Results are bitwise the same under every plan.  SLR_ERR_ARG for
+ * values out of range, a largest subdomain that does not fit the share, or
+ * live batches. */
+int slr_set_bsolve_plan(slr_ctx *c, int32_t several, int32_t threads, int32_t lds_div, int32_t rmax,
+                        int32_t persistent);
 
 /* slr_analyze: the host part of slr_setup only (classification, DD
  * ordering, factorisations, level schedules) -- no device memory is

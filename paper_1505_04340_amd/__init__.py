@@ -89,7 +89,8 @@ class slr_info(ctypes.Structure):
                 ("lanczos_reorth", _I32), ("tune_b_threads1", _I32), ("tune_b_lds_div1", _I32),
                 ("tune_b_threadsM", _I32), ("tune_b_lds_divM", _I32), ("tune_b_rmaxM", _I32),
                 ("lr_chunks", _I32), ("s1", _I64), ("k2", _I32), ("lanczos_steps2", _I32), ("c1_levels", _I32),
-                ("c2_levels", _I32), ("theta2", _D), ("nnz_LC1", _I64), ("nnz_LC2", _I64), ("nnz_F", _I64)]
+                ("c2_levels", _I32), ("theta2", _D), ("nnz_LC1", _I64), ("nnz_LC2", _I64), ("nnz_F", _I64),
+                ("tune_b_persistentM", _I32)]
 
 
 def _sig(name, res, args):
@@ -126,6 +127,7 @@ slr_set_allocator = _sig("slr_set_allocator", None, [SLR_ALLOC_FN, SLR_FREE_FN, 
 slr_query = _sig("slr_query", ctypes.c_int, [_P, ctypes.POINTER(slr_info)])
 slr_export = _sig("slr_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P])
 slr_export_inner = _sig("slr_export_inner", ctypes.c_int, [_P, _P, _P, _P])
+slr_set_bsolve_plan = _sig("slr_set_bsolve_plan", ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32])
 slr_spmv = _sig("slr_spmv", ctypes.c_int, [_P, _P, _P, _I32, _P])
 slr_batch_create = _sig("slr_batch_create", ctypes.c_int, [_P, _I32, _I32, _D, _I32, ctypes.POINTER(_P)])
 slr_batch_admit = _sig("slr_batch_admit", ctypes.c_int, [_P, _P, _P, _I32, _I64, _P])
@@ -143,7 +145,7 @@ EXPORTED = ("slr_default_opts", "slr_default_solve_opts", "slr_setup", "slr_anal
             "slr_grow_lowrank", "slr_refactor",
             "slr_time_kernel", "slr_apply", "slr_apply_dd", "slr_apply_dd_noalloc",
             "slr_solve", "slr_solve_workspace_bytes", "slr_query", "slr_export", "slr_export_inner", "slr_spmv",
-            "slr_trim", "slr_export_setup", "slr_import", "slr_set_allocator", "slr_autotune",
+            "slr_trim", "slr_export_setup", "slr_import", "slr_set_allocator", "slr_autotune", "slr_set_bsolve_plan",
             "slr_batch_create", "slr_batch_admit", "slr_batch_step", "slr_batch_poll",
             "slr_batch_active", "slr_batch_bytes", "slr_batch_destroy", "slr_destroy",
             "slr_strerror", "slr_last_error", "slr_device_lds_bytes")
@@ -340,7 +342,15 @@ class SLR:
         _check(slr_autotune(self._h, nrhs, reps, _stream(stream)), "slr_autotune")
         self.info = self.query()
         return {k: self.info[k] for k in ("tune_b_threads1", "tune_b_lds_div1", "tune_b_threadsM",
-                                          "tune_b_lds_divM", "tune_b_rmaxM", "lr_chunks")}
+                                          "tune_b_lds_divM", "tune_b_rmaxM", "tune_b_persistentM", "lr_chunks")}
+
+    def set_bsolve_plan(self, several: bool, threads: int = 0, lds_div: int = 1, rmax: int = 16,
+                        persistent: bool = False):
+        """Set the B kernel's launch shape (slr_set_bsolve_plan); threads=0
+        restores the built-in plan."""
+        _check(slr_set_bsolve_plan(self._h, 1 if several else 0, threads, lds_div, rmax, 1 if persistent else 0),
+               "slr_set_bsolve_plan")
+        self.info = self.query()
 
     def trim(self):
         """Release the scratch kept between calls (slr_trim)."""

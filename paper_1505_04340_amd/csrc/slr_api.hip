@@ -9,7 +9,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -288,7 +290,16 @@ struct slr_ctx {
   // workgroup may take (1/lds_div), and the most columns per workgroup
   struct BTune {
     int32_t threads = 0, lds_div = 1, rmax = 16;
+    int32_t persistent = 0;     // 1: a resident grid walks a longest-first schedule
   } tune1, tuneM;              // one column; several columns
+  // schedules of the persistent B launch, by (column groups, workgroups)
+  struct BSched {
+    int32_t ncg = 0, nwg = 0;
+    int32_t *ptr = nullptr, *items = nullptr;
+  };
+  std::vector<BSched> bsched;
+  DevPool schedpool;
+  std::vector<double> b_cost_h;  // per subdomain: work estimate of one B solve item
   DevPool lrpool;               // U, U64, dsc
   // Recursive interface solver (opts.c_levels == 2, Sec. 5.2): C = [C1 F;
   // F^T C2] in HID order.  The connectors of C1 form a block-diagonal
@@ -462,6 +473,44 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   return SLR_OK;
 }
 
+// Schedule of the persistent B launch for ncg column groups on nwg
+// workgroups: the items (subdomain, column group), longest first by the
+// per-subdomain estimate, each given to the workgroup with the least work
+// so far (longest-processing-time order); kept per (ncg, nwg).
+const slr_ctx::BSched *b_schedule(slr_ctx *c, int32_t ncg, int32_t nwg) {
+  for (const auto &b : c->bsched)
+    if (b.ncg == ncg && b.nwg == nwg) return &b;
+  const int32_t p = c->p;
+  std::vector<int32_t> items;
+  items.reserve((size_t)p * ncg);
+  for (int32_t g = 0; g < ncg; ++g)
+    for (int32_t q = 0; q < p; ++q) items.push_back((g << 16) | q);
+  std::stable_sort(items.begin(), items.end(),
+                   [&](int32_t x, int32_t y) { return c->b_cost_h[x & 0xFFFF] > c->b_cost_h[y & 0xFFFF]; });
+  std::vector<std::vector<int32_t>> per(nwg);
+  std::priority_queue<std::pair<double, int32_t>, std::vector<std::pair<double, int32_t>>, std::greater<>> heap;
+  for (int32_t w = 0; w < nwg; ++w) heap.emplace(0.0, w);
+  for (int32_t it : items) {
+    auto [load, w] = heap.top();
+    heap.pop();
+    per[w].push_back(it);
+    heap.emplace(load + c->b_cost_h[it & 0xFFFF], w);
+  }
+  std::vector<int32_t> ptr(1, 0), flat;
+  for (const auto &v : per) {
+    flat.insert(flat.end(), v.begin(), v.end());
+    ptr.push_back((int32_t)flat.size());
+  }
+  slr_ctx::BSched b;
+  b.ncg = ncg;
+  b.nwg = nwg;
+  b.ptr = c->schedpool.upload(ptr);
+  b.items = c->schedpool.upload(flat);
+  if (!b.ptr || !b.items) return nullptr;
+  c->bsched.push_back(b);
+  return &c->bsched.back();
+}
+
 // LDS plan of the B kernel: right-hand sides per workgroup R and the
 // staging buffer for the packed sweeps.  Total LDS = stage + pad16(x) +
 // 16 (max_lev + 1).  R is the largest value (<= nrhs, <= 16) that still
@@ -511,7 +560,21 @@ int run_bsolve(slr_ctx *c, const BlockArrays<TS> &B, const BArgs &a0, hipStream_
   a.stage_bytes = stage;
   const size_t lds = (size_t)stage + kStageDummyBytes + pad16h((int64_t)sizeof(TC) * (c->b_max_m * R + 1)) +
                     16 * (size_t)(c->b_max_lev + 1);
-  launch_bsolve<TS, TC>(B, c->p, a, threads, lds, st);
+  int32_t grid = c->p;
+  if (tu.threads > 0 && tu.persistent) {
+    // resident workgroups: by waves (32 per CU) and by LDS
+    const int32_t per_cu = std::max<int32_t>(1, std::min<int32_t>(2048 / threads, (int32_t)(c->lds_limit / lds)));
+    const int32_t nwg = c->n_cu * per_cu;
+    const int32_t ncg = (a.nrhs + R - 1) / R;
+    if ((int64_t)c->p * ncg > nwg && c->p <= 65535 && ncg <= 32767) {
+      const slr_ctx::BSched *sc = b_schedule(c, ncg, nwg);
+      if (!sc) return fail(SLR_ERR_OOM, "persistent schedule");
+      a.sched = sc->items;
+      a.sched_ptr = sc->ptr;
+      grid = nwg;
+    }
+  }
+  launch_bsolve<TS, TC>(B, grid, a, threads, lds, st);
   return SLR_OK;
 }
 
@@ -1618,6 +1681,11 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
                    bool &ok, RfMaps *rm) {
   BSizes sz;
   ok = pack_blocks<TS>(c->pool, H.blocks, B, sz, rm);
+  // work estimate of one item of a subdomain for the persistent schedule:
+  // its dependent levels, plus its entries (staging)
+  c->b_cost_h.clear();
+  for (const Block &b : H.blocks)
+    c->b_cost_h.push_back((double)(b.fwd.nlev + b.bwd.nlev) + (double)(b.fwd.ci.size() + b.bwd.ci.size()) / 256.0);
   c->b_max_m = sz.max_m;
   c->b_max_lev = sz.max_lev;
   c->b_max_level_bytes = sz.max_level_bytes;
@@ -1870,6 +1938,7 @@ int export_setup(const slr_ctx *cc, std::vector<uint8_t> &blob) {
   if (rc) return rc;
   // launch shapes and rank-k chunks (slr_autotune)
   w.pod(c->tune1); w.pod(c->tuneM); w.pod(c->lr_nblk_tuned); w.pod(c->lrm_nblk);
+  w.vec(c->b_cost_h);
   // low-rank part (FP64; the stored precision is rebuilt from it on import)
   w.pod(c->k); w.pod(c->theta);
   std::vector<double> U((size_t)c->s * c->k);
@@ -1943,7 +2012,9 @@ int import_setup(const uint8_t *buf, size_t bytes, hipStream_t st, slr_ctx **out
   if (c->n) HIPCHK(hipMemcpy(c->perm_h.data(), c->perm, sizeof(int64_t) * c->n, hipMemcpyDeviceToHost));
   std::vector<double> U;
   r.pod(c->tune1); r.pod(c->tuneM); r.pod(c->lr_nblk_tuned); r.pod(c->lrm_nblk);
-  if (c->tune1.lds_div < 1 || c->tuneM.lds_div < 1 || c->tune1.threads < 0 || c->tune1.threads > 1024 ||
+  r.vec(c->b_cost_h);
+  if ((int64_t)c->b_cost_h.size() != c->p ||
+      c->tune1.lds_div < 1 || c->tuneM.lds_div < 1 || c->tune1.threads < 0 || c->tune1.threads > 1024 ||
       c->tuneM.threads < 0 || c->tuneM.threads > 1024 || c->lrm_nblk < 1 || c->lr_nblk_tuned < 0)
     return bad("launch shapes");
   r.pod(c->k); r.pod(c->theta);
@@ -2405,7 +2476,10 @@ int slr_autotune(slr_ctx *c, int32_t nrhs, int32_t reps, void *hip_stream) {
       int32_t R = 0, stage = 0;
       if (!b_lds_plan(c, one ? 1 : std::min(nrhs, 16), tcb, R, stage, c->lds_limit / div)) continue;
       for (int32_t r = R; r >= 1; r = (r > 1 ? std::max(1, r / 2) : 0)) {
-        cand.push_back(slr_ctx::BTune{th, div, r});
+        cand.push_back(slr_ctx::BTune{th, div, r, 0});
+        // several columns: the same shape as a persistent grid walking a
+        // longest-first schedule of (subdomain, column group) items
+        if (!one) cand.push_back(slr_ctx::BTune{th, div, r, 1});
         if (one || r == 1) break;
       }
     }
@@ -2462,7 +2536,35 @@ int slr_autotune(slr_ctx *c, int32_t nrhs, int32_t reps, void *hip_stream) {
   c->info.tune_b_threadsM = c->tuneM.threads;
   c->info.tune_b_lds_divM = c->tuneM.lds_div;
   c->info.tune_b_rmaxM = c->tuneM.threads ? c->tuneM.rmax : 0;
+  c->info.tune_b_persistentM = c->tuneM.threads ? c->tuneM.persistent : 0;
   c->info.lr_chunks = c->uk_prec == SLR_BF16 ? c->lrm_nblk : c->lr_nblk;
+  return SLR_OK;
+}
+
+int slr_set_bsolve_plan(slr_ctx *c, int32_t several, int32_t threads, int32_t lds_div, int32_t rmax,
+                        int32_t persistent) {
+  if (!c) return fail(SLR_ERR_ARG, "null");
+  if (c->live_batches > 0) return fail(SLR_ERR_ARG, "the context still has batches");
+  slr_ctx::BTune &tu = several ? c->tuneM : c->tune1;
+  if (threads == 0) {
+    tu = slr_ctx::BTune{};
+  } else {
+    if ((threads != 256 && threads != 512 && threads != 1024) || lds_div < 1 || lds_div > 8 || rmax < 1 ||
+        rmax > 16 || (persistent != 0 && persistent != 1))
+      return fail(SLR_ERR_ARG, "bad B launch plan");
+    int32_t R = 0, stage = 0;
+    const size_t tcb = (c->fact_prec == SLR_FP64) ? 8 : 4;
+    if (!b_lds_plan(c, several ? std::min(rmax, 16) : 1, tcb, R, stage, c->lds_limit / lds_div) ||
+        !b_lds_plan(c, 1, 8, R, stage, c->lds_limit / lds_div))
+      return fail(SLR_ERR_ARG, "the largest subdomain does not fit that share of the LDS");
+    tu = slr_ctx::BTune{threads, lds_div, rmax, persistent};
+  }
+  c->info.tune_b_threads1 = c->tune1.threads;
+  c->info.tune_b_lds_div1 = c->tune1.lds_div;
+  c->info.tune_b_threadsM = c->tuneM.threads;
+  c->info.tune_b_lds_divM = c->tuneM.lds_div;
+  c->info.tune_b_rmaxM = c->tuneM.threads ? c->tuneM.rmax : 0;
+  c->info.tune_b_persistentM = c->tuneM.threads ? c->tuneM.persistent : 0;
   return SLR_OK;
 }
 
@@ -2543,6 +2645,7 @@ void slr_destroy(slr_ctx *c) {
   c->lrpool.release();
   c->ppool.release();
   c->spool.release();
+  c->schedpool.release();
   delete c;
 }
 
@@ -2552,7 +2655,7 @@ int slr_query(const slr_ctx *c, slr_info *info) {
   info->lr_chunks = c->uk_prec == SLR_BF16 ? c->lrm_nblk : c->lr_nblk;
   info->device_bytes =
       c->pool.bytes + c->lrpool.bytes + c->ws.pool.bytes + c->spool.bytes + c->ppool.bytes + c->rf.pool.bytes +
-      (int64_t)(c->lz.cap + c->gm.cap);
+      c->schedpool.bytes + (int64_t)(c->lz.cap + c->gm.cap);
   return SLR_OK;
 }
 

@@ -117,6 +117,12 @@ struct BArgs {
   int32_t R = 1;              // right-hand sides per workgroup
   int32_t stage_bytes = 0;    // LDS staging buffer for the packed sweeps
   int32_t sweeps = 3;         // bit 0: forward sweep, bit 1: backward sweep
+  // persistent launch (sched != nullptr): workgroup w takes the work items
+  // sched[sched_ptr[w] .. sched_ptr[w+1]), each (column group << 16) |
+  // subdomain, in that order; otherwise blockIdx.x is the subdomain and
+  // blockIdx.y the column group
+  const int32_t *sched = nullptr;
+  const int32_t *sched_ptr = nullptr;
 };
 
 // Numeric refactorisation on the device: one stored coefficient (TS) at

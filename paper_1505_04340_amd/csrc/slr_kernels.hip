@@ -511,18 +511,18 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
   }
 }
 
-// One launch: for subdomain blockIdx.x and right-hand sides
-// [blockIdx.y * R, +Rg): prologue (f, E y) into LDS, forward and backward
+// One work item: subdomain sub and right-hand sides [cg * R, +Rg):
+// prologue (f, E y) into LDS, forward and backward
 // sweeps in LDS (or only one of them, by a.sweeps), then u and the E^T
 // epilogue.  KE > 0: every packed row has exactly KE entries (padding has
 // w = 0); KE == 0: the ELL form of any width.  Either way the sweeps run
 // one wave per column with double-buffered staging.
 template <typename TS, typename TC, int KE>
-__global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
+__device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArgs &a, int sub, int cg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const BlockDesc d = B.desc[blockIdx.x];
+  const BlockDesc d = B.desc[sub];
   const int R = a.R;
-  const int c0 = blockIdx.y * R;
+  const int c0 = cg * R;
   const int Rg = min(R, a.nrhs - c0);
   const int m = d.m;
   const int XS = B.max_m;
@@ -623,6 +623,22 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   }
 }
 
+// One launch of the batched B solves: one workgroup per (subdomain, column
+// group), or a persistent grid walking its scheduled items (the shared
+// memory is reused after a barrier between items).
+template <typename TS, typename TC, int KE>
+__global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
+  if (a.sched) {
+    for (int it = a.sched_ptr[blockIdx.x]; it < a.sched_ptr[blockIdx.x + 1]; ++it) {
+      const int item = a.sched[it];
+      bsolve_item<TS, TC, KE>(B, a, item & 0xFFFF, item >> 16);
+      __syncthreads();
+    }
+  } else {
+    bsolve_item<TS, TC, KE>(B, a, blockIdx.x, blockIdx.y);
+  }
+}
+
 template <typename TS, typename TC, int KE>
 void launch_bsolve_k(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
                      hipStream_t st) {
@@ -632,7 +648,8 @@ void launch_bsolve_k(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_
                               (int)lds_bytes);
     attr_bytes = lds_bytes;
   }
-  dim3 grid(p, (a.nrhs + a.R - 1) / a.R);
+  // persistent: p is the number of workgroups of the schedule
+  dim3 grid(p, a.sched ? 1 : (a.nrhs + a.R - 1) / a.R);
   hipLaunchKernelGGL((k_bsolve<TS, TC, KE>), grid, dim3(threads), lds_bytes, st, B, a);
 }
 

@@ -205,3 +205,29 @@ def test_autotune_keeps_results(prec):
     Gi = type(G).import_setup(G.export_setup())
     assert Gi.info["lr_chunks"] == G.info["lr_chunks"]
     assert np.array_equal(Gi.apply(_dev(r)).cpu().numpy(), Z)
+
+
+@pytest.mark.parametrize("prec", [("fp64", "fp64"), ("fp32", "bf16")])
+def test_persistent_bsolve_plan_is_bitwise_the_same(prec):
+    """The batching form's persistent launch (a resident grid walking a
+    longest-first schedule of (subdomain, column group) items over
+    subdomains of uneven size) gives the same bits as the plain grid, for
+    several shapes, and survives the serialised setup."""
+    fp, up = prec
+    print(f"persistent B plan: {fp}/{up}", flush=True)
+    pr = si.make_config("diffusion2d_1024", N=256, boxes=8)     # 64 subdomains of uneven size
+    G = _slr(pr, k=16, lanczos_steps=80, c_order="multicolor", fact_prec=fp, uk_prec=up)
+    r = _dev(np.random.default_rng(10).uniform(-1, 1, (pr.n, 32)))
+    Z = G.apply(r).cpu().numpy()
+    for threads, div, rmax in ((256, 4, 1), (512, 2, 2), (1024, 1, 4)):
+        G.set_bsolve_plan(True, threads, div, rmax, persistent=True)
+        assert G.info["tune_b_persistentM"] == 1
+        assert np.array_equal(G.apply(r).cpu().numpy(), Z), (threads, div, rmax)
+        G.set_bsolve_plan(True, threads, div, rmax, persistent=False)
+        assert np.array_equal(G.apply(r).cpu().numpy(), Z), (threads, div, rmax)
+    G.set_bsolve_plan(True, 512, 2, 2, persistent=True)
+    Gi = type(G).import_setup(G.export_setup())
+    assert Gi.info["tune_b_persistentM"] == 1
+    assert np.array_equal(Gi.apply(r).cpu().numpy(), Z)
+    G.set_bsolve_plan(True, 0)
+    assert G.info["tune_b_persistentM"] == 0 and G.info["tune_b_threadsM"] == 0

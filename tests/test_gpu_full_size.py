@@ -182,3 +182,55 @@ def test_shifted_128_fgmres_recursive_interface_converges():
     rr = np.linalg.norm(b[:, 0] - pr.scipy() @ x.cpu().numpy()) / np.linalg.norm(b[:, 0])
     assert info[0]["status"] == 0 and rr <= 1e-8, (info, rr)
     assert abs(info[0]["iters"] - gold["iters"]) <= 1, (info[0]["iters"], gold["iters"])
+
+
+def test_diffusion_1024_fp64_apply_and_pcg_counts(diffusion):
+    """The FP64 form of the 1024^2 workload at full size: the apply of 32
+    columns against the oracle on the device's low-rank part (sampled
+    columns, 1e-12), and PCG on the sampled right-hand sides within +-1
+    iteration of the oracle's own run (tests/golden/pcg_counts.json,
+    written by tests/golden/make_counts.py)."""
+    import json
+    import os
+    import paper_1505_04340_amd as P
+    with open(os.path.join(os.path.dirname(__file__), "golden", "pcg_counts.json")) as f:
+        gold = json.load(f)["diffusion2d_1024"]
+    pr = diffusion
+    print("diffusion 1024^2 fp64 apply and pcg", flush=True)
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, c_order="multicolor",
+              v0=pr.v0())
+    ex = G.export()
+    Po = O.setup(pr.csr, pr.part, pr.nparts, pr.k, 0, b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor",
+                 lowrank=(ex["U"], ex["lambda"], ex["theta"]))
+    r = np.random.default_rng(22).uniform(-1, 1, (pr.n, 32))
+    z = G.apply(torch.tensor(r, dtype=torch.float64, device="cuda")).cpu().numpy()
+    cols = [0, 13, 31]
+    assert _relerr(z[:, cols], Po.apply(r[:, cols])).max() <= 1e-12
+    xs, b = pr.rhs()
+    bc = b[:, gold["columns"]]
+    x, infos = G.solve(torch.tensor(bc, dtype=torch.float64, device="cuda"), "pcg", rtol=1e-8, maxit=3000)
+    A = pr.scipy()
+    rr = np.linalg.norm(bc - A @ x.cpu().numpy().reshape(pr.n, -1), axis=0) / np.linalg.norm(bc, axis=0)
+    assert rr.max() <= 1e-8 and all(i["status"] == 0 for i in infos)
+    for i, want in zip(infos, gold["iters"]):
+        assert abs(i["iters"] - want) <= 1, ([i["iters"] for i in infos], gold["iters"])
+
+
+def test_serve_512_pcg_count_in_multicolour_order():
+    """The 2-D 512^2 serving matrix (C's factor in multicolour order, the
+    device's reading): PCG within +-1 iteration of the oracle's count in the
+    same order; the oracle's count in subdomain order is recorded beside it
+    (tests/golden/pcg_counts.json)."""
+    import json
+    import os
+    import paper_1505_04340_amd as P
+    with open(os.path.join(os.path.dirname(__file__), "golden", "pcg_counts.json")) as f:
+        gold = json.load(f)["serve_lap2d_512_multicolor"]
+    pr = si.make_config("serve_lap2d_512")
+    print("serve 512^2 pcg", flush=True)
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, c_order="multicolor",
+              v0=pr.v0())
+    xs, b = pr.rhs()
+    x, info = G.solve(torch.tensor(b[:, 0], dtype=torch.float64, device="cuda"), "pcg", rtol=1e-8, maxit=1000)
+    assert info[0]["status"] == 0 and info[0]["relres"] <= 1e-8
+    assert abs(info[0]["iters"] - gold["iters"]) <= 1, (info[0]["iters"], gold["iters"])

@@ -171,6 +171,13 @@ def test_lap3d_lanczos_apply_pcg(which, lap3d, lap3d_mc):
     G = _slr(pr, c_order=which)
     ex, gv, gb = _lanczos_parity(G, Po, pr.k)
     assert (ex["perm"] == Po.perm).all()
+    # theta = lambda_{k+1} enters every apply: it is a Ritz value of the
+    # oracle's T_m to within the two residual bounds (which Ritz value
+    # sits at position k+1 may differ when a multiple eigenvalue is seen
+    # once on one side and twice on the other)
+    ov, ob = _ritz_bounds(Po.alpha, Po.beta)
+    th = ex["theta"]
+    assert th == gv[pr.k] and np.min(np.abs(ov - th) - ob) <= gb[pr.k] + 1e-10 * abs(th)
     # apply parity on the oracle's low-rank part
     Gi = _slr(pr, c_order=which, lowrank=(Po.U, Po.lam, Po.theta))
     r = _rand(pr.n, 2, 5)
