@@ -216,8 +216,8 @@ typedef struct {
   int32_t c1_levels, c2_levels;
   double theta2;
   int64_t nnz_LC1, nnz_LC2, nnz_F;  /* entries of L1, L2 and of F         */
-  /* 1: several-column B solves run as a persistent grid (slr_autotune's
-     or slr_set_bsolve_plan's choice) */
+  /* 1 or 2: several-column B solves run as a persistent grid (slr_autotune's
+     or slr_set_bsolve_plan's choice; 2: columns per item by subdomain size) */
   int32_t tune_b_persistentM;
 } slr_info;
 
@@ -259,7 +259,9 @@ int slr_setup(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts *
  * first by each subdomain's levels and entries, each item given to the
  * workgroup with the least work so far; the batching form with subdomains
  * of uneven size (a launch with no more items than workgroups stays a plain
- * grid).  Results are bitwise the same under every plan.  SLR_ERR_ARG for
+ * grid).  persistent = 2: the same, with each subdomain taking as many
+ * columns per item as its own rows let the workgroup's x region hold (at
+ * most one fewer than its waves), so small subdomains take more columns.  Results are bitwise the same under every plan.  SLR_ERR_ARG for
  * values out of range, a largest subdomain that does not fit the share, or
  * live batches. */
 int slr_set_bsolve_plan(slr_ctx *c, int32_t several, int32_t threads, int32_t lds_div, int32_t rmax,

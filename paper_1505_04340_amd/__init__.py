@@ -345,10 +345,10 @@ class SLR:
                                           "tune_b_lds_divM", "tune_b_rmaxM", "tune_b_persistentM", "lr_chunks")}
 
     def set_bsolve_plan(self, several: bool, threads: int = 0, lds_div: int = 1, rmax: int = 16,
-                        persistent: bool = False):
+                        persistent: int = 0):
         """Set the B kernel's launch shape (slr_set_bsolve_plan); threads=0
-        restores the built-in plan."""
-        _check(slr_set_bsolve_plan(self._h, 1 if several else 0, threads, lds_div, rmax, 1 if persistent else 0),
+        restores the built-in plan; persistent 0, 1 or 2."""
+        _check(slr_set_bsolve_plan(self._h, 1 if several else 0, threads, lds_div, rmax, int(persistent)),
                "slr_set_bsolve_plan")
         self.info = self.query()
 

@@ -290,16 +290,18 @@ struct slr_ctx {
   // workgroup may take (1/lds_div), and the most columns per workgroup
   struct BTune {
     int32_t threads = 0, lds_div = 1, rmax = 16;
-    int32_t persistent = 0;     // 1: a resident grid walks a longest-first schedule
+    int32_t persistent = 0;     // 1: a resident grid walks a longest-first schedule; 2: the same with
+                                // each subdomain's own column count
   } tune1, tuneM;              // one column; several columns
   // schedules of the persistent B launch, by (column groups, workgroups)
   struct BSched {
-    int32_t ncg = 0, nwg = 0;
+    int32_t mode = 0, nrhs = 0, R = 0, nwg = 0, waves = 0;
     int32_t *ptr = nullptr, *items = nullptr;
   };
   std::vector<BSched> bsched;
   DevPool schedpool;
   std::vector<double> b_cost_h;  // per subdomain: work estimate of one B solve item
+  std::vector<int32_t> b_m_h;    // per subdomain: interior rows
   DevPool lrpool;               // U, U64, dsc
   // Recursive interface solver (opts.c_levels == 2, Sec. 5.2): C = [C1 F;
   // F^T C2] in HID order.  The connectors of C1 form a block-diagonal
@@ -473,18 +475,34 @@ int ws_ensure(slr_ctx *c, ApplyWS &w, int32_t nrhs) {
   return SLR_OK;
 }
 
-// Schedule of the persistent B launch for ncg column groups on nwg
-// workgroups: the items (subdomain, column group), longest first by the
-// per-subdomain estimate, each given to the workgroup with the least work
-// so far (longest-processing-time order); kept per (ncg, nwg).
-const slr_ctx::BSched *b_schedule(slr_ctx *c, int32_t ncg, int32_t nwg) {
+// Schedule of the persistent B launch for nrhs columns on nwg workgroups
+// of `waves` waves with R columns of the largest subdomain: the items,
+// longest first by the per-subdomain estimate, each given to the
+// workgroup with the least work so far (longest-processing-time order).
+// mode 1: items (subdomain, group of R columns); mode 2: each subdomain
+// takes as many columns per item as its rows let the x region hold (at
+// most one fewer than the waves, so that one wave stages, and 255).
+// Kept per (mode, nrhs, R, nwg, waves).
+const slr_ctx::BSched *b_schedule(slr_ctx *c, int32_t mode, int32_t nrhs, int32_t R, int32_t nwg, int32_t waves) {
   for (const auto &b : c->bsched)
-    if (b.ncg == ncg && b.nwg == nwg) return &b;
+    if (b.mode == mode && b.nrhs == nrhs && b.R == R && b.nwg == nwg && b.waves == waves) return &b;
   const int32_t p = c->p;
   std::vector<int32_t> items;
-  items.reserve((size_t)p * ncg);
-  for (int32_t g = 0; g < ncg; ++g)
-    for (int32_t q = 0; q < p; ++q) items.push_back((g << 16) | q);
+  if (mode == 1) {
+    const int32_t ncg = (nrhs + R - 1) / R;
+    for (int32_t g = 0; g < ncg; ++g)
+      for (int32_t q = 0; q < p; ++q) items.push_back((g << 16) | q);
+  } else {
+    const int64_t cap = (int64_t)c->b_max_m * R;
+    for (int32_t q = 0; q < p; ++q) {
+      const int64_t mq = std::max<int64_t>(c->b_m_h[q], 1);
+      const int32_t rq = (int32_t)std::max<int64_t>(1, std::min<int64_t>({cap / mq, std::max(waves - 1, 1), 255}));
+      for (int32_t c0 = 0; c0 < nrhs; c0 += rq) {
+        const int32_t rg = std::min(rq, nrhs - c0);
+        items.push_back((int32_t)((uint32_t)q | ((uint32_t)c0 << 16) | ((uint32_t)rg << 24)));
+      }
+    }
+  }
   std::stable_sort(items.begin(), items.end(),
                    [&](int32_t x, int32_t y) { return c->b_cost_h[x & 0xFFFF] > c->b_cost_h[y & 0xFFFF]; });
   std::vector<std::vector<int32_t>> per(nwg);
@@ -502,8 +520,11 @@ const slr_ctx::BSched *b_schedule(slr_ctx *c, int32_t ncg, int32_t nwg) {
     ptr.push_back((int32_t)flat.size());
   }
   slr_ctx::BSched b;
-  b.ncg = ncg;
+  b.mode = mode;
+  b.nrhs = nrhs;
+  b.R = R;
   b.nwg = nwg;
+  b.waves = waves;
   b.ptr = c->schedpool.upload(ptr);
   b.items = c->schedpool.upload(flat);
   if (!b.ptr || !b.items) return nullptr;
@@ -566,11 +587,13 @@ int run_bsolve(slr_ctx *c, const BlockArrays<TS> &B, const BArgs &a0, hipStream_
     const int32_t per_cu = std::max<int32_t>(1, std::min<int32_t>(2048 / threads, (int32_t)(c->lds_limit / lds)));
     const int32_t nwg = c->n_cu * per_cu;
     const int32_t ncg = (a.nrhs + R - 1) / R;
+    const int32_t mode = tu.persistent == 2 && a.nrhs <= 255 ? 2 : 1;
     if ((int64_t)c->p * ncg > nwg && c->p <= 65535 && ncg <= 32767) {
-      const slr_ctx::BSched *sc = b_schedule(c, ncg, nwg);
+      const slr_ctx::BSched *sc = b_schedule(c, mode, a.nrhs, R, nwg, threads / 64);
       if (!sc) return fail(SLR_ERR_OOM, "persistent schedule");
       a.sched = sc->items;
       a.sched_ptr = sc->ptr;
+      a.var_cols = mode == 2 ? 1 : 0;
       grid = nwg;
     }
   }
@@ -1684,8 +1707,11 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
   // work estimate of one item of a subdomain for the persistent schedule:
   // its dependent levels, plus its entries (staging)
   c->b_cost_h.clear();
-  for (const Block &b : H.blocks)
+  c->b_m_h.clear();
+  for (const Block &b : H.blocks) {
     c->b_cost_h.push_back((double)(b.fwd.nlev + b.bwd.nlev) + (double)(b.fwd.ci.size() + b.bwd.ci.size()) / 256.0);
+    c->b_m_h.push_back(b.m);
+  }
   c->b_max_m = sz.max_m;
   c->b_max_lev = sz.max_lev;
   c->b_max_level_bytes = sz.max_level_bytes;
@@ -1939,6 +1965,7 @@ int export_setup(const slr_ctx *cc, std::vector<uint8_t> &blob) {
   // launch shapes and rank-k chunks (slr_autotune)
   w.pod(c->tune1); w.pod(c->tuneM); w.pod(c->lr_nblk_tuned); w.pod(c->lrm_nblk);
   w.vec(c->b_cost_h);
+  w.vec(c->b_m_h);
   // low-rank part (FP64; the stored precision is rebuilt from it on import)
   w.pod(c->k); w.pod(c->theta);
   std::vector<double> U((size_t)c->s * c->k);
@@ -2013,7 +2040,8 @@ int import_setup(const uint8_t *buf, size_t bytes, hipStream_t st, slr_ctx **out
   std::vector<double> U;
   r.pod(c->tune1); r.pod(c->tuneM); r.pod(c->lr_nblk_tuned); r.pod(c->lrm_nblk);
   r.vec(c->b_cost_h);
-  if ((int64_t)c->b_cost_h.size() != c->p ||
+  r.vec(c->b_m_h);
+  if ((int64_t)c->b_cost_h.size() != c->p || (int64_t)c->b_m_h.size() != c->p ||
       c->tune1.lds_div < 1 || c->tuneM.lds_div < 1 || c->tune1.threads < 0 || c->tune1.threads > 1024 ||
       c->tuneM.threads < 0 || c->tuneM.threads > 1024 || c->lrm_nblk < 1 || c->lr_nblk_tuned < 0)
     return bad("launch shapes");
@@ -2479,7 +2507,10 @@ int slr_autotune(slr_ctx *c, int32_t nrhs, int32_t reps, void *hip_stream) {
         cand.push_back(slr_ctx::BTune{th, div, r, 0});
         // several columns: the same shape as a persistent grid walking a
         // longest-first schedule of (subdomain, column group) items
-        if (!one) cand.push_back(slr_ctx::BTune{th, div, r, 1});
+        if (!one) {
+          cand.push_back(slr_ctx::BTune{th, div, r, 1});
+          cand.push_back(slr_ctx::BTune{th, div, r, 2});
+        }
         if (one || r == 1) break;
       }
     }
@@ -2550,7 +2581,7 @@ int slr_set_bsolve_plan(slr_ctx *c, int32_t several, int32_t threads, int32_t ld
     tu = slr_ctx::BTune{};
   } else {
     if ((threads != 256 && threads != 512 && threads != 1024) || lds_div < 1 || lds_div > 8 || rmax < 1 ||
-        rmax > 16 || (persistent != 0 && persistent != 1))
+        rmax > 16 || persistent < 0 || persistent > 2)
       return fail(SLR_ERR_ARG, "bad B launch plan");
     int32_t R = 0, stage = 0;
     const size_t tcb = (c->fact_prec == SLR_FP64) ? 8 : 4;

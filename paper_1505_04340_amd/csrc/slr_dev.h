@@ -123,6 +123,10 @@ struct BArgs {
   // blockIdx.y the column group
   const int32_t *sched = nullptr;
   const int32_t *sched_ptr = nullptr;
+  // persistent with per-subdomain column counts: items are subdomain |
+  // (first column << 16) | (columns << 24), each subdomain's x stored with
+  // its own row count as stride, as many columns as the x region holds
+  int32_t var_cols = 0;
 };
 
 // Numeric refactorisation on the device: one stored coefficient (TS) at

@@ -145,8 +145,9 @@ __host__ __device__ constexpr int pad8(int x) { return (x + 7) & ~7; }
 __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
 
 // x lives in LDS column-major: column r of the workgroup's right-hand sides
-// at xs[r * XS + row], XS = the largest subdomain size; xs[XS * R] is a
-// dummy slot that absorbs stores past the end.
+// at xs[r * XS + row], XS = the largest subdomain size (a persistent item
+// with its own column count: its subdomain's size), in a region of
+// max_m * R + 1 values.
 //
 // One level of an ELL-packed sweep (any row width K) for one column, solved
 // by one wave.  Rows of width K <= 8: one lane per row, entries subtracted
@@ -518,18 +519,18 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
 // w = 0); KE == 0: the ELL form of any width.  Either way the sweeps run
 // one wave per column with double-buffered staging.
 template <typename TS, typename TC, int KE>
-__device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArgs &a, int sub, int cg) {
+__device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArgs &a, int sub, int c0, int Rg,
+                                            int XS) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BlockDesc d = B.desc[sub];
   const int R = a.R;
-  const int c0 = cg * R;
-  const int Rg = min(R, a.nrhs - c0);
   const int m = d.m;
-  const int XS = B.max_m;
-  // LDS: [stage][dummy slots][x: XS*R + 1 TC][levptr f, b][lvb f, b]
+  // LDS: [stage][dummy slots][x: max_m*R + 1 TC][levptr f, b][lvb f, b]; the
+  // item's Rg columns of XS rows each fit the x region (XS*Rg <= max_m*R)
   uint8_t *stage = smem;
   TC *xs = reinterpret_cast<TC *>(smem + a.stage_bytes + kStageDummyBytes);
-  int32_t *levf = reinterpret_cast<int32_t *>(smem + a.stage_bytes + kStageDummyBytes + pad16((int)sizeof(TC) * (XS * R + 1)));
+  int32_t *levf =
+      reinterpret_cast<int32_t *>(smem + a.stage_bytes + kStageDummyBytes + pad16((int)sizeof(TC) * (B.max_m * R + 1)));
   int32_t *levb = levf + B.max_lev + 1;
   int32_t *lvbf = levb + B.max_lev + 1;
   int32_t *lvbb = lvbf + B.max_lev + 1;
@@ -630,12 +631,21 @@ template <typename TS, typename TC, int KE>
 __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   if (a.sched) {
     for (int it = a.sched_ptr[blockIdx.x]; it < a.sched_ptr[blockIdx.x + 1]; ++it) {
-      const int item = a.sched[it];
-      bsolve_item<TS, TC, KE>(B, a, item & 0xFFFF, item >> 16);
+      const uint32_t item = (uint32_t)a.sched[it];
+      const int sub = (int)(item & 0xFFFFu);
+      if (a.var_cols) {
+        // columns [c0, c0 + Rg) of the subdomain, with its own row stride
+        const int c0 = (int)((item >> 16) & 0xFFu), Rg = (int)(item >> 24);
+        bsolve_item<TS, TC, KE>(B, a, sub, c0, Rg, B.desc[sub].m);
+      } else {
+        const int c0 = (int)(item >> 16) * a.R;
+        bsolve_item<TS, TC, KE>(B, a, sub, c0, min(a.R, a.nrhs - c0), B.max_m);
+      }
       __syncthreads();
     }
   } else {
-    bsolve_item<TS, TC, KE>(B, a, blockIdx.x, blockIdx.y);
+    const int c0 = blockIdx.y * a.R;
+    bsolve_item<TS, TC, KE>(B, a, blockIdx.x, c0, min(a.R, a.nrhs - c0), B.max_m);
   }
 }
 

@@ -220,14 +220,13 @@ def test_persistent_bsolve_plan_is_bitwise_the_same(prec):
     r = _dev(np.random.default_rng(10).uniform(-1, 1, (pr.n, 32)))
     Z = G.apply(r).cpu().numpy()
     for threads, div, rmax in ((256, 4, 1), (512, 2, 2), (1024, 1, 4)):
-        G.set_bsolve_plan(True, threads, div, rmax, persistent=True)
-        assert G.info["tune_b_persistentM"] == 1
-        assert np.array_equal(G.apply(r).cpu().numpy(), Z), (threads, div, rmax)
-        G.set_bsolve_plan(True, threads, div, rmax, persistent=False)
-        assert np.array_equal(G.apply(r).cpu().numpy(), Z), (threads, div, rmax)
-    G.set_bsolve_plan(True, 512, 2, 2, persistent=True)
+        for mode in (1, 2, 0):
+            G.set_bsolve_plan(True, threads, div, rmax, persistent=mode)
+            assert G.info["tune_b_persistentM"] == mode
+            assert np.array_equal(G.apply(r).cpu().numpy(), Z), (threads, div, rmax, mode)
+    G.set_bsolve_plan(True, 512, 2, 2, persistent=2)
     Gi = type(G).import_setup(G.export_setup())
-    assert Gi.info["tune_b_persistentM"] == 1
+    assert Gi.info["tune_b_persistentM"] == 2
     assert np.array_equal(Gi.apply(r).cpu().numpy(), Z)
     G.set_bsolve_plan(True, 0)
     assert G.info["tune_b_persistentM"] == 0 and G.info["tune_b_threadsM"] == 0
