@@ -17,7 +17,9 @@ factorisation is setup and is not timed.  Prints one JSON line.
 Beside the step rate the line carries the 64^3 apply and B-kernel
 rooflines, the serving comparison, the oracle's rate on a host core and
 (large_apply) the apply bandwidth on the shifted 128^3 workload, where the
-apply is bound by bytes rather than by dependency chains.
+apply is bound by bytes rather than by dependency chains, (large_solve)
+that workload solved in the form that converges, and (multi_rhs_apply) the
+32-column apply of the 1024^2 diffusion workload after autotuning.
 """
 from __future__ import annotations
 
@@ -374,6 +376,44 @@ def large_apply(P, torch, reps=20):
     return out
 
 
+def large_solve(P, torch):
+    """The shifted 3-D 128^3 workload in the form that converges: ILDLT B_i
+    in minimum degree order, drop tolerance 1e-4, k = 64 from 320 Lanczos
+    steps, and the recursive SLR on C (HID order, ICT C1 / C2, inner rank 64
+    from 320 steps); FGMRES(40) to rtol 1e-8 (at most 3000 iterations) on
+    the workload's right-hand side.  Setup, apply and solve time, the
+    iteration count (the oracle's is 931) and the true FP64 residual."""
+    import slr_inputs as si
+    pr = si.make_config("shifted3d_128")
+    t0 = time.perf_counter()
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact="ildlt", c_fact="ict",
+              droptol=1e-4, c_order="hid", b_order="mindeg", c_levels=2, k2=64, v0=pr.v0())
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = G.query()
+    ms = G.time_kernel("apply", 1, 10)
+    xs, b = pr.rhs()
+    bd = torch.tensor(b[:, 0], dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x, sinfo = G.solve(bd, "fgmres", rtol=1e-8, maxit=3000)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t1
+    rr = float(np.linalg.norm(b[:, 0] - pr.scipy() @ x.cpu().numpy()) / np.linalg.norm(b[:, 0]))
+    ab = apply_bytes(info, 1, 8, 8, info["k"])
+    out = {"workload": "shifted 3-D 7-point Laplacian 128^3 (n=2097152), 20 negative eigenvalues, 8x8x8 boxes; "
+                       "ILDLT B_i (minimum degree order), recursive SLR on C (HID order, ICT C1/C2, inner k=64), "
+                       "drop tolerance 1e-4, k=64 from 320 Lanczos steps, FGMRES(40), rtol 1e-8, FP64",
+           "setup_s": round(setup_s, 2), "setup_host_s": round(info["setup_host_s"], 2),
+           "setup_lanczos_s": round(info["setup_lanczos_s"], 3), "apply_ms": round(ms, 4),
+           "apply_GBs": round(ab / (ms * 1e-3) / 1e9, 1), "iters": sinfo[0]["iters"], "status": sinfo[0]["status"],
+           "solve_s": round(solve_s, 3), "true_relres": rr, "oracle_iters": 931}
+    log(f"[bench:large] recursive FGMRES: {sinfo[0]['iters']} iterations in {solve_s:.2f} s, relres {rr:.2e}")
+    del G
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving(P, torch, n_req, seed=13):
     """Continuous batching (mixed form, flexible CG) vs one-request-at-a-time
     plain FP64 PCG over four resident preconditioners."""
@@ -551,6 +591,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_large:
         out["large_apply"] = large_apply(P, torch)
+        out["large_solve"] = large_solve(P, torch)
     if not args.no_multi:
         out["multi_rhs_apply"] = multi_rhs_apply(P, torch)
     if not args.no_serve:

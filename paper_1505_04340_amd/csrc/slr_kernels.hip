@@ -758,7 +758,24 @@ __global__ void __launch_bounds__(256) k_sweep2(SweepArrays<TS> S, int nrows, co
     const int row = S.rows[t];
     const int e0 = S.rp[t], e1 = S.rp[t + 1];
     TC acc = cvt<TC>(S.sc[t]) * (TC)xc[row];
-    for (int e = e0; e < e1; ++e) acc -= cvt<TC>(S.w2[e]) * (TC)xc[S.ci[e]];
+    // four entries at a time: indices and weights, then the gathers, then
+    // the subtractions in entry order (clamped loads past the row end are
+    // not used)
+    for (int e = e0; e < e1; e += 4) {
+      int c[4];
+      TC wv[4], xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ee = min(e + u, e1 - 1);
+        c[u] = S.ci[ee];
+        wv[u] = cvt<TC>(S.w2[ee]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = (TC)xc[c[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e + u < e1) acc -= wv[u] * xv[u];
+    }
     yc[row] = (double)acc;
     if (dv) d = (double)acc * dv[row];
   }
