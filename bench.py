@@ -205,7 +205,7 @@ def multi_rhs_apply(P, torch, nrhs=32, reps=10):
 
 
 def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=False, recursive=False,
-                  solve=False):
+                  solve=False, plan=None):
     """Only set up one workload and time its apply (for profiler runs).
     threshold: ILDLT / ICT local solvers with drop tolerance 1e-4, B_i in
     minimum degree order and C in HID order (the form in which the shifted
@@ -231,6 +231,11 @@ def apply_profile(P, torch, name, form, nrhs, reps, autotune=False, threshold=Fa
     setup_s = time.perf_counter() - t0
     log(f"{name} set up in {setup_s:.1f} s")
     tune = G.autotune(nrhs) if autotune else None
+    if plan:
+        # a B launch plan given as threads,lds_div,rmax,persistent (slr_set_bsolve_plan)
+        th, dv, rm, pe = (int(v) for v in plan.split(","))
+        G.set_bsolve_plan(nrhs > 1, th, dv, rm, pe)
+        tune = {"plan": plan}
     info = G.query()
     ms = G.time_kernel("apply", nrhs, reps)
     stages = {s: round(G.time_kernel(s, nrhs, reps), 5) for s in ("bsolve1", "cfwd", "lowrank", "cbwd", "bsolve2")}
@@ -516,6 +521,8 @@ def main():
     ap.add_argument("--recursive", action="store_true",
                     help="with --threshold: the recursive SLR on C (inner rank 64)")
     ap.add_argument("--solve", action="store_true", help="with --apply-profile: one FGMRES(40) solve as well")
+    ap.add_argument("--plan", default=None,
+                    help="with --apply-profile: B launch plan threads,lds_div,rmax,persistent (slr_set_bsolve_plan)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -525,7 +532,7 @@ def main():
         import paper_1505_04340_amd as P
         torch.cuda.set_device(0)
         apply_profile(P, torch, args.apply_profile, args.apply_form, args.nrhs, args.reps, args.autotune,
-                      args.threshold, args.recursive, args.solve)
+                      args.threshold, args.recursive, args.solve, args.plan)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
