@@ -57,17 +57,20 @@ def _converged_set(vals, bnds, tol=1e-9):
     return np.array(out)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 @pytest.mark.parametrize("name,over,bf,cf,bo,k,k2", CASES)
 def test_recursive_interface_apply(name, over, bf, cf, bo, k, k2, prec):
+    """"mixed" is FP32 factors at both levels with a BF16 outer U_k (the
+    inner U2 stays FP64)."""
     import paper_1505_04340_amd as P
     print(f"recursive apply {name} {over} {bf}/{cf} {bo} k={k} k2={k2} {prec}", flush=True)
     pr = si.make_config(name, **over)
     kw = _kw(bf, cf, bo, k, k2)
-    G = P.SLR(pr.csr, pr.part, pr.nparts, k=k, v0=pr.v0(), fact_prec=prec, uk_prec=prec, **kw)
+    fp, up = ("fp32", "bf16") if prec == "mixed" else (prec, prec)
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=k, v0=pr.v0(), fact_prec=fp, uk_prec=up, **kw)
     ex, ei = G.export(), G.export_inner()
     assert G.info["k2"] == k2 and G.info["s1"] == ei["s1"] > 0
-    Po = O.setup(pr.csr, pr.part, pr.nparts, k, v0=pr.v0(), fact_prec=prec, uk_prec=prec,
+    Po = O.setup(pr.csr, pr.part, pr.nparts, k, v0=pr.v0(), fact_prec=fp, uk_prec=up,
                  lowrank=(ex["U"], ex["lambda"], ex["theta"]), lowrank2=(ei["U"], ei["lambda"], ei["theta"]), **kw)
     assert (ex["perm"] == Po.perm).all() and G.info["s1"] == Po.FC.s1
     if cf != "chol":
@@ -131,3 +134,52 @@ def test_recursive_interface_solve(case):
     rr = np.linalg.norm(b[:, 0] - pr.scipy() @ x.cpu().numpy()) / np.linalg.norm(b[:, 0])
     assert ro.converged and info[0]["status"] == 0 and rr <= 1e-8, (info, rr)
     assert abs(info[0]["iters"] - ro.iters) <= 1, (info[0]["iters"], ro.iters)
+
+
+@pytest.mark.parametrize("form", ["recursive", "separator", "separator_recursive"])
+def test_batch_with_recursive_and_separator_contexts(form):
+    """Continuous batching over a context with the recursive interface
+    solver and/or an edge-based partition: every request's result and count
+    are the same whether it runs alone or shares the batch with others that
+    arrive while it is in flight, and each converges to 1e-8."""
+    import paper_1505_04340_amd as P
+    print(f"batch {form}", flush=True)
+    if form == "recursive":
+        pr = si.make_config("lap3d_64", N=24, boxes=3)
+        csr, part, p, v0 = pr.csr, pr.part, pr.nparts, pr.v0()
+        kw = _kw("ict", "ict", "mindeg", 16, 8)
+    else:
+        csr = si.laplacian_3d(25)
+        part, p, v0 = si.separator_partition(25, 3, 3), 27, si.lanczos_start(csr[3])
+        kw = dict(lanczos_steps=40, c_order="hid", b_fact="ict", c_fact="ict",
+                  c_levels=2 if form == "separator_recursive" else 1, k2=4)
+    G = P.SLR(csr, part, p, k=8 if form != "recursive" else 16, v0=v0, **kw)
+    n = csr[3]
+    rng = np.random.default_rng(11)
+    reqs = [rng.uniform(-1, 1, (n, r)) for r in (1, 3, 2, 1)]
+    alone = []
+    for q, b in enumerate(reqs):
+        bt = P.Batch(G, 4, "pcg", maxit=500)
+        bt.admit(_dev(b), q)
+        out = []
+        while not out:
+            bt.step(4)
+            out = bt.poll()
+        alone.append((out[0][1].cpu().numpy(), out[0][2]))
+        bt.close()
+    bt = P.Batch(G, 5, "pcg", maxit=500)
+    got, pending, steps = {}, list(enumerate(reqs)), 0
+    while len(got) < len(reqs):
+        while pending and bt.admit(_dev(pending[0][1]), pending[0][0]) is not None:
+            pending.pop(0)
+        bt.step(3)
+        steps += 1
+        for tag, x, info in bt.poll():
+            got[tag] = (x.cpu().numpy(), info)
+        assert steps < 1000
+    bt.close()
+    for q in range(len(reqs)):
+        (xa, ia), (xm, im) = alone[q], got[q]
+        assert ia["status"] == 0 and im["status"] == 0 and im["relres"] <= 1e-8
+        assert ia["iters"] == im["iters"]
+        assert np.array_equal(xa.reshape(n, -1), xm.reshape(n, -1))
