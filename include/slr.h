@@ -219,6 +219,10 @@ typedef struct {
   /* 1 or 2: several-column B solves run as a persistent grid (slr_autotune's
      or slr_set_bsolve_plan's choice; 2: columns per item by subdomain size) */
   int32_t tune_b_persistentM;
+  /* subdomains whose B sweeps keep x in LDS in the forward sweep's level
+     order rather than the row order (chosen at setup where a model of the
+     LDS bank conflicts of the sweeps' gathers favours it clearly) */
+  int32_t b_lds_level_order;
 } slr_info;
 
 typedef struct slr_ctx slr_ctx;

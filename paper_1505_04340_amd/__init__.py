@@ -90,7 +90,7 @@ class slr_info(ctypes.Structure):
                 ("tune_b_threadsM", _I32), ("tune_b_lds_divM", _I32), ("tune_b_rmaxM", _I32),
                 ("lr_chunks", _I32), ("s1", _I64), ("k2", _I32), ("lanczos_steps2", _I32), ("c1_levels", _I32),
                 ("c2_levels", _I32), ("theta2", _D), ("nnz_LC1", _I64), ("nnz_LC2", _I64), ("nnz_F", _I64),
-                ("tune_b_persistentM", _I32)]
+                ("tune_b_persistentM", _I32), ("b_lds_level_order", _I32)]
 
 
 def _sig(name, res, args):

@@ -1548,34 +1548,122 @@ int32_t pack_sweep_runs(const Sweep &sw, std::vector<uint8_t> &data, std::vector
   return nseg;
 }
 
-// Sizes of a packed block set that the B kernel's LDS plan needs.// Sizes of a packed block set that the B kernel's LDS plan needs.
+// Sizes of a packed block set that the B kernel's LDS plan needs.
 struct BSizes {
   int32_t max_m = 0, max_lev = 0, max_level_bytes = 0;
+  int32_t level_order = 0;   // blocks whose LDS layout is the level order
   int64_t data_bytes = 0;
 };
 
+// Modelled LDS bank cost of a block's two sweeps with x laid out by pos
+// (elements of eb bytes): the rows of a level in groups of 64 (one wave
+// access each), one gather per entry slot plus the store; an access costs
+// the largest number of distinct 4-byte words that fall into one of 64
+// banks (its serialisation).
+int64_t lds_sweep_cost(const Block &b, const std::vector<int32_t> &pos, int eb) {
+  constexpr int kBanks = 64;
+  const int32_t wpe = eb / 4;   // 4-byte words per element
+  int64_t cost = 0;
+  std::vector<int32_t> stamp((size_t)std::max(b.m, 1) * wpe, -1);   // last access that touched a word
+  int32_t cnt[kBanks], id = 0;
+  for (const Sweep *sw : {&b.fwd, &b.bwd})
+    for (int32_t l = 0; l < sw->nlev; ++l)
+      for (int32_t t0 = sw->levptr[l]; t0 < sw->levptr[l + 1]; t0 += 64) {
+        const int32_t t1 = std::min(t0 + 64, sw->levptr[l + 1]);
+        int32_t K = 0;
+        for (int32_t t = t0; t < t1; ++t) K = std::max(K, sw->rp[t + 1] - sw->rp[t]);
+        for (int32_t e = -1; e < K; ++e, ++id) {
+          std::fill(cnt, cnt + kBanks, 0);
+          int32_t worst = 0;
+          for (int32_t t = t0; t < t1; ++t) {
+            const int32_t c = (e >= 0 && e < sw->rp[t + 1] - sw->rp[t]) ? sw->ci[sw->rp[t] + e] : sw->rows[t];
+            for (int32_t h = 0; h < wpe; ++h) {
+              const int32_t w = pos[c] * wpe + h;
+              if (stamp[w] == id) continue;
+              stamp[w] = id;
+              worst = std::max(worst, ++cnt[w % kBanks]);
+            }
+          }
+          cost += worst;
+        }
+      }
+  return cost;
+}
+
+// The LDS position of each row of a block.  In the input order the rows of
+// one level of a stencil-like factor lie a grid line apart, so a wave's
+// gathers can all fall into a few banks (a line length of 65 puts every
+// lane of a 2-D anti-diagonal into the same bank).  In the forward sweep's
+// level order the rows of a level sit side by side and so do the earlier
+// rows that neighbouring lanes gather; but then the load of f and the store
+// of u scatter.  The level order is taken when the modelled sweep cost in
+// the input order is more than 3.5 times that in level order, else the
+// identity.  Only rows of fixed small width (zero-fill factors) are
+// modelled; other blocks keep the identity.
+std::vector<int32_t> lds_positions(const Block &b, bool fixed_width, int eb) {
+  std::vector<int32_t> id(std::max(b.m, 0)), pos(std::max(b.m, 0), -1);
+  for (int32_t r = 0; r < b.m; ++r) id[r] = r;
+  if (!fixed_width || b.fwd.nrows != b.m || (int32_t)b.fwd.rows.size() != b.m) return id;
+  for (int32_t t = 0; t < b.m; ++t) {
+    const int32_t r = b.fwd.rows[t];
+    if (r < 0 || r >= b.m || pos[r] >= 0) return id;
+    pos[r] = t;
+  }
+  return 2 * lds_sweep_cost(b, id, eb) > 7 * lds_sweep_cost(b, pos, eb) ? pos : id;
+}
+
+// Rename a block's local rows by pos: sweep rows and columns, E rows and
+// E^T columns (same schedules, entry order and coefficients).
+void relabel_block(Block &b, const std::vector<int32_t> &pos) {
+  for (Sweep *sw : {&b.fwd, &b.bwd}) {
+    for (int32_t &r : sw->rows) r = pos[r];
+    for (int32_t &c : sw->ci) c = pos[c];
+  }
+  for (int32_t &r : b.e_row) r = pos[r];
+  for (int32_t &r : b.t_j) r = pos[r];
+}
+
+// The fixed row width of a block set's packed sweeps: the widest row of any
+// sweep when it is at most 4 (rows are padded to it), else 0 (ELL form).
+int32_t packed_width(const std::vector<Block> &blocks) {
+  int32_t widest = 0;
+  for (const Block &b : blocks)
+    for (const Sweep *sw : {&b.fwd, &b.bwd})
+      for (int32_t t = 0; t < sw->nrows; ++t) widest = std::max(widest, sw->rp[t + 1] - sw->rp[t]);
+  return (widest >= 1 && widest <= 4) ? widest : 0;
+}
+
 // Pack and upload a set of diagonal blocks (factor sweeps, E and E^T rows)
-// for the B kernel.
+// for the B kernel.  Every local index in the packed data is an LDS
+// position (lds_positions); B.xpos maps a block's rows to them, or is null
+// when every block keeps the identity.
 template <typename TS>
 bool pack_blocks(DevPool &P, const std::vector<Block> &blocks, BlockArrays<TS> &B, BSizes &sz, RfMaps *rm) {
   const int32_t nbk = (int32_t)blocks.size();
   std::vector<BlockDesc> desc(nbk);
   std::vector<int32_t> lev, lvb;
   std::vector<uint8_t> data;
-  std::vector<uint16_t> e_row, t_j;
+  std::vector<uint16_t> e_row, t_j, xpos;
+  bool any_moved = false;
   std::vector<int32_t> e_q, t_q;
   std::vector<double> e_val, t_val;
   int32_t max_m = 0, max_lev = 0, max_lb = 0, max_K = 0;
   bool ok = true;
-  // widest row of any sweep; rows are padded to it when it is small
-  int32_t widest = 0;
-  for (const Block &b : blocks)
-    for (const Sweep *sw : {&b.fwd, &b.bwd})
-      for (int32_t t = 0; t < sw->nrows; ++t) widest = std::max(widest, sw->rp[t + 1] - sw->rp[t]);
-  const int32_t Kfix = (widest >= 1 && widest <= 4) ? widest : 0;
+  const int32_t Kfix = packed_width(blocks);
   for (int32_t q = 0; q < nbk; ++q) {
-    const Block &b = blocks[q];
+    const Block &b0 = blocks[q];
     BlockDesc &d = desc[q];
+    const std::vector<int32_t> pos = lds_positions(b0, Kfix > 0, (int)sizeof(TS));
+    Block b = b0;
+    relabel_block(b, pos);
+    if ((int64_t)xpos.size() < (int64_t)b.m0 + b.m) xpos.resize((size_t)b.m0 + b.m, 0);
+    bool moved = false;
+    for (int32_t r = 0; r < b.m; ++r) {
+      xpos[(size_t)b.m0 + r] = (uint16_t)pos[r];
+      moved |= pos[r] != r;
+    }
+    any_moved |= moved;
+    sz.level_order += moved;
     d.m0 = b.m0;
     d.m = b.m;
     if (b.m > 65535) ok = false;   // uint16 local indices
@@ -1650,6 +1738,7 @@ bool pack_blocks(DevPool &P, const std::vector<Block> &blocks, BlockArrays<TS> &
   B.e_val = P.upload(conv<TS>(e_val));
   B.t_q = P.upload(t_q); B.t_j = P.upload(t_j);
   B.t_val = P.upload(conv<TS>(t_val));
+  B.xpos = any_moved ? P.upload(xpos) : nullptr;
   B.max_m = max_m;
   B.max_lev = max_lev;
   B.max_level_bytes = max_lb;
@@ -1659,7 +1748,8 @@ bool pack_blocks(DevPool &P, const std::vector<Block> &blocks, BlockArrays<TS> &
   sz.max_lev = max_lev;
   sz.max_level_bytes = max_lb;
   sz.data_bytes = (int64_t)data.size();
-  return ok && B.desc && B.lev && B.lvb && B.data && B.e_row && B.e_q && B.e_val && B.t_q && B.t_j && B.t_val;
+  return ok && B.desc && B.lev && B.lvb && B.data && B.e_row && B.e_q && B.e_val && B.t_q && B.t_j && B.t_val &&
+         (B.xpos || !any_moved);
 }
 
 // Upload one interface sweep (level-sorted rows, CSR weights, scales and,
@@ -1713,6 +1803,7 @@ void upload_blocks(slr_ctx *c, const HostSetup &H, BlockArrays<TS> &B, SweepArra
     c->b_m_h.push_back(b.m);
   }
   c->b_max_m = sz.max_m;
+  c->info.b_lds_level_order = sz.level_order;
   c->b_max_lev = sz.max_lev;
   c->b_max_level_bytes = sz.max_level_bytes;
   c->b_data_bytes = sz.data_bytes;
@@ -1854,7 +1945,7 @@ int lowrank_done(slr_ctx *c, double t1, hipStream_t st) {
 // followed by the bytes.  Device arrays are written in a fixed order (the
 // list below), so import can allocate and fill them in that order and
 // point the same fields at them.
-constexpr char kSetupMagic[8] = {'S', 'L', 'R', 'S', 'E', 'T', 'v', '1'};
+constexpr char kSetupMagic[8] = {'S', 'L', 'R', 'S', 'E', 'T', 'v', '2'};
 
 uint64_t fnv1a(const uint8_t *p, size_t n) {
   uint64_t h = 0xcbf29ce484222325ull;
@@ -1920,7 +2011,7 @@ std::vector<const void **> setup_fields(slr_ctx *c, BlockArrays<TS> &B, SweepArr
   auto f = [](auto &ptr) { return reinterpret_cast<const void **>(const_cast<void *>((const void *)&ptr)); };
   std::vector<const void **> v = {f(c->perm), f(c->a_rp), f(c->a_ci), f(c->a_v),
                                   f(B.desc), f(B.lev), f(B.lvb), f(B.data), f(B.e_row), f(B.e_q), f(B.e_val),
-                                  f(B.t_q), f(B.t_j), f(B.t_val)};
+                                  f(B.t_q), f(B.t_j), f(B.t_val), f(B.xpos)};
   for (SweepArrays<TS> *S : {&Cf, &Cb})
     for (const void **q : {f(S->lev), f(S->rows), f(S->rp), f(S->ci), f(S->w), f(S->sc), f(S->w2)}) v.push_back(q);
   return v;
@@ -2627,12 +2718,23 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
   info->m_min = INT64_MAX;
   const int64_t fb = o->fact_prec == SLR_FP32 ? 4 : 8;
   int64_t bytes = (int64_t)H.a_ci.size() * 12 + (H.n + 1) * 8 + H.n * 8;
+  {
+    const int32_t Kfix = packed_width(H.blocks);
+    for (const auto &b : H.blocks) {
+      const std::vector<int32_t> pos = lds_positions(b, Kfix > 0, (int)fb);
+      for (int32_t r = 0; r < b.m; ++r)
+        if (pos[r] != r) {
+          ++info->b_lds_level_order;
+          break;
+        }
+    }
+  }
   for (const auto &b : H.blocks) {
     info->nnz_LB += b.nnz_L;
     info->b_levels_max = std::max({info->b_levels_max, b.fwd.nlev, b.bwd.nlev});
     info->m_min = std::min<int64_t>(info->m_min, b.m);
     info->m_max = std::max<int64_t>(info->m_max, b.m);
-    bytes += (int64_t)(b.fwd.ci.size() + b.bwd.ci.size()) * (4 + fb) + (int64_t)b.m * (2 * (8 + fb) + 8) +
+    bytes += (int64_t)(b.fwd.ci.size() + b.bwd.ci.size()) * (4 + fb) + (int64_t)b.m * (2 * (8 + fb) + 10) +
              (int64_t)(b.e_q.size() + b.t_j.size()) * (4 + fb);
   }
   bytes += (int64_t)(H.cfwd.ci.size() + H.cbwd.ci.size()) * (4 + fb) + H.s * 2 * (8 + fb);
@@ -2647,7 +2749,7 @@ int slr_analyze(const slr_csr *A, const int32_t *part, int32_t p, const slr_opts
     info->nnz_F = (int64_t)H.ft_ci.size();
     for (const auto &b : H.c1blocks) {
       info->c1_levels = std::max({info->c1_levels, b.fwd.nlev, b.bwd.nlev});
-      bytes += (int64_t)(b.fwd.ci.size() + b.bwd.ci.size()) * (4 + fb) + (int64_t)b.m * 2 * (8 + fb) +
+      bytes += (int64_t)(b.fwd.ci.size() + b.bwd.ci.size()) * (4 + fb) + (int64_t)b.m * (2 * (8 + fb) + 2) +
                (int64_t)b.e_q.size() * (4 + fb);
     }
     bytes += (int64_t)(H.c2fwd.ci.size() + H.c2bwd.ci.size()) * (4 + fb) + (H.s - H.s1) * 2 * (8 + fb) +

@@ -76,6 +76,10 @@ struct BlockArrays {
   const int32_t *t_q = nullptr;
   const uint16_t *t_j = nullptr;
   const TS *t_val = nullptr;
+  // LDS position of interior row m0 + r of a block (r local): every local
+  // index above (packed streams, E rows, E^T columns) is such a position;
+  // null: position = local row in every block
+  const uint16_t *xpos = nullptr;
   int32_t max_m = 0;
   int32_t max_lev = 0;
   int32_t max_level_bytes = 0;     // largest single level segment

@@ -518,7 +518,7 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
 // epilogue.  KE > 0: every packed row has exactly KE entries (padding has
 // w = 0); KE == 0: the ELL form of any width.  Either way the sweeps run
 // one wave per column with double-buffered staging.
-template <typename TS, typename TC, int KE>
+template <typename TS, typename TC, int KE, bool XP>
 __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArgs &a, int sub, int c0, int Rg,
                                             int XS) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -536,6 +536,8 @@ __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArg
   int32_t *lvbb = lvbf + B.max_lev + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
   TC *xdummy = reinterpret_cast<TC *>(stage + a.stage_bytes) + (tid & 63);
+  // LDS position of each local row (XP false: the row itself)
+  const uint16_t *xp = XP ? B.xpos + d.m0 : nullptr;
   // level pointers into LDS, then rhs = a_f f_i (loads batched 4 per
   // thread), by the threads gt = 0 .. gn-1
   auto prologue = [&](int gt, int gn) {
@@ -548,6 +550,34 @@ __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArg
       lvbb[i] = B.lvb[d.b_lvb + i];
     }
     const int mt = m * Rg;
+    if constexpr (XP) {
+      // rows at their LDS positions
+      for (int t0 = gt; t0 < mt; t0 += 4 * gn) {
+        double v[4];
+        int ps[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = min(t0 + u * gn, mt - 1);
+          const int r = t / m, row = t - r * m;
+          ps[u] = r * XS + (int)xp[row];
+        }
+        if (a.a_f != 0.0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = min(t0 + u * gn, mt - 1);
+            const int r = t / m, row = t - r * m;
+            v[u] = a.a_f * a.f[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldf];
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          *(t0 + u * gn < mt ? xs + ps[u] : xdummy) = (TC)v[u];   // past the end: the lane's dummy slot
+      }
+      return;
+    }
     for (int t0 = gt; t0 < mt; t0 += 4 * gn) {
       double v[4];
       if (a.a_f != 0.0) {
@@ -570,6 +600,20 @@ __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArg
       }
     }
   };
+  // XP: LDS positions of the first rows this thread stores at the end
+  // (rows tid + i * nt, two per register), fetched now so that the u store
+  // waits on no global load
+  constexpr int kPosPre = 8;
+  uint32_t pre[kPosPre / 2];
+  if constexpr (XP) {
+    if (a.u && m > 0) {
+#pragma unroll
+      for (int i = 0; i < kPosPre / 2; ++i) {
+        const int r0 = min(tid + 2 * i * nt, m - 1), r1 = min(tid + (2 * i + 1) * nt, m - 1);
+        pre[i] = (uint32_t)xp[r0] | ((uint32_t)xp[r1] << 16);
+      }
+    }
+  }
   // the sweeps this launch runs (a.sweeps: bit 0 forward, bit 1 backward)
   const int fn = (a.sweeps & 1) ? d.f_nlev : 0, bn = (a.sweeps & 2) ? d.b_nlev : 0;
   {
@@ -602,7 +646,23 @@ __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArg
   }
   sweeps_pipelined<TS, TC, KE>(B.data + d.f_data, levf, lvbf, fn, B.data + d.b_data, levb, lvbb, bn, xs, XS, Rg,
                                stage, a.stage_bytes, true);
-  if (a.u) {
+  if constexpr (XP) {
+    if (a.u) {
+      // each row's LDS position taken once for its Rg columns
+      double *uc = a.u + d.m0 + (int64_t)c0 * a.ldu;
+#pragma unroll
+      for (int i = 0; i < kPosPre; ++i) {
+        const int row = tid + i * nt;
+        const int ps = (int)((pre[i / 2] >> (16 * (i & 1))) & 0xFFFFu);
+        if (row < m)
+          for (int r = 0; r < Rg; ++r) uc[row + (int64_t)r * a.ldu] = (double)xs[r * XS + ps];
+      }
+      for (int row = tid + kPosPre * nt; row < m; row += nt) {
+        const int ps = (int)xp[row];
+        for (int r = 0; r < Rg; ++r) uc[row + (int64_t)r * a.ldu] = (double)xs[r * XS + ps];
+      }
+    }
+  } else if (a.u) {
     for (int t = tid; t < m * Rg; t += nt) {
       const int r = t / m, row = t - r * m;
       a.u[(int64_t)(d.m0 + row) + (int64_t)(c0 + r) * a.ldu] = (double)xs[r * XS + row];
@@ -627,7 +687,7 @@ __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArg
 // One launch of the batched B solves: one workgroup per (subdomain, column
 // group), or a persistent grid walking its scheduled items (the shared
 // memory is reused after a barrier between items).
-template <typename TS, typename TC, int KE>
+template <typename TS, typename TC, int KE, bool XP>
 __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
   if (a.sched) {
     for (int it = a.sched_ptr[blockIdx.x]; it < a.sched_ptr[blockIdx.x + 1]; ++it) {
@@ -636,31 +696,41 @@ __global__ void __launch_bounds__(1024) k_bsolve(BlockArrays<TS> B, BArgs a) {
       if (a.var_cols) {
         // columns [c0, c0 + Rg) of the subdomain, with its own row stride
         const int c0 = (int)((item >> 16) & 0xFFu), Rg = (int)(item >> 24);
-        bsolve_item<TS, TC, KE>(B, a, sub, c0, Rg, B.desc[sub].m);
+        bsolve_item<TS, TC, KE, XP>(B, a, sub, c0, Rg, B.desc[sub].m);
       } else {
         const int c0 = (int)(item >> 16) * a.R;
-        bsolve_item<TS, TC, KE>(B, a, sub, c0, min(a.R, a.nrhs - c0), B.max_m);
+        bsolve_item<TS, TC, KE, XP>(B, a, sub, c0, min(a.R, a.nrhs - c0), B.max_m);
       }
       __syncthreads();
     }
   } else {
     const int c0 = blockIdx.y * a.R;
-    bsolve_item<TS, TC, KE>(B, a, blockIdx.x, c0, min(a.R, a.nrhs - c0), B.max_m);
+    bsolve_item<TS, TC, KE, XP>(B, a, blockIdx.x, c0, min(a.R, a.nrhs - c0), B.max_m);
   }
 }
 
-template <typename TS, typename TC, int KE>
+template <typename TS, typename TC, int KE, bool XP>
 void launch_bsolve_k(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
                      hipStream_t st) {
   static size_t attr_bytes = 0;
   if (lds_bytes > 65536 && lds_bytes > attr_bytes) {
-    (void)hipFuncSetAttribute((const void *)k_bsolve<TS, TC, KE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_bsolve<TS, TC, KE, XP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_bytes);
     attr_bytes = lds_bytes;
   }
   // persistent: p is the number of workgroups of the schedule
   dim3 grid(p, a.sched ? 1 : (a.nrhs + a.R - 1) / a.R);
-  hipLaunchKernelGGL((k_bsolve<TS, TC, KE>), grid, dim3(threads), lds_bytes, st, B, a);
+  hipLaunchKernelGGL((k_bsolve<TS, TC, KE, XP>), grid, dim3(threads), lds_bytes, st, B, a);
+}
+// the variant with LDS positions (B.xpos) exists for the fixed-width forms
+// only: the host keeps the row order for the ELL form
+template <typename TS, typename TC, int KE>
+void launch_bsolve_x(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads, size_t lds_bytes,
+                     hipStream_t st) {
+  if (B.xpos)
+    launch_bsolve_k<TS, TC, KE, true>(B, p, a, threads, lds_bytes, st);
+  else
+    launch_bsolve_k<TS, TC, KE, false>(B, p, a, threads, lds_bytes, st);
 }
 
 // B.pack_K > 0: every packed row has exactly pack_K entries
@@ -668,11 +738,11 @@ template <typename TS, typename TC>
 void launch_bsolve(const BlockArrays<TS> &B, int32_t p, const BArgs &a, int32_t threads,
                    size_t lds_bytes, hipStream_t st) {
   switch (B.pack_K) {
-    case 1: launch_bsolve_k<TS, TC, 1>(B, p, a, threads, lds_bytes, st); break;
-    case 2: launch_bsolve_k<TS, TC, 2>(B, p, a, threads, lds_bytes, st); break;
-    case 3: launch_bsolve_k<TS, TC, 3>(B, p, a, threads, lds_bytes, st); break;
-    case 4: launch_bsolve_k<TS, TC, 4>(B, p, a, threads, lds_bytes, st); break;
-    default: launch_bsolve_k<TS, TC, 0>(B, p, a, threads, lds_bytes, st); break;
+    case 1: launch_bsolve_x<TS, TC, 1>(B, p, a, threads, lds_bytes, st); break;
+    case 2: launch_bsolve_x<TS, TC, 2>(B, p, a, threads, lds_bytes, st); break;
+    case 3: launch_bsolve_x<TS, TC, 3>(B, p, a, threads, lds_bytes, st); break;
+    case 4: launch_bsolve_x<TS, TC, 4>(B, p, a, threads, lds_bytes, st); break;
+    default: launch_bsolve_k<TS, TC, 0, false>(B, p, a, threads, lds_bytes, st); break;
   }
 }
 

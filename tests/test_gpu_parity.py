@@ -164,6 +164,35 @@ def test_lap2d_pcg(lap2d):
     assert rr <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_level_order_lds_layout(prec):
+    """Two 2-D subdomains of interior width 65, whose B sweeps keep x in LDS
+    in level order (the row order would put every lane of an anti-diagonal
+    into one bank): the apply at 1 and 5 columns (plain and persistent
+    launch) matches the oracle, and PCG takes the oracle's count."""
+    import paper_1505_04340_amd as P
+    N = 132
+    csr, part = si.laplacian_2d(N), (np.arange(N * N) % N >= 66).astype(np.int32)
+    v0 = si.lanczos_start(csr[3])
+    kw = dict(lanczos_steps=40, c_order="multicolor", fact_prec=prec, uk_prec=prec)
+    G = P.SLR(csr, part, 2, k=8, v0=v0, **kw)
+    assert G.info["b_lds_level_order"] == 2
+    ex = G.export()
+    Po = O.setup(csr, part, 2, 8, v0=v0, lowrank=(ex["U"], ex["lambda"], ex["theta"]), **kw)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    for nrhs, persistent in ((1, 0), (5, 0), (5, 2)):
+        if nrhs > 1:
+            G.set_bsolve_plan(True, 1024 if persistent else 0, 1, 16, persistent)
+        r = _rand(N * N, nrhs, 70 + nrhs + persistent)
+        assert _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max() <= tol
+    if prec == "fp64":
+        Pown = O.setup(csr, part, 2, 8, v0=v0, **kw)
+        b = _rand(N * N, 1, 80)[:, 0]
+        ro = O.solve(Pown, b, "pcg")
+        x, info = P.SLR(csr, part, 2, k=8, v0=v0, **kw).solve(_dev(b), "pcg")
+        assert ro.converged and info[0]["status"] == 0 and abs(info[0]["iters"] - ro.iters) <= 1
+
+
 # ------------------------------------------------------- 64^3, IC(0) / IC(0)
 @pytest.mark.parametrize("which", ["subdomain", "multicolor"])
 def test_lap3d_lanczos_apply_pcg(which, lap3d, lap3d_mc):

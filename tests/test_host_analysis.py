@@ -149,3 +149,23 @@ def test_analysis_errors_are_reported():
     with pytest.raises(P.SLRError) as e:
         P.analyze(csr, pr.part, 4, b_fact="ildlt0")
     assert e.value.code == P.SLR_ERR_C_NOT_SPD
+
+
+def _strips(N, cut):
+    """Two subdomains of a 2-D grid: grid columns [0, cut) and [cut, N)."""
+    return (np.arange(N * N) % N >= cut).astype(np.int32)
+
+
+def test_lds_layout_choice():
+    """The B kernel keeps a subdomain's x in LDS in level order only where
+    the row order would put a wave's gathers into few banks: a 2-D interior
+    of width 65 (anti-diagonal neighbours 64 words apart) takes it, a width
+    of 63 and the 3-D boxes of the 64^3 workload keep the row order."""
+    import paper_1505_04340_amd as P
+    for N, want in ((132, 2), (130, 1)):
+        for fp in ("fp64", "fp32"):
+            info, _ = P.analyze(si.laplacian_2d(N), _strips(N, 66), 2, fact_prec=fp)
+            assert info["b_lds_level_order"] == want, (N, fp, info["b_lds_level_order"])
+    pr = si.make_config("lap3d_64")
+    info, _ = P.analyze(pr.csr, pr.part, pr.nparts)
+    assert info["b_lds_level_order"] == 0
