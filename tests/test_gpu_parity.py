@@ -169,7 +169,9 @@ def test_level_order_lds_layout(prec):
     """Two 2-D subdomains of interior width 65, whose B sweeps keep x in LDS
     in level order (the row order would put every lane of an anti-diagonal
     into one bank): the apply at 1 and 5 columns (plain and persistent
-    launch) matches the oracle, and PCG takes the oracle's count."""
+    launch) matches the oracle, an imported copy and a refactorised
+    context apply bitwise like their references, and PCG takes the
+    oracle's count."""
     import paper_1505_04340_amd as P
     N = 132
     csr, part = si.laplacian_2d(N), (np.arange(N * N) % N >= 66).astype(np.int32)
@@ -185,12 +187,28 @@ def test_level_order_lds_layout(prec):
             G.set_bsolve_plan(True, 1024 if persistent else 0, 1, 16, persistent)
         r = _rand(N * N, nrhs, 70 + nrhs + persistent)
         assert _relerr(G.apply(_dev(r)).cpu().numpy(), Po.apply(r)).max() <= tol
+    # the serialised setup carries the positions: the imported context
+    # applies bit for bit like this one
+    Gi = P.SLR.import_setup(G.export_setup())
+    assert Gi.info["b_lds_level_order"] == 2
+    r = _rand(N * N, 3, 79)
+    assert np.array_equal(Gi.apply(_dev(r)).cpu().numpy(), G.apply(_dev(r)).cpu().numpy())
     if prec == "fp64":
         Pown = O.setup(csr, part, 2, 8, v0=v0, **kw)
         b = _rand(N * N, 1, 80)[:, 0]
         ro = O.solve(Pown, b, "pcg")
         x, info = P.SLR(csr, part, 2, k=8, v0=v0, **kw).solve(_dev(b), "pcg")
         assert ro.converged and info[0]["status"] == 0 and abs(info[0]["iters"] - ro.iters) <= 1
+        # device refactorisation with new values: bitwise a fresh setup
+        rng = np.random.default_rng(81)
+        A1 = si.diffusion_2d(N, np.exp(rng.standard_normal((N + 2, N + 2))))
+        A2 = si.diffusion_2d(N, np.exp(rng.standard_normal((N + 2, N + 2))))
+        Gr = P.SLR(A1, part, 2, k=8, v0=v0, refactor=True, **kw)
+        assert Gr.info["b_lds_level_order"] == 2
+        ex = Gr.export()
+        Gr.refactor(A2)
+        F = P.SLR(A2, part, 2, lowrank=(ex["U"], ex["lambda"], ex["theta"]), **kw)
+        assert np.array_equal(Gr.apply(_dev(r)).cpu().numpy(), F.apply(_dev(r)).cpu().numpy())
 
 
 # ------------------------------------------------------- 64^3, IC(0) / IC(0)
