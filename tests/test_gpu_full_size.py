@@ -44,6 +44,15 @@ def test_diffusion_1024_apply_32rhs_bf16_mfma(diffusion):
     zo = Po.apply(r[:, cols])
     err = _relerr(z[:, cols], zo)
     assert err.max() <= 1e-5, err
+    # the subdomains whose x sits in LDS in level order are those the host
+    # analysis names (the interiors 57, 65 and 73 wide), and the launch the
+    # bench times (persistent, per-subdomain column counts) gives the same
+    # bits as the plain grid
+    ih, _ = P.analyze(pr.csr, pr.part, pr.nparts, c_order="multicolor", fact_prec="fp32", uk_prec="bf16")
+    assert G.info["b_lds_level_order"] == ih["b_lds_level_order"] > 0
+    G.set_bsolve_plan(True, 1024, 1, 6, 2)
+    z2 = G.apply(torch.tensor(r, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert np.array_equal(z2, z)
 
 
 def test_diffusion_1024_fcg_32rhs_converges(diffusion):
