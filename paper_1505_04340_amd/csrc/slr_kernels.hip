@@ -270,7 +270,21 @@ __device__ __forceinline__ void solve_staged_ell(const uint8_t *sbase, const int
 // it, one round trip each): past the end, loads clamp to the last vector and
 // stores go to the lane's own dummy slot after the stage.  U is chosen so
 // that one batch covers the copy when it can.
+// An empty statement that reads the U loaded vectors (as 64-bit register
+// pairs, one statement): they are all in registers at once at this point.
 template <int U>
+__device__ __forceinline__ void pin_vectors(const uint4 (&v)[U]) {
+  uint64_t p[2 * U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    p[2 * u] = ((uint64_t)v[u].y << 32) | v[u].x;
+    p[2 * u + 1] = ((uint64_t)v[u].w << 32) | v[u].z;
+  }
+  static_assert(U == 4, "pinned batches are of 4 vectors");
+  asm volatile("" ::"v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3]), "v"(p[4]), "v"(p[5]), "v"(p[6]), "v"(p[7]));
+}
+
+template <int U, bool Pin>
 __device__ __forceinline__ void stage_batch(const uint4 *src0, int n0, const uint4 *src1, int nv, uint4 *dst,
                                             uint4 *dummy, int gt, int gn) {
   for (int i0 = gt; i0 < nv; i0 += U * gn) {
@@ -280,6 +294,11 @@ __device__ __forceinline__ void stage_batch(const uint4 *src0, int n0, const uin
       const int i = min(i0 + u * gn, nv - 1);
       v[u] = i < n0 ? src0[i] : src1[i - n0];
     }
+    // all U loaded vectors in registers at once before the first store, so
+    // that the loads go out together: short of registers (the copy shares
+    // its kernel with the sweeps) the scheduler otherwise pairs each load
+    // with its store and waits on each in turn, one round trip per vector
+    if constexpr (Pin) pin_vectors<U>(v);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * gn;
@@ -288,7 +307,12 @@ __device__ __forceinline__ void stage_batch(const uint4 *src0, int n0, const uin
   }
 }
 
-// dummy: the kStageDummyBytes after the stage
+// dummy: the kStageDummyBytes after the stage.  InLoop: the copy beside
+// the sweeps, in pinned batches of 4 (what the registers left there hold);
+// else the first chunk, in batches of up to 12, left to the scheduler
+// (pinning those measured slower: the first chunk is copied beside the
+// prologue's loads of f).
+template <bool InLoop>
 __device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, const uint8_t *src1, int bytes1,
                                            uint8_t *stage, uint8_t *dummy, int gt, int gn) {
   const int n0 = bytes0 >> 4, nv = n0 + (bytes1 >> 4);
@@ -296,12 +320,14 @@ __device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, cons
   const uint4 *s1 = reinterpret_cast<const uint4 *>(src1);
   uint4 *dst = reinterpret_cast<uint4 *>(stage);
   uint4 *dm = reinterpret_cast<uint4 *>(dummy) + (threadIdx.x & 63);
-  if (nv <= 4 * gn)
-    stage_batch<4>(s0, n0, s1, nv, dst, dm, gt, gn);
+  if constexpr (InLoop)
+    stage_batch<4, true>(s0, n0, s1, nv, dst, dm, gt, gn);
+  else if (nv <= 4 * gn)
+    stage_batch<4, false>(s0, n0, s1, nv, dst, dm, gt, gn);
   else if (nv <= 8 * gn)
-    stage_batch<8>(s0, n0, s1, nv, dst, dm, gt, gn);
+    stage_batch<8, false>(s0, n0, s1, nv, dst, dm, gt, gn);
   else
-    stage_batch<12>(s0, n0, s1, nv, dst, dm, gt, gn);
+    stage_batch<12, false>(s0, n0, s1, nv, dst, dm, gt, gn);
 }
 
 // Fixed-width row records (see BlockDesc): KR int32 indices [row, columns,
@@ -435,7 +461,7 @@ __device__ __forceinline__ void stage_first(const uint8_t *data, const int32_t *
   const bool ok = cand <= nlev && (lane == 0 || v - b0 <= half);
   const int l1 = (int)__popcll(__ballot(ok));
   const int b1 = __builtin_amdgcn_readlane(v, l1 - 1);
-  stage_copy(data + b0, b1 - b0, data, 0, stage, dummy, gt, gn);
+  stage_copy<false>(data + b0, b1 - b0, data, 0, stage, dummy, gt, gn);
 }
 
 // Both sweeps of one subdomain (fixed-width records for KE > 0, the ELL form
@@ -470,7 +496,7 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
   auto copy_chunk = [&](int sw, int l0, int l1, uint8_t *dst, int gt, int gn) {
     const int32_t *lvb = sw ? lvbb : lvbf;
     const uint8_t *data = sw ? bdata : fdata;
-    stage_copy(data + lvb[l0], lvb[l1] - lvb[l0], data, 0, dst, dummy, gt, gn);
+    stage_copy<true>(data + lvb[l0], lvb[l1] - lvb[l0], data, 0, dst, dummy, gt, gn);
   };
   int sw = fn > 0 ? 0 : 1;
   if (sw == 1 && bn == 0) return;
