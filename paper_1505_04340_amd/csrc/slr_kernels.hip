@@ -979,7 +979,9 @@ __global__ void __launch_bounds__(256) k_lr_fold(const double *part, int nb, int
   if (lane == 0) cbuf[t] = v * dsc[t % k];
 }
 
-template <typename TU>
+// RT columns per pass: each group of 8 entries of a U row is loaded once for
+// RT columns; every column sums its entries in the same order whatever RT.
+template <typename TU, int RT>
 __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k, const double *w,
                                                   int64_t ldw, double *wout, int64_t ldo, int nrhs,
                                                   const double *cbuf, double rho) {
@@ -988,19 +990,45 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s) return;
-  for (int r = 0; r < nrhs; ++r) {
-    double acc = 0.0;
+  for (int r0 = 0; r0 < nrhs; r0 += RT) {
+    const int nr = min(RT, nrhs - r0);
+    double acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = 0.0;
     int q = 0;
     for (; q + 8 <= k; q += 8) {
       double u[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) u[e] = cvt<double>(U[i + (int64_t)(q + e) * s]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) acc += u[e] * cs[r * k + q + e];
+      for (int r = 0; r < RT; ++r) {
+        const int rr = min(r, nr - 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[r] += u[e] * cs[(r0 + rr) * k + q + e];
+      }
     }
-    for (; q < k; ++q) acc += cvt<double>(U[i + (int64_t)q * s]) * cs[r * k + q];
-    wout[i + (int64_t)r * ldo] = rho * w[i + (int64_t)r * ldw] + acc;
+    for (; q < k; ++q) {
+      const double uq = cvt<double>(U[i + (int64_t)q * s]);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[r] += uq * cs[(r0 + min(r, nr - 1)) * k + q];
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (r < nr) wout[i + (int64_t)(r0 + r) * ldo] = rho * w[i + (int64_t)(r0 + r) * ldw] + acc[r];
   }
+}
+
+template <typename TU>
+void launch_lr_update(const TU *U, int64_t s, int32_t k, const double *w, int64_t ldw, double *wout, int64_t ldo,
+                      int32_t nrhs, const double *cbuf, double rho, hipStream_t st) {
+  const dim3 grid((unsigned)((s + 255) / 256));
+  const size_t lds = sizeof(double) * k * nrhs;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_lr_update<TU, 1>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL((k_lr_update<TU, 8>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+  else
+    hipLaunchKernelGGL((k_lr_update<TU, 16>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
 }
 
 // ---------------------------------------------------------------------------
@@ -1014,8 +1042,10 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
 // over only 64 VEC / ldk lanes.  The update U c reads the column-major U
 // (one row per thread, which measured faster than the row-major form).
 // ---------------------------------------------------------------------------
-constexpr int LRR_RT = 4;   // right-hand sides per register tile
-constexpr int LRR_GU = 4;   // groups in flight per lane
+// Register tiles (template arguments of k_lr_partial_rm): LRR_RT right-hand
+// sides per pass over U, LRR_GU groups in flight per lane: 4 x 4 up to four
+// columns, 8 x 2 up to eight, 16 x 1 above (each column's sum is the same
+// whatever the tile).
 
 template <typename TU>
 struct LrVec;
@@ -1046,7 +1076,7 @@ __device__ __forceinline__ void lr_unpack<float>(const float4 &x, double *u) {
 }
 
 // partial sums U^T w over the groups of block b -> part[(b nrhs + r) k + q]
-template <typename TU>
+template <typename TU, int LRR_RT, int LRR_GU>
 __global__ void __launch_bounds__(256) k_lr_partial_rm(const TU *U, int ldk, int64_t ng, int64_t s, int k,
                                                        const double *w, int64_t ldw, int nrhs, double *part) {
   constexpr int VEC = LrVec<TU>::V;
@@ -1155,11 +1185,18 @@ void launch_lowrank_rm(const TU *Urm, const TU *U, int64_t s, int32_t k, const d
   }
   int32_t ldk;
   const int64_t ng = lr_rm_groups<TU>(s, k, ldk);
-  hipLaunchKernelGGL((k_lr_partial_rm<TU>), dim3(nblk), dim3(256), 0, st, Urm, ldk, ng, s, k, w, ldw, nrhs, part);
+  if (nrhs <= 4)
+    hipLaunchKernelGGL((k_lr_partial_rm<TU, 4, 4>), dim3(nblk), dim3(256), 0, st, Urm, ldk, ng, s, k, w, ldw, nrhs,
+                       part);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL((k_lr_partial_rm<TU, 8, 2>), dim3(nblk), dim3(256), 0, st, Urm, ldk, ng, s, k, w, ldw, nrhs,
+                       part);
+  else
+    hipLaunchKernelGGL((k_lr_partial_rm<TU, 16, 1>), dim3(nblk), dim3(256), 0, st, Urm, ldk, ng, s, k, w, ldw, nrhs,
+                       part);
   hipLaunchKernelGGL(k_lr_fold, dim3((unsigned)((k * nrhs + 3) / 4)), dim3(256), 0, st, part, nblk, k * nrhs, k,
                      dsc, cbuf);
-  hipLaunchKernelGGL((k_lr_update<TU>), dim3((unsigned)((s + 255) / 256)), dim3(256), sizeof(double) * k * nrhs, st,
-                     U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+  launch_lr_update<TU>(U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1405,8 +1442,7 @@ void launch_lowrank(const TU *U, int64_t s, int32_t k, const double *dsc, double
   hipLaunchKernelGGL((k_lr_partial<TU>), dim3(nblk), dim3(LR_THREADS), 0, st, U, s, k, w, ldw, nrhs, part);
   hipLaunchKernelGGL(k_lr_fold, dim3((unsigned)((k * nrhs + 3) / 4)), dim3(256), 0, st, part, nblk, k * nrhs, k,
                      dsc, cbuf);
-  hipLaunchKernelGGL((k_lr_update<TU>), dim3((unsigned)((s + 255) / 256)), dim3(256),
-                     sizeof(double) * k * nrhs, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+  launch_lr_update<TU>(U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho, st);
 }
 
 // ---------------------------------------------------------------------------
