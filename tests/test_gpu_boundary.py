@@ -230,3 +230,18 @@ def test_persistent_bsolve_plan_is_bitwise_the_same(prec):
     assert np.array_equal(Gi.apply(r).cpu().numpy(), Z)
     G.set_bsolve_plan(True, 0)
     assert G.info["tune_b_persistentM"] == 0 and G.info["tune_b_threadsM"] == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_column_results_do_not_depend_on_the_column_count(prec):
+    """A column of a several-column apply equals, bit for bit, the same
+    column applied alone, at column counts that take every register tile
+    of the rank-k kernels (1, 4, 8 and 16 columns per pass) and several B
+    kernel column groups: the batched service relies on this."""
+    pr = si.make_config("lap3d_64", N=32, boxes=4)
+    G = _slr(pr, k=16, lanczos_steps=80, c_order="multicolor", fact_prec=prec, uk_prec=prec)
+    R = np.random.default_rng(91).uniform(-1, 1, (pr.n, 20))
+    alone = np.column_stack([G.apply(_dev(R[:, j])).cpu().numpy() for j in range(20)])
+    for nc in (5, 12, 20):
+        Z = G.apply(_dev(R[:, :nc])).cpu().numpy()
+        assert np.array_equal(Z, alone[:, :nc]), nc
