@@ -307,11 +307,28 @@ __device__ __forceinline__ void stage_batch(const uint4 *src0, int n0, const uin
   }
 }
 
+// Copy nv 16-byte vectors from src into the LDS at dst with direct
+// global-to-LDS loads: each wave moves 64 consecutive vectors per
+// instruction (lane l's vector to the wave's base + 16 l), no registers
+// involved, so every load of the copy is in flight at once; lanes past the
+// end are inactive.  gt - lane and gn are multiples of 64.  The loads are
+// complete when this returns.
+__device__ __forceinline__ void stage_dma(const uint4 *src, int nv, uint4 *dst, int gt, int gn) {
+  const int lane = threadIdx.x & 63;
+  for (int i0 = gt - lane; i0 < nv; i0 += gn) {
+    const int i = i0 + lane;
+    if (i < nv)
+      __builtin_amdgcn_global_load_lds(static_cast<const void *>(src + i),
+                                       (__attribute__((address_space(3))) void *)(dst + i0), 16, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 // dummy: the kStageDummyBytes after the stage.  InLoop: the copy beside
-// the sweeps, in pinned batches of 4 (what the registers left there hold);
-// else the first chunk, in batches of up to 12, left to the scheduler
-// (pinning those measured slower: the first chunk is copied beside the
-// prologue's loads of f).
+// the sweeps, by direct global-to-LDS loads (stage_dma; src1 unused);
+// else the first chunk, in batches of up to 12 through registers, left to
+// the scheduler (the first chunk is copied beside the prologue's loads of
+// f).
 template <bool InLoop>
 __device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, const uint8_t *src1, int bytes1,
                                            uint8_t *stage, uint8_t *dummy, int gt, int gn) {
@@ -321,7 +338,7 @@ __device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, cons
   uint4 *dst = reinterpret_cast<uint4 *>(stage);
   uint4 *dm = reinterpret_cast<uint4 *>(dummy) + (threadIdx.x & 63);
   if constexpr (InLoop)
-    stage_batch<4, true>(s0, n0, s1, nv, dst, dm, gt, gn);
+    stage_dma(s0, n0, dst, gt, gn);
   else if (nv <= 4 * gn)
     stage_batch<4, false>(s0, n0, s1, nv, dst, dm, gt, gn);
   else if (nv <= 8 * gn)
