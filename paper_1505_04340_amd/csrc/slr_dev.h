@@ -93,9 +93,9 @@ struct BlockArrays {
 //   z     = B_i^{-1} rhs                      (forward + backward sweep in LDS)
 //   u_i   = z                                 (if u != nullptr)
 //   gout_q = c_g * g_q + d_t * (E^T z)_q      (epilogue, q owned by i; if gout)
-// LDS bytes after the B kernel's stage that absorb the copy's stores past
-// the end: one 16-byte slot per lane of a wave, so that such stores from one
-// instruction never hit the same bank.
+// LDS bytes after the B kernel's stage that absorb the prologue's stores
+// past the end of x's rows: one 16-byte slot per lane of a wave, so that
+// such stores from one instruction never hit the same bank.
 constexpr int kStageDummyBytes = 1024;
 // ELL level segments: header bytes and the largest piece of a level
 constexpr int kEllHeaderBytes = 16;

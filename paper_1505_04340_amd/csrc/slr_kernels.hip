@@ -262,51 +262,6 @@ __device__ __forceinline__ void solve_staged_ell(const uint8_t *sbase, const int
   for (int l = l0; l < l1; ++l) ell_level_wave<TS, TC>(sbase + (lvb[l] - lvb[l0]), lev[l + 1] - lev[l], xc, lane);
 }
 
-// Copy nv 16-byte vectors into the LDS stage: vector i comes from src0[i]
-// for i < n0, else from src1[i - n0] (two byte streams staged back to back),
-// by the gn threads gt = 0 .. gn-1 of a group of whole waves.  U loads per
-// thread are issued as one batch before their LDS stores.  Neither is
-// predicated (a predicated store lets the compiler sink its load next to
-// it, one round trip each): past the end, loads clamp to the last vector and
-// stores go to the lane's own dummy slot after the stage.  U is chosen so
-// that one batch covers the copy when it can.
-// An empty statement that reads the U loaded vectors (as 64-bit register
-// pairs, one statement): they are all in registers at once at this point.
-template <int U>
-__device__ __forceinline__ void pin_vectors(const uint4 (&v)[U]) {
-  uint64_t p[2 * U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    p[2 * u] = ((uint64_t)v[u].y << 32) | v[u].x;
-    p[2 * u + 1] = ((uint64_t)v[u].w << 32) | v[u].z;
-  }
-  static_assert(U == 4, "pinned batches are of 4 vectors");
-  asm volatile("" ::"v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3]), "v"(p[4]), "v"(p[5]), "v"(p[6]), "v"(p[7]));
-}
-
-template <int U, bool Pin>
-__device__ __forceinline__ void stage_batch(const uint4 *src0, int n0, const uint4 *src1, int nv, uint4 *dst,
-                                            uint4 *dummy, int gt, int gn) {
-  for (int i0 = gt; i0 < nv; i0 += U * gn) {
-    uint4 v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = min(i0 + u * gn, nv - 1);
-      v[u] = i < n0 ? src0[i] : src1[i - n0];
-    }
-    // all U loaded vectors in registers at once before the first store, so
-    // that the loads go out together: short of registers (the copy shares
-    // its kernel with the sweeps) the scheduler otherwise pairs each load
-    // with its store and waits on each in turn, one round trip per vector
-    if constexpr (Pin) pin_vectors<U>(v);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * gn;
-      *(i < nv ? dst + i : dummy) = v[u];
-    }
-  }
-}
-
 // Copy nv 16-byte vectors from src into the LDS at dst with direct
 // global-to-LDS loads: each wave moves 64 consecutive vectors per
 // instruction (lane l's vector to the wave's base + 16 l), no registers
@@ -322,29 +277,6 @@ __device__ __forceinline__ void stage_dma(const uint4 *src, int nv, uint4 *dst, 
                                        (__attribute__((address_space(3))) void *)(dst + i0), 16, 0, 0);
   }
   __builtin_amdgcn_s_waitcnt(0);
-}
-
-// dummy: the kStageDummyBytes after the stage.  InLoop: the copy beside
-// the sweeps, by direct global-to-LDS loads (stage_dma; src1 unused);
-// else the first chunk, in batches of up to 12 through registers, left to
-// the scheduler (the first chunk is copied beside the prologue's loads of
-// f).
-template <bool InLoop>
-__device__ __forceinline__ void stage_copy(const uint8_t *src0, int bytes0, const uint8_t *src1, int bytes1,
-                                           uint8_t *stage, uint8_t *dummy, int gt, int gn) {
-  const int n0 = bytes0 >> 4, nv = n0 + (bytes1 >> 4);
-  const uint4 *s0 = reinterpret_cast<const uint4 *>(src0);
-  const uint4 *s1 = reinterpret_cast<const uint4 *>(src1);
-  uint4 *dst = reinterpret_cast<uint4 *>(stage);
-  uint4 *dm = reinterpret_cast<uint4 *>(dummy) + (threadIdx.x & 63);
-  if constexpr (InLoop)
-    stage_dma(s0, n0, dst, gt, gn);
-  else if (nv <= 4 * gn)
-    stage_batch<4, false>(s0, n0, s1, nv, dst, dm, gt, gn);
-  else if (nv <= 8 * gn)
-    stage_batch<8, false>(s0, n0, s1, nv, dst, dm, gt, gn);
-  else
-    stage_batch<12, false>(s0, n0, s1, nv, dst, dm, gt, gn);
 }
 
 // Fixed-width row records (see BlockDesc): KR int32 indices [row, columns,
@@ -470,7 +402,7 @@ __device__ __forceinline__ void solve_staged(const uint8_t *sbase, const int32_t
 // read straight from the global level offsets glvb, copied by the threads
 // gt = 0 .. gn-1 of a group of whole waves.
 __device__ __forceinline__ void stage_first(const uint8_t *data, const int32_t *glvb, int nlev, int half,
-                                            uint8_t *stage, uint8_t *dummy, int gt, int gn) {
+                                            uint8_t *stage, int gt, int gn) {
   const int lane = threadIdx.x & 63;
   const int cand = 1 + lane;
   const int b0 = glvb[0];
@@ -478,7 +410,7 @@ __device__ __forceinline__ void stage_first(const uint8_t *data, const int32_t *
   const bool ok = cand <= nlev && (lane == 0 || v - b0 <= half);
   const int l1 = (int)__popcll(__ballot(ok));
   const int b1 = __builtin_amdgcn_readlane(v, l1 - 1);
-  stage_copy<false>(data + b0, b1 - b0, data, 0, stage, dummy, gt, gn);
+  stage_dma(reinterpret_cast<const uint4 *>(data + b0), (b1 - b0) >> 4, reinterpret_cast<uint4 *>(stage), gt, gn);
 }
 
 // Both sweeps of one subdomain (fixed-width records for KE > 0, the ELL form
@@ -498,7 +430,6 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
                                                  uint8_t *stage, int stage_bytes, bool staged0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int half = (stage_bytes >> 1) & ~15;
-  uint8_t *dummy = stage + stage_bytes;
   const bool stagers = Rg < nw;
   // end of the chunk starting at level l0: the largest l1 <= l0 + 64 with
   // levels [l0, l1) fitting half the stage (at least one level); lane i
@@ -513,7 +444,8 @@ __device__ __forceinline__ void sweeps_pipelined(const uint8_t *fdata, const int
   auto copy_chunk = [&](int sw, int l0, int l1, uint8_t *dst, int gt, int gn) {
     const int32_t *lvb = sw ? lvbb : lvbf;
     const uint8_t *data = sw ? bdata : fdata;
-    stage_copy<true>(data + lvb[l0], lvb[l1] - lvb[l0], data, 0, dst, dummy, gt, gn);
+    stage_dma(reinterpret_cast<const uint4 *>(data + lvb[l0]), (lvb[l1] - lvb[l0]) >> 4,
+              reinterpret_cast<uint4 *>(dst), gt, gn);
   };
   int sw = fn > 0 ? 0 : 1;
   if (sw == 1 && bn == 0) return;
@@ -665,8 +597,7 @@ __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArg
       const int sw0 = fn > 0 ? 0 : 1;
       if (sw0 == 0 || bn > 0)
         stage_first(B.data + (sw0 ? d.b_data : d.f_data), B.lvb + (sw0 ? d.b_lvb : d.f_lvb),
-                    sw0 ? bn : fn, (a.stage_bytes >> 1) & ~15, stage, stage + a.stage_bytes,
-                    tid - nt / 2, nt - nt / 2);
+                    sw0 ? bn : fn, (a.stage_bytes >> 1) & ~15, stage, tid - nt / 2, nt - nt / 2);
     } else {
       prologue(tid, nt / 2);
     }
