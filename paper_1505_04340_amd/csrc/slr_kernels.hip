@@ -525,6 +525,26 @@ __device__ __forceinline__ void bsolve_item(const BlockArrays<TS> &B, const BArg
       lvbb[i] = B.lvb[d.b_lvb + i];
     }
     const int mt = m * Rg;
+    if constexpr (!XP && sizeof(TC) == 8) {
+      if (a.a_f == 1.0) {
+        // the f columns go straight into x by direct global-to-LDS loads
+        // (4-byte words: a column need not start on 16 bytes), all in
+        // flight at once; gt - lane and gn are multiples of 64
+        const int lane = gt & 63, nd = 2 * m;
+        for (int r = 0; r < Rg; ++r) {
+          const uint32_t *src = reinterpret_cast<const uint32_t *>(a.f + d.m0 + (int64_t)(c0 + r) * a.ldf);
+          uint32_t *dst = reinterpret_cast<uint32_t *>(xs + r * XS);
+          for (int i0 = gt - lane; i0 < nd; i0 += gn) {
+            const int i = i0 + lane;
+            if (i < nd)
+              __builtin_amdgcn_global_load_lds(static_cast<const void *>(src + i),
+                                               (__attribute__((address_space(3))) void *)(dst + i0), 4, 0, 0);
+          }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        return;
+      }
+    }
     if constexpr (XP) {
       // rows at their LDS positions
       for (int t0 = gt; t0 < mt; t0 += 4 * gn) {
