@@ -55,7 +55,7 @@ class Service:
 
     def __init__(self, slrs, method: str = "fcg", rtol: float = 1e-8, maxit: int = 300,
                  hbm_budget_bytes: int = 8 << 30, max_cols: int = 64, batch_cols: int = 32,
-                 iters_per_round: int = 4):
+                 iters_per_round: int = 16):
         import torch
         self.slrs = slrs
         self.method, self.rtol, self.maxit = method, rtol, maxit
