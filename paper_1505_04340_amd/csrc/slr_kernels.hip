@@ -2601,9 +2601,8 @@ __device__ void cgs2_cols(double *x, int m, int K, double *h) {
 }
 
 // ortho_cols' Cholesky (LDS, all threads) and its triangular solve with a
-// row of W in registers for K <= ORTHO_KR (loops unrolled to ORTHO_KR,
+// row of W in registers for K <= 64 (loops unrolled to 32 or 64 entries,
 // columns past K idle).
-constexpr int ORTHO_KR = 32;
 
 // All threads: G (row-major K x K Gram matrix) = R^T R, right-looking in
 // LDS.  Step j takes the pivot (the updated G[j][j]), writes row j of R over
@@ -2626,10 +2625,23 @@ __device__ __forceinline__ void chol_lds(double *G, int K, double *dg, int *flag
     __syncthreads();
     for (int l = j + tid; l < K; l += nt) G[j * K + l] = G[j * K + l] * rs;
     __syncthreads();
-    const int nq = K - 1 - j;
-    for (int p = tid; p < nq * nq; p += nt) {
-      const int q = j + 1 + p / nq, l = j + 1 + p % nq;
-      if (q <= l) G[q * K + l] -= G[j * K + q] * G[j * K + l];
+    // trailing block: columns by lane in a group of 32, rows by group, four
+    // rows' operands loaded before their updates are stored
+    const int rstep = nt >> 5;
+    for (int l = j + 1 + (tid & 31); l < K; l += 32) {
+      const double rl = G[j * K + l];
+      for (int q0 = j + 1 + (tid >> 5); q0 <= l; q0 += 4 * rstep) {
+        double rq[4], g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = min(q0 + u * rstep, l);
+          rq[u] = G[j * K + q];
+          g[u] = G[q * K + l];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q0 + u * rstep <= l) G[(q0 + u * rstep) * K + l] = g[u] - rq[u] * rl;
+      }
     }
     __syncthreads();
   }
@@ -2637,12 +2649,13 @@ __device__ __forceinline__ void chol_lds(double *G, int K, double *dg, int *flag
 
 // One row w of W (K entries): w <- w R^{-1} by forward substitution in
 // column order, R (upper triangle of G) read by broadcast.
+template <int KR>
 __device__ __forceinline__ void solve_row_regs(double *w, const double *G, int K) {
-  double x[ORTHO_KR];
+  double x[KR];
 #pragma unroll
-  for (int q = 0; q < ORTHO_KR; ++q) x[q] = q < K ? w[q] : 0.0;
+  for (int q = 0; q < KR; ++q) x[q] = q < K ? w[q] : 0.0;
 #pragma unroll
-  for (int j = 0; j < ORTHO_KR; ++j)
+  for (int j = 0; j < KR; ++j)
     if (j < K) {
       double v = x[j];
 #pragma unroll
@@ -2650,7 +2663,7 @@ __device__ __forceinline__ void solve_row_regs(double *w, const double *G, int K
       x[j] = v / G[j * K + j];
     }
 #pragma unroll
-  for (int q = 0; q < ORTHO_KR; ++q)
+  for (int q = 0; q < KR; ++q)
     if (q < K) w[q] = x[q];
 }
 
@@ -2661,7 +2674,8 @@ __device__ __forceinline__ void solve_row_regs(double *w, const double *G, int K
 // is (nearly) in the span of the earlier ones (Cholesky pivot below 1e-8 of
 // the column's squared norm) sends the block to Gram-Schmidt twice instead.
 // G: K*K doubles of LDS, h: K + 1, flag: one int of LDS.
-__device__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *flag) {
+template <bool WIDE>
+__device__ __forceinline__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *flag) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int pass = 0; pass < 2; ++pass) {
     if (tid == 0) *flag = 0;
@@ -2693,9 +2707,11 @@ __device__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *f
     __syncthreads();
     if (*flag) break;
     // W <- W R^{-1}, one row per thread, by forward substitution in column
-    // order (the row in registers when K <= ORTHO_KR)
-    if (K <= ORTHO_KR) {
-      for (int r = tid; r < m; r += nt) solve_row_regs(W + (int64_t)r * K, G, K);
+    // order (the row in registers when K <= 32, or K <= 64 with WIDE)
+    if (K <= 32) {
+      for (int r = tid; r < m; r += nt) solve_row_regs<32>(W + (int64_t)r * K, G, K);
+    } else if (WIDE && K <= 64) {
+      for (int r = tid; r < m; r += nt) solve_row_regs<64>(W + (int64_t)r * K, G, K);
     } else {
       for (int r = tid; r < m; r += nt) {
         for (int j = 0; j < K; ++j) {
@@ -2823,7 +2839,6 @@ __global__ void __launch_bounds__(EIG_THREADS) k_eig_ortho(int m, int K, double 
   double *h = eig_lds, *G = h + (K + 1), *xl = G + (size_t)K * K;
   __shared__ int flag;
   const int tid = threadIdx.x, nt = blockDim.x;
-  double *W = xs_lds ? xl : X;
   if (xs_lds) {
     // eight loads per thread in flight
     const int mk = m * K;
@@ -2837,7 +2852,17 @@ __global__ void __launch_bounds__(EIG_THREADS) k_eig_ortho(int m, int K, double 
     }
     __syncthreads();
   }
-  ortho_cols(W, m, K, G, h, &flag);
+  // W in LDS: its own inlined copy, which addresses W as LDS
+  double *W = xs_lds ? xl : X;
+  if (xs_lds) {
+    ortho_cols<false>(xl, m, K, G, h, &flag);
+  } else {
+    // W through an opaque generic pointer: with flat accesses the compiler
+    // schedules the 64-wide row solve without spilling registers
+    double *Xg = X;
+    asm volatile("" : "+s"(Xg));
+    ortho_cols<true>(Xg, m, K, G, h, &flag);
+  }
   if (final_) {
     for (int i = tid; i < m * K; i += nt) {
       const int r = i / K, q = i - r * K;
@@ -2883,8 +2908,8 @@ void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, doub
 // Y: m x K col-major, U64 column-major s x k, k <= K).  Also writes the
 // storage copy U (column-major, rounded to TU).
 // U = V Y (s x k), one row per thread, QT columns of Y per pass staged in
-// LDS; a row's V loads go out eight at a time and each output sums over j in
-// ascending order.
+// LDS; a row's V loads go out eight at a time, a group ahead of their use,
+// and each output sums over j in ascending order.
 template <typename TU, int QT>
 __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const double *V, int64_t ldv,
                                               const double *Y, double *U64, TU *U) {
@@ -2902,10 +2927,17 @@ __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const dou
     double acc[QT];
 #pragma unroll
     for (int q = 0; q < QT; ++q) acc[q] = 0.0;
+    // the next eight V loads go out while the current eight are used
+    double vn[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vn[u] = V[ic + (int64_t)min(u, m - 1) * ldv];
     for (int j0 = 0; j0 < m; j0 += 8) {
       double vj[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) vj[u] = V[ic + (int64_t)min(j0 + u, m - 1) * ldv];
+      for (int u = 0; u < 8; ++u) {
+        vj[u] = vn[u];
+        vn[u] = V[ic + (int64_t)min(j0 + 8 + u, m - 1) * ldv];
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (j0 + u < m) {
