@@ -947,9 +947,14 @@ __global__ void __launch_bounds__(256) k_lr_fold(const double *part, int nb, int
   if (lane == 0) cbuf[t] = v * dsc[t % k];
 }
 
-// RT columns per pass: each group of 8 entries of a U row is loaded once for
-// RT columns; every column sums its entries in the same order whatever RT.
-template <typename TU, int RT>
+// one right-hand side: U entries in flight per lane in the update (LRU_QB1)
+// and groups in flight per lane in the partial sums (LRR_GU1)
+constexpr int LRU_QB1 = 16;
+constexpr int LRR_GU1 = 16;
+// RT columns per pass: each group of QB entries of a U row is loaded once
+// for RT columns; every column sums its entries in the same order whatever
+// RT and QB.  One column: w is loaded before the U entries.
+template <typename TU, int RT, int QB>
 __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k, const double *w,
                                                   int64_t ldw, double *wout, int64_t ldo, int nrhs,
                                                   const double *cbuf, double rho) {
@@ -958,21 +963,23 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s) return;
+  double w1 = 0.0;
+  if constexpr (RT == 1) w1 = w[i];
   for (int r0 = 0; r0 < nrhs; r0 += RT) {
     const int nr = min(RT, nrhs - r0);
     double acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r] = 0.0;
     int q = 0;
-    for (; q + 8 <= k; q += 8) {
-      double u[8];
+    for (; q + QB <= k; q += QB) {
+      double u[QB];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) u[e] = cvt<double>(U[i + (int64_t)(q + e) * s]);
+      for (int e = 0; e < QB; ++e) u[e] = cvt<double>(U[i + (int64_t)(q + e) * s]);
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
         const int rr = min(r, nr - 1);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc[r] += u[e] * cs[(r0 + rr) * k + q + e];
+        for (int e = 0; e < QB; ++e) acc[r] += u[e] * cs[(r0 + rr) * k + q + e];
       }
     }
     for (; q < k; ++q) {
@@ -980,9 +987,13 @@ __global__ void __launch_bounds__(256) k_lr_update(const TU *U, int64_t s, int k
 #pragma unroll
       for (int r = 0; r < RT; ++r) acc[r] += uq * cs[(r0 + min(r, nr - 1)) * k + q];
     }
+    if constexpr (RT == 1) {
+      wout[i] = fma(rho, w1, acc[0]);   // the fused form of the general case
+    } else {
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
-      if (r < nr) wout[i + (int64_t)(r0 + r) * ldo] = rho * w[i + (int64_t)(r0 + r) * ldw] + acc[r];
+      for (int r = 0; r < RT; ++r)
+        if (r < nr) wout[i + (int64_t)(r0 + r) * ldo] = rho * w[i + (int64_t)(r0 + r) * ldw] + acc[r];
+    }
   }
 }
 
@@ -992,11 +1003,14 @@ void launch_lr_update(const TU *U, int64_t s, int32_t k, const double *w, int64_
   const dim3 grid((unsigned)((s + 255) / 256));
   const size_t lds = sizeof(double) * k * nrhs;
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_lr_update<TU, 1>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+    hipLaunchKernelGGL((k_lr_update<TU, 1, LRU_QB1>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs,
+                       cbuf, rho);
   else if (nrhs <= 8)
-    hipLaunchKernelGGL((k_lr_update<TU, 8>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+    hipLaunchKernelGGL((k_lr_update<TU, 8, 8>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf,
+                       rho);
   else
-    hipLaunchKernelGGL((k_lr_update<TU, 16>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf, rho);
+    hipLaunchKernelGGL((k_lr_update<TU, 16, 8>), grid, dim3(256), lds, st, U, s, k, w, ldw, wout, ldo, nrhs, cbuf,
+                       rho);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,9 +1025,9 @@ void launch_lr_update(const TU *U, int64_t s, int32_t k, const double *w, int64_
 // (one row per thread, which measured faster than the row-major form).
 // ---------------------------------------------------------------------------
 // Register tiles (template arguments of k_lr_partial_rm): LRR_RT right-hand
-// sides per pass over U, LRR_GU groups in flight per lane: 4 x 4 up to four
-// columns, 8 x 2 up to eight, 16 x 1 above (each column's sum is the same
-// whatever the tile).
+// sides per pass over U, LRR_GU groups in flight per lane: 1 x LRR_GU1 for
+// one column, 4 x 4 up to four columns, 8 x 2 up to eight, 16 x 1 above
+// (each column's sum is the same whatever the tile).
 
 template <typename TU>
 struct LrVec;
@@ -1153,7 +1167,10 @@ void launch_lowrank_rm(const TU *Urm, const TU *U, int64_t s, int32_t k, const d
   }
   int32_t ldk;
   const int64_t ng = lr_rm_groups<TU>(s, k, ldk);
-  if (nrhs <= 4)
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_lr_partial_rm<TU, 1, LRR_GU1>), dim3(nblk), dim3(256), 0, st, Urm, ldk, ng, s, k, w, ldw,
+                       nrhs, part);
+  else if (nrhs <= 4)
     hipLaunchKernelGGL((k_lr_partial_rm<TU, 4, 4>), dim3(nblk), dim3(256), 0, st, Urm, ldk, ng, s, k, w, ldw, nrhs,
                        part);
   else if (nrhs <= 8)
