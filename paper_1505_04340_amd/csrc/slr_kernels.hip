@@ -2684,6 +2684,59 @@ __device__ __forceinline__ void solve_row_regs(double *w, const double *G, int K
     if (q < K) w[q] = x[q];
 }
 
+// Gram matrix G = W^T W of a row-major m x K block in global memory (K <=
+// 64), upper triangle by pairs and mirrored, as the direct loop of
+// ortho_cols: the rows go through LDS (S: GR_ROWS x K doubles) in chunks,
+// and every pair keeps its four partial sums over the same rows in the same
+// order (rows 4g + u into sum u, the rows past the last whole group into
+// sum 0), so G is bit for bit the direct loop's.
+constexpr int GR_ROWS = 64;
+constexpr int GR_PMAX = (64 * 65 / 2 + EIG_THREADS - 1) / EIG_THREADS;
+__device__ __forceinline__ void gram_staged(const double *W, int m, int K, double *G, double *S) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int npair = K * (K + 1) / 2;
+  int pi[GR_PMAX], pj[GR_PMAX];
+  double acc[GR_PMAX][4];
+#pragma unroll
+  for (int q = 0; q < GR_PMAX; ++q) {
+    int i = 0, rem = min(tid + q * nt, npair - 1);
+    while (rem >= K - i) {
+      rem -= K - i;
+      ++i;
+    }
+    pi[q] = i;
+    pj[q] = i + rem;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
+  }
+  for (int r0 = 0; r0 < m; r0 += GR_ROWS) {
+    const int nr = min(GR_ROWS, m - r0);
+    __syncthreads();
+    for (int e = tid; e < nr * K; e += nt) S[e] = W[(int64_t)r0 * K + e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < GR_PMAX; ++q)
+      if (tid + q * nt < npair) {
+        const int i = pi[q], j = pj[q];
+        int rr = 0;
+        for (; rr + 3 < nr; rr += 4) {
+          acc[q][0] += S[rr * K + i] * S[rr * K + j];
+          acc[q][1] += S[(rr + 1) * K + i] * S[(rr + 1) * K + j];
+          acc[q][2] += S[(rr + 2) * K + i] * S[(rr + 2) * K + j];
+          acc[q][3] += S[(rr + 3) * K + i] * S[(rr + 3) * K + j];
+        }
+        for (; rr < nr; ++rr) acc[q][0] += S[rr * K + i] * S[rr * K + j];
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < GR_PMAX; ++q)
+    if (tid + q * nt < npair) {
+      const double v = (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
+      G[pi[q] * K + pj[q]] = v;
+      G[pj[q] * K + pi[q]] = v;
+    }
+}
+
 // Orthonormalise the K columns of the row-major m x K block W in column
 // order by Cholesky QR, twice: G = W^T W, G = R^T R (R upper triangular),
 // W <- W R^{-1}.  In exact arithmetic this is the Gram-Schmidt result; the
@@ -2692,13 +2745,16 @@ __device__ __forceinline__ void solve_row_regs(double *w, const double *G, int K
 // the column's squared norm) sends the block to Gram-Schmidt twice instead.
 // G: K*K doubles of LDS, h: K + 1, flag: one int of LDS.
 template <bool WIDE>
-__device__ __forceinline__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *flag) {
+__device__ __forceinline__ void ortho_cols(double *W, int m, int K, double *G, double *h, int *flag,
+                                           double *S = nullptr) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int pass = 0; pass < 2; ++pass) {
     if (tid == 0) *flag = 0;
-    // Gram matrix, upper triangle by pairs (i <= j), mirrored
+    // Gram matrix, upper triangle by pairs (i <= j), mirrored (W in global
+    // memory with K <= 64: rows staged through S)
     const int npair = K * (K + 1) / 2;
-    for (int p = tid; p < npair; p += nt) {
+    if (WIDE && S && K <= 64) gram_staged(W, m, K, G, S);
+    for (int p = tid; p < npair && !(WIDE && S && K <= 64); p += nt) {
       int i = 0, rem = p;
       while (rem >= K - i) {
         rem -= K - i;
@@ -2878,7 +2934,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_eig_ortho(int m, int K, double 
     // schedules the 64-wide row solve without spilling registers
     double *Xg = X;
     asm volatile("" : "+s"(Xg));
-    ortho_cols<true>(Xg, m, K, G, h, &flag);
+    ortho_cols<true>(Xg, m, K, G, h, &flag, K <= 64 ? xl : nullptr);
   }
   if (final_) {
     for (int i = tid; i < m * K; i += nt) {
@@ -2909,7 +2965,9 @@ void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, doub
   const size_t base = sizeof(double) * (K + 1 + (size_t)K * K);
   const size_t xb = sizeof(double) * (size_t)m * K;
   const int xs_lds = base + xb <= 128 * 1024 ? 1 : 0;
-  const size_t ort_lds = base + (xs_lds ? xb : 0);
+  // block in global memory: K <= 64 stages rows for the Gram matrix
+  const size_t gb = K <= 64 ? sizeof(double) * GR_ROWS * (size_t)K : 0;
+  const size_t ort_lds = base + (xs_lds ? xb : gb);
   if (ort_lds > 65536 && ort_lds > ort_attr) {
     (void)hipFuncSetAttribute((const void *)k_eig_ortho, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ort_lds);
     ort_attr = ort_lds;
