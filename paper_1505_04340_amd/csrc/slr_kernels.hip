@@ -2982,15 +2982,21 @@ void launch_tridiag_eig(int32_t m, const double *alpha, const double *beta, doub
 // Ritz vectors: U64[i, q] = sum_j V[i, j] Y[j, q]  (V: s x m col-major,
 // Y: m x K col-major, U64 column-major s x k, k <= K).  Also writes the
 // storage copy U (column-major, rounded to TU).
-// U = V Y (s x k), one row per thread, QT columns of Y per pass staged in
-// LDS; a row's V loads go out eight at a time, a group ahead of their use,
-// and each output sums over j in ascending order.
-template <typename TU, int QT>
+// U = V Y (s x k), RT rows per thread (rows i + r * blockDim.x of the
+// block's run), QT columns of Y per pass staged in LDS: every Y entry read
+// from LDS serves RT rows.  A row's V loads go out eight at a time, a group
+// ahead of their use, and each output sums over j in ascending order
+// whatever QT and RT.
+template <typename TU, int QT, int RT>
 __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const double *V, int64_t ldv,
                                               const double *Y, double *U64, TU *U) {
   extern __shared__ __align__(16) double ys[];  // m x QT tile
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ic = i < s ? i : s - 1;   // rows past the end load row s - 1 and store nothing
+  int64_t ir[RT], ic[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    ir[r] = (int64_t)blockIdx.x * blockDim.x * RT + (int64_t)r * blockDim.x + threadIdx.x;
+    ic[r] = ir[r] < s ? ir[r] : s - 1;   // rows past the end load row s - 1 and store nothing
+  }
   for (int q0 = 0; q0 < k; q0 += QT) {
     const int nq = min(QT, k - q0);
     __syncthreads();
@@ -2999,20 +3005,25 @@ __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const dou
       ys[j * QT + q] = q < nq ? Y[j + (int64_t)(q0 + q) * m] : 0.0;
     }
     __syncthreads();
-    double acc[QT];
+    double acc[RT][QT];
 #pragma unroll
-    for (int q = 0; q < QT; ++q) acc[q] = 0.0;
-    // the next eight V loads go out while the current eight are used
-    double vn[8];
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) vn[u] = V[ic + (int64_t)min(u, m - 1) * ldv];
+      for (int q = 0; q < QT; ++q) acc[r][q] = 0.0;
+    double vn[RT][8];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vn[r][u] = V[ic[r] + (int64_t)min(u, m - 1) * ldv];
     for (int j0 = 0; j0 < m; j0 += 8) {
-      double vj[8];
+      double vj[RT][8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        vj[u] = vn[u];
-        vn[u] = V[ic + (int64_t)min(j0 + 8 + u, m - 1) * ldv];
-      }
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          vj[r][u] = vn[r][u];
+          vn[r][u] = V[ic[r] + (int64_t)min(j0 + 8 + u, m - 1) * ldv];
+        }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (j0 + u < m) {
@@ -3020,36 +3031,55 @@ __global__ void __launch_bounds__(256) k_ritz(int64_t s, int m, int k, const dou
 #pragma unroll
           for (int q = 0; q < QT / 2; ++q) {
             const double2 y = yr[q];
-            acc[2 * q] += vj[u] * y.x;
-            acc[2 * q + 1] += vj[u] * y.y;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+              acc[r][2 * q] += vj[r][u] * y.x;
+              acc[r][2 * q + 1] += vj[r][u] * y.y;
+            }
           }
         }
     }
-    if (i < s)
 #pragma unroll
-      for (int q = 0; q < QT; ++q)
-        if (q < nq) {
-          U64[i + (int64_t)(q0 + q) * s] = acc[q];
-          U[i + (int64_t)(q0 + q) * s] = round_store<TU>(acc[q]);
-        }
+    for (int r = 0; r < RT; ++r)
+      if (ir[r] < s)
+#pragma unroll
+        for (int q = 0; q < QT; ++q)
+          if (q < nq) {
+            U64[ir[r] + (int64_t)(q0 + q) * s] = acc[r][q];
+            U[ir[r] + (int64_t)(q0 + q) * s] = round_store<TU>(acc[r][q]);
+          }
   }
+}
+
+template <typename TU, int QT, int RT>
+void launch_ritz_t(int64_t s, int32_t m, int32_t k, const double *V, int64_t ldv, const double *Y, double *U64,
+                   TU *U, hipStream_t st) {
+  static size_t attr = 0;
+  const size_t lds = sizeof(double) * (size_t)m * QT;
+  if (lds > 65536 && lds > attr) {
+    (void)hipFuncSetAttribute((const void *)k_ritz<TU, QT, RT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = lds;
+  }
+  const unsigned nb = (unsigned)((s + 256 * RT - 1) / (256 * RT));
+  hipLaunchKernelGGL((k_ritz<TU, QT, RT>), dim3(nb), dim3(256), lds, st, s, m, k, V, ldv, Y, U64, U);
 }
 
 template <typename TU>
 void launch_ritz(int64_t s, int32_t m, int32_t k, const double *V, int64_t ldv, const double *Y, double *U64,
                  TU *U, hipStream_t st) {
   if (s == 0 || k == 0) return;
-  // 32 columns per pass when the tile fits 64 KiB, else 16 (m <= 1024)
-  const bool wide = (size_t)m * 32 * sizeof(double) <= 65536;
-  const size_t lds = sizeof(double) * m * (wide ? 32 : 16);
-  const unsigned nb = (unsigned)((s + 255) / 256);
-  if (wide) {
-    hipLaunchKernelGGL((k_ritz<TU, 32>), dim3(nb), dim3(256), lds, st, s, m, k, V, ldv, Y, U64, U);
-  } else {
-    if (lds > 65536)
-      (void)hipFuncSetAttribute((const void *)k_ritz<TU, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_ritz<TU, 16>), dim3(nb), dim3(256), lds, st, s, m, k, V, ldv, Y, U64, U);
-  }
+  // 32 columns per pass when the tile fits 160 KiB of LDS, else 16 (m <=
+  // 1024); two rows per thread when there are rows enough to fill the chip
+  const bool wide = (size_t)m * 32 * sizeof(double) <= 160 * 1024;
+  const bool two = s >= (int64_t)1 << 19;
+  if (wide && two)
+    launch_ritz_t<TU, 32, 2>(s, m, k, V, ldv, Y, U64, U, st);
+  else if (wide)
+    launch_ritz_t<TU, 32, 1>(s, m, k, V, ldv, Y, U64, U, st);
+  else if (two)
+    launch_ritz_t<TU, 16, 2>(s, m, k, V, ldv, Y, U64, U, st);
+  else
+    launch_ritz_t<TU, 16, 1>(s, m, k, V, ldv, Y, U64, U, st);
 }
 
 // storage copy of a row-major FP64 U (import path)
