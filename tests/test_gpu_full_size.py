@@ -84,6 +84,37 @@ def test_shifted_128_apply_fp32_ildlt():
     assert err.max() <= 1e-5, err
 
 
+def test_shifted_128_device_ritz_pairs():
+    """The device eigensolve and Ritz vectors at full size (shifted 128^3,
+    FP64, 320 Lanczos steps, k = 64: the orthonormalisation's Gram matrix
+    read through LDS, 64-wide row solves, two rows per thread in U = V Y).
+    The device's Ritz values are the eigenvalues of its own tridiagonal T as
+    LAPACK computes them; its Ritz vectors are orthonormal to sqrt(eps)
+    level (partial reorthogonalisation); and each kept vector u_i is a Ritz
+    vector of the oracle's H (eq. H, Sec. 5.1, the oracle's own factors):
+    ||H u_i - lambda_i u_i|| stays within the residual bound
+    beta_m |e_m^T y_i| that T gives, plus a rounding allowance."""
+    import paper_1505_04340_amd as P
+    print("shifted 128^3 fp64 ritz pairs", flush=True)
+    pr = si.make_config("shifted3d_128")
+    G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
+              c_fact=pr.c_fact, c_order="multicolor", v0=pr.v0())
+    ex = G.export()
+    al, be = ex["alpha"], ex["beta"]
+    mm = len(al)
+    T = np.diag(al) + np.diag(be[:mm - 1], 1) + np.diag(be[:mm - 1], -1)
+    ev, Y = np.linalg.eigh(T)
+    ev, bnd = ev[::-1], be[-1] * np.abs(Y[-1, ::-1])
+    assert np.allclose(ev, ex["ritz"], rtol=1e-12, atol=1e-14)
+    U, lam = ex["U"], ex["lambda"]
+    k = U.shape[1]
+    assert k == len(lam) and k > 0
+    assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-7
+    Po = O.setup(pr.csr, pr.part, pr.nparts, 0, 0, b_fact=pr.b_fact, c_fact=pr.c_fact, c_order="multicolor")
+    res = np.array([np.linalg.norm(Po.G(U[:, i]) - lam[i] * U[:, i]) for i in range(k)])
+    assert np.all(res <= bnd[:k] + 1e-6 * np.maximum(1.0, np.abs(lam))), (res, bnd[:k])
+
+
 def test_shifted_128_apply_fp64_pair_path():
     """The shifted 128^3 workload with FP64 factors and U_k: 512 subdomains,
     so the one-column apply takes the two-workgroups-per-CU B solves.  The
