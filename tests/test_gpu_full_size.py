@@ -84,10 +84,12 @@ def test_shifted_128_apply_fp32_ildlt():
     assert err.max() <= 1e-5, err
 
 
-def test_shifted_128_device_ritz_pairs():
-    """The device eigensolve and Ritz vectors at full size (shifted 128^3,
-    FP64, 320 Lanczos steps, k = 64: the orthonormalisation's Gram matrix
-    read through LDS, 64-wide row solves, two rows per thread in U = V Y).
+@pytest.mark.parametrize("name", ["shifted3d_128", "diffusion2d_1024"])
+def test_device_ritz_pairs_full_size(name):
+    """The device eigensolve and Ritz vectors at full size, FP64, 320 Lanczos
+    steps, k = 64: the orthonormalisation's Gram matrix read through LDS and
+    64-wide row solves, with U = V Y in 32-column tiles, two rows per thread
+    on the 128^3 interface (s = 615,608) and one on the 1024^2 (s = 60,540).
     The device's Ritz values are the eigenvalues of its own tridiagonal T as
     LAPACK computes them; its Ritz vectors are orthonormal to sqrt(eps)
     level (partial reorthogonalisation); and each kept vector u_i is a Ritz
@@ -95,8 +97,8 @@ def test_shifted_128_device_ritz_pairs():
     ||H u_i - lambda_i u_i|| stays within the residual bound
     beta_m |e_m^T y_i| that T gives, plus a rounding allowance."""
     import paper_1505_04340_amd as P
-    print("shifted 128^3 fp64 ritz pairs", flush=True)
-    pr = si.make_config("shifted3d_128")
+    print(f"{name} fp64 ritz pairs", flush=True)
+    pr = si.make_config(name)
     G = P.SLR(pr.csr, pr.part, pr.nparts, k=pr.k, lanczos_steps=pr.lanczos_steps, b_fact=pr.b_fact,
               c_fact=pr.c_fact, c_order="multicolor", v0=pr.v0())
     ex = G.export()
